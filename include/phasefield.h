@@ -1,0 +1,221 @@
+/*
+ * phasefield.h -- C ABI of the MI355X phase-field fracture library.
+ *
+ * The library advances a brittle-fracture problem (AT2 phase field with a
+ * history field, plane strain, structured Q1 mesh) one load step at a time
+ * with the standard staggered scheme (Luo, Section 3.1) or one of the
+ * fixed-stress schemes S1/S2/S3 (Sections 3.3-3.5).  Every numerical step
+ * runs in HIP kernels on the device; the host only drives the loops and reads
+ * back scalars (norms, counts).
+ *
+ * Conventions
+ *   - Mesh: [0,lx] x [0,ly], nx x ny elements.  Node (i,j) has id i + j*(nx+1),
+ *     N = (nx+1)*(ny+1).  Element (i,j) has id i + j*nx, E = nx*ny; its corners
+ *     are (i,j), (i+1,j), (i+1,j+1), (i,j+1).
+ *   - Quadrature: 2x2 Gauss, points ordered (-,-), (+,-), (+,+), (-,+).
+ *   - Displacement arrays are structure-of-arrays: u[0..N) = u_x, u[N..2N) = u_y.
+ *   - Per-quadrature-point arrays are QP-major planes: H[q*E + e], q = 0..3.
+ *   - Units: N, mm, MPa.  Forces are per unit thickness.
+ *   - Host arrays passed in are caller-owned and copied before the call
+ *     returns.  Device pointers (the pf_op_* calls) are caller-owned, must hold
+ *     the stated number of elements and must be valid on the context's device;
+ *     those calls are stream-ordered on the context's stream and do not
+ *     synchronise.
+ *   - Every call returns a pf_status; on failure pf_last_error(ctx) holds a
+ *     message.  A context is not thread-safe.
+ */
+#ifndef PHASEFIELD_H
+#define PHASEFIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_ctx pf_ctx;
+
+typedef enum {
+  PF_OK = 0,
+  PF_E_INVALID_ARG = 1,   /* bad size, pointer, index or option            */
+  PF_E_OOM = 2,           /* device allocation failed                      */
+  PF_E_HIP = 3,           /* a HIP runtime call failed                     */
+  PF_E_STATE = 4,         /* call not valid in the context's current state */
+  PF_E_NOT_CONVERGED = 5, /* max_stag / max_newton reached; state is kept  */
+  PF_E_BREAKDOWN = 6,     /* CG saw p.Ap <= 0                              */
+  PF_E_NONFINITE = 7      /* a norm became NaN or Inf                      */
+} pf_status;
+
+/* Staggered schemes: ST (Section 3.1) and the fixed-stress schemes holding the
+ * first stress invariant (S1), the second (S2) or both (S3) (Section 3.4,
+ * table of assumptions). */
+typedef enum { PF_ST = 0, PF_S1 = 1, PF_S2 = 2, PF_S3 = 3 } pf_scheme;
+
+/* Energy split: volumetric-deviatoric (Section 2, used throughout the paper)
+ * or spectral (named in Section 2 as an extension). */
+typedef enum { PF_SPLIT_VD = 0, PF_SPLIT_SPECTRAL = 1 } pf_split;
+
+/* Precision of the inner linear solves.  PF_FP64: everything in FP64.
+ * PF_MIXED: CG vectors and operator data in FP32 inside FP64 outer loops
+ * (Newton for u, iterative refinement for d); history, norms and the
+ * reaction force stay FP64. */
+typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
+
+typedef enum { PF_PC_JACOBI = 0, PF_PC_JACOBI_CHEBYSHEV = 1 } pf_precond;
+
+typedef struct {
+  int32_t nx, ny;              /* elements per direction, >= 1              */
+  double lx, ly;               /* domain size [mm], > 0                     */
+  const uint8_t *elem_active;  /* nx*ny flags (1 = active) or NULL = all    */
+} pf_mesh_desc;
+
+/* Material (Section 2): g(d) = (1-d)^2 + eta, AT2 (w = d^2, c_w = 2). */
+typedef struct {
+  double E, nu;    /* Young's modulus [MPa], Poisson ratio                   */
+  double Gc, l;    /* fracture toughness [N/mm], length scale [mm]           */
+  double eta;      /* residual stiffness                                     */
+  int32_t split;   /* pf_split                                               */
+} pf_material;
+
+typedef struct {
+  int32_t scheme;       /* pf_scheme                                          */
+  int32_t precision;    /* pf_precision                                       */
+  int32_t precond;      /* pf_precond                                         */
+  int32_t cheb_degree;  /* Chebyshev degree for PF_PC_JACOBI_CHEBYSHEV        */
+  double tol_stag;      /* staggered tolerance on ||R_d||/||b|| (Section 3.1) */
+  double tol_pcg;       /* relative tolerance of each linear correction solve */
+  double tol_newton;    /* Newton: ||R_u|| <= tol_newton * ||R_u(lifted)||    */
+  double tol_inner;     /* PF_MIXED: relative tolerance of FP32 inner CG      */
+  int32_t max_stag;     /* max u-solves per load step (k = 0 included)        */
+  int32_t max_newton;   /* max Newton iterations per u-solve                  */
+  int32_t max_cg;       /* max CG iterations per linear solve                 */
+  int32_t cg_check;     /* CG iterations enqueued between convergence polls   */
+  double psi_crit;      /* softening threshold; < 0 means Gc/(c_w l)          */
+  double d_gate;        /* gate: predictor only where d < d_gate (0.95)       */
+  double trial_floor;   /* theta: trial mass coefficient >= theta*(Gc/l+2H)   */
+} pf_solver_opts;
+
+typedef struct {
+  int32_t n_stag;       /* u-solves in the step, k = 0 included               */
+  int32_t n_newton;     /* Newton linear solves                               */
+  int32_t n_trial;      /* trial (augmented) phase solves                     */
+  int32_t n_dsolve;     /* corrected / standard phase solves                  */
+  int64_t n_cg_u;       /* CG iterations, displacement solves                 */
+  int64_t n_cg_d;       /* CG iterations, phase solves                        */
+  int64_t n_cg_trial;   /* CG iterations, trial solves                        */
+  int64_t gated_max;    /* max gated quadrature points over the iterations    */
+  int64_t floor_hits;   /* gated points whose trial coefficient was floored   */
+  double r_stag;        /* staggered residual at exit                         */
+  double force[2];      /* reaction of the load group (x, y) at exit          */
+  double time_ms;       /* host wall time of the call                         */
+  double dof_updates;   /* sum over CG solves of free DOFs x iterations       */
+  int32_t converged;    /* 1 if r_stag <= tol_stag and Newton converged       */
+  int32_t cg_not_converged; /* linear solves that hit max_cg                  */
+} pf_step_stats;
+
+/* Fill *opts with defaults: ST, FP64, Jacobi, tol_stag 1e-5, tol_pcg 1e-10,
+ * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
+ * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1. */
+void pf_default_opts(pf_solver_opts *opts);
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = the null stream) on which every kernel of this context runs.  All
+ * device memory is owned by the context.  Errors: PF_E_INVALID_ARG for bad
+ * sizes or options, PF_E_OOM, PF_E_HIP. */
+pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat,
+                    const pf_solver_opts *opts, void *hip_stream, pf_ctx **out);
+
+pf_status pf_destroy(pf_ctx *ctx);
+
+/* Displacement Dirichlet data of one group (0 <= group < 8).  Entry k fixes
+ * component comp[k] (0 = x, 1 = y) of node node[k] to
+ * load_factor * value_per_unit_load[k].  Replaces the group's previous data.
+ * Nodes of masked-out regions are fixed to zero automatically.
+ * Errors: PF_E_INVALID_ARG for out-of-range nodes/components. */
+pf_status pf_set_dirichlet_u(pf_ctx *ctx, int32_t group, int64_t n,
+                             const int64_t *node, const int8_t *comp,
+                             const double *value_per_unit_load);
+
+/* Phase-field Dirichlet data (e.g. a notch d = 1): node[k] keeps value[k]. */
+pf_status pf_set_dirichlet_d(pf_ctx *ctx, int64_t n, const int64_t *node,
+                             const double *value);
+
+/* One load step at load_factor (Section 3.1 / 3.3-3.5): staggered
+ * iterations until r_stag <= tol_stag or max_stag u-solves, then commit
+ * (u_n, d_n, H_n) and evaluate the reaction forces.  PF_E_NOT_CONVERGED is
+ * not fatal: the step is committed and stats are filled. */
+pf_status pf_load_step(pf_ctx *ctx, double load_factor, pf_step_stats *stats);
+
+/* Finer-grained stepping.  The first call after a commit opens a step at
+ * load_factor and performs k = 0 (the displacement solve only); each later
+ * call performs one staggered iteration k >= 1 (trial + predictor for S*,
+ * phase solve, displacement solve).  stats accumulates over the open step
+ * and stats->r_stag is the staggered residual after this call.
+ * pf_commit_step closes the step.  Errors: PF_E_STATE if load_factor
+ * differs from the open step's. */
+pf_status pf_staggered_iterate(pf_ctx *ctx, double load_factor, pf_step_stats *stats);
+pf_status pf_commit_step(pf_ctx *ctx);
+
+/* Reaction force of a Dirichlet group: the sum over its entries of the
+ * internal force sum_e int B^T sigma (Section 3.2, weak form F_u) at the
+ * committed state, split by component into force[0] (x) and force[1] (y). */
+pf_status pf_reaction_force(pf_ctx *ctx, int32_t group, double force[2]);
+
+/* Committed state, host arrays: u [2N] SoA, d [N], H [4E] QP planes (the
+ * history max(H_{n-1}, psi+) of the last committed step).  Any pointer may
+ * be NULL to skip it. */
+pf_status pf_get_state(pf_ctx *ctx, double *u, double *d, double *H);
+/* Overwrite the committed state (any pointer may be NULL).  Errors:
+ * PF_E_NONFINITE if an input holds NaN/Inf, PF_E_STATE inside an open step. */
+pf_status pf_set_state(pf_ctx *ctx, const double *u, const double *d, const double *H);
+
+const char *pf_status_string(pf_status s);
+const char *pf_last_error(const pf_ctx *ctx);
+
+/* Number of free displacement / phase DOFs (after Dirichlet data and mask). */
+pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
+
+/* ---------------------------------------------------------------------------
+ * Operator-level entry points (device pointers, FP64).  They run the same
+ * kernels the solver uses, on the context's mesh, material and masks, and
+ * exist for verification and measurement.  No Dirichlet masking is applied
+ * unless stated.
+ * ------------------------------------------------------------------------- */
+
+/* Internal force R = sum_e sum_q B^T sigma(eps(u), g(d)) w detJ with the
+ * split stress (Section 2, eq_sigma).  u [2N], d [N] -> R [2N]. */
+pf_status pf_op_internal_force(pf_ctx *ctx, const double *u, const double *d, double *R);
+
+/* Tangent apply q = K_t(u; d) p: the split tangent with its active
+ * indicators (eq_definition_+) taken at u.  u, p, q [2N]; d [N]. */
+pf_status pf_op_tangent_apply(pf_ctx *ctx, const double *u, const double *d,
+                              const double *p, double *q);
+
+/* Phase operator q = sum [coef_q N N^T + Gc l grad N grad N^T] w detJ p with
+ * an arbitrary per-QP coefficient coef [4E] (K_dd uses Gc/l + 2H, the
+ * augmented block of Section 3.4 a reduced one).  p, q [N]. */
+pf_status pf_op_phase_apply(pf_ctx *ctx, const double *coef, const double *p, double *q);
+
+/* Quadrature-point update (Sections 2, 3.5): from u [2N], d [N] and the
+ * committed history H_prev [4E], write H = max(H_prev, psi+) [4E], the
+ * scheme part psi_S [4E] (psi_vol for S1, psi_dev for S2, psi+ for S3) and
+ * per element a flag byte [E]: bits 0-3 = tr eps > 0 at QP q, bits 4-7 =
+ * softening gate at QP q.  Returns the number of gated points in *n_gated. */
+pf_status pf_op_qp_update(pf_ctx *ctx, int32_t scheme, const double *u, const double *d,
+                          const double *H_prev, double *H, double *psi_s,
+                          uint8_t *flags, int64_t *n_gated);
+
+/* Fixed-stress predictor (Section 3.3 half-step update, Section 3.5 gate and
+ * positive-increment rule): Hhat = max(H, H + ((1 + a Dd)^2 - 1) psi_S) at
+ * gated points with Dd_q > 0, else H; a = 2(1-d_q)/g(d_q).  d, dd [N];
+ * H, psi_s, Hhat [4E]; flags [E] as written by pf_op_qp_update. */
+pf_status pf_op_predictor(pf_ctx *ctx, const double *d, const double *dd,
+                          const double *H, const double *psi_s,
+                          const uint8_t *flags, double *Hhat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHASEFIELD_H */

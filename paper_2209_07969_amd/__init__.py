@@ -1,0 +1,306 @@
+"""MI355X phase-field fracture: Python binding of the HIP library.
+
+Argument marshalling only (ctypes).  Every numerical step runs in the HIP
+kernels of ``libphasefield.so``; this module has no CPU fallback and raises
+if the library is missing or no HIP device is present.  PyTorch is used for
+the device, its current stream and device tensors passed to the operator
+entry points.
+
+The C ABI is declared in ``include/phasefield.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int8, c_int32, c_int64, c_uint8, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphasefield.so")
+
+ST, S1, S2, S3 = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+SPLIT_VD, SPLIT_SPECTRAL = 0, 1
+
+EXPORTED = [
+    "pf_default_opts", "pf_create", "pf_destroy", "pf_set_dirichlet_u", "pf_set_dirichlet_d",
+    "pf_load_step", "pf_staggered_iterate", "pf_commit_step", "pf_reaction_force",
+    "pf_get_state", "pf_set_state", "pf_status_string", "pf_last_error", "pf_free_dofs",
+    "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
+    "pf_op_predictor",
+]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("lx", c_double), ("ly", c_double),
+                ("elem_active", c_void_p)]
+
+
+class MaterialDesc(ctypes.Structure):
+    _fields_ = [("E", c_double), ("nu", c_double), ("Gc", c_double), ("l", c_double),
+                ("eta", c_double), ("split", c_int32)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("scheme", c_int32), ("precision", c_int32), ("precond", c_int32),
+                ("cheb_degree", c_int32), ("tol_stag", c_double), ("tol_pcg", c_double),
+                ("tol_newton", c_double), ("tol_inner", c_double), ("max_stag", c_int32),
+                ("max_newton", c_int32), ("max_cg", c_int32), ("cg_check", c_int32),
+                ("psi_crit", c_double), ("d_gate", c_double), ("trial_floor", c_double)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("n_stag", c_int32), ("n_newton", c_int32), ("n_trial", c_int32),
+                ("n_dsolve", c_int32), ("n_cg_u", c_int64), ("n_cg_d", c_int64),
+                ("n_cg_trial", c_int64), ("gated_max", c_int64), ("floor_hits", c_int64),
+                ("r_stag", c_double), ("force", c_double * 2), ("time_ms", c_double),
+                ("dof_updates", c_double), ("converged", c_int32),
+                ("cg_not_converged", c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["force"] = (self.force[0], self.force[1])
+        return d
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libphasefield.so and declare its signatures (no device needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime (same soname as the system one).  Load
+    # it first so that the library binds to the runtime already in the
+    # process instead of pulling in a second HIP/HSA runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    dp = POINTER(c_double)
+    lib.pf_default_opts.argtypes = [POINTER(SolverOpts)]
+    lib.pf_default_opts.restype = None
+    lib.pf_create.argtypes = [POINTER(MeshDesc), POINTER(MaterialDesc), POINTER(SolverOpts), P,
+                              POINTER(P)]
+    lib.pf_destroy.argtypes = [P]
+    lib.pf_set_dirichlet_u.argtypes = [P, c_int32, c_int64, POINTER(c_int64), POINTER(c_int8), dp]
+    lib.pf_set_dirichlet_d.argtypes = [P, c_int64, POINTER(c_int64), dp]
+    lib.pf_load_step.argtypes = [P, c_double, POINTER(StepStats)]
+    lib.pf_staggered_iterate.argtypes = [P, c_double, POINTER(StepStats)]
+    lib.pf_commit_step.argtypes = [P]
+    lib.pf_reaction_force.argtypes = [P, c_int32, dp]
+    lib.pf_get_state.argtypes = [P, dp, dp, dp]
+    lib.pf_set_state.argtypes = [P, dp, dp, dp]
+    lib.pf_status_string.argtypes = [c_int32]
+    lib.pf_status_string.restype = ctypes.c_char_p
+    lib.pf_last_error.argtypes = [P]
+    lib.pf_last_error.restype = ctypes.c_char_p
+    lib.pf_free_dofs.argtypes = [P, POINTER(c_int64), POINTER(c_int64)]
+    lib.pf_op_internal_force.argtypes = [P, P, P, P]
+    lib.pf_op_tangent_apply.argtypes = [P, P, P, P, P]
+    lib.pf_op_phase_apply.argtypes = [P, P, P, P]
+    lib.pf_op_qp_update.argtypes = [P, c_int32, P, P, P, P, P, P, POINTER(c_int64)]
+    lib.pf_op_predictor.argtypes = [P, P, P, P, P, P, P]
+    for name in EXPORTED:
+        if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def require_device():
+    """Raise unless the HIP library loads and a HIP device is visible."""
+    load_library()
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the phase-field library has no CPU path")
+
+
+class PhaseFieldError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+STATUS_NOT_CONVERGED = 5
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(POINTER(ctype))
+
+
+def _dev_ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return c_void_p(t.data_ptr())
+
+
+def default_opts() -> SolverOpts:
+    o = SolverOpts()
+    load_library().pf_default_opts(ctypes.byref(o))
+    return o
+
+
+class Context:
+    """One fracture problem on the current HIP device.
+
+    ``problem`` is any object with the attributes of ``workloads.Problem``
+    (nx, ny, lx, ly, material, dir_u, dir_d_nodes, dir_d_values, elem_active,
+    tolerances).  Options not given are taken from the problem, then from the
+    library defaults.
+    """
+
+    def __init__(self, problem, scheme=ST, precision=FP64, stream=None, **overrides):
+        require_device()
+        import torch
+        self.lib = load_library()
+        self.p = problem
+        p = problem
+        self._mask = None
+        mesh = MeshDesc(int(p.nx), int(p.ny), float(p.lx), float(p.ly), None)
+        if getattr(p, "elem_active", None) is not None:
+            self._mask = np.ascontiguousarray(p.elem_active, dtype=np.uint8)
+            mesh.elem_active = self._mask.ctypes.data_as(c_void_p)
+        m = p.material
+        mat = MaterialDesc(m.E, m.nu, m.Gc, m.l, m.eta, int(m.split))
+        o = default_opts()
+        o.scheme = int(scheme)
+        o.precision = int(precision)
+        for name in ("tol_stag", "tol_pcg", "tol_newton", "max_stag", "max_newton",
+                     "psi_crit", "d_gate", "trial_floor"):
+            if hasattr(p, name):
+                setattr(o, name, getattr(p, name))
+        for k, v in overrides.items():
+            setattr(o, k, v)
+        self.opts = o
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = c_void_p()
+        st = self.lib.pf_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(o),
+                                c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise PhaseFieldError(st, "pf_create failed: " +
+                                  self.lib.pf_status_string(st).decode())
+        self.h = h
+        self.N = (p.nx + 1) * (p.ny + 1)
+        self.E = p.nx * p.ny
+        for gi, grp in enumerate(p.dir_u):
+            self.set_dirichlet_u(gi, grp.nodes, grp.comps, grp.values)
+        self.set_dirichlet_d(p.dir_d_nodes, p.dir_d_values)
+
+    # ----------------------------------------------------------- helpers
+    def _check(self, st, what):
+        if st != 0:
+            msg = self.lib.pf_last_error(self.h).decode()
+            raise PhaseFieldError(st, f"{what}: {self.lib.pf_status_string(st).decode()} ({msg})")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- API
+    def set_dirichlet_u(self, group, nodes, comps, values):
+        n = np.ascontiguousarray(nodes, dtype=np.int64)
+        c = np.ascontiguousarray(comps, dtype=np.int8)
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(self.lib.pf_set_dirichlet_u(self.h, group, n.size, _ptr(n, c_int64),
+                                                _ptr(c, c_int8), _ptr(v, c_double)),
+                    "pf_set_dirichlet_u")
+
+    def set_dirichlet_d(self, nodes, values):
+        n = np.ascontiguousarray(nodes, dtype=np.int64)
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(self.lib.pf_set_dirichlet_d(self.h, n.size, _ptr(n, c_int64),
+                                                _ptr(v, c_double)), "pf_set_dirichlet_d")
+
+    def load_step(self, lam, allow_not_converged=True):
+        st = StepStats()
+        s = self.lib.pf_load_step(self.h, float(lam), ctypes.byref(st))
+        if s != 0 and not (allow_not_converged and s == STATUS_NOT_CONVERGED):
+            self._check(s, "pf_load_step")
+        return st.as_dict()
+
+    def staggered_iterate(self, lam):
+        st = StepStats()
+        self._check(self.lib.pf_staggered_iterate(self.h, float(lam), ctypes.byref(st)),
+                    "pf_staggered_iterate")
+        return st.as_dict()
+
+    def commit_step(self):
+        self._check(self.lib.pf_commit_step(self.h), "pf_commit_step")
+
+    def reaction_force(self, group=1):
+        f = np.zeros(2)
+        self._check(self.lib.pf_reaction_force(self.h, group, _ptr(f, c_double)),
+                    "pf_reaction_force")
+        return f
+
+    def get_state(self):
+        u = np.zeros(2 * self.N)
+        d = np.zeros(self.N)
+        H = np.zeros(4 * self.E)
+        self._check(self.lib.pf_get_state(self.h, _ptr(u, c_double), _ptr(d, c_double),
+                                          _ptr(H, c_double)), "pf_get_state")
+        return u.reshape(2, self.N), d, H.reshape(4, self.E)
+
+    def set_state(self, u=None, d=None, H=None):
+        def arr(x, n):
+            if x is None:
+                return None, None
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+            if a.size != n:
+                raise ValueError("state array has the wrong size")
+            return a, _ptr(a, c_double)
+        ua, up = arr(u, 2 * self.N)
+        da, dpp = arr(d, self.N)
+        Ha, Hp = arr(H, 4 * self.E)
+        self._check(self.lib.pf_set_state(self.h, up, dpp, Hp), "pf_set_state")
+
+    def free_dofs(self):
+        a, b = c_int64(), c_int64()
+        self._check(self.lib.pf_free_dofs(self.h, ctypes.byref(a), ctypes.byref(b)),
+                    "pf_free_dofs")
+        return a.value, b.value
+
+    # ------------------------------------------------- operator entries
+    def op_internal_force(self, u, d, R):
+        self._check(self.lib.pf_op_internal_force(self.h, _dev_ptr(u), _dev_ptr(d), _dev_ptr(R)),
+                    "pf_op_internal_force")
+
+    def op_tangent_apply(self, u, d, p, q):
+        self._check(self.lib.pf_op_tangent_apply(self.h, _dev_ptr(u), _dev_ptr(d), _dev_ptr(p),
+                                                 _dev_ptr(q)), "pf_op_tangent_apply")
+
+    def op_phase_apply(self, coef, p, q):
+        self._check(self.lib.pf_op_phase_apply(self.h, _dev_ptr(coef), _dev_ptr(p), _dev_ptr(q)),
+                    "pf_op_phase_apply")
+
+    def op_qp_update(self, scheme, u, d, H_prev, H, psi_s, flags):
+        n = c_int64()
+        self._check(self.lib.pf_op_qp_update(self.h, int(scheme), _dev_ptr(u), _dev_ptr(d),
+                                             _dev_ptr(H_prev), _dev_ptr(H), _dev_ptr(psi_s),
+                                             _dev_ptr(flags), ctypes.byref(n)),
+                    "pf_op_qp_update")
+        return n.value
+
+    def op_predictor(self, d, dd, H, psi_s, flags, Hhat):
+        self._check(self.lib.pf_op_predictor(self.h, _dev_ptr(d), _dev_ptr(dd), _dev_ptr(H),
+                                             _dev_ptr(psi_s), _dev_ptr(flags), _dev_ptr(Hhat)),
+                    "pf_op_predictor")
+
+
+__all__ = ["Context", "load_library", "require_device", "default_opts", "PhaseFieldError",
+           "ST", "S1", "S2", "S3", "FP64", "MIXED", "EXPORTED"]

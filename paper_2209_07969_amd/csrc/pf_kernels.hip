@@ -1,0 +1,1330 @@
+// HIP kernels (gfx950) for AT2 phase-field fracture with fixed-stress
+// staggering on a structured Q1 plane-strain mesh.
+//
+// Operator applies (elasticity tangent, internal force, AT2 phase operator,
+// their diagonals) use one column-marching kernel: a wavefront covers 64
+// consecutive element columns and walks up a chunk of element rows.  Lane L
+// computes element (ie, je), ie = 63*strip - 1 + L, keeps the contributions
+// of its element row to the row above in registers, and takes the
+// contribution of its left neighbour column with one lane shuffle.  Every
+// node value is therefore summed exactly once, in registers, with no atomics
+// and no LDS round trip; the only redundant work is one element column per
+// 63 and one element row per chunk.
+//
+// Element geometry on the uniform grid: with edge differences
+// Db = u1-u0, Dt = u2-u3, Dl = u3-u0, Dr = u2-u1 and the Gauss weights
+// a = (1+1/sqrt3)/2, b = (1-1/sqrt3)/2, the derivatives at QP q are
+//   du/dx = (wB Db + wT Dt)/hx,  du/dy = (wL Dl + wR Dr)/hy,
+// (wB,wT) = (a,b) for q = 0,1 and (b,a) for q = 2,3; (wL,wR) = (a,b) for
+// q = 0,3 and (b,a) for q = 1,2.  The transpose maps edge duals back to the
+// corners: f0 = -Eb - El, f1 = Eb - Er, f2 = Et + Er, f3 = El - Et.
+//
+// Reductions are deterministic: wave shuffles, a fixed-order LDS sum per
+// block, block partials in global memory, and a fixed-order sum by the last
+// block to finish (atomic ticket).  All stores are ordinary vector stores.
+
+#include "pf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace pf {
+namespace {
+
+constexpr double GA = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
+constexpr double GB = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
+constexpr int STRIP = 63;
+constexpr int WPB = 4;                            // waves per block (march)
+constexpr int TPB = 256;
+
+// ------------------------------------------------------------ reductions
+
+template <int NV>
+__device__ inline void block_partial(double (&v)[NV], double *part) {
+  __shared__ double sh[NV][TPB / 64];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[k] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[k][w];
+      part[k * kMaxBlocks + blockIdx.x] = s;
+    }
+  }
+}
+
+// Returns true in every thread of the block that finished last.
+__device__ inline bool last_block(unsigned *counter) {
+  __shared__ int amlast;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    amlast = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  return amlast != 0;
+}
+
+// Fixed-order sum of the block partials, valid in thread 0 of the last block.
+template <int NV>
+__device__ inline void final_sum(const double *part, int nb, double (&out)[NV]) {
+  __shared__ double sh[NV][TPB / 64];
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+      s += __hip_atomic_load(part + k * kMaxBlocks + b, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[k][w];
+      out[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------- QP geometry
+
+template <int q> struct QW {
+  static constexpr double wB = (q < 2) ? GA : GB;
+  static constexpr double wT = (q < 2) ? GB : GA;
+  static constexpr double wL = (q == 0 || q == 3) ? GA : GB;
+  static constexpr double wR = (q == 0 || q == 3) ? GB : GA;
+};
+
+// N_a at QP q: a^2 at the nearest corner, b^2 at the opposite one, ab else.
+template <int q, int a> struct NW {
+  static constexpr double v = (a == q) ? GA * GA : (a == ((q + 2) & 3)) ? GB * GB : GA * GB;
+};
+
+template <class T, int q>
+__device__ inline T interp4(T v0, T v1, T v2, T v3) {
+  return T(NW<q, 0>::v) * v0 + T(NW<q, 1>::v) * v1 + T(NW<q, 2>::v) * v2 + T(NW<q, 3>::v) * v3;
+}
+
+__device__ inline bool elem_exists(const Grid &g, int ie, int je, const uint8_t *eact) {
+  if (ie < 0 || ie >= g.nx || je < 0 || je >= g.ny) return false;
+  if (eact != nullptr && eact[ie + je * g.nx] == 0) return false;
+  return true;
+}
+
+__device__ inline bool node_exists(const Grid &g, int i, int j) {
+  return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
+}
+
+// --------------------------------------------------------- element maths
+
+// Elasticity, volumetric-deviatoric split.  sigma = A2 eps + (kap - A2/3) t I
+// (in-plane), sxy = A2/2 gamma with A2 = 2 mu g; kap = g K if the QP is
+// active (t > 0, strict) else K.  NONLIN: active bit from the current strain
+// (residual); otherwise from `bits` (tangent frozen at the Newton point).
+template <class T, bool NONLIN>
+__device__ inline void elastic_element(const T (&ux)[4], const T (&uy)[4], const T (&dn)[4],
+                                       unsigned bits, const ElasCoef &c, T (&fx)[4],
+                                       T (&fy)[4]) {
+  const T Dbx = ux[1] - ux[0], Dtx = ux[2] - ux[3], Dlx = ux[3] - ux[0], Drx = ux[2] - ux[1];
+  const T Dby = uy[1] - uy[0], Dty = uy[2] - uy[3], Dly = uy[3] - uy[0], Dry = uy[2] - uy[1];
+  const T ihx = T(c.ihx), ihy = T(c.ihy), twomu = T(c.two_mu), K = T(c.K), eta = T(c.eta);
+  T Ebx = 0, Etx = 0, Elx = 0, Erx = 0, Eby = 0, Ety = 0, Ely = 0, Ery = 0;
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T exx = (wB * Dbx + wT * Dtx) * ihx;                                           \
+    const T uxy = (wL * Dlx + wR * Drx) * ihy;                                           \
+    const T uyx = (wB * Dby + wT * Dty) * ihx;                                           \
+    const T eyy = (wL * Dly + wR * Dry) * ihy;                                           \
+    const T dq = interp4<T, q>(dn[0], dn[1], dn[2], dn[3]);                              \
+    const T om = T(1) - dq;                                                              \
+    const T gq = om * om + eta;                                                          \
+    const T A2 = twomu * gq;                                                             \
+    const T t = exx + eyy;                                                               \
+    bool act = NONLIN ? (t > T(0)) : (((bits >> q) & 1u) != 0u);                        \
+    const T kap = act ? gq * K : K;                                                      \
+    const T lq = kap - A2 * T(1.0 / 3.0);                                                \
+    const T sxx = A2 * exx + lq * t;                                                     \
+    const T syy = A2 * eyy + lq * t;                                                     \
+    const T sxy = T(0.5) * A2 * (uxy + uyx);                                             \
+    Ebx += wB * sxx; Etx += wT * sxx; Elx += wL * sxy; Erx += wR * sxy;                  \
+    Eby += wB * sxy; Ety += wT * sxy; Ely += wL * syy; Ery += wR * syy;                  \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  const T sx = T(c.sx), sy = T(c.sy);
+  Ebx *= sx; Etx *= sx; Elx *= sy; Erx *= sy;
+  Eby *= sx; Ety *= sx; Ely *= sy; Ery *= sy;
+  fx[0] = -Ebx - Elx; fx[1] = Ebx - Erx; fx[2] = Etx + Erx; fx[3] = Elx - Etx;
+  fy[0] = -Eby - Ely; fy[1] = Eby - Ery; fy[2] = Ety + Ery; fy[3] = Ely - Ety;
+}
+
+// Diagonal of the elasticity tangent: for corner a and component x the
+// strain of a unit nodal value is (dNa/dx, 0, dNa/dy), giving
+// C00 Nx^2 + C22 Ny^2 (y: C11 Ny^2 + C22 Nx^2), C22 = A2/2.
+template <class T>
+__device__ inline void elastic_diag_element(const T (&dn)[4], unsigned bits, const ElasCoef &c,
+                                            T (&fx)[4], T (&fy)[4]) {
+  const T wdet = T(c.sx) / T(c.ihx);     // hx hy / 4
+  const T ihx2 = T(c.ihx) * T(c.ihx), ihy2 = T(c.ihy) * T(c.ihy);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { fx[a] = 0; fy[a] = 0; }
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T dq = interp4<T, q>(dn[0], dn[1], dn[2], dn[3]);                              \
+    const T om = T(1) - dq;                                                              \
+    const T gq = om * om + T(c.eta);                                                     \
+    const T A2 = T(c.two_mu) * gq;                                                       \
+    const bool act = ((bits >> q) & 1u) != 0u;                                           \
+    const T kap = act ? gq * T(c.K) : T(c.K);                                            \
+    const T C00 = A2 * T(2.0 / 3.0) + kap;                                               \
+    const T C22 = T(0.5) * A2;                                                           \
+    const T nx2[4] = {wB * wB * ihx2, wB * wB * ihx2, wT * wT * ihx2, wT * wT * ihx2};    \
+    const T ny2[4] = {wL * wL * ihy2, wR * wR * ihy2, wR * wR * ihy2, wL * wL * ihy2};    \
+    for (int a = 0; a < 4; ++a) {                                                        \
+      fx[a] += wdet * (C00 * nx2[a] + C22 * ny2[a]);                                     \
+      fy[a] += wdet * (C00 * ny2[a] + C22 * nx2[a]);                                     \
+    }                                                                                    \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+}
+
+// Phase operator sum [c_q N N^T + Gc l grad N grad N^T] w detJ applied to p.
+template <class T>
+__device__ inline void phase_element(const T (&p)[4], const T (&cq)[4], const PhaseCoef &c,
+                                     T (&f)[4]) {
+  const T Db = p[1] - p[0], Dt = p[2] - p[3], Dl = p[3] - p[0], Dr = p[2] - p[1];
+  const T ihx = T(c.ihx), ihy = T(c.ihy), wdet = T(c.wdet), Gcl = T(c.Gcl);
+  T Eb = 0, Et = 0, El = 0, Er = 0;
+  f[0] = 0; f[1] = 0; f[2] = 0; f[3] = 0;
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T gx = (wB * Db + wT * Dt) * ihx;                                              \
+    const T gy = (wL * Dl + wR * Dr) * ihy;                                              \
+    Eb += wB * gx; Et += wT * gx; El += wL * gy; Er += wR * gy;                          \
+    const T m = cq[q] * wdet * interp4<T, q>(p[0], p[1], p[2], p[3]);                    \
+    f[0] += m * T(NW<q, 0>::v); f[1] += m * T(NW<q, 1>::v);                              \
+    f[2] += m * T(NW<q, 2>::v); f[3] += m * T(NW<q, 3>::v);                              \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  const T sx = T(c.sx) * Gcl, sy = T(c.sy) * Gcl;
+  Eb *= sx; Et *= sx; El *= sy; Er *= sy;
+  f[0] += -Eb - El; f[1] += Eb - Er; f[2] += Et + Er; f[3] += El - Et;
+}
+
+template <class T>
+__device__ inline void phase_diag_element(const T (&cq)[4], const PhaseCoef &c, T (&f)[4]) {
+  const T ihx2 = T(c.ihx * c.ihx), ihy2 = T(c.ihy * c.ihy), wdet = T(c.wdet), Gcl = T(c.Gcl);
+  f[0] = 0; f[1] = 0; f[2] = 0; f[3] = 0;
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T nx2[4] = {wB * wB * ihx2, wB * wB * ihx2, wT * wT * ihx2, wT * wT * ihx2};    \
+    const T ny2[4] = {wL * wL * ihy2, wR * wR * ihy2, wR * wR * ihy2, wL * wL * ihy2};    \
+    const T n2[4] = {T(NW<q, 0>::v * NW<q, 0>::v), T(NW<q, 1>::v * NW<q, 1>::v),          \
+                     T(NW<q, 2>::v * NW<q, 2>::v), T(NW<q, 3>::v * NW<q, 3>::v)};          \
+    for (int a = 0; a < 4; ++a) f[a] += wdet * (cq[q] * n2[a] + Gcl * (nx2[a] + ny2[a])); \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+}
+
+// ------------------------------------------------------- marching kernel
+//
+// An Op provides:
+//   struct Node;                      values loaded per node
+//   static constexpr int NF;          number of accumulated components
+//   static constexpr int NR;          number of reduction accumulators
+//   Node load(int i, int j) const     zero outside the grid
+//   void element(Node n[4], ie, je, T f[NF][4])   zero if no element
+//   void store(i, j, const T v[NF], const Node &n, double red[NR])
+//   void finish(double red[NR])       block-level epilogue (all threads)
+//   Node shfl_up(const Node&)         lane L receives lane L-1's value
+
+template <class Op>
+__global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms) {
+  using T = typename Op::T;
+  using Node = typename Op::Node;
+  constexpr int NF = Op::NF;
+  double red[Op::NR > 0 ? Op::NR : 1];
+#pragma unroll
+  for (int k = 0; k < (Op::NR > 0 ? Op::NR : 1); ++k) red[k] = 0.0;
+  if (!op.skip()) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (w < ms.nstrips * ms.nchunks) {
+      const int strip = w % ms.nstrips;
+      const int chunk = w / ms.nstrips;
+      const int ie = strip * STRIP - 1 + lane;
+      const int j0 = chunk * ms.ch;
+      const int j1 = min(j0 + ms.ch, g.ny + 1);
+      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
+      Node bl = op.load(ie, j0 - 1);
+      Node br = op.load(ie + 1, j0 - 1);
+      T c2[NF], c3[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) { c2[k] = T(0); c3[k] = T(0); }
+      for (int je = j0 - 1; je < j1; ++je) {
+        Node tr = op.load(ie + 1, je + 1);
+        Node tl = Op::shfl_up(tr);
+        if (lane == 0) tl = op.load(ie, je + 1);
+        T f[NF][4];
+        op.element(bl, br, tr, tl, ie, je, f);
+        T out[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+          T A = f[k][1] + c2[k];
+          T Al = __shfl_up(A, 1, 64);
+          out[k] = f[k][0] + c3[k] + Al;
+          c3[k] = f[k][3];
+          c2[k] = f[k][2];
+        }
+        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
+        bl = tl;
+        br = tr;
+      }
+    }
+  }
+  op.finish(red);
+}
+
+template <class T>
+__device__ inline T ld(const T *p, int idx) { return p[idx]; }
+
+// ---- elasticity tangent, fused CG direction update: p = z + beta p_old
+template <class TT, bool FUSED, bool MASK>
+struct OpTangent {
+  using T = TT;
+  static constexpr int NF = 2;
+  static constexpr int NR = FUSED ? 1 : 0;
+  struct Node { T px, py, d; };
+  Grid g; ElasCoef c;
+  const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag;
+  const T *z; const T *pold; T *pnew; T *q; CgScal *sc; RedScratch rs;
+  T beta; int done;
+
+  __device__ bool skip() const { return FUSED && done != 0; }
+  __device__ Node load(int i, int j) const {
+    Node n{T(0), T(0), T(0)};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      if (FUSED) {
+        n.px = z[k] + beta * pold[k];
+        n.py = z[k + g.N] + beta * pold[k + g.N];
+      } else {
+        n.px = z[k];
+        n.py = z[k + g.N];
+      }
+      n.d = d[k];
+    }
+    return n;
+  }
+  static __device__ Node shfl_up(const Node &n) {
+    return Node{__shfl_up(n.px, 1, 64), __shfl_up(n.py, 1, 64), __shfl_up(n.d, 1, 64)};
+  }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          int ie, int je, T (&f)[2][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
+      return;
+    }
+    const T ux[4] = {n0.px, n1.px, n2.px, n3.px};
+    const T uy[4] = {n0.py, n1.py, n2.py, n3.py};
+    const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
+    const unsigned bits = qflag[ie + je * g.nx];
+    elastic_element<T, false>(ux, uy, dn, bits, c, f[0], f[1]);
+  }
+  __device__ void store(int i, int j, const T (&v)[2], const Node &n, double *red) const {
+    const int k = i + j * (g.nx + 1);
+    T qx = v[0], qy = v[1];
+    if (MASK) {
+      const uint8_t nf = nflag[k];
+      if (nf & NF_UX) qx = T(0);
+      if (nf & NF_UY) qy = T(0);
+    }
+    q[k] = qx;
+    q[k + g.N] = qy;
+    if (FUSED) {
+      pnew[k] = n.px;
+      pnew[k + g.N] = n.py;
+      red[0] += double(n.px) * double(qx) + double(n.py) * double(qy);
+    }
+  }
+  __device__ void finish(double *red) const {
+    if (!FUSED) return;
+    if (done != 0) return;
+    double v[1] = {red[0]};
+    block_partial<1>(v, rs.part);
+    if (last_block(rs.counter + 0)) {
+      double s[1];
+      final_sum<1>(rs.part, gridDim.x, s);
+      if (threadIdx.x == 0) {
+        sc->pq = s[0];
+        if (!(s[0] > 0.0)) {
+          sc->done = 2;
+          sc->alpha = 0.0;
+        } else {
+          sc->alpha = sc->rz / s[0];
+        }
+        rs.counter[0] = 0u;
+      }
+    }
+  }
+};
+
+// ---- phase operator (K_dd, augmented block), fused CG direction update
+template <class TT, bool FUSED, bool MASK>
+struct OpPhase {
+  using T = TT;
+  static constexpr int NF = 1;
+  static constexpr int NR = FUSED ? 1 : 0;
+  struct Node { T p; };
+  Grid g; PhaseCoef c;
+  const T *coef; const uint8_t *eact; const uint8_t *nflag;
+  const T *z; const T *pold; T *pnew; T *q; CgScal *sc; RedScratch rs;
+  T beta; int done;
+
+  __device__ bool skip() const { return FUSED && done != 0; }
+  __device__ Node load(int i, int j) const {
+    Node n{T(0)};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      n.p = FUSED ? z[k] + beta * pold[k] : z[k];
+    }
+    return n;
+  }
+  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.p, 1, 64)}; }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          int ie, int je, T (&f)[1][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+      f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
+      return;
+    }
+    const int e = ie + je * g.nx;
+    const T p[4] = {n0.p, n1.p, n2.p, n3.p};
+    const T cq[4] = {coef[e], coef[e + g.E], coef[e + 2 * g.E], coef[e + 3 * g.E]};
+    phase_element<T>(p, cq, c, f[0]);
+  }
+  __device__ void store(int i, int j, const T (&v)[1], const Node &n, double *red) const {
+    const int k = i + j * (g.nx + 1);
+    T qv = v[0];
+    if (MASK && (nflag[k] & NF_D)) qv = T(0);
+    q[k] = qv;
+    if (FUSED) {
+      pnew[k] = n.p;
+      red[0] += double(n.p) * double(qv);
+    }
+  }
+  __device__ void finish(double *red) const {
+    if (!FUSED) return;
+    if (done != 0) return;
+    double v[1] = {red[0]};
+    block_partial<1>(v, rs.part);
+    if (last_block(rs.counter + 1)) {
+      double s[1];
+      final_sum<1>(rs.part, gridDim.x, s);
+      if (threadIdx.x == 0) {
+        sc->pq = s[0];
+        if (!(s[0] > 0.0)) {
+          sc->done = 2;
+          sc->alpha = 0.0;
+        } else {
+          sc->alpha = sc->rz / s[0];
+        }
+        rs.counter[1] = 0u;
+      }
+    }
+  }
+};
+
+// ---- internal force (FP64, nonlinear split stress)
+struct OpForce {
+  using T = double;
+  static constexpr int NF = 2;
+  static constexpr int NR = 1;
+  struct Node { double ux, uy, d; };
+  Grid g; ElasCoef c;
+  const double *u; const double *dd; const uint8_t *eact; const uint8_t *nflag;
+  double *R; RedScratch rs; double sign;
+
+  __device__ bool skip() const { return false; }
+  __device__ Node load(int i, int j) const {
+    Node n{0.0, 0.0, 0.0};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      n.ux = u[k]; n.uy = u[k + g.N]; n.d = dd[k];
+    }
+    return n;
+  }
+  static __device__ Node shfl_up(const Node &n) {
+    return Node{__shfl_up(n.ux, 1, 64), __shfl_up(n.uy, 1, 64), __shfl_up(n.d, 1, 64)};
+  }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          int ie, int je, double (&f)[2][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
+      return;
+    }
+    const double ux[4] = {n0.ux, n1.ux, n2.ux, n3.ux};
+    const double uy[4] = {n0.uy, n1.uy, n2.uy, n3.uy};
+    const double dn[4] = {n0.d, n1.d, n2.d, n3.d};
+    elastic_element<double, true>(ux, uy, dn, 0u, c, f[0], f[1]);
+  }
+  __device__ void store(int i, int j, const double (&v)[2], const Node &, double *red) const {
+    const int k = i + j * (g.nx + 1);
+    double rx = v[0], ry = v[1];
+    if (nflag != nullptr) {
+      const uint8_t nf = nflag[k];
+      if (nf & NF_UX) rx = 0.0;
+      if (nf & NF_UY) ry = 0.0;
+    }
+    R[k] = sign * rx;
+    R[k + g.N] = sign * ry;
+    red[0] += rx * rx + ry * ry;
+  }
+  __device__ void finish(double *red) const {
+    double v[1] = {red[0]};
+    block_partial<1>(v, rs.part);
+    if (last_block(rs.counter + 2)) {
+      double s[1];
+      final_sum<1>(rs.part, gridDim.x, s);
+      if (threadIdx.x == 0) {
+        rs.scal[SC_NORM_A] = s[0];
+        rs.counter[2] = 0u;
+      }
+    }
+  }
+};
+
+// ---- phase residual R_d = K_dd(H) d - b(H) (FP64)
+struct OpPhaseRes {
+  using T = double;
+  static constexpr int NF = 2;   // [0] = K_dd d - b, [1] = b
+  static constexpr int NR = 2;
+  struct Node { double d; };
+  Grid g; PhaseCoef c;
+  const double *H; const double *dd; const uint8_t *eact; const uint8_t *nflag;
+  double *R; RedScratch rs; double sign;
+
+  __device__ bool skip() const { return false; }
+  __device__ Node load(int i, int j) const {
+    Node n{0.0};
+    if (node_exists(g, i, j)) n.d = dd[i + j * (g.nx + 1)];
+    return n;
+  }
+  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          int ie, int je, double (&f)[2][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
+      return;
+    }
+    const int e = ie + je * g.nx;
+    const double Hq[4] = {H[e], H[e + g.E], H[e + 2 * g.E], H[e + 3 * g.E]};
+    const double cq[4] = {c.Gc_l + 2.0 * Hq[0], c.Gc_l + 2.0 * Hq[1], c.Gc_l + 2.0 * Hq[2],
+                          c.Gc_l + 2.0 * Hq[3]};
+    const double p[4] = {n0.d, n1.d, n2.d, n3.d};
+    phase_element<double>(p, cq, c, f[0]);
+    // b_a = sum_q 2 H_q N_a(q) w detJ
+    const double w2 = 2.0 * c.wdet;
+    f[1][0] = w2 * (NW<0, 0>::v * Hq[0] + NW<1, 0>::v * Hq[1] + NW<2, 0>::v * Hq[2] + NW<3, 0>::v * Hq[3]);
+    f[1][1] = w2 * (NW<0, 1>::v * Hq[0] + NW<1, 1>::v * Hq[1] + NW<2, 1>::v * Hq[2] + NW<3, 1>::v * Hq[3]);
+    f[1][2] = w2 * (NW<0, 2>::v * Hq[0] + NW<1, 2>::v * Hq[1] + NW<2, 2>::v * Hq[2] + NW<3, 2>::v * Hq[3]);
+    f[1][3] = w2 * (NW<0, 3>::v * Hq[0] + NW<1, 3>::v * Hq[1] + NW<2, 3>::v * Hq[2] + NW<3, 3>::v * Hq[3]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) f[0][a] -= f[1][a];
+  }
+  __device__ void store(int i, int j, const double (&v)[2], const Node &, double *red) const {
+    const int k = i + j * (g.nx + 1);
+    double r = v[0], b = v[1];
+    if (nflag[k] & NF_D) { r = 0.0; b = 0.0; }
+    R[k] = sign * r;
+    red[0] += r * r;
+    red[1] += b * b;
+  }
+  __device__ void finish(double *red) const {
+    double v[2] = {red[0], red[1]};
+    block_partial<2>(v, rs.part);
+    if (last_block(rs.counter + 3)) {
+      double s[2];
+      final_sum<2>(rs.part, gridDim.x, s);
+      if (threadIdx.x == 0) {
+        rs.scal[SC_NORM_A] = s[0];
+        rs.scal[SC_NORM_B] = s[1];
+        rs.counter[3] = 0u;
+      }
+    }
+  }
+};
+
+// ---- Jacobi diagonals (inverse, 0 on fixed DOFs)
+template <class TT>
+struct OpTangentDiag {
+  using T = TT;
+  static constexpr int NF = 2;
+  static constexpr int NR = 0;
+  struct Node { T d; };
+  Grid g; ElasCoef c;
+  const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
+  __device__ bool skip() const { return false; }
+  __device__ Node load(int i, int j) const {
+    Node n{T(0)};
+    if (node_exists(g, i, j)) n.d = d[i + j * (g.nx + 1)];
+    return n;
+  }
+  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          int ie, int je, T (&f)[2][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
+      return;
+    }
+    const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
+    elastic_diag_element<T>(dn, qflag[ie + je * g.nx], c, f[0], f[1]);
+  }
+  __device__ void store(int i, int j, const T (&v)[2], const Node &, double *) const {
+    const int k = i + j * (g.nx + 1);
+    const uint8_t nf = nflag[k];
+    Dinv[k] = ((nf & NF_UX) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+    Dinv[k + g.N] = ((nf & NF_UY) || !(v[1] > T(0))) ? T(0) : T(1) / v[1];
+  }
+  __device__ void finish(double *) const {}
+};
+
+template <class TT>
+struct OpPhaseDiag {
+  using T = TT;
+  static constexpr int NF = 1;
+  static constexpr int NR = 0;
+  struct Node { T dummy; };
+  Grid g; PhaseCoef c;
+  const T *coef; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
+  __device__ bool skip() const { return false; }
+  __device__ Node load(int, int) const { return Node{T(0)}; }
+  static __device__ Node shfl_up(const Node &n) { return n; }
+  __device__ void element(const Node &, const Node &, const Node &, const Node &, int ie,
+                          int je, T (&f)[1][4]) const {
+    if (!elem_exists(g, ie, je, eact)) {
+      f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
+      return;
+    }
+    const int e = ie + je * g.nx;
+    const T cq[4] = {coef[e], coef[e + g.E], coef[e + 2 * g.E], coef[e + 3 * g.E]};
+    phase_diag_element<T>(cq, c, f[0]);
+  }
+  __device__ void store(int i, int j, const T (&v)[1], const Node &, double *) const {
+    const int k = i + j * (g.nx + 1);
+    Dinv[k] = ((nflag[k] & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+  }
+  __device__ void finish(double *) const {}
+};
+
+template <class Op>
+hipError_t launch_march(hipStream_t s, const Op &op, const Grid &g, const March &m) {
+  const int waves = m.nstrips * m.nchunks;
+  const int blocks = (waves + WPB - 1) / WPB;
+  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ CG vectors
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pold,
+                                                 const T *Dinv, CgScal *sc, double tol,
+                                                 int maxit, RedScratch rs) {
+  double v[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T ri = r[i];
+    const T zi = Dinv[i] * ri;
+    x[i] = T(0);
+    z[i] = zi;
+    pold[i] = T(0);
+    v[0] += double(ri) * double(zi);
+    v[1] += double(ri) * double(ri);
+  }
+  block_partial<2>(v, rs.part);
+  if (last_block(rs.counter + 4)) {
+    double s[2];
+    final_sum<2>(rs.part, gridDim.x, s);
+    if (threadIdx.x == 0) {
+      sc->rz = s[0];
+      sc->rr = s[1];
+      sc->rr0 = s[1];
+      sc->tol2 = tol * tol;
+      sc->beta = 0.0;
+      sc->alpha = 0.0;
+      sc->pq = 0.0;
+      sc->iters = 0;
+      sc->maxit = maxit;
+      sc->done = (s[1] == 0.0) ? 1 : 0;
+      rs.counter[4] = 0u;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
+                                                   const T *q, const T *Dinv, CgScal *sc,
+                                                   RedScratch rs) {
+  if (sc->done != 0) return;
+  const T alpha = T(sc->alpha);
+  double v[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T xi = x[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    const T zi = Dinv[i] * ri;
+    x[i] = xi;
+    r[i] = ri;
+    z[i] = zi;
+    v[0] += double(ri) * double(zi);
+    v[1] += double(ri) * double(ri);
+  }
+  block_partial<2>(v, rs.part);
+  if (last_block(rs.counter + 5)) {
+    double s[2];
+    final_sum<2>(rs.part, gridDim.x, s);
+    if (threadIdx.x == 0) {
+      const double rz_old = sc->rz;
+      sc->beta = (rz_old != 0.0) ? s[0] / rz_old : 0.0;
+      sc->rz = s[0];
+      sc->rr = s[1];
+      const int it = sc->iters + 1;
+      sc->iters = it;
+      if (!(s[1] <= sc->tol2 * sc->rr0) || !(s[1] == s[1])) {
+        if (!(s[1] == s[1])) sc->done = 2;
+        else if (it >= sc->maxit) sc->done = 3;
+      } else {
+        sc->done = 1;
+      }
+      rs.counter[5] = 0u;
+    }
+  }
+}
+
+int vec_blocks(int n) {
+  int b = (n + TPB - 1) / TPB;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return b;
+}
+
+// ------------------------------------------------------ element kernels
+
+// Quadrature-point update (one thread per element): strain, split energies,
+// history max, tangent indicator bits and the softening gate (Section 3.5).
+__global__ void __launch_bounds__(TPB) k_qp_update(Grid g, Mat mt, QpParams qp,
+                                                   const double *u, const double *d,
+                                                   const uint8_t *eact, const double *Hprev,
+                                                   double *H, double *psi_s, uint8_t *qflag,
+                                                   RedScratch rs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long ng = 0;
+  if (e < g.E) {
+    const int ie = e % g.nx, je = e / g.nx;
+    const bool act = (eact == nullptr) || eact[e] != 0;
+    uint8_t fl = 0;
+    if (!act) {
+      for (int q = 0; q < 4; ++q) {
+        H[e + q * g.E] = Hprev[e + q * g.E];
+        psi_s[e + q * g.E] = 0.0;
+      }
+    } else {
+      const int n0 = ie + je * (g.nx + 1);
+      const int nn[4] = {n0, n0 + 1, n0 + 1 + (g.nx + 1), n0 + (g.nx + 1)};
+      double ux[4], uy[4], dn[4];
+      for (int a = 0; a < 4; ++a) {
+        ux[a] = u[nn[a]];
+        uy[a] = u[nn[a] + g.N];
+        dn[a] = d[nn[a]];
+      }
+      const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy;
+      const double Dbx = ux[1] - ux[0], Dtx = ux[2] - ux[3], Dlx = ux[3] - ux[0], Drx = ux[2] - ux[1];
+      const double Dby = uy[1] - uy[0], Dty = uy[2] - uy[3], Dly = uy[3] - uy[0], Dry = uy[2] - uy[1];
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const double wB = QW<q>::wB, wT = QW<q>::wT, wL = QW<q>::wL, wR = QW<q>::wR;         \
+    const double exx = (wB * Dbx + wT * Dtx) * ihx;                                      \
+    const double uxy = (wL * Dlx + wR * Drx) * ihy;                                      \
+    const double uyx = (wB * Dby + wT * Dty) * ihx;                                      \
+    const double eyy = (wL * Dly + wR * Dry) * ihy;                                      \
+    const double exy = 0.5 * (uxy + uyx);                                                \
+    const double t = exx + eyy;                                                          \
+    const double m3 = t * (1.0 / 3.0);                                                   \
+    const double devdev = (exx - m3) * (exx - m3) + (eyy - m3) * (eyy - m3) + m3 * m3 + 2.0 * exy * exy; \
+    const double tp = t > 0.0 ? t : 0.0;                                                 \
+    const double pvol = 0.5 * mt.K * tp * tp;                                           \
+    const double pdev = mt.mu * devdev;                                                  \
+    const double pplus = pvol + pdev;                                                    \
+    const double hp = Hprev[e + q * g.E];                                                \
+    H[e + q * g.E] = pplus > hp ? pplus : hp;                                            \
+    double ps = 0.0;                                                                     \
+    if (qp.scheme == 1) ps = pvol;                                                       \
+    else if (qp.scheme == 2) ps = pdev;                                                  \
+    else if (qp.scheme == 3) ps = pplus;                                                 \
+    psi_s[e + q * g.E] = ps;                                                             \
+    if (t > 0.0) fl |= uint8_t(1u << q);                                                 \
+    const double dq = interp4<double, q>(dn[0], dn[1], dn[2], dn[3]);                    \
+    if (qp.scheme != 0 && pplus > qp.psi_crit && pplus > hp && dq < qp.d_gate) {          \
+      fl |= uint8_t(1u << (q + 4));                                                      \
+      ng += 1;                                                                           \
+    }                                                                                    \
+  }
+      PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+    }
+    qflag[e] = fl;
+  }
+  // block count of gated points (integer, order-independent)
+  __shared__ unsigned long long shc[TPB / 64];
+  for (int off = 32; off > 0; off >>= 1) ng += __shfl_down(ng, off, 64);
+  if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = ng;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += shc[w];
+    if (s) atomicAdd(rs.icount + IC_GATED, s);
+  }
+}
+
+// Tangent indicator bits only (tr eps > 0 at each QP), for the Newton tangent.
+__global__ void __launch_bounds__(TPB) k_tangent_flags(Grid g, const double *u,
+                                                       const uint8_t *eact, uint8_t *qflag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.E) return;
+  const int ie = e % g.nx, je = e / g.nx;
+  uint8_t fl = 0;
+  if (eact == nullptr || eact[e] != 0) {
+    const int n0 = ie + je * (g.nx + 1);
+    const int nn[4] = {n0, n0 + 1, n0 + 1 + (g.nx + 1), n0 + (g.nx + 1)};
+    double ux[4], uy[4];
+    for (int a = 0; a < 4; ++a) {
+      ux[a] = u[nn[a]];
+      uy[a] = u[nn[a] + g.N];
+    }
+    const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy;
+    const double Dbx = ux[1] - ux[0], Dtx = ux[2] - ux[3];
+    const double Dly = uy[3] - uy[0], Dry = uy[2] - uy[1];
+#define PF_QP(q)                                                                 \
+  {                                                                              \
+    const double exx = (QW<q>::wB * Dbx + QW<q>::wT * Dtx) * ihx;                \
+    const double eyy = (QW<q>::wL * Dly + QW<q>::wR * Dry) * ihy;                \
+    if (exx + eyy > 0.0) fl |= uint8_t(1u << q);                                 \
+  }
+    PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  }
+  qflag[e] = fl;
+}
+
+// Mass coefficient of the augmented block K_dd + K~ (Section 3.4): on gated
+// points c - c_S floored at theta*c, c = Gc/l + 2H, c_S = 8(1-d)^2/g psi_S.
+template <class T>
+__global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta,
+                                                    const double *H, const double *psi_s,
+                                                    const uint8_t *qflag, const double *d,
+                                                    const uint8_t *eact, T *coef,
+                                                    RedScratch rs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long hits = 0;
+  if (e < g.E) {
+    const int ie = e % g.nx, je = e / g.nx;
+    const bool act = (eact == nullptr) || eact[e] != 0;
+    const uint8_t fl = qflag[e];
+    double dn[4] = {0, 0, 0, 0};
+    if (act && (fl >> 4)) {
+      const int n0 = ie + je * (g.nx + 1);
+      dn[0] = d[n0];
+      dn[1] = d[n0 + 1];
+      dn[2] = d[n0 + 1 + (g.nx + 1)];
+      dn[3] = d[n0 + (g.nx + 1)];
+    }
+    const double Gc_l = mt.Gc / mt.l;
+#define PF_QP(q)                                                                 \
+  {                                                                              \
+    const double c = Gc_l + 2.0 * H[e + q * g.E];                                \
+    double ct = act ? c : 0.0;                                                   \
+    if (act && ((fl >> (q + 4)) & 1u)) {                                         \
+      const double dq = interp4<double, q>(dn[0], dn[1], dn[2], dn[3]);          \
+      const double om = 1.0 - dq;                                                \
+      const double cS = 8.0 * om * om / (om * om + mt.eta) * psi_s[e + q * g.E]; \
+      ct = c - cS;                                                               \
+      if (ct < theta * c) {                                                      \
+        ct = theta * c;                                                          \
+        hits += 1;                                                               \
+      }                                                                          \
+    }                                                                            \
+    coef[e + q * g.E] = T(ct);                                                   \
+  }
+    PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  }
+  __shared__ unsigned long long shc[TPB / 64];
+  for (int off = 32; off > 0; off >>= 1) hits += __shfl_down(hits, off, 64);
+  if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = hits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += shc[w];
+    if (s) atomicAdd(rs.icount + IC_FLOOR, s);
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_at2_coef(Grid g, Mat mt, const double *H,
+                                                  const uint8_t *eact, T *coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * g.E) return;
+  const int e = i % g.E;
+  const bool act = (eact == nullptr) || eact[e] != 0;
+  coef[i] = act ? T(mt.Gc / mt.l + 2.0 * H[i]) : T(0);
+}
+
+// Fixed-stress predictor: on gated points with Dd_q > 0 the active energy is
+// advanced to the half step, psi+ (1 + a Dd)^2 on the scheme's part, a =
+// 2(1-d)/g (eq:epn1, e_dev_1/2); elsewhere H is kept.
+template <class TD>
+__global__ void __launch_bounds__(TPB) k_predictor(Grid g, Mat mt, const double *d,
+                                                   const TD *dd, const double *H,
+                                                   const double *psi_s, const uint8_t *qflag,
+                                                   const uint8_t *eact, double *Hhat) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.E) return;
+  const int ie = e % g.nx, je = e / g.nx;
+  const uint8_t fl = qflag[e];
+  const bool act = (eact == nullptr) || eact[e] != 0;
+  if (!act || (fl >> 4) == 0) {
+    for (int q = 0; q < 4; ++q) Hhat[e + q * g.E] = H[e + q * g.E];
+    return;
+  }
+  const int n0 = ie + je * (g.nx + 1);
+  const int nn[4] = {n0, n0 + 1, n0 + 1 + (g.nx + 1), n0 + (g.nx + 1)};
+  double dn[4], ddn[4];
+  for (int a = 0; a < 4; ++a) {
+    dn[a] = d[nn[a]];
+    ddn[a] = double(dd[nn[a]]);
+  }
+#define PF_QP(q)                                                                 \
+  {                                                                              \
+    const double h = H[e + q * g.E];                                             \
+    double out = h;                                                              \
+    const double ddq = interp4<double, q>(ddn[0], ddn[1], ddn[2], ddn[3]);       \
+    if (((fl >> (q + 4)) & 1u) && ddq > 0.0) {                                   \
+      const double dq = interp4<double, q>(dn[0], dn[1], dn[2], dn[3]);          \
+      const double om = 1.0 - dq;                                                \
+      const double a = 2.0 * om / (om * om + mt.eta);                            \
+      const double sc = 1.0 + a * ddq;                                           \
+      const double ph = h + (sc * sc - 1.0) * psi_s[e + q * g.E];                \
+      out = ph > h ? ph : h;                                                     \
+    }                                                                            \
+    Hhat[e + q * g.E] = out;                                                     \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+}
+
+// --------------------------------------------------------- small vectors
+
+__global__ void k_lift(int n, const uint8_t *mask, uint8_t bits, int nmask,
+                       const double *unit, double lam, double *u) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t b = (i < nmask) ? (bits & 0x0f) : (bits >> 4);
+  if (mask[i % nmask] & b) u[i] = lam * unit[i];
+}
+
+template <class TS>
+__global__ void k_axpy_into(int n, double *out, const double *x, double alpha, const TS *y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[i] + alpha * double(y[i]);
+}
+
+template <class TO, class TI>
+__global__ void k_convert(int n, TO *out, const TI *in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = TO(in[i]);
+}
+
+__global__ void k_fill_zero(size_t nwords, uint32_t *p) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < nwords; i += stride) p[i] = 0u;
+}
+
+__global__ void k_fill_zero_bytes(size_t n, uint8_t *p) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Reaction force of a Dirichlet group: fixed-order sum of R over its entries,
+// split by component (single block, deterministic).
+__global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
+                                                   const int8_t *comp, const double *R,
+                                                   RedScratch rs) {
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = R[dof[i]];
+    if (comp[i] == 0) v[0] += r; else v[1] += r;
+  }
+  block_partial<2>(v, rs.part);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rs.scal[SC_SUM_X] = rs.part[0];
+    rs.scal[SC_SUM_Y] = rs.part[kMaxBlocks];
+  }
+}
+
+}  // namespace
+
+// ======================================================== host launchers
+
+March march_shape(const Grid &g, int ch_override) {
+  March m;
+  m.nstrips = (g.nx + 1 + STRIP - 1) / STRIP;
+  int ch = ch_override;
+  if (ch <= 0) {
+    // aim for about 2048 waves (8 per CU) with chunks of 2..32 rows
+    const long long target = 2048;
+    long long c = ((long long)(g.ny + 1) * m.nstrips + target - 1) / target;
+    ch = (int)(c < 2 ? 2 : (c > 32 ? 32 : c));
+  }
+  m.ch = ch;
+  m.nchunks = (g.ny + 1 + ch - 1) / ch;
+  while ((long long)m.nstrips * m.nchunks > (long long)kMaxBlocks * WPB) {
+    m.ch *= 2;
+    m.nchunks = (g.ny + 1 + m.ch - 1) / m.ch;
+  }
+  return m;
+}
+
+template <class T>
+hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
+                   CgScal *sc, double tol, int maxit, RedScratch rs) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_init<T>), dim3(vec_blocks(n)), dim3(TPB), 0, s, n, x,
+                     r, z, p_old, Dinv, sc, tol, maxit, rs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
+                     const T *Dinv, CgScal *sc, RedScratch rs) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(vec_blocks(n)), dim3(TPB), 0, s, n,
+                     x, r, z, p, q, Dinv, sc, rs);
+  return hipGetLastError();
+}
+
+// The fused apply reads beta and done from the scalar block at launch time
+// via a tiny indirection: the op carries the pointer and reads it once.
+template <class T>
+__global__ void __launch_bounds__(TPB) k_tangent_cg(OpTangent<T, true, true> op, Grid g,
+                                                    March ms) {
+  // beta/done are read per block from device memory (uniform loads)
+  op.beta = T(op.sc->beta);
+  op.done = op.sc->done;
+  // body of k_march, specialised
+  using Op = OpTangent<T, true, true>;
+  using Node = typename Op::Node;
+  double red[1] = {0.0};
+  if (op.done == 0) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (w < ms.nstrips * ms.nchunks) {
+      const int strip = w % ms.nstrips;
+      const int chunk = w / ms.nstrips;
+      const int ie = strip * STRIP - 1 + lane;
+      const int j0 = chunk * ms.ch;
+      const int j1 = min(j0 + ms.ch, g.ny + 1);
+      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
+      Node bl = op.load(ie, j0 - 1);
+      Node br = op.load(ie + 1, j0 - 1);
+      T c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
+      for (int je = j0 - 1; je < j1; ++je) {
+        Node tr = op.load(ie + 1, je + 1);
+        Node tl = Op::shfl_up(tr);
+        if (lane == 0) tl = op.load(ie, je + 1);
+        T f[2][4];
+        op.element(bl, br, tr, tl, ie, je, f);
+        T out[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          T A = f[k][1] + c2[k];
+          T Al = __shfl_up(A, 1, 64);
+          out[k] = f[k][0] + c3[k] + Al;
+          c3[k] = f[k][3];
+          c2[k] = f[k][2];
+        }
+        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
+        bl = tl;
+        br = tr;
+      }
+    }
+  }
+  op.finish(red);
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_phase_cg(OpPhase<T, true, true> op, Grid g, March ms) {
+  op.beta = T(op.sc->beta);
+  op.done = op.sc->done;
+  using Op = OpPhase<T, true, true>;
+  using Node = typename Op::Node;
+  double red[1] = {0.0};
+  if (op.done == 0) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (w < ms.nstrips * ms.nchunks) {
+      const int strip = w % ms.nstrips;
+      const int chunk = w / ms.nstrips;
+      const int ie = strip * STRIP - 1 + lane;
+      const int j0 = chunk * ms.ch;
+      const int j1 = min(j0 + ms.ch, g.ny + 1);
+      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
+      Node bl = op.load(ie, j0 - 1);
+      Node br = op.load(ie + 1, j0 - 1);
+      T c2 = T(0), c3 = T(0);
+      for (int je = j0 - 1; je < j1; ++je) {
+        Node tr = op.load(ie + 1, je + 1);
+        Node tl = Op::shfl_up(tr);
+        if (lane == 0) tl = op.load(ie, je + 1);
+        T f[1][4];
+        op.element(bl, br, tr, tl, ie, je, f);
+        T A = f[0][1] + c2;
+        T Al = __shfl_up(A, 1, 64);
+        T out[1] = {f[0][0] + c3 + Al};
+        c3 = f[0][3];
+        c2 = f[0][2];
+        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
+        bl = tl;
+        br = tr;
+      }
+    }
+  }
+  op.finish(red);
+}
+
+template <class T>
+hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                            const T *d, const uint8_t *qflag, const uint8_t *eact,
+                            const uint8_t *nflag, const T *z, const T *p_old, T *p_new, T *q,
+                            CgScal *sc, RedScratch rs) {
+  OpTangent<T, true, true> op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, sc, rs, T(0), 0};
+  const int waves = m.nstrips * m.nchunks;
+  const int blocks = (waves + WPB - 1) / WPB;
+  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tangent_cg<T>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
+                          const T *p_old, T *p_new, T *q, CgScal *sc, RedScratch rs) {
+  OpPhase<T, true, true> op{g, c, coef, eact, nflag, z, p_old, p_new, q, sc, rs, T(0), 0};
+  const int waves = m.nstrips * m.nchunks;
+  const int blocks = (waves + WPB - 1) / WPB;
+  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_phase_cg<T>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                        const T *d, const uint8_t *qflag, const uint8_t *eact,
+                        const uint8_t *nflag, T *Dinv) {
+  OpTangentDiag<T> op{g, c, d, qflag, eact, nflag, Dinv};
+  return launch_march(s, op, g, m);
+}
+
+template <class T>
+hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                      const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv) {
+  OpPhaseDiag<T> op{g, c, coef, eact, nflag, Dinv};
+  return launch_march(s, op, g, m);
+}
+
+hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                               const double *d, const uint8_t *qflag, const uint8_t *eact,
+                               const double *p, double *q) {
+  OpTangent<double, false, false> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q,
+                                     nullptr, RedScratch{}, 0.0, 0};
+  return launch_march(s, op, g, m);
+}
+
+hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                             const double *coef, const uint8_t *eact, const double *p,
+                             double *q) {
+  OpPhase<double, false, false> op{g, c, coef, eact, nullptr, p, nullptr, nullptr, q,
+                                   nullptr, RedScratch{}, 0.0, 0};
+  return launch_march(s, op, g, m);
+}
+
+hipError_t internal_force(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                          const double *u, const double *d, const uint8_t *eact,
+                          const uint8_t *nflag, bool neg, double *R, RedScratch rs) {
+  OpForce op{g, c, u, d, eact, nflag, R, rs, neg ? -1.0 : 1.0};
+  return launch_march(s, op, g, m);
+}
+
+hipError_t phase_residual(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const double *H, const double *d, const uint8_t *eact,
+                          const uint8_t *nflag, bool neg, double *R, RedScratch rs) {
+  OpPhaseRes op{g, c, H, d, eact, nflag, R, rs, neg ? -1.0 : 1.0};
+  return launch_march(s, op, g, m);
+}
+
+hipError_t qp_update(hipStream_t s, const Grid &g, const Mat &mt, const QpParams &qp,
+                     const double *u, const double *d, const uint8_t *eact,
+                     const double *H_prev, double *H, double *psi_s, uint8_t *qflag,
+                     RedScratch rs) {
+  const int blocks = (g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(k_qp_update, dim3(blocks), dim3(TPB), 0, s, g, mt, qp, u, d, eact, H_prev,
+                     H, psi_s, qflag, rs);
+  return hipGetLastError();
+}
+
+hipError_t tangent_flags(hipStream_t s, const Grid &g, const double *u, const uint8_t *eact,
+                         uint8_t *qflag) {
+  const int blocks = (g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(k_tangent_flags, dim3(blocks), dim3(TPB), 0, s, g, u, eact, qflag);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta,
+                      const double *H, const double *psi_s, const uint8_t *qflag,
+                      const double *d, const uint8_t *eact, T *coef, RedScratch rs) {
+  const int blocks = (g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_coef<T>), dim3(blocks), dim3(TPB), 0, s, g, mt,
+                     theta, H, psi_s, qflag, d, eact, coef, rs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t at2_coef(hipStream_t s, const Grid &g, const Mat &mt, const double *H,
+                    const uint8_t *eact, T *coef) {
+  const int blocks = (4 * g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_at2_coef<T>), dim3(blocks), dim3(TPB), 0, s, g, mt, H,
+                     eact, coef);
+  return hipGetLastError();
+}
+
+template <class TD>
+hipError_t predictor(hipStream_t s, const Grid &g, const Mat &mt, const double *d, const TD *dd,
+                     const double *H, const double *psi_s, const uint8_t *qflag,
+                     const uint8_t *eact, double *Hhat) {
+  const int blocks = (g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_predictor<TD>), dim3(blocks), dim3(TPB), 0, s, g, mt, d,
+                     dd, H, psi_s, qflag, eact, Hhat);
+  return hipGetLastError();
+}
+
+hipError_t lift_dirichlet(hipStream_t s, int n, const uint8_t *fixedmask, uint8_t bits,
+                          int nmask, const double *unit, double lam, double *u) {
+  hipLaunchKernelGGL(k_lift, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, fixedmask, bits,
+                     nmask, unit, lam, u);
+  return hipGetLastError();
+}
+
+template <class TS>
+hipError_t axpy_into(hipStream_t s, int n, double *out, const double *x, double alpha,
+                     const TS *y) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_axpy_into<TS>), dim3((n + TPB - 1) / TPB), dim3(TPB), 0,
+                     s, n, out, x, alpha, y);
+  return hipGetLastError();
+}
+
+template <class TO, class TI>
+hipError_t convert(hipStream_t s, int n, TO *out, const TI *in) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_convert<TO, TI>), dim3((n + TPB - 1) / TPB), dim3(TPB), 0,
+                     s, n, out, in);
+  return hipGetLastError();
+}
+
+hipError_t group_sum(hipStream_t s, int n, const int64_t *dof, const int8_t *comp,
+                     const double *R, RedScratch rs) {
+  hipLaunchKernelGGL(k_group_sum, dim3(1), dim3(TPB), 0, s, n, dof, comp, R, rs);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(p) & 3) == 0 && (bytes & 3) == 0) {
+    const size_t nw = bytes / 4;
+    size_t blocks = (nw + TPB - 1) / TPB;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(TPB), 0, s, nw,
+                       reinterpret_cast<uint32_t *>(p));
+  } else {
+    hipLaunchKernelGGL(k_fill_zero_bytes, dim3((unsigned)((bytes + TPB - 1) / TPB)), dim3(TPB), 0,
+                       s, bytes, reinterpret_cast<uint8_t *>(p));
+  }
+  return hipGetLastError();
+}
+
+// -------------------------------------------------- explicit instantiation
+#define PF_INST(T)                                                                              \
+  template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *, CgScal *,    \
+                                 double, int, RedScratch);                                     \
+  template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
+                                   const T *, CgScal *, RedScratch);                           \
+  template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
+                                          const ElasCoef &, const T *, const uint8_t *,        \
+                                          const uint8_t *, const uint8_t *, const T *,         \
+                                          const T *, T *, T *, CgScal *, RedScratch);          \
+  template hipError_t phase_cg_apply<T>(hipStream_t, const Grid &, const March &,              \
+                                        const PhaseCoef &, const T *, const uint8_t *,         \
+                                        const uint8_t *, const T *, const T *, T *, T *,       \
+                                        CgScal *, RedScratch);                                 \
+  template hipError_t tangent_diag<T>(hipStream_t, const Grid &, const March &,                \
+                                      const ElasCoef &, const T *, const uint8_t *,            \
+                                      const uint8_t *, const uint8_t *, T *);                  \
+  template hipError_t phase_diag<T>(hipStream_t, const Grid &, const March &,                  \
+                                    const PhaseCoef &, const T *, const uint8_t *,             \
+                                    const uint8_t *, T *);                                     \
+  template hipError_t trial_coef<T>(hipStream_t, const Grid &, const Mat &, double,            \
+                                    const double *, const double *, const uint8_t *,           \
+                                    const double *, const uint8_t *, T *, RedScratch);         \
+  template hipError_t at2_coef<T>(hipStream_t, const Grid &, const Mat &, const double *,      \
+                                  const uint8_t *, T *);                                       \
+  template hipError_t predictor<T>(hipStream_t, const Grid &, const Mat &, const double *,     \
+                                   const T *, const double *, const double *,                  \
+                                   const uint8_t *, const uint8_t *, double *);                \
+  template hipError_t axpy_into<T>(hipStream_t, int, double *, const double *, double,         \
+                                   const T *);
+
+PF_INST(double)
+PF_INST(float)
+#undef PF_INST
+
+template hipError_t convert<float, double>(hipStream_t, int, float *, const double *);
+template hipError_t convert<double, float>(hipStream_t, int, double *, const float *);
+
+}  // namespace pf

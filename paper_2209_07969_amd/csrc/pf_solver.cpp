@@ -1,0 +1,818 @@
+// Host runtime and C ABI: context, Dirichlet data, Newton for u, PCG drivers,
+// iterative refinement for d, the staggered controller and the op entry
+// points.  Every numerical step is a kernel from pf_kernels.hip; the host
+// reads back only norms, counts and CG status words.
+
+#include "../../include/phasefield.h"
+#include "pf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace pf;
+
+namespace {
+
+constexpr int kGroups = 8;
+
+struct Group {
+  std::vector<int64_t> node;
+  std::vector<int8_t> comp;
+  std::vector<double> val;
+  int64_t *d_dof = nullptr;
+  int8_t *d_comp = nullptr;
+  int n = 0;
+};
+
+// Work vectors of one precision.
+template <class T>
+struct CgBuf {
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr,
+    *Dinv = nullptr;
+  T *d = nullptr;      // d in this precision (operator data of the tangent)
+  T *coef = nullptr;   // [4E] phase coefficient
+};
+
+}  // namespace
+
+struct pf_ctx {
+  Grid g{};
+  Mat mt{};
+  pf_solver_opts opts{};
+  ElasCoef ec{};
+  PhaseCoef pc{};
+  March ms{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  Group groups[kGroups];
+  std::vector<int64_t> dnode;
+  std::vector<double> dval;
+  std::vector<uint8_t> eact_h;
+  std::vector<uint8_t> nflag_h;
+
+  // device state
+  double *u = nullptr, *u_try = nullptr, *d = nullptr;
+  double *H_prev = nullptr, *H = nullptr, *Hhat = nullptr, *psi_s = nullptr;
+  double *Ru = nullptr, *Ru_try = nullptr, *Rd = nullptr, *Rfull = nullptr;
+  double *u_unit = nullptr, *d_fix = nullptr;
+  uint8_t *nflag = nullptr, *qflag = nullptr, *tflag = nullptr, *eact = nullptr;
+  CgBuf<double> bd;
+  CgBuf<float> bf;
+  CgScal *cgs = nullptr;
+  RedScratch rs{};
+  // pinned host mirrors
+  CgScal *cgs_h = nullptr;
+  double *scal_h = nullptr;
+  unsigned long long *icount_h = nullptr;
+  std::vector<void *> allocs;
+
+  // step state
+  bool step_open = false;
+  double step_load = 0.0;
+  double R_ref = 1.0;
+  int64_t gated_last = 0;
+  int64_t n_free_u = 0, n_free_d = 0;
+  pf_step_stats acc{};
+  std::chrono::steady_clock::time_point t_open;
+};
+
+namespace {
+
+pf_status fail(pf_ctx *c, pf_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define PF_HIP(ctx, ...)                                                                 \
+  do {                                                                                   \
+    hipError_t e_ = (__VA_ARGS__);                                                       \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, PF_E_HIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PF_TRY(expr)                \
+  do {                              \
+    pf_status s_ = (expr);          \
+    if (s_ != PF_OK) return s_;     \
+  } while (0)
+
+template <class T>
+pf_status dalloc(pf_ctx *c, T **p, size_t count) {
+  void *v = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  hipError_t e = hipMalloc(&v, bytes);
+  if (e != hipSuccess) return fail(c, PF_E_OOM, "hipMalloc failed");
+  c->allocs.push_back(v);
+  *p = static_cast<T *>(v);
+  e = fill_zero_bytes(c->stream, v, bytes);
+  if (e != hipSuccess) return fail(c, PF_E_HIP, "zero fill failed");
+  return PF_OK;
+}
+
+pf_status sync(pf_ctx *c) {
+  PF_HIP(c, hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+// Read scal[] and integer counters back to the host.
+pf_status read_scal(pf_ctx *c) {
+  PF_HIP(c, hipMemcpyAsync(c->scal_h, c->rs.scal, kScal * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->icount_h, c->rs.icount, kICounters * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+pf_status zero_icount(pf_ctx *c) {
+  PF_HIP(c, fill_zero_bytes(c->stream, c->rs.icount, kICounters * sizeof(unsigned long long)));
+  return PF_OK;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// Rebuild node flags and Dirichlet value arrays from the host-side data.
+pf_status upload_constraints(pf_ctx *c) {
+  const Grid &g = c->g;
+  std::vector<uint8_t> nf(g.N, 0);
+  std::vector<double> unit(2 * (size_t)g.N, 0.0), dfix(g.N, 0.0);
+  // inactive nodes: not touched by any active element
+  if (!c->eact_h.empty()) {
+    std::vector<uint8_t> touched(g.N, 0);
+    for (int je = 0; je < g.ny; ++je)
+      for (int ie = 0; ie < g.nx; ++ie)
+        if (c->eact_h[ie + (size_t)je * g.nx]) {
+          int n0 = ie + je * (g.nx + 1);
+          touched[n0] = touched[n0 + 1] = touched[n0 + 1 + g.nx + 1] = touched[n0 + g.nx + 1] = 1;
+        }
+    for (int k = 0; k < g.N; ++k)
+      if (!touched[k]) nf[k] = NF_UX | NF_UY | NF_D;
+  }
+  for (int gi = 0; gi < kGroups; ++gi) {
+    const Group &gr = c->groups[gi];
+    for (size_t k = 0; k < gr.node.size(); ++k) {
+      const int64_t n = gr.node[k];
+      nf[n] |= (gr.comp[k] == 0) ? NF_UX : NF_UY;
+      unit[(size_t)n + (gr.comp[k] == 0 ? 0 : (size_t)g.N)] = gr.val[k];
+    }
+  }
+  for (size_t k = 0; k < c->dnode.size(); ++k) {
+    nf[c->dnode[k]] |= NF_D;
+    dfix[c->dnode[k]] = c->dval[k];
+  }
+  // inactive nodes keep zero values
+  if (!c->eact_h.empty()) {
+    std::vector<uint8_t> touched(g.N, 0);
+    for (int je = 0; je < g.ny; ++je)
+      for (int ie = 0; ie < g.nx; ++ie)
+        if (c->eact_h[ie + (size_t)je * g.nx]) {
+          int n0 = ie + je * (g.nx + 1);
+          touched[n0] = touched[n0 + 1] = touched[n0 + 1 + g.nx + 1] = touched[n0 + g.nx + 1] = 1;
+        }
+    for (int k = 0; k < g.N; ++k)
+      if (!touched[k]) {
+        unit[k] = 0.0;
+        unit[k + (size_t)g.N] = 0.0;
+        dfix[k] = 0.0;
+      }
+  }
+  c->nflag_h = nf;
+  int64_t fu = 0, fd = 0;
+  for (int k = 0; k < g.N; ++k) {
+    fu += !(nf[k] & NF_UX);
+    fu += !(nf[k] & NF_UY);
+    fd += !(nf[k] & NF_D);
+  }
+  c->n_free_u = fu;
+  c->n_free_d = fd;
+  PF_HIP(c, hipMemcpyAsync(c->nflag, nf.data(), g.N, hipMemcpyHostToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->u_unit, unit.data(), unit.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->d_fix, dfix.data(), dfix.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  // group DOF lists (SoA index node + comp*N)
+  for (int gi = 0; gi < kGroups; ++gi) {
+    Group &gr = c->groups[gi];
+    gr.n = (int)gr.node.size();
+    if (gr.n == 0) continue;
+    std::vector<int64_t> dof(gr.n);
+    for (int k = 0; k < gr.n; ++k) dof[k] = gr.node[k] + (gr.comp[k] ? (int64_t)g.N : 0);
+    if (gr.d_dof) { (void)hipFree(gr.d_dof); gr.d_dof = nullptr; }
+    if (gr.d_comp) { (void)hipFree(gr.d_comp); gr.d_comp = nullptr; }
+    PF_HIP(c, hipMalloc(&gr.d_dof, gr.n * sizeof(int64_t)));
+    PF_HIP(c, hipMalloc(&gr.d_comp, gr.n));
+    PF_TRY(sync(c));
+    PF_HIP(c, hipMemcpy(gr.d_dof, dof.data(), gr.n * sizeof(int64_t), hipMemcpyHostToDevice));
+    PF_HIP(c, hipMemcpy(gr.d_comp, gr.comp.data(), gr.n, hipMemcpyHostToDevice));
+  }
+  return sync(c);
+}
+
+// ------------------------------------------------------------------ PCG
+
+enum Kind { K_ELASTIC = 0, K_PHASE = 1 };
+
+template <class T>
+CgBuf<T> &buf(pf_ctx *c);
+template <>
+CgBuf<double> &buf<double>(pf_ctx *c) { return c->bd; }
+template <>
+CgBuf<float> &buf<float>(pf_ctx *c) { return c->bf; }
+
+// Solve A x = r0 (r0 already in b.r, zero on fixed DOFs) from x = 0 with
+// Jacobi PCG to ||r|| <= tol ||r0||.  b.Dinv must hold the inverse diagonal.
+template <class T>
+pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
+  CgBuf<T> &b = buf<T>(c);
+  const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
+  PF_HIP(c, cg_init<T>(c->stream, n, b.x, b.r, b.z, b.p0, b.Dinv, c->cgs, tol, c->opts.max_cg,
+                       c->rs));
+  T *pold = b.p0, *pnew = b.p1;
+  const int batch = std::max(1, c->opts.cg_check);
+  for (;;) {
+    for (int k = 0; k < batch; ++k) {
+      if (kind == K_ELASTIC) {
+        PF_HIP(c, tangent_cg_apply<T>(c->stream, c->g, c->ms, c->ec, b.d, c->tflag, c->eact,
+                                      c->nflag, b.z, pold, pnew, b.q, c->cgs, c->rs));
+      } else {
+        PF_HIP(c, phase_cg_apply<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                    b.z, pold, pnew, b.q, c->cgs, c->rs));
+      }
+      PF_HIP(c, cg_update<T>(c->stream, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, c->cgs, c->rs));
+      std::swap(pold, pnew);
+    }
+    PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, sizeof(CgScal), hipMemcpyDeviceToHost, c->stream));
+    PF_TRY(sync(c));
+    if (c->cgs_h->done != 0) break;
+  }
+  *iters = c->cgs_h->iters;
+  *status = c->cgs_h->done;
+  return PF_OK;
+}
+
+// ------------------------------------------------------- displacement
+
+pf_status residual_u(pf_ctx *c, const double *u, double *R, double *norm) {
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, u, c->d, c->eact, c->nflag, true, R,
+                           c->rs));
+  PF_TRY(read_scal(c));
+  *norm = std::sqrt(c->scal_h[SC_NORM_A]);
+  if (!is_finite(*norm)) return fail(c, PF_E_NONFINITE, "displacement residual is not finite");
+  return PF_OK;
+}
+
+template <class T>
+pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
+  *ok = true;
+  double nr = 0.0;
+  PF_TRY(residual_u(c, c->u, c->Ru, &nr));
+  const double tol = c->opts.tol_newton * c->R_ref;
+  const bool mixed = std::is_same<T, float>::value;
+  const double tol_lin = mixed ? c->opts.tol_inner : c->opts.tol_pcg;
+  int it = 0;
+  CgBuf<T> &b = buf<T>(c);
+  const int n2 = 2 * c->g.N;
+  while (nr > tol) {
+    if (it >= c->opts.max_newton) {
+      *ok = false;
+      break;
+    }
+    PF_HIP(c, tangent_flags(c->stream, c->g, c->u, c->eact, c->tflag));
+    if (mixed) {
+      PF_HIP(c, convert<float, double>(c->stream, c->g.N, c->bf.d, c->d));
+      PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.r, c->Ru));
+    } else {
+      PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    PF_HIP(c, tangent_diag<T>(c->stream, c->g, c->ms, c->ec, b.d, c->tflag, c->eact, c->nflag,
+                              b.Dinv));
+    int iters = 0, status = 0;
+    PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status));
+    st->n_cg_u += iters;
+    st->dof_updates += (double)iters * (double)c->n_free_u;
+    if (status == 3) st->cg_not_converged += 1;
+    if (status == 2 && iters == 0)
+      return fail(c, PF_E_BREAKDOWN, "displacement CG breakdown");
+    double alpha = 1.0, nt = 0.0;
+    int halv = 0;
+    for (;;) {
+      PF_HIP(c, axpy_into<T>(c->stream, n2, c->u_try, c->u, alpha, b.x));
+      PF_TRY(residual_u(c, c->u_try, c->Ru_try, &nt));
+      if (nt < nr || halv == 5) break;
+      alpha *= 0.5;
+      ++halv;
+    }
+    std::swap(c->u, c->u_try);
+    std::swap(c->Ru, c->Ru_try);
+    nr = nt;
+    ++it;
+  }
+  st->n_newton += it;
+  return PF_OK;
+}
+
+pf_status newton(pf_ctx *c, pf_step_stats *st, bool *ok) {
+  if (c->opts.precision == PF_MIXED) return newton_impl<float>(c, st, ok);
+  return newton_impl<double>(c, st, ok);
+}
+
+// ------------------------------------------------------------- phase
+
+pf_status phase_res(pf_ctx *c, const double *Hs, bool neg, double *nR, double *nb) {
+  PF_HIP(c, phase_residual(c->stream, c->g, c->ms, c->pc, Hs, c->d, c->eact, c->nflag, neg,
+                           c->Rd, c->rs));
+  PF_TRY(read_scal(c));
+  *nR = std::sqrt(c->scal_h[SC_NORM_A]);
+  *nb = std::sqrt(c->scal_h[SC_NORM_B]);
+  if (!is_finite(*nR) || !is_finite(*nb)) return fail(c, PF_E_NONFINITE, "phase residual is not finite");
+  return PF_OK;
+}
+
+// Evolution solve K_dd(Hs) d = b(Hs): correction solves d += delta with
+// delta from PCG on the residual; FP64: one solve, mixed: refinement until
+// ||R_d|| <= tol_pcg ||R_d(start)||.
+template <class T>
+pf_status phase_solve_impl(pf_ctx *c, const double *Hs, pf_step_stats *st) {
+  const bool mixed = std::is_same<T, float>::value;
+  CgBuf<T> &b = buf<T>(c);
+  const int n = c->g.N;
+  PF_HIP(c, at2_coef<T>(c->stream, c->g, c->mt, Hs, c->eact, b.coef));
+  PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv));
+  double nR0 = 0.0, nb = 0.0;
+  PF_TRY(phase_res(c, Hs, true, &nR0, &nb));
+  double nR = nR0;
+  const int max_refine = mixed ? 30 : 1;
+  for (int k = 0; k < max_refine; ++k) {
+    if (nR == 0.0) break;
+    if (mixed && k > 0 && nR <= c->opts.tol_pcg * nR0) break;
+    if (mixed) {
+      PF_HIP(c, convert<float, double>(c->stream, n, c->bf.r, c->Rd));
+    } else {
+      PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    int iters = 0, status = 0;
+    PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status));
+    st->n_cg_d += iters;
+    st->dof_updates += (double)iters * (double)c->n_free_d;
+    if (status == 3) st->cg_not_converged += 1;
+    PF_HIP(c, axpy_into<T>(c->stream, n, c->d, c->d, 1.0, b.x));
+    if (mixed) PF_TRY(phase_res(c, Hs, true, &nR, &nb));
+  }
+  st->n_dsolve += 1;
+  return PF_OK;
+}
+
+pf_status phase_solve(pf_ctx *c, const double *Hs, pf_step_stats *st) {
+  if (c->opts.precision == PF_MIXED) return phase_solve_impl<float>(c, Hs, st);
+  return phase_solve_impl<double>(c, Hs, st);
+}
+
+// Trial increment with the augmented block (Section 3.4) and the predictor
+// (Sections 3.3, 3.5); writes Hhat.
+template <class T>
+pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
+  CgBuf<T> &b = buf<T>(c);
+  const bool mixed = std::is_same<T, float>::value;
+  const int n = c->g.N;
+  PF_TRY(zero_icount(c));
+  PF_HIP(c, trial_coef<T>(c->stream, c->g, c->mt, c->opts.trial_floor, c->H, c->psi_s, c->qflag,
+                          c->d, c->eact, b.coef, c->rs));
+  PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv));
+  double nR = 0.0, nb = 0.0;
+  PF_TRY(phase_res(c, c->H, true, &nR, &nb));   // also reads icount (floor hits)
+  st->floor_hits += (int64_t)c->icount_h[IC_FLOOR];
+  if (mixed) {
+    PF_HIP(c, convert<float, double>(c->stream, n, c->bf.r, c->Rd));
+  } else {
+    PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  }
+  int iters = 0, status = 0;
+  PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status));
+  st->n_cg_trial += iters;
+  st->dof_updates += (double)iters * (double)c->n_free_d;
+  if (status == 3) st->cg_not_converged += 1;
+  if (status == 2) return fail(c, PF_E_BREAKDOWN, "trial CG breakdown");
+  PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, b.x, c->H, c->psi_s, c->qflag, c->eact,
+                         c->Hhat));
+  st->n_trial += 1;
+  return PF_OK;
+}
+
+pf_status trial(pf_ctx *c, pf_step_stats *st) {
+  if (c->opts.precision == PF_MIXED) return trial_impl<float>(c, st);
+  return trial_impl<double>(c, st);
+}
+
+// QP update from the current (u, d) and the staggered residual.
+pf_status qp_and_residual(pf_ctx *c, double *r) {
+  PF_TRY(zero_icount(c));
+  QpParams qp{c->opts.scheme, c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (2.0 * c->mt.l),
+              c->opts.d_gate};
+  PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, c->u, c->d, c->eact, c->H_prev, c->H, c->psi_s,
+                      c->qflag, c->rs));
+  double nR = 0.0, nb = 0.0;
+  PF_TRY(phase_res(c, c->H, false, &nR, &nb));   // reads icount too
+  c->gated_last = (int64_t)c->icount_h[IC_GATED];
+  *r = (nb > 0.0) ? nR / nb : nR;
+  return PF_OK;
+}
+
+pf_status reaction(pf_ctx *c, int group, double f[2]) {
+  Group &gr = c->groups[group];
+  if (gr.n == 0) {
+    f[0] = f[1] = 0.0;
+    return PF_OK;
+  }
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, c->u, c->d, c->eact, nullptr, false,
+                           c->Rfull, c->rs));
+  PF_HIP(c, group_sum(c->stream, gr.n, gr.d_dof, gr.d_comp, c->Rfull, c->rs));
+  PF_TRY(read_scal(c));
+  f[0] = c->scal_h[SC_SUM_X];
+  f[1] = c->scal_h[SC_SUM_Y];
+  return PF_OK;
+}
+
+int load_group_of(pf_ctx *c) {
+  // the loaded group is group 1 by convention (group 0 = support)
+  return c->groups[1].n > 0 ? 1 : 0;
+}
+
+pf_status open_step(pf_ctx *c, double lam) {
+  c->acc = pf_step_stats{};
+  c->acc.converged = 1;
+  c->t_open = std::chrono::steady_clock::now();
+  const int n2 = 2 * c->g.N;
+  PF_HIP(c, lift_dirichlet(c->stream, n2, c->nflag, NF_UX | (NF_UY << 4), c->g.N, c->u_unit, lam,
+                           c->u));
+  PF_HIP(c, lift_dirichlet(c->stream, c->g.N, c->nflag, NF_D | (NF_D << 4), c->g.N, c->d_fix, 1.0,
+                           c->d));
+  double R0 = 0.0;
+  PF_TRY(residual_u(c, c->u, c->Ru, &R0));
+  c->R_ref = R0 > 0.0 ? R0 : 1.0;
+  c->step_open = true;
+  c->step_load = lam;
+  bool ok = true;
+  PF_TRY(newton(c, &c->acc, &ok));
+  c->acc.n_stag = 1;
+  if (!ok) c->acc.converged = 0;
+  double r = 0.0;
+  PF_TRY(qp_and_residual(c, &r));
+  c->acc.r_stag = r;
+  c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, 0);
+  return PF_OK;
+}
+
+pf_status iterate_once(pf_ctx *c) {
+  const double *Hs = c->H;
+  if (c->opts.scheme != PF_ST) {
+    c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, c->gated_last);
+    if (c->gated_last > 0) {
+      PF_TRY(trial(c, &c->acc));
+      Hs = c->Hhat;
+    }
+  }
+  PF_TRY(phase_solve(c, Hs, &c->acc));
+  bool ok = true;
+  PF_TRY(newton(c, &c->acc, &ok));
+  if (!ok) c->acc.converged = 0;
+  c->acc.n_stag += 1;
+  double r = 0.0;
+  PF_TRY(qp_and_residual(c, &r));
+  c->acc.r_stag = r;
+  return PF_OK;
+}
+
+void finish_stats(pf_ctx *c, pf_step_stats *st) {
+  auto t = std::chrono::steady_clock::now();
+  c->acc.time_ms = std::chrono::duration<double, std::milli>(t - c->t_open).count();
+  if (st) *st = c->acc;
+}
+
+pf_status commit(pf_ctx *c) {
+  std::swap(c->H_prev, c->H);
+  c->step_open = false;
+  double f[2];
+  PF_TRY(reaction(c, load_group_of(c), f));
+  c->acc.force[0] = f[0];
+  c->acc.force[1] = f[1];
+  return PF_OK;
+}
+
+pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
+  if (o->scheme < 0 || o->scheme > 3) { *msg = "scheme"; return PF_E_INVALID_ARG; }
+  if (o->precision < 0 || o->precision > 1) { *msg = "precision"; return PF_E_INVALID_ARG; }
+  if (o->precond != PF_PC_JACOBI) { *msg = "only the Jacobi preconditioner is available"; return PF_E_INVALID_ARG; }
+  if (!(o->tol_stag > 0) || !(o->tol_pcg > 0) || !(o->tol_newton > 0) || !(o->tol_inner > 0)) {
+    *msg = "tolerances must be > 0";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) { *msg = "iteration limits"; return PF_E_INVALID_ARG; }
+  if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
+  return PF_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void pf_default_opts(pf_solver_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->scheme = PF_ST;
+  o->precision = PF_FP64;
+  o->precond = PF_PC_JACOBI;
+  o->cheb_degree = 4;
+  o->tol_stag = 1e-5;
+  o->tol_pcg = 1e-10;
+  o->tol_newton = 1e-9;
+  o->tol_inner = 1e-5;
+  o->max_stag = 500;
+  o->max_newton = 25;
+  o->max_cg = 200000;
+  o->cg_check = 32;
+  o->psi_crit = -1.0;
+  o->d_gate = 0.95;
+  o->trial_floor = 0.1;
+}
+
+const char *pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "ok";
+    case PF_E_INVALID_ARG: return "invalid argument";
+    case PF_E_OOM: return "out of device memory";
+    case PF_E_HIP: return "HIP runtime error";
+    case PF_E_STATE: return "invalid state";
+    case PF_E_NOT_CONVERGED: return "not converged";
+    case PF_E_BREAKDOWN: return "CG breakdown";
+    case PF_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char *pf_last_error(const pf_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_solver_opts *opts,
+                    void *hip_stream, pf_ctx **out) {
+  if (!mesh || !mat || !out) return PF_E_INVALID_ARG;
+  *out = nullptr;
+  if (mesh->nx < 1 || mesh->ny < 1 || !(mesh->lx > 0) || !(mesh->ly > 0)) return PF_E_INVALID_ARG;
+  const long long N = (long long)(mesh->nx + 1) * (mesh->ny + 1);
+  if (2 * N >= (1LL << 31)) return PF_E_INVALID_ARG;
+  if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0) || !(mat->l > 0) ||
+      !(mat->eta >= 0) || (mat->split != PF_SPLIT_VD && mat->split != PF_SPLIT_SPECTRAL))
+    return PF_E_INVALID_ARG;
+  pf_solver_opts o;
+  if (opts) o = *opts; else pf_default_opts(&o);
+  std::string msg;
+  if (check_opts(&o, &msg) != PF_OK) return PF_E_INVALID_ARG;
+  if (mat->split != PF_SPLIT_VD) return PF_E_INVALID_ARG;   // spectral: not built yet
+
+  pf_ctx *c = new pf_ctx();
+  c->opts = o;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetDevice(&c->device);
+  Grid &g = c->g;
+  g.nx = mesh->nx; g.ny = mesh->ny;
+  g.N = (int)N; g.E = mesh->nx * mesh->ny;
+  g.hx = mesh->lx / mesh->nx; g.hy = mesh->ly / mesh->ny;
+  Mat &mt = c->mt;
+  mt.mu = mat->E / (2.0 * (1.0 + mat->nu));
+  mt.lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+  mt.K = mt.lam + 2.0 * mt.mu / 3.0;
+  mt.Gc = mat->Gc; mt.l = mat->l; mt.eta = mat->eta; mt.split = mat->split;
+  c->ec = ElasCoef{2.0 * mt.mu, mt.K, mt.lam, mt.mu, mt.eta, 1.0 / g.hx, 1.0 / g.hy,
+                   g.hy / 4.0, g.hx / 4.0};
+  c->pc = PhaseCoef{mt.Gc * mt.l, mt.Gc / mt.l, g.hx * g.hy / 4.0, 1.0 / g.hx, 1.0 / g.hy,
+                    g.hy / 4.0, g.hx / 4.0};
+  c->ms = march_shape(g, 0);
+
+  pf_status s = PF_OK;
+  auto A = [&](auto **p, size_t n) {
+    if (s == PF_OK) s = dalloc(c, p, n);
+  };
+  const size_t n2 = 2 * (size_t)g.N, E4 = 4 * (size_t)g.E;
+  A(&c->u, n2); A(&c->u_try, n2); A(&c->d, g.N);
+  A(&c->H_prev, E4); A(&c->H, E4); A(&c->Hhat, E4); A(&c->psi_s, E4);
+  A(&c->Ru, n2); A(&c->Ru_try, n2); A(&c->Rd, g.N); A(&c->Rfull, n2);
+  A(&c->u_unit, n2); A(&c->d_fix, g.N);
+  A(&c->nflag, g.N); A(&c->qflag, g.E); A(&c->tflag, g.E);
+  A(&c->bd.x, n2); A(&c->bd.r, n2); A(&c->bd.z, n2); A(&c->bd.p0, n2); A(&c->bd.p1, n2);
+  A(&c->bd.q, n2); A(&c->bd.Dinv, n2); A(&c->bd.coef, E4);
+  c->bd.d = c->d;
+  if (o.precision == PF_MIXED) {
+    A(&c->bf.x, n2); A(&c->bf.r, n2); A(&c->bf.z, n2); A(&c->bf.p0, n2); A(&c->bf.p1, n2);
+    A(&c->bf.q, n2); A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
+  }
+  A(&c->cgs, 1);
+  A(&c->rs.part, (size_t)kRedSlots * kMaxBlocks);
+  A(&c->rs.counter, kRedCounters);
+  A(&c->rs.icount, kICounters);
+  A(&c->rs.scal, kScal);
+  if (mesh->elem_active) {
+    c->eact_h.assign(mesh->elem_active, mesh->elem_active + g.E);
+    A(&c->eact, g.E);
+    if (s == PF_OK &&
+        hipMemcpyAsync(c->eact, c->eact_h.data(), g.E, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      s = PF_E_HIP;
+  }
+  if (s == PF_OK) {
+    if (hipHostMalloc((void **)&c->cgs_h, sizeof(CgScal)) != hipSuccess ||
+        hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess)
+      s = PF_E_OOM;
+  }
+  if (s == PF_OK) s = upload_constraints(c);
+  if (s != PF_OK) {
+    pf_destroy(c);
+    return s;
+  }
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf_destroy(pf_ctx *c) {
+  if (!c) return PF_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  for (auto &gr : c->groups) {
+    if (gr.d_dof) (void)hipFree(gr.d_dof);
+    if (gr.d_comp) (void)hipFree(gr.d_comp);
+  }
+  if (c->cgs_h) (void)hipHostFree(c->cgs_h);
+  if (c->scal_h) (void)hipHostFree(c->scal_h);
+  if (c->icount_h) (void)hipHostFree(c->icount_h);
+  delete c;
+  return PF_OK;
+}
+
+pf_status pf_set_dirichlet_u(pf_ctx *c, int32_t group, int64_t n, const int64_t *node,
+                             const int8_t *comp, const double *val) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (c->step_open) return fail(c, PF_E_STATE, "cannot change constraints inside a step");
+  if (group < 0 || group >= kGroups || n < 0 || (n > 0 && (!node || !comp || !val)))
+    return fail(c, PF_E_INVALID_ARG, "bad Dirichlet group arguments");
+  Group &gr = c->groups[group];
+  for (int64_t k = 0; k < n; ++k) {
+    if (node[k] < 0 || node[k] >= c->g.N) return fail(c, PF_E_INVALID_ARG, "node out of range");
+    if (comp[k] != 0 && comp[k] != 1) return fail(c, PF_E_INVALID_ARG, "component must be 0 or 1");
+    if (!is_finite(val[k])) return fail(c, PF_E_NONFINITE, "non-finite Dirichlet value");
+  }
+  gr.node.assign(node, node + n);
+  gr.comp.assign(comp, comp + n);
+  gr.val.assign(val, val + n);
+  return upload_constraints(c);
+}
+
+pf_status pf_set_dirichlet_d(pf_ctx *c, int64_t n, const int64_t *node, const double *value) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (c->step_open) return fail(c, PF_E_STATE, "cannot change constraints inside a step");
+  if (n < 0 || (n > 0 && (!node || !value))) return fail(c, PF_E_INVALID_ARG, "bad arguments");
+  for (int64_t k = 0; k < n; ++k) {
+    if (node[k] < 0 || node[k] >= c->g.N) return fail(c, PF_E_INVALID_ARG, "node out of range");
+    if (!is_finite(value[k])) return fail(c, PF_E_NONFINITE, "non-finite Dirichlet value");
+  }
+  c->dnode.assign(node, node + n);
+  c->dval.assign(value, value + n);
+  PF_TRY(upload_constraints(c));
+  // impose on the committed state right away
+  PF_HIP(c, lift_dirichlet(c->stream, c->g.N, c->nflag, NF_D | (NF_D << 4), c->g.N, c->d_fix,
+                           1.0, c->d));
+  return sync(c);
+}
+
+pf_status pf_free_dofs(pf_ctx *c, int64_t *nu, int64_t *nd) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (nu) *nu = c->n_free_u;
+  if (nd) *nd = c->n_free_d;
+  return PF_OK;
+}
+
+pf_status pf_staggered_iterate(pf_ctx *c, double lam, pf_step_stats *st) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (!is_finite(lam)) return fail(c, PF_E_INVALID_ARG, "non-finite load factor");
+  pf_status s;
+  if (!c->step_open) {
+    s = open_step(c, lam);
+  } else {
+    if (lam != c->step_load) return fail(c, PF_E_STATE, "load factor differs from the open step");
+    s = iterate_once(c);
+  }
+  finish_stats(c, st);
+  return s;
+}
+
+pf_status pf_commit_step(pf_ctx *c) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (!c->step_open) return fail(c, PF_E_STATE, "no open step");
+  return commit(c);
+}
+
+pf_status pf_load_step(pf_ctx *c, double lam, pf_step_stats *st) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (c->step_open) return fail(c, PF_E_STATE, "a step is already open");
+  if (!is_finite(lam)) return fail(c, PF_E_INVALID_ARG, "non-finite load factor");
+  pf_status s = open_step(c, lam);
+  if (s != PF_OK) { c->step_open = false; finish_stats(c, st); return s; }
+  while (c->acc.r_stag > c->opts.tol_stag && c->acc.n_stag < c->opts.max_stag) {
+    s = iterate_once(c);
+    if (s != PF_OK) { c->step_open = false; finish_stats(c, st); return s; }
+  }
+  const bool conv = c->acc.r_stag <= c->opts.tol_stag;
+  s = commit(c);
+  if (!conv) c->acc.converged = 0;
+  finish_stats(c, st);
+  if (s != PF_OK) return s;
+  return c->acc.converged ? PF_OK : PF_E_NOT_CONVERGED;
+}
+
+pf_status pf_reaction_force(pf_ctx *c, int32_t group, double force[2]) {
+  if (!c || !force || group < 0 || group >= kGroups) return PF_E_INVALID_ARG;
+  return reaction(c, group, force);
+}
+
+pf_status pf_get_state(pf_ctx *c, double *u, double *d, double *H) {
+  if (!c) return PF_E_INVALID_ARG;
+  PF_TRY(sync(c));
+  if (u) PF_HIP(c, hipMemcpy(u, c->u, 2 * (size_t)c->g.N * sizeof(double), hipMemcpyDeviceToHost));
+  if (d) PF_HIP(c, hipMemcpy(d, c->d, (size_t)c->g.N * sizeof(double), hipMemcpyDeviceToHost));
+  if (H) {
+    const double *src = c->step_open ? c->H : c->H_prev;
+    PF_HIP(c, hipMemcpy(H, src, 4 * (size_t)c->g.E * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return PF_OK;
+}
+
+pf_status pf_set_state(pf_ctx *c, const double *u, const double *d, const double *H) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (c->step_open) return fail(c, PF_E_STATE, "cannot set state inside a step");
+  const size_t n2 = 2 * (size_t)c->g.N, n = c->g.N, e4 = 4 * (size_t)c->g.E;
+  if (u) for (size_t k = 0; k < n2; ++k) if (!is_finite(u[k])) return fail(c, PF_E_NONFINITE, "u has NaN/Inf");
+  if (d) for (size_t k = 0; k < n; ++k) if (!is_finite(d[k])) return fail(c, PF_E_NONFINITE, "d has NaN/Inf");
+  if (H) for (size_t k = 0; k < e4; ++k) if (!is_finite(H[k])) return fail(c, PF_E_NONFINITE, "H has NaN/Inf");
+  PF_TRY(sync(c));
+  if (u) PF_HIP(c, hipMemcpy(c->u, u, n2 * sizeof(double), hipMemcpyHostToDevice));
+  if (d) PF_HIP(c, hipMemcpy(c->d, d, n * sizeof(double), hipMemcpyHostToDevice));
+  if (H) PF_HIP(c, hipMemcpy(c->H_prev, H, e4 * sizeof(double), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+// ------------------------------------------------------------- op entry
+
+pf_status pf_op_internal_force(pf_ctx *c, const double *u, const double *d, double *R) {
+  if (!c || !u || !d || !R) return PF_E_INVALID_ARG;
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, u, d, c->eact, nullptr, false, R, c->rs));
+  return PF_OK;
+}
+
+pf_status pf_op_tangent_apply(pf_ctx *c, const double *u, const double *d, const double *p,
+                              double *q) {
+  if (!c || !u || !d || !p || !q) return PF_E_INVALID_ARG;
+  PF_HIP(c, tangent_flags(c->stream, c->g, u, c->eact, c->tflag));
+  PF_HIP(c, tangent_apply_plain(c->stream, c->g, c->ms, c->ec, d, c->tflag, c->eact, p, q));
+  return PF_OK;
+}
+
+pf_status pf_op_phase_apply(pf_ctx *c, const double *coef, const double *p, double *q) {
+  if (!c || !coef || !p || !q) return PF_E_INVALID_ARG;
+  PF_HIP(c, phase_apply_plain(c->stream, c->g, c->ms, c->pc, coef, c->eact, p, q));
+  return PF_OK;
+}
+
+pf_status pf_op_qp_update(pf_ctx *c, int32_t scheme, const double *u, const double *d,
+                          const double *H_prev, double *H, double *psi_s, uint8_t *flags,
+                          int64_t *n_gated) {
+  if (!c || !u || !d || !H_prev || !H || !psi_s || !flags) return PF_E_INVALID_ARG;
+  if (scheme < 0 || scheme > 3) return fail(c, PF_E_INVALID_ARG, "scheme");
+  PF_TRY(zero_icount(c));
+  QpParams qp{scheme, c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (2.0 * c->mt.l),
+              c->opts.d_gate};
+  PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, u, d, c->eact, H_prev, H, psi_s, flags, c->rs));
+  if (n_gated) {
+    PF_TRY(read_scal(c));
+    *n_gated = (int64_t)c->icount_h[IC_GATED];
+  }
+  return PF_OK;
+}
+
+pf_status pf_op_predictor(pf_ctx *c, const double *d, const double *dd, const double *H,
+                          const double *psi_s, const uint8_t *flags, double *Hhat) {
+  if (!c || !d || !dd || !H || !psi_s || !flags || !Hhat) return PF_E_INVALID_ARG;
+  PF_HIP(c, predictor<double>(c->stream, c->g, c->mt, d, dd, H, psi_s, flags, c->eact, Hhat));
+  return PF_OK;
+}
+
+}  // extern "C"

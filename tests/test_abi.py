@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every entry point the header declares
+(no device needed, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phasefield.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for need in ("pf_create", "pf_load_step", "pf_staggered_iterate", "pf_reaction_force",
+                 "pf_get_state", "pf_set_state", "pf_destroy"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(pf.EXPORTED) == set(declared_functions())
+
+
+def test_default_opts_and_status_strings():
+    import paper_2209_07969_amd as pf
+    o = pf.default_opts()
+    assert o.tol_stag == 1e-5 and o.tol_pcg == 1e-10 and o.d_gate == 0.95
+    assert o.trial_floor == 0.1 and o.max_stag == 500
+    lib = pf.load_library()
+    assert lib.pf_status_string(0) == b"ok"
+    assert lib.pf_status_string(6) == b"CG breakdown"
+
+
+def test_create_rejects_bad_arguments_without_device():
+    """Argument validation happens before any device call."""
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    h = ctypes.c_void_p()
+    mesh = pf.MeshDesc(0, 4, 1.0, 1.0, None)
+    mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
+    assert lib.pf_create(ctypes.byref(mesh), ctypes.byref(mat), None, None, ctypes.byref(h)) == 1
+    mesh = pf.MeshDesc(4, 4, 1.0, 1.0, None)
+    bad = pf.MaterialDesc(2.1e5, 0.6, 2.7, 0.03, 1e-6, 0)
+    assert lib.pf_create(ctypes.byref(mesh), ctypes.byref(bad), None, None, ctypes.byref(h)) == 1
+    o = pf.default_opts()
+    o.trial_floor = 0.0
+    assert lib.pf_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(o), None,
+                         ctypes.byref(h)) == 1
+    assert not h.value
+
+
+def test_struct_layouts_match_header():
+    import paper_2209_07969_amd as pf
+    # 4 int32 + 4 double + 4 int32 + 3 double
+    assert ctypes.sizeof(pf.SolverOpts) == 4 * 4 + 4 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(pf.MeshDesc) == 8 + 16 + 8
+    assert ctypes.sizeof(pf.MaterialDesc) == 5 * 8 + 8

@@ -1,0 +1,174 @@
+"""End-to-end parity of the HIP staggered solver against the FP64 oracle (GPU).
+
+Tolerances: relative L2 of u <= 1e-7 (FP64) / 1e-6 (mixed), max |d diff|
+<= 1e-5, reaction-force curve error <= 1e-4 of its maximum, staggered counts
+within +-1 per step.  Where the counts of a step differ, the two sides stop at
+different staggered iterates of that step; u and d are then compared at the
+staggered tolerance only (both are valid iterates).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def soa(o_u):
+    return np.stack([o_u[0::2], o_u[1::2]])
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def compare_history(pf, p, scheme, precision, n_steps, u_tol):
+    orc = Oracle(p, scheme)
+    ctx = pf.Context(p, scheme=scheme, precision=precision)
+    F_o, F_g = [], []
+    worst = {"u": 0.0, "d": 0.0, "dstag": 0}
+    for n, lam in enumerate(p.loads[:n_steps]):
+        so = orc.load_step(float(lam))
+        sg = ctx.load_step(float(lam))
+        print(f"step {n+1} lam={lam:.3e} stag oracle={so.n_stag} gpu={sg['n_stag']} "
+              f"F {so.force:.6f} {sg['force'][p.load_comp]:.6f}", flush=True)
+        F_o.append(so.force)
+        F_g.append(sg["force"][p.load_comp])
+        assert abs(so.n_stag - sg["n_stag"]) <= 1, (n, so.n_stag, sg["n_stag"])
+        u, d, H = ctx.get_state()
+        eu = rel_l2(u, soa(orc.u))
+        ed = np.abs(d - orc.d).max()
+        worst["dstag"] = max(worst["dstag"], abs(so.n_stag - sg["n_stag"]))
+        if so.n_stag == sg["n_stag"]:
+            worst["u"] = max(worst["u"], eu)
+            worst["d"] = max(worst["d"], ed)
+            assert eu <= u_tol, (n, eu)
+            assert ed <= 1e-5, (n, ed)
+    F_o, F_g = np.array(F_o), np.array(F_g)
+    err = np.abs(F_g - F_o).max() / np.abs(F_o).max()
+    print("worst", worst, "force err", err, flush=True)
+    assert err <= 1e-4
+    ctx.close()
+    return worst
+
+
+def bar_closed_form(p, lam):
+    m = p.material
+    Ep = m.E / (1 - m.nu ** 2)
+    eps = lam / p.ly
+    d = m.l * Ep * eps ** 2 / (m.Gc + m.l * Ep * eps ** 2)
+    return d, ((1 - d) ** 2 + m.eta) * Ep * eps * p.lx
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_homogeneous_bar_closed_form(gpu_lib, scheme, precision):
+    p = W.homogeneous_bar(nx=9, ny=70, lx=1.0, ly=1.0, du=5e-3, steps=6)
+    ctx = gpu_lib.Context(p, scheme=scheme, precision=precision)
+    for lam in p.loads:
+        st = ctx.load_step(float(lam))
+        d_ref, F_ref = bar_closed_form(p, lam)
+        u, d, H = ctx.get_state()
+        np.testing.assert_allclose(d, d_ref, rtol=1e-8 if precision == 0 else 1e-6)
+        assert np.isclose(st["force"][1], F_ref, rtol=1e-8 if precision == 0 else 1e-6)
+        assert st["converged"] == 1
+        assert st["n_stag"] <= 3
+    ctx.close()
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_small_panel_history_fp64(gpu_lib, scheme):
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=8)
+    compare_history(gpu_lib, p, scheme, 0, 8, 1e-7)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_small_panel_history_mixed(gpu_lib, scheme):
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=8)
+    compare_history(gpu_lib, p, scheme, 1, 8, 1e-6)
+
+
+def test_ragged_panel_history_fp64(gpu_lib):
+    """Non-square ragged mesh spanning several wave strips and chunks."""
+    p = W.tension_panel(n=16, l=0.08, du=1e-3, steps=5)
+    p.nx, p.ny = 133, 40
+    nx, ny = p.nx, p.ny
+    p.dir_u = [W._fix(W._edge_nodes(nx, ny, "bottom"), (0, 1)),
+               W.DirichletU(W._edge_nodes(nx, ny, "top"), np.ones(nx + 1, np.int8),
+                            np.ones(nx + 1))]
+    p.dir_d_nodes = W.notch_nodes(nx, ny, 1.0, 1.0, 0.5)
+    p.dir_d_values = np.ones(p.dir_d_nodes.shape)
+    compare_history(gpu_lib, p, 1, 0, 5, 1e-7)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+def test_teacher_forced_nucleation_step(gpu_lib, scheme):
+    """Inject the oracle's committed state before the nucleation step and
+    compare that one step."""
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=8)
+    orc = Oracle(p, scheme)
+    for lam in p.loads[:3]:
+        orc.load_step(float(lam))
+    u, d, H = orc.get_state()
+    ctx = gpu_lib.Context(p, scheme=scheme)
+    ctx.set_state(u, d, H)
+    lam = float(p.loads[3])
+    so = orc.load_step(lam)
+    sg = ctx.load_step(lam)
+    assert abs(so.n_stag - sg["n_stag"]) <= 1
+    ug, dg, Hg = ctx.get_state()
+    if so.n_stag == sg["n_stag"]:
+        assert rel_l2(ug, soa(orc.u)) <= 1e-7
+        assert np.abs(dg - orc.d).max() <= 1e-5
+    assert abs(sg["force"][1] - so.force) <= 1e-4 * abs(so.force)
+    ctx.close()
+
+
+def test_config_tension64_first_steps(gpu_lib):
+    """64^2 notched tension panel, the first 8 load steps (pre-nucleation)."""
+    p = W.config_tension64()
+    compare_history(gpu_lib, p, 0, 0, 8, 1e-7)
+
+
+def test_state_roundtrip_and_errors(gpu_lib):
+    p = W.tension_panel(n=8, l=0.1, du=1e-3, steps=2)
+    ctx = gpu_lib.Context(p, scheme=1)
+    ctx.load_step(p.loads[0])
+    u, d, H = ctx.get_state()
+    ctx2 = gpu_lib.Context(p, scheme=1)
+    ctx2.set_state(u, d, H)
+    u2, d2, H2 = ctx2.get_state()
+    np.testing.assert_array_equal(u, u2)
+    np.testing.assert_array_equal(d, d2)
+    np.testing.assert_array_equal(H, H2)
+    bad = d.copy()
+    bad[3] = np.nan
+    with pytest.raises(gpu_lib.PhaseFieldError):
+        ctx2.set_state(d=bad)
+    # staggered_iterate / commit protocol
+    s0 = ctx2.staggered_iterate(p.loads[1])
+    assert s0["n_stag"] == 1
+    with pytest.raises(gpu_lib.PhaseFieldError):
+        ctx2.staggered_iterate(p.loads[1] * 2)
+    while s0["r_stag"] > p.tol_stag:
+        s0 = ctx2.staggered_iterate(p.loads[1])
+    ctx2.commit_step()
+    with pytest.raises(gpu_lib.PhaseFieldError):
+        ctx2.commit_step()
+    ref = ctx.load_step(p.loads[1])
+    assert ref["n_stag"] == s0["n_stag"]
+    np.testing.assert_allclose(ctx2.reaction_force(1), ref["force"], rtol=1e-12)
+    ctx.close()
+    ctx2.close()
+
+
+def test_max_stag_reports_not_converged(gpu_lib):
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=4)
+    ctx = gpu_lib.Context(p, scheme=0, max_stag=2)
+    st = None
+    for lam in p.loads[:4]:
+        st = ctx.load_step(lam)
+    assert st["converged"] == 0 and st["n_stag"] == 2
+    ctx.close()
