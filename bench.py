@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: staggered phase-field fracture on one MI355X.
+
+Metric: time per load step / load history and GDOF-updates/s of the
+fixed-stress S1 scheme in mixed precision (FP32 inner CG, FP64 outer loops),
+against the plain FP64 standard scheme on the same GPU.
+
+Workload (default): 512 x 512 Q1 single-edge-notched tension panel (unit
+square, notch y = 0.5, x <= 0.5 as Dirichlet d = 1), E = 210 GPa, nu = 0.3,
+Gc = 2.7 N/mm, l = 0.004 mm, eta = 1e-6, volumetric-deviatoric split, top
+edge u_y ramped by 6e-5 mm per step.  A "step" is one load step of that
+history: the staggered iterations until ||R_d||/||b|| <= 1e-5, each with the
+QP update, the S1 trial solve and predictor, the phase solve, the Newton
+displacement solve (PCG with fused reductions) and the reaction force.
+W warmup steps (load steps 1..W) run untimed, then K load steps are timed.
+
+value = GDOF-updates/s of S1 mixed over the timed steps (sum over all CG
+solves of free DOFs x iterations, divided by the wall time between two
+device synchronisations).  Inputs are resident in HBM before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time per load history and GDOF-updates/s, S1 mixed vs std FP64, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fused_apply_bytes_per_node(prec):
+    """Algorithmic bytes per node of the fused elasticity CG apply:
+    read z (2 comps), p_old (2), d (1), node flag (1 B), element flag (1 B per
+    element ~ node); write p_new (2), q (2)."""
+    w = 4 if prec == "mixed" else 8
+    return (2 + 2 + 1 + 2 + 2) * w + 1 + 1
+
+
+def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False):
+    import torch
+    ctx = pf.Context(problem, scheme=scheme, precision=precision)
+    if profile:
+        ctx.set_profiling(True)
+    for n in range(warmup):
+        st = ctx.load_step(float(problem.loads[n]))
+        log(f"  warmup step {n+1}: n_stag={st['n_stag']} cg_u={st['n_cg_u']} "
+            f"cg_d={st['n_cg_d']} cg_trial={st['n_cg_trial']} {st['time_ms']:.0f} ms")
+    if profile:
+        ctx.set_profiling(True)     # reset counters: only timed steps count
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows = []
+    for n in range(warmup, warmup + steps):
+        st = ctx.load_step(float(problem.loads[n]))
+        rows.append(st)
+        log(f"  timed step {n+1}: n_stag={st['n_stag']} newton={st['n_newton']} "
+            f"cg_u={st['n_cg_u']} cg_d={st['n_cg_d']} cg_trial={st['n_cg_trial']} "
+            f"gated={st['gated_max']} F={st['force'][1]:.4f} {st['time_ms']:.0f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return ctx, rows, t1 - t0
+
+
+def cpu_baseline(pf, problem):
+    """Oracle (FP64, sparse direct solves) on a bounded sample: the k = 0
+    displacement solve of load step 1 limited to one Newton iteration.  The
+    GPU performs the same sample (FP64 ST, one Newton iteration) and its
+    DOF-update count converts the oracle's time into the metric's unit."""
+    import dataclasses
+
+    import oracle
+    p1 = dataclasses.replace(problem)
+    p1.max_newton = 1
+    ctx = pf.Context(p1, scheme=pf.ST, precision=pf.FP64, max_newton=1)
+    st = ctx.staggered_iterate(float(p1.loads[0]))
+    gpu_updates = st["dof_updates"]
+    ctx.close()
+    import numpy as np
+    orc = oracle.Oracle(p1, 0)
+    lam = float(p1.loads[0])
+    t0 = time.perf_counter()
+    u = orc.u.copy()
+    u[orc.u_fixed] = lam * orc.u_unit[orc.u_fixed]
+    R0 = np.linalg.norm(orc.residual_u(u, orc.d)[orc.u_free])
+    u, nit, _ = orc.newton(u, orc.d, R0 if R0 > 0 else 1.0)
+    parts = orc.energies(u, orc.d)
+    H = np.maximum(orc.H, parts["psi_plus"])
+    orc.stag_residual(orc.d, H)
+    t = time.perf_counter() - t0
+    cores = 1
+    return {
+        "value": gpu_updates / t / 1e9,
+        "unit": "GDOF-updates/s (GPU-equivalent)",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{problem.name}: load step 1, k=0 displacement solve with one Newton "
+                   f"iteration (assembled CSR + SuperLU), {t:.1f} s on 1 host core; "
+                   f"rate = GPU CG DOF-updates for the same sample ({gpu_updates:.3e}) / "
+                   f"oracle time"),
+        "seconds": t,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tension512")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-st", action="store_true", help="skip the ST FP64 comparison run")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2209_07969_amd as pf
+    import workloads as W
+
+    pf.require_device()
+    problem = {"tension512": W.config_tension512, "tension64": W.config_tension64}[args.workload]()
+    if args.warmup + args.steps > len(problem.loads):
+        raise SystemExit("warmup + steps exceeds the load history")
+
+    log(f"S1 mixed on {problem.name}")
+    ctx, rows, secs = run_steps(pf, problem, pf.S1, pf.MIXED, args.warmup, args.steps,
+                                profile=True)
+    updates = sum(r["dof_updates"] for r in rows)
+    value = updates / secs / 1e9
+    ms_per_step = secs * 1e3 / args.steps
+    launches, kms, nodes = ctx.kernel_time(0)
+    avg_ms = kms / max(launches, 1)
+    bpn = fused_apply_bytes_per_node("mixed")
+    alg_bytes = bpn * nodes
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    ctx.close()
+
+    st_res = None
+    if not args.no_st:
+        log(f"ST FP64 on {problem.name}")
+        ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps)
+        upd2 = sum(r["dof_updates"] for r in rows2)
+        st_res = {
+            "ms_per_step": secs2 * 1e3 / args.steps,
+            "gdof_updates_per_s": upd2 / secs2 / 1e9,
+            "n_stag": [r["n_stag"] for r in rows2],
+        }
+        ctx2.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline sample")
+        cpu = cpu_baseline(pf, problem)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GDOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{problem.name}: {problem.nx}x{problem.ny} Q1 notched tension panel, "
+                         f"l={problem.material.l} mm, load steps {args.warmup + 1}.."
+                         f"{args.warmup + args.steps} of {len(problem.loads)} x "
+                         f"{problem.loads[0]:.0e} mm"),
+            "scheme": "S1", "precision": "mixed (FP32 inner CG, FP64 outer)",
+            "free_dofs_u": None, "tol_stag": problem.tol_stag, "tol_pcg": problem.tol_pcg,
+        },
+        "s1_mixed": {"n_stag": [r["n_stag"] for r in rows],
+                     "time_ms": [round(r["time_ms"], 1) for r in rows]},
+        "st_fp64": st_res,
+        "speedup_s1_mixed_vs_st_fp64": (st_res["ms_per_step"] / ms_per_step) if st_res else None,
+        "roofline": {
+            "kernel": "k_tangent_cg<float> (fused CG direction update + elasticity tangent apply)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+            "sampled_launches": launches,
+            "bytes_per_launch": alg_bytes,
+        },
+        "cpu_baseline": cpu,
+    }
+    if cpu is not None:
+        cpu.pop("seconds", None)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -28,7 +28,7 @@ EXPORTED = [
     "pf_load_step", "pf_staggered_iterate", "pf_commit_step", "pf_reaction_force",
     "pf_get_state", "pf_set_state", "pf_status_string", "pf_last_error", "pf_free_dofs",
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
-    "pf_op_predictor",
+    "pf_op_predictor", "pf_set_profiling", "pf_kernel_time",
 ]
 
 
@@ -105,6 +105,9 @@ def load_library(path: str = LIB_PATH):
     lib.pf_op_phase_apply.argtypes = [P, P, P, P]
     lib.pf_op_qp_update.argtypes = [P, c_int32, P, P, P, P, P, P, POINTER(c_int64)]
     lib.pf_op_predictor.argtypes = [P, P, P, P, P, P, P]
+    lib.pf_set_profiling.argtypes = [P, c_int32]
+    lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
+                                   POINTER(c_int64)]
     for name in EXPORTED:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
@@ -274,6 +277,17 @@ class Context:
         self._check(self.lib.pf_free_dofs(self.h, ctypes.byref(a), ctypes.byref(b)),
                     "pf_free_dofs")
         return a.value, b.value
+
+    def set_profiling(self, enable=True):
+        self._check(self.lib.pf_set_profiling(self.h, 1 if enable else 0), "pf_set_profiling")
+
+    def kernel_time(self, kernel):
+        """(sampled launches, total ms, nodes per launch) of a CG kernel."""
+        n, ms, nodes = c_int64(), c_double(), c_int64()
+        self._check(self.lib.pf_kernel_time(self.h, int(kernel), ctypes.byref(n),
+                                            ctypes.byref(ms), ctypes.byref(nodes)),
+                    "pf_kernel_time")
+        return n.value, ms.value, nodes.value
 
     # ------------------------------------------------- operator entries
     def op_internal_force(self, u, d, R):

@@ -21,20 +21,31 @@ struct Mat {
   int split;      // 0 = volumetric-deviatoric, 1 = spectral
 };
 
-// Per-solve CG scalars, resident in device memory.  Written by the last
-// block of a kernel (thread 0, vector store), read by the following kernels.
-struct CgScal {
-  double rz;      // r.z of the current residual
-  double pq;      // p.Ap of the current direction
-  double alpha;   // rz / pq
-  double beta;    // rz_new / rz_old (0 on the first iteration)
-  double rr;      // r.r of the current residual
+// Per-solve CG state in device memory.  The CG loop has no communication
+// between blocks of one kernel: each kernel writes block partials with plain
+// stores, and every block of the next kernel reduces them in a fixed order in
+// its prologue, so all blocks hold bit-identical scalars.  Block 0 records
+// the scalars for later kernels in the half of this struct the current
+// kernel does not read (A = written by the operator apply, B = written by the
+// vector update / init), each half on its own 128-byte line.
+struct alignas(128) CgHalfA {
+  double rz;      // r.z entering this iteration
+  double rr;      // r.r entering this iteration
   double rr0;     // r.r of the initial residual
-  double tol2;    // converged when rr <= tol2 * rr0
-  int done;       // 0 running, 1 converged, 2 breakdown (pq <= 0), 3 maxit
+  int done;       // 0 running, 1 converged, 2 breakdown/non-finite, 3 maxit
   int iters;      // completed iterations
-  int maxit;
+};
+struct alignas(128) CgHalfB {
+  double rz_prev; // r.z of the previous iteration (for beta)
+  double rr0;
+  int done;
+  int iters;
+  int first;      // 1 before the first direction
   int pad;
+};
+struct CgState {
+  CgHalfA a;
+  CgHalfB b;
 };
 
 // Node flag bits
@@ -49,20 +60,20 @@ struct March {
   int ch;         // node rows owned per wave
 };
 
-// Scratch for block reductions with last-block finalisation.
+// Scratch for block reductions.  Kernels that reduce run at most kPMax
+// blocks and write one partial per block and value.
+constexpr int kPMax = 512;
 struct RedScratch {
-  double *part;        // [kRedSlots * kMaxBlocks]
-  unsigned *counter;   // [kRedCounters]
-  unsigned long long *icount;  // [kICounters] integer counters
-  double *scal;        // [kScal] generic reduced scalars
+  double *partA;               // [kPMax]      operator-apply partials (p.q)
+  double *partB;               // [2 * kPMax]  vector-update partials (r.z, r.r)
+  double *partR;               // [2 * kPMax]  residual-norm partials
+  unsigned long long *icount;  // [kICounters] integer counters (atomic adds)
+  double *scal;                // [kScal]      finalised scalars
 };
-constexpr int kMaxBlocks = 4096;
-constexpr int kRedSlots = 4;
-constexpr int kRedCounters = 8;
 constexpr int kICounters = 8;
 constexpr int kScal = 16;
 
-// Generic scalar slots in RedScratch::scal
+// Slots in RedScratch::scal and ::icount
 enum ScalSlot {
   SC_NORM_A = 0,    // ||R||^2 of the last residual kernel
   SC_NORM_B = 1,    // ||b||^2 (phase residual)
@@ -70,6 +81,17 @@ enum ScalSlot {
   SC_SUM_Y = 3,     // group reaction y
 };
 enum ICounter { IC_GATED = 0, IC_FLOOR = 1 };
+
+// Launch geometry of one CG solve: grid sizes of the apply (ga) and of the
+// vector kernels (gb); each kernel's prologue reduces the other's partials.
+struct CgArgs {
+  CgState *st;
+  double *partA;
+  double *partB;
+  int ga, gb;
+  double tol2;
+  int maxit;
+};
 
 // Operator coefficients passed by value.
 struct ElasCoef {
@@ -91,22 +113,23 @@ March march_shape(const Grid &g, int ch_override);
 
 // CG (T = double or float).  p_old/p_new are the two direction buffers; the
 // apply computes p_new = z + beta p_old on the fly and q = A p_new.
+CgArgs cg_args(const Grid &g, const March &m, int n, CgState *st, RedScratch rs, double tol,
+               int maxit);
 template <class T>
 hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
-                   CgScal *sc, double tol, int maxit, RedScratch rs);
+                   const CgArgs &ca);
 template <class T>
 hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, CgScal *sc, RedScratch rs);
+                     const T *Dinv, const CgArgs &ca);
 template <class T>
 hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                             const T *d, const uint8_t *qflag, const uint8_t *eact,
                             const uint8_t *nflag, const T *z, const T *p_old, T *p_new,
-                            T *q, CgScal *sc, RedScratch rs);
+                            T *q, const CgArgs &ca);
 template <class T>
 hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const T *coef, const uint8_t *eact, const uint8_t *nflag,
-                          const T *z, const T *p_old, T *p_new, T *q, CgScal *sc,
-                          RedScratch rs);
+                          const T *z, const T *p_old, T *p_new, T *q, const CgArgs &ca);
 template <class T>
 hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                         const T *d, const uint8_t *qflag, const uint8_t *eact,

@@ -19,9 +19,12 @@
 // q = 0,3 and (b,a) for q = 1,2.  The transpose maps edge duals back to the
 // corners: f0 = -Eb - El, f1 = Eb - Er, f2 = Et + Er, f3 = El - Et.
 //
-// Reductions are deterministic: wave shuffles, a fixed-order LDS sum per
-// block, block partials in global memory, and a fixed-order sum by the last
-// block to finish (atomic ticket).  All stores are ordinary vector stores.
+// Reductions are deterministic and need no communication between blocks of
+// one kernel: wave shuffles and a fixed-order LDS sum give one partial per
+// block, stored with a plain vector store; the next kernel in the stream
+// (every one of its blocks, or a one-block finaliser) sums the partials in a
+// fixed order.  Device-scope fences are avoided on purpose: on a GPU whose
+// L2 is split across dies they write back the local L2.
 
 #include "pf_internal.h"
 
@@ -38,6 +41,8 @@ constexpr int TPB = 256;
 
 // ------------------------------------------------------------ reductions
 
+// Block partial of NV sums: wave shuffles, then a fixed-order LDS sum by
+// thread 0, stored to part[k * kPMax + blockIdx.x].  All threads call it.
 template <int NV>
 __device__ inline void block_partial(double (&v)[NV], double *part) {
   __shared__ double sh[NV][TPB / 64];
@@ -60,49 +65,33 @@ __device__ inline void block_partial(double (&v)[NV], double *part) {
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += sh[k][w];
-      part[k * kMaxBlocks + blockIdx.x] = s;
+      part[k * kPMax + blockIdx.x] = s;
     }
   }
 }
 
-// Returns true in every thread of the block that finished last.
-__device__ inline bool last_block(unsigned *counter) {
-  __shared__ int amlast;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    amlast = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  return amlast != 0;
-}
-
-// Fixed-order sum of the block partials, valid in thread 0 of the last block.
+// Fixed-order sum of np partials written by an earlier kernel, returned in
+// every thread of the block (bit-identical in every block).
 template <int NV>
-__device__ inline void final_sum(const double *part, int nb, double (&out)[NV]) {
+__device__ inline void block_sum(const double *part, int np, double (&out)[NV]) {
   __shared__ double sh[NV][TPB / 64];
-  __threadfence();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-      s += __hip_atomic_load(part + k * kMaxBlocks + b, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    for (int b = threadIdx.x; b < np; b += blockDim.x) s += part[k * kPMax + b];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = blockDim.x >> 6;
+  const int nw = blockDim.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += sh[k][w];
-      out[k] = s;
-    }
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[k][w];
+    out[k] = s;
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------- QP geometry
@@ -255,78 +244,106 @@ __device__ inline void phase_diag_element(const T (&cq)[4], const PhaseCoef &c, 
 // ------------------------------------------------------- marching kernel
 //
 // An Op provides:
-//   struct Node;                      values loaded per node
-//   static constexpr int NF;          number of accumulated components
-//   static constexpr int NR;          number of reduction accumulators
-//   Node load(int i, int j) const     zero outside the grid
-//   void element(Node n[4], ie, je, T f[NF][4])   zero if no element
+//   T, Node, Elem, NF (accumulated components), NR (reduction values)
+//   Node load(i, j)          node values, zero outside the grid
+//   Node zero()
+//   Elem eload(ie, je)       element data (flags, coefficients)
+//   void element(bl, br, tr, tl, ie, je, const Elem&, T f[NF][4])
 //   void store(i, j, const T v[NF], const Node &n, double red[NR])
-//   void finish(double red[NR])       block-level epilogue (all threads)
-//   Node shfl_up(const Node&)         lane L receives lane L-1's value
+//   static Node shfl_up(const Node&)   lane L receives lane L-1's value
+// The next row's node and element loads are issued before the current row's
+// element is computed.
 
 template <class Op>
-__global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms) {
+__device__ inline void march_wave(const Op &op, const Grid &g, const March &ms, int w, int lane,
+                                  double *red) {
   using T = typename Op::T;
   using Node = typename Op::Node;
+  using Elem = typename Op::Elem;
   constexpr int NF = Op::NF;
-  double red[Op::NR > 0 ? Op::NR : 1];
+  const int strip = w % ms.nstrips;
+  const int chunk = w / ms.nstrips;
+  const int ie = strip * STRIP - 1 + lane;
+  const int j0 = chunk * ms.ch;
+  const int j1 = min(j0 + ms.ch, g.ny + 1);
+  const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
+  Node bl = op.load(ie, j0 - 1);
+  Node br = op.load(ie + 1, j0 - 1);
+  Node tr = op.load(ie + 1, j0);
+  Node tl0 = (lane == 0) ? op.load(ie, j0) : op.zero();
+  Elem el = op.eload(ie, j0 - 1);
+  T c2[NF], c3[NF];
 #pragma unroll
-  for (int k = 0; k < (Op::NR > 0 ? Op::NR : 1); ++k) red[k] = 0.0;
-  if (!op.skip()) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
-    if (w < ms.nstrips * ms.nchunks) {
-      const int strip = w % ms.nstrips;
-      const int chunk = w / ms.nstrips;
-      const int ie = strip * STRIP - 1 + lane;
-      const int j0 = chunk * ms.ch;
-      const int j1 = min(j0 + ms.ch, g.ny + 1);
-      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
-      Node bl = op.load(ie, j0 - 1);
-      Node br = op.load(ie + 1, j0 - 1);
-      T c2[NF], c3[NF];
+  for (int k = 0; k < NF; ++k) { c2[k] = T(0); c3[k] = T(0); }
+  for (int je = j0 - 1; je < j1; ++je) {
+    const bool more = je + 1 < j1;
+    const Node trn = more ? op.load(ie + 1, je + 2) : op.zero();
+    const Node tl0n = (more && lane == 0) ? op.load(ie, je + 2) : op.zero();
+    const Elem eln = more ? op.eload(ie, je + 1) : Elem{};
+    Node tl = Op::shfl_up(tr);
+    if (lane == 0) tl = tl0;
+    T f[NF][4];
+    op.element(bl, br, tr, tl, ie, je, el, f);
+    T out[NF];
 #pragma unroll
-      for (int k = 0; k < NF; ++k) { c2[k] = T(0); c3[k] = T(0); }
-      for (int je = j0 - 1; je < j1; ++je) {
-        Node tr = op.load(ie + 1, je + 1);
-        Node tl = Op::shfl_up(tr);
-        if (lane == 0) tl = op.load(ie, je + 1);
-        T f[NF][4];
-        op.element(bl, br, tr, tl, ie, je, f);
-        T out[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) {
-          T A = f[k][1] + c2[k];
-          T Al = __shfl_up(A, 1, 64);
-          out[k] = f[k][0] + c3[k] + Al;
-          c3[k] = f[k][3];
-          c2[k] = f[k][2];
-        }
-        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
-        bl = tl;
-        br = tr;
-      }
+    for (int k = 0; k < NF; ++k) {
+      const T A = f[k][1] + c2[k];
+      const T Al = __shfl_up(A, 1, 64);
+      out[k] = f[k][0] + c3[k] + Al;
+      c3[k] = f[k][3];
+      c2[k] = f[k][2];
     }
+    if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
+    bl = tl;
+    br = tr;
+    tr = trn;
+    tl0 = tl0n;
+    el = eln;
   }
-  op.finish(red);
 }
 
-template <class T>
-__device__ inline T ld(const T *p, int idx) { return p[idx]; }
+// Generic marching kernel: waves loop over (strip, chunk) work items; an op
+// with NR > 0 writes block partials to `part`.
+template <class Op>
+__global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms, double *part) {
+  constexpr int NRR = Op::NR > 0 ? Op::NR : 1;
+  double red[NRR];
+#pragma unroll
+  for (int k = 0; k < NRR; ++k) red[k] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int nw = ms.nstrips * ms.nchunks;
+  for (int w = blockIdx.x * WPB + (threadIdx.x >> 6); w < nw; w += gridDim.x * WPB)
+    march_wave(op, g, ms, w, lane, red);
+  if (Op::NR > 0) block_partial<NRR>(red, part);
+}
 
-// ---- elasticity tangent, fused CG direction update: p = z + beta p_old
+int march_blocks(const March &m) {
+  const int nw = m.nstrips * m.nchunks;
+  int b = (nw + WPB - 1) / WPB;
+  return b > kPMax ? kPMax : b;
+}
+
+// Element data: flags byte for the tangent, 4 QP coefficients for the phase.
+struct ElemFlags { uint8_t bits; uint8_t active; };
+template <class T> struct ElemCoef { T c[4]; uint8_t active; };
+struct ElemH { double H[4]; uint8_t active; };
+struct ElemNone { uint8_t active; };
+
+// ---- elasticity tangent (optionally fused with the CG direction update
+//      p = z + beta p_old; the fused op also accumulates p.q)
 template <class TT, bool FUSED, bool MASK>
 struct OpTangent {
   using T = TT;
+  using Elem = ElemFlags;
   static constexpr int NF = 2;
   static constexpr int NR = FUSED ? 1 : 0;
   struct Node { T px, py, d; };
   Grid g; ElasCoef c;
   const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag;
-  const T *z; const T *pold; T *pnew; T *q; CgScal *sc; RedScratch rs;
-  T beta; int done;
+  const T *z; const T *pold; T *pnew; T *q;
+  T beta;
 
-  __device__ bool skip() const { return FUSED && done != 0; }
+  __device__ Node zero() const { return Node{T(0), T(0), T(0)}; }
   __device__ Node load(int i, int j) const {
     Node n{T(0), T(0), T(0)};
     if (node_exists(g, i, j)) {
@@ -342,12 +359,20 @@ struct OpTangent {
     }
     return n;
   }
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{0, 0};
+    if (elem_exists(g, ie, je, eact)) {
+      e.bits = qflag[ie + je * g.nx];
+      e.active = 1;
+    }
+    return e;
+  }
   static __device__ Node shfl_up(const Node &n) {
     return Node{__shfl_up(n.px, 1, 64), __shfl_up(n.py, 1, 64), __shfl_up(n.d, 1, 64)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int ie, int je, T (&f)[2][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+                          int, int, const Elem &e, T (&f)[2][4]) const {
+    if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
       return;
@@ -355,8 +380,7 @@ struct OpTangent {
     const T ux[4] = {n0.px, n1.px, n2.px, n3.px};
     const T uy[4] = {n0.py, n1.py, n2.py, n3.py};
     const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    const unsigned bits = qflag[ie + je * g.nx];
-    elastic_element<T, false>(ux, uy, dn, bits, c, f[0], f[1]);
+    elastic_element<T, false>(ux, uy, dn, e.bits, c, f[0], f[1]);
   }
   __device__ void store(int i, int j, const T (&v)[2], const Node &n, double *red) const {
     const int k = i + j * (g.nx + 1);
@@ -374,41 +398,22 @@ struct OpTangent {
       red[0] += double(n.px) * double(qx) + double(n.py) * double(qy);
     }
   }
-  __device__ void finish(double *red) const {
-    if (!FUSED) return;
-    if (done != 0) return;
-    double v[1] = {red[0]};
-    block_partial<1>(v, rs.part);
-    if (last_block(rs.counter + 0)) {
-      double s[1];
-      final_sum<1>(rs.part, gridDim.x, s);
-      if (threadIdx.x == 0) {
-        sc->pq = s[0];
-        if (!(s[0] > 0.0)) {
-          sc->done = 2;
-          sc->alpha = 0.0;
-        } else {
-          sc->alpha = sc->rz / s[0];
-        }
-        rs.counter[0] = 0u;
-      }
-    }
-  }
 };
 
-// ---- phase operator (K_dd, augmented block), fused CG direction update
+// ---- phase operator (K_dd, augmented block), optionally fused
 template <class TT, bool FUSED, bool MASK>
 struct OpPhase {
   using T = TT;
+  using Elem = ElemCoef<TT>;
   static constexpr int NF = 1;
   static constexpr int NR = FUSED ? 1 : 0;
   struct Node { T p; };
   Grid g; PhaseCoef c;
   const T *coef; const uint8_t *eact; const uint8_t *nflag;
-  const T *z; const T *pold; T *pnew; T *q; CgScal *sc; RedScratch rs;
-  T beta; int done;
+  const T *z; const T *pold; T *pnew; T *q;
+  T beta;
 
-  __device__ bool skip() const { return FUSED && done != 0; }
+  __device__ Node zero() const { return Node{T(0)}; }
   __device__ Node load(int i, int j) const {
     Node n{T(0)};
     if (node_exists(g, i, j)) {
@@ -417,16 +422,27 @@ struct OpPhase {
     }
     return n;
   }
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{};
+    if (elem_exists(g, ie, je, eact)) {
+      const int el = ie + je * g.nx;
+      e.c[0] = coef[el];
+      e.c[1] = coef[el + g.E];
+      e.c[2] = coef[el + 2 * g.E];
+      e.c[3] = coef[el + 3 * g.E];
+      e.active = 1;
+    }
+    return e;
+  }
   static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.p, 1, 64)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int ie, int je, T (&f)[1][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+                          int, int, const Elem &e, T (&f)[1][4]) const {
+    if (!e.active) {
       f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
       return;
     }
-    const int e = ie + je * g.nx;
     const T p[4] = {n0.p, n1.p, n2.p, n3.p};
-    const T cq[4] = {coef[e], coef[e + g.E], coef[e + 2 * g.E], coef[e + 3 * g.E]};
+    const T cq[4] = {e.c[0], e.c[1], e.c[2], e.c[3]};
     phase_element<T>(p, cq, c, f[0]);
   }
   __device__ void store(int i, int j, const T (&v)[1], const Node &n, double *red) const {
@@ -439,39 +455,21 @@ struct OpPhase {
       red[0] += double(n.p) * double(qv);
     }
   }
-  __device__ void finish(double *red) const {
-    if (!FUSED) return;
-    if (done != 0) return;
-    double v[1] = {red[0]};
-    block_partial<1>(v, rs.part);
-    if (last_block(rs.counter + 1)) {
-      double s[1];
-      final_sum<1>(rs.part, gridDim.x, s);
-      if (threadIdx.x == 0) {
-        sc->pq = s[0];
-        if (!(s[0] > 0.0)) {
-          sc->done = 2;
-          sc->alpha = 0.0;
-        } else {
-          sc->alpha = sc->rz / s[0];
-        }
-        rs.counter[1] = 0u;
-      }
-    }
-  }
 };
 
-// ---- internal force (FP64, nonlinear split stress)
+// ---- internal force (FP64, nonlinear split stress); reduces ||R||^2 over
+//      free DOFs when a node-flag array is given
 struct OpForce {
   using T = double;
+  using Elem = ElemNone;
   static constexpr int NF = 2;
   static constexpr int NR = 1;
   struct Node { double ux, uy, d; };
   Grid g; ElasCoef c;
   const double *u; const double *dd; const uint8_t *eact; const uint8_t *nflag;
-  double *R; RedScratch rs; double sign;
+  double *R; double sign;
 
-  __device__ bool skip() const { return false; }
+  __device__ Node zero() const { return Node{0.0, 0.0, 0.0}; }
   __device__ Node load(int i, int j) const {
     Node n{0.0, 0.0, 0.0};
     if (node_exists(g, i, j)) {
@@ -480,12 +478,15 @@ struct OpForce {
     }
     return n;
   }
+  __device__ Elem eload(int ie, int je) const {
+    return Elem{uint8_t(elem_exists(g, ie, je, eact) ? 1 : 0)};
+  }
   static __device__ Node shfl_up(const Node &n) {
     return Node{__shfl_up(n.ux, 1, 64), __shfl_up(n.uy, 1, 64), __shfl_up(n.d, 1, 64)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int ie, int je, double (&f)[2][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+                          int, int, const Elem &e, double (&f)[2][4]) const {
+    if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
       return;
@@ -507,46 +508,47 @@ struct OpForce {
     R[k + g.N] = sign * ry;
     red[0] += rx * rx + ry * ry;
   }
-  __device__ void finish(double *red) const {
-    double v[1] = {red[0]};
-    block_partial<1>(v, rs.part);
-    if (last_block(rs.counter + 2)) {
-      double s[1];
-      final_sum<1>(rs.part, gridDim.x, s);
-      if (threadIdx.x == 0) {
-        rs.scal[SC_NORM_A] = s[0];
-        rs.counter[2] = 0u;
-      }
-    }
-  }
 };
 
-// ---- phase residual R_d = K_dd(H) d - b(H) (FP64)
+// ---- phase residual R_d = K_dd(H) d - b(H) (FP64); reduces ||R_d||^2 and
+//      ||b||^2 over free nodes
 struct OpPhaseRes {
   using T = double;
+  using Elem = ElemH;
   static constexpr int NF = 2;   // [0] = K_dd d - b, [1] = b
   static constexpr int NR = 2;
   struct Node { double d; };
   Grid g; PhaseCoef c;
   const double *H; const double *dd; const uint8_t *eact; const uint8_t *nflag;
-  double *R; RedScratch rs; double sign;
+  double *R; double sign;
 
-  __device__ bool skip() const { return false; }
+  __device__ Node zero() const { return Node{0.0}; }
   __device__ Node load(int i, int j) const {
     Node n{0.0};
     if (node_exists(g, i, j)) n.d = dd[i + j * (g.nx + 1)];
     return n;
   }
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{};
+    if (elem_exists(g, ie, je, eact)) {
+      const int el = ie + je * g.nx;
+      e.H[0] = H[el];
+      e.H[1] = H[el + g.E];
+      e.H[2] = H[el + 2 * g.E];
+      e.H[3] = H[el + 3 * g.E];
+      e.active = 1;
+    }
+    return e;
+  }
   static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int ie, int je, double (&f)[2][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+                          int, int, const Elem &e, double (&f)[2][4]) const {
+    if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
       return;
     }
-    const int e = ie + je * g.nx;
-    const double Hq[4] = {H[e], H[e + g.E], H[e + 2 * g.E], H[e + 3 * g.E]};
+    const double *Hq = e.H;
     const double cq[4] = {c.Gc_l + 2.0 * Hq[0], c.Gc_l + 2.0 * Hq[1], c.Gc_l + 2.0 * Hq[2],
                           c.Gc_l + 2.0 * Hq[3]};
     const double p[4] = {n0.d, n1.d, n2.d, n3.d};
@@ -568,46 +570,42 @@ struct OpPhaseRes {
     red[0] += r * r;
     red[1] += b * b;
   }
-  __device__ void finish(double *red) const {
-    double v[2] = {red[0], red[1]};
-    block_partial<2>(v, rs.part);
-    if (last_block(rs.counter + 3)) {
-      double s[2];
-      final_sum<2>(rs.part, gridDim.x, s);
-      if (threadIdx.x == 0) {
-        rs.scal[SC_NORM_A] = s[0];
-        rs.scal[SC_NORM_B] = s[1];
-        rs.counter[3] = 0u;
-      }
-    }
-  }
 };
 
 // ---- Jacobi diagonals (inverse, 0 on fixed DOFs)
 template <class TT>
 struct OpTangentDiag {
   using T = TT;
+  using Elem = ElemFlags;
   static constexpr int NF = 2;
   static constexpr int NR = 0;
   struct Node { T d; };
   Grid g; ElasCoef c;
   const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
-  __device__ bool skip() const { return false; }
+  __device__ Node zero() const { return Node{T(0)}; }
   __device__ Node load(int i, int j) const {
     Node n{T(0)};
     if (node_exists(g, i, j)) n.d = d[i + j * (g.nx + 1)];
     return n;
   }
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{0, 0};
+    if (elem_exists(g, ie, je, eact)) {
+      e.bits = qflag[ie + je * g.nx];
+      e.active = 1;
+    }
+    return e;
+  }
   static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int ie, int je, T (&f)[2][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+                          int, int, const Elem &e, T (&f)[2][4]) const {
+    if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
       return;
     }
     const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    elastic_diag_element<T>(dn, qflag[ie + je * g.nx], c, f[0], f[1]);
+    elastic_diag_element<T>(dn, e.bits, c, f[0], f[1]);
   }
   __device__ void store(int i, int j, const T (&v)[2], const Node &, double *) const {
     const int k = i + j * (g.nx + 1);
@@ -615,52 +613,92 @@ struct OpTangentDiag {
     Dinv[k] = ((nf & NF_UX) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
     Dinv[k + g.N] = ((nf & NF_UY) || !(v[1] > T(0))) ? T(0) : T(1) / v[1];
   }
-  __device__ void finish(double *) const {}
 };
 
 template <class TT>
 struct OpPhaseDiag {
   using T = TT;
+  using Elem = ElemCoef<TT>;
   static constexpr int NF = 1;
   static constexpr int NR = 0;
   struct Node { T dummy; };
   Grid g; PhaseCoef c;
   const T *coef; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
-  __device__ bool skip() const { return false; }
+  __device__ Node zero() const { return Node{T(0)}; }
   __device__ Node load(int, int) const { return Node{T(0)}; }
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{};
+    if (elem_exists(g, ie, je, eact)) {
+      const int el = ie + je * g.nx;
+      e.c[0] = coef[el];
+      e.c[1] = coef[el + g.E];
+      e.c[2] = coef[el + 2 * g.E];
+      e.c[3] = coef[el + 3 * g.E];
+      e.active = 1;
+    }
+    return e;
+  }
   static __device__ Node shfl_up(const Node &n) { return n; }
-  __device__ void element(const Node &, const Node &, const Node &, const Node &, int ie,
-                          int je, T (&f)[1][4]) const {
-    if (!elem_exists(g, ie, je, eact)) {
+  __device__ void element(const Node &, const Node &, const Node &, const Node &, int, int,
+                          const Elem &e, T (&f)[1][4]) const {
+    if (!e.active) {
       f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
       return;
     }
-    const int e = ie + je * g.nx;
-    const T cq[4] = {coef[e], coef[e + g.E], coef[e + 2 * g.E], coef[e + 3 * g.E]};
+    const T cq[4] = {e.c[0], e.c[1], e.c[2], e.c[3]};
     phase_diag_element<T>(cq, c, f[0]);
   }
   __device__ void store(int i, int j, const T (&v)[1], const Node &, double *) const {
     const int k = i + j * (g.nx + 1);
     Dinv[k] = ((nflag[k] & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
   }
-  __device__ void finish(double *) const {}
 };
 
 template <class Op>
-hipError_t launch_march(hipStream_t s, const Op &op, const Grid &g, const March &m) {
-  const int waves = m.nstrips * m.nchunks;
-  const int blocks = (waves + WPB - 1) / WPB;
-  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+hipError_t launch_march(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                        double *part) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(march_blocks(m)), dim3(TPB), 0, s, op,
+                     g, m, part);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ CG vectors
+// Finalise NV block partials into scal[slot..slot+NV) (one block).
+template <int NV>
+__global__ void __launch_bounds__(TPB) k_finalize(const double *part, int np, double *scal,
+                                                  int slot) {
+  double s[NV];
+  block_sum<NV>(part, np, s);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) scal[slot + k] = s[k];
+  }
+}
+
+template <class Op, int NV>
+hipError_t launch_march_reduce(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                               RedScratch rs, int slot) {
+  const int nb = march_blocks(m);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(nb), dim3(TPB), 0, s, op, g, m,
+                     rs.partR);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_finalize<NV>), dim3(1), dim3(TPB), 0, s, rs.partR, nb,
+                     rs.scal, slot);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- CG kernels
+//
+// Iteration k = apply kernel A_k then vector kernel B_k.
+//   A_k: reduce B_{k-1}'s partials -> rz_k, rr_k; decide done; beta =
+//        rz_k / rz_{k-1}; p = z + beta p_old; q = A p; partials p.q.
+//   B_k: reduce A_k's partials -> pq; alpha = rz_k / pq; x += alpha p;
+//        r -= alpha q; z = D^-1 r; partials r.z, r.r.
+// Block 0 of each kernel records its scalars in its own half of CgState.
 
 template <class T>
 __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pold,
-                                                 const T *Dinv, CgScal *sc, double tol,
-                                                 int maxit, RedScratch rs) {
+                                                 const T *Dinv, CgArgs ca) {
   double v[2] = {0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const T ri = r[i];
@@ -671,32 +709,83 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
     v[0] += double(ri) * double(zi);
     v[1] += double(ri) * double(ri);
   }
-  block_partial<2>(v, rs.part);
-  if (last_block(rs.counter + 4)) {
-    double s[2];
-    final_sum<2>(rs.part, gridDim.x, s);
-    if (threadIdx.x == 0) {
-      sc->rz = s[0];
-      sc->rr = s[1];
-      sc->rr0 = s[1];
-      sc->tol2 = tol * tol;
-      sc->beta = 0.0;
-      sc->alpha = 0.0;
-      sc->pq = 0.0;
-      sc->iters = 0;
-      sc->maxit = maxit;
-      sc->done = (s[1] == 0.0) ? 1 : 0;
-      rs.counter[4] = 0u;
-    }
+  block_partial<2>(v, ca.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = 0.0;
+    ca.st->b.rr0 = 0.0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = 0;
+    ca.st->b.first = 1;
   }
+}
+
+// Prologue of the apply kernels: returns done (uniform) and beta.
+__device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
+  double s[2];
+  block_sum<2>(ca.partB, ca.gb, s);
+  const double rz = s[0], rr = s[1];
+  const int first = ca.st->b.first;
+  const int iters = ca.st->b.iters;
+  int done = ca.st->b.done;
+  const double rr0 = first ? rr : ca.st->b.rr0;
+  if (!done) {
+    if (!(rr == rr) || !(rz == rz)) done = 2;
+    else if (rr <= ca.tol2 * rr0) done = 1;
+    else if (iters >= ca.maxit) done = 3;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->a.rz = rz;
+    ca.st->a.rr = rr;
+    ca.st->a.rr0 = rr0;
+    ca.st->a.done = done;
+    ca.st->a.iters = iters;
+  }
+  *beta = first ? 0.0 : rz / ca.st->b.rz_prev;
+  return done;
+}
+
+template <class Op>
+__global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+  double beta = 0.0;
+  if (cg_apply_prologue(ca, &beta) != 0) return;
+  op.beta = typename Op::T(beta);
+  double red[1] = {0.0};
+  const int lane = threadIdx.x & 63;
+  const int nw = ms.nstrips * ms.nchunks;
+  for (int w = blockIdx.x * WPB + (threadIdx.x >> 6); w < nw; w += gridDim.x * WPB)
+    march_wave(op, g, ms, w, lane, red);
+  block_partial<1>(red, ca.partA);
 }
 
 template <class T>
 __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
-                                                   const T *q, const T *Dinv, CgScal *sc,
-                                                   RedScratch rs) {
-  if (sc->done != 0) return;
-  const T alpha = T(sc->alpha);
+                                                   const T *q, const T *Dinv, CgArgs ca) {
+  const int done = ca.st->a.done;
+  const double rz = ca.st->a.rz;
+  const double rr0 = ca.st->a.rr0;
+  const int iters = ca.st->a.iters;
+  if (done != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ca.st->b.done = done;
+      ca.st->b.iters = iters;
+      ca.st->b.rr0 = rr0;
+      ca.st->b.first = 0;
+    }
+    return;
+  }
+  double pqs[1];
+  block_sum<1>(ca.partA, ca.ga, pqs);
+  const double pq = pqs[0];
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ca.st->b.done = 2;
+      ca.st->b.iters = iters;
+      ca.st->b.rr0 = rr0;
+      ca.st->b.first = 0;
+    }
+    return;
+  }
+  const T alpha = T(rz / pq);
   double v[2] = {0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const T xi = x[i] + alpha * p[i];
@@ -708,31 +797,19 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, cons
     v[0] += double(ri) * double(zi);
     v[1] += double(ri) * double(ri);
   }
-  block_partial<2>(v, rs.part);
-  if (last_block(rs.counter + 5)) {
-    double s[2];
-    final_sum<2>(rs.part, gridDim.x, s);
-    if (threadIdx.x == 0) {
-      const double rz_old = sc->rz;
-      sc->beta = (rz_old != 0.0) ? s[0] / rz_old : 0.0;
-      sc->rz = s[0];
-      sc->rr = s[1];
-      const int it = sc->iters + 1;
-      sc->iters = it;
-      if (!(s[1] <= sc->tol2 * sc->rr0) || !(s[1] == s[1])) {
-        if (!(s[1] == s[1])) sc->done = 2;
-        else if (it >= sc->maxit) sc->done = 3;
-      } else {
-        sc->done = 1;
-      }
-      rs.counter[5] = 0u;
-    }
+  block_partial<2>(v, ca.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = rz;
+    ca.st->b.rr0 = rr0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = iters + 1;
+    ca.st->b.first = 0;
   }
 }
 
 int vec_blocks(int n) {
-  int b = (n + TPB - 1) / TPB;
-  if (b > 2048) b = 2048;
+  int b = (n + 4 * TPB - 1) / (4 * TPB);
+  if (b > kPMax) b = kPMax;
   if (b < 1) b = 1;
   return b;
 }
@@ -994,11 +1071,11 @@ __global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
     const double r = R[dof[i]];
     if (comp[i] == 0) v[0] += r; else v[1] += r;
   }
-  block_partial<2>(v, rs.part);
+  block_partial<2>(v, rs.partR);
   __syncthreads();
   if (threadIdx.x == 0) {
-    rs.scal[SC_SUM_X] = rs.part[0];
-    rs.scal[SC_SUM_Y] = rs.part[kMaxBlocks];
+    rs.scal[SC_SUM_X] = rs.partR[0];
+    rs.scal[SC_SUM_Y] = rs.partR[kPMax];
   }
 }
 
@@ -1018,140 +1095,58 @@ March march_shape(const Grid &g, int ch_override) {
   }
   m.ch = ch;
   m.nchunks = (g.ny + 1 + ch - 1) / ch;
-  while ((long long)m.nstrips * m.nchunks > (long long)kMaxBlocks * WPB) {
-    m.ch *= 2;
-    m.nchunks = (g.ny + 1 + m.ch - 1) / m.ch;
-  }
   return m;
+}
+
+CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, double tol,
+               int maxit) {
+  CgArgs ca;
+  ca.st = st;
+  ca.partA = rs.partA;
+  ca.partB = rs.partB;
+  ca.ga = march_blocks(m);
+  ca.gb = vec_blocks(n);
+  ca.tol2 = tol * tol;
+  ca.maxit = maxit;
+  return ca;
 }
 
 template <class T>
 hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
-                   CgScal *sc, double tol, int maxit, RedScratch rs) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_init<T>), dim3(vec_blocks(n)), dim3(TPB), 0, s, n, x,
-                     r, z, p_old, Dinv, sc, tol, maxit, rs);
+                   const CgArgs &ca) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_init<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
+                     p_old, Dinv, ca);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, CgScal *sc, RedScratch rs) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(vec_blocks(n)), dim3(TPB), 0, s, n,
-                     x, r, z, p, q, Dinv, sc, rs);
+                     const T *Dinv, const CgArgs &ca) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
+                     p, q, Dinv, ca);
   return hipGetLastError();
-}
-
-// The fused apply reads beta and done from the scalar block at launch time
-// via a tiny indirection: the op carries the pointer and reads it once.
-template <class T>
-__global__ void __launch_bounds__(TPB) k_tangent_cg(OpTangent<T, true, true> op, Grid g,
-                                                    March ms) {
-  // beta/done are read per block from device memory (uniform loads)
-  op.beta = T(op.sc->beta);
-  op.done = op.sc->done;
-  // body of k_march, specialised
-  using Op = OpTangent<T, true, true>;
-  using Node = typename Op::Node;
-  double red[1] = {0.0};
-  if (op.done == 0) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
-    if (w < ms.nstrips * ms.nchunks) {
-      const int strip = w % ms.nstrips;
-      const int chunk = w / ms.nstrips;
-      const int ie = strip * STRIP - 1 + lane;
-      const int j0 = chunk * ms.ch;
-      const int j1 = min(j0 + ms.ch, g.ny + 1);
-      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
-      Node bl = op.load(ie, j0 - 1);
-      Node br = op.load(ie + 1, j0 - 1);
-      T c2[2] = {T(0), T(0)}, c3[2] = {T(0), T(0)};
-      for (int je = j0 - 1; je < j1; ++je) {
-        Node tr = op.load(ie + 1, je + 1);
-        Node tl = Op::shfl_up(tr);
-        if (lane == 0) tl = op.load(ie, je + 1);
-        T f[2][4];
-        op.element(bl, br, tr, tl, ie, je, f);
-        T out[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          T A = f[k][1] + c2[k];
-          T Al = __shfl_up(A, 1, 64);
-          out[k] = f[k][0] + c3[k] + Al;
-          c3[k] = f[k][3];
-          c2[k] = f[k][2];
-        }
-        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
-        bl = tl;
-        br = tr;
-      }
-    }
-  }
-  op.finish(red);
-}
-
-template <class T>
-__global__ void __launch_bounds__(TPB) k_phase_cg(OpPhase<T, true, true> op, Grid g, March ms) {
-  op.beta = T(op.sc->beta);
-  op.done = op.sc->done;
-  using Op = OpPhase<T, true, true>;
-  using Node = typename Op::Node;
-  double red[1] = {0.0};
-  if (op.done == 0) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * WPB + (threadIdx.x >> 6);
-    if (w < ms.nstrips * ms.nchunks) {
-      const int strip = w % ms.nstrips;
-      const int chunk = w / ms.nstrips;
-      const int ie = strip * STRIP - 1 + lane;
-      const int j0 = chunk * ms.ch;
-      const int j1 = min(j0 + ms.ch, g.ny + 1);
-      const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
-      Node bl = op.load(ie, j0 - 1);
-      Node br = op.load(ie + 1, j0 - 1);
-      T c2 = T(0), c3 = T(0);
-      for (int je = j0 - 1; je < j1; ++je) {
-        Node tr = op.load(ie + 1, je + 1);
-        Node tl = Op::shfl_up(tr);
-        if (lane == 0) tl = op.load(ie, je + 1);
-        T f[1][4];
-        op.element(bl, br, tr, tl, ie, je, f);
-        T A = f[0][1] + c2;
-        T Al = __shfl_up(A, 1, 64);
-        T out[1] = {f[0][0] + c3 + Al};
-        c3 = f[0][3];
-        c2 = f[0][2];
-        if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
-        bl = tl;
-        br = tr;
-      }
-    }
-  }
-  op.finish(red);
 }
 
 template <class T>
 hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                             const T *d, const uint8_t *qflag, const uint8_t *eact,
                             const uint8_t *nflag, const T *z, const T *p_old, T *p_new, T *q,
-                            CgScal *sc, RedScratch rs) {
-  OpTangent<T, true, true> op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, sc, rs, T(0), 0};
-  const int waves = m.nstrips * m.nchunks;
-  const int blocks = (waves + WPB - 1) / WPB;
-  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tangent_cg<T>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+                            const CgArgs &ca) {
+  using Op = OpTangent<T, true, true>;
+  Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0)};
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<Op>), dim3(ca.ga), dim3(TPB), 0, s, op, g, m,
+                     ca);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
-                          const T *p_old, T *p_new, T *q, CgScal *sc, RedScratch rs) {
-  OpPhase<T, true, true> op{g, c, coef, eact, nflag, z, p_old, p_new, q, sc, rs, T(0), 0};
-  const int waves = m.nstrips * m.nchunks;
-  const int blocks = (waves + WPB - 1) / WPB;
-  if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_phase_cg<T>), dim3(blocks), dim3(TPB), 0, s, op, g, m);
+                          const T *p_old, T *p_new, T *q, const CgArgs &ca) {
+  using Op = OpPhase<T, true, true>;
+  Op op{g, c, coef, eact, nflag, z, p_old, p_new, q, T(0)};
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<Op>), dim3(ca.ga), dim3(TPB), 0, s, op, g, m,
+                     ca);
   return hipGetLastError();
 }
 
@@ -1160,44 +1155,42 @@ hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const Elas
                         const T *d, const uint8_t *qflag, const uint8_t *eact,
                         const uint8_t *nflag, T *Dinv) {
   OpTangentDiag<T> op{g, c, d, qflag, eact, nflag, Dinv};
-  return launch_march(s, op, g, m);
+  return launch_march(s, op, g, m, nullptr);
 }
 
 template <class T>
 hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                       const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv) {
   OpPhaseDiag<T> op{g, c, coef, eact, nflag, Dinv};
-  return launch_march(s, op, g, m);
+  return launch_march(s, op, g, m, nullptr);
 }
 
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                                const double *d, const uint8_t *qflag, const uint8_t *eact,
                                const double *p, double *q) {
-  OpTangent<double, false, false> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q,
-                                     nullptr, RedScratch{}, 0.0, 0};
-  return launch_march(s, op, g, m);
+  OpTangent<double, false, false> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q, 0.0};
+  return launch_march(s, op, g, m, nullptr);
 }
 
 hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                              const double *coef, const uint8_t *eact, const double *p,
                              double *q) {
-  OpPhase<double, false, false> op{g, c, coef, eact, nullptr, p, nullptr, nullptr, q,
-                                   nullptr, RedScratch{}, 0.0, 0};
-  return launch_march(s, op, g, m);
+  OpPhase<double, false, false> op{g, c, coef, eact, nullptr, p, nullptr, nullptr, q, 0.0};
+  return launch_march(s, op, g, m, nullptr);
 }
 
 hipError_t internal_force(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                           const double *u, const double *d, const uint8_t *eact,
                           const uint8_t *nflag, bool neg, double *R, RedScratch rs) {
-  OpForce op{g, c, u, d, eact, nflag, R, rs, neg ? -1.0 : 1.0};
-  return launch_march(s, op, g, m);
+  OpForce op{g, c, u, d, eact, nflag, R, neg ? -1.0 : 1.0};
+  return launch_march_reduce<OpForce, 1>(s, op, g, m, rs, SC_NORM_A);
 }
 
 hipError_t phase_residual(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const double *H, const double *d, const uint8_t *eact,
                           const uint8_t *nflag, bool neg, double *R, RedScratch rs) {
-  OpPhaseRes op{g, c, H, d, eact, nflag, R, rs, neg ? -1.0 : 1.0};
-  return launch_march(s, op, g, m);
+  OpPhaseRes op{g, c, H, d, eact, nflag, R, neg ? -1.0 : 1.0};
+  return launch_march_reduce<OpPhaseRes, 2>(s, op, g, m, rs, SC_NORM_A);
 }
 
 hipError_t qp_update(hipStream_t s, const Grid &g, const Mat &mt, const QpParams &qp,
@@ -1291,18 +1284,18 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
 
 // -------------------------------------------------- explicit instantiation
 #define PF_INST(T)                                                                              \
-  template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *, CgScal *,    \
-                                 double, int, RedScratch);                                     \
+  template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *,             \
+                                 const CgArgs &);                                              \
   template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
-                                   const T *, CgScal *, RedScratch);                           \
+                                   const T *, const CgArgs &);                                 \
   template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
                                           const ElasCoef &, const T *, const uint8_t *,        \
                                           const uint8_t *, const uint8_t *, const T *,         \
-                                          const T *, T *, T *, CgScal *, RedScratch);          \
+                                          const T *, T *, T *, const CgArgs &);                \
   template hipError_t phase_cg_apply<T>(hipStream_t, const Grid &, const March &,              \
                                         const PhaseCoef &, const T *, const uint8_t *,         \
                                         const uint8_t *, const T *, const T *, T *, T *,       \
-                                        CgScal *, RedScratch);                                 \
+                                        const CgArgs &);                                       \
   template hipError_t tangent_diag<T>(hipStream_t, const Grid &, const March &,                \
                                       const ElasCoef &, const T *, const uint8_t *,            \
                                       const uint8_t *, const uint8_t *, T *);                  \

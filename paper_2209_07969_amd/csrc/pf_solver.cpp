@@ -68,13 +68,19 @@ struct pf_ctx {
   uint8_t *nflag = nullptr, *qflag = nullptr, *tflag = nullptr, *eact = nullptr;
   CgBuf<double> bd;
   CgBuf<float> bf;
-  CgScal *cgs = nullptr;
+  CgState *cgs = nullptr;
   RedScratch rs{};
   // pinned host mirrors
-  CgScal *cgs_h = nullptr;
+  CgState *cgs_h = nullptr;
   double *scal_h = nullptr;
   unsigned long long *icount_h = nullptr;
   std::vector<void *> allocs;
+
+  // sampled kernel timing
+  bool profiling = false;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t prof_launches[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
 
   // step state
   bool step_open = false;
@@ -234,28 +240,45 @@ template <class T>
 pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
   CgBuf<T> &b = buf<T>(c);
   const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
-  PF_HIP(c, cg_init<T>(c->stream, n, b.x, b.r, b.z, b.p0, b.Dinv, c->cgs, tol, c->opts.max_cg,
-                       c->rs));
+  const CgArgs ca = cg_args(c->g, c->ms, n, c->cgs, c->rs, tol, c->opts.max_cg);
+  PF_HIP(c, cg_init<T>(c->stream, n, b.x, b.r, b.z, b.p0, b.Dinv, ca));
   T *pold = b.p0, *pnew = b.p1;
   const int batch = std::max(1, c->opts.cg_check);
+  const int kid = (kind == K_ELASTIC) ? 0 : 1;
   for (;;) {
+    // the first iteration of a batch is the timed sample (it always runs:
+    // the status word was polled as "running" just before)
+    const bool timed = c->profiling;
     for (int k = 0; k < batch; ++k) {
+      const bool t = timed && k == 0;
+      if (t) PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
       if (kind == K_ELASTIC) {
         PF_HIP(c, tangent_cg_apply<T>(c->stream, c->g, c->ms, c->ec, b.d, c->tflag, c->eact,
-                                      c->nflag, b.z, pold, pnew, b.q, c->cgs, c->rs));
+                                      c->nflag, b.z, pold, pnew, b.q, ca));
       } else {
         PF_HIP(c, phase_cg_apply<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
-                                    b.z, pold, pnew, b.q, c->cgs, c->rs));
+                                    b.z, pold, pnew, b.q, ca));
       }
-      PF_HIP(c, cg_update<T>(c->stream, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, c->cgs, c->rs));
+      if (t) PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
+      PF_HIP(c, cg_update<T>(c->stream, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, ca));
+      if (t) PF_HIP(c, hipEventRecord(c->ev[2], c->stream));
       std::swap(pold, pnew);
     }
-    PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, sizeof(CgScal), hipMemcpyDeviceToHost, c->stream));
+    PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
     PF_TRY(sync(c));
-    if (c->cgs_h->done != 0) break;
+    if (timed) {
+      float a = 0.f, u = 0.f;
+      PF_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+      PF_HIP(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
+      c->prof_launches[kid] += 1;
+      c->prof_ms[kid] += a;
+      c->prof_launches[2] += 1;
+      c->prof_ms[2] += u;
+    }
+    if (c->cgs_h->b.done != 0) break;
   }
-  *iters = c->cgs_h->iters;
-  *status = c->cgs_h->done;
+  *iters = c->cgs_h->b.iters;
+  *status = c->cgs_h->b.done;
   return PF_OK;
 }
 
@@ -618,8 +641,9 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     A(&c->bf.q, n2); A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
   }
   A(&c->cgs, 1);
-  A(&c->rs.part, (size_t)kRedSlots * kMaxBlocks);
-  A(&c->rs.counter, kRedCounters);
+  A(&c->rs.partA, (size_t)kPMax);
+  A(&c->rs.partB, 2 * (size_t)kPMax);
+  A(&c->rs.partR, 2 * (size_t)kPMax);
   A(&c->rs.icount, kICounters);
   A(&c->rs.scal, kScal);
   if (mesh->elem_active) {
@@ -630,7 +654,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
       s = PF_E_HIP;
   }
   if (s == PF_OK) {
-    if (hipHostMalloc((void **)&c->cgs_h, sizeof(CgScal)) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->cgs_h, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess)
       s = PF_E_OOM;
@@ -652,6 +676,8 @@ pf_status pf_destroy(pf_ctx *c) {
     if (gr.d_dof) (void)hipFree(gr.d_dof);
     if (gr.d_comp) (void)hipFree(gr.d_comp);
   }
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->cgs_h) (void)hipHostFree(c->cgs_h);
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
@@ -767,6 +793,28 @@ pf_status pf_set_state(pf_ctx *c, const double *u, const double *d, const double
   if (u) PF_HIP(c, hipMemcpy(c->u, u, n2 * sizeof(double), hipMemcpyHostToDevice));
   if (d) PF_HIP(c, hipMemcpy(c->d, d, n * sizeof(double), hipMemcpyHostToDevice));
   if (H) PF_HIP(c, hipMemcpy(c->H_prev, H, e4 * sizeof(double), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+pf_status pf_set_profiling(pf_ctx *c, int32_t enable) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (enable && !c->ev[0]) {
+    for (auto &e : c->ev) PF_HIP(c, hipEventCreate(&e));
+  }
+  c->profiling = enable != 0;
+  for (int k = 0; k < 3; ++k) {
+    c->prof_launches[k] = 0;
+    c->prof_ms[k] = 0.0;
+  }
+  return PF_OK;
+}
+
+pf_status pf_kernel_time(pf_ctx *c, int32_t kernel, int64_t *launches, double *total_ms,
+                         int64_t *nodes_per_launch) {
+  if (!c || kernel < 0 || kernel > 2) return PF_E_INVALID_ARG;
+  if (launches) *launches = c->prof_launches[kernel];
+  if (total_ms) *total_ms = c->prof_ms[kernel];
+  if (nodes_per_launch) *nodes_per_launch = c->g.N;
   return PF_OK;
 }
 
