@@ -176,12 +176,14 @@ const char *pf_last_error(const pf_ctx *ctx);
 /* Number of free displacement / phase DOFs (after Dirichlet data and mask). */
 pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
 
-/* Kernel timing for measurement.  When enabled, the CG drivers bracket one
- * launch per enqueued batch of each CG kernel with HIP events on the
- * context's stream (a sample of the launches, so the overhead stays
- * negligible) and accumulate the elapsed times.  kernel: 0 = elasticity
- * tangent apply (fused CG direction update), 1 = phase operator apply
- * (fused), 2 = CG vector update.  Enabling resets the counters. */
+/* Kernel timing for measurement.  When enabled, the CG drivers time a sample
+ * of the CG kernel launches with HIP events on the context's stream: per
+ * enqueued batch, the first iteration's operator apply is launched four
+ * times back to back (it is idempotent) between one event pair, and its
+ * vector update once.  Launch counts and elapsed times accumulate.
+ * kernel: 0 = elasticity tangent apply (fused CG direction update),
+ * 1 = phase operator apply (fused), 2 = CG vector update.  Enabling resets
+ * the counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,
                          int64_t *nodes_per_launch);

@@ -121,27 +121,30 @@ hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Di
 template <class T>
 hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
                      const T *Dinv, const CgArgs &ca);
+// split = 1 (spectral): the tangent is re-derived per QP from the
+// linearisation point ulin [2N] instead of the indicator bits.
 template <class T>
 hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                            const T *d, const uint8_t *qflag, const uint8_t *eact,
-                            const uint8_t *nflag, const T *z, const T *p_old, T *p_new,
-                            T *q, const CgArgs &ca);
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *z,
+                            const T *p_old, T *p_new, T *q, const CgArgs &ca);
 template <class T>
 hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const T *coef, const uint8_t *eact, const uint8_t *nflag,
                           const T *z, const T *p_old, T *p_new, T *q, const CgArgs &ca);
 template <class T>
 hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                        const T *d, const uint8_t *qflag, const uint8_t *eact,
-                        const uint8_t *nflag, T *Dinv);
+                        int split, const T *ulin, const T *d, const uint8_t *qflag,
+                        const uint8_t *eact, const uint8_t *nflag, T *Dinv);
 template <class T>
 hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                       const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv);
 
 // Plain operator applies (no CG fusion, no masking) for the op entry points.
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                               const double *d, const uint8_t *qflag, const uint8_t *eact,
-                               const double *p, double *q);
+                               int split, const double *ulin, const double *d,
+                               const uint8_t *qflag, const uint8_t *eact, const double *p,
+                               double *q);
 hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                              const double *coef, const uint8_t *eact, const double *p,
                              double *q);
@@ -150,7 +153,7 @@ hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const
 // fixed DOFs are zeroed, optionally negated (neg), and ||R||^2 over free DOFs
 // goes to scal[SC_NORM_A].
 hipError_t internal_force(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                          const double *u, const double *d, const uint8_t *eact,
+                          int split, const double *u, const double *d, const uint8_t *eact,
                           const uint8_t *nflag, bool neg, double *R, RedScratch rs);
 // Phase residual R_d = K_dd(H) d - b(H) on free nodes (0 on fixed), written
 // negated if neg; ||R_d||^2 -> scal[SC_NORM_A], ||b||^2 -> scal[SC_NORM_B].

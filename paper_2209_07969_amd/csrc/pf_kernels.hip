@@ -35,7 +35,6 @@ namespace {
 
 constexpr double GA = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
 constexpr double GB = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
-constexpr int STRIP = 63;
 constexpr int WPB = 4;                            // waves per block (march)
 constexpr int TPB = 256;
 
@@ -199,6 +198,156 @@ __device__ inline void elastic_diag_element(const T (&dn)[4], unsigned bits, con
 #undef PF_QP
 }
 
+// Spectral split (Miehe), plane strain with the out-of-plane eigenvalue 0.
+// In-plane eigenvalues e1 >= e2 of eps; with P1 = (eps - e2 I)/(e1 - e2) the
+// active strain is eps+ = eps (e2 > 0), 0 (e1 <= 0) or e1 P1 (mixed signs),
+// and its derivative along an increment de is de, 0 or
+//   (1 - 2 th)(P1:de) P1 + th (P1 de + de P1),  th = e1/(e1 - e2).
+// In the mixed case e1 - e2 >= max(e1, -e2) > 0, so no division degenerates.
+// Stress: sigma = lam kap t I + 2 mu (g - 1) eps+ + 2 mu eps, kap = g if
+// t > 0 else 1 (the same for the tangent with eps+ -> d eps+).
+template <class T>
+struct SpecLin {
+  T a, b, cc, th, e1;
+  int cs;   // 0: no eigenvalue active, 1: both active, 2: only e1 active
+};
+
+template <class T>
+__device__ inline void spec_lin(T exx, T eyy, T exy, SpecLin<T> &s) {
+  const T t = exx + eyy;
+  const T dd = T(0.5) * (exx - eyy);
+  const T r = sqrt(dd * dd + exy * exy);
+  const T e1 = T(0.5) * t + r, e2 = T(0.5) * t - r;
+  s.e1 = e1;
+  s.a = s.b = s.cc = s.th = T(0);
+  if (e2 > T(0)) {
+    s.cs = 1;
+  } else if (!(e1 > T(0))) {
+    s.cs = 0;
+  } else {
+    s.cs = 2;
+    const T D = e1 - e2;
+    s.a = (exx - e2) / D;
+    s.b = exy / D;
+    s.cc = (eyy - e2) / D;
+    s.th = e1 / D;
+  }
+}
+
+template <class T>
+__device__ inline void spec_dplus(const SpecLin<T> &s, T dxx, T dyy, T dxy, T &oxx, T &oyy,
+                                  T &oxy) {
+  if (s.cs == 1) {
+    oxx = dxx; oyy = dyy; oxy = dxy;
+  } else if (s.cs == 0) {
+    oxx = T(0); oyy = T(0); oxy = T(0);
+  } else {
+    const T sp = s.a * dxx + T(2) * s.b * dxy + s.cc * dyy;
+    const T k1 = (T(1) - T(2) * s.th) * sp;
+    oxx = k1 * s.a + T(2) * s.th * (s.a * dxx + s.b * dxy);
+    oyy = k1 * s.cc + T(2) * s.th * (s.b * dxy + s.cc * dyy);
+    oxy = k1 * s.b + s.th * (s.b * (dxx + dyy) + dxy);
+  }
+}
+
+// Spectral-split element: NONLIN = internal force at (ux, uy); otherwise the
+// tangent at the linearisation point (lx, ly) applied to (ux, uy).
+template <class T, bool NONLIN>
+__device__ inline void spectral_element(const T (&ux)[4], const T (&uy)[4], const T (&dn)[4],
+                                        const T (&lx)[4], const T (&ly)[4], const ElasCoef &c,
+                                        T (&fx)[4], T (&fy)[4]) {
+  const T Dbx = ux[1] - ux[0], Dtx = ux[2] - ux[3], Dlx = ux[3] - ux[0], Drx = ux[2] - ux[1];
+  const T Dby = uy[1] - uy[0], Dty = uy[2] - uy[3], Dly = uy[3] - uy[0], Dry = uy[2] - uy[1];
+  const T Lbx = lx[1] - lx[0], Ltx = lx[2] - lx[3], Llx = lx[3] - lx[0], Lrx = lx[2] - lx[1];
+  const T Lby = ly[1] - ly[0], Lty = ly[2] - ly[3], Lly = ly[3] - ly[0], Lry = ly[2] - ly[1];
+  const T ihx = T(c.ihx), ihy = T(c.ihy), twomu = T(c.two_mu), lam = T(c.lam), eta = T(c.eta);
+  T Ebx = 0, Etx = 0, Elx = 0, Erx = 0, Eby = 0, Ety = 0, Ely = 0, Ery = 0;
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T exx = (wB * Dbx + wT * Dtx) * ihx;                                           \
+    const T eyy = (wL * Dly + wR * Dry) * ihy;                                           \
+    const T exy = T(0.5) * ((wL * Dlx + wR * Drx) * ihy + (wB * Dby + wT * Dty) * ihx);  \
+    T pxx, pyy, pxy, tl;                                                                 \
+    if (NONLIN) {                                                                        \
+      SpecLin<T> sl;                                                                     \
+      spec_lin(exx, eyy, exy, sl);                                                       \
+      if (sl.cs == 1) { pxx = exx; pyy = eyy; pxy = exy; }                               \
+      else if (sl.cs == 0) { pxx = T(0); pyy = T(0); pxy = T(0); }                       \
+      else { pxx = sl.e1 * sl.a; pyy = sl.e1 * sl.cc; pxy = sl.e1 * sl.b; }              \
+      tl = exx + eyy;                                                                    \
+    } else {                                                                             \
+      const T lxx = (wB * Lbx + wT * Ltx) * ihx;                                         \
+      const T lyy = (wL * Lly + wR * Lry) * ihy;                                         \
+      const T lxy = T(0.5) * ((wL * Llx + wR * Lrx) * ihy + (wB * Lby + wT * Lty) * ihx);\
+      SpecLin<T> sl;                                                                     \
+      spec_lin(lxx, lyy, lxy, sl);                                                       \
+      spec_dplus(sl, exx, eyy, exy, pxx, pyy, pxy);                                      \
+      tl = lxx + lyy;                                                                    \
+    }                                                                                    \
+    const T dq = interp4<T, q>(dn[0], dn[1], dn[2], dn[3]);                              \
+    const T om = T(1) - dq;                                                              \
+    const T gq = om * om + eta;                                                          \
+    const T kv = lam * ((tl > T(0)) ? gq : T(1)) * (exx + eyy);                          \
+    const T m2 = twomu * (gq - T(1));                                                    \
+    const T sxx = kv + m2 * pxx + twomu * exx;                                           \
+    const T syy = kv + m2 * pyy + twomu * eyy;                                           \
+    const T sxy = m2 * pxy + twomu * exy;                                                \
+    Ebx += wB * sxx; Etx += wT * sxx; Elx += wL * sxy; Erx += wR * sxy;                  \
+    Eby += wB * sxy; Ety += wT * sxy; Ely += wL * syy; Ery += wR * syy;                  \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  const T sx = T(c.sx), sy = T(c.sy);
+  Ebx *= sx; Etx *= sx; Elx *= sy; Erx *= sy;
+  Eby *= sx; Ety *= sx; Ely *= sy; Ery *= sy;
+  fx[0] = -Ebx - Elx; fx[1] = Ebx - Erx; fx[2] = Etx + Erx; fx[3] = Elx - Etx;
+  fy[0] = -Eby - Ely; fy[1] = Eby - Ery; fy[2] = Ety + Ery; fy[3] = Ely - Ety;
+}
+
+// Diagonal of the spectral tangent at (lx, ly): the unit nodal value of
+// corner a, component x, has strain (Nx, 0, Ny/2) and contributes
+// sxx Nx + sxy Ny (component y: (0, Ny, Nx/2) -> syy Ny + sxy Nx).
+template <class T>
+__device__ inline void spectral_diag_element(const T (&dn)[4], const T (&lx)[4], const T (&ly)[4],
+                                             const ElasCoef &c, T (&fx)[4], T (&fy)[4]) {
+  const T Lbx = lx[1] - lx[0], Ltx = lx[2] - lx[3], Llx = lx[3] - lx[0], Lrx = lx[2] - lx[1];
+  const T Lby = ly[1] - ly[0], Lty = ly[2] - ly[3], Lly = ly[3] - ly[0], Lry = ly[2] - ly[1];
+  const T ihx = T(c.ihx), ihy = T(c.ihy), twomu = T(c.two_mu), lam = T(c.lam);
+  const T wdet = T(c.sx) / T(c.ihx);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { fx[a] = 0; fy[a] = 0; }
+#define PF_QP(q)                                                                         \
+  {                                                                                      \
+    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
+    const T lxx = (wB * Lbx + wT * Ltx) * ihx;                                           \
+    const T lyy = (wL * Lly + wR * Lry) * ihy;                                           \
+    const T lxy = T(0.5) * ((wL * Llx + wR * Lrx) * ihy + (wB * Lby + wT * Lty) * ihx);  \
+    SpecLin<T> sl;                                                                       \
+    spec_lin(lxx, lyy, lxy, sl);                                                         \
+    const T dq = interp4<T, q>(dn[0], dn[1], dn[2], dn[3]);                              \
+    const T om = T(1) - dq;                                                              \
+    const T gq = om * om + T(c.eta);                                                     \
+    const T kap = lam * ((lxx + lyy > T(0)) ? gq : T(1));                                \
+    const T m2 = twomu * (gq - T(1));                                                    \
+    const T Nx[4] = {-wB * ihx, wB * ihx, wT * ihx, -wT * ihx};                          \
+    const T Ny[4] = {-wL * ihy, -wR * ihy, wR * ihy, wL * ihy};                          \
+    for (int a = 0; a < 4; ++a) {                                                        \
+      T pxx, pyy, pxy;                                                                   \
+      spec_dplus(sl, Nx[a], T(0), T(0.5) * Ny[a], pxx, pyy, pxy);                        \
+      const T sxx = kap * Nx[a] + m2 * pxx + twomu * Nx[a];                              \
+      const T sxy = m2 * pxy + twomu * T(0.5) * Ny[a];                                   \
+      fx[a] += wdet * (sxx * Nx[a] + sxy * Ny[a]);                                       \
+      spec_dplus(sl, T(0), Ny[a], T(0.5) * Nx[a], pxx, pyy, pxy);                        \
+      const T syy = kap * Ny[a] + m2 * pyy + twomu * Ny[a];                              \
+      const T sxy2 = m2 * pxy + twomu * T(0.5) * Nx[a];                                  \
+      fy[a] += wdet * (syy * Ny[a] + sxy2 * Nx[a]);                                      \
+    }                                                                                    \
+  }
+  PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+}
+
 // Phase operator sum [c_q N N^T + Gc l grad N grad N^T] w detJ applied to p.
 template <class T>
 __device__ inline void phase_element(const T (&p)[4], const T (&cq)[4], const PhaseCoef &c,
@@ -243,47 +392,71 @@ __device__ inline void phase_diag_element(const T (&cq)[4], const PhaseCoef &c, 
 
 // ------------------------------------------------------- marching kernel
 //
+// Work item = (strip, chunk).  Lane L of a wave holds node column
+// c = 62*strip - 1 + L and computes element column c - 1 (lane 0 computes
+// none), so the wave owns node columns 62*strip .. 62*strip + 61 and each
+// node is summed once: corner 0 of its own element plus, by one lane
+// shuffle, corner 1 of the left neighbour's.  The chunk owns CH node rows;
+// all CH + 2 node rows and CH + 1 element rows of a work item are loaded
+// into registers before any element is computed, so a wave has its whole
+// item in flight at once.
+//
 // An Op provides:
 //   T, Node, Elem, NF (accumulated components), NR (reduction values)
-//   Node load(i, j)          node values, zero outside the grid
-//   Node zero()
-//   Elem eload(ie, je)       element data (flags, coefficients)
-//   void element(bl, br, tr, tl, ie, je, const Elem&, T f[NF][4])
+//   Node load(i, j)          raw node values, zero outside the grid
+//   void fin(Node &)         turn raw values into operand values (CG: p = z + beta p_old)
+//   Elem eload(ie, je)       element data (flags, coefficients); .active = 0 if none
+//   void element(bl, br, tr, tl, const Elem&, T f[NF][4])
 //   void store(i, j, const T v[NF], const Node &n, double red[NR])
 //   static Node shfl_up(const Node&)   lane L receives lane L-1's value
-// The next row's node and element loads are issued before the current row's
-// element is computed.
 
-template <class Op>
-__device__ inline void march_wave(const Op &op, const Grid &g, const March &ms, int w, int lane,
-                                  double *red) {
+constexpr int CSTRIP = 62;
+
+template <int CH, class Op>
+struct Item {
+  typename Op::Node R[CH + 2];
+  typename Op::Elem El[CH + 1];
+};
+
+template <int CH, class Op>
+__device__ inline void item_load(const Op &op, const Grid &g, const March &ms, int w, int lane,
+                                 Item<CH, Op> &it) {
+  const int strip = w % ms.nstrips;
+  const int chunk = w / ms.nstrips;
+  const int c = strip * CSTRIP - 1 + lane;
+  const int j0 = chunk * CH;
+#pragma unroll
+  for (int r = 0; r < CH + 2; ++r) it.R[r] = op.load(c, j0 - 1 + r);
+#pragma unroll
+  for (int r = 0; r < CH + 1; ++r)
+    it.El[r] = (lane > 0) ? op.eload(c - 1, j0 - 1 + r) : typename Op::Elem{};
+}
+
+template <int CH, class Op>
+__device__ inline void item_compute(const Op &op, const Grid &g, const March &ms, int w,
+                                    int lane, Item<CH, Op> &it, double *red) {
   using T = typename Op::T;
   using Node = typename Op::Node;
-  using Elem = typename Op::Elem;
   constexpr int NF = Op::NF;
   const int strip = w % ms.nstrips;
   const int chunk = w / ms.nstrips;
-  const int ie = strip * STRIP - 1 + lane;
-  const int j0 = chunk * ms.ch;
-  const int j1 = min(j0 + ms.ch, g.ny + 1);
-  const bool own_col = lane > 0 && ie >= 0 && ie <= g.nx;
-  Node bl = op.load(ie, j0 - 1);
-  Node br = op.load(ie + 1, j0 - 1);
-  Node tr = op.load(ie + 1, j0);
-  Node tl0 = (lane == 0) ? op.load(ie, j0) : op.zero();
-  Elem el = op.eload(ie, j0 - 1);
+  const int n = strip * CSTRIP - 2 + lane;          // node column this lane stores
+  const int j0 = chunk * CH;
+  const bool own_col = lane >= 2 && n >= 0 && n <= g.nx;
+#pragma unroll
+  for (int r = 0; r < CH + 2; ++r) op.fin(it.R[r]);
+  Node br = it.R[0];
+  Node bl = Op::shfl_up(br);
   T c2[NF], c3[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) { c2[k] = T(0); c3[k] = T(0); }
-  for (int je = j0 - 1; je < j1; ++je) {
-    const bool more = je + 1 < j1;
-    const Node trn = more ? op.load(ie + 1, je + 2) : op.zero();
-    const Node tl0n = (more && lane == 0) ? op.load(ie, je + 2) : op.zero();
-    const Elem eln = more ? op.eload(ie, je + 1) : Elem{};
-    Node tl = Op::shfl_up(tr);
-    if (lane == 0) tl = tl0;
+#pragma unroll
+  for (int r = 0; r < CH + 1; ++r) {
+    const int je = j0 - 1 + r;
+    const Node tr = it.R[r + 1];
+    const Node tl = Op::shfl_up(tr);
     T f[NF][4];
-    op.element(bl, br, tr, tl, ie, je, el, f);
+    op.element(bl, br, tr, tl, it.El[r], f);
     T out[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
@@ -293,27 +466,32 @@ __device__ inline void march_wave(const Op &op, const Grid &g, const March &ms, 
       c3[k] = f[k][3];
       c2[k] = f[k][2];
     }
-    if (je >= j0 && own_col) op.store(ie, je, out, bl, red);
+    if (r >= 1 && own_col && je <= g.ny) op.store(n, je, out, bl, red);
     bl = tl;
     br = tr;
-    tr = trn;
-    tl0 = tl0n;
-    el = eln;
   }
 }
 
-// Generic marching kernel: waves loop over (strip, chunk) work items; an op
-// with NR > 0 writes block partials to `part`.
-template <class Op>
+template <int CH, class Op>
+__device__ inline void march_items(const Op &op, const Grid &g, const March &ms, int wfirst,
+                                   double *red) {
+  const int lane = threadIdx.x & 63;
+  const int nw = ms.nstrips * ms.nchunks;
+  for (int w = wfirst; w < nw; w += gridDim.x * WPB) {
+    Item<CH, Op> it;
+    item_load<CH>(op, g, ms, w, lane, it);
+    item_compute<CH>(op, g, ms, w, lane, it, red);
+  }
+}
+
+// Generic marching kernel; an op with NR > 0 writes block partials to `part`.
+template <int CH, class Op>
 __global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms, double *part) {
   constexpr int NRR = Op::NR > 0 ? Op::NR : 1;
   double red[NRR];
 #pragma unroll
   for (int k = 0; k < NRR; ++k) red[k] = 0.0;
-  const int lane = threadIdx.x & 63;
-  const int nw = ms.nstrips * ms.nchunks;
-  for (int w = blockIdx.x * WPB + (threadIdx.x >> 6); w < nw; w += gridDim.x * WPB)
-    march_wave(op, g, ms, w, lane, red);
+  march_items<CH>(op, g, ms, blockIdx.x * WPB + (threadIdx.x >> 6), red);
   if (Op::NR > 0) block_partial<NRR>(red, part);
 }
 
@@ -331,33 +509,44 @@ struct ElemNone { uint8_t active; };
 
 // ---- elasticity tangent (optionally fused with the CG direction update
 //      p = z + beta p_old; the fused op also accumulates p.q)
-template <class TT, bool FUSED, bool MASK>
+template <class TT, bool FUSED, bool MASK, int SPL = 0>
 struct OpTangent {
   using T = TT;
   using Elem = ElemFlags;
   static constexpr int NF = 2;
   static constexpr int NR = FUSED ? 1 : 0;
-  struct Node { T px, py, d; };
+  // raw: px, py = z; ox, oy = p_old (fused only); fin: p = z + beta p_old;
+  // lx, ly = linearisation point (spectral split only)
+  struct Node { T px, py, d, ox, oy, lx, ly; };
   Grid g; ElasCoef c;
   const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag;
   const T *z; const T *pold; T *pnew; T *q;
   T beta;
+  const T *ulin;
 
-  __device__ Node zero() const { return Node{T(0), T(0), T(0)}; }
   __device__ Node load(int i, int j) const {
-    Node n{T(0), T(0), T(0)};
+    Node n{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     if (node_exists(g, i, j)) {
       const int k = i + j * (g.nx + 1);
+      n.px = z[k];
+      n.py = z[k + g.N];
       if (FUSED) {
-        n.px = z[k] + beta * pold[k];
-        n.py = z[k + g.N] + beta * pold[k + g.N];
-      } else {
-        n.px = z[k];
-        n.py = z[k + g.N];
+        n.ox = pold[k];
+        n.oy = pold[k + g.N];
+      }
+      if (SPL == 1) {
+        n.lx = ulin[k];
+        n.ly = ulin[k + g.N];
       }
       n.d = d[k];
     }
     return n;
+  }
+  __device__ void fin(Node &n) const {
+    if (FUSED) {
+      n.px += beta * n.ox;
+      n.py += beta * n.oy;
+    }
   }
   __device__ Elem eload(int ie, int je) const {
     Elem e{0, 0};
@@ -368,10 +557,12 @@ struct OpTangent {
     return e;
   }
   static __device__ Node shfl_up(const Node &n) {
-    return Node{__shfl_up(n.px, 1, 64), __shfl_up(n.py, 1, 64), __shfl_up(n.d, 1, 64)};
+    return Node{__shfl_up(n.px, 1, 64), __shfl_up(n.py, 1, 64), __shfl_up(n.d, 1, 64), T(0),
+                T(0), SPL == 1 ? __shfl_up(n.lx, 1, 64) : T(0),
+                SPL == 1 ? __shfl_up(n.ly, 1, 64) : T(0)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int, int, const Elem &e, T (&f)[2][4]) const {
+                          const Elem &e, T (&f)[2][4]) const {
     if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
@@ -380,7 +571,13 @@ struct OpTangent {
     const T ux[4] = {n0.px, n1.px, n2.px, n3.px};
     const T uy[4] = {n0.py, n1.py, n2.py, n3.py};
     const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    elastic_element<T, false>(ux, uy, dn, e.bits, c, f[0], f[1]);
+    if (SPL == 1) {
+      const T lx[4] = {n0.lx, n1.lx, n2.lx, n3.lx};
+      const T ly[4] = {n0.ly, n1.ly, n2.ly, n3.ly};
+      spectral_element<T, false>(ux, uy, dn, lx, ly, c, f[0], f[1]);
+    } else {
+      elastic_element<T, false>(ux, uy, dn, e.bits, c, f[0], f[1]);
+    }
   }
   __device__ void store(int i, int j, const T (&v)[2], const Node &n, double *red) const {
     const int k = i + j * (g.nx + 1);
@@ -407,20 +604,23 @@ struct OpPhase {
   using Elem = ElemCoef<TT>;
   static constexpr int NF = 1;
   static constexpr int NR = FUSED ? 1 : 0;
-  struct Node { T p; };
+  struct Node { T p, o; };
   Grid g; PhaseCoef c;
   const T *coef; const uint8_t *eact; const uint8_t *nflag;
   const T *z; const T *pold; T *pnew; T *q;
   T beta;
 
-  __device__ Node zero() const { return Node{T(0)}; }
   __device__ Node load(int i, int j) const {
-    Node n{T(0)};
+    Node n{T(0), T(0)};
     if (node_exists(g, i, j)) {
       const int k = i + j * (g.nx + 1);
-      n.p = FUSED ? z[k] + beta * pold[k] : z[k];
+      n.p = z[k];
+      if (FUSED) n.o = pold[k];
     }
     return n;
+  }
+  __device__ void fin(Node &n) const {
+    if (FUSED) n.p += beta * n.o;
   }
   __device__ Elem eload(int ie, int je) const {
     Elem e{};
@@ -434,9 +634,9 @@ struct OpPhase {
     }
     return e;
   }
-  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.p, 1, 64)}; }
+  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.p, 1, 64), T(0)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int, int, const Elem &e, T (&f)[1][4]) const {
+                          const Elem &e, T (&f)[1][4]) const {
     if (!e.active) {
       f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
       return;
@@ -459,6 +659,7 @@ struct OpPhase {
 
 // ---- internal force (FP64, nonlinear split stress); reduces ||R||^2 over
 //      free DOFs when a node-flag array is given
+template <int SPL>
 struct OpForce {
   using T = double;
   using Elem = ElemNone;
@@ -469,7 +670,6 @@ struct OpForce {
   const double *u; const double *dd; const uint8_t *eact; const uint8_t *nflag;
   double *R; double sign;
 
-  __device__ Node zero() const { return Node{0.0, 0.0, 0.0}; }
   __device__ Node load(int i, int j) const {
     Node n{0.0, 0.0, 0.0};
     if (node_exists(g, i, j)) {
@@ -478,6 +678,7 @@ struct OpForce {
     }
     return n;
   }
+  __device__ void fin(Node &) const {}
   __device__ Elem eload(int ie, int je) const {
     return Elem{uint8_t(elem_exists(g, ie, je, eact) ? 1 : 0)};
   }
@@ -485,7 +686,7 @@ struct OpForce {
     return Node{__shfl_up(n.ux, 1, 64), __shfl_up(n.uy, 1, 64), __shfl_up(n.d, 1, 64)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int, int, const Elem &e, double (&f)[2][4]) const {
+                          const Elem &e, double (&f)[2][4]) const {
     if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
@@ -494,7 +695,8 @@ struct OpForce {
     const double ux[4] = {n0.ux, n1.ux, n2.ux, n3.ux};
     const double uy[4] = {n0.uy, n1.uy, n2.uy, n3.uy};
     const double dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    elastic_element<double, true>(ux, uy, dn, 0u, c, f[0], f[1]);
+    if (SPL == 1) spectral_element<double, true>(ux, uy, dn, ux, uy, c, f[0], f[1]);
+    else elastic_element<double, true>(ux, uy, dn, 0u, c, f[0], f[1]);
   }
   __device__ void store(int i, int j, const double (&v)[2], const Node &, double *red) const {
     const int k = i + j * (g.nx + 1);
@@ -522,12 +724,12 @@ struct OpPhaseRes {
   const double *H; const double *dd; const uint8_t *eact; const uint8_t *nflag;
   double *R; double sign;
 
-  __device__ Node zero() const { return Node{0.0}; }
   __device__ Node load(int i, int j) const {
     Node n{0.0};
     if (node_exists(g, i, j)) n.d = dd[i + j * (g.nx + 1)];
     return n;
   }
+  __device__ void fin(Node &) const {}
   __device__ Elem eload(int ie, int je) const {
     Elem e{};
     if (elem_exists(g, ie, je, eact)) {
@@ -542,7 +744,7 @@ struct OpPhaseRes {
   }
   static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int, int, const Elem &e, double (&f)[2][4]) const {
+                          const Elem &e, double (&f)[2][4]) const {
     if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
@@ -573,21 +775,29 @@ struct OpPhaseRes {
 };
 
 // ---- Jacobi diagonals (inverse, 0 on fixed DOFs)
-template <class TT>
+template <class TT, int SPL = 0>
 struct OpTangentDiag {
   using T = TT;
   using Elem = ElemFlags;
   static constexpr int NF = 2;
   static constexpr int NR = 0;
-  struct Node { T d; };
+  struct Node { T d, lx, ly; };
   Grid g; ElasCoef c;
   const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
-  __device__ Node zero() const { return Node{T(0)}; }
+  const T *ulin;
   __device__ Node load(int i, int j) const {
-    Node n{T(0)};
-    if (node_exists(g, i, j)) n.d = d[i + j * (g.nx + 1)];
+    Node n{T(0), T(0), T(0)};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      n.d = d[k];
+      if (SPL == 1) {
+        n.lx = ulin[k];
+        n.ly = ulin[k + g.N];
+      }
+    }
     return n;
   }
+  __device__ void fin(Node &) const {}
   __device__ Elem eload(int ie, int je) const {
     Elem e{0, 0};
     if (elem_exists(g, ie, je, eact)) {
@@ -596,16 +806,25 @@ struct OpTangentDiag {
     }
     return e;
   }
-  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
+  static __device__ Node shfl_up(const Node &n) {
+    return Node{__shfl_up(n.d, 1, 64), SPL == 1 ? __shfl_up(n.lx, 1, 64) : T(0),
+                SPL == 1 ? __shfl_up(n.ly, 1, 64) : T(0)};
+  }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
-                          int, int, const Elem &e, T (&f)[2][4]) const {
+                          const Elem &e, T (&f)[2][4]) const {
     if (!e.active) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
       return;
     }
     const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    elastic_diag_element<T>(dn, e.bits, c, f[0], f[1]);
+    if (SPL == 1) {
+      const T lx[4] = {n0.lx, n1.lx, n2.lx, n3.lx};
+      const T ly[4] = {n0.ly, n1.ly, n2.ly, n3.ly};
+      spectral_diag_element<T>(dn, lx, ly, c, f[0], f[1]);
+    } else {
+      elastic_diag_element<T>(dn, e.bits, c, f[0], f[1]);
+    }
   }
   __device__ void store(int i, int j, const T (&v)[2], const Node &, double *) const {
     const int k = i + j * (g.nx + 1);
@@ -624,8 +843,8 @@ struct OpPhaseDiag {
   struct Node { T dummy; };
   Grid g; PhaseCoef c;
   const T *coef; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
-  __device__ Node zero() const { return Node{T(0)}; }
   __device__ Node load(int, int) const { return Node{T(0)}; }
+  __device__ void fin(Node &) const {}
   __device__ Elem eload(int ie, int je) const {
     Elem e{};
     if (elem_exists(g, ie, je, eact)) {
@@ -639,7 +858,7 @@ struct OpPhaseDiag {
     return e;
   }
   static __device__ Node shfl_up(const Node &n) { return n; }
-  __device__ void element(const Node &, const Node &, const Node &, const Node &, int, int,
+  __device__ void element(const Node &, const Node &, const Node &, const Node &,
                           const Elem &e, T (&f)[1][4]) const {
     if (!e.active) {
       f[0][0] = f[0][1] = f[0][2] = f[0][3] = T(0);
@@ -657,8 +876,13 @@ struct OpPhaseDiag {
 template <class Op>
 hipError_t launch_march(hipStream_t s, const Op &op, const Grid &g, const March &m,
                         double *part) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(march_blocks(m)), dim3(TPB), 0, s, op,
-                     g, m, part);
+  const dim3 grid(march_blocks(m)), block(TPB);
+  switch (m.ch) {
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<2, Op>), grid, block, 0, s, op, g, m, part); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<4, Op>), grid, block, 0, s, op, g, m, part); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<8, Op>), grid, block, 0, s, op, g, m, part); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -678,9 +902,7 @@ template <class Op, int NV>
 hipError_t launch_march_reduce(hipStream_t s, const Op &op, const Grid &g, const March &m,
                                RedScratch rs, int slot) {
   const int nb = march_blocks(m);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<Op>), dim3(nb), dim3(TPB), 0, s, op, g, m,
-                     rs.partR);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_march(s, op, g, m, rs.partR);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_finalize<NV>), dim3(1), dim3(TPB), 0, s, rs.partR, nb,
                      rs.scal, slot);
@@ -744,16 +966,20 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
   return done;
 }
 
-template <class Op>
+template <int CH, class Op>
 __global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+  const int lane = threadIdx.x & 63;
+  const int w0 = blockIdx.x * WPB + (threadIdx.x >> 6);
+  const int nw = ms.nstrips * ms.nchunks;
+  // issue the first work item's loads before the prologue's reduction
+  Item<CH, Op> it;
+  if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
   double beta = 0.0;
   if (cg_apply_prologue(ca, &beta) != 0) return;
   op.beta = typename Op::T(beta);
   double red[1] = {0.0};
-  const int lane = threadIdx.x & 63;
-  const int nw = ms.nstrips * ms.nchunks;
-  for (int w = blockIdx.x * WPB + (threadIdx.x >> 6); w < nw; w += gridDim.x * WPB)
-    march_wave(op, g, ms, w, lane, red);
+  if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
+  march_items<CH>(op, g, ms, w0 + gridDim.x * WPB, red);
   block_partial<1>(red, ca.partA);
 }
 
@@ -858,8 +1084,18 @@ __global__ void __launch_bounds__(TPB) k_qp_update(Grid g, Mat mt, QpParams qp,
     const double m3 = t * (1.0 / 3.0);                                                   \
     const double devdev = (exx - m3) * (exx - m3) + (eyy - m3) * (eyy - m3) + m3 * m3 + 2.0 * exy * exy; \
     const double tp = t > 0.0 ? t : 0.0;                                                 \
-    const double pvol = 0.5 * mt.K * tp * tp;                                           \
-    const double pdev = mt.mu * devdev;                                                  \
+    double pvol, pdev;                                                                   \
+    if (mt.split == 1) {                                                                 \
+      const double hd = 0.5 * (exx - eyy);                                               \
+      const double rr = sqrt(hd * hd + exy * exy);                                       \
+      const double e1 = 0.5 * t + rr, e2 = 0.5 * t - rr;                                 \
+      const double p1 = e1 > 0.0 ? e1 : 0.0, p2 = e2 > 0.0 ? e2 : 0.0;                   \
+      pvol = 0.5 * mt.lam * tp * tp;                                                     \
+      pdev = mt.mu * (p1 * p1 + p2 * p2);                                                \
+    } else {                                                                             \
+      pvol = 0.5 * mt.K * tp * tp;                                                       \
+      pdev = mt.mu * devdev;                                                             \
+    }                                                                                    \
     const double pplus = pvol + pdev;                                                    \
     const double hp = Hprev[e + q * g.E];                                                \
     H[e + q * g.E] = pplus > hp ? pplus : hp;                                            \
@@ -1085,13 +1321,18 @@ __global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
 
 March march_shape(const Grid &g, int ch_override) {
   March m;
-  m.nstrips = (g.nx + 1 + STRIP - 1) / STRIP;
+  m.nstrips = (g.nx + 1 + CSTRIP - 1) / CSTRIP;
   int ch = ch_override;
-  if (ch <= 0) {
-    // aim for about 2048 waves (8 per CU) with chunks of 2..32 rows
-    const long long target = 2048;
-    long long c = ((long long)(g.ny + 1) * m.nstrips + target - 1) / target;
-    ch = (int)(c < 2 ? 2 : (c > 32 ? 32 : c));
+  if (ch != 2 && ch != 4 && ch != 8) {
+    // smallest chunk that fits one work item per wave of a full launch
+    const long long waves = (long long)kPMax * WPB;
+    ch = 8;
+    for (int c : {2, 4}) {
+      if ((long long)m.nstrips * ((g.ny + 1 + c - 1) / c) <= waves) {
+        ch = c;
+        break;
+      }
+    }
   }
   m.ch = ch;
   m.nchunks = (g.ny + 1 + ch - 1) / ch;
@@ -1127,16 +1368,32 @@ hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T
   return hipGetLastError();
 }
 
+template <class Op>
+hipError_t launch_cg_apply(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                           const CgArgs &ca) {
+  const dim3 grid(ca.ga), block(TPB);
+  switch (m.ch) {
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<2, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<4, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<8, Op>), grid, block, 0, s, op, g, m, ca); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                            const T *d, const uint8_t *qflag, const uint8_t *eact,
-                            const uint8_t *nflag, const T *z, const T *p_old, T *p_new, T *q,
-                            const CgArgs &ca) {
-  using Op = OpTangent<T, true, true>;
-  Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0)};
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<Op>), dim3(ca.ga), dim3(TPB), 0, s, op, g, m,
-                     ca);
-  return hipGetLastError();
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *z,
+                            const T *p_old, T *p_new, T *q, const CgArgs &ca) {
+  if (split == 1) {
+    using Op = OpTangent<T, true, true, 1>;
+    Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), ulin};
+    return launch_cg_apply(s, op, g, m, ca);
+  }
+  using Op = OpTangent<T, true, true, 0>;
+  Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), nullptr};
+  return launch_cg_apply(s, op, g, m, ca);
 }
 
 template <class T>
@@ -1145,16 +1402,18 @@ hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const Ph
                           const T *p_old, T *p_new, T *q, const CgArgs &ca) {
   using Op = OpPhase<T, true, true>;
   Op op{g, c, coef, eact, nflag, z, p_old, p_new, q, T(0)};
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<Op>), dim3(ca.ga), dim3(TPB), 0, s, op, g, m,
-                     ca);
-  return hipGetLastError();
+  return launch_cg_apply(s, op, g, m, ca);
 }
 
 template <class T>
 hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                        const T *d, const uint8_t *qflag, const uint8_t *eact,
-                        const uint8_t *nflag, T *Dinv) {
-  OpTangentDiag<T> op{g, c, d, qflag, eact, nflag, Dinv};
+                        int split, const T *ulin, const T *d, const uint8_t *qflag,
+                        const uint8_t *eact, const uint8_t *nflag, T *Dinv) {
+  if (split == 1) {
+    OpTangentDiag<T, 1> op{g, c, d, qflag, eact, nflag, Dinv, ulin};
+    return launch_march(s, op, g, m, nullptr);
+  }
+  OpTangentDiag<T, 0> op{g, c, d, qflag, eact, nflag, Dinv, nullptr};
   return launch_march(s, op, g, m, nullptr);
 }
 
@@ -1166,9 +1425,16 @@ hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseC
 }
 
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                               const double *d, const uint8_t *qflag, const uint8_t *eact,
-                               const double *p, double *q) {
-  OpTangent<double, false, false> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q, 0.0};
+                               int split, const double *ulin, const double *d,
+                               const uint8_t *qflag, const uint8_t *eact, const double *p,
+                               double *q) {
+  if (split == 1) {
+    OpTangent<double, false, false, 1> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q,
+                                          0.0, ulin};
+    return launch_march(s, op, g, m, nullptr);
+  }
+  OpTangent<double, false, false, 0> op{g, c, d, qflag, eact, nullptr, p, nullptr, nullptr, q,
+                                        0.0, nullptr};
   return launch_march(s, op, g, m, nullptr);
 }
 
@@ -1180,10 +1446,14 @@ hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const
 }
 
 hipError_t internal_force(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                          const double *u, const double *d, const uint8_t *eact,
+                          int split, const double *u, const double *d, const uint8_t *eact,
                           const uint8_t *nflag, bool neg, double *R, RedScratch rs) {
-  OpForce op{g, c, u, d, eact, nflag, R, neg ? -1.0 : 1.0};
-  return launch_march_reduce<OpForce, 1>(s, op, g, m, rs, SC_NORM_A);
+  if (split == 1) {
+    OpForce<1> op{g, c, u, d, eact, nflag, R, neg ? -1.0 : 1.0};
+    return launch_march_reduce<OpForce<1>, 1>(s, op, g, m, rs, SC_NORM_A);
+  }
+  OpForce<0> op{g, c, u, d, eact, nflag, R, neg ? -1.0 : 1.0};
+  return launch_march_reduce<OpForce<0>, 1>(s, op, g, m, rs, SC_NORM_A);
 }
 
 hipError_t phase_residual(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
@@ -1289,16 +1559,16 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
   template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
                                    const T *, const CgArgs &);                                 \
   template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
-                                          const ElasCoef &, const T *, const uint8_t *,        \
-                                          const uint8_t *, const uint8_t *, const T *,         \
-                                          const T *, T *, T *, const CgArgs &);                \
+                                          const ElasCoef &, int, const T *, const T *,         \
+                                          const uint8_t *, const uint8_t *, const uint8_t *,   \
+                                          const T *, const T *, T *, T *, const CgArgs &);     \
   template hipError_t phase_cg_apply<T>(hipStream_t, const Grid &, const March &,              \
                                         const PhaseCoef &, const T *, const uint8_t *,         \
                                         const uint8_t *, const T *, const T *, T *, T *,       \
                                         const CgArgs &);                                       \
   template hipError_t tangent_diag<T>(hipStream_t, const Grid &, const March &,                \
-                                      const ElasCoef &, const T *, const uint8_t *,            \
-                                      const uint8_t *, const uint8_t *, T *);                  \
+                                      const ElasCoef &, int, const T *, const T *,             \
+                                      const uint8_t *, const uint8_t *, const uint8_t *, T *); \
   template hipError_t phase_diag<T>(hipStream_t, const Grid &, const March &,                  \
                                     const PhaseCoef &, const T *, const uint8_t *,             \
                                     const uint8_t *, T *);                                     \

@@ -38,6 +38,7 @@ struct CgBuf {
   T *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr,
     *Dinv = nullptr;
   T *d = nullptr;      // d in this precision (operator data of the tangent)
+  T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
   T *coef = nullptr;   // [4E] phase coefficient
 };
 
@@ -75,6 +76,16 @@ struct pf_ctx {
   double *scal_h = nullptr;
   unsigned long long *icount_h = nullptr;
   std::vector<void *> allocs;
+
+  // captured CG batches (hipGraph), keyed by solve kind and precision
+  struct GraphEntry {
+    int kind, fp32, niter;
+    double tol;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool use_graphs = true;
 
   // sampled kernel timing
   bool profiling = false;
@@ -226,6 +237,7 @@ pf_status upload_constraints(pf_ctx *c) {
 // ------------------------------------------------------------------ PCG
 
 enum Kind { K_ELASTIC = 0, K_PHASE = 1 };
+constexpr int kTimedRepeat = 4;
 
 template <class T>
 CgBuf<T> &buf(pf_ctx *c);
@@ -234,35 +246,88 @@ CgBuf<double> &buf<double>(pf_ctx *c) { return c->bd; }
 template <>
 CgBuf<float> &buf<float>(pf_ctx *c) { return c->bf; }
 
+// Enqueue `iters` CG iterations (apply + update pairs) starting from the
+// direction buffer p0 (iters is even, so the buffers end where they began).
+template <class T>
+pf_status enqueue_iters(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n, int iters,
+                        bool time_first) {
+  CgBuf<T> &b = buf<T>(c);
+  T *pold = b.p0, *pnew = b.p1;
+  for (int k = 0; k < iters; ++k) {
+    // Timed sample: the apply kernel is idempotent (it rewrites p_new, q and
+    // its partials from inputs it does not modify), so it is launched
+    // kTimedRepeat times back to back between one event pair and the
+    // per-launch time is the elapsed time divided by kTimedRepeat.
+    const bool t = time_first && k == 0;
+    if (t) PF_HIP(c, hipEventRecord(c->ev[0], st));
+    for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
+      if (kind == K_ELASTIC) {
+        PF_HIP(c, tangent_cg_apply<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                      c->tflag, c->eact, c->nflag, b.z, pold, pnew, b.q, ca));
+      } else {
+        PF_HIP(c, phase_cg_apply<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.z,
+                                    pold, pnew, b.q, ca));
+      }
+    }
+    if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
+    PF_HIP(c, cg_update<T>(st, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, ca));
+    if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
+    std::swap(pold, pnew);
+  }
+  return PF_OK;
+}
+
+// Graph of `niter` CG iterations for this solve kind, captured on a private
+// stream the first time it is needed and launched on the context's stream.
+template <class T>
+pf_status cg_graph(pf_ctx *c, Kind kind, const CgArgs &ca, int n, double tol, int niter,
+                   hipGraphExec_t *out) {
+  const int fp32 = std::is_same<T, float>::value ? 1 : 0;
+  for (auto &e : c->graphs)
+    if (e.kind == kind && e.fp32 == fp32 && e.niter == niter && e.tol == tol) {
+      *out = e.exec;
+      return PF_OK;
+    }
+  if (!c->cap_stream) PF_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  PF_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  pf_status s = enqueue_iters<T>(c, c->cap_stream, kind, ca, n, niter, false);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (s != PF_OK) return s;
+  if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  c->graphs.push_back({kind, fp32, niter, tol, ex});
+  *out = ex;
+  return PF_OK;
+}
+
 // Solve A x = r0 (r0 already in b.r, zero on fixed DOFs) from x = 0 with
 // Jacobi PCG to ||r|| <= tol ||r0||.  b.Dinv must hold the inverse diagonal.
+// Batches of cg_check iterations are enqueued (as a captured graph) between
+// polls of the device-side status word; iterations after convergence exit
+// at once.
 template <class T>
 pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
   CgBuf<T> &b = buf<T>(c);
   const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
   const CgArgs ca = cg_args(c->g, c->ms, n, c->cgs, c->rs, tol, c->opts.max_cg);
   PF_HIP(c, cg_init<T>(c->stream, n, b.x, b.r, b.z, b.p0, b.Dinv, ca));
-  T *pold = b.p0, *pnew = b.p1;
-  const int batch = std::max(1, c->opts.cg_check);
+  int batch = std::max(4, c->opts.cg_check);
+  batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
+  const bool timed = c->profiling;
+  hipGraphExec_t ex = nullptr;
+  const int ngraph = timed ? batch - 2 : batch;
+  if (c->use_graphs) PF_TRY(cg_graph<T>(c, kind, ca, n, tol, ngraph, &ex));
   for (;;) {
-    // the first iteration of a batch is the timed sample (it always runs:
-    // the status word was polled as "running" just before)
-    const bool timed = c->profiling;
-    for (int k = 0; k < batch; ++k) {
-      const bool t = timed && k == 0;
-      if (t) PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
-      if (kind == K_ELASTIC) {
-        PF_HIP(c, tangent_cg_apply<T>(c->stream, c->g, c->ms, c->ec, b.d, c->tflag, c->eact,
-                                      c->nflag, b.z, pold, pnew, b.q, ca));
-      } else {
-        PF_HIP(c, phase_cg_apply<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
-                                    b.z, pold, pnew, b.q, ca));
-      }
-      if (t) PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
-      PF_HIP(c, cg_update<T>(c->stream, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, ca));
-      if (t) PF_HIP(c, hipEventRecord(c->ev[2], c->stream));
-      std::swap(pold, pnew);
+    if (timed) PF_TRY(enqueue_iters<T>(c, c->stream, kind, ca, n, 2, true));
+    if (ex) {
+      PF_HIP(c, hipGraphLaunch(ex, c->stream));
+    } else {
+      PF_TRY(enqueue_iters<T>(c, c->stream, kind, ca, n, ngraph, false));
     }
     PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
     PF_TRY(sync(c));
@@ -270,7 +335,7 @@ pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
       float a = 0.f, u = 0.f;
       PF_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
       PF_HIP(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
-      c->prof_launches[kid] += 1;
+      c->prof_launches[kid] += kTimedRepeat;
       c->prof_ms[kid] += a;
       c->prof_launches[2] += 1;
       c->prof_ms[2] += u;
@@ -285,8 +350,8 @@ pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
 // ------------------------------------------------------- displacement
 
 pf_status residual_u(pf_ctx *c, const double *u, double *R, double *norm) {
-  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, u, c->d, c->eact, c->nflag, true, R,
-                           c->rs));
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, c->mt.split, u, c->d, c->eact,
+                           c->nflag, true, R, c->rs));
   PF_TRY(read_scal(c));
   *norm = std::sqrt(c->scal_h[SC_NORM_A]);
   if (!is_finite(*norm)) return fail(c, PF_E_NONFINITE, "displacement residual is not finite");
@@ -313,12 +378,17 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
     if (mixed) {
       PF_HIP(c, convert<float, double>(c->stream, c->g.N, c->bf.d, c->d));
       PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.r, c->Ru));
+      if (c->mt.split == 1) PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.ulin, c->u));
     } else {
       PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
                                c->stream));
     }
-    PF_HIP(c, tangent_diag<T>(c->stream, c->g, c->ms, c->ec, b.d, c->tflag, c->eact, c->nflag,
-                              b.Dinv));
+    if (!mixed && c->mt.split == 1)   // the Newton point, in a buffer whose address captured
+                                     // graphs can keep (u is swapped by the line search)
+      PF_HIP(c, hipMemcpyAsync(c->bd.ulin, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    PF_HIP(c, tangent_diag<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                              c->eact, c->nflag, b.Dinv));
     int iters = 0, status = 0;
     PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status));
     st->n_cg_u += iters;
@@ -458,8 +528,8 @@ pf_status reaction(pf_ctx *c, int group, double f[2]) {
     f[0] = f[1] = 0.0;
     return PF_OK;
   }
-  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, c->u, c->d, c->eact, nullptr, false,
-                           c->Rfull, c->rs));
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, c->mt.split, c->u, c->d, c->eact,
+                           nullptr, false, c->Rfull, c->rs));
   PF_HIP(c, group_sum(c->stream, gr.n, gr.d_dof, gr.d_comp, c->Rfull, c->rs));
   PF_TRY(read_scal(c));
   f[0] = c->scal_h[SC_SUM_X];
@@ -602,7 +672,6 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   if (opts) o = *opts; else pf_default_opts(&o);
   std::string msg;
   if (check_opts(&o, &msg) != PF_OK) return PF_E_INVALID_ARG;
-  if (mat->split != PF_SPLIT_VD) return PF_E_INVALID_ARG;   // spectral: not built yet
 
   pf_ctx *c = new pf_ctx();
   c->opts = o;
@@ -635,10 +704,12 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   A(&c->nflag, g.N); A(&c->qflag, g.E); A(&c->tflag, g.E);
   A(&c->bd.x, n2); A(&c->bd.r, n2); A(&c->bd.z, n2); A(&c->bd.p0, n2); A(&c->bd.p1, n2);
   A(&c->bd.q, n2); A(&c->bd.Dinv, n2); A(&c->bd.coef, E4);
+  if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bd.ulin, n2);
   c->bd.d = c->d;
   if (o.precision == PF_MIXED) {
     A(&c->bf.x, n2); A(&c->bf.r, n2); A(&c->bf.z, n2); A(&c->bf.p0, n2); A(&c->bf.p1, n2);
     A(&c->bf.q, n2); A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
+    if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
   A(&c->cgs, 1);
   A(&c->rs.partA, (size_t)kPMax);
@@ -678,6 +749,8 @@ pf_status pf_destroy(pf_ctx *c) {
   }
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->cgs_h) (void)hipHostFree(c->cgs_h);
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
@@ -822,7 +895,8 @@ pf_status pf_kernel_time(pf_ctx *c, int32_t kernel, int64_t *launches, double *t
 
 pf_status pf_op_internal_force(pf_ctx *c, const double *u, const double *d, double *R) {
   if (!c || !u || !d || !R) return PF_E_INVALID_ARG;
-  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, u, d, c->eact, nullptr, false, R, c->rs));
+  PF_HIP(c, internal_force(c->stream, c->g, c->ms, c->ec, c->mt.split, u, d, c->eact, nullptr,
+                           false, R, c->rs));
   return PF_OK;
 }
 
@@ -830,7 +904,8 @@ pf_status pf_op_tangent_apply(pf_ctx *c, const double *u, const double *d, const
                               double *q) {
   if (!c || !u || !d || !p || !q) return PF_E_INVALID_ARG;
   PF_HIP(c, tangent_flags(c->stream, c->g, u, c->eact, c->tflag));
-  PF_HIP(c, tangent_apply_plain(c->stream, c->g, c->ms, c->ec, d, c->tflag, c->eact, p, q));
+  PF_HIP(c, tangent_apply_plain(c->stream, c->g, c->ms, c->ec, c->mt.split, u, d, c->tflag,
+                                c->eact, p, q));
   return PF_OK;
 }
 

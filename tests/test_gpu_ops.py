@@ -29,8 +29,8 @@ def to_inter(u_soa, N):
     return u
 
 
-def make(pf, nx, ny, masked=False, scheme=0):
-    p = W.tension_panel(n=4, l=0.05)
+def make(pf, nx, ny, masked=False, scheme=0, split=0):
+    p = W.tension_panel(n=4, l=0.05, split=split)
     p.nx, p.ny, p.lx, p.ly = nx, ny, 1.3, 0.7
     p.dir_u = [W.DirichletU(np.array([0], np.int64), np.array([0], np.int8), np.zeros(1)),
                W.DirichletU(np.array([1], np.int64), np.array([1], np.int8), np.zeros(1))]
@@ -58,11 +58,12 @@ def host(t):
     return t.cpu().numpy()
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 @pytest.mark.parametrize("masked", [False, True])
-def test_internal_force_and_tangent(gpu_lib, nx, ny, masked):
+def test_internal_force_and_tangent(gpu_lib, nx, ny, masked, split):
     import torch
-    p, ctx, orc = make(gpu_lib, nx, ny, masked)
+    p, ctx, orc = make(gpu_lib, nx, ny, masked, split=split)
     N = p.n_nodes
     rng = np.random.default_rng(nx * 100 + ny)
     u = rng.normal(size=2 * N) * 1e-3
@@ -104,11 +105,12 @@ def test_phase_apply(gpu_lib, nx, ny, masked):
     ctx.close()
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("scheme", [0, 1, 2, 3])
-def test_qp_update_and_predictor(gpu_lib, scheme):
+def test_qp_update_and_predictor(gpu_lib, scheme, split):
     import torch
     nx, ny = 41, 19
-    p, ctx, orc = make(gpu_lib, nx, ny, masked=False, scheme=scheme)
+    p, ctx, orc = make(gpu_lib, nx, ny, masked=False, scheme=scheme, split=split)
     N, E = p.n_nodes, p.n_elems
     rng = np.random.default_rng(100 + scheme)
     u = rng.normal(size=2 * N) * 2e-3
@@ -131,8 +133,12 @@ def test_qp_update_and_predictor(gpu_lib, scheme):
     PS = torch.zeros_like(H)
     fl = torch.zeros(E, dtype=torch.uint8, device="cuda")
     ng = ctx.op_qp_update(scheme, uG, dG, HpG, H, PS, fl)
-    np.testing.assert_allclose(host(H).reshape(4, E).T, H_orc, rtol=1e-13, atol=0)
-    np.testing.assert_allclose(host(PS).reshape(4, E).T, psi_s, rtol=1e-12,
+    # spectral: the smaller eigenvalue t/2 - r cancels when |e2| << |e1|, so
+    # the two sides' strain roundings (edge differences vs. B matrices) show
+    # up at ~1e-12 relative in psi
+    rt = 1e-13 if split == 0 else 1e-11
+    np.testing.assert_allclose(host(H).reshape(4, E).T, H_orc, rtol=rt, atol=0)
+    np.testing.assert_allclose(host(PS).reshape(4, E).T, psi_s, rtol=max(rt, 1e-12),
                                atol=1e-14 * max(psi_s.max(), 1))
     flags = host(fl)
     bits_t = np.stack([(flags >> q) & 1 for q in range(4)], axis=1).astype(bool)

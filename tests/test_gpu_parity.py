@@ -90,6 +90,28 @@ def test_small_panel_history_mixed(gpu_lib, scheme):
     compare_history(gpu_lib, p, scheme, 1, 8, 1e-6)
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_shear_spectral_history_fp64(gpu_lib, scheme):
+    """Shear panel with the spectral split: cracks under mixed-sign
+    principal strains; S* predictors active from step 5."""
+    p = W.shear_panel(n=16, l=0.1, du=2e-3, steps=8)
+    compare_history(gpu_lib, p, scheme, 0, 8, 1e-7)
+
+
+@pytest.mark.parametrize("scheme", [1, 3])
+def test_shear_spectral_history_mixed(gpu_lib, scheme):
+    p = W.shear_panel(n=16, l=0.1, du=2e-3, steps=8)
+    compare_history(gpu_lib, p, scheme, 1, 8, 1e-6)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_lshape_masked_history_fp64(gpu_lib, scheme):
+    """L-shaped panel on a 32^2 grid with the upper-right quadrant masked
+    out, the load patch and the d = 0 zone; steps 1-3 include nucleation."""
+    p = W.lshape_panel(n=32, steps=10, total=0.3)
+    compare_history(gpu_lib, p, scheme, 0, 3, 1e-7)
+
+
 def test_ragged_panel_history_fp64(gpu_lib):
     """Non-square ragged mesh spanning several wave strips and chunks."""
     p = W.tension_panel(n=16, l=0.08, du=1e-3, steps=5)
