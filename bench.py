@@ -45,6 +45,22 @@ def fused_apply_bytes_per_node(prec):
     return (2 + 2 + 1 + 2 + 2) * w + 1 + 1
 
 
+def measured_traffic():
+    """Per-launch HBM bytes of the dominant kernel from the committed counter
+    runs (profiles/hbm_traffic_tension512.json), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_tension512.json")
+    src = os.path.join(ROOT, "paper_2209_07969_amd", "csrc", "pf_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False):
     import torch
     ctx = pf.Context(problem, scheme=scheme, precision=precision)
@@ -118,6 +134,10 @@ def main():
     ap.add_argument("--workload", default="tension512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-st", action="store_true", help="skip the ST FP64 comparison run")
+    ap.add_argument("--full-history", action="store_true",
+                    help="time the whole load history (warmup 0, all steps) for both schemes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -131,6 +151,17 @@ def main():
 
     pf.require_device()
     problem = {"tension512": W.config_tension512, "tension64": W.config_tension64}[args.workload]()
+    if args.full_history:
+        args.warmup, args.steps = 0, len(problem.loads)
+    if args.copy_calibration:
+        # plain elementwise kernels of known size for counter scaling: a fill
+        # (256 MiB written) and a scale-copy (256 MiB read + 256 MiB written)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.warmup + args.steps > len(problem.loads):
         raise SystemExit("warmup + steps exceeds the load history")
 
@@ -196,7 +227,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_us": avg_ms * 1e3,
             "sampled_launches": launches,
             "bytes_per_launch": alg_bytes,

@@ -94,6 +94,9 @@ typedef struct {
   double psi_crit;      /* softening threshold; < 0 means Gc/(c_w l)          */
   double d_gate;        /* gate: predictor only where d < d_gate (0.95)       */
   double trial_floor;   /* theta: trial mass coefficient >= theta*(Gc/l+2H)   */
+  int32_t march_rows;   /* node rows per work item of the operator kernels:   */
+                        /* 2, 4 or 8; 0 = chosen from the mesh size           */
+  int32_t reserved;
 } pf_solver_opts;
 
 typedef struct {
@@ -116,7 +119,8 @@ typedef struct {
 
 /* Fill *opts with defaults: ST, FP64, Jacobi, tol_stag 1e-5, tol_pcg 1e-10,
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
- * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1. */
+ * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
+ * march_rows 0. */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

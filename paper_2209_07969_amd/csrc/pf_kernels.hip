@@ -472,6 +472,19 @@ __device__ inline void item_compute(const Op &op, const Grid &g, const March &ms
   }
 }
 
+// XCD-aware block order: workgroups are dispatched to the 8 dies round
+// robin, so block b runs on die b % 8.  Renumbering the blocks so that each
+// die owns a contiguous range makes the work items of one die a horizontal
+// band of the mesh, and the node rows shared by vertically adjacent chunks
+// are then re-read from that die's own L2.  The map is a bijection of
+// [0, nb).
+constexpr int kXcd = 8;
+__device__ inline int xcd_block(int b, int nb) {
+  const int x = b % kXcd, k = b / kXcd;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  return x * per + min(x, rem) + k;
+}
+
 template <int CH, class Op>
 __device__ inline void march_items(const Op &op, const Grid &g, const March &ms, int wfirst,
                                    double *red) {
@@ -491,7 +504,7 @@ __global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms, double *
   double red[NRR];
 #pragma unroll
   for (int k = 0; k < NRR; ++k) red[k] = 0.0;
-  march_items<CH>(op, g, ms, blockIdx.x * WPB + (threadIdx.x >> 6), red);
+  march_items<CH>(op, g, ms, xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6), red);
   if (Op::NR > 0) block_partial<NRR>(red, part);
 }
 
@@ -969,7 +982,7 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
 template <int CH, class Op>
 __global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
   const int lane = threadIdx.x & 63;
-  const int w0 = blockIdx.x * WPB + (threadIdx.x >> 6);
+  const int w0 = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
   const int nw = ms.nstrips * ms.nchunks;
   // issue the first work item's loads before the prologue's reduction
   Item<CH, Op> it;

@@ -613,6 +613,10 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   }
   if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) { *msg = "iteration limits"; return PF_E_INVALID_ARG; }
   if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
+  if (o->march_rows != 0 && o->march_rows != 2 && o->march_rows != 4 && o->march_rows != 8) {
+    *msg = "march_rows must be 0, 2, 4 or 8";
+    return PF_E_INVALID_ARG;
+  }
   return PF_OK;
 }
 
@@ -690,7 +694,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
                    g.hy / 4.0, g.hx / 4.0};
   c->pc = PhaseCoef{mt.Gc * mt.l, mt.Gc / mt.l, g.hx * g.hy / 4.0, 1.0 / g.hx, 1.0 / g.hy,
                     g.hy / 4.0, g.hx / 4.0};
-  c->ms = march_shape(g, 0);
+  c->ms = march_shape(g, o.march_rows);
 
   pf_status s = PF_OK;
   auto A = [&](auto **p, size_t n) {
