@@ -37,12 +37,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fused_apply_bytes_per_node(prec):
-    """Algorithmic bytes per node of the fused elasticity CG apply:
-    read z (2 comps), p_old (2), d (1), node flag (1 B), element flag (1 B per
-    element ~ node); write p_new (2), q (2)."""
+def cg_iteration_bytes_per_node(prec):
+    """Algorithmic bytes per node of one single-kernel CG iteration on the
+    elasticity tangent (2 components per node): read r, w, s, D^-1, p, x
+    (6 vectors x 2 comps) and d (1), the node flag (1 B) and the element
+    flag (1 B per element ~ node); write r, w, s, p, x (5 vectors x 2)."""
     w = 4 if prec == "mixed" else 8
-    return (2 + 2 + 1 + 2 + 2) * w + 1 + 1
+    return (6 * 2 + 1 + 5 * 2) * w + 1 + 1
 
 
 def measured_traffic():
@@ -173,7 +174,7 @@ def main():
     ms_per_step = secs * 1e3 / args.steps
     launches, kms, nodes = ctx.kernel_time(0)
     avg_ms = kms / max(launches, 1)
-    bpn = fused_apply_bytes_per_node("mixed")
+    bpn = cg_iteration_bytes_per_node("mixed")
     alg_bytes = bpn * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     ctx.close()
@@ -221,7 +222,7 @@ def main():
         "st_fp64": st_res,
         "speedup_s1_mixed_vs_st_fp64": (st_res["ms_per_step"] / ms_per_step) if st_res else None,
         "roofline": {
-            "kernel": "k_tangent_cg<float> (fused CG direction update + elasticity tangent apply)",
+            "kernel": "k_cg1<4, OpTangent<float>> (one CG iteration: recurrences + tangent apply)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

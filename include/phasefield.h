@@ -182,12 +182,12 @@ pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
 
 /* Kernel timing for measurement.  When enabled, the CG drivers time a sample
  * of the CG kernel launches with HIP events on the context's stream: per
- * enqueued batch, the first iteration's operator apply is launched four
- * times back to back (it is idempotent) between one event pair, and its
- * vector update once.  Launch counts and elapsed times accumulate.
- * kernel: 0 = elasticity tangent apply (fused CG direction update),
- * 1 = phase operator apply (fused), 2 = CG vector update.  Enabling resets
- * the counters. */
+ * enqueued batch, the first iteration's kernel (one whole CG iteration; it
+ * only reads the previous parity's buffers, so repeating it is idempotent)
+ * is launched four times back to back between one event pair.  Launch
+ * counts and elapsed times accumulate.  kernel: 0 = elasticity CG
+ * iteration, 1 = phase CG iteration, 2 = reserved (always 0).  Enabling
+ * resets the counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,
                          int64_t *nodes_per_launch);

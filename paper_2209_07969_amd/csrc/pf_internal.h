@@ -21,33 +21,6 @@ struct Mat {
   int split;      // 0 = volumetric-deviatoric, 1 = spectral
 };
 
-// Per-solve CG state in device memory.  The CG loop has no communication
-// between blocks of one kernel: each kernel writes block partials with plain
-// stores, and every block of the next kernel reduces them in a fixed order in
-// its prologue, so all blocks hold bit-identical scalars.  Block 0 records
-// the scalars for later kernels in the half of this struct the current
-// kernel does not read (A = written by the operator apply, B = written by the
-// vector update / init), each half on its own 128-byte line.
-struct alignas(128) CgHalfA {
-  double rz;      // r.z entering this iteration
-  double rr;      // r.r entering this iteration
-  double rr0;     // r.r of the initial residual
-  int done;       // 0 running, 1 converged, 2 breakdown/non-finite, 3 maxit
-  int iters;      // completed iterations
-};
-struct alignas(128) CgHalfB {
-  double rz_prev; // r.z of the previous iteration (for beta)
-  double rr0;
-  int done;
-  int iters;
-  int first;      // 1 before the first direction
-  int pad;
-};
-struct CgState {
-  CgHalfA a;
-  CgHalfB b;
-};
-
 // Node flag bits
 constexpr uint8_t NF_UX = 1;   // u_x fixed (Dirichlet or inactive node)
 constexpr uint8_t NF_UY = 2;   // u_y fixed
@@ -64,8 +37,6 @@ struct March {
 // blocks and write one partial per block and value.
 constexpr int kPMax = 512;
 struct RedScratch {
-  double *partA;               // [kPMax]      operator-apply partials (p.q)
-  double *partB;               // [2 * kPMax]  vector-update partials (r.z, r.r)
   double *partR;               // [2 * kPMax]  residual-norm partials
   unsigned long long *icount;  // [kICounters] integer counters (atomic adds)
   double *scal;                // [kScal]      finalised scalars
@@ -82,15 +53,37 @@ enum ScalSlot {
 };
 enum ICounter { IC_GATED = 0, IC_FLOOR = 1 };
 
-// Launch geometry of one CG solve: grid sizes of the apply (ga) and of the
-// vector kernels (gb); each kernel's prologue reduces the other's partials.
-struct CgArgs {
-  CgState *st;
-  double *partA;
-  double *partB;
-  int ga, gb;
+// Single-kernel CG (Chronopoulos-Gear recurrences): one kernel per iteration.
+// Kernel K_i reduces the partials of K_{i-1} (gamma = r.u, delta = w.u,
+// r.r) in its prologue, applies the pending recurrences of iteration i-1 to
+// the vectors it reads and computes w_i = A u_i.  Vectors read at halo nodes
+// and everything the kernel writes are double-buffered by iteration parity,
+// so the kernel only reads parity i-1 and writes parity i: it is idempotent.
+struct alignas(128) Cg1State {
+  double alpha_prev;   // alpha of the update applied by this kernel
+  double gamma_prev;   // gamma of that update
+  double rr0;          // r.r of the initial residual
+  double rr;           // r.r entering this kernel
+  int done;            // 0 running, 1 converged, 2 breakdown/non-finite, 3 maxit
+  int iters;           // completed updates of x
+  int first;           // 1 after the initial kernel
+  int pad;
+};
+
+template <class T>
+struct CgVecs {
+  T *R[2], *W[2], *S[2], *X[2], *P[2];
+  const T *Dinv;
+};
+
+struct Cg1Args {
+  Cg1State *st;        // [2] by parity
+  double *part;        // [2][3][kPMax] by parity
+  int np;              // number of blocks (partials) of every CG kernel
   double tol2;
   int maxit;
+  int parity;          // i & 1
+  int init;            // 1 for K_0
 };
 
 // Operator coefficients passed by value.
@@ -113,25 +106,18 @@ March march_shape(const Grid &g, int ch_override);
 
 // CG (T = double or float).  p_old/p_new are the two direction buffers; the
 // apply computes p_new = z + beta p_old on the fly and q = A p_new.
-CgArgs cg_args(const Grid &g, const March &m, int n, CgState *st, RedScratch rs, double tol,
-               int maxit);
+// Single-kernel CG iteration for the elasticity tangent / the phase operator.
 template <class T>
-hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
-                   const CgArgs &ca);
+hipError_t tangent_cg1(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                       int split, const T *ulin, const T *d, const uint8_t *qflag,
+                       const uint8_t *eact, const uint8_t *nflag, const CgVecs<T> &v,
+                       const Cg1Args &a);
 template <class T>
-hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, const CgArgs &ca);
-// split = 1 (spectral): the tangent is re-derived per QP from the
-// linearisation point ulin [2N] instead of the indicator bits.
-template <class T>
-hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                            int split, const T *ulin, const T *d, const uint8_t *qflag,
-                            const uint8_t *eact, const uint8_t *nflag, const T *z,
-                            const T *p_old, T *p_new, T *q, const CgArgs &ca);
-template <class T>
-hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
-                          const T *coef, const uint8_t *eact, const uint8_t *nflag,
-                          const T *z, const T *p_old, T *p_new, T *q, const CgArgs &ca);
+hipError_t phase_cg1(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                     const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                     const CgVecs<T> &v, const Cg1Args &a);
+int cg1_blocks(const March &m);
+
 template <class T>
 hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                         int split, const T *ulin, const T *d, const uint8_t *qflag,

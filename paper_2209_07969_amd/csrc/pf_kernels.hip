@@ -561,6 +561,31 @@ struct OpTangent {
       n.py += beta * n.oy;
     }
   }
+  // operator data only (no CG vectors): d and, for the spectral split, the
+  // linearisation point
+  __device__ Node load_aux(int i, int j) const {
+    Node n{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      n.d = d[k];
+      if (SPL == 1) {
+        n.lx = ulin[k];
+        n.ly = ulin[k + g.N];
+      }
+    }
+    return n;
+  }
+  __device__ void set_u(Node &n, const T (&u)[2]) const {
+    n.px = u[0];
+    n.py = u[1];
+  }
+  __device__ void get_u(const Node &n, T (&u)[2]) const {
+    u[0] = n.px;
+    u[1] = n.py;
+  }
+  __device__ bool masked(int k, int q) const {
+    return (nflag[k] & (q == 0 ? NF_UX : NF_UY)) != 0;
+  }
   __device__ Elem eload(int ie, int je) const {
     Elem e{0, 0};
     if (elem_exists(g, ie, je, eact)) {
@@ -635,6 +660,10 @@ struct OpPhase {
   __device__ void fin(Node &n) const {
     if (FUSED) n.p += beta * n.o;
   }
+  __device__ Node load_aux(int, int) const { return Node{T(0), T(0)}; }
+  __device__ void set_u(Node &n, const T (&u)[1]) const { n.p = u[0]; }
+  __device__ void get_u(const Node &n, T (&u)[1]) const { u[0] = n.p; }
+  __device__ bool masked(int k, int) const { return (nflag[k] & NF_D) != 0; }
   __device__ Elem eload(int ie, int je) const {
     Elem e{};
     if (elem_exists(g, ie, je, eact)) {
@@ -922,136 +951,257 @@ hipError_t launch_march_reduce(hipStream_t s, const Op &op, const Grid &g, const
   return hipGetLastError();
 }
 
-// --------------------------------------------------------- CG kernels
+// --------------------------------------------------- single-kernel CG
 //
-// Iteration k = apply kernel A_k then vector kernel B_k.
-//   A_k: reduce B_{k-1}'s partials -> rz_k, rr_k; decide done; beta =
-//        rz_k / rz_{k-1}; p = z + beta p_old; q = A p; partials p.q.
-//   B_k: reduce A_k's partials -> pq; alpha = rz_k / pq; x += alpha p;
-//        r -= alpha q; z = D^-1 r; partials r.z, r.r.
-// Block 0 of each kernel records its scalars in its own half of CgState.
+// Chronopoulos-Gear CG with one reduction and one kernel per iteration.
+// Iteration i (kernel K_i, i >= 1) with alpha = alpha_{i-1}, beta = beta_{i-1}
+// from the prologue:
+//   s_{i-1} = w_{i-1} + beta s_{i-2}         (every node of the work item)
+//   r_i     = r_{i-1} - alpha s_{i-1}
+//   u_i     = D^-1 r_i
+//   p_{i-1} = u_{i-1} + beta p_{i-2},  x_i = x_{i-1} + alpha p_{i-1}   (owned)
+//   w_i     = A u_i;  partials gamma_i = r_i.u_i, delta_i = w_i.u_i, r_i.r_i
+// with beta_{i-1} = gamma_{i-1}/gamma_{i-2} and
+// alpha_{i-1} = gamma_{i-1} / (delta_{i-1} - beta_{i-1} gamma_{i-1}/alpha_{i-2}).
+// K_0 forms u_0 = D^-1 r_0, w_0 = A u_0 and zeroes x_0, p_{-1}, s_{-1}.
+// The halo rows of a work item recompute s, r, u from the parity-(i-1)
+// vectors they read, so no block needs another block's output of the same
+// kernel.
 
-template <class T>
-__global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pold,
-                                                 const T *Dinv, CgArgs ca) {
-  double v[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const T ri = r[i];
-    const T zi = Dinv[i] * ri;
-    x[i] = T(0);
-    z[i] = zi;
-    pold[i] = T(0);
-    v[0] += double(ri) * double(zi);
-    v[1] += double(ri) * double(ri);
-  }
-  block_partial<2>(v, ca.partB);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ca.st->b.rz_prev = 0.0;
-    ca.st->b.rr0 = 0.0;
-    ca.st->b.done = 0;
-    ca.st->b.iters = 0;
-    ca.st->b.first = 1;
-  }
-}
-
-// Prologue of the apply kernels: returns done (uniform) and beta.
-__device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
-  double s[2];
-  block_sum<2>(ca.partB, ca.gb, s);
-  const double rz = s[0], rr = s[1];
-  const int first = ca.st->b.first;
-  const int iters = ca.st->b.iters;
-  int done = ca.st->b.done;
-  const double rr0 = first ? rr : ca.st->b.rr0;
+__device__ inline int cg1_prologue(const Cg1Args &a, double *alpha, double *beta) {
+  const int cur = a.parity, prv = cur ^ 1;
+  double s3[3];
+  block_sum<3>(a.part + prv * 3 * kPMax, a.np, s3);
+  const double gam = s3[0], del = s3[1], rr = s3[2];
+  const Cg1State S = a.st[prv];
+  int done = S.done;
+  const double rr0 = S.first ? rr : S.rr0;
+  double al = 0.0, be = 0.0;
   if (!done) {
-    if (!(rr == rr) || !(rz == rz)) done = 2;
-    else if (rr <= ca.tol2 * rr0) done = 1;
-    else if (iters >= ca.maxit) done = 3;
+    if (!(rr == rr) || !(gam == gam) || !(del == del)) done = 2;
+    else if (rr <= a.tol2 * rr0) done = 1;
+    else if (S.iters >= a.maxit) done = 3;
+  }
+  if (!done) {
+    if (S.first) {
+      be = 0.0;
+      const double den = del;
+      if (!(den > 0.0)) done = 2;
+      else al = gam / den;
+    } else {
+      be = gam / S.gamma_prev;
+      const double den = del - be * gam / S.alpha_prev;
+      if (!(den > 0.0)) done = 2;
+      else al = gam / den;
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ca.st->a.rz = rz;
-    ca.st->a.rr = rr;
-    ca.st->a.rr0 = rr0;
-    ca.st->a.done = done;
-    ca.st->a.iters = iters;
+    Cg1State o;
+    o.alpha_prev = al;
+    o.gamma_prev = gam;
+    o.rr0 = rr0;
+    o.rr = rr;
+    o.done = done;
+    o.iters = done ? S.iters : S.iters + 1;
+    o.first = 0;
+    o.pad = 0;
+    a.st[cur] = o;
   }
-  *beta = first ? 0.0 : rz / ca.st->b.rz_prev;
+  *alpha = al;
+  *beta = be;
   return done;
 }
 
 template <int CH, class Op>
-__global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+struct Cg1Item {
+  using T = typename Op::T;
+  static constexpr int NC = Op::NF;
+  T r[CH + 2][NC], w[CH + 2][NC], s[CH + 2][NC], di[CH + 2][NC];
+  T po[CH][NC], xo[CH][NC];
+  typename Op::Node aux[CH + 2];
+  typename Op::Elem El[CH + 1];
+};
+
+template <int CH, class Op>
+__device__ inline void cg1_load(const Op &op, const Grid &g, const March &ms, int w, int lane,
+                                const CgVecs<typename Op::T> &v, const Cg1Args &a,
+                                Cg1Item<CH, Op> &it) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NF;
+  const int cur = a.parity, prv = cur ^ 1;
+  const int strip = w % ms.nstrips, chunk = w / ms.nstrips;
+  const int c = strip * CSTRIP - 1 + lane;
+  const int j0 = chunk * CH;
+  const T *Rin = a.init ? v.R[cur] : v.R[prv];
+#pragma unroll
+  for (int r = 0; r < CH + 2; ++r) {
+    const int j = j0 - 1 + r;
+    it.aux[r] = op.load_aux(c, j);
+    const bool ex = node_exists(g, c, j);
+    const int k = c + j * (g.nx + 1);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      it.r[r][q] = ex ? Rin[k + q * g.N] : T(0);
+      it.di[r][q] = ex ? v.Dinv[k + q * g.N] : T(0);
+      it.w[r][q] = (ex && !a.init) ? v.W[prv][k + q * g.N] : T(0);
+      it.s[r][q] = (ex && !a.init) ? v.S[cur][k + q * g.N] : T(0);
+    }
+  }
+  // owned rows j0 .. j0+CH-1 also need p and x (owned column only)
+  const int n = c - 1;
+  const bool own_col = lane >= 2 && n >= 0 && n <= g.nx;
+#pragma unroll
+  for (int r = 0; r < CH; ++r) {
+    const int j = j0 + r;
+    const bool ok = own_col && j <= g.ny && !a.init;
+    const int k = n + j * (g.nx + 1);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      it.po[r][q] = ok ? v.P[prv][k + q * g.N] : T(0);
+      it.xo[r][q] = ok ? v.X[prv][k + q * g.N] : T(0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < CH + 1; ++r)
+    it.El[r] = (lane > 0) ? op.eload(c - 1, j0 - 1 + r) : typename Op::Elem{};
+}
+
+template <int CH, class Op>
+__device__ inline void cg1_compute(const Op &op, const Grid &g, const March &ms, int w, int lane,
+                                   const CgVecs<typename Op::T> &v, const Cg1Args &a,
+                                   typename Op::T alpha, typename Op::T beta,
+                                   Cg1Item<CH, Op> &it, double (&red)[3]) {
+  using T = typename Op::T;
+  using Node = typename Op::Node;
+  constexpr int NC = Op::NF;
+  const int cur = a.parity, prv = cur ^ 1;
+  const int strip = w % ms.nstrips, chunk = w / ms.nstrips;
+  const int c = strip * CSTRIP - 1 + lane;
+  const int n = c - 1;                          // node column this lane stores
+  const int j0 = chunk * CH;
+  const bool own_col = lane >= 2 && n >= 0 && n <= g.nx;
+  // recurrences at every node of the item (lane holds column c)
+  T u[CH + 2][NC], rn[CH + 2][NC], sn[CH + 2][NC];
+#pragma unroll
+  for (int r = 0; r < CH + 2; ++r) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      if (a.init) {
+        sn[r][q] = T(0);
+        rn[r][q] = it.r[r][q];
+      } else {
+        sn[r][q] = it.w[r][q] + beta * it.s[r][q];
+        rn[r][q] = it.r[r][q] - alpha * sn[r][q];
+      }
+      u[r][q] = it.di[r][q] * rn[r][q];
+    }
+  }
+  // owned updates: the lane storing column n = c - 1 takes the values of the
+  // left neighbour lane (column c - 1) by one shuffle
+#pragma unroll
+  for (int r = 1; r <= CH; ++r) {
+    T rl[NC], sl[NC], ul[NC], rol[NC], dil[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      rl[q] = __shfl_up(rn[r][q], 1, 64);
+      sl[q] = __shfl_up(sn[r][q], 1, 64);
+      ul[q] = __shfl_up(u[r][q], 1, 64);
+      rol[q] = __shfl_up(it.r[r][q], 1, 64);
+      dil[q] = __shfl_up(it.di[r][q], 1, 64);
+    }
+    const int j = j0 - 1 + r;
+    if (own_col && j <= g.ny) {
+      const int k = n + j * (g.nx + 1);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        T pn, xn;
+        if (a.init) {
+          pn = T(0);
+          xn = T(0);
+        } else {
+          pn = dil[q] * rol[q] + beta * it.po[r - 1][q];   // p_{i-1} = u_{i-1} + beta p_{i-2}
+          xn = it.xo[r - 1][q] + alpha * pn;
+        }
+        v.P[cur][k + q * g.N] = pn;
+        v.X[cur][k + q * g.N] = xn;
+        if (!a.init) v.R[cur][k + q * g.N] = rl[q];
+        v.S[prv][k + q * g.N] = sl[q];
+        red[0] += double(rl[q]) * double(ul[q]);
+        red[2] += double(rl[q]) * double(rl[q]);
+      }
+    }
+  }
+  // w = A u over the item's element rows
+  Node nodes[CH + 2];
+#pragma unroll
+  for (int r = 0; r < CH + 2; ++r) {
+    nodes[r] = it.aux[r];
+    op.set_u(nodes[r], u[r]);
+  }
+  Node br = nodes[0];
+  Node bl = Op::shfl_up(br);
+  T c2[NC], c3[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) { c2[q] = T(0); c3[q] = T(0); }
+#pragma unroll
+  for (int r = 0; r < CH + 1; ++r) {
+    const int je = j0 - 1 + r;
+    const Node tr = nodes[r + 1];
+    const Node tl = Op::shfl_up(tr);
+    T f[NC][4];
+    op.element(bl, br, tr, tl, it.El[r], f);
+    T out[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T A = f[q][1] + c2[q];
+      const T Al = __shfl_up(A, 1, 64);
+      out[q] = f[q][0] + c3[q] + Al;
+      c3[q] = f[q][3];
+      c2[q] = f[q][2];
+    }
+    if (r >= 1 && own_col && je <= g.ny) {
+      const int k = n + je * (g.nx + 1);
+      T uo[NC];
+      op.get_u(bl, uo);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const T wv = op.masked(k, q) ? T(0) : out[q];
+        v.W[cur][k + q * g.N] = wv;
+        red[1] += double(wv) * double(uo[q]);
+      }
+    }
+    bl = tl;
+    br = tr;
+  }
+}
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_cg1(Op op, Grid g, March ms,
+                                             CgVecs<typename Op::T> v, Cg1Args a) {
+  using T = typename Op::T;
   const int lane = threadIdx.x & 63;
   const int w0 = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
   const int nw = ms.nstrips * ms.nchunks;
-  // issue the first work item's loads before the prologue's reduction
-  Item<CH, Op> it;
-  if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
-  double beta = 0.0;
-  if (cg_apply_prologue(ca, &beta) != 0) return;
-  op.beta = typename Op::T(beta);
-  double red[1] = {0.0};
-  if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
-  march_items<CH>(op, g, ms, w0 + gridDim.x * WPB, red);
-  block_partial<1>(red, ca.partA);
+  Cg1Item<CH, Op> it;
+  if (w0 < nw) cg1_load<CH>(op, g, ms, w0, lane, v, a, it);
+  double alpha = 0.0, beta = 0.0;
+  if (!a.init) {
+    if (cg1_prologue(a, &alpha, &beta) != 0) return;
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Cg1State o{};
+    o.first = 1;
+    a.st[0] = o;
+  }
+  double red[3] = {0.0, 0.0, 0.0};
+  if (w0 < nw) cg1_compute<CH>(op, g, ms, w0, lane, v, a, T(alpha), T(beta), it, red);
+  for (int w = w0 + gridDim.x * WPB; w < nw; w += gridDim.x * WPB) {
+    Cg1Item<CH, Op> it2;
+    cg1_load<CH>(op, g, ms, w, lane, v, a, it2);
+    cg1_compute<CH>(op, g, ms, w, lane, v, a, T(alpha), T(beta), it2, red);
+  }
+  block_partial<3>(red, a.part + a.parity * 3 * kPMax);
 }
 
-template <class T>
-__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
-                                                   const T *q, const T *Dinv, CgArgs ca) {
-  const int done = ca.st->a.done;
-  const double rz = ca.st->a.rz;
-  const double rr0 = ca.st->a.rr0;
-  const int iters = ca.st->a.iters;
-  if (done != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ca.st->b.done = done;
-      ca.st->b.iters = iters;
-      ca.st->b.rr0 = rr0;
-      ca.st->b.first = 0;
-    }
-    return;
-  }
-  double pqs[1];
-  block_sum<1>(ca.partA, ca.ga, pqs);
-  const double pq = pqs[0];
-  if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ca.st->b.done = 2;
-      ca.st->b.iters = iters;
-      ca.st->b.rr0 = rr0;
-      ca.st->b.first = 0;
-    }
-    return;
-  }
-  const T alpha = T(rz / pq);
-  double v[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const T xi = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    const T zi = Dinv[i] * ri;
-    x[i] = xi;
-    r[i] = ri;
-    z[i] = zi;
-    v[0] += double(ri) * double(zi);
-    v[1] += double(ri) * double(ri);
-  }
-  block_partial<2>(v, ca.partB);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ca.st->b.rz_prev = rz;
-    ca.st->b.rr0 = rr0;
-    ca.st->b.done = 0;
-    ca.st->b.iters = iters + 1;
-    ca.st->b.first = 0;
-  }
-}
-
-int vec_blocks(int n) {
-  int b = (n + 4 * TPB - 1) / (4 * TPB);
-  if (b > kPMax) b = kPMax;
-  if (b < 1) b = 1;
-  return b;
-}
 
 // ------------------------------------------------------ element kernels
 
@@ -1352,70 +1502,48 @@ March march_shape(const Grid &g, int ch_override) {
   return m;
 }
 
-CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, double tol,
-               int maxit) {
-  CgArgs ca;
-  ca.st = st;
-  ca.partA = rs.partA;
-  ca.partB = rs.partB;
-  ca.ga = march_blocks(m);
-  ca.gb = vec_blocks(n);
-  ca.tol2 = tol * tol;
-  ca.maxit = maxit;
-  return ca;
-}
 
-template <class T>
-hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
-                   const CgArgs &ca) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_init<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
-                     p_old, Dinv, ca);
-  return hipGetLastError();
-}
 
-template <class T>
-hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, const CgArgs &ca) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
-                     p, q, Dinv, ca);
-  return hipGetLastError();
-}
+
+
+
+
+int cg1_blocks(const March &m) { return march_blocks(m); }
 
 template <class Op>
-hipError_t launch_cg_apply(hipStream_t s, const Op &op, const Grid &g, const March &m,
-                           const CgArgs &ca) {
-  const dim3 grid(ca.ga), block(TPB);
+hipError_t launch_cg1(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                      const CgVecs<typename Op::T> &v, const Cg1Args &a) {
+  const dim3 grid(a.np), block(TPB);
   switch (m.ch) {
-    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<2, Op>), grid, block, 0, s, op, g, m, ca); break;
-    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<4, Op>), grid, block, 0, s, op, g, m, ca); break;
-    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<8, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg1<2, Op>), grid, block, 0, s, op, g, m, v, a); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg1<4, Op>), grid, block, 0, s, op, g, m, v, a); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg1<8, Op>), grid, block, 0, s, op, g, m, v, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
-                            int split, const T *ulin, const T *d, const uint8_t *qflag,
-                            const uint8_t *eact, const uint8_t *nflag, const T *z,
-                            const T *p_old, T *p_new, T *q, const CgArgs &ca) {
+hipError_t tangent_cg1(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                       int split, const T *ulin, const T *d, const uint8_t *qflag,
+                       const uint8_t *eact, const uint8_t *nflag, const CgVecs<T> &v,
+                       const Cg1Args &a) {
   if (split == 1) {
-    using Op = OpTangent<T, true, true, 1>;
-    Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), ulin};
-    return launch_cg_apply(s, op, g, m, ca);
+    OpTangent<T, false, true, 1> op{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr,
+                                    nullptr, T(0), ulin};
+    return launch_cg1(s, op, g, m, v, a);
   }
-  using Op = OpTangent<T, true, true, 0>;
-  Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), nullptr};
-  return launch_cg_apply(s, op, g, m, ca);
+  OpTangent<T, false, true, 0> op{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr,
+                                  nullptr, T(0), nullptr};
+  return launch_cg1(s, op, g, m, v, a);
 }
 
 template <class T>
-hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
-                          const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
-                          const T *p_old, T *p_new, T *q, const CgArgs &ca) {
-  using Op = OpPhase<T, true, true>;
-  Op op{g, c, coef, eact, nflag, z, p_old, p_new, q, T(0)};
-  return launch_cg_apply(s, op, g, m, ca);
+hipError_t phase_cg1(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                     const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                     const CgVecs<T> &v, const Cg1Args &a) {
+  OpPhase<T, false, true> op{g, c, coef, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0)};
+  return launch_cg1(s, op, g, m, v, a);
 }
 
 template <class T>
@@ -1567,18 +1695,6 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
 
 // -------------------------------------------------- explicit instantiation
 #define PF_INST(T)                                                                              \
-  template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *,             \
-                                 const CgArgs &);                                              \
-  template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
-                                   const T *, const CgArgs &);                                 \
-  template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
-                                          const ElasCoef &, int, const T *, const T *,         \
-                                          const uint8_t *, const uint8_t *, const uint8_t *,   \
-                                          const T *, const T *, T *, T *, const CgArgs &);     \
-  template hipError_t phase_cg_apply<T>(hipStream_t, const Grid &, const March &,              \
-                                        const PhaseCoef &, const T *, const uint8_t *,         \
-                                        const uint8_t *, const T *, const T *, T *, T *,       \
-                                        const CgArgs &);                                       \
   template hipError_t tangent_diag<T>(hipStream_t, const Grid &, const March &,                \
                                       const ElasCoef &, int, const T *, const T *,             \
                                       const uint8_t *, const uint8_t *, const uint8_t *, T *); \
@@ -1594,7 +1710,14 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                    const T *, const double *, const double *,                  \
                                    const uint8_t *, const uint8_t *, double *);                \
   template hipError_t axpy_into<T>(hipStream_t, int, double *, const double *, double,         \
-                                   const T *);
+                                   const T *);                                                 \
+  template hipError_t tangent_cg1<T>(hipStream_t, const Grid &, const March &, const ElasCoef &, \
+                                     int, const T *, const T *, const uint8_t *,               \
+                                     const uint8_t *, const uint8_t *, const CgVecs<T> &,      \
+                                     const Cg1Args &);                                         \
+  template hipError_t phase_cg1<T>(hipStream_t, const Grid &, const March &, const PhaseCoef &, \
+                                   const T *, const uint8_t *, const uint8_t *,                \
+                                   const CgVecs<T> &, const Cg1Args &);
 
 PF_INST(double)
 PF_INST(float)

@@ -35,8 +35,11 @@ struct Group {
 // Work vectors of one precision.
 template <class T>
 struct CgBuf {
-  T *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr,
-    *Dinv = nullptr;
+  // single-kernel CG vectors, double-buffered by iteration parity; the
+  // right-hand side of a solve goes into R[0]
+  T *R[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr}, *S[2] = {nullptr, nullptr},
+    *X[2] = {nullptr, nullptr}, *P[2] = {nullptr, nullptr};
+  T *Dinv = nullptr;
   T *d = nullptr;      // d in this precision (operator data of the tangent)
   T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
   T *coef = nullptr;   // [4E] phase coefficient
@@ -69,10 +72,11 @@ struct pf_ctx {
   uint8_t *nflag = nullptr, *qflag = nullptr, *tflag = nullptr, *eact = nullptr;
   CgBuf<double> bd;
   CgBuf<float> bf;
-  CgState *cgs = nullptr;
+  Cg1State *cgs = nullptr;     // [2]
+  double *cgpart = nullptr;     // [2][3][kPMax]
   RedScratch rs{};
   // pinned host mirrors
-  CgState *cgs_h = nullptr;
+  Cg1State *cgs_h = nullptr;   // [2]
   double *scal_h = nullptr;
   unsigned long long *icount_h = nullptr;
   std::vector<void *> allocs;
@@ -246,33 +250,47 @@ CgBuf<double> &buf<double>(pf_ctx *c) { return c->bd; }
 template <>
 CgBuf<float> &buf<float>(pf_ctx *c) { return c->bf; }
 
-// Enqueue `iters` CG iterations (apply + update pairs) starting from the
-// direction buffer p0 (iters is even, so the buffers end where they began).
 template <class T>
-pf_status enqueue_iters(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n, int iters,
-                        bool time_first) {
+CgVecs<T> cg_vecs(CgBuf<T> &b) {
+  CgVecs<T> v;
+  for (int k = 0; k < 2; ++k) {
+    v.R[k] = b.R[k];
+    v.W[k] = b.W[k];
+    v.S[k] = b.S[k];
+    v.X[k] = b.X[k];
+    v.P[k] = b.P[k];
+  }
+  v.Dinv = b.Dinv;
+  return v;
+}
+
+template <class T>
+pf_status launch_k(pf_ctx *c, hipStream_t st, Kind kind, const Cg1Args &a) {
   CgBuf<T> &b = buf<T>(c);
-  T *pold = b.p0, *pnew = b.p1;
+  const CgVecs<T> v = cg_vecs(b);
+  if (kind == K_ELASTIC) {
+    PF_HIP(c, tangent_cg1<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag, c->eact,
+                             c->nflag, v, a));
+  } else {
+    PF_HIP(c, phase_cg1<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, v, a));
+  }
+  return PF_OK;
+}
+
+// Enqueue `iters` CG iterations (one kernel each) starting at parity 1
+// (iters is even, so the batch ends at parity 0).  With time_first, the first
+// kernel (idempotent: it reads parity-0 buffers and writes parity-1 ones) is
+// launched kTimedRepeat times between one event pair.
+template <class T>
+pf_status enqueue_iters(pf_ctx *c, hipStream_t st, Kind kind, Cg1Args a, int iters,
+                        bool time_first) {
   for (int k = 0; k < iters; ++k) {
-    // Timed sample: the apply kernel is idempotent (it rewrites p_new, q and
-    // its partials from inputs it does not modify), so it is launched
-    // kTimedRepeat times back to back between one event pair and the
-    // per-launch time is the elapsed time divided by kTimedRepeat.
+    a.parity = (k + 1) & 1;
+    a.init = 0;
     const bool t = time_first && k == 0;
     if (t) PF_HIP(c, hipEventRecord(c->ev[0], st));
-    for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
-      if (kind == K_ELASTIC) {
-        PF_HIP(c, tangent_cg_apply<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
-                                      c->tflag, c->eact, c->nflag, b.z, pold, pnew, b.q, ca));
-      } else {
-        PF_HIP(c, phase_cg_apply<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.z,
-                                    pold, pnew, b.q, ca));
-      }
-    }
+    for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) PF_TRY(launch_k<T>(c, st, kind, a));
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
-    PF_HIP(c, cg_update<T>(st, n, b.x, b.r, b.z, pnew, b.q, b.Dinv, ca));
-    if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
-    std::swap(pold, pnew);
   }
   return PF_OK;
 }
@@ -280,7 +298,7 @@ pf_status enqueue_iters(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, 
 // Graph of `niter` CG iterations for this solve kind, captured on a private
 // stream the first time it is needed and launched on the context's stream.
 template <class T>
-pf_status cg_graph(pf_ctx *c, Kind kind, const CgArgs &ca, int n, double tol, int niter,
+pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter,
                    hipGraphExec_t *out) {
   const int fp32 = std::is_same<T, float>::value ? 1 : 0;
   for (auto &e : c->graphs)
@@ -290,7 +308,7 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const CgArgs &ca, int n, double tol, in
     }
   if (!c->cap_stream) PF_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   PF_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  pf_status s = enqueue_iters<T>(c, c->cap_stream, kind, ca, n, niter, false);
+  pf_status s = enqueue_iters<T>(c, c->cap_stream, kind, a, niter, false);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   if (s != PF_OK) return s;
@@ -304,46 +322,51 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const CgArgs &ca, int n, double tol, in
   return PF_OK;
 }
 
-// Solve A x = r0 (r0 already in b.r, zero on fixed DOFs) from x = 0 with
-// Jacobi PCG to ||r|| <= tol ||r0||.  b.Dinv must hold the inverse diagonal.
-// Batches of cg_check iterations are enqueued (as a captured graph) between
-// polls of the device-side status word; iterations after convergence exit
-// at once.
+// Solve A x = r0 (r0 in b.R[0], zero on fixed DOFs) from x = 0 with Jacobi
+// PCG (single-kernel CG) to ||r|| <= tol ||r0||.  b.Dinv holds the inverse
+// diagonal.  Batches of cg_check iterations are enqueued (as a captured
+// graph) between polls of the device-side status; kernels after convergence
+// exit in their prologue.  *xout points to the solution buffer.
 template <class T>
-pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status) {
+pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
   CgBuf<T> &b = buf<T>(c);
-  const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
-  const CgArgs ca = cg_args(c->g, c->ms, n, c->cgs, c->rs, tol, c->opts.max_cg);
-  PF_HIP(c, cg_init<T>(c->stream, n, b.x, b.r, b.z, b.p0, b.Dinv, ca));
+  Cg1Args a;
+  a.st = c->cgs;
+  a.part = c->cgpart;
+  a.np = cg1_blocks(c->ms);
+  a.tol2 = tol * tol;
+  a.maxit = c->opts.max_cg;
+  a.parity = 0;
+  a.init = 1;
+  PF_TRY(launch_k<T>(c, c->stream, kind, a));
   int batch = std::max(4, c->opts.cg_check);
   batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
   const bool timed = c->profiling;
   hipGraphExec_t ex = nullptr;
   const int ngraph = timed ? batch - 2 : batch;
-  if (c->use_graphs) PF_TRY(cg_graph<T>(c, kind, ca, n, tol, ngraph, &ex));
+  if (c->use_graphs) PF_TRY(cg_graph<T>(c, kind, a, tol, ngraph, &ex));
   for (;;) {
-    if (timed) PF_TRY(enqueue_iters<T>(c, c->stream, kind, ca, n, 2, true));
+    if (timed) PF_TRY(enqueue_iters<T>(c, c->stream, kind, a, 2, true));
     if (ex) {
       PF_HIP(c, hipGraphLaunch(ex, c->stream));
     } else {
-      PF_TRY(enqueue_iters<T>(c, c->stream, kind, ca, n, ngraph, false));
+      PF_TRY(enqueue_iters<T>(c, c->stream, kind, a, ngraph, false));
     }
-    PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    PF_HIP(c, hipMemcpyAsync(c->cgs_h, c->cgs, 2 * sizeof(Cg1State), hipMemcpyDeviceToHost,
+                             c->stream));
     PF_TRY(sync(c));
     if (timed) {
-      float a = 0.f, u = 0.f;
-      PF_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
-      PF_HIP(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
+      float ms = 0.f;
+      PF_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
       c->prof_launches[kid] += kTimedRepeat;
-      c->prof_ms[kid] += a;
-      c->prof_launches[2] += 1;
-      c->prof_ms[2] += u;
+      c->prof_ms[kid] += ms;
     }
-    if (c->cgs_h->b.done != 0) break;
+    if (c->cgs_h[0].done != 0) break;
   }
-  *iters = c->cgs_h->b.iters;
-  *status = c->cgs_h->b.done;
+  *iters = c->cgs_h[0].iters;
+  *status = c->cgs_h[0].done;
+  *xout = b.X[*iters & 1];
   return PF_OK;
 }
 
@@ -377,10 +400,10 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
     PF_HIP(c, tangent_flags(c->stream, c->g, c->u, c->eact, c->tflag));
     if (mixed) {
       PF_HIP(c, convert<float, double>(c->stream, c->g.N, c->bf.d, c->d));
-      PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.r, c->Ru));
+      PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.R[0], c->Ru));
       if (c->mt.split == 1) PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.ulin, c->u));
     } else {
-      PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+      PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
                                c->stream));
     }
     if (!mixed && c->mt.split == 1)   // the Newton point, in a buffer whose address captured
@@ -390,7 +413,8 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
     PF_HIP(c, tangent_diag<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
                               c->eact, c->nflag, b.Dinv));
     int iters = 0, status = 0;
-    PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status));
+    T *xs = nullptr;
+    PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status, &xs));
     st->n_cg_u += iters;
     st->dof_updates += (double)iters * (double)c->n_free_u;
     if (status == 3) st->cg_not_converged += 1;
@@ -399,7 +423,7 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
     double alpha = 1.0, nt = 0.0;
     int halv = 0;
     for (;;) {
-      PF_HIP(c, axpy_into<T>(c->stream, n2, c->u_try, c->u, alpha, b.x));
+      PF_HIP(c, axpy_into<T>(c->stream, n2, c->u_try, c->u, alpha, xs));
       PF_TRY(residual_u(c, c->u_try, c->Ru_try, &nt));
       if (nt < nr || halv == 5) break;
       alpha *= 0.5;
@@ -449,17 +473,18 @@ pf_status phase_solve_impl(pf_ctx *c, const double *Hs, pf_step_stats *st) {
     if (nR == 0.0) break;
     if (mixed && k > 0 && nR <= c->opts.tol_pcg * nR0) break;
     if (mixed) {
-      PF_HIP(c, convert<float, double>(c->stream, n, c->bf.r, c->Rd));
+      PF_HIP(c, convert<float, double>(c->stream, n, c->bf.R[0], c->Rd));
     } else {
-      PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+      PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
                                c->stream));
     }
     int iters = 0, status = 0;
-    PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status));
+    T *xs = nullptr;
+    PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status, &xs));
     st->n_cg_d += iters;
     st->dof_updates += (double)iters * (double)c->n_free_d;
     if (status == 3) st->cg_not_converged += 1;
-    PF_HIP(c, axpy_into<T>(c->stream, n, c->d, c->d, 1.0, b.x));
+    PF_HIP(c, axpy_into<T>(c->stream, n, c->d, c->d, 1.0, xs));
     if (mixed) PF_TRY(phase_res(c, Hs, true, &nR, &nb));
   }
   st->n_dsolve += 1;
@@ -486,18 +511,19 @@ pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
   PF_TRY(phase_res(c, c->H, true, &nR, &nb));   // also reads icount (floor hits)
   st->floor_hits += (int64_t)c->icount_h[IC_FLOOR];
   if (mixed) {
-    PF_HIP(c, convert<float, double>(c->stream, n, c->bf.r, c->Rd));
+    PF_HIP(c, convert<float, double>(c->stream, n, c->bf.R[0], c->Rd));
   } else {
-    PF_HIP(c, hipMemcpyAsync(c->bd.r, c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+    PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
   }
   int iters = 0, status = 0;
-  PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status));
+  T *xs = nullptr;
+  PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status, &xs));
   st->n_cg_trial += iters;
   st->dof_updates += (double)iters * (double)c->n_free_d;
   if (status == 3) st->cg_not_converged += 1;
   if (status == 2) return fail(c, PF_E_BREAKDOWN, "trial CG breakdown");
-  PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, b.x, c->H, c->psi_s, c->qflag, c->eact,
+  PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, xs, c->H, c->psi_s, c->qflag, c->eact,
                          c->Hhat));
   st->n_trial += 1;
   return PF_OK;
@@ -706,18 +732,23 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   A(&c->Ru, n2); A(&c->Ru_try, n2); A(&c->Rd, g.N); A(&c->Rfull, n2);
   A(&c->u_unit, n2); A(&c->d_fix, g.N);
   A(&c->nflag, g.N); A(&c->qflag, g.E); A(&c->tflag, g.E);
-  A(&c->bd.x, n2); A(&c->bd.r, n2); A(&c->bd.z, n2); A(&c->bd.p0, n2); A(&c->bd.p1, n2);
-  A(&c->bd.q, n2); A(&c->bd.Dinv, n2); A(&c->bd.coef, E4);
+  for (int k = 0; k < 2; ++k) {
+    A(&c->bd.R[k], n2); A(&c->bd.W[k], n2); A(&c->bd.S[k], n2); A(&c->bd.X[k], n2);
+    A(&c->bd.P[k], n2);
+  }
+  A(&c->bd.Dinv, n2); A(&c->bd.coef, E4);
   if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bd.ulin, n2);
   c->bd.d = c->d;
   if (o.precision == PF_MIXED) {
-    A(&c->bf.x, n2); A(&c->bf.r, n2); A(&c->bf.z, n2); A(&c->bf.p0, n2); A(&c->bf.p1, n2);
-    A(&c->bf.q, n2); A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
+    for (int k = 0; k < 2; ++k) {
+      A(&c->bf.R[k], n2); A(&c->bf.W[k], n2); A(&c->bf.S[k], n2); A(&c->bf.X[k], n2);
+      A(&c->bf.P[k], n2);
+    }
+    A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
-  A(&c->cgs, 1);
-  A(&c->rs.partA, (size_t)kPMax);
-  A(&c->rs.partB, 2 * (size_t)kPMax);
+  A(&c->cgs, 2);
+  A(&c->cgpart, 6 * (size_t)kPMax);
   A(&c->rs.partR, 2 * (size_t)kPMax);
   A(&c->rs.icount, kICounters);
   A(&c->rs.scal, kScal);
@@ -729,7 +760,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
       s = PF_E_HIP;
   }
   if (s == PF_OK) {
-    if (hipHostMalloc((void **)&c->cgs_h, sizeof(CgState)) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->cgs_h, 2 * sizeof(Cg1State)) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess)
       s = PF_E_OOM;
