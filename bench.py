@@ -37,13 +37,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cg_iteration_bytes_per_node(prec):
-    """Algorithmic bytes per node of one single-kernel CG iteration on the
-    elasticity tangent (2 components per node): read r, w, s, D^-1, p, x
-    (6 vectors x 2 comps) and d (1), the node flag (1 B) and the element
-    flag (1 B per element ~ node); write r, w, s, p, x (5 vectors x 2)."""
-    w = 4 if prec == "mixed" else 8
-    return (6 * 2 + 1 + 5 * 2) * w + 1 + 1
+def fused_apply_bytes_per_node():
+    """Algorithmic bytes per node of the FP32 fused elasticity CG apply
+    (k_cg_apply, used by the FP32 inner solves): read z (2 comps), p_old (2),
+    d (1), node flag (1 B), element flag (1 B per element ~ node); write
+    p_new (2), q (2)."""
+    return (2 + 2 + 1 + 2 + 2) * 4 + 1 + 1
 
 
 def measured_traffic():
@@ -174,7 +173,7 @@ def main():
     ms_per_step = secs * 1e3 / args.steps
     launches, kms, nodes = ctx.kernel_time(0)
     avg_ms = kms / max(launches, 1)
-    bpn = cg_iteration_bytes_per_node("mixed")
+    bpn = fused_apply_bytes_per_node()
     alg_bytes = bpn * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     ctx.close()
@@ -222,7 +221,7 @@ def main():
         "st_fp64": st_res,
         "speedup_s1_mixed_vs_st_fp64": (st_res["ms_per_step"] / ms_per_step) if st_res else None,
         "roofline": {
-            "kernel": "k_cg1<4, OpTangent<float>> (one CG iteration: recurrences + tangent apply)",
+            "kernel": "k_cg_apply<4, OpTangent<float>> (fused CG direction update + tangent apply)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -182,11 +182,13 @@ pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
 
 /* Kernel timing for measurement.  When enabled, the CG drivers time a sample
  * of the CG kernel launches with HIP events on the context's stream: per
- * enqueued batch, the first iteration's kernel (one whole CG iteration; it
- * only reads the previous parity's buffers, so repeating it is idempotent)
- * is launched four times back to back between one event pair.  Launch
- * counts and elapsed times accumulate.  kernel: 0 = elasticity CG
- * iteration, 1 = phase CG iteration, 2 = reserved (always 0).  Enabling
+ * enqueued batch, the first iteration's operator kernel (idempotent: it only
+ * reads buffers it does not write) is launched four times back to back
+ * between one event pair.  Launch counts and elapsed times accumulate.
+ * FP64 solves use the single-kernel CG (the timed kernel is a whole
+ * iteration); FP32 inner solves use the two-kernel CG (the timed kernel is
+ * the fused operator apply, and its vector update is timed once per batch).
+ * kernel: 0 = elasticity, 1 = phase, 2 = FP32 vector update.  Enabling
  * resets the counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,

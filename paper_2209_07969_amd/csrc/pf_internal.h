@@ -21,6 +21,33 @@ struct Mat {
   int split;      // 0 = volumetric-deviatoric, 1 = spectral
 };
 
+// Per-solve CG state in device memory.  The CG loop has no communication
+// between blocks of one kernel: each kernel writes block partials with plain
+// stores, and every block of the next kernel reduces them in a fixed order in
+// its prologue, so all blocks hold bit-identical scalars.  Block 0 records
+// the scalars for later kernels in the half of this struct the current
+// kernel does not read (A = written by the operator apply, B = written by the
+// vector update / init), each half on its own 128-byte line.
+struct alignas(128) CgHalfA {
+  double rz;      // r.z entering this iteration
+  double rr;      // r.r entering this iteration
+  double rr0;     // r.r of the initial residual
+  int done;       // 0 running, 1 converged, 2 breakdown/non-finite, 3 maxit
+  int iters;      // completed iterations
+};
+struct alignas(128) CgHalfB {
+  double rz_prev; // r.z of the previous iteration (for beta)
+  double rr0;
+  int done;
+  int iters;
+  int first;      // 1 before the first direction
+  int pad;
+};
+struct CgState {
+  CgHalfA a;
+  CgHalfB b;
+};
+
 // Node flag bits
 constexpr uint8_t NF_UX = 1;   // u_x fixed (Dirichlet or inactive node)
 constexpr uint8_t NF_UY = 2;   // u_y fixed
@@ -86,6 +113,17 @@ struct Cg1Args {
   int init;            // 1 for K_0
 };
 
+// Launch geometry of one CG solve: grid sizes of the apply (ga) and of the
+// vector kernels (gb); each kernel's prologue reduces the other's partials.
+struct CgArgs {
+  CgState *st;
+  double *partA;
+  double *partB;
+  int ga, gb;
+  double tol2;
+  int maxit;
+};
+
 // Operator coefficients passed by value.
 struct ElasCoef {
   double two_mu, K, lam, mu, eta;
@@ -106,6 +144,25 @@ March march_shape(const Grid &g, int ch_override);
 
 // CG (T = double or float).  p_old/p_new are the two direction buffers; the
 // apply computes p_new = z + beta p_old on the fly and q = A p_new.
+CgArgs cg_args(const Grid &g, const March &m, int n, CgState *st, RedScratch rs, double tol,
+               int maxit);
+template <class T>
+hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
+                   const CgArgs &ca);
+template <class T>
+hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
+                     const T *Dinv, const CgArgs &ca);
+// split = 1 (spectral): the tangent is re-derived per QP from the
+// linearisation point ulin [2N] instead of the indicator bits.
+template <class T>
+hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *z,
+                            const T *p_old, T *p_new, T *q, const CgArgs &ca);
+template <class T>
+hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                          const T *z, const T *p_old, T *p_new, T *q, const CgArgs &ca);
 // Single-kernel CG iteration for the elasticity tangent / the phase operator.
 template <class T>
 hipError_t tangent_cg1(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,

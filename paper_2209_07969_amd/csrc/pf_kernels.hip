@@ -951,6 +951,140 @@ hipError_t launch_march_reduce(hipStream_t s, const Op &op, const Grid &g, const
   return hipGetLastError();
 }
 
+// ------------------------------------------------- two-kernel CG (FP32)
+//
+// Standard PCG with two kernels per iteration, used for the FP32 inner
+// solves (its recurrences keep their convergence rate at FP32 rounding,
+// where the single-reduction form below loses about a fifth).
+// Iteration k = apply kernel A_k then vector kernel B_k.
+//   A_k: reduce B_{k-1}'s partials -> rz_k, rr_k; decide done; beta =
+//        rz_k / rz_{k-1}; p = z + beta p_old; q = A p; partials p.q.
+//   B_k: reduce A_k's partials -> pq; alpha = rz_k / pq; x += alpha p;
+//        r -= alpha q; z = D^-1 r; partials r.z, r.r.
+// Block 0 of each kernel records its scalars in its own half of CgState.
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pold,
+                                                 const T *Dinv, CgArgs ca) {
+  double v[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T ri = r[i];
+    const T zi = Dinv[i] * ri;
+    x[i] = T(0);
+    z[i] = zi;
+    pold[i] = T(0);
+    v[0] += double(ri) * double(zi);
+    v[1] += double(ri) * double(ri);
+  }
+  block_partial<2>(v, ca.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = 0.0;
+    ca.st->b.rr0 = 0.0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = 0;
+    ca.st->b.first = 1;
+  }
+}
+
+// Prologue of the apply kernels: returns done (uniform) and beta.
+__device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
+  double s[2];
+  block_sum<2>(ca.partB, ca.gb, s);
+  const double rz = s[0], rr = s[1];
+  const int first = ca.st->b.first;
+  const int iters = ca.st->b.iters;
+  int done = ca.st->b.done;
+  const double rr0 = first ? rr : ca.st->b.rr0;
+  if (!done) {
+    if (!(rr == rr) || !(rz == rz)) done = 2;
+    else if (rr <= ca.tol2 * rr0) done = 1;
+    else if (iters >= ca.maxit) done = 3;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->a.rz = rz;
+    ca.st->a.rr = rr;
+    ca.st->a.rr0 = rr0;
+    ca.st->a.done = done;
+    ca.st->a.iters = iters;
+  }
+  *beta = first ? 0.0 : rz / ca.st->b.rz_prev;
+  return done;
+}
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+  const int lane = threadIdx.x & 63;
+  const int w0 = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
+  const int nw = ms.nstrips * ms.nchunks;
+  // issue the first work item's loads before the prologue's reduction
+  Item<CH, Op> it;
+  if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
+  double beta = 0.0;
+  if (cg_apply_prologue(ca, &beta) != 0) return;
+  op.beta = typename Op::T(beta);
+  double red[1] = {0.0};
+  if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
+  march_items<CH>(op, g, ms, w0 + gridDim.x * WPB, red);
+  block_partial<1>(red, ca.partA);
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
+                                                   const T *q, const T *Dinv, CgArgs ca) {
+  const int done = ca.st->a.done;
+  const double rz = ca.st->a.rz;
+  const double rr0 = ca.st->a.rr0;
+  const int iters = ca.st->a.iters;
+  if (done != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ca.st->b.done = done;
+      ca.st->b.iters = iters;
+      ca.st->b.rr0 = rr0;
+      ca.st->b.first = 0;
+    }
+    return;
+  }
+  double pqs[1];
+  block_sum<1>(ca.partA, ca.ga, pqs);
+  const double pq = pqs[0];
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ca.st->b.done = 2;
+      ca.st->b.iters = iters;
+      ca.st->b.rr0 = rr0;
+      ca.st->b.first = 0;
+    }
+    return;
+  }
+  const T alpha = T(rz / pq);
+  double v[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T xi = x[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    const T zi = Dinv[i] * ri;
+    x[i] = xi;
+    r[i] = ri;
+    z[i] = zi;
+    v[0] += double(ri) * double(zi);
+    v[1] += double(ri) * double(ri);
+  }
+  block_partial<2>(v, ca.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = rz;
+    ca.st->b.rr0 = rr0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = iters + 1;
+    ca.st->b.first = 0;
+  }
+}
+
+int vec_blocks(int n) {
+  int b = (n + 4 * TPB - 1) / (4 * TPB);
+  if (b > kPMax) b = kPMax;
+  if (b < 1) b = 1;
+  return b;
+}
+
 // --------------------------------------------------- single-kernel CG
 //
 // Chronopoulos-Gear CG with one reduction and one kernel per iteration.
@@ -1508,6 +1642,72 @@ March march_shape(const Grid &g, int ch_override) {
 
 
 
+template <class T>
+hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
+                   const CgArgs &ca) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_init<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
+                     p_old, Dinv, ca);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
+                     const T *Dinv, const CgArgs &ca) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
+                     p, q, Dinv, ca);
+  return hipGetLastError();
+}
+
+template <class Op>
+hipError_t launch_cg_apply(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                           const CgArgs &ca) {
+  const dim3 grid(ca.ga), block(TPB);
+  switch (m.ch) {
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<2, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<4, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<8, Op>), grid, block, 0, s, op, g, m, ca); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_cg_apply(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *z,
+                            const T *p_old, T *p_new, T *q, const CgArgs &ca) {
+  if (split == 1) {
+    using Op = OpTangent<T, true, true, 1>;
+    Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), ulin};
+    return launch_cg_apply(s, op, g, m, ca);
+  }
+  using Op = OpTangent<T, true, true, 0>;
+  Op op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), nullptr};
+  return launch_cg_apply(s, op, g, m, ca);
+}
+
+template <class T>
+hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
+                          const T *p_old, T *p_new, T *q, const CgArgs &ca) {
+  using Op = OpPhase<T, true, true>;
+  Op op{g, c, coef, eact, nflag, z, p_old, p_new, q, T(0)};
+  return launch_cg_apply(s, op, g, m, ca);
+}
+
+CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, double tol,
+               int maxit) {
+  CgArgs ca;
+  ca.st = st;
+  ca.partA = rs.partR;
+  ca.partB = rs.partR + 2 * kPMax;
+  ca.ga = march_blocks(m);
+  ca.gb = vec_blocks(n);
+  ca.tol2 = tol * tol;
+  ca.maxit = maxit;
+  return ca;
+}
+
 int cg1_blocks(const March &m) { return march_blocks(m); }
 
 template <class Op>
@@ -1711,6 +1911,18 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                    const uint8_t *, const uint8_t *, double *);                \
   template hipError_t axpy_into<T>(hipStream_t, int, double *, const double *, double,         \
                                    const T *);                                                 \
+  template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *,             \
+                                 const CgArgs &);                                              \
+  template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
+                                   const T *, const CgArgs &);                                 \
+  template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
+                                          const ElasCoef &, int, const T *, const T *,         \
+                                          const uint8_t *, const uint8_t *, const uint8_t *,   \
+                                          const T *, const T *, T *, T *, const CgArgs &);     \
+  template hipError_t phase_cg_apply<T>(hipStream_t, const Grid &, const March &,              \
+                                        const PhaseCoef &, const T *, const uint8_t *,         \
+                                        const uint8_t *, const T *, const T *, T *, T *,       \
+                                        const CgArgs &);                                       \
   template hipError_t tangent_cg1<T>(hipStream_t, const Grid &, const March &, const ElasCoef &, \
                                      int, const T *, const T *, const uint8_t *,               \
                                      const uint8_t *, const uint8_t *, const CgVecs<T> &,      \

@@ -73,6 +73,8 @@ struct pf_ctx {
   CgBuf<double> bd;
   CgBuf<float> bf;
   Cg1State *cgs = nullptr;     // [2]
+  CgState *cgs2 = nullptr;      // two-kernel CG state
+  CgState *cgs2_h = nullptr;
   double *cgpart = nullptr;     // [2][3][kPMax]
   RedScratch rs{};
   // pinned host mirrors
@@ -83,7 +85,7 @@ struct pf_ctx {
 
   // captured CG batches (hipGraph), keyed by solve kind and precision
   struct GraphEntry {
-    int kind, fp32, niter;
+    int kind, fp32, niter, variant;
     double tol;
     hipGraphExec_t exec;
   };
@@ -302,7 +304,7 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter
                    hipGraphExec_t *out) {
   const int fp32 = std::is_same<T, float>::value ? 1 : 0;
   for (auto &e : c->graphs)
-    if (e.kind == kind && e.fp32 == fp32 && e.niter == niter && e.tol == tol) {
+    if (e.kind == kind && e.fp32 == fp32 && e.niter == niter && e.tol == tol && e.variant == 1) {
       *out = e.exec;
       return PF_OK;
     }
@@ -317,8 +319,94 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter
   e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  c->graphs.push_back({kind, fp32, niter, tol, ex});
+  c->graphs.push_back({kind, fp32, niter, 1, tol, ex});
   *out = ex;
+  return PF_OK;
+}
+
+// ---- two-kernel CG (standard recurrences), used for the FP32 inner solves.
+// Buffers: x = X[0], r = R[0], z = W[0], p_old/p_new = P[0]/P[1], q = S[0].
+template <class T>
+pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n, int iters,
+                         bool time_first) {
+  CgBuf<T> &b = buf<T>(c);
+  T *pold = b.P[0], *pnew = b.P[1];
+  for (int k = 0; k < iters; ++k) {
+    // the apply kernel is idempotent (it rewrites p_new, q and its partials
+    // from inputs it does not modify): the timed sample repeats it
+    const bool t = time_first && k == 0;
+    if (t) PF_HIP(c, hipEventRecord(c->ev[0], st));
+    for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
+      if (kind == K_ELASTIC) {
+        PF_HIP(c, tangent_cg_apply<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                                      c->eact, c->nflag, b.W[0], pold, pnew, b.S[0], ca));
+      } else {
+        PF_HIP(c, phase_cg_apply<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.W[0],
+                                    pold, pnew, b.S[0], ca));
+      }
+    }
+    if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
+    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca));
+    if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
+    std::swap(pold, pnew);
+  }
+  return PF_OK;
+}
+
+template <class T>
+pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
+  CgBuf<T> &b = buf<T>(c);
+  const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
+  const CgArgs ca = cg_args(c->g, c->ms, n, c->cgs2, c->rs, tol, c->opts.max_cg);
+  PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
+  int batch = std::max(4, c->opts.cg_check);
+  batch += batch & 1;
+  const int kid = (kind == K_ELASTIC) ? 0 : 1;
+  const bool timed = c->profiling;
+  const int ngraph = timed ? batch - 2 : batch;
+  const int fp32 = std::is_same<T, float>::value ? 1 : 0;
+  hipGraphExec_t ex = nullptr;
+  if (c->use_graphs) {
+    for (auto &e : c->graphs)
+      if (e.kind == kind && e.fp32 == fp32 && e.niter == ngraph && e.tol == tol && e.variant == 2)
+        ex = e.exec;
+    if (!ex) {
+      if (!c->cap_stream) PF_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      PF_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      pf_status s = enqueue_iters2<T>(c, c->cap_stream, kind, ca, n, ngraph, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (s != PF_OK) return s;
+      if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      c->graphs.push_back({kind, fp32, ngraph, 2, tol, ex});
+    }
+  }
+  for (;;) {
+    if (timed) PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, 2, true));
+    if (ex) {
+      PF_HIP(c, hipGraphLaunch(ex, c->stream));
+    } else {
+      PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, ngraph, false));
+    }
+    PF_HIP(c, hipMemcpyAsync(c->cgs2_h, c->cgs2, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    PF_TRY(sync(c));
+    if (timed) {
+      float a = 0.f, u = 0.f;
+      PF_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+      PF_HIP(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
+      c->prof_launches[kid] += kTimedRepeat;
+      c->prof_ms[kid] += a;
+      c->prof_launches[2] += 1;
+      c->prof_ms[2] += u;
+    }
+    if (c->cgs2_h->b.done != 0) break;
+  }
+  *iters = c->cgs2_h->b.iters;
+  *status = c->cgs2_h->b.done;
+  *xout = b.X[0];
   return PF_OK;
 }
 
@@ -329,6 +417,7 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter
 // exit in their prologue.  *xout points to the solution buffer.
 template <class T>
 pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
+  if (std::is_same<T, float>::value) return pcg2<T>(c, kind, tol, iters, status, xout);
   CgBuf<T> &b = buf<T>(c);
   Cg1Args a;
   a.st = c->cgs;
@@ -748,8 +837,9 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
   A(&c->cgs, 2);
+  A(&c->cgs2, 1);
   A(&c->cgpart, 6 * (size_t)kPMax);
-  A(&c->rs.partR, 2 * (size_t)kPMax);
+  A(&c->rs.partR, 4 * (size_t)kPMax);
   A(&c->rs.icount, kICounters);
   A(&c->rs.scal, kScal);
   if (mesh->elem_active) {
@@ -761,6 +851,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   }
   if (s == PF_OK) {
     if (hipHostMalloc((void **)&c->cgs_h, 2 * sizeof(Cg1State)) != hipSuccess ||
+        hipHostMalloc((void **)&c->cgs2_h, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess)
       s = PF_E_OOM;
@@ -787,6 +878,7 @@ pf_status pf_destroy(pf_ctx *c) {
   for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->cgs_h) (void)hipHostFree(c->cgs_h);
+  if (c->cgs2_h) (void)hipHostFree(c->cgs2_h);
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
   delete c;
