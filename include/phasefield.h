@@ -180,6 +180,28 @@ const char *pf_last_error(const pf_ctx *ctx);
 /* Number of free displacement / phase DOFs (after Dirichlet data and mask). */
 pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
 
+/* ---------------------------------------------------------------------------
+ * Batched sweeps: many independent problems advanced together.  Each member
+ * context should have its own HIP stream (pf_create's hip_stream); a pool of
+ * `workers` host threads (0 = 4) runs pf_load_step on the members, so the
+ * kernels of different members execute concurrently on the GPU.  Results are
+ * identical to stepping the members one by one (every kernel is
+ * deterministic).  The batch borrows its members: destroy it first.
+ * ------------------------------------------------------------------------- */
+typedef struct pf_batch pf_batch;
+pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out);
+/* load_factors[n], stats[n] (may be NULL).  Returns PF_OK, or
+ * PF_E_NOT_CONVERGED if any member did not converge (all members are still
+ * committed), or the first error of a member. */
+pf_status pf_batch_load_step(pf_batch *b, const double *load_factors, pf_step_stats *stats);
+pf_status pf_batch_destroy(pf_batch *b);
+
+/* Autotuning of the operator kernels' work-item height (2, 4 or 8 node rows
+ * per wave): times `reps` launches of the displacement CG kernel for each
+ * candidate on the current state and keeps the fastest; *chosen receives it.
+ * Must be called outside an open step. */
+pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
+
 /* Kernel timing for measurement.  When enabled, the CG drivers time a sample
  * of the CG kernel launches with HIP events on the context's stream: per
  * enqueued batch, the first iteration's operator kernel (idempotent: it only

@@ -28,7 +28,8 @@ EXPORTED = [
     "pf_load_step", "pf_staggered_iterate", "pf_commit_step", "pf_reaction_force",
     "pf_get_state", "pf_set_state", "pf_status_string", "pf_last_error", "pf_free_dofs",
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
-    "pf_op_predictor", "pf_set_profiling", "pf_kernel_time",
+    "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create",
+    "pf_batch_load_step", "pf_batch_destroy", "pf_autotune",
 ]
 
 
@@ -107,6 +108,10 @@ def load_library(path: str = LIB_PATH):
     lib.pf_op_qp_update.argtypes = [P, c_int32, P, P, P, P, P, P, POINTER(c_int64)]
     lib.pf_op_predictor.argtypes = [P, P, P, P, P, P, P]
     lib.pf_set_profiling.argtypes = [P, c_int32]
+    lib.pf_batch_create.argtypes = [c_int32, POINTER(P), c_int32, POINTER(P)]
+    lib.pf_batch_load_step.argtypes = [P, POINTER(c_double), POINTER(StepStats)]
+    lib.pf_batch_destroy.argtypes = [P]
+    lib.pf_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
     lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_int64)]
     for name in EXPORTED:
@@ -279,6 +284,12 @@ class Context:
                     "pf_free_dofs")
         return a.value, b.value
 
+    def autotune(self, reps=20):
+        """Pick the fastest work-item height for this mesh; returns it."""
+        ch = c_int32()
+        self._check(self.lib.pf_autotune(self.h, int(reps), ctypes.byref(ch)), "pf_autotune")
+        return ch.value
+
     def set_profiling(self, enable=True):
         self._check(self.lib.pf_set_profiling(self.h, 1 if enable else 0), "pf_set_profiling")
 
@@ -317,5 +328,42 @@ class Context:
                     "pf_op_predictor")
 
 
-__all__ = ["Context", "load_library", "require_device", "default_opts", "PhaseFieldError",
+class Batch:
+    """Several contexts advanced together (each should own a HIP stream, e.g.
+    Context(..., stream=torch.cuda.Stream().cuda_stream))."""
+
+    def __init__(self, contexts, workers=4):
+        self.lib = load_library()
+        self.members = list(contexts)
+        arr = (c_void_p * len(self.members))(*[c.h for c in self.members])
+        h = c_void_p()
+        st = self.lib.pf_batch_create(len(self.members), arr, int(workers), ctypes.byref(h))
+        if st != 0:
+            raise PhaseFieldError(st, "pf_batch_create failed")
+        self.h = h
+
+    def load_step(self, load_factors, allow_not_converged=True):
+        n = len(self.members)
+        lam = np.ascontiguousarray(load_factors, dtype=np.float64)
+        if lam.size != n:
+            raise ValueError("one load factor per member")
+        stats = (StepStats * n)()
+        s = self.lib.pf_batch_load_step(self.h, _ptr(lam, c_double), stats)
+        if s != 0 and not (allow_not_converged and s == STATUS_NOT_CONVERGED):
+            raise PhaseFieldError(s, "pf_batch_load_step: " + self.lib.pf_status_string(s).decode())
+        return [stats[i].as_dict() for i in range(n)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Batch", "Context", "load_library", "require_device", "default_opts", "PhaseFieldError",
            "ST", "S1", "S2", "S3", "FP64", "MIXED", "EXPORTED"]

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1015,6 +1017,124 @@ pf_status pf_kernel_time(pf_ctx *c, int32_t kernel, int64_t *launches, double *t
   if (launches) *launches = c->prof_launches[kernel];
   if (total_ms) *total_ms = c->prof_ms[kernel];
   if (nodes_per_launch) *nodes_per_launch = c->g.N;
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------- batch
+
+struct pf_batch {
+  std::vector<pf_ctx *> members;
+  int workers = 4;
+};
+
+pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out) {
+  if (!out || n < 1 || !members || workers < 0) return PF_E_INVALID_ARG;
+  *out = nullptr;
+  std::vector<pf_ctx *> m(members, members + n);
+  for (int i = 0; i < n; ++i) {
+    if (!m[i]) return PF_E_INVALID_ARG;
+    for (int j = 0; j < i; ++j)
+      if (m[j] == m[i]) return PF_E_INVALID_ARG;
+  }
+  pf_batch *b = new pf_batch();
+  b->members = std::move(m);
+  b->workers = workers > 0 ? workers : 4;
+  *out = b;
+  return PF_OK;
+}
+
+pf_status pf_batch_load_step(pf_batch *b, const double *lam, pf_step_stats *stats) {
+  if (!b || !lam) return PF_E_INVALID_ARG;
+  const int n = (int)b->members.size();
+  std::vector<pf_status> st(n, PF_OK);
+  std::vector<pf_step_stats> ss(n);
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) return;
+      st[i] = pf_load_step(b->members[i], lam[i], &ss[i]);
+    }
+  };
+  const int nw = std::min(b->workers, n);
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(work);
+  work();
+  for (auto &t : th) t.join();
+  if (stats)
+    for (int i = 0; i < n; ++i) stats[i] = ss[i];
+  pf_status worst = PF_OK;
+  for (int i = 0; i < n; ++i) {
+    if (st[i] != PF_OK && st[i] != PF_E_NOT_CONVERGED) return st[i];
+    if (st[i] == PF_E_NOT_CONVERGED) worst = PF_E_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+pf_status pf_batch_destroy(pf_batch *b) {
+  delete b;
+  return PF_OK;
+}
+
+// ------------------------------------------------------------- autotune
+
+pf_status pf_autotune(pf_ctx *c, int32_t reps, int32_t *chosen) {
+  if (!c || reps < 1) return PF_E_INVALID_ARG;
+  if (c->step_open) return fail(c, PF_E_STATE, "cannot autotune inside a step");
+  if (!c->ev[0]) {
+    for (auto &e : c->ev) PF_HIP(c, hipEventCreate(&e));
+  }
+  // operator data for the timed kernel: tangent bits and diagonal at the
+  // committed state; right-hand side: the residual after lifting the
+  // Dirichlet data to load factor 1 (nonzero, so no kernel exits early)
+  const int n2 = 2 * c->g.N;
+  PF_HIP(c, hipMemcpyAsync(c->u_try, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  PF_HIP(c, lift_dirichlet(c->stream, n2, c->nflag, NF_UX | (NF_UY << 4), c->g.N, c->u_unit, 1.0,
+                           c->u_try));
+  double nr = 0.0;
+  PF_TRY(residual_u(c, c->u_try, c->Ru, &nr));
+  PF_HIP(c, tangent_flags(c->stream, c->g, c->u, c->eact, c->tflag));
+  const March keep = c->ms;
+  float best = 0.f;
+  int best_ch = keep.ch;
+  for (int ch : {2, 4, 8}) {
+    c->ms = march_shape(c->g, ch);
+    if (c->mt.split == 1)
+      PF_HIP(c, hipMemcpyAsync(c->bd.ulin, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    PF_HIP(c, tangent_diag<double>(c->stream, c->g, c->ms, c->ec, c->mt.split, c->bd.ulin, c->d,
+                                   c->tflag, c->eact, c->nflag, c->bd.Dinv));
+    PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    Cg1Args a;
+    a.st = c->cgs;
+    a.part = c->cgpart;
+    a.np = cg1_blocks(c->ms);
+    a.tol2 = 0.0;
+    a.maxit = 1 << 30;
+    a.parity = 0;
+    a.init = 1;
+    PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
+    a.init = 0;
+    a.parity = 1;
+    PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));   // warm
+    PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
+    for (int r = 0; r < reps; ++r) PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
+    PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
+    PF_TRY(sync(c));
+    float ms = 0.f;
+    PF_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    if (best == 0.f || ms < best) {
+      best = ms;
+      best_ch = ch;
+    }
+  }
+  c->ms = march_shape(c->g, best_ch);
+  // graphs captured with another work-item shape are stale
+  for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+  c->graphs.clear();
+  if (chosen) *chosen = best_ch;
   return PF_OK;
 }
 

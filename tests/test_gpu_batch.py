@@ -1,0 +1,52 @@
+"""Batched sweeps and autotuning (GPU): a batch of members on their own streams
+gives bit-identical results to stepping them one by one; autotuning keeps
+parity with the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def test_batch_matches_sequential(gpu_lib):
+    import torch
+    probs = [W.tension_panel(n=n, l=0.1, du=1e-3, steps=4, notch=a)
+             for n, a in ((16, 0.5), (24, 0.375), (20, 0.45))]
+    seq = [gpu_lib.Context(p, scheme=s) for p, s in zip(probs, (1, 0, 3))]
+    streams = [torch.cuda.Stream() for _ in probs]
+    bat = [gpu_lib.Context(p, scheme=s, stream=st.cuda_stream)
+           for p, s, st in zip(probs, (1, 0, 3), streams)]
+    B = gpu_lib.Batch(bat, workers=3)
+    for k in range(4):
+        lams = [float(p.loads[k]) for p in probs]
+        sb = B.load_step(lams)
+        for i, c in enumerate(seq):
+            s = c.load_step(lams[i])
+            assert s["n_stag"] == sb[i]["n_stag"]
+            assert s["force"] == sb[i]["force"]
+    for a, b in zip(seq, bat):
+        ua, da, Ha = a.get_state()
+        ub, db, Hb = b.get_state()
+        np.testing.assert_array_equal(ua, ub)
+        np.testing.assert_array_equal(da, db)
+        np.testing.assert_array_equal(Ha, Hb)
+    B.close()
+
+
+def test_autotune_keeps_parity(gpu_lib):
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=5)
+    ctx = gpu_lib.Context(p, scheme=1)
+    orc = Oracle(p, 1)
+    for lam in p.loads[:2]:
+        ctx.load_step(float(lam))
+        orc.load_step(float(lam))
+    ch = ctx.autotune(5)
+    assert ch in (2, 4, 8)
+    for lam in p.loads[2:]:
+        sg = ctx.load_step(float(lam))
+        so = orc.load_step(float(lam))
+        assert abs(sg["n_stag"] - so.n_stag) <= 1
+        assert abs(sg["force"][1] - so.force) <= 1e-4 * abs(so.force)
+    ctx.close()
