@@ -17,6 +17,16 @@ W warmup steps (load steps 1..W) run untimed, then K load steps are timed.
 value = GDOF-updates/s of S1 mixed over the timed steps (sum over all CG
 solves of free DOFs x iterations, divided by the wall time between two
 device synchronisations).  Inputs are resident in HBM before timing.
+
+Two further modes print their own single JSON line:
+  --workload sweep64     the seeded 64-instance tension sweep (mesh sizes
+                         128..512, Gc, l and notch drawn per instance), S1
+                         mixed with autotuned work items: load steps W+1..W+K
+                         of every instance, batched (members on their own
+                         streams, host worker pool) against one by one;
+  --workload apply-sizes the FP32 fused tangent apply and the CG vector
+                         update at 512^2 .. 4096^2 (one displacement solve of
+                         a notched panel, CG capped), against the HBM peak.
 """
 from __future__ import annotations
 
@@ -43,6 +53,12 @@ def fused_apply_bytes_per_node():
     d (1), node flag (1 B), element flag (1 B per element ~ node); write
     p_new (2), q (2)."""
     return (2 + 2 + 1 + 2 + 2) * 4 + 1 + 1
+
+
+def update_bytes_per_node():
+    """Algorithmic bytes per node of the FP32 CG vector update (k_cg_update):
+    per DOF read x, p, q, r, D^-1 and write x, r, z, two DOFs per node."""
+    return 2 * (5 + 3) * 4
 
 
 def measured_traffic():
@@ -126,12 +142,116 @@ def cpu_baseline(pf, problem):
     }
 
 
+def run_sweep(pf, args):
+    """Batched vs one-by-one throughput of the 64-instance sweep."""
+    import torch
+
+    import workloads as W
+    probs = W.batch_instances()
+    steps, warm = args.steps, args.warmup
+    # one by one: each instance alone on the default stream
+    chosen, t_seq, upd_seq, forces_seq = [], 0.0, 0.0, []
+    for i, p in enumerate(probs):
+        ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED)
+        chosen.append(ctx.autotune(10))
+        for n in range(warm):
+            ctx.load_step(float(p.loads[n]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = [ctx.load_step(float(p.loads[n])) for n in range(warm, warm + steps)]
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        upd_seq += sum(r["dof_updates"] for r in rows)
+        forces_seq.append([r["force"] for r in rows])
+        ctx.close()
+        if (i + 1) % 16 == 0:
+            log(f"  one by one: {i + 1}/64 instances, {t_seq:.1f} s timed")
+    # batched: members on their own streams, same work-item heights
+    streams = [torch.cuda.Stream() for _ in probs]
+    ctxs = [pf.Context(p, scheme=pf.S1, precision=pf.MIXED, stream=st.cuda_stream,
+                       march_rows=ch) for p, st, ch in zip(probs, streams, chosen)]
+    B = pf.Batch(ctxs, workers=args.workers)
+    for n in range(warm):
+        B.load_step([float(p.loads[n]) for p in probs])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows_b = [B.load_step([float(p.loads[n]) for p in probs]) for n in range(warm, warm + steps)]
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    upd_bat = sum(r["dof_updates"] for rows in rows_b for r in rows)
+    same = all(rows_b[k][i]["force"] == forces_seq[i][k]
+               for i in range(len(probs)) for k in range(steps))
+    B.close()
+    for c in ctxs:
+        c.close()
+    sizes = [p.nx for p in probs]
+    value = upd_bat / t_bat / 1e9
+    return {
+        "metric": "GDOF-updates/s, 64-instance S1 mixed sweep, batched vs one by one, 1 MI355X",
+        "value": value, "unit": "GDOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": t_bat * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"sweep64: 64 seeded notched tension instances, meshes "
+                                f"{min(sizes)}^2..{max(sizes)}^2 (sum {sum(s * s for s in sizes)} "
+                                f"elements), load steps {warm + 1}..{warm + steps} of 50"),
+                   "scheme": "S1", "precision": "mixed", "workers": args.workers,
+                   "march_rows": sorted(set(chosen))},
+        "one_by_one": {"value": upd_seq / t_seq / 1e9, "seconds": t_seq},
+        "batched_seconds": t_bat,
+        "speedup_batched_vs_one_by_one": t_seq / t_bat,
+        "identical_forces": same,
+    }
+
+
+def run_apply_sizes(pf, args):
+    """Fused FP32 tangent apply and CG vector update over mesh sizes."""
+    import workloads as W
+    out = []
+    for n in (512, 1024, 2048, 4096):
+        p = W.tension_panel(n=n, l=4.0 / n, du=6e-5, steps=1)
+        ctx = pf.Context(p, scheme=pf.ST, precision=pf.MIXED, max_stag=1, max_newton=1,
+                         max_cg=args.apply_iters)
+        ctx.set_profiling(True)
+        ctx.load_step(float(p.loads[0]))
+        la, ms_a, nodes = ctx.kernel_time(0)
+        lu, ms_u, _ = ctx.kernel_time(2)
+        ctx.close()
+        ta, tu = ms_a / max(la, 1), ms_u / max(lu, 1)
+        ba = fused_apply_bytes_per_node() * nodes
+        bu = update_bytes_per_node() * nodes
+        out.append({
+            "mesh": f"{n}x{n}", "nodes": nodes,
+            "apply_us": ta * 1e3, "apply_GBs": ba / (ta * 1e-3) / 1e9,
+            "apply_frac": ba / (ta * 1e-3) / 1e9 / HBM_PEAK_GBS, "apply_launches": la,
+            "update_us": tu * 1e3, "update_GBs": bu / (tu * 1e-3) / 1e9,
+            "update_frac": bu / (tu * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        })
+        log(f"  {n}^2: apply {ta * 1e3:.1f} us {out[-1]['apply_GBs']:.0f} GB/s, "
+            f"update {tu * 1e3:.1f} us {out[-1]['update_GBs']:.0f} GB/s")
+    big = out[-1]
+    return {
+        "metric": "fused FP32 tangent apply GB/s vs mesh size, 1 MI355X",
+        "value": big["apply_GBs"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "apply-sizes: notched tension panels 512^2..4096^2, one "
+                               f"displacement solve capped at {args.apply_iters} CG iterations"},
+        "roofline": {"bound": "hbm", "achieved": big["apply_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": big["apply_frac"], "traffic": None},
+        "sizes": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tension512")
+    ap.add_argument("--workload", default="tension512",
+                    choices=["tension512", "tension64", "sweep64", "apply-sizes"])
+    ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
+    ap.add_argument("--apply-iters", type=int, default=512,
+                    help="CG iterations per size in the apply-sizes mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-st", action="store_true", help="skip the ST FP64 comparison run")
     ap.add_argument("--full-history", action="store_true",
@@ -150,6 +270,12 @@ def main():
     import workloads as W
 
     pf.require_device()
+    if args.workload == "sweep64":
+        print(json.dumps(run_sweep(pf, args)))
+        return
+    if args.workload == "apply-sizes":
+        print(json.dumps(run_apply_sizes(pf, args)))
+        return
     problem = {"tension512": W.config_tension512, "tension64": W.config_tension64}[args.workload]()
     if args.full_history:
         args.warmup, args.steps = 0, len(problem.loads)

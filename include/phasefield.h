@@ -62,6 +62,9 @@ typedef enum { PF_SPLIT_VD = 0, PF_SPLIT_SPECTRAL = 1 } pf_split;
  * reaction force stay FP64. */
 typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
 
+/* Preconditioner of the linear solves: Jacobi, or Jacobi-Chebyshev (m
+ * Chebyshev steps on D^-1 A over [lambda_max/30, lambda_max], lambda_max from
+ * a power iteration once per context and solve kind, times 1.2). */
 typedef enum { PF_PC_JACOBI = 0, PF_PC_JACOBI_CHEBYSHEV = 1 } pf_precond;
 
 typedef struct {
@@ -82,7 +85,9 @@ typedef struct {
   int32_t scheme;       /* pf_scheme                                          */
   int32_t precision;    /* pf_precision                                       */
   int32_t precond;      /* pf_precond                                         */
-  int32_t cheb_degree;  /* Chebyshev degree for PF_PC_JACOBI_CHEBYSHEV        */
+  int32_t cheb_degree;  /* Chebyshev steps m (1..16) for PF_PC_JACOBI_CHEBYSHEV; odd
+                           m keeps the preconditioner SPD even if the
+                           estimated lambda_max is too low                   */
   double tol_stag;      /* staggered tolerance on ||R_d||/||b|| (Section 3.1) */
   double tol_pcg;       /* relative tolerance of each linear correction solve */
   double tol_newton;    /* Newton: ||R_u|| <= tol_newton * ||R_u(lifted)||    */
@@ -117,7 +122,7 @@ typedef struct {
   int32_t cg_not_converged; /* linear solves that hit max_cg                  */
 } pf_step_stats;
 
-/* Fill *opts with defaults: ST, FP64, Jacobi, tol_stag 1e-5, tol_pcg 1e-10,
+/* Fill *opts with defaults: ST, FP64, Jacobi (cheb_degree 3), tol_stag 1e-5, tol_pcg 1e-10,
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
  * march_rows 0. */
@@ -130,7 +135,25 @@ void pf_default_opts(pf_solver_opts *opts);
 pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat,
                     const pf_solver_opts *opts, void *hip_stream, pf_ctx **out);
 
+/* Release every device buffer (through the release callback when an
+ * allocator is installed) and the context itself. */
 pf_status pf_destroy(pf_ctx *ctx);
+
+/* Device-memory allocator for the context's buffers, e.g. a framework's
+ * caching allocator.  alloc(bytes, user) returns device memory on the
+ * context's device, aligned to 256 bytes, or NULL; release(ptr, user) takes
+ * it back.  The call moves every buffer the context already holds to memory
+ * from alloc (contents copied on the context's stream, then synchronised)
+ * and returns the old buffers to the previous allocator; later allocations
+ * and pf_destroy use the new pair.  Both NULL restores hipMalloc/hipFree.
+ * The callbacks and user must stay valid until pf_destroy or the next
+ * pf_set_allocator.  Captured CG batches are discarded and re-captured on
+ * first use.  Errors: PF_E_INVALID_ARG if exactly one callback is NULL,
+ * PF_E_STATE inside an open step, PF_E_OOM if alloc returns NULL or
+ * misaligned memory (the context then keeps its old buffers). */
+typedef void *(*pf_alloc_fn)(size_t bytes, void *user);
+typedef void (*pf_release_fn)(void *ptr, void *user);
+pf_status pf_set_allocator(pf_ctx *ctx, pf_alloc_fn alloc, pf_release_fn release, void *user);
 
 /* Displacement Dirichlet data of one group (0 <= group < 8).  Entry k fixes
  * component comp[k] (0 = x, 1 = y) of node node[k] to

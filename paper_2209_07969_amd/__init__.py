@@ -12,7 +12,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_double, c_int8, c_int32, c_int64, c_uint8, c_void_p
+from ctypes import (CFUNCTYPE, POINTER, c_double, c_int8, c_int32, c_int64, c_size_t, c_uint8,
+                    c_void_p)
 
 import numpy as np
 
@@ -29,8 +30,12 @@ EXPORTED = [
     "pf_get_state", "pf_set_state", "pf_status_string", "pf_last_error", "pf_free_dofs",
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
     "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create",
-    "pf_batch_load_step", "pf_batch_destroy", "pf_autotune",
+    "pf_batch_load_step", "pf_batch_destroy", "pf_autotune", "pf_set_allocator",
 ]
+
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+RELEASE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
 
 
 class MeshDesc(ctypes.Structure):
@@ -112,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.pf_batch_load_step.argtypes = [P, POINTER(c_double), POINTER(StepStats)]
     lib.pf_batch_destroy.argtypes = [P]
     lib.pf_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
+    lib.pf_set_allocator.argtypes = [P, ALLOC_FN, RELEASE_FN, P]
     lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_int64)]
     for name in EXPORTED:
@@ -289,6 +295,32 @@ class Context:
         ch = c_int32()
         self._check(self.lib.pf_autotune(self.h, int(reps), ctypes.byref(ch)), "pf_autotune")
         return ch.value
+
+    def use_torch_allocator(self):
+        """Move the context's device buffers into PyTorch's caching allocator
+        (blocks tied to the context's stream); pf_destroy returns them."""
+        import torch
+        dev = torch.cuda.current_device()
+        stream = int(self.stream or 0)
+
+        def alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except RuntimeError:
+                return None
+
+        def release(ptr, _user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (ALLOC_FN(alloc), RELEASE_FN(release))
+        self._check(self.lib.pf_set_allocator(self.h, cbs[0], cbs[1], None), "pf_set_allocator")
+        self._alloc_cbs = cbs      # must outlive the buffers
+
+    def use_default_allocator(self):
+        """Move the buffers back to hipMalloc memory."""
+        self._check(self.lib.pf_set_allocator(self.h, ALLOC_FN(), RELEASE_FN(), None),
+                    "pf_set_allocator")
+        self._alloc_cbs = None
 
     def set_profiling(self, enable=True):
         self._check(self.lib.pf_set_profiling(self.h, 1 if enable else 0), "pf_set_profiling")

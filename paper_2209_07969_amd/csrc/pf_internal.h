@@ -122,6 +122,19 @@ struct CgArgs {
   int ga, gb;
   double tol2;
   int maxit;
+  int ext;    // 1: z comes from an external preconditioner (Chebyshev), which
+              // also writes the (r.z, r.r) partials; the vector kernels then
+              // update only x and r
+  int npb;    // number of (r.z, r.r) partials the apply prologue reduces
+};
+
+// One Jacobi-Chebyshev step (z = p(D^-1 A) D^-1 r by Chebyshev iteration on
+// A y = r from y = 0): d_0 = D^-1 r / theta; d_k = c1 d_{k-1} + c2 D^-1 res_k;
+// y_{k+1} = y_k + d_k; res_{k+1} = res_k - A d_k.
+struct ChebStep {
+  double inv_theta;
+  double c1, c2;
+  int last;
 };
 
 // Operator coefficients passed by value.
@@ -163,6 +176,35 @@ template <class T>
 hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const T *coef, const uint8_t *eact, const uint8_t *nflag,
                           const T *z, const T *p_old, T *p_new, T *q, const CgArgs &ca);
+// Jacobi-Chebyshev preconditioner kernels (two-kernel CG, ext = 1).
+template <class T>
+hipError_t cheb_init(hipStream_t s, int n, const T *r, const T *Dinv, T *d0, T *z, T *res,
+                     const CgArgs &ca, const ChebStep &cs);
+template <class T>
+hipError_t tangent_cheb_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                             int split, const T *ulin, const T *d, const uint8_t *qflag,
+                             const uint8_t *eact, const uint8_t *nflag, const T *dprev, T *dnext,
+                             T *z, T *res, const T *r, const T *Dinv, const CgArgs &ca,
+                             const ChebStep &cs);
+template <class T>
+hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                           const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                           const T *dprev, T *dnext, T *z, T *res, const T *r, const T *Dinv,
+                           const CgArgs &ca, const ChebStep &cs);
+// Power iteration step for lambda_max(D^-1 A): vnext = D^-1 A (scale v);
+// scal[SC_NORM_A] = v'Av and scal[SC_NORM_B] = v'Dv (of the scaled v).
+template <class T>
+hipError_t tangent_power_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                              int split, const T *ulin, const T *d, const uint8_t *qflag,
+                              const uint8_t *eact, const uint8_t *nflag, const T *v, T *vnext,
+                              const T *Dinv, double scale, RedScratch rs);
+template <class T>
+hipError_t phase_power_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                            const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *v,
+                            T *vnext, const T *Dinv, double scale, RedScratch rs);
+template <class T>
+hipError_t power_start(hipStream_t s, int n, const T *Dinv, T *v);
+
 // Single-kernel CG iteration for the elasticity tangent / the phase operator.
 template <class T>
 hipError_t tangent_cg1(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,

@@ -968,15 +968,17 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
                                                  const T *Dinv, CgArgs ca) {
   double v[2] = {0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const T ri = r[i];
-    const T zi = Dinv[i] * ri;
     x[i] = T(0);
-    z[i] = zi;
     pold[i] = T(0);
-    v[0] += double(ri) * double(zi);
-    v[1] += double(ri) * double(ri);
+    if (!ca.ext) {
+      const T ri = r[i];
+      const T zi = Dinv[i] * ri;
+      z[i] = zi;
+      v[0] += double(ri) * double(zi);
+      v[1] += double(ri) * double(ri);
+    }
   }
-  block_partial<2>(v, ca.partB);
+  if (!ca.ext) block_partial<2>(v, ca.partB);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ca.st->b.rz_prev = 0.0;
     ca.st->b.rr0 = 0.0;
@@ -989,7 +991,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
 // Prologue of the apply kernels: returns done (uniform) and beta.
 __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
   double s[2];
-  block_sum<2>(ca.partB, ca.gb, s);
+  block_sum<2>(ca.partB, ca.npb, s);
   const double rz = s[0], rr = s[1];
   const int first = ca.st->b.first;
   const int iters = ca.st->b.iters;
@@ -1028,9 +1030,40 @@ __global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArg
   block_partial<1>(red, ca.partA);
 }
 
+// Elements per thread whose operands are loaded before the scalars.
+constexpr int kUpd = 4;
+
 template <class T>
-__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
-                                                   const T *q, const T *Dinv, CgArgs ca) {
+__device__ inline void upd_load(int n, int i0, int stride, const T *__restrict__ x,
+                                const T *__restrict__ p, const T *__restrict__ q,
+                                const T *__restrict__ r, const T *__restrict__ Dinv, bool ext,
+                                T (&xv)[kUpd], T (&pv)[kUpd], T (&qv)[kUpd], T (&rv)[kUpd],
+                                T (&dv)[kUpd]) {
+#pragma unroll
+  for (int k = 0; k < kUpd; ++k) {
+    const int i = i0 + k * stride;
+    xv[k] = pv[k] = qv[k] = rv[k] = dv[k] = T(0);
+    if (i < n) {
+      xv[k] = x[i];
+      pv[k] = p[i];
+      qv[k] = q[i];
+      rv[k] = r[i];
+      if (!ext) dv[k] = Dinv[i];
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *__restrict__ r,
+                                                   T *__restrict__ z, const T *__restrict__ p,
+                                                   const T *__restrict__ q,
+                                                   const T *__restrict__ Dinv, CgArgs ca) {
+  const int stride = gridDim.x * blockDim.x;
+  int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ext = ca.ext != 0;
+  // the first group's operands are in flight while the scalars are reduced
+  T xv[kUpd], pv[kUpd], qv[kUpd], rv[kUpd], dv[kUpd];
+  upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
   const int done = ca.st->a.done;
   const double rz = ca.st->a.rz;
   const double rr0 = ca.st->a.rr0;
@@ -1058,17 +1091,28 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, cons
   }
   const T alpha = T(rz / pq);
   double v[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const T xi = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    const T zi = Dinv[i] * ri;
-    x[i] = xi;
-    r[i] = ri;
-    z[i] = zi;
-    v[0] += double(ri) * double(zi);
-    v[1] += double(ri) * double(ri);
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < kUpd; ++k) {
+      const int i = i0 + k * stride;
+      if (i < n) {
+        const T xi = xv[k] + alpha * pv[k];
+        const T ri = rv[k] - alpha * qv[k];
+        x[i] = xi;
+        r[i] = ri;
+        if (!ext) {
+          const T zi = dv[k] * ri;
+          z[i] = zi;
+          v[0] += double(ri) * double(zi);
+          v[1] += double(ri) * double(ri);
+        }
+      }
+    }
+    i0 += kUpd * stride;
+    if (i0 >= n) break;
+    upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
   }
-  block_partial<2>(v, ca.partB);
+  if (!ext) block_partial<2>(v, ca.partB);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ca.st->b.rz_prev = rz;
     ca.st->b.rr0 = rr0;
@@ -1083,6 +1127,121 @@ int vec_blocks(int n) {
   if (b > kPMax) b = kPMax;
   if (b < 1) b = 1;
   return b;
+}
+
+// ------------------------------------------ Jacobi-Chebyshev and power
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cheb_init(int n, const T *r, const T *Dinv, T *d0, T *z,
+                                                   T *res, CgArgs ca, ChebStep cs) {
+  double v[2] = {0.0, 0.0};
+  const T it = T(cs.inv_theta);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T ri = r[i];
+    const T di = Dinv[i] * ri * it;
+    d0[i] = di;
+    z[i] = di;
+    res[i] = ri;
+    v[0] += double(ri) * double(di);
+    v[1] += double(ri) * double(ri);
+  }
+  if (cs.last) block_partial<2>(v, ca.partB);
+}
+
+// Chebyshev step on top of an operator op (its input vector is d_{k-1}).
+template <class Base>
+struct OpCheb {
+  using T = typename Base::T;
+  using Elem = typename Base::Elem;
+  using Node = typename Base::Node;
+  static constexpr int NF = Base::NF;
+  static constexpr int NR = 2;
+  Base base;
+  const T *r; const T *Dinv; T *dnext; T *z; T *res;
+  int N;
+  T c1, c2;
+  int last;
+  __device__ Node load(int i, int j) const { return base.load(i, j); }
+  __device__ void fin(Node &n) const { base.fin(n); }
+  __device__ Elem eload(int ie, int je) const { return base.eload(ie, je); }
+  static __device__ Node shfl_up(const Node &n) { return Base::shfl_up(n); }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          const Elem &e, T (&f)[NF][4]) const {
+    base.element(n0, n1, n2, n3, e, f);
+  }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+    const int k = i + j * (base.g.nx + 1);
+    T dp[NF];
+    base.get_u(n, dp);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int idx = k + q * N;
+      const T Ad = base.masked(k, q) ? T(0) : v[q];
+      const T rs = res[idx] - Ad;
+      const T dk = c1 * dp[q] + c2 * Dinv[idx] * rs;
+      const T y = z[idx] + dk;
+      res[idx] = rs;
+      dnext[idx] = dk;
+      z[idx] = y;
+      if (last) {
+        const T ri = r[idx];
+        red[0] += double(ri) * double(y);
+        red[1] += double(ri) * double(ri);
+      }
+    }
+  }
+};
+
+// Power-iteration step on D^-1 A: the input vector is scaled by `scale`.
+template <class Base>
+struct OpPower {
+  using T = typename Base::T;
+  using Elem = typename Base::Elem;
+  using Node = typename Base::Node;
+  static constexpr int NF = Base::NF;
+  static constexpr int NR = 2;
+  Base base;
+  const T *Dinv; T *vnext;
+  int N;
+  T scale;
+  __device__ Node load(int i, int j) const { return base.load(i, j); }
+  __device__ void fin(Node &n) const {
+    T u[NF];
+    base.get_u(n, u);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) u[q] *= scale;
+    base.set_u(n, u);
+  }
+  __device__ Elem eload(int ie, int je) const { return base.eload(ie, je); }
+  static __device__ Node shfl_up(const Node &n) { return Base::shfl_up(n); }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          const Elem &e, T (&f)[NF][4]) const {
+    base.element(n0, n1, n2, n3, e, f);
+  }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+    const int k = i + j * (base.g.nx + 1);
+    T vv[NF];
+    base.get_u(n, vv);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int idx = k + q * N;
+      const T di = Dinv[idx];
+      const T Av = base.masked(k, q) ? T(0) : v[q];
+      vnext[idx] = di * Av;
+      red[0] += double(vv[q]) * double(Av);
+      if (di > T(0)) red[1] += double(vv[q]) * double(vv[q]) / double(di);
+    }
+  }
+};
+
+template <class T>
+__global__ void k_power_start(int n, const T *Dinv, T *v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // deterministic start with components along every eigenvector
+  const unsigned h = (unsigned)i * 2654435761u;
+  const T w = T(0.5) + T((h >> 8) & 0xffff) * T(1.0 / 65536.0);
+  v[i] = Dinv[i] > T(0) ? w : T(0);
 }
 
 // --------------------------------------------------- single-kernel CG
@@ -1705,7 +1864,80 @@ CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, 
   ca.gb = vec_blocks(n);
   ca.tol2 = tol * tol;
   ca.maxit = maxit;
+  ca.ext = 0;
+  ca.npb = ca.gb;
   return ca;
+}
+
+template <class T>
+hipError_t cheb_init(hipStream_t s, int n, const T *r, const T *Dinv, T *d0, T *z, T *res,
+                     const CgArgs &ca, const ChebStep &cs) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cheb_init<T>), dim3(ca.gb), dim3(TPB), 0, s, n, r, Dinv,
+                     d0, z, res, ca, cs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_cheb_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                             int split, const T *ulin, const T *d, const uint8_t *qflag,
+                             const uint8_t *eact, const uint8_t *nflag, const T *dprev, T *dnext,
+                             T *z, T *res, const T *r, const T *Dinv, const CgArgs &ca,
+                             const ChebStep &cs) {
+  if (split == 1) {
+    using B = OpTangent<T, false, true, 1>;
+    OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), ulin},
+                 r, Dinv, dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+    return launch_march(s, op, g, m, ca.partB);
+  }
+  using B = OpTangent<T, false, true, 0>;
+  OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), nullptr},
+               r, Dinv, dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+  return launch_march(s, op, g, m, ca.partB);
+}
+
+template <class T>
+hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                           const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                           const T *dprev, T *dnext, T *z, T *res, const T *r, const T *Dinv,
+                           const CgArgs &ca, const ChebStep &cs) {
+  using B = OpPhase<T, false, true>;
+  OpCheb<B> op{B{g, c, coef, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0)}, r, Dinv,
+               dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+  return launch_march(s, op, g, m, ca.partB);
+}
+
+template <class T>
+hipError_t tangent_power_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                              int split, const T *ulin, const T *d, const uint8_t *qflag,
+                              const uint8_t *eact, const uint8_t *nflag, const T *v, T *vnext,
+                              const T *Dinv, double scale, RedScratch rs) {
+  if (split == 1) {
+    using B = OpTangent<T, false, true, 1>;
+    OpPower<B> op{B{g, c, d, qflag, eact, nflag, v, nullptr, nullptr, nullptr, T(0), ulin}, Dinv,
+                  vnext, g.N, T(scale)};
+    return launch_march_reduce<OpPower<B>, 2>(s, op, g, m, rs, SC_NORM_A);
+  }
+  using B = OpTangent<T, false, true, 0>;
+  OpPower<B> op{B{g, c, d, qflag, eact, nflag, v, nullptr, nullptr, nullptr, T(0), nullptr}, Dinv,
+                vnext, g.N, T(scale)};
+  return launch_march_reduce<OpPower<B>, 2>(s, op, g, m, rs, SC_NORM_A);
+}
+
+template <class T>
+hipError_t phase_power_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                            const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *v,
+                            T *vnext, const T *Dinv, double scale, RedScratch rs) {
+  using B = OpPhase<T, false, true>;
+  OpPower<B> op{B{g, c, coef, eact, nflag, v, nullptr, nullptr, nullptr, T(0)}, Dinv, vnext, g.N,
+                T(scale)};
+  return launch_march_reduce<OpPower<B>, 2>(s, op, g, m, rs, SC_NORM_A);
+}
+
+template <class T>
+hipError_t power_start(hipStream_t s, int n, const T *Dinv, T *v) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_power_start<T>), dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s,
+                     n, Dinv, v);
+  return hipGetLastError();
 }
 
 int cg1_blocks(const March &m) { return march_blocks(m); }
@@ -1923,6 +2155,26 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                         const PhaseCoef &, const T *, const uint8_t *,         \
                                         const uint8_t *, const T *, const T *, T *, T *,       \
                                         const CgArgs &);                                       \
+  template hipError_t cheb_init<T>(hipStream_t, int, const T *, const T *, T *, T *, T *,     \
+                                   const CgArgs &, const ChebStep &);                          \
+  template hipError_t tangent_cheb_step<T>(hipStream_t, const Grid &, const March &,           \
+                                           const ElasCoef &, int, const T *, const T *,        \
+                                           const uint8_t *, const uint8_t *, const uint8_t *,  \
+                                           const T *, T *, T *, T *, const T *, const T *,     \
+                                           const CgArgs &, const ChebStep &);                  \
+  template hipError_t phase_cheb_step<T>(hipStream_t, const Grid &, const March &,             \
+                                         const PhaseCoef &, const T *, const uint8_t *,        \
+                                         const uint8_t *, const T *, T *, T *, T *, const T *, \
+                                         const T *, const CgArgs &, const ChebStep &);         \
+  template hipError_t tangent_power_step<T>(hipStream_t, const Grid &, const March &,          \
+                                            const ElasCoef &, int, const T *, const T *,       \
+                                            const uint8_t *, const uint8_t *, const uint8_t *, \
+                                            const T *, T *, const T *, double, RedScratch);    \
+  template hipError_t phase_power_step<T>(hipStream_t, const Grid &, const March &,            \
+                                          const PhaseCoef &, const T *, const uint8_t *,       \
+                                          const uint8_t *, const T *, T *, const T *, double,  \
+                                          RedScratch);                                         \
+  template hipError_t power_start<T>(hipStream_t, int, const T *, T *);                        \
   template hipError_t tangent_cg1<T>(hipStream_t, const Grid &, const March &, const ElasCoef &, \
                                      int, const T *, const T *, const uint8_t *,               \
                                      const uint8_t *, const uint8_t *, const CgVecs<T> &,      \

@@ -34,6 +34,12 @@ struct Group {
   int n = 0;
 };
 
+struct Allocator {
+  pf_alloc_fn alloc = nullptr;
+  pf_release_fn release = nullptr;
+  void *user = nullptr;
+};
+
 // Work vectors of one precision.
 template <class T>
 struct CgBuf {
@@ -83,7 +89,14 @@ struct pf_ctx {
   Cg1State *cgs_h = nullptr;   // [2]
   double *scal_h = nullptr;
   unsigned long long *icount_h = nullptr;
-  std::vector<void *> allocs;
+  // every library-owned device buffer: the field that holds it and its size
+  struct Buf {
+    void **field;
+    size_t bytes;
+  };
+  std::vector<Buf> bufs;
+  // installed device allocator (null callbacks: hipMalloc / hipFree)
+  Allocator al{};
 
   // captured CG batches (hipGraph), keyed by solve kind and precision
   struct GraphEntry {
@@ -94,6 +107,9 @@ struct pf_ctx {
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;
   bool use_graphs = true;
+
+  // Jacobi-Chebyshev: lambda_max(D^-1 A) estimates per [kind][fp32]
+  double lmax[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 
   // sampled kernel timing
   bool profiling = false;
@@ -131,15 +147,34 @@ pf_status fail(pf_ctx *c, pf_status s, const std::string &msg) {
     if (s_ != PF_OK) return s_;     \
   } while (0)
 
+// Device memory from an installed allocator, or hipMalloc.
+hipError_t raw_alloc(const Allocator &al, void **p, size_t bytes) {
+  *p = nullptr;
+  if (!al.alloc) return hipMalloc(p, bytes);
+  void *v = al.alloc(bytes, al.user);
+  if (!v) return hipErrorOutOfMemory;
+  if (reinterpret_cast<uintptr_t>(v) % 256 != 0) {
+    al.release(v, al.user);
+    return hipErrorOutOfMemory;
+  }
+  *p = v;
+  return hipSuccess;
+}
+
+void raw_free(const Allocator &al, void *p) {
+  if (!p) return;
+  if (al.release) al.release(p, al.user);
+  else (void)hipFree(p);
+}
+
 template <class T>
 pf_status dalloc(pf_ctx *c, T **p, size_t count) {
   void *v = nullptr;
   size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-  hipError_t e = hipMalloc(&v, bytes);
-  if (e != hipSuccess) return fail(c, PF_E_OOM, "hipMalloc failed");
-  c->allocs.push_back(v);
+  if (raw_alloc(c->al, &v, bytes) != hipSuccess) return fail(c, PF_E_OOM, "device allocation failed");
+  c->bufs.push_back({reinterpret_cast<void **>(p), bytes});
   *p = static_cast<T *>(v);
-  e = fill_zero_bytes(c->stream, v, bytes);
+  hipError_t e = fill_zero_bytes(c->stream, v, bytes);
   if (e != hipSuccess) return fail(c, PF_E_HIP, "zero fill failed");
   return PF_OK;
 }
@@ -231,11 +266,18 @@ pf_status upload_constraints(pf_ctx *c) {
     if (gr.n == 0) continue;
     std::vector<int64_t> dof(gr.n);
     for (int k = 0; k < gr.n; ++k) dof[k] = gr.node[k] + (gr.comp[k] ? (int64_t)g.N : 0);
-    if (gr.d_dof) { (void)hipFree(gr.d_dof); gr.d_dof = nullptr; }
-    if (gr.d_comp) { (void)hipFree(gr.d_comp); gr.d_comp = nullptr; }
-    PF_HIP(c, hipMalloc(&gr.d_dof, gr.n * sizeof(int64_t)));
-    PF_HIP(c, hipMalloc(&gr.d_comp, gr.n));
     PF_TRY(sync(c));
+    raw_free(c->al, gr.d_dof);
+    raw_free(c->al, gr.d_comp);
+    gr.d_dof = nullptr;
+    gr.d_comp = nullptr;
+    void *vd = nullptr, *vc = nullptr;
+    if (raw_alloc(c->al, &vd, gr.n * sizeof(int64_t)) != hipSuccess)
+      return fail(c, PF_E_OOM, "device allocation failed");
+    gr.d_dof = static_cast<int64_t *>(vd);
+    if (raw_alloc(c->al, &vc, std::max(gr.n, 16)) != hipSuccess)
+      return fail(c, PF_E_OOM, "device allocation failed");
+    gr.d_comp = static_cast<int8_t *>(vc);
     PF_HIP(c, hipMemcpy(gr.d_dof, dof.data(), gr.n * sizeof(int64_t), hipMemcpyHostToDevice));
     PF_HIP(c, hipMemcpy(gr.d_comp, gr.comp.data(), gr.n, hipMemcpyHostToDevice));
   }
@@ -246,6 +288,10 @@ pf_status upload_constraints(pf_ctx *c) {
 
 enum Kind { K_ELASTIC = 0, K_PHASE = 1 };
 constexpr int kTimedRepeat = 4;
+// Jacobi-Chebyshev interval [lambda_max / kChebRatio, lambda_max] with
+// lambda_max = kChebSafety x the power-iteration estimate
+constexpr double kChebRatio = 30.0;
+constexpr double kChebSafety = 1.2;
 
 template <class T>
 CgBuf<T> &buf(pf_ctx *c);
@@ -328,9 +374,75 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter
 
 // ---- two-kernel CG (standard recurrences), used for the FP32 inner solves.
 // Buffers: x = X[0], r = R[0], z = W[0], p_old/p_new = P[0]/P[1], q = S[0].
+// lambda_max of D^-1 A by 20 power-iteration steps on the current operator
+// (Rayleigh quotient in the D inner product), once per solve kind and
+// precision; b.Dinv must be set.  Buffers R[1]/W[1] serve as scratch.
+template <class T>
+pf_status estimate_lmax(pf_ctx *c, Kind kind, double *out) {
+  CgBuf<T> &b = buf<T>(c);
+  const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
+  PF_HIP(c, power_start<T>(c->stream, n, b.Dinv, b.R[1]));
+  T *v = b.R[1], *vn = b.W[1];
+  double scale = 1.0, lam = 0.0;
+  for (int it = 0; it < 20; ++it) {
+    if (kind == K_ELASTIC) {
+      PF_HIP(c, tangent_power_step<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                      c->tflag, c->eact, c->nflag, v, vn, b.Dinv, scale, c->rs));
+    } else {
+      PF_HIP(c, phase_power_step<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, v,
+                                    vn, b.Dinv, scale, c->rs));
+    }
+    PF_TRY(read_scal(c));
+    const double A = c->scal_h[SC_NORM_A], B = c->scal_h[SC_NORM_B];
+    if (!(B > 0.0) || !(A > 0.0)) break;
+    lam = A / B;
+    scale = 1.0 / (lam * std::sqrt(B));
+    std::swap(v, vn);
+  }
+  *out = lam > 0.0 ? lam : 4.0;
+  return PF_OK;
+}
+
+// Chebyshev coefficients for degree m on [lmax / ratio, lmax]
+void cheb_steps(double lmax, int m, std::vector<ChebStep> *out) {
+  const double hi = lmax, lo = lmax / kChebRatio;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  out->clear();
+  double rho = 1.0 / sigma;
+  ChebStep s0{1.0 / theta, 0.0, 0.0, m == 1 ? 1 : 0};
+  out->push_back(s0);
+  for (int k = 1; k < m; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    ChebStep sk{1.0 / theta, rn * rho, 2.0 * rn / delta, k == m - 1 ? 1 : 0};
+    out->push_back(sk);
+    rho = rn;
+  }
+}
+
+// z = Chebyshev(r) (partials r.z, r.r from the last step)
+template <class T>
+pf_status enqueue_cheb(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n,
+                       const std::vector<ChebStep> &cs) {
+  CgBuf<T> &b = buf<T>(c);
+  T *D[2] = {b.R[1], b.W[1]};
+  PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], b.W[0], b.S[1], ca, cs[0]));
+  for (size_t k = 1; k < cs.size(); ++k) {
+    if (kind == K_ELASTIC) {
+      PF_HIP(c, tangent_cheb_step<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                                     c->eact, c->nflag, D[(k - 1) & 1], D[k & 1], b.W[0], b.S[1],
+                                     b.R[0], b.Dinv, ca, cs[k]));
+    } else {
+      PF_HIP(c, phase_cheb_step<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                   D[(k - 1) & 1], D[k & 1], b.W[0], b.S[1], b.R[0], b.Dinv, ca,
+                                   cs[k]));
+    }
+  }
+  return PF_OK;
+}
+
 template <class T>
 pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n, int iters,
-                         bool time_first) {
+                         bool time_first, const std::vector<ChebStep> *cs) {
   CgBuf<T> &b = buf<T>(c);
   T *pold = b.P[0], *pnew = b.P[1];
   for (int k = 0; k < iters; ++k) {
@@ -350,6 +462,7 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
     PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca));
     if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
+    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs));
     std::swap(pold, pnew);
   }
   return PF_OK;
@@ -359,23 +472,40 @@ template <class T>
 pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
   CgBuf<T> &b = buf<T>(c);
   const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
-  const CgArgs ca = cg_args(c->g, c->ms, n, c->cgs2, c->rs, tol, c->opts.max_cg);
+  CgArgs ca = cg_args(c->g, c->ms, n, c->cgs2, c->rs, tol, c->opts.max_cg);
+  const int fp32 = std::is_same<T, float>::value ? 1 : 0;
+  const bool cheb = c->opts.precond == PF_PC_JACOBI_CHEBYSHEV;
+  std::vector<ChebStep> cs;
+  if (cheb) {
+    double &lm = c->lmax[kind][fp32];
+    if (lm == 0.0) {
+      double est = 0.0;
+      PF_TRY(estimate_lmax<T>(c, kind, &est));
+      lm = kChebSafety * est;
+    }
+    cheb_steps(lm, std::max(1, c->opts.cheb_degree), &cs);
+    ca.ext = 1;
+    ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
+  }
   PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
+  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs));
   int batch = std::max(4, c->opts.cg_check);
   batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
   const bool timed = c->profiling;
   const int ngraph = timed ? batch - 2 : batch;
-  const int fp32 = std::is_same<T, float>::value ? 1 : 0;
+  const int variant = cheb ? 3 : 2;
   hipGraphExec_t ex = nullptr;
   if (c->use_graphs) {
     for (auto &e : c->graphs)
-      if (e.kind == kind && e.fp32 == fp32 && e.niter == ngraph && e.tol == tol && e.variant == 2)
+      if (e.kind == kind && e.fp32 == fp32 && e.niter == ngraph && e.tol == tol &&
+          e.variant == variant)
         ex = e.exec;
     if (!ex) {
       if (!c->cap_stream) PF_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       PF_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      pf_status s = enqueue_iters2<T>(c, c->cap_stream, kind, ca, n, ngraph, false);
+      pf_status s = enqueue_iters2<T>(c, c->cap_stream, kind, ca, n, ngraph, false,
+                                      cheb ? &cs : nullptr);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
       if (s != PF_OK) return s;
@@ -383,15 +513,15 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
       e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(c, PF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      c->graphs.push_back({kind, fp32, ngraph, 2, tol, ex});
+      c->graphs.push_back({kind, fp32, ngraph, variant, tol, ex});
     }
   }
   for (;;) {
-    if (timed) PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, 2, true));
+    if (timed) PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, 2, true, cheb ? &cs : nullptr));
     if (ex) {
       PF_HIP(c, hipGraphLaunch(ex, c->stream));
     } else {
-      PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, ngraph, false));
+      PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, ngraph, false, cheb ? &cs : nullptr));
     }
     PF_HIP(c, hipMemcpyAsync(c->cgs2_h, c->cgs2, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
     PF_TRY(sync(c));
@@ -419,7 +549,8 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
 // exit in their prologue.  *xout points to the solution buffer.
 template <class T>
 pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
-  if (std::is_same<T, float>::value) return pcg2<T>(c, kind, tol, iters, status, xout);
+  if (std::is_same<T, float>::value || c->opts.precond == PF_PC_JACOBI_CHEBYSHEV)
+    return pcg2<T>(c, kind, tol, iters, status, xout);
   CgBuf<T> &b = buf<T>(c);
   Cg1Args a;
   a.st = c->cgs;
@@ -723,7 +854,11 @@ pf_status commit(pf_ctx *c) {
 pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   if (o->scheme < 0 || o->scheme > 3) { *msg = "scheme"; return PF_E_INVALID_ARG; }
   if (o->precision < 0 || o->precision > 1) { *msg = "precision"; return PF_E_INVALID_ARG; }
-  if (o->precond != PF_PC_JACOBI) { *msg = "only the Jacobi preconditioner is available"; return PF_E_INVALID_ARG; }
+  if (o->precond != PF_PC_JACOBI && o->precond != PF_PC_JACOBI_CHEBYSHEV) { *msg = "precond"; return PF_E_INVALID_ARG; }
+  if (o->precond == PF_PC_JACOBI_CHEBYSHEV && (o->cheb_degree < 1 || o->cheb_degree > 16)) {
+    *msg = "cheb_degree must be in 1..16";
+    return PF_E_INVALID_ARG;
+  }
   if (!(o->tol_stag > 0) || !(o->tol_pcg > 0) || !(o->tol_newton > 0) || !(o->tol_inner > 0)) {
     *msg = "tolerances must be > 0";
     return PF_E_INVALID_ARG;
@@ -749,7 +884,7 @@ void pf_default_opts(pf_solver_opts *o) {
   o->scheme = PF_ST;
   o->precision = PF_FP64;
   o->precond = PF_PC_JACOBI;
-  o->cheb_degree = 4;
+  o->cheb_degree = 3;
   o->tol_stag = 1e-5;
   o->tol_pcg = 1e-10;
   o->tol_newton = 1e-9;
@@ -870,10 +1005,10 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
 pf_status pf_destroy(pf_ctx *c) {
   if (!c) return PF_OK;
   (void)hipStreamSynchronize(c->stream);
-  for (void *p : c->allocs) (void)hipFree(p);
+  for (auto &b : c->bufs) raw_free(c->al, *b.field);
   for (auto &gr : c->groups) {
-    if (gr.d_dof) (void)hipFree(gr.d_dof);
-    if (gr.d_comp) (void)hipFree(gr.d_comp);
+    raw_free(c->al, gr.d_dof);
+    raw_free(c->al, gr.d_comp);
   }
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -884,6 +1019,50 @@ pf_status pf_destroy(pf_ctx *c) {
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
   delete c;
+  return PF_OK;
+}
+
+pf_status pf_set_allocator(pf_ctx *c, pf_alloc_fn alloc, pf_release_fn release, void *user) {
+  if (!c) return PF_E_INVALID_ARG;
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(c, PF_E_INVALID_ARG, "allocator needs both callbacks or neither");
+  if (c->step_open) return fail(c, PF_E_STATE, "cannot move buffers inside a step");
+  PF_TRY(sync(c));
+  // every buffer to move: the registered ones, then the group DOF lists
+  std::vector<std::pair<void **, size_t>> moves;
+  for (auto &b : c->bufs) moves.push_back({b.field, b.bytes});
+  for (auto &gr : c->groups) {
+    if (gr.d_dof) moves.push_back({reinterpret_cast<void **>(&gr.d_dof), gr.n * sizeof(int64_t)});
+    if (gr.d_comp) moves.push_back({reinterpret_cast<void **>(&gr.d_comp),
+                                    (size_t)std::max(gr.n, 16)});
+  }
+  const Allocator nal{alloc, release, user};
+  std::vector<void *> fresh(moves.size(), nullptr);
+  for (size_t k = 0; k < moves.size(); ++k) {
+    if (raw_alloc(nal, &fresh[k], moves[k].second) != hipSuccess) {
+      for (size_t j = 0; j < k; ++j) raw_free(nal, fresh[j]);
+      return fail(c, PF_E_OOM, "allocator returned no (or misaligned) memory");
+    }
+  }
+  for (size_t k = 0; k < moves.size(); ++k) {
+    hipError_t e = hipMemcpyAsync(fresh[k], *moves[k].first, moves[k].second,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && k + 1 == moves.size()) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(c->stream);
+      for (void *v : fresh) raw_free(nal, v);
+      return fail(c, PF_E_HIP, std::string("buffer copy: ") + hipGetErrorString(e));
+    }
+  }
+  // captured graphs hold the old addresses
+  for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+  c->graphs.clear();
+  for (size_t k = 0; k < moves.size(); ++k) {
+    raw_free(c->al, *moves[k].first);
+    *moves[k].first = fresh[k];
+  }
+  c->bd.d = c->d;
+  c->al = nal;
   return PF_OK;
 }
 

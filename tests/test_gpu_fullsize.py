@@ -1,0 +1,158 @@
+"""Full-size checks (GPU): the configurations at their real mesh sizes, in the
+launch configuration the benchmark uses, checked on sampled outputs that the
+oracle computes one by one from the GPU's state:
+
+* H at sampled elements: max(H_prev, psi+(u, d)) from the oracle's point
+  functions (exact up to rounding);
+* the displacement residual at sampled free nodes and the phase residual at
+  sampled free phase nodes: each from an oracle mesh window of the 2x2
+  elements around the node (the node's row of the global residual is then
+  complete); the phase residual is bounded by TOL_ST * ||b|| (b global from
+  H), the displacement residual by 1e-7 of the largest nodal reaction;
+* the reaction force of the loaded edge: the oracle's internal force summed
+  over the loaded nodes, from the element rows that touch them.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly as asm
+from oracle.constitutive import Constitutive
+from oracle.fem import Mesh
+
+pytestmark = pytest.mark.gpu
+
+
+def window(p, u_soa, d, i0, j0, ni, nj):
+    """Oracle mesh over elements [i0, i0+ni) x [j0, j0+nj) with its node values."""
+    hx, hy = p.lx / p.nx, p.ly / p.ny
+    m = Mesh(ni, nj, ni * hx, nj * hy)
+    jj, ii = np.meshgrid(np.arange(j0, j0 + nj + 1), np.arange(i0, i0 + ni + 1), indexing="ij")
+    gid = (ii + jj * (p.nx + 1)).reshape(-1)
+    u = np.empty(2 * gid.size)
+    u[0::2] = u_soa[0][gid]
+    u[1::2] = u_soa[1][gid]
+    if p.elem_active is not None:
+        ej, ei = np.meshgrid(np.arange(j0, j0 + nj), np.arange(i0, i0 + ni), indexing="ij")
+        act = p.elem_active[(ei + ej * p.nx).reshape(-1)]
+        m = Mesh(ni, nj, ni * hx, nj * hy, act)
+    return m, u, d[gid], gid
+
+
+def run_gpu(pf, p, scheme, precision, steps):
+    ctx = pf.Context(p, scheme=scheme, precision=precision)
+    H_prev = None
+    st = None
+    for n in range(steps):
+        if n == steps - 1:
+            H_prev = ctx.get_state()[2].copy()
+        st = ctx.load_step(float(p.loads[n]))
+    u, d, H = ctx.get_state()
+    ctx.close()
+    return st, u, d, H, H_prev
+
+
+def check_state(p, st, u, d, H, H_prev, rng, n_samples=150):
+    cons = Constitutive(p.material.E, p.material.nu, p.material.split)
+    eta = p.material.eta
+    E = p.nx * p.ny
+    # --- H at sampled active elements
+    act = np.ones(E, bool) if p.elem_active is None else p.elem_active.astype(bool)
+    els = rng.choice(np.nonzero(act)[0], size=min(n_samples, int(act.sum())), replace=False)
+    for e in els:
+        i, j = e % p.nx, e // p.nx
+        m, uw, dw, _ = window(p, u, d, i, j, 1, 1)
+        psi = cons.parts(m.strain(uw))["psi_plus"][0]
+        Hexp = np.maximum(H_prev[:, e], psi)
+        np.testing.assert_allclose(H[:, e], Hexp, rtol=1e-10, atol=1e-12 * max(Hexp.max(), 1.0))
+    # --- global ||b(H)|| (phase right-hand side over free phase nodes)
+    mfull_b = np.zeros((p.ny + 1) * (p.nx + 1))
+    wdet = (p.lx / p.nx) * (p.ly / p.ny) / 4
+    ga = (1 + 1 / np.sqrt(3)) / 2
+    gb = (1 - 1 / np.sqrt(3)) / 2
+    Nq = np.array([[ga * ga, ga * gb, gb * gb, ga * gb], [ga * gb, ga * ga, ga * gb, gb * gb],
+                   [gb * gb, ga * gb, ga * ga, ga * gb], [ga * gb, gb * gb, ga * gb, ga * ga]])
+    ej, ei = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    n0 = (ei + ej * (p.nx + 1)).reshape(-1)
+    conn = np.stack([n0, n0 + 1, n0 + 2 + p.nx, n0 + 1 + p.nx], axis=1)
+    be = 2 * wdet * (H.T * act[:, None]) @ Nq          # [e, a] = sum_q 2 H_q N_a(q) w detJ
+    np.add.at(mfull_b, conn, be)
+    fixed_d = np.zeros_like(mfull_b, bool)
+    fixed_d[p.dir_d_nodes] = True
+    node_act = np.zeros_like(fixed_d)
+    node_act[conn[act].reshape(-1)] = True
+    fixed_d |= ~node_act
+    nb = np.linalg.norm(mfull_b[~fixed_d])
+    # --- local residuals at sampled interior free nodes
+    fixed_u = np.zeros((2, mfull_b.size), bool)
+    for grp in p.dir_u:
+        fixed_u[grp.comps.astype(int), grp.nodes] = True
+    fixed_u[:, ~node_act] = True
+    Rmax = 0.0
+    F_nodes = []
+    grp = p.dir_u[p.load_group]
+    # reaction from the element rows touching the loaded nodes
+    for node, comp in zip(grp.nodes, grp.comps):
+        i, j = node % (p.nx + 1), node // (p.nx + 1)
+        i0, j0 = max(i - 1, 0), max(j - 1, 0)
+        ni, nj = min(i + 1, p.nx) - i0, min(j + 1, p.ny) - j0
+        m, uw, dw, gid = window(p, u, d, i0, j0, ni, nj)
+        R = asm.internal_force(m, cons, uw, dw, eta)
+        loc = int(np.nonzero(gid == node)[0][0])
+        F_nodes.append(R[2 * loc + comp])
+    F_nodes = np.array(F_nodes)
+    comps = grp.comps.astype(int)
+    F = np.array([F_nodes[comps == 0].sum(), F_nodes[comps == 1].sum()])
+    np.testing.assert_allclose(st["force"], F, rtol=1e-9, atol=1e-9 * np.abs(F).max())
+    Rscale = np.abs(F_nodes).max()
+    kk = np.arange(mfull_b.size)
+    interior = kk[(kk % (p.nx + 1) > 0) & (kk % (p.nx + 1) < p.nx) & (kk // (p.nx + 1) > 0)
+                  & (kk // (p.nx + 1) < p.ny) & node_act]
+    nodes = rng.choice(interior, size=n_samples, replace=False)
+    for node in nodes:
+        i, j = node % (p.nx + 1), node // (p.nx + 1)
+        m, uw, dw, gid = window(p, u, d, i - 1, j - 1, 2, 2)
+        Ru = asm.internal_force(m, cons, uw, dw, eta)[8:10]     # center node = local 4
+        for c in range(2):
+            if not fixed_u[c, node]:
+                Rmax = max(Rmax, abs(Ru[c]))
+        if not fixed_d[node]:
+            ew = np.array([(i - 1) + (j - 1) * p.nx, i + (j - 1) * p.nx, (i - 1) + j * p.nx,
+                           i + j * p.nx])
+            if p.elem_active is not None:
+                ew = ew[p.elem_active[ew].astype(bool)]
+            Hw = H[:, ew].T
+            K = asm.phase_matrix(m, asm.at2_coefficient(Hw, p.material.Gc, p.material.l),
+                                 p.material.Gc, p.material.l)
+            b = asm.phase_rhs(m, Hw)
+            Rd = (K @ dw - b)[4]
+            assert abs(Rd) <= p.tol_stag * nb, (node, Rd, nb)
+    assert Rmax <= 1e-7 * Rscale, (Rmax, Rscale)
+
+
+def test_fullsize_tension512_s1_mixed(gpu_lib):
+    p = W.config_tension512()
+    st, u, d, H, Hp = run_gpu(gpu_lib, p, 1, 1, 3)
+    assert st["converged"] == 1
+    check_state(p, st, u, d, H, Hp, np.random.default_rng(512))
+
+
+def test_fullsize_tension512_st_fp64(gpu_lib):
+    p = W.config_tension512()
+    st, u, d, H, Hp = run_gpu(gpu_lib, p, 0, 0, 2)
+    assert st["converged"] == 1
+    check_state(p, st, u, d, H, Hp, np.random.default_rng(513))
+
+
+def test_fullsize_shear1024_spectral_s3_mixed(gpu_lib):
+    p = W.config_shear1024()
+    st, u, d, H, Hp = run_gpu(gpu_lib, p, 3, 1, 2)
+    assert st["converged"] == 1
+    check_state(p, st, u, d, H, Hp, np.random.default_rng(1024))
+
+
+def test_fullsize_lshape2048_s1_mixed(gpu_lib):
+    p = W.config_lshape2048()
+    st, u, d, H, Hp = run_gpu(gpu_lib, p, 1, 1, 2)
+    assert st["converged"] == 1
+    check_state(p, st, u, d, H, Hp, np.random.default_rng(2048), n_samples=100)

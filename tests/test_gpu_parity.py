@@ -112,6 +112,24 @@ def test_lshape_masked_history_fp64(gpu_lib, scheme):
     compare_history(gpu_lib, p, scheme, 0, 3, 1e-7)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chebyshev_preconditioner_history(gpu_lib, precision):
+    """Jacobi-Chebyshev preconditioned solves reach the same fixed points."""
+    p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=6)
+    orc = Oracle(p, 1)
+    ctx = gpu_lib.Context(p, scheme=1, precision=precision, precond=1, cheb_degree=3)
+    for lam in p.loads:
+        so = orc.load_step(float(lam))
+        sg = ctx.load_step(float(lam))
+        assert abs(so.n_stag - sg["n_stag"]) <= 1
+        assert abs(sg["force"][1] - so.force) <= 1e-4 * abs(so.force)
+        if so.n_stag == sg["n_stag"]:
+            u, d, H = ctx.get_state()
+            assert rel_l2(u, soa(orc.u)) <= (1e-7 if precision == 0 else 1e-6)
+            assert np.abs(d - orc.d).max() <= 1e-5
+    ctx.close()
+
+
 def test_ragged_panel_history_fp64(gpu_lib):
     """Non-square ragged mesh spanning several wave strips and chunks."""
     p = W.tension_panel(n=16, l=0.08, du=1e-3, steps=5)
