@@ -61,10 +61,11 @@ struct March {
 };
 
 // Scratch for block reductions.  Kernels that reduce run at most kPMax
-// blocks and write one partial per block and value.
-constexpr int kPMax = 512;
+// blocks (8 waves per SIMD at four waves per block) and write one partial
+// per block and value.
+constexpr int kPMax = 2048;
 struct RedScratch {
-  double *partR;               // [2 * kPMax]  residual-norm partials
+  double *partR;               // [4 * kPMax]  block partials
   unsigned long long *icount;  // [kICounters] integer counters (atomic adds)
   double *scal;                // [kScal]      finalised scalars
 };
@@ -162,9 +163,19 @@ CgArgs cg_args(const Grid &g, const March &m, int n, CgState *st, RedScratch rs,
 template <class T>
 hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
                    const CgArgs &ca);
+// First Chebyshev step fused into the CG update (Jacobi-Chebyshev only):
+// d0 = z = D^-1 r / theta and res = r; the partials r.z, r.r are written
+// when the polynomial has degree 1.  d0 == nullptr: no fused step.
+template <class T>
+struct ChebFuse {
+  T *d0;
+  T *res;
+  double inv_theta;
+  int last;
+};
 template <class T>
 hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, const CgArgs &ca);
+                     const T *Dinv, const CgArgs &ca, const ChebFuse<T> &cf);
 // split = 1 (spectral): the tangent is re-derived per QP from the
 // linearisation point ulin [2N] instead of the indicator bits.
 template <class T>

@@ -38,22 +38,63 @@ constexpr double GB = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
 constexpr int WPB = 4;                            // waves per block (march)
 constexpr int TPB = 256;
 
+// ------------------------------------------------------- lane shifts
+
+// Lane L receives lane L-1's value (lane 0 receives 0).  One DPP
+// whole-wavefront shift per 32-bit word: a plain VALU move, with no LDS
+// crossbar round trip as a general shuffle would need.
+constexpr int kDppWaveShr1 = 0x138;
+__device__ inline int lane_up_bits(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, kDppWaveShr1, 0xf, 0xf, false);
+}
+__device__ inline float lane_up(float x) {
+  return __int_as_float(lane_up_bits(__float_as_int(x)));
+}
+__device__ inline double lane_up(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = lane_up_bits(static_cast<int>(b));
+  const int hi = lane_up_bits(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
 // ------------------------------------------------------------ reductions
 
-// Block partial of NV sums: wave shuffles, then a fixed-order LDS sum by
+// DPP move of a double: lanes whose source lies outside the row (or whose
+// row is masked off by ROWS) receive 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_take(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf,
+                                             false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+// Sum over the wavefront, complete in lane 63: a shift-and-add scan within
+// each 16-lane row (shifts 1, 2, 4, 8), then row 0's total into row 1 and
+// row 2's into row 3 (row_bcast:15), then row 1's into rows 2-3
+// (row_bcast:31).  Fixed order, so every launch gives the same bits.
+__device__ inline double wave_sum_last(double x) {
+  x += dpp_take<0x111, 0xf>(x);
+  x += dpp_take<0x112, 0xf>(x);
+  x += dpp_take<0x114, 0xf>(x);
+  x += dpp_take<0x118, 0xf>(x);
+  x += dpp_take<0x142, 0xa>(x);
+  x += dpp_take<0x143, 0xc>(x);
+  return x;
+}
+
+// Block partial of NV sums: wave sums, then a fixed-order LDS sum by
 // thread 0, stored to part[k * kPMax + blockIdx.x].  All threads call it.
 template <int NV>
 __device__ inline void block_partial(double (&v)[NV], double *part) {
   __shared__ double sh[NV][TPB / 64];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    v[k] = x;
-  }
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_last(v[k]);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
+  if (lane == 63) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
   }
@@ -78,9 +119,8 @@ __device__ inline void block_sum(const double *part, int np, double (&out)[NV]) 
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
     for (int b = threadIdx.x; b < np; b += blockDim.x) s += part[k * kPMax + b];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
+    s = wave_sum_last(s);
+    if ((threadIdx.x & 63) == 63) sh[k][threadIdx.x >> 6] = s;
   }
   __syncthreads();
   const int nw = blockDim.x >> 6;
@@ -461,7 +501,7 @@ __device__ inline void item_compute(const Op &op, const Grid &g, const March &ms
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const T A = f[k][1] + c2[k];
-      const T Al = __shfl_up(A, 1, 64);
+      const T Al = lane_up(A);
       out[k] = f[k][0] + c3[k] + Al;
       c3[k] = f[k][3];
       c2[k] = f[k][2];
@@ -595,9 +635,9 @@ struct OpTangent {
     return e;
   }
   static __device__ Node shfl_up(const Node &n) {
-    return Node{__shfl_up(n.px, 1, 64), __shfl_up(n.py, 1, 64), __shfl_up(n.d, 1, 64), T(0),
-                T(0), SPL == 1 ? __shfl_up(n.lx, 1, 64) : T(0),
-                SPL == 1 ? __shfl_up(n.ly, 1, 64) : T(0)};
+    return Node{lane_up(n.px), lane_up(n.py), lane_up(n.d), T(0),
+                T(0), SPL == 1 ? lane_up(n.lx) : T(0),
+                SPL == 1 ? lane_up(n.ly) : T(0)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, T (&f)[2][4]) const {
@@ -676,7 +716,7 @@ struct OpPhase {
     }
     return e;
   }
-  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.p, 1, 64), T(0)}; }
+  static __device__ Node shfl_up(const Node &n) { return Node{lane_up(n.p), T(0)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, T (&f)[1][4]) const {
     if (!e.active) {
@@ -725,7 +765,7 @@ struct OpForce {
     return Elem{uint8_t(elem_exists(g, ie, je, eact) ? 1 : 0)};
   }
   static __device__ Node shfl_up(const Node &n) {
-    return Node{__shfl_up(n.ux, 1, 64), __shfl_up(n.uy, 1, 64), __shfl_up(n.d, 1, 64)};
+    return Node{lane_up(n.ux), lane_up(n.uy), lane_up(n.d)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, double (&f)[2][4]) const {
@@ -784,7 +824,7 @@ struct OpPhaseRes {
     }
     return e;
   }
-  static __device__ Node shfl_up(const Node &n) { return Node{__shfl_up(n.d, 1, 64)}; }
+  static __device__ Node shfl_up(const Node &n) { return Node{lane_up(n.d)}; }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, double (&f)[2][4]) const {
     if (!e.active) {
@@ -849,8 +889,8 @@ struct OpTangentDiag {
     return e;
   }
   static __device__ Node shfl_up(const Node &n) {
-    return Node{__shfl_up(n.d, 1, 64), SPL == 1 ? __shfl_up(n.lx, 1, 64) : T(0),
-                SPL == 1 ? __shfl_up(n.ly, 1, 64) : T(0)};
+    return Node{lane_up(n.d), SPL == 1 ? lane_up(n.lx) : T(0),
+                SPL == 1 ? lane_up(n.ly) : T(0)};
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, T (&f)[2][4]) const {
@@ -1057,10 +1097,15 @@ template <class T>
 __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *__restrict__ r,
                                                    T *__restrict__ z, const T *__restrict__ p,
                                                    const T *__restrict__ q,
-                                                   const T *__restrict__ Dinv, CgArgs ca) {
+                                                   const T *__restrict__ Dinv, CgArgs ca,
+                                                   ChebFuse<T> cf) {
   const int stride = gridDim.x * blockDim.x;
   int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ext = ca.ext != 0;
+  // ext: the preconditioner runs elsewhere; fused: its first step is here
+  const bool fused = cf.d0 != nullptr;
+  const bool ext = ca.ext != 0 && !fused;
+  const bool parts = !ext && (!fused || cf.last);
+  const T it = T(cf.inv_theta);
   // the first group's operands are in flight while the scalars are reduced
   T xv[kUpd], pv[kUpd], qv[kUpd], rv[kUpd], dv[kUpd];
   upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
@@ -1068,39 +1113,48 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *
   const double rz = ca.st->a.rz;
   const double rr0 = ca.st->a.rr0;
   const int iters = ca.st->a.iters;
-  if (done != 0) {
+  int exitc = done;
+  double pq = 0.0;
+  if (exitc == 0) {
+    double pqs[1];
+    block_sum<1>(ca.partA, ca.ga, pqs);
+    pq = pqs[0];
+    if (!(pq > 0.0)) exitc = 2;
+  }
+  if (exitc != 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ca.st->b.done = done;
+      ca.st->b.done = exitc;
       ca.st->b.iters = iters;
       ca.st->b.rr0 = rr0;
       ca.st->b.first = 0;
     }
-    return;
+    // a fused Chebyshev step still runs on the unchanged r, as it would
+    // in a kernel of its own
+    if (!fused) return;
   }
-  double pqs[1];
-  block_sum<1>(ca.partA, ca.ga, pqs);
-  const double pq = pqs[0];
-  if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ca.st->b.done = 2;
-      ca.st->b.iters = iters;
-      ca.st->b.rr0 = rr0;
-      ca.st->b.first = 0;
-    }
-    return;
-  }
-  const T alpha = T(rz / pq);
+  const bool act = exitc == 0;
+  const T alpha = act ? T(rz / pq) : T(0);
   double v[2] = {0.0, 0.0};
   for (;;) {
 #pragma unroll
     for (int k = 0; k < kUpd; ++k) {
       const int i = i0 + k * stride;
       if (i < n) {
-        const T xi = xv[k] + alpha * pv[k];
-        const T ri = rv[k] - alpha * qv[k];
-        x[i] = xi;
-        r[i] = ri;
-        if (!ext) {
+        T ri = rv[k];
+        if (act) {
+          const T xi = xv[k] + alpha * pv[k];
+          ri = rv[k] - alpha * qv[k];
+          x[i] = xi;
+          r[i] = ri;
+        }
+        if (fused) {
+          const T zi = dv[k] * ri * it;
+          cf.d0[i] = zi;
+          z[i] = zi;
+          cf.res[i] = ri;
+          v[0] += double(ri) * double(zi);
+          v[1] += double(ri) * double(ri);
+        } else if (!ext) {
           const T zi = dv[k] * ri;
           z[i] = zi;
           v[0] += double(ri) * double(zi);
@@ -1112,8 +1166,8 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *
     if (i0 >= n) break;
     upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
   }
-  if (!ext) block_partial<2>(v, ca.partB);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (parts) block_partial<2>(v, ca.partB);
+  if (act && blockIdx.x == 0 && threadIdx.x == 0) {
     ca.st->b.rz_prev = rz;
     ca.st->b.rr0 = rr0;
     ca.st->b.done = 0;
@@ -1396,11 +1450,11 @@ __device__ inline void cg1_compute(const Op &op, const Grid &g, const March &ms,
     T rl[NC], sl[NC], ul[NC], rol[NC], dil[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      rl[q] = __shfl_up(rn[r][q], 1, 64);
-      sl[q] = __shfl_up(sn[r][q], 1, 64);
-      ul[q] = __shfl_up(u[r][q], 1, 64);
-      rol[q] = __shfl_up(it.r[r][q], 1, 64);
-      dil[q] = __shfl_up(it.di[r][q], 1, 64);
+      rl[q] = lane_up(rn[r][q]);
+      sl[q] = lane_up(sn[r][q]);
+      ul[q] = lane_up(u[r][q]);
+      rol[q] = lane_up(it.r[r][q]);
+      dil[q] = lane_up(it.di[r][q]);
     }
     const int j = j0 - 1 + r;
     if (own_col && j <= g.ny) {
@@ -1447,7 +1501,7 @@ __device__ inline void cg1_compute(const Op &op, const Grid &g, const March &ms,
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const T A = f[q][1] + c2[q];
-      const T Al = __shfl_up(A, 1, 64);
+      const T Al = lane_up(A);
       out[q] = f[q][0] + c3[q] + Al;
       c3[q] = f[q][3];
       c2[q] = f[q][2];
@@ -1780,8 +1834,8 @@ March march_shape(const Grid &g, int ch_override) {
   m.nstrips = (g.nx + 1 + CSTRIP - 1) / CSTRIP;
   int ch = ch_override;
   if (ch != 2 && ch != 4 && ch != 8) {
-    // smallest chunk that fits one work item per wave of a full launch
-    const long long waves = (long long)kPMax * WPB;
+    // smallest chunk that gives at most two work items per SIMD
+    const long long waves = 2LL * 4 * 256;
     ch = 8;
     for (int c : {2, 4}) {
       if ((long long)m.nstrips * ((g.ny + 1 + c - 1) / c) <= waves) {
@@ -1811,9 +1865,9 @@ hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Di
 
 template <class T>
 hipError_t cg_update(hipStream_t s, int n, T *x, T *r, T *z, const T *p, const T *q,
-                     const T *Dinv, const CgArgs &ca) {
+                     const T *Dinv, const CgArgs &ca, const ChebFuse<T> &cf) {
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<T>), dim3(ca.gb), dim3(TPB), 0, s, n, x, r, z,
-                     p, q, Dinv, ca);
+                     p, q, Dinv, ca, cf);
   return hipGetLastError();
 }
 
@@ -2146,7 +2200,7 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
   template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *,             \
                                  const CgArgs &);                                              \
   template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
-                                   const T *, const CgArgs &);                                 \
+                                   const T *, const CgArgs &, const ChebFuse<T> &);            \
   template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \
                                           const ElasCoef &, int, const T *, const T *,         \
                                           const uint8_t *, const uint8_t *, const uint8_t *,   \

@@ -422,10 +422,11 @@ void cheb_steps(double lmax, int m, std::vector<ChebStep> *out) {
 // z = Chebyshev(r) (partials r.z, r.r from the last step)
 template <class T>
 pf_status enqueue_cheb(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n,
-                       const std::vector<ChebStep> &cs) {
+                       const std::vector<ChebStep> &cs, bool first_done) {
   CgBuf<T> &b = buf<T>(c);
   T *D[2] = {b.R[1], b.W[1]};
-  PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], b.W[0], b.S[1], ca, cs[0]));
+  if (!first_done)
+    PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], b.W[0], b.S[1], ca, cs[0]));
   for (size_t k = 1; k < cs.size(); ++k) {
     if (kind == K_ELASTIC) {
       PF_HIP(c, tangent_cheb_step<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
@@ -460,9 +461,12 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
       }
     }
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
-    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca));
+    // Jacobi-Chebyshev: the update also takes the polynomial's first step
+    ChebFuse<T> cf{nullptr, nullptr, 0.0, 0};
+    if (cs) cf = ChebFuse<T>{b.R[1], b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
+    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca, cf));
     if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
-    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs));
+    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, true));
     std::swap(pold, pnew);
   }
   return PF_OK;
@@ -488,7 +492,7 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
   PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
-  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs));
+  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, false));
   int batch = std::max(4, c->opts.cg_check);
   batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
