@@ -22,8 +22,9 @@ Two further modes print their own single JSON line:
   --workload sweep64     the seeded 64-instance tension sweep (mesh sizes
                          128..512, Gc, l and notch drawn per instance), S1
                          mixed with autotuned work items: load steps W+1..W+K
-                         of every instance, batched (members on their own
-                         streams, host worker pool) against one by one;
+                         of every instance, batched with shared CG launches
+                         (value), batched on concurrent streams, and one by
+                         one;
   --workload apply-sizes the FP32 fused tangent apply and the CG vector
                          update at 512^2 .. 4096^2 (one displacement solve of
                          a notched panel, CG capped), against the HBM peak.
@@ -166,24 +167,31 @@ def run_sweep(pf, args):
         ctx.close()
         if (i + 1) % 16 == 0:
             log(f"  one by one: {i + 1}/64 instances, {t_seq:.1f} s timed")
-    # batched: members on their own streams, same work-item heights
-    streams = [torch.cuda.Stream() for _ in probs]
-    ctxs = [pf.Context(p, scheme=pf.S1, precision=pf.MIXED, stream=st.cuda_stream,
-                       march_rows=ch) for p, st, ch in zip(probs, streams, chosen)]
-    B = pf.Batch(ctxs, workers=args.workers)
-    for n in range(warm):
-        B.load_step([float(p.loads[n]) for p in probs])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rows_b = [B.load_step([float(p.loads[n]) for p in probs]) for n in range(warm, warm + steps)]
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
-    upd_bat = sum(r["dof_updates"] for rows in rows_b for r in rows)
-    same = all(rows_b[k][i]["force"] == forces_seq[i][k]
-               for i in range(len(probs)) for k in range(steps))
-    B.close()
-    for c in ctxs:
-        c.close()
+    # batched, both modes: members on their own streams, same work-item heights
+    def batched(shared):
+        streams = [torch.cuda.Stream() for _ in probs]
+        ctxs = [pf.Context(p, scheme=pf.S1, precision=pf.MIXED, stream=st.cuda_stream,
+                           march_rows=ch) for p, st, ch in zip(probs, streams, chosen)]
+        B = pf.Batch(ctxs, workers=args.workers, shared=shared)
+        for n in range(warm):
+            B.load_step([float(p.loads[n]) for p in probs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = [B.load_step([float(p.loads[n]) for p in probs])
+                for n in range(warm, warm + steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        B.close()
+        for c in ctxs:
+            c.close()
+        upd = sum(r["dof_updates"] for rr in rows for r in rr)
+        same = all(rows[k][i]["force"] == forces_seq[i][k]
+                   for i in range(len(probs)) for k in range(steps))
+        log(f"  batched ({'shared launches' if shared else 'concurrent streams'}): {t:.2f} s, "
+            f"identical to one by one: {same}")
+        return t, upd, same
+    t_str, upd_str, same_str = batched(False)
+    t_bat, upd_bat, same = batched(True)
     sizes = [p.nx for p in probs]
     value = upd_bat / t_bat / 1e9
     return {
@@ -197,6 +205,8 @@ def run_sweep(pf, args):
                    "scheme": "S1", "precision": "mixed", "workers": args.workers,
                    "march_rows": sorted(set(chosen))},
         "one_by_one": {"value": upd_seq / t_seq / 1e9, "seconds": t_seq},
+        "concurrent_streams": {"value": upd_str / t_str / 1e9, "seconds": t_str,
+                               "identical_forces": same_str},
         "batched_seconds": t_bat,
         "speedup_batched_vs_one_by_one": t_seq / t_bat,
         "identical_forces": same,

@@ -204,15 +204,25 @@ const char *pf_last_error(const pf_ctx *ctx);
 pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
 
 /* ---------------------------------------------------------------------------
- * Batched sweeps: many independent problems advanced together.  Each member
- * context should have its own HIP stream (pf_create's hip_stream); a pool of
- * `workers` host threads (0 = 4) runs pf_load_step on the members, so the
- * kernels of different members execute concurrently on the GPU.  Results are
- * identical to stepping the members one by one (every kernel is
- * deterministic).  The batch borrows its members: destroy it first.
+ * Batched sweeps: many independent problems advanced together (a parameter
+ * sweep of uneven instances).  Each member context should have its own HIP
+ * stream (pf_create's hip_stream).  Two modes:
+ *  - shared launches (default): one host thread per member runs its load
+ *    step; its FP32 Jacobi CG solves (mixed precision) are queued, and once
+ *    every member still inside its step is waiting, all queued systems are
+ *    iterated together: per CG iteration one apply launch per (operator,
+ *    split, work-item height) and one update launch, over a table of the
+ *    systems, each keeping the blocks it would have on its own.  Other
+ *    solves (FP64, Jacobi-Chebyshev) run on the member's stream.
+ *  - concurrent streams: a pool of `workers` host threads (0 = 4) runs the
+ *    members' steps, whose kernels overlap on the GPU.
+ * Results are bit-identical to stepping the members one by one in either
+ * mode.  The batch borrows its members: destroy it first.
  * ------------------------------------------------------------------------- */
 typedef struct pf_batch pf_batch;
 pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out);
+/* enable = 1: shared launches (default); 0: concurrent streams. */
+pf_status pf_batch_set_shared_launches(pf_batch *b, int32_t enable);
 /* load_factors[n], stats[n] (may be NULL).  Returns PF_OK, or
  * PF_E_NOT_CONVERGED if any member did not converge (all members are still
  * committed), or the first error of a member. */

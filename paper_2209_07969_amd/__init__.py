@@ -31,6 +31,7 @@ EXPORTED = [
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
     "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create",
     "pf_batch_load_step", "pf_batch_destroy", "pf_autotune", "pf_set_allocator",
+    "pf_batch_set_shared_launches",
 ]
 
 
@@ -116,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.pf_batch_create.argtypes = [c_int32, POINTER(P), c_int32, POINTER(P)]
     lib.pf_batch_load_step.argtypes = [P, POINTER(c_double), POINTER(StepStats)]
     lib.pf_batch_destroy.argtypes = [P]
+    lib.pf_batch_set_shared_launches.argtypes = [P, c_int32]
     lib.pf_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
     lib.pf_set_allocator.argtypes = [P, ALLOC_FN, RELEASE_FN, P]
     lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
@@ -362,9 +364,11 @@ class Context:
 
 class Batch:
     """Several contexts advanced together (each should own a HIP stream, e.g.
-    Context(..., stream=torch.cuda.Stream().cuda_stream))."""
+    Context(..., stream=torch.cuda.Stream().cuda_stream)).  shared=True runs
+    the members' FP32 Jacobi CG solves through shared launches; False runs the
+    members concurrently on their streams from `workers` host threads."""
 
-    def __init__(self, contexts, workers=4):
+    def __init__(self, contexts, workers=4, shared=True):
         self.lib = load_library()
         self.members = list(contexts)
         arr = (c_void_p * len(self.members))(*[c.h for c in self.members])
@@ -373,6 +377,9 @@ class Batch:
         if st != 0:
             raise PhaseFieldError(st, "pf_batch_create failed")
         self.h = h
+        st = self.lib.pf_batch_set_shared_launches(h, 1 if shared else 0)
+        if st != 0:
+            raise PhaseFieldError(st, "pf_batch_set_shared_launches failed")
 
     def load_step(self, load_factors, allow_not_converged=True):
         n = len(self.members)

@@ -163,6 +163,42 @@ CgArgs cg_args(const Grid &g, const March &m, int n, CgState *st, RedScratch rs,
 template <class T>
 hipError_t cg_init(hipStream_t s, int n, T *x, T *r, T *z, T *p_old, const T *Dinv,
                    const CgArgs &ca);
+// ---- batched CG: the systems of many contexts advanced by shared launches.
+// Every system keeps the blocks it has in a launch of its own (same work
+// items, same partial slots, so its results are bit-identical); bmap[b] is
+// the table entry of block b of a shared launch and entry.b0 its first block.
+constexpr int kBatchEntryBytes = 512;   // stride of an apply-table entry
+template <class T>
+struct BatchUpdateEntry {
+  T *x, *r, *z;
+  const T *p, *q, *Dinv;
+  CgArgs ca;
+  int n, b0, nb;
+  int *status;   // [2]: done and iteration count after this update
+};
+// Apply-table entry of one system (written to dst, kBatchEntryBytes bytes),
+// with the operands of tangent_cg_apply / phase_cg_apply.
+template <class T>
+void tangent_batch_entry(void *dst, const Grid &g, const March &m, const ElasCoef &c, int split,
+                         const T *ulin, const T *d, const uint8_t *qflag, const uint8_t *eact,
+                         const uint8_t *nflag, const T *z, const T *p_old, T *p_new, T *q,
+                         const CgArgs &ca, int b0, int nb);
+template <class T>
+void phase_batch_entry(void *dst, const Grid &g, const March &m, const PhaseCoef &c,
+                       const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
+                       const T *p_old, T *p_new, T *q, const CgArgs &ca, int b0, int nb);
+// Shared launches: one apply over the entries of one (operator, split, work
+// item height), one update over any entries.
+template <class T>
+hipError_t tangent_cg_apply_batch(hipStream_t s, int split, int ch, const void *tab,
+                                  const int *bmap, int nblocks);
+template <class T>
+hipError_t phase_cg_apply_batch(hipStream_t s, int ch, const void *tab, const int *bmap,
+                                int nblocks);
+template <class T>
+hipError_t cg_update_batch(hipStream_t s, const BatchUpdateEntry<T> *tab, const int *bmap,
+                           int nblocks);
+
 // First Chebyshev step fused into the CG update (Jacobi-Chebyshev only):
 // d0 = z = D^-1 r / theta and res = r; the partials r.z, r.r are written
 // when the polynomial has degree 1.  d0 == nullptr: no fused step.

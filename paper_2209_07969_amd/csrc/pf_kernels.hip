@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 namespace pf {
 namespace {
 
@@ -87,9 +89,9 @@ __device__ inline double wave_sum_last(double x) {
 }
 
 // Block partial of NV sums: wave sums, then a fixed-order LDS sum by
-// thread 0, stored to part[k * kPMax + blockIdx.x].  All threads call it.
+// thread 0, stored to part[k * kPMax + bid].  All threads call it.
 template <int NV>
-__device__ inline void block_partial(double (&v)[NV], double *part) {
+__device__ inline void block_partial_at(double (&v)[NV], double *part, int bid) {
   __shared__ double sh[NV][TPB / 64];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = wave_sum_last(v[k]);
@@ -105,9 +107,14 @@ __device__ inline void block_partial(double (&v)[NV], double *part) {
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += sh[k][w];
-      part[k * kPMax + blockIdx.x] = s;
+      part[k * kPMax + bid] = s;
     }
   }
+}
+
+template <int NV>
+__device__ inline void block_partial(double (&v)[NV], double *part) {
+  block_partial_at<NV>(v, part, blockIdx.x);
 }
 
 // Fixed-order sum of np partials written by an earlier kernel, returned in
@@ -527,10 +534,10 @@ __device__ inline int xcd_block(int b, int nb) {
 
 template <int CH, class Op>
 __device__ inline void march_items(const Op &op, const Grid &g, const March &ms, int wfirst,
-                                   double *red) {
+                                   int wstride, double *red) {
   const int lane = threadIdx.x & 63;
   const int nw = ms.nstrips * ms.nchunks;
-  for (int w = wfirst; w < nw; w += gridDim.x * WPB) {
+  for (int w = wfirst; w < nw; w += wstride) {
     Item<CH, Op> it;
     item_load<CH>(op, g, ms, w, lane, it);
     item_compute<CH>(op, g, ms, w, lane, it, red);
@@ -544,7 +551,8 @@ __global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms, double *
   double red[NRR];
 #pragma unroll
   for (int k = 0; k < NRR; ++k) red[k] = 0.0;
-  march_items<CH>(op, g, ms, xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6), red);
+  march_items<CH>(op, g, ms, xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6),
+                  gridDim.x * WPB, red);
   if (Op::NR > 0) block_partial<NRR>(red, part);
 }
 
@@ -1029,7 +1037,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
 }
 
 // Prologue of the apply kernels: returns done (uniform) and beta.
-__device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
+__device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta, int bid) {
   double s[2];
   block_sum<2>(ca.partB, ca.npb, s);
   const double rz = s[0], rr = s[1];
@@ -1042,7 +1050,7 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
     else if (rr <= ca.tol2 * rr0) done = 1;
     else if (iters >= ca.maxit) done = 3;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     ca.st->a.rz = rz;
     ca.st->a.rr = rr;
     ca.st->a.rr0 = rr0;
@@ -1053,21 +1061,28 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta) {
   return done;
 }
 
+// Block bid of nb of the apply A_k (one CG system).
 template <int CH, class Op>
-__global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+__device__ inline void cg_apply_run(Op op, const Grid &g, const March &ms, const CgArgs &ca,
+                                    int bid, int nb) {
   const int lane = threadIdx.x & 63;
-  const int w0 = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
+  const int w0 = xcd_block(bid, nb) * WPB + (threadIdx.x >> 6);
   const int nw = ms.nstrips * ms.nchunks;
   // issue the first work item's loads before the prologue's reduction
   Item<CH, Op> it;
   if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
   double beta = 0.0;
-  if (cg_apply_prologue(ca, &beta) != 0) return;
+  if (cg_apply_prologue(ca, &beta, bid) != 0) return;
   op.beta = typename Op::T(beta);
   double red[1] = {0.0};
   if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
-  march_items<CH>(op, g, ms, w0 + gridDim.x * WPB, red);
-  block_partial<1>(red, ca.partA);
+  march_items<CH>(op, g, ms, w0 + nb * WPB, nb * WPB, red);
+  block_partial_at<1>(red, ca.partA, bid);
+}
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArgs ca) {
+  cg_apply_run<CH>(op, g, ms, ca, blockIdx.x, gridDim.x);
 }
 
 // Elements per thread whose operands are loaded before the scalars.
@@ -1093,14 +1108,14 @@ __device__ inline void upd_load(int n, int i0, int stride, const T *__restrict__
   }
 }
 
+// Block bid of nb of the update B_k (one CG system).
 template <class T>
-__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *__restrict__ r,
-                                                   T *__restrict__ z, const T *__restrict__ p,
-                                                   const T *__restrict__ q,
-                                                   const T *__restrict__ Dinv, CgArgs ca,
-                                                   ChebFuse<T> cf) {
-  const int stride = gridDim.x * blockDim.x;
-  int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void cg_update_run(int n, T *__restrict__ x, T *__restrict__ r,
+                                     T *__restrict__ z, const T *__restrict__ p,
+                                     const T *__restrict__ q, const T *__restrict__ Dinv,
+                                     const CgArgs &ca, const ChebFuse<T> &cf, int bid, int nb) {
+  const int stride = nb * blockDim.x;
+  int i0 = bid * blockDim.x + threadIdx.x;
   // ext: the preconditioner runs elsewhere; fused: its first step is here
   const bool fused = cf.d0 != nullptr;
   const bool ext = ca.ext != 0 && !fused;
@@ -1122,7 +1137,7 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *
     if (!(pq > 0.0)) exitc = 2;
   }
   if (exitc != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       ca.st->b.done = exitc;
       ca.st->b.iters = iters;
       ca.st->b.rr0 = rr0;
@@ -1166,13 +1181,52 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int n, T *__restrict__ x, T *
     if (i0 >= n) break;
     upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
   }
-  if (parts) block_partial<2>(v, ca.partB);
-  if (act && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (parts) block_partial_at<2>(v, ca.partB, bid);
+  if (act && bid == 0 && threadIdx.x == 0) {
     ca.st->b.rz_prev = rz;
     ca.st->b.rr0 = rr0;
     ca.st->b.done = 0;
     ca.st->b.iters = iters + 1;
     ca.st->b.first = 0;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_update(int n, T *x, T *r, T *z, const T *p,
+                                                   const T *q, const T *Dinv, CgArgs ca,
+                                                   ChebFuse<T> cf) {
+  cg_update_run<T>(n, x, r, z, p, q, Dinv, ca, cf, blockIdx.x, gridDim.x);
+}
+
+// Shared launches of many CG systems (see BatchUpdateEntry).
+template <class Op>
+struct BatchApplyEntry {
+  Op op;
+  Grid g;
+  March ms;
+  CgArgs ca;
+  int b0, nb;
+};
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_cg_apply_batch(const char *tab, const int *bmap) {
+  const BatchApplyEntry<Op> &e =
+      *reinterpret_cast<const BatchApplyEntry<Op> *>(tab + size_t(bmap[blockIdx.x]) *
+                                                               kBatchEntryBytes);
+  cg_apply_run<CH>(e.op, e.g, e.ms, e.ca, blockIdx.x - e.b0, e.nb);
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_cg_update_batch(const BatchUpdateEntry<T> *tab,
+                                                         const int *bmap) {
+  const BatchUpdateEntry<T> &e = tab[bmap[blockIdx.x]];
+  const int bid = blockIdx.x - e.b0;
+  const ChebFuse<T> none{nullptr, nullptr, 0.0, 0};
+  cg_update_run<T>(e.n, e.x, e.r, e.z, e.p, e.q, e.Dinv, e.ca, none, bid, e.nb);
+  // the thread that wrote this system's CG state also publishes it
+  if (bid == 0 && threadIdx.x == 0) {
+    e.status[0] = e.ca.st->b.done;
+    e.status[1] = e.ca.st->b.iters;
   }
 }
 
@@ -1908,6 +1962,73 @@ hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const Ph
   return launch_cg_apply(s, op, g, m, ca);
 }
 
+template <class Op>
+void write_batch_entry(void *dst, const Op &op, const Grid &g, const March &m, const CgArgs &ca,
+                       int b0, int nb) {
+  static_assert(sizeof(BatchApplyEntry<Op>) <= kBatchEntryBytes, "batch entry too large");
+  BatchApplyEntry<Op> e{op, g, m, ca, b0, nb};
+  std::memcpy(dst, &e, sizeof(e));
+}
+
+template <class T>
+void tangent_batch_entry(void *dst, const Grid &g, const March &m, const ElasCoef &c, int split,
+                         const T *ulin, const T *d, const uint8_t *qflag, const uint8_t *eact,
+                         const uint8_t *nflag, const T *z, const T *p_old, T *p_new, T *q,
+                         const CgArgs &ca, int b0, int nb) {
+  if (split == 1) {
+    using Op = OpTangent<T, true, true, 1>;
+    write_batch_entry(dst, Op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), ulin}, g, m,
+                      ca, b0, nb);
+  } else {
+    using Op = OpTangent<T, true, true, 0>;
+    write_batch_entry(dst, Op{g, c, d, qflag, eact, nflag, z, p_old, p_new, q, T(0), nullptr}, g,
+                      m, ca, b0, nb);
+  }
+}
+
+template <class T>
+void phase_batch_entry(void *dst, const Grid &g, const March &m, const PhaseCoef &c,
+                       const T *coef, const uint8_t *eact, const uint8_t *nflag, const T *z,
+                       const T *p_old, T *p_new, T *q, const CgArgs &ca, int b0, int nb) {
+  using Op = OpPhase<T, true, true>;
+  write_batch_entry(dst, Op{g, c, coef, eact, nflag, z, p_old, p_new, q, T(0)}, g, m, ca, b0, nb);
+}
+
+template <class Op>
+hipError_t launch_apply_batch(hipStream_t s, int ch, const void *tab, const int *bmap,
+                              int nblocks) {
+  const dim3 grid(nblocks), block(TPB);
+  const char *t = static_cast<const char *>(tab);
+  switch (ch) {
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<2, Op>), grid, block, 0, s, t, bmap); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<4, Op>), grid, block, 0, s, t, bmap); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<8, Op>), grid, block, 0, s, t, bmap); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_cg_apply_batch(hipStream_t s, int split, int ch, const void *tab,
+                                  const int *bmap, int nblocks) {
+  if (split == 1) return launch_apply_batch<OpTangent<T, true, true, 1>>(s, ch, tab, bmap, nblocks);
+  return launch_apply_batch<OpTangent<T, true, true, 0>>(s, ch, tab, bmap, nblocks);
+}
+
+template <class T>
+hipError_t phase_cg_apply_batch(hipStream_t s, int ch, const void *tab, const int *bmap,
+                                int nblocks) {
+  return launch_apply_batch<OpPhase<T, true, true>>(s, ch, tab, bmap, nblocks);
+}
+
+template <class T>
+hipError_t cg_update_batch(hipStream_t s, const BatchUpdateEntry<T> *tab, const int *bmap,
+                           int nblocks) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update_batch<T>), dim3(nblocks), dim3(TPB), 0, s, tab,
+                     bmap);
+  return hipGetLastError();
+}
+
 CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, double tol,
                int maxit) {
   CgArgs ca;
@@ -2240,6 +2361,21 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
 PF_INST(double)
 PF_INST(float)
 #undef PF_INST
+
+template void tangent_batch_entry<float>(void *, const Grid &, const March &, const ElasCoef &,
+                                         int, const float *, const float *, const uint8_t *,
+                                         const uint8_t *, const uint8_t *, const float *,
+                                         const float *, float *, float *, const CgArgs &, int,
+                                         int);
+template void phase_batch_entry<float>(void *, const Grid &, const March &, const PhaseCoef &,
+                                       const float *, const uint8_t *, const uint8_t *,
+                                       const float *, const float *, float *, float *,
+                                       const CgArgs &, int, int);
+template hipError_t tangent_cg_apply_batch<float>(hipStream_t, int, int, const void *,
+                                                  const int *, int);
+template hipError_t phase_cg_apply_batch<float>(hipStream_t, int, const void *, const int *, int);
+template hipError_t cg_update_batch<float>(hipStream_t, const BatchUpdateEntry<float> *,
+                                           const int *, int);
 
 template hipError_t convert<float, double>(hipStream_t, int, float *, const double *);
 template hipError_t convert<double, float>(hipStream_t, int, double *, const float *);

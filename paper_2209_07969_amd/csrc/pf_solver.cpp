@@ -10,8 +10,13 @@
 
 #include <algorithm>
 #include <atomic>
-#include <thread>
 #include <chrono>
+#include <condition_variable>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +57,8 @@ struct CgBuf {
   T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
   T *coef = nullptr;   // [4E] phase coefficient
 };
+
+struct BatchSvc;
 
 }  // namespace
 
@@ -110,6 +117,10 @@ struct pf_ctx {
 
   // Jacobi-Chebyshev: lambda_max(D^-1 A) estimates per [kind][fp32]
   double lmax[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+
+  // shared CG launches of a batch (set only inside pf_batch_load_step)
+  BatchSvc *svc = nullptr;
+  hipEvent_t ready_ev = nullptr;
 
   // sampled kernel timing
   bool profiling = false;
@@ -472,8 +483,278 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
   return PF_OK;
 }
 
+// ------------------------------------------------ shared CG launches
+
+// One FP32 Jacobi CG solve served by shared launches.
+struct CgRequest {
+  pf_ctx *c = nullptr;
+  Kind kind = K_ELASTIC;
+  double tol = 0.0;
+  int iters = 0, status = 0;
+  bool done = false;
+  pf_status err = PF_OK;
+  std::string msg;
+};
+
+// A request inside the running shared CG loop.
+struct ActiveCg {
+  CgRequest *r;
+  CgArgs ca;
+  int n, split, ch;
+};
+
+// Batch service (continuous batching of CG solves): member threads queue
+// their solves; a service thread keeps one CG loop running over every active
+// system, two shared launches (one apply per operator kind, split and
+// work-item height, one update) per iteration.  At each status poll, every
+// `check` iterations, finished systems are handed back to their members and
+// queued ones join, so no member waits for another's solve.
+struct BatchSvc {
+  std::mutex mu;
+  std::condition_variable work_cv;   // service: new requests or stop
+  std::condition_variable done_cv;   // members: a request finished
+  std::vector<CgRequest *> pending;
+  bool stop = false;
+  hipStream_t stream = nullptr;
+  char *dblob = nullptr, *hblob = nullptr;
+  size_t cap = 0;
+  int check = 32;
+  // launch layout of the current active set
+  struct Launch {
+    int kind, split, ch, nb;
+    size_t tab, map, count;
+  };
+  std::vector<Launch> applies;
+  size_t utab = 0, umap = 0, stat = 0;
+  int ublocks = 0;
+
+  ~BatchSvc() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (dblob) (void)hipFree(dblob);
+    if (hblob) (void)hipHostFree(hblob);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Start a request's CG on the service stream (after its member's right-hand
+// side is in place).
+hipError_t admit(BatchSvc *svc, CgRequest *r, ActiveCg *a) {
+  pf_ctx *c = r->c;
+  CgBuf<float> &b = c->bf;
+  a->r = r;
+  a->n = (r->kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
+  a->ca = cg_args(c->g, c->ms, a->n, c->cgs2, c->rs, r->tol, c->opts.max_cg);
+  a->split = (r->kind == K_ELASTIC) ? c->mt.split : 0;
+  a->ch = c->ms.ch;
+  hipError_t e = hipStreamWaitEvent(svc->stream, c->ready_ev, 0);
+  if (e != hipSuccess) return e;
+  return cg_init<float>(svc->stream, a->n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, a->ca);
+}
+
+// Tables and block maps of the active set, uploaded to the device.  Each
+// system keeps the blocks of its own launch.  Systems join at even shared
+// iteration counts, so iteration k of every system uses direction buffers
+// of parity k & 1 (two tables).
+hipError_t rebuild(BatchSvc *svc, const std::vector<ActiveCg> &act) {
+  std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+  for (int i = 0; i < (int)act.size(); ++i)
+    groups[std::make_tuple((int)act[i].r->kind, act[i].split, act[i].ch)].push_back(i);
+  const size_t nr = act.size();
+  svc->applies.clear();
+  std::vector<std::vector<int>> members;
+  size_t off = 0;
+  for (auto &kv : groups) {
+    BatchSvc::Launch L{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), 0,
+                       off, 0, kv.second.size()};
+    for (int i : kv.second) L.nb += act[i].ca.ga;
+    off += 2 * L.count * (size_t)kBatchEntryBytes;
+    svc->applies.push_back(L);
+    members.push_back(kv.second);
+  }
+  svc->utab = align_up(off, 256);
+  off = svc->utab + 2 * nr * sizeof(BatchUpdateEntry<float>);
+  for (auto &L : svc->applies) {
+    L.map = align_up(off, 256);
+    off = L.map + (size_t)L.nb * sizeof(int);
+  }
+  svc->ublocks = 0;
+  for (auto &a : act) svc->ublocks += a.ca.gb;
+  svc->umap = align_up(off, 256);
+  off = svc->umap + (size_t)svc->ublocks * sizeof(int);
+  svc->stat = align_up(off, 256);
+  const size_t total = svc->stat + 2 * nr * sizeof(int);
+  if (total > svc->cap) {
+    if (svc->dblob) (void)hipFree(svc->dblob);
+    if (svc->hblob) (void)hipHostFree(svc->hblob);
+    svc->dblob = svc->hblob = nullptr;
+    svc->cap = 0;
+    const size_t want = align_up(total * 2, 1 << 16);
+    hipError_t e = hipMalloc((void **)&svc->dblob, want);
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc((void **)&svc->hblob, want);
+    if (e != hipSuccess) return e;
+    svc->cap = want;
+  }
+  char *h = svc->hblob;
+  int *dstat = reinterpret_cast<int *>(svc->dblob + svc->stat);
+  std::memset(h, 0, total);
+  for (size_t gi = 0; gi < svc->applies.size(); ++gi) {
+    const BatchSvc::Launch &L = svc->applies[gi];
+    int *map = reinterpret_cast<int *>(h + L.map);
+    int b0 = 0;
+    for (size_t j = 0; j < L.count; ++j) {
+      const ActiveCg &a = act[members[gi][j]];
+      pf_ctx *c = a.r->c;
+      CgBuf<float> &b = c->bf;
+      for (int par = 0; par < 2; ++par) {
+        void *e = h + L.tab + (par * L.count + j) * (size_t)kBatchEntryBytes;
+        float *pold = b.P[par], *pnew = b.P[par ^ 1];
+        if (L.kind == K_ELASTIC)
+          tangent_batch_entry<float>(e, c->g, c->ms, c->ec, L.split, b.ulin, b.d, c->tflag,
+                                     c->eact, c->nflag, b.W[0], pold, pnew, b.S[0], a.ca, b0,
+                                     a.ca.ga);
+        else
+          phase_batch_entry<float>(e, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.W[0],
+                                   pold, pnew, b.S[0], a.ca, b0, a.ca.ga);
+      }
+      for (int k = 0; k < a.ca.ga; ++k) map[b0 + k] = (int)j;
+      b0 += a.ca.ga;
+    }
+  }
+  auto *ut = reinterpret_cast<BatchUpdateEntry<float> *>(h + svc->utab);
+  int *umap = reinterpret_cast<int *>(h + svc->umap);
+  int b0 = 0;
+  for (size_t i = 0; i < nr; ++i) {
+    const ActiveCg &a = act[i];
+    CgBuf<float> &b = a.r->c->bf;
+    for (int par = 0; par < 2; ++par)
+      ut[par * nr + i] = BatchUpdateEntry<float>{b.X[0], b.R[0], b.W[0], b.P[par ^ 1], b.S[0],
+                                                 b.Dinv, a.ca, a.n, b0, a.ca.gb,
+                                                 dstat + 2 * i};
+    for (int k = 0; k < a.ca.gb; ++k) umap[b0 + k] = (int)i;
+    b0 += a.ca.gb;
+  }
+  return hipMemcpyAsync(svc->dblob, h, total, hipMemcpyHostToDevice, svc->stream);
+}
+
+// `check` shared iterations of the active set from iteration K (even).
+hipError_t run_iters(BatchSvc *svc, size_t nr) {
+  char *d = svc->dblob;
+  const auto *dut = reinterpret_cast<const BatchUpdateEntry<float> *>(d + svc->utab);
+  const int *dumap = reinterpret_cast<const int *>(d + svc->umap);
+  for (int k = 0; k < svc->check; ++k) {
+    const int par = k & 1;
+    for (const auto &L : svc->applies) {
+      const void *tab = d + L.tab + par * L.count * (size_t)kBatchEntryBytes;
+      const int *map = reinterpret_cast<const int *>(d + L.map);
+      const hipError_t e = L.kind == K_ELASTIC
+                               ? tangent_cg_apply_batch<float>(svc->stream, L.split, L.ch, tab,
+                                                               map, L.nb)
+                               : phase_cg_apply_batch<float>(svc->stream, L.ch, tab, map, L.nb);
+      if (e != hipSuccess) return e;
+    }
+    const hipError_t e = cg_update_batch<float>(svc->stream, dut + par * nr, dumap, svc->ublocks);
+    if (e != hipSuccess) return e;
+  }
+  int *hstat = reinterpret_cast<int *>(svc->hblob + svc->stat);
+  const int *dstat = reinterpret_cast<const int *>(d + svc->stat);
+  hipError_t e = hipMemcpyAsync(hstat, dstat, 2 * nr * sizeof(int), hipMemcpyDeviceToHost,
+                                svc->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(svc->stream);
+}
+
+// Service thread: admit, iterate, hand back, until stopped with nothing left.
+void service_loop(BatchSvc *svc) {
+  std::vector<ActiveCg> act;
+  std::unique_lock<std::mutex> lk(svc->mu);
+  for (;;) {
+    svc->work_cv.wait(lk, [&] { return !act.empty() || !svc->pending.empty() || svc->stop; });
+    if (act.empty() && svc->pending.empty()) break;   // stopped
+    std::vector<CgRequest *> add;
+    add.swap(svc->pending);
+    lk.unlock();
+    hipError_t e = hipSuccess;
+    for (CgRequest *r : add) {
+      ActiveCg a{};
+      if (e == hipSuccess) e = admit(svc, r, &a);
+      a.r = r;
+      act.push_back(a);
+    }
+    if (e == hipSuccess && !add.empty()) e = rebuild(svc, act);
+    if (e == hipSuccess) e = run_iters(svc, act.size());
+    std::vector<ActiveCg> keep;
+    bool removed = false;
+    lk.lock();
+    if (e != hipSuccess) {
+      for (auto &a : act) {
+        a.r->err = PF_E_HIP;
+        a.r->msg = hipGetErrorString(e);
+        a.r->done = true;
+      }
+      act.clear();
+    } else {
+      const int *hstat = reinterpret_cast<const int *>(svc->hblob + svc->stat);
+      for (size_t i = 0; i < act.size(); ++i) {
+        if (hstat[2 * i] != 0) {
+          act[i].r->status = hstat[2 * i];
+          act[i].r->iters = hstat[2 * i + 1];
+          act[i].r->done = true;
+          removed = true;
+        } else {
+          keep.push_back(act[i]);
+        }
+      }
+      act.swap(keep);
+    }
+    svc->done_cv.notify_all();
+    if (removed && !act.empty() && svc->pending.empty()) {
+      lk.unlock();
+      e = rebuild(svc, act);
+      lk.lock();
+      if (e != hipSuccess) {
+        for (auto &a : act) {
+          a.r->err = PF_E_HIP;
+          a.r->msg = hipGetErrorString(e);
+          a.r->done = true;
+        }
+        act.clear();
+        svc->done_cv.notify_all();
+      }
+    }
+  }
+}
+
+// Queue this context's FP32 Jacobi solve with the batch service and wait.
+pf_status shared_pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, float **xout) {
+  if (!c->ready_ev) PF_HIP(c, hipEventCreateWithFlags(&c->ready_ev, hipEventDisableTiming));
+  PF_HIP(c, hipEventRecord(c->ready_ev, c->stream));
+  CgRequest req;
+  req.c = c;
+  req.kind = kind;
+  req.tol = tol;
+  BatchSvc *svc = c->svc;
+  {
+    std::unique_lock<std::mutex> lk(svc->mu);
+    svc->pending.push_back(&req);
+    svc->work_cv.notify_one();
+    svc->done_cv.wait(lk, [&] { return req.done; });
+  }
+  if (req.err != PF_OK) return fail(c, req.err, "shared CG launch: " + req.msg);
+  *iters = req.iters;
+  *status = req.status;
+  *xout = c->bf.X[0];
+  return PF_OK;
+}
+
 template <class T>
 pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->svc && c->opts.precond == PF_PC_JACOBI && !c->profiling)
+      return shared_pcg(c, kind, tol, iters, status, xout);
+  }
   CgBuf<T> &b = buf<T>(c);
   const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
   CgArgs ca = cg_args(c->g, c->ms, n, c->cgs2, c->rs, tol, c->opts.max_cg);
@@ -1016,6 +1297,7 @@ pf_status pf_destroy(pf_ctx *c) {
   }
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
   for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->cgs_h) (void)hipHostFree(c->cgs_h);
@@ -1208,6 +1490,8 @@ pf_status pf_kernel_time(pf_ctx *c, int32_t kernel, int64_t *launches, double *t
 struct pf_batch {
   std::vector<pf_ctx *> members;
   int workers = 4;
+  bool shared = true;
+  std::unique_ptr<BatchSvc> svc;
 };
 
 pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out) {
@@ -1226,24 +1510,58 @@ pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf
   return PF_OK;
 }
 
+pf_status pf_batch_set_shared_launches(pf_batch *b, int32_t enable) {
+  if (!b) return PF_E_INVALID_ARG;
+  b->shared = enable != 0;
+  return PF_OK;
+}
+
 pf_status pf_batch_load_step(pf_batch *b, const double *lam, pf_step_stats *stats) {
   if (!b || !lam) return PF_E_INVALID_ARG;
   const int n = (int)b->members.size();
   std::vector<pf_status> st(n, PF_OK);
   std::vector<pf_step_stats> ss(n);
-  std::atomic<int> next(0);
-  auto work = [&]() {
-    for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) return;
-      st[i] = pf_load_step(b->members[i], lam[i], &ss[i]);
+  if (b->shared) {
+    // one host thread per member; FP32 Jacobi CG solves go to the service
+    if (!b->svc) {
+      auto svc = std::make_unique<BatchSvc>();
+      if (hipStreamCreateWithFlags(&svc->stream, hipStreamNonBlocking) != hipSuccess)
+        return PF_E_HIP;
+      b->svc = std::move(svc);
     }
-  };
-  const int nw = std::min(b->workers, n);
-  std::vector<std::thread> th;
-  for (int w = 1; w < nw; ++w) th.emplace_back(work);
-  work();
-  for (auto &t : th) t.join();
+    BatchSvc *svc = b->svc.get();
+    int check = std::max(4, b->members[0]->opts.cg_check);
+    svc->check = check + (check & 1);
+    svc->stop = false;
+    for (pf_ctx *c : b->members) c->svc = svc;
+    std::thread service(service_loop, svc);
+    auto work = [&](int i) { st[i] = pf_load_step(b->members[i], lam[i], &ss[i]); };
+    std::vector<std::thread> th;
+    for (int i = 1; i < n; ++i) th.emplace_back(work, i);
+    work(0);
+    for (auto &t : th) t.join();
+    {
+      std::lock_guard<std::mutex> lk(svc->mu);
+      svc->stop = true;
+    }
+    svc->work_cv.notify_all();
+    service.join();
+    for (pf_ctx *c : b->members) c->svc = nullptr;
+  } else {
+    std::atomic<int> next(0);
+    auto work = [&]() {
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= n) return;
+        st[i] = pf_load_step(b->members[i], lam[i], &ss[i]);
+      }
+    };
+    const int nw = std::min(b->workers, n);
+    std::vector<std::thread> th;
+    for (int w = 1; w < nw; ++w) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+  }
   if (stats)
     for (int i = 0; i < n; ++i) stats[i] = ss[i];
   pf_status worst = PF_OK;

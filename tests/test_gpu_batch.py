@@ -35,6 +35,44 @@ def test_batch_matches_sequential(gpu_lib):
     B.close()
 
 
+def _mixed_members():
+    """Uneven mixed-precision members: two work-item heights, a spectral
+    member and a masked L-shape, so the shared launches hold several apply
+    groups and both operator kinds."""
+    return [
+        (W.tension_panel(n=16, l=0.1, du=1e-3, steps=4, notch=0.5), 1, {}),
+        (W.tension_panel(n=24, l=0.1, du=1e-3, steps=4, notch=0.375), 1, {"march_rows": 2}),
+        (W.tension_panel(n=20, l=0.1, du=1e-3, steps=4, notch=0.45), 0, {"march_rows": 8}),
+        (W.shear_panel(n=16, l=0.1, du=2e-3, steps=4), 3, {}),
+        (W.lshape_panel(n=32, steps=4, total=0.12), 1, {}),
+    ]
+
+
+@pytest.mark.parametrize("shared", [True, False])
+def test_batch_mixed_matches_sequential(gpu_lib, shared):
+    import torch
+    mem = _mixed_members()
+    seq = [gpu_lib.Context(p, scheme=s, precision=1, **kw) for p, s, kw in mem]
+    streams = [torch.cuda.Stream() for _ in mem]
+    bat = [gpu_lib.Context(p, scheme=s, precision=1, stream=st.cuda_stream, **kw)
+           for (p, s, kw), st in zip(mem, streams)]
+    B = gpu_lib.Batch(bat, workers=3, shared=shared)
+    for k in range(4):
+        lams = [float(p.loads[k]) for p, _, _ in mem]
+        sb = B.load_step(lams)
+        for i, c in enumerate(seq):
+            s = c.load_step(lams[i])
+            for key in ("n_stag", "n_newton", "n_cg_u", "n_cg_d", "n_cg_trial"):
+                assert s[key] == sb[i][key], (shared, k, i, key, s[key], sb[i][key])
+            assert s["force"] == sb[i]["force"]
+    for a, b in zip(seq, bat):
+        for x, y in zip(a.get_state(), b.get_state()):
+            np.testing.assert_array_equal(x, y)
+    B.close()
+    for c in seq + bat:
+        c.close()
+
+
 def test_autotune_keeps_parity(gpu_lib):
     p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=5)
     ctx = gpu_lib.Context(p, scheme=1)
