@@ -220,7 +220,7 @@ def run_apply_sizes(pf, args):
     out = []
     for n in (512, 1024, 2048, 4096):
         p = W.tension_panel(n=n, l=4.0 / n, du=6e-5, steps=1)
-        for ch in (0, 2, 4, 8):
+        for ch in (0, 1, 2, 4, 8):
             ctx = pf.Context(p, scheme=pf.ST, precision=pf.MIXED, max_stag=1, max_newton=1,
                              max_cg=args.apply_iters, march_rows=ch)
             ctx.set_profiling(True)

@@ -101,7 +101,10 @@ typedef struct {
   double trial_floor;   /* theta: trial mass coefficient >= theta*(Gc/l+2H)   */
   int32_t march_rows;   /* node rows per work item of the operator kernels:   */
                         /* 2, 4 or 8; 0 = chosen from the mesh size           */
-  int32_t reserved;
+  int32_t cg_kernels;   /* CG formulation: 0 = by precision (FP64: one kernel  */
+                        /* per iteration, FP32: two), 1 = one kernel per      */
+                        /* iteration (Chronopoulos-Gear recurrences, one      */
+                        /* reduction), 2 = two kernels (standard recurrences) */
 } pf_solver_opts;
 
 typedef struct {
@@ -125,7 +128,7 @@ typedef struct {
 /* Fill *opts with defaults: ST, FP64, Jacobi (cheb_degree 3), tol_stag 1e-5, tol_pcg 1e-10,
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
- * march_rows 0. */
+ * march_rows 0, cg_kernels 0. */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

@@ -54,10 +54,14 @@ constexpr uint8_t NF_UY = 2;   // u_y fixed
 constexpr uint8_t NF_D = 4;    // d fixed
 
 // Column-marching launch shape for the node-accumulating operators.
+// Work decomposition of the operator kernels.  ch = 2, 4 or 8: column
+// marching, one wave per (strip of 62 node columns, chunk of ch node rows).
+// ch = 1: LDS tiles, one block per tile of 15 x 15 owned nodes (nstrips x
+// nchunks tiles), one element per thread.
 struct March {
-  int nstrips;    // wave strips across x (63 owned node columns each)
-  int nchunks;    // row chunks along y
-  int ch;         // node rows owned per wave
+  int nstrips;    // marching: wave strips across x; tiles: tiles across x
+  int nchunks;    // marching: row chunks along y;   tiles: tiles along y
+  int ch;         // node rows per marching item, or 1 for LDS tiles
 };
 
 // Scratch for block reductions.  Kernels that reduce run at most kPMax

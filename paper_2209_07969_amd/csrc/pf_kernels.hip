@@ -532,6 +532,90 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * per + min(x, rem) + k;
 }
 
+// ------------------------------------------------------------ LDS tiles
+//
+// One block per tile of kTile x kTile owned nodes.  The block stages the
+// (kTile+2)^2 nodes around the tile in LDS (after fin), each of its 256
+// threads computes one of the (kTile+1)^2 elements touching the tile and
+// writes the element's corner values to LDS, and each owned node sums the
+// four corner values of its elements.  Compared with column marching the
+// dependency chain of a wave is one element instead of a column of them,
+// at the price of computing the ring of elements around the tile in both
+// neighbouring tiles.
+
+constexpr int kTile = 15;
+constexpr int kTileN = kTile + 2;   // staged nodes per side
+constexpr int kTileE = kTile + 1;   // elements per side (kTileE^2 == TPB)
+constexpr int kTileLoads = (kTileN * kTileN + TPB - 1) / TPB;
+
+template <class Op>
+struct TileLds {
+  typename Op::Node node[kTileN * kTileN];
+  typename Op::T f[Op::NF][4][kTileE * kTileE];
+};
+
+template <class Op>
+struct TileRegs {
+  typename Op::Node n[kTileLoads];
+  typename Op::Elem e;
+};
+
+template <class Op>
+__device__ inline void tile_load(const Op &op, const March &ms, int tile, TileRegs<Op> &tr) {
+  static_assert(kTileE * kTileE == TPB, "one element per thread");
+  const int i0 = (tile % ms.nstrips) * kTile - 1, j0 = (tile / ms.nstrips) * kTile - 1;
+#pragma unroll
+  for (int r = 0; r < kTileLoads; ++r) {
+    const int k = threadIdx.x + r * TPB;
+    if (k < kTileN * kTileN) tr.n[r] = op.load(i0 + k % kTileN, j0 + k / kTileN);
+  }
+  tr.e = op.eload(i0 + threadIdx.x % kTileE, j0 + threadIdx.x / kTileE);
+}
+
+template <class Op>
+__device__ inline void tile_compute(const Op &op, const Grid &g, const March &ms, int tile,
+                                    TileRegs<Op> &tr, TileLds<Op> &sm, double *red) {
+  using T = typename Op::T;
+  constexpr int NF = Op::NF;
+#pragma unroll
+  for (int r = 0; r < kTileLoads; ++r) {
+    const int k = threadIdx.x + r * TPB;
+    if (k < kTileN * kTileN) {
+      op.fin(tr.n[r]);
+      sm.node[k] = tr.n[r];
+    }
+  }
+  __syncthreads();
+  {
+    // element (el, ej) of the tile: corner 0 is staged node (el, ej)
+    const int el = threadIdx.x % kTileE, ej = threadIdx.x / kTileE;
+    const int b = ej * kTileN + el;
+    T f[NF][4];
+    op.element(sm.node[b], sm.node[b + 1], sm.node[b + kTileN + 1], sm.node[b + kTileN], tr.e, f);
+#pragma unroll
+    for (int q = 0; q < NF; ++q)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sm.f[q][a][threadIdx.x] = f[q][a];
+  }
+  __syncthreads();
+  if (threadIdx.x < kTile * kTile) {
+    // owned node (li, lj) is staged node (li+1, lj+1): corner 2 of element
+    // (li, lj), 3 of (li+1, lj), 1 of (li, lj+1), 0 of (li+1, lj+1)
+    const int li = threadIdx.x % kTile, lj = threadIdx.x / kTile;
+    const int i = (tile % ms.nstrips) * kTile + li, j = (tile / ms.nstrips) * kTile + lj;
+    if (i <= g.nx && j <= g.ny) {
+      const int e = lj * kTileE + li;
+      T out[NF];
+#pragma unroll
+      for (int q = 0; q < NF; ++q)
+        out[q] = sm.f[q][2][e] + sm.f[q][3][e + 1] + sm.f[q][1][e + kTileE] +
+                 sm.f[q][0][e + kTileE + 1];
+      op.store(i, j, out, sm.node[(lj + 1) * kTileN + li + 1], red);
+    }
+  }
+  __syncthreads();   // the LDS is reused by the block's next tile
+}
+
 template <int CH, class Op>
 __device__ inline void march_items(const Op &op, const Grid &g, const March &ms, int wfirst,
                                    int wstride, double *red) {
@@ -551,14 +635,24 @@ __global__ void __launch_bounds__(TPB) k_march(Op op, Grid g, March ms, double *
   double red[NRR];
 #pragma unroll
   for (int k = 0; k < NRR; ++k) red[k] = 0.0;
-  march_items<CH>(op, g, ms, xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6),
-                  gridDim.x * WPB, red);
+  if constexpr (CH == 1) {
+    __shared__ TileLds<Op> sm;
+    const int nt = ms.nstrips * ms.nchunks;
+    for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
+      TileRegs<Op> tr;
+      tile_load(op, ms, t, tr);
+      tile_compute(op, g, ms, t, tr, sm, red);
+    }
+  } else {
+    march_items<CH>(op, g, ms, xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6),
+                    gridDim.x * WPB, red);
+  }
   if (Op::NR > 0) block_partial<NRR>(red, part);
 }
 
 int march_blocks(const March &m) {
   const int nw = m.nstrips * m.nchunks;
-  int b = (nw + WPB - 1) / WPB;
+  int b = m.ch == 1 ? nw : (nw + WPB - 1) / WPB;
   return b > kPMax ? kPMax : b;
 }
 
@@ -968,6 +1062,7 @@ hipError_t launch_march(hipStream_t s, const Op &op, const Grid &g, const March 
                         double *part) {
   const dim3 grid(march_blocks(m)), block(TPB);
   switch (m.ch) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<1, Op>), grid, block, 0, s, op, g, m, part); break;
     case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<2, Op>), grid, block, 0, s, op, g, m, part); break;
     case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<4, Op>), grid, block, 0, s, op, g, m, part); break;
     case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_march<8, Op>), grid, block, 0, s, op, g, m, part); break;
@@ -1065,18 +1160,34 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta, int bid)
 template <int CH, class Op>
 __device__ inline void cg_apply_run(Op op, const Grid &g, const March &ms, const CgArgs &ca,
                                     int bid, int nb) {
-  const int lane = threadIdx.x & 63;
-  const int w0 = xcd_block(bid, nb) * WPB + (threadIdx.x >> 6);
-  const int nw = ms.nstrips * ms.nchunks;
-  // issue the first work item's loads before the prologue's reduction
-  Item<CH, Op> it;
-  if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
-  double beta = 0.0;
-  if (cg_apply_prologue(ca, &beta, bid) != 0) return;
-  op.beta = typename Op::T(beta);
   double red[1] = {0.0};
-  if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
-  march_items<CH>(op, g, ms, w0 + nb * WPB, nb * WPB, red);
+  if constexpr (CH == 1) {
+    __shared__ TileLds<Op> sm;
+    const int nt = ms.nstrips * ms.nchunks;
+    int t = xcd_block(bid, nb);
+    // the first tile's loads are in flight during the prologue's reduction
+    TileRegs<Op> tr;
+    if (t < nt) tile_load(op, ms, t, tr);
+    double beta = 0.0;
+    if (cg_apply_prologue(ca, &beta, bid) != 0) return;
+    op.beta = typename Op::T(beta);
+    for (; t < nt; t += nb) {
+      tile_compute(op, g, ms, t, tr, sm, red);
+      if (t + nb < nt) tile_load(op, ms, t + nb, tr);
+    }
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int w0 = xcd_block(bid, nb) * WPB + (threadIdx.x >> 6);
+    const int nw = ms.nstrips * ms.nchunks;
+    // issue the first work item's loads before the prologue's reduction
+    Item<CH, Op> it;
+    if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
+    double beta = 0.0;
+    if (cg_apply_prologue(ca, &beta, bid) != 0) return;
+    op.beta = typename Op::T(beta);
+    if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
+    march_items<CH>(op, g, ms, w0 + nb * WPB, nb * WPB, red);
+  }
   block_partial_at<1>(red, ca.partA, bid);
 }
 
@@ -1885,6 +1996,12 @@ __global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
 
 March march_shape(const Grid &g, int ch_override) {
   March m;
+  if (ch_override == 1) {
+    m.ch = 1;
+    m.nstrips = (g.nx + 1 + kTile - 1) / kTile;
+    m.nchunks = (g.ny + 1 + kTile - 1) / kTile;
+    return m;
+  }
   m.nstrips = (g.nx + 1 + CSTRIP - 1) / CSTRIP;
   int ch = ch_override;
   if (ch != 2 && ch != 4 && ch != 8) {
@@ -1930,6 +2047,7 @@ hipError_t launch_cg_apply(hipStream_t s, const Op &op, const Grid &g, const Mar
                            const CgArgs &ca) {
   const dim3 grid(ca.ga), block(TPB);
   switch (m.ch) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<1, Op>), grid, block, 0, s, op, g, m, ca); break;
     case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<2, Op>), grid, block, 0, s, op, g, m, ca); break;
     case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<4, Op>), grid, block, 0, s, op, g, m, ca); break;
     case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply<8, Op>), grid, block, 0, s, op, g, m, ca); break;
@@ -2000,6 +2118,7 @@ hipError_t launch_apply_batch(hipStream_t s, int ch, const void *tab, const int 
   const dim3 grid(nblocks), block(TPB);
   const char *t = static_cast<const char *>(tab);
   switch (ch) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<1, Op>), grid, block, 0, s, t, bmap); break;
     case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<2, Op>), grid, block, 0, s, t, bmap); break;
     case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<4, Op>), grid, block, 0, s, t, bmap); break;
     case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_apply_batch<8, Op>), grid, block, 0, s, t, bmap); break;

@@ -834,7 +834,10 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
 // exit in their prologue.  *xout points to the solution buffer.
 template <class T>
 pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
-  if (std::is_same<T, float>::value || c->opts.precond == PF_PC_JACOBI_CHEBYSHEV)
+  // the single-kernel formulation marches columns; LDS tiles use two kernels
+  const bool two = c->opts.cg_kernels == 2 || c->ms.ch == 1 ||
+                   (c->opts.cg_kernels == 0 && std::is_same<T, float>::value);
+  if (two || c->opts.precond == PF_PC_JACOBI_CHEBYSHEV)
     return pcg2<T>(c, kind, tol, iters, status, xout);
   CgBuf<T> &b = buf<T>(c);
   Cg1Args a;
@@ -1150,8 +1153,13 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   }
   if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) { *msg = "iteration limits"; return PF_E_INVALID_ARG; }
   if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
-  if (o->march_rows != 0 && o->march_rows != 2 && o->march_rows != 4 && o->march_rows != 8) {
-    *msg = "march_rows must be 0, 2, 4 or 8";
+  if (o->cg_kernels < 0 || o->cg_kernels > 2) {
+    *msg = "cg_kernels must be 0, 1 or 2";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->march_rows < 0 || o->march_rows > 8 || (o->march_rows > 2 && o->march_rows != 4 &&
+                                                  o->march_rows != 8)) {
+    *msg = "march_rows must be 0, 1, 2, 4 or 8";
     return PF_E_INVALID_ARG;
   }
   return PF_OK;
@@ -1160,6 +1168,46 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
 }  // namespace
 
 // =================================================================== C ABI
+
+namespace {
+
+// Average time of `reps` launches of the context's two-kernel CG apply
+// (idempotent: it rewrites p_new, q and its partials from inputs it does not
+// modify) in precision T with the current work decomposition.  u_try holds
+// the right-hand side's source state (see pf_autotune).
+template <class T>
+pf_status time_cg_apply(pf_ctx *c, int reps, float *ms) {
+  CgBuf<T> &b = buf<T>(c);
+  const int n2 = 2 * c->g.N;
+  if (std::is_same<T, float>::value) {
+    PF_HIP(c, convert<float, double>(c->stream, c->g.N, c->bf.d, c->d));
+    PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.R[0], c->Ru));
+    if (c->mt.split == 1) PF_HIP(c, convert<float, double>(c->stream, n2, c->bf.ulin, c->u));
+  } else {
+    PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    if (c->mt.split == 1)
+      PF_HIP(c, hipMemcpyAsync(c->bd.ulin, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+  }
+  PF_HIP(c, tangent_diag<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                            c->eact, c->nflag, b.Dinv));
+  CgArgs ca = cg_args(c->g, c->ms, n2, c->cgs2, c->rs, 0.0, 1 << 30);
+  PF_HIP(c, cg_init<T>(c->stream, n2, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
+  auto apply = [&]() {
+    return tangent_cg_apply<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                               c->eact, c->nflag, b.W[0], b.P[0], b.P[1], b.S[0], ca);
+  };
+  PF_HIP(c, apply());   // warm
+  PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
+  for (int r = 0; r < reps; ++r) PF_HIP(c, apply());
+  PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
+  PF_TRY(sync(c));
+  PF_HIP(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+  return PF_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1599,40 +1647,51 @@ pf_status pf_autotune(pf_ctx *c, int32_t reps, int32_t *chosen) {
   const March keep = c->ms;
   float best = 0.f;
   int best_ch = keep.ch;
-  for (int ch : {2, 4, 8}) {
+  // the displacement solves use the single-kernel CG (column marching only)
+  // in FP64 with Jacobi unless two kernels are asked for
+  const bool fp32 = c->opts.precision == PF_MIXED;
+  const bool cg1 = !fp32 && c->opts.precond == PF_PC_JACOBI && c->opts.cg_kernels != 2;
+  const std::vector<int> cands = cg1 ? std::vector<int>{2, 4, 8} : std::vector<int>{1, 2, 4, 8};
+  for (int ch : cands) {
     c->ms = march_shape(c->g, ch);
-    if (c->mt.split == 1)
-      PF_HIP(c, hipMemcpyAsync(c->bd.ulin, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
-                               c->stream));
-    PF_HIP(c, tangent_diag<double>(c->stream, c->g, c->ms, c->ec, c->mt.split, c->bd.ulin, c->d,
-                                   c->tflag, c->eact, c->nflag, c->bd.Dinv));
-    PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream));
-    Cg1Args a;
-    a.st = c->cgs;
-    a.part = c->cgpart;
-    a.np = cg1_blocks(c->ms);
-    a.tol2 = 0.0;
-    a.maxit = 1 << 30;
-    a.parity = 0;
-    a.init = 1;
-    PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
-    a.init = 0;
-    a.parity = 1;
-    PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));   // warm
-    PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
-    for (int r = 0; r < reps; ++r) PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
-    PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
-    PF_TRY(sync(c));
     float ms = 0.f;
-    PF_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    if (cg1) {
+      if (c->mt.split == 1)
+        PF_HIP(c, hipMemcpyAsync(c->bd.ulin, c->u, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+      PF_HIP(c, tangent_diag<double>(c->stream, c->g, c->ms, c->ec, c->mt.split, c->bd.ulin,
+                                     c->d, c->tflag, c->eact, c->nflag, c->bd.Dinv));
+      PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Ru, n2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+      Cg1Args a;
+      a.st = c->cgs;
+      a.part = c->cgpart;
+      a.np = cg1_blocks(c->ms);
+      a.tol2 = 0.0;
+      a.maxit = 1 << 30;
+      a.parity = 0;
+      a.init = 1;
+      PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
+      a.init = 0;
+      a.parity = 1;
+      PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));   // warm
+      PF_HIP(c, hipEventRecord(c->ev[0], c->stream));
+      for (int r = 0; r < reps; ++r) PF_TRY(launch_k<double>(c, c->stream, K_ELASTIC, a));
+      PF_HIP(c, hipEventRecord(c->ev[1], c->stream));
+      PF_TRY(sync(c));
+      PF_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    } else if (fp32) {
+      PF_TRY(time_cg_apply<float>(c, reps, &ms));
+    } else {
+      PF_TRY(time_cg_apply<double>(c, reps, &ms));
+    }
     if (best == 0.f || ms < best) {
       best = ms;
       best_ch = ch;
     }
   }
   c->ms = march_shape(c->g, best_ch);
-  // graphs captured with another work-item shape are stale
+  // graphs captured with another work decomposition are stale
   for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
   c->graphs.clear();
   if (chosen) *chosen = best_ch;

@@ -2,8 +2,9 @@
 operator on the same seeded inputs (GPU).
 
 Meshes are ragged (several wave strips and row chunks plus a partial one) and
-one case masks out elements.  Tolerances are relative to the operator scale:
-both sides are FP64 and differ only in summation order.
+one case masks out elements; both work decompositions run (column marching,
+march_rows 0, and LDS tiles, march_rows 1).  Tolerances are relative to the
+operator scale: both sides are FP64 and differ only in summation order.
 """
 import numpy as np
 import pytest
@@ -29,7 +30,7 @@ def to_inter(u_soa, N):
     return u
 
 
-def make(pf, nx, ny, masked=False, scheme=0, split=0):
+def make(pf, nx, ny, masked=False, scheme=0, split=0, march_rows=0):
     p = W.tension_panel(n=4, l=0.05, split=split)
     p.nx, p.ny, p.lx, p.ly = nx, ny, 1.3, 0.7
     p.dir_u = [W.DirichletU(np.array([0], np.int64), np.array([0], np.int8), np.zeros(1)),
@@ -39,7 +40,7 @@ def make(pf, nx, ny, masked=False, scheme=0, split=0):
     if masked:
         jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
         p.elem_active = (~((ii >= nx // 2) & (jj >= ny // 2))).astype(np.uint8).reshape(-1)
-    ctx = pf.Context(p, scheme=scheme)
+    ctx = pf.Context(p, scheme=scheme, march_rows=march_rows)
     orc = Oracle(p, scheme)
     return p, ctx, orc
 
@@ -58,12 +59,13 @@ def host(t):
     return t.cpu().numpy()
 
 
+@pytest.mark.parametrize("rows", [0, 1])
 @pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 @pytest.mark.parametrize("masked", [False, True])
-def test_internal_force_and_tangent(gpu_lib, nx, ny, masked, split):
+def test_internal_force_and_tangent(gpu_lib, nx, ny, masked, split, rows):
     import torch
-    p, ctx, orc = make(gpu_lib, nx, ny, masked, split=split)
+    p, ctx, orc = make(gpu_lib, nx, ny, masked, split=split, march_rows=rows)
     N = p.n_nodes
     rng = np.random.default_rng(nx * 100 + ny)
     u = rng.normal(size=2 * N) * 1e-3
@@ -87,11 +89,12 @@ def test_internal_force_and_tangent(gpu_lib, nx, ny, masked, split):
     ctx.close()
 
 
+@pytest.mark.parametrize("rows", [0, 1])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 @pytest.mark.parametrize("masked", [False, True])
-def test_phase_apply(gpu_lib, nx, ny, masked):
+def test_phase_apply(gpu_lib, nx, ny, masked, rows):
     import torch
-    p, ctx, orc = make(gpu_lib, nx, ny, masked)
+    p, ctx, orc = make(gpu_lib, nx, ny, masked, march_rows=rows)
     N, E = p.n_nodes, p.n_elems
     rng = np.random.default_rng(7 + nx)
     coef_planes = rng.uniform(0.1, 50.0, size=(4, E))

@@ -24,9 +24,9 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def compare_history(pf, p, scheme, precision, n_steps, u_tol):
+def compare_history(pf, p, scheme, precision, n_steps, u_tol, **opts):
     orc = Oracle(p, scheme)
-    ctx = pf.Context(p, scheme=scheme, precision=precision)
+    ctx = pf.Context(p, scheme=scheme, precision=precision, **opts)
     F_o, F_g = [], []
     worst = {"u": 0.0, "d": 0.0, "dstag": 0}
     for n, lam in enumerate(p.loads[:n_steps]):
@@ -128,6 +128,36 @@ def test_chebyshev_preconditioner_history(gpu_lib, precision):
             assert rel_l2(u, soa(orc.u)) <= (1e-7 if precision == 0 else 1e-6)
             assert np.abs(d - orc.d).max() <= 1e-5
     ctx.close()
+
+
+def _ragged_panel():
+    p = W.tension_panel(n=16, l=0.08, du=1e-3, steps=5)
+    p.nx, p.ny = 133, 40
+    nx, ny = p.nx, p.ny
+    p.dir_u = [W._fix(W._edge_nodes(nx, ny, "bottom"), (0, 1)),
+               W.DirichletU(W._edge_nodes(nx, ny, "top"), np.ones(nx + 1, np.int8),
+                            np.ones(nx + 1))]
+    p.dir_d_nodes = W.notch_nodes(nx, ny, 1.0, 1.0, 0.5)
+    p.dir_d_values = np.ones(p.dir_d_nodes.shape)
+    return p
+
+
+@pytest.mark.parametrize("case", ["tension_s1_mixed", "tension_st_fp64", "shear_s3_mixed",
+                                  "lshape_s1_fp64", "ragged_s1_mixed"])
+def test_lds_tiles_history(gpu_lib, case):
+    """The LDS-tile work decomposition (march_rows 1) reaches the oracle's
+    fixed points: VD and spectral, masked, ragged, FP64 and mixed."""
+    if case == "tension_s1_mixed":
+        p, sch, prec, n, tol = W.tension_panel(n=16, l=0.1, du=1e-3, steps=8), 1, 1, 8, 1e-6
+    elif case == "tension_st_fp64":
+        p, sch, prec, n, tol = W.tension_panel(n=16, l=0.1, du=1e-3, steps=8), 0, 0, 8, 1e-7
+    elif case == "shear_s3_mixed":
+        p, sch, prec, n, tol = W.shear_panel(n=16, l=0.1, du=2e-3, steps=8), 3, 1, 8, 1e-6
+    elif case == "lshape_s1_fp64":
+        p, sch, prec, n, tol = W.lshape_panel(n=32, steps=10, total=0.3), 1, 0, 3, 1e-7
+    else:
+        p, sch, prec, n, tol = _ragged_panel(), 1, 1, 5, 1e-6
+    compare_history(gpu_lib, p, sch, prec, n, tol, march_rows=1)
 
 
 def test_ragged_panel_history_fp64(gpu_lib):
