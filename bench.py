@@ -12,6 +12,8 @@ edge u_y ramped by 6e-5 mm per step.  A "step" is one load step of that
 history: the staggered iterations until ||R_d||/||b|| <= 1e-5, each with the
 QP update, the S1 trial solve and predictor, the phase solve, the Newton
 displacement solve (PCG with fused reductions) and the reaction force.
+Both schemes use Jacobi-Chebyshev preconditioning (degree 3 for the FP32
+inner solves, 5 for FP64) and the work decomposition the autotuner picks.
 W warmup steps (load steps 1..W) run untimed, then K load steps are timed.
 
 value = GDOF-updates/s of S1 mixed over the timed steps (sum over all CG
@@ -56,16 +58,25 @@ def fused_apply_bytes_per_node():
     return (2 + 2 + 1 + 2 + 2) * 4 + 1 + 1
 
 
+def cheb_step_bytes_per_node():
+    """Algorithmic bytes per node of an FP32 Jacobi-Chebyshev step on the
+    tangent (k_march<OpCheb<OpTangent<float>>>, not the last step): read
+    d_{k-1}, z, res, D^-1 (2 comps each), d, node flag, element flag (1 B per
+    element ~ node); write d_k, z, res (2 comps each)."""
+    return (2 + 2 + 2 + 2 + 1 + 2 + 2 + 2) * 4 + 1 + 1
+
+
 def update_bytes_per_node():
     """Algorithmic bytes per node of the FP32 CG vector update (k_cg_update):
     per DOF read x, p, q, r, D^-1 and write x, r, z, two DOFs per node."""
     return 2 * (5 + 3) * 4
 
 
-def measured_traffic():
+def measured_traffic(kname):
     """Per-launch HBM bytes of the dominant kernel from the committed counter
     runs (profiles/hbm_traffic_tension512.json), or None when the kernel
-    source has changed since the counters were taken."""
+    source has changed since the counters were taken or the counters were
+    taken on another kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_tension512.json")
     src = os.path.join(ROOT, "paper_2209_07969_amd", "csrc", "pf_kernels.hip")
@@ -73,14 +84,20 @@ def measured_traffic():
         return None
     rec = json.load(open(path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha:
+    if rec.get("kernel_source_sha256") != sha or rec.get("kernel") != kname:
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False):
+def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degree=None,
+              tune_reps=0):
+    """Run load steps 1..warmup untimed and warmup+1..warmup+steps timed.
+    degree: Jacobi-Chebyshev degree (None = plain Jacobi); tune_reps > 0:
+    pick the work decomposition with the autotuner first."""
     import torch
-    ctx = pf.Context(problem, scheme=scheme, precision=precision)
+    opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
+    ctx = pf.Context(problem, scheme=scheme, precision=precision, **opts)
+    ctx.chosen_rows = ctx.autotune(tune_reps) if tune_reps > 0 else None
     if profile:
         ctx.set_profiling(True)
     for n in range(warmup):
@@ -261,10 +278,18 @@ def main():
     ap.add_argument("--workload", default="tension512",
                     choices=["tension512", "tension64", "sweep64", "apply-sizes"])
     ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
+    ap.add_argument("--jacobi", action="store_true",
+                    help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
+    ap.add_argument("--s1-degree", type=int, default=3, help="Chebyshev degree, S1 mixed")
+    ap.add_argument("--st-degree", type=int, default=5, help="Chebyshev degree, ST FP64")
+    ap.add_argument("--tune-reps", type=int, default=10,
+                    help="autotuner launches per candidate (0: library default decomposition)")
     ap.add_argument("--apply-iters", type=int, default=512,
                     help="CG iterations per size in the apply-sizes mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-st", action="store_true", help="skip the ST FP64 comparison run")
+    ap.add_argument("--st-only", action="store_true",
+                    help="time only the ST FP64 run (long histories in separate jobs)")
     ap.add_argument("--full-history", action="store_true",
                     help="time the whole load history (warmup 0, all steps) for both schemes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -302,15 +327,44 @@ def main():
     if args.warmup + args.steps > len(problem.loads):
         raise SystemExit("warmup + steps exceeds the load history")
 
+    s1_deg, st_deg = (None, None) if args.jacobi else (args.s1_degree, args.st_degree)
+    if args.st_only:
+        log(f"ST FP64 on {problem.name}")
+        ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
+                                       degree=st_deg, tune_reps=args.tune_reps)
+        print(json.dumps({
+            "metric": "time per load step, ST FP64 (comparison run)",
+            "value": secs2 * 1e3 / args.steps, "unit": "ms/step", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs2 * 1e3 / args.steps,
+            "higher_is_better": False, "seconds": secs2,
+            "gdof_updates_per_s": sum(r["dof_updates"] for r in rows2) / secs2 / 1e9,
+            "n_stag": [r["n_stag"] for r in rows2],
+            "time_ms": [round(r["time_ms"], 1) for r in rows2],
+            "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
+            "march_rows": ctx2.chosen_rows, "dtype": "f64", "data": "synthetic"}))
+        ctx2.close()
+        return
     log(f"S1 mixed on {problem.name}")
     ctx, rows, secs = run_steps(pf, problem, pf.S1, pf.MIXED, args.warmup, args.steps,
-                                profile=True)
+                                profile=True, degree=s1_deg, tune_reps=args.tune_reps)
     updates = sum(r["dof_updates"] for r in rows)
     value = updates / secs / 1e9
     ms_per_step = secs * 1e3 / args.steps
-    launches, kms, nodes = ctx.kernel_time(0)
-    avg_ms = kms / max(launches, 1)
-    bpn = fused_apply_bytes_per_node()
+    rows_s1 = ctx.chosen_rows if ctx.chosen_rows is not None else ctx.opts.march_rows
+    # dominant kernel per CG iteration of the displacement solves: the fused
+    # apply (one launch) or the Chebyshev steps (degree - 1 launches)
+    la, ma, nodes = ctx.kernel_time(0)
+    lc, mc, _ = ctx.kernel_time(3)
+    t_apply = ma / max(la, 1)
+    t_cheb = mc / max(lc, 1)
+    nsteps = (s1_deg - 1) if s1_deg else 0
+    if lc and nsteps * t_cheb > t_apply:
+        kname = f"k_march<{rows_s1}, OpCheb<OpTangent<float>>> (Jacobi-Chebyshev step)"
+        launches, avg_ms, bpn = lc, t_cheb, cheb_step_bytes_per_node()
+    else:
+        kname = (f"k_cg_apply<{rows_s1}, OpTangent<float>> (fused CG direction update + "
+                 f"tangent apply)")
+        launches, avg_ms, bpn = la, t_apply, fused_apply_bytes_per_node()
     alg_bytes = bpn * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     ctx.close()
@@ -318,12 +372,16 @@ def main():
     st_res = None
     if not args.no_st:
         log(f"ST FP64 on {problem.name}")
-        ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps)
+        ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
+                                       degree=st_deg, tune_reps=args.tune_reps)
         upd2 = sum(r["dof_updates"] for r in rows2)
         st_res = {
             "ms_per_step": secs2 * 1e3 / args.steps,
             "gdof_updates_per_s": upd2 / secs2 / 1e9,
             "n_stag": [r["n_stag"] for r in rows2],
+            "time_ms": [round(r["time_ms"], 1) for r in rows2],
+            "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
+            "march_rows": ctx2.chosen_rows,
         }
         ctx2.close()
 
@@ -351,20 +409,22 @@ def main():
                          f"{args.warmup + args.steps} of {len(problem.loads)} x "
                          f"{problem.loads[0]:.0e} mm"),
             "scheme": "S1", "precision": "mixed (FP32 inner CG, FP64 outer)",
-            "free_dofs_u": None, "tol_stag": problem.tol_stag, "tol_pcg": problem.tol_pcg,
+            "precond": "jacobi" if s1_deg is None else f"jacobi-chebyshev degree {s1_deg}",
+            "march_rows": rows_s1,
+            "tol_stag": problem.tol_stag, "tol_pcg": problem.tol_pcg,
         },
         "s1_mixed": {"n_stag": [r["n_stag"] for r in rows],
                      "time_ms": [round(r["time_ms"], 1) for r in rows]},
         "st_fp64": st_res,
         "speedup_s1_mixed_vs_st_fp64": (st_res["ms_per_step"] / ms_per_step) if st_res else None,
         "roofline": {
-            "kernel": "k_cg_apply<4, OpTangent<float>> (fused CG direction update + tangent apply)",
+            "kernel": kname,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(kname),
             "avg_launch_us": avg_ms * 1e3,
             "sampled_launches": launches,
             "bytes_per_launch": alg_bytes,

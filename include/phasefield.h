@@ -243,10 +243,12 @@ pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
  * enqueued batch, the first iteration's operator kernel (idempotent: it only
  * reads buffers it does not write) is launched four times back to back
  * between one event pair.  Launch counts and elapsed times accumulate.
- * FP64 solves use the single-kernel CG (the timed kernel is a whole
- * iteration); FP32 inner solves use the two-kernel CG (the timed kernel is
- * the fused operator apply, and its vector update is timed once per batch).
- * kernel: 0 = elasticity, 1 = phase, 2 = FP32 vector update.  Enabling
+ * Single-kernel CG solves time that kernel (a whole iteration); two-kernel
+ * CG solves time the fused operator apply, and their vector update once per
+ * batch (one launch between the events).  With Jacobi-Chebyshev the first
+ * polynomial step of the displacement solves (also repeatable) is timed
+ * like the apply.  kernel: 0 = elasticity CG kernel, 1 = phase CG kernel,
+ * 2 = two-kernel vector update, 3 = elasticity Chebyshev step.  Enabling
  * resets the counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,

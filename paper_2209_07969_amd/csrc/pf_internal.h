@@ -231,17 +231,20 @@ hipError_t phase_cg_apply(hipStream_t s, const Grid &g, const March &m, const Ph
 template <class T>
 hipError_t cheb_init(hipStream_t s, int n, const T *r, const T *Dinv, T *d0, T *z, T *res,
                      const CgArgs &ca, const ChebStep &cs);
+// One Chebyshev step: reads z_in/res_in, writes z_out/res_out (distinct
+// buffers, so a launch can be repeated).
 template <class T>
 hipError_t tangent_cheb_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                              int split, const T *ulin, const T *d, const uint8_t *qflag,
                              const uint8_t *eact, const uint8_t *nflag, const T *dprev, T *dnext,
-                             T *z, T *res, const T *r, const T *Dinv, const CgArgs &ca,
-                             const ChebStep &cs);
+                             const T *z_in, T *z_out, const T *res_in, T *res_out, const T *r,
+                             const T *Dinv, const CgArgs &ca, const ChebStep &cs);
 template <class T>
 hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                            const T *coef, const uint8_t *eact, const uint8_t *nflag,
-                           const T *dprev, T *dnext, T *z, T *res, const T *r, const T *Dinv,
-                           const CgArgs &ca, const ChebStep &cs);
+                           const T *dprev, T *dnext, const T *z_in, T *z_out, const T *res_in,
+                           T *res_out, const T *r, const T *Dinv, const CgArgs &ca,
+                           const ChebStep &cs);
 // Power iteration step for lambda_max(D^-1 A): vnext = D^-1 A (scale v);
 // scal[SC_NORM_A] = v'Av and scal[SC_NORM_B] = v'Dv (of the scaled v).
 template <class T>

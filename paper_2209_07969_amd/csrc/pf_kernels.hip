@@ -1367,7 +1367,10 @@ __global__ void __launch_bounds__(TPB) k_cheb_init(int n, const T *r, const T *D
   if (cs.last) block_partial<2>(v, ca.partB);
 }
 
-// Chebyshev step on top of an operator op (its input vector is d_{k-1}).
+// Chebyshev step on top of an operator op (its input vector is d_{k-1}):
+// d_k = c1 d_{k-1} + c2 D^-1 (res - A d_{k-1}), z += d_k, res -= A d_{k-1}.
+// z and res are read from one buffer and written to another, so a launch
+// leaves its inputs intact and may be repeated (timing samples).
 template <class Base>
 struct OpCheb {
   using T = typename Base::T;
@@ -1376,7 +1379,8 @@ struct OpCheb {
   static constexpr int NF = Base::NF;
   static constexpr int NR = 2;
   Base base;
-  const T *r; const T *Dinv; T *dnext; T *z; T *res;
+  const T *r; const T *Dinv; T *dnext;
+  const T *zi; const T *resi; T *zo; T *reso;
   int N;
   T c1, c2;
   int last;
@@ -1396,12 +1400,12 @@ struct OpCheb {
     for (int q = 0; q < NF; ++q) {
       const int idx = k + q * N;
       const T Ad = base.masked(k, q) ? T(0) : v[q];
-      const T rs = res[idx] - Ad;
+      const T rs = resi[idx] - Ad;
       const T dk = c1 * dp[q] + c2 * Dinv[idx] * rs;
-      const T y = z[idx] + dk;
-      res[idx] = rs;
+      const T y = zi[idx] + dk;
+      reso[idx] = rs;
       dnext[idx] = dk;
-      z[idx] = y;
+      zo[idx] = y;
       if (last) {
         const T ri = r[idx];
         red[0] += double(ri) * double(y);
@@ -2175,28 +2179,30 @@ template <class T>
 hipError_t tangent_cheb_step(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
                              int split, const T *ulin, const T *d, const uint8_t *qflag,
                              const uint8_t *eact, const uint8_t *nflag, const T *dprev, T *dnext,
-                             T *z, T *res, const T *r, const T *Dinv, const CgArgs &ca,
-                             const ChebStep &cs) {
+                             const T *z_in, T *z_out, const T *res_in, T *res_out, const T *r,
+                             const T *Dinv, const CgArgs &ca, const ChebStep &cs) {
   if (split == 1) {
     using B = OpTangent<T, false, true, 1>;
     OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), ulin},
-                 r, Dinv, dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+                 r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2),
+                 cs.last};
     return launch_march(s, op, g, m, ca.partB);
   }
   using B = OpTangent<T, false, true, 0>;
   OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), nullptr},
-               r, Dinv, dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+               r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2), cs.last};
   return launch_march(s, op, g, m, ca.partB);
 }
 
 template <class T>
 hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                            const T *coef, const uint8_t *eact, const uint8_t *nflag,
-                           const T *dprev, T *dnext, T *z, T *res, const T *r, const T *Dinv,
-                           const CgArgs &ca, const ChebStep &cs) {
+                           const T *dprev, T *dnext, const T *z_in, T *z_out, const T *res_in,
+                           T *res_out, const T *r, const T *Dinv, const CgArgs &ca,
+                           const ChebStep &cs) {
   using B = OpPhase<T, false, true>;
   OpCheb<B> op{B{g, c, coef, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0)}, r, Dinv,
-               dnext, z, res, g.N, T(cs.c1), T(cs.c2), cs.last};
+               dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2), cs.last};
   return launch_march(s, op, g, m, ca.partB);
 }
 
@@ -2454,12 +2460,14 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
   template hipError_t tangent_cheb_step<T>(hipStream_t, const Grid &, const March &,           \
                                            const ElasCoef &, int, const T *, const T *,        \
                                            const uint8_t *, const uint8_t *, const uint8_t *,  \
-                                           const T *, T *, T *, T *, const T *, const T *,     \
-                                           const CgArgs &, const ChebStep &);                  \
+                                           const T *, T *, const T *, T *, const T *, T *,     \
+                                           const T *, const T *, const CgArgs &,               \
+                                           const ChebStep &);                                  \
   template hipError_t phase_cheb_step<T>(hipStream_t, const Grid &, const March &,             \
                                          const PhaseCoef &, const T *, const uint8_t *,        \
-                                         const uint8_t *, const T *, T *, T *, T *, const T *, \
-                                         const T *, const CgArgs &, const ChebStep &);         \
+                                         const uint8_t *, const T *, T *, const T *, T *,      \
+                                         const T *, T *, const T *, const T *,                 \
+                                         const CgArgs &, const ChebStep &);                    \
   template hipError_t tangent_power_step<T>(hipStream_t, const Grid &, const March &,          \
                                             const ElasCoef &, int, const T *, const T *,       \
                                             const uint8_t *, const uint8_t *, const uint8_t *, \

@@ -55,6 +55,7 @@ struct CgBuf {
   T *Dinv = nullptr;
   T *d = nullptr;      // d in this precision (operator data of the tangent)
   T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
+  T *zc = nullptr, *rc = nullptr;   // second z and residual of the Chebyshev steps
   T *coef = nullptr;   // [4E] phase coefficient
 };
 
@@ -125,8 +126,8 @@ struct pf_ctx {
   // sampled kernel timing
   bool profiling = false;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  int64_t prof_launches[3] = {0, 0, 0};
-  double prof_ms[3] = {0.0, 0.0, 0.0};
+  int64_t prof_launches[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
 
   // step state
   bool step_open = false;
@@ -302,6 +303,11 @@ constexpr int kTimedRepeat = 4;
 // Jacobi-Chebyshev interval [lambda_max / kChebRatio, lambda_max] with
 // lambda_max = kChebSafety x the power-iteration estimate
 constexpr double kChebRatio = 30.0;
+// FP64 iterative refinement of the phase solve (mixed precision): floor of
+// the attainable residual relative to ||b||, and the reduction per pass
+// below which the passes are taken to have stalled
+constexpr double kRefineFloor = 1e-13;
+constexpr double kRefineStall = 0.5;
 constexpr double kChebSafety = 1.2;
 
 template <class T>
@@ -433,21 +439,33 @@ void cheb_steps(double lmax, int m, std::vector<ChebStep> *out) {
 // z = Chebyshev(r) (partials r.z, r.r from the last step)
 template <class T>
 pf_status enqueue_cheb(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n,
-                       const std::vector<ChebStep> &cs, bool first_done) {
+                       const std::vector<ChebStep> &cs, bool first_done, bool timed) {
   CgBuf<T> &b = buf<T>(c);
   T *D[2] = {b.R[1], b.W[1]};
+  // z and the residual alternate between two buffers; the first step
+  // starts from the buffer that makes the last one end in W[0]
+  T *zb[2] = {b.W[0], b.zc}, *rb[2] = {b.S[1], b.rc};
+  const int i0 = (int)((cs.size() - 1) & 1);
   if (!first_done)
-    PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], b.W[0], b.S[1], ca, cs[0]));
+    PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], zb[i0], rb[i0], ca, cs[0]));
   for (size_t k = 1; k < cs.size(); ++k) {
-    if (kind == K_ELASTIC) {
-      PF_HIP(c, tangent_cheb_step<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
-                                     c->eact, c->nflag, D[(k - 1) & 1], D[k & 1], b.W[0], b.S[1],
+    const int in = i0 ^ (int)((k - 1) & 1), out = i0 ^ (int)(k & 1);
+    // the steps leave their inputs intact: the timed sample repeats the first
+    const bool t = timed && k == 1;
+    if (t) PF_HIP(c, hipEventRecord(c->ev[3], st));
+    for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
+      if (kind == K_ELASTIC) {
+        PF_HIP(c, tangent_cheb_step<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                       c->tflag, c->eact, c->nflag, D[(k - 1) & 1], D[k & 1],
+                                       zb[in], zb[out], rb[in], rb[out], b.R[0], b.Dinv, ca,
+                                       cs[k]));
+      } else {
+        PF_HIP(c, phase_cheb_step<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                     D[(k - 1) & 1], D[k & 1], zb[in], zb[out], rb[in], rb[out],
                                      b.R[0], b.Dinv, ca, cs[k]));
-    } else {
-      PF_HIP(c, phase_cheb_step<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
-                                   D[(k - 1) & 1], D[k & 1], b.W[0], b.S[1], b.R[0], b.Dinv, ca,
-                                   cs[k]));
+      }
     }
+    if (t) PF_HIP(c, hipEventRecord(c->ev[4], st));
   }
   return PF_OK;
 }
@@ -473,11 +491,17 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
     }
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
     // Jacobi-Chebyshev: the update also takes the polynomial's first step
+    // (z and residual into the buffers the first Chebyshev step reads)
     ChebFuse<T> cf{nullptr, nullptr, 0.0, 0};
-    if (cs) cf = ChebFuse<T>{b.R[1], b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
-    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca, cf));
+    T *zfirst = b.W[0];
+    if (cs) {
+      const bool odd = (((*cs).size() - 1) & 1) != 0;
+      zfirst = odd ? b.zc : b.W[0];
+      cf = ChebFuse<T>{b.R[1], odd ? b.rc : b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
+    }
+    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], zfirst, pnew, b.S[0], b.Dinv, ca, cf));
     if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
-    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, true));
+    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, true, t && cs->size() > 1));
     std::swap(pold, pnew);
   }
   return PF_OK;
@@ -773,7 +797,7 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
   PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
-  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, false));
+  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, false, false));
   int batch = std::max(4, c->opts.cg_check);
   batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
@@ -818,6 +842,12 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
       c->prof_ms[kid] += a;
       c->prof_launches[2] += 1;
       c->prof_ms[2] += u;
+      if (cheb && cs.size() > 1 && kind == K_ELASTIC) {
+        float q = 0.f;
+        PF_HIP(c, hipEventElapsedTime(&q, c->ev[3], c->ev[4]));
+        c->prof_launches[3] += kTimedRepeat;
+        c->prof_ms[3] += q;
+      }
     }
     if (c->cgs2_h->b.done != 0) break;
   }
@@ -977,11 +1007,16 @@ pf_status phase_solve_impl(pf_ctx *c, const double *Hs, pf_step_stats *st) {
   PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv));
   double nR0 = 0.0, nb = 0.0;
   PF_TRY(phase_res(c, Hs, true, &nR0, &nb));
-  double nR = nR0;
+  double nR = nR0, nR_prev = 0.0;
   const int max_refine = mixed ? 30 : 1;
+  // refinement target: tol_pcg relative to the initial residual, but not
+  // below what an FP64 residual of this system can resolve (kRefineFloor of
+  // ||b||); passes that stop reducing the residual end the loop too
+  const double target = std::max(c->opts.tol_pcg * nR0, kRefineFloor * nb);
   for (int k = 0; k < max_refine; ++k) {
     if (nR == 0.0) break;
-    if (mixed && k > 0 && nR <= c->opts.tol_pcg * nR0) break;
+    if (mixed && k > 0 && (nR <= target || nR > kRefineStall * nR_prev)) break;
+    nR_prev = nR;
     if (mixed) {
       PF_HIP(c, convert<float, double>(c->stream, n, c->bf.R[0], c->Rd));
     } else {
@@ -1295,7 +1330,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     A(&c->bd.R[k], n2); A(&c->bd.W[k], n2); A(&c->bd.S[k], n2); A(&c->bd.X[k], n2);
     A(&c->bd.P[k], n2);
   }
-  A(&c->bd.Dinv, n2); A(&c->bd.coef, E4);
+  A(&c->bd.Dinv, n2); A(&c->bd.coef, E4); A(&c->bd.zc, n2); A(&c->bd.rc, n2);
   if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bd.ulin, n2);
   c->bd.d = c->d;
   if (o.precision == PF_MIXED) {
@@ -1303,7 +1338,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
       A(&c->bf.R[k], n2); A(&c->bf.W[k], n2); A(&c->bf.S[k], n2); A(&c->bf.X[k], n2);
       A(&c->bf.P[k], n2);
     }
-    A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N);
+    A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N); A(&c->bf.zc, n2); A(&c->bf.rc, n2);
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
   A(&c->cgs, 2);
@@ -1517,7 +1552,7 @@ pf_status pf_set_profiling(pf_ctx *c, int32_t enable) {
     for (auto &e : c->ev) PF_HIP(c, hipEventCreate(&e));
   }
   c->profiling = enable != 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     c->prof_launches[k] = 0;
     c->prof_ms[k] = 0.0;
   }
@@ -1526,7 +1561,7 @@ pf_status pf_set_profiling(pf_ctx *c, int32_t enable) {
 
 pf_status pf_kernel_time(pf_ctx *c, int32_t kernel, int64_t *launches, double *total_ms,
                          int64_t *nodes_per_launch) {
-  if (!c || kernel < 0 || kernel > 2) return PF_E_INVALID_ARG;
+  if (!c || kernel < 0 || kernel > 3) return PF_E_INVALID_ARG;
   if (launches) *launches = c->prof_launches[kernel];
   if (total_ms) *total_ms = c->prof_ms[kernel];
   if (nodes_per_launch) *nodes_per_launch = c->g.N;
