@@ -43,6 +43,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time per load history and GDOF-updates/s, S1 mixed vs std FP64, 1 MI355X"
+KIND = {"tension512": "notched tension panel", "tension64": "notched tension panel",
+        "shear1024": "notched shear panel (spectral split)",
+        "lshape2048": "L-shaped panel (masked quadrant)"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -276,7 +279,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tension512",
-                    choices=["tension512", "tension64", "sweep64", "apply-sizes"])
+                    choices=["tension512", "tension64", "shear1024", "lshape2048", "sweep64",
+                             "apply-sizes"])
     ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
     ap.add_argument("--jacobi", action="store_true",
                     help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
@@ -312,7 +316,9 @@ def main():
     if args.workload == "apply-sizes":
         print(json.dumps(run_apply_sizes(pf, args)))
         return
-    problem = {"tension512": W.config_tension512, "tension64": W.config_tension64}[args.workload]()
+    problem = {"tension512": W.config_tension512, "tension64": W.config_tension64,
+               "shear1024": W.config_shear1024,
+               "lshape2048": W.config_lshape2048}[args.workload]()
     if args.full_history:
         args.warmup, args.steps = 0, len(problem.loads)
     if args.copy_calibration:
@@ -404,10 +410,10 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{problem.name}: {problem.nx}x{problem.ny} Q1 notched tension panel, "
+            "workload": (f"{problem.name}: {problem.nx}x{problem.ny} Q1 {KIND[args.workload]}, "
                          f"l={problem.material.l} mm, load steps {args.warmup + 1}.."
                          f"{args.warmup + args.steps} of {len(problem.loads)} x "
-                         f"{problem.loads[0]:.0e} mm"),
+                         f"{problem.loads[0]:.2g} mm"),
             "scheme": "S1", "precision": "mixed (FP32 inner CG, FP64 outer)",
             "precond": "jacobi" if s1_deg is None else f"jacobi-chebyshev degree {s1_deg}",
             "march_rows": rows_s1,

@@ -44,10 +44,12 @@ constexpr int TPB = 256;
 
 // Lane L receives lane L-1's value (lane 0 receives 0).  One DPP
 // whole-wavefront shift per 32-bit word: a plain VALU move, with no LDS
-// crossbar round trip as a general shuffle would need.
+// crossbar round trip as a general shuffle would need.  bound_ctrl makes
+// the hardware write 0 where the source lane does not exist, so no old value
+// has to be set up first.
 constexpr int kDppWaveShr1 = 0x138;
 __device__ inline int lane_up_bits(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, kDppWaveShr1, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0, x, kDppWaveShr1, 0xf, 0xf, true);
 }
 __device__ inline float lane_up(float x) {
   return __int_as_float(lane_up_bits(__float_as_int(x)));
@@ -182,14 +184,21 @@ __device__ inline void elastic_element(const T (&ux)[4], const T (&uy)[4], const
   const T Dbx = ux[1] - ux[0], Dtx = ux[2] - ux[3], Dlx = ux[3] - ux[0], Drx = ux[2] - ux[1];
   const T Dby = uy[1] - uy[0], Dty = uy[2] - uy[3], Dly = uy[3] - uy[0], Dry = uy[2] - uy[1];
   const T ihx = T(c.ihx), ihy = T(c.ihy), twomu = T(c.two_mu), K = T(c.K), eta = T(c.eta);
-  T Ebx = 0, Etx = 0, Elx = 0, Erx = 0, Eby = 0, Ety = 0, Ely = 0, Ery = 0;
+  const T a = T(GA), b = T(GB);
+  // x-derivatives take one value on the bottom QP pair (0, 1) and one on the
+  // top pair (2, 3); y-derivatives one on the left pair (0, 3) and one on
+  // the right pair (1, 2)
+  const T exB = (a * Dbx + b * Dtx) * ihx, exT = (b * Dbx + a * Dtx) * ihx;
+  const T vxB = (a * Dby + b * Dty) * ihx, vxT = (b * Dby + a * Dty) * ihx;
+  const T eyL = (a * Dly + b * Dry) * ihy, eyR = (b * Dly + a * Dry) * ihy;
+  const T uyL = (a * Dlx + b * Drx) * ihy, uyR = (b * Dlx + a * Drx) * ihy;
+  T sxx[4], syy[4], sxy[4];
 #define PF_QP(q)                                                                         \
   {                                                                                      \
-    const T wB = T(QW<q>::wB), wT = T(QW<q>::wT), wL = T(QW<q>::wL), wR = T(QW<q>::wR);  \
-    const T exx = (wB * Dbx + wT * Dtx) * ihx;                                           \
-    const T uxy = (wL * Dlx + wR * Drx) * ihy;                                           \
-    const T uyx = (wB * Dby + wT * Dty) * ihx;                                           \
-    const T eyy = (wL * Dly + wR * Dry) * ihy;                                           \
+    const T exx = (q < 2) ? exB : exT;                                                   \
+    const T uyx = (q < 2) ? vxB : vxT;                                                   \
+    const T eyy = (q == 0 || q == 3) ? eyL : eyR;                                        \
+    const T uxy = (q == 0 || q == 3) ? uyL : uyR;                                        \
     const T dq = interp4<T, q>(dn[0], dn[1], dn[2], dn[3]);                              \
     const T om = T(1) - dq;                                                              \
     const T gq = om * om + eta;                                                          \
@@ -198,17 +207,23 @@ __device__ inline void elastic_element(const T (&ux)[4], const T (&uy)[4], const
     bool act = NONLIN ? (t > T(0)) : (((bits >> q) & 1u) != 0u);                        \
     const T kap = act ? gq * K : K;                                                      \
     const T lq = kap - A2 * T(1.0 / 3.0);                                                \
-    const T sxx = A2 * exx + lq * t;                                                     \
-    const T syy = A2 * eyy + lq * t;                                                     \
-    const T sxy = T(0.5) * A2 * (uxy + uyx);                                             \
-    Ebx += wB * sxx; Etx += wT * sxx; Elx += wL * sxy; Erx += wR * sxy;                  \
-    Eby += wB * sxy; Ety += wT * sxy; Ely += wL * syy; Ery += wR * syy;                  \
+    sxx[q] = A2 * exx + lq * t;                                                          \
+    syy[q] = A2 * eyy + lq * t;                                                          \
+    sxy[q] = T(0.5) * A2 * (uxy + uyx);                                                  \
   }
   PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
 #undef PF_QP
-  const T sx = T(c.sx), sy = T(c.sy);
-  Ebx *= sx; Etx *= sx; Elx *= sy; Erx *= sy;
-  Eby *= sx; Ety *= sx; Ely *= sy; Ery *= sy;
+  // edge duals: each is a weighted sum over a QP pair, with the quadrature
+  // scale folded into the weights
+  const T sa = T(c.sx) * a, sb = T(c.sx) * b, ta = T(c.sy) * a, tb = T(c.sy) * b;
+  const T xB = sxx[0] + sxx[1], xT = sxx[2] + sxx[3];
+  const T yL = syy[0] + syy[3], yR = syy[1] + syy[2];
+  const T sB = sxy[0] + sxy[1], sT = sxy[2] + sxy[3];
+  const T sL = sxy[0] + sxy[3], sR = sxy[1] + sxy[2];
+  const T Ebx = sa * xB + sb * xT, Etx = sb * xB + sa * xT;
+  const T Elx = ta * sL + tb * sR, Erx = tb * sL + ta * sR;
+  const T Eby = sa * sB + sb * sT, Ety = sb * sB + sa * sT;
+  const T Ely = ta * yL + tb * yR, Ery = tb * yL + ta * yR;
   fx[0] = -Ebx - Elx; fx[1] = Ebx - Erx; fx[2] = Etx + Erx; fx[3] = Elx - Etx;
   fy[0] = -Eby - Ely; fy[1] = Eby - Ery; fy[2] = Ety + Ery; fy[3] = Ely - Ety;
 }
