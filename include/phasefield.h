@@ -244,12 +244,15 @@ pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
  * reads buffers it does not write) is launched four times back to back
  * between one event pair.  Launch counts and elapsed times accumulate.
  * Single-kernel CG solves time that kernel (a whole iteration); two-kernel
- * CG solves time the fused operator apply, and their vector update once per
- * batch (one launch between the events).  With Jacobi-Chebyshev the first
- * polynomial step of the displacement solves (also repeatable) is timed
- * like the apply.  kernel: 0 = elasticity CG kernel, 1 = phase CG kernel,
- * 2 = two-kernel vector update, 3 = elasticity Chebyshev step.  Enabling
- * resets the counters. */
+ * CG solves time the fused operator apply and their vector update.  The
+ * update is one launch between the events, except with Jacobi-Chebyshev of
+ * degree >= 2, where it is fused with the first polynomial step into a
+ * repeatable operator kernel timed like the apply.  The next polynomial
+ * step of the displacement solves (degree >= 3, repeatable) is timed too.
+ * kernel: 0 = elasticity CG kernel, 1 = phase CG kernel, 2 = vector update
+ * (fused with the first Chebyshev step where it applies) of the
+ * displacement solves, 3 = elasticity Chebyshev step.  Enabling resets the
+ * counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,
                          int64_t *nodes_per_launch);

@@ -245,6 +245,23 @@ hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const P
                            const T *dprev, T *dnext, const T *z_in, T *z_out, const T *res_in,
                            T *res_out, const T *r, const T *Dinv, const CgArgs &ca,
                            const ChebStep &cs);
+// CG vector update fused with the first Chebyshev step (degree >= 2):
+// x_out = x_in + alpha p and r_out = r_in - alpha q (out of place, so the
+// launch can be repeated); d1 -> dnext, z1 -> z_out, res1 -> res_out; s0 the
+// polynomial's initial step (1/theta), s1 its first step.
+template <class T>
+hipError_t tangent_updcheb(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                           int split, const T *ulin, const T *d, const uint8_t *qflag,
+                           const uint8_t *eact, const uint8_t *nflag, const T *x_in, T *x_out,
+                           const T *r_in, T *r_out, const T *p, const T *q, const T *Dinv,
+                           T *dnext, T *z_out, T *res_out, const CgArgs &ca, const ChebStep &s0,
+                           const ChebStep &s1);
+template <class T>
+hipError_t phase_updcheb(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                         const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                         const T *x_in, T *x_out, const T *r_in, T *r_out, const T *p,
+                         const T *q, const T *Dinv, T *dnext, T *z_out, T *res_out,
+                         const CgArgs &ca, const ChebStep &s0, const ChebStep &s1);
 // Power iteration step for lambda_max(D^-1 A): vnext = D^-1 A (scale v);
 // scal[SC_NORM_A] = v'Av and scal[SC_NORM_B] = v'Dv (of the scaled v).
 template <class T>

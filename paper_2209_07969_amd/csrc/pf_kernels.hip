@@ -1211,6 +1211,78 @@ __global__ void __launch_bounds__(TPB) k_cg_apply(Op op, Grid g, March ms, CgArg
   cg_apply_run<CH>(op, g, ms, ca, blockIdx.x, gridDim.x);
 }
 
+// Prologue of the fused update: the CG state, p.q from the apply's
+// partials and alpha.  Records the exit in the state (bid 0) and returns
+// whether the iteration is active (uniform).
+__device__ inline bool cg_update_prologue(const CgArgs &ca, double *alpha, int bid) {
+  const int done = ca.st->a.done;
+  const double rz = ca.st->a.rz;
+  const double rr0 = ca.st->a.rr0;
+  const int iters = ca.st->a.iters;
+  int exitc = done;
+  double pq = 0.0;
+  if (exitc == 0) {
+    double pqs[1];
+    block_sum<1>(ca.partA, ca.ga, pqs);
+    pq = pqs[0];
+    if (!(pq > 0.0)) exitc = 2;
+  }
+  if (exitc != 0 && bid == 0 && threadIdx.x == 0) {
+    ca.st->b.done = exitc;
+    ca.st->b.iters = iters;
+    ca.st->b.rr0 = rr0;
+    ca.st->b.first = 0;
+  }
+  *alpha = exitc == 0 ? rz / pq : 0.0;
+  return exitc == 0;
+}
+
+// Block bid of nb of the fused update + first Chebyshev step.  Unlike the
+// apply it never exits early: after convergence the step still runs on the
+// unchanged r, as the separate kernels did.
+template <int CH, class Op>
+__device__ inline void cg_updcheb_run(Op op, const Grid &g, const March &ms, const CgArgs &ca,
+                                      int bid, int nb) {
+  double red[2] = {0.0, 0.0};
+  double alpha = 0.0;
+  if constexpr (CH == 1) {
+    __shared__ TileLds<Op> sm;
+    const int nt = ms.nstrips * ms.nchunks;
+    int t = xcd_block(bid, nb);
+    TileRegs<Op> tr;
+    if (t < nt) tile_load(op, ms, t, tr);
+    op.act = cg_update_prologue(ca, &alpha, bid) ? 1 : 0;
+    op.alpha = typename Op::T(alpha);
+    for (; t < nt; t += nb) {
+      tile_compute(op, g, ms, t, tr, sm, red);
+      if (t + nb < nt) tile_load(op, ms, t + nb, tr);
+    }
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int w0 = xcd_block(bid, nb) * WPB + (threadIdx.x >> 6);
+    const int nw = ms.nstrips * ms.nchunks;
+    Item<CH, Op> it;
+    if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
+    op.act = cg_update_prologue(ca, &alpha, bid) ? 1 : 0;
+    op.alpha = typename Op::T(alpha);
+    if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
+    march_items<CH>(op, g, ms, w0 + nb * WPB, nb * WPB, red);
+  }
+  if (op.last) block_partial_at<2>(red, ca.partB, bid);
+  if (op.act && bid == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = ca.st->a.rz;
+    ca.st->b.rr0 = ca.st->a.rr0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = ca.st->a.iters + 1;
+    ca.st->b.first = 0;
+  }
+}
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_cg_updcheb(Op op, Grid g, March ms, CgArgs ca) {
+  cg_updcheb_run<CH>(op, g, ms, ca, blockIdx.x, gridDim.x);
+}
+
 // Elements per thread whose operands are loaded before the scalars.
 constexpr int kUpd = 4;
 
@@ -1425,6 +1497,101 @@ struct OpCheb {
         const T ri = r[idx];
         red[0] += double(ri) * double(y);
         red[1] += double(ri) * double(ri);
+      }
+    }
+  }
+};
+
+// CG vector update fused with the first Chebyshev step (degree >= 2):
+// staged nodes (halo included) take r_new = r - alpha q (when the CG is
+// still active) and d0 = D^-1 r_new / theta; the operator is applied to d0;
+// owned nodes then write x + alpha p and r_new (to the other buffer of the
+// x and r pairs) and the step's outputs res1 = r_new - A d0,
+// d1 = c1 d0 + c2 D^-1 res1, z1 = d0 + d1.  Nothing it reads is written, so
+// a launch may be repeated (timing samples).
+template <class Base>
+struct OpUpdCheb {
+  using T = typename Base::T;
+  using Elem = typename Base::Elem;
+  static constexpr int NF = Base::NF;
+  static constexpr int NR = 2;
+  struct Node {
+    typename Base::Node b;
+    T r[NF], q[NF], di[NF], x[NF], p[NF];
+  };
+  Base base;
+  const T *x; const T *r; T *xo; T *ro; const T *p; const T *q; const T *Dinv;
+  T *dnext; T *zo; T *reso;
+  int N;
+  T alpha, inv_theta, c1, c2;
+  int act, last;
+  __device__ Node load(int i, int j) const {
+    Node n;
+    n.b = base.load_aux(i, j);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) n.r[f] = n.q[f] = n.di[f] = n.x[f] = n.p[f] = T(0);
+    if (node_exists(base.g, i, j)) {
+      const int k = i + j * (base.g.nx + 1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int idx = k + f * N;
+        n.r[f] = r[idx];
+        n.q[f] = q[idx];
+        n.di[f] = Dinv[idx];
+        n.x[f] = x[idx];
+        n.p[f] = p[idx];
+      }
+    }
+    return n;
+  }
+  __device__ void fin(Node &n) const {
+    T d0[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      if (act) n.r[f] = n.r[f] - alpha * n.q[f];
+      d0[f] = n.di[f] * n.r[f] * inv_theta;
+    }
+    base.set_u(n.b, d0);
+  }
+  __device__ Elem eload(int ie, int je) const { return base.eload(ie, je); }
+  static __device__ Node shfl_up(const Node &n) {
+    Node m;
+    m.b = Base::shfl_up(n.b);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      m.r[f] = lane_up(n.r[f]);
+      m.q[f] = T(0);
+      m.di[f] = lane_up(n.di[f]);
+      m.x[f] = lane_up(n.x[f]);
+      m.p[f] = lane_up(n.p[f]);
+    }
+    return m;
+  }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          const Elem &e, T (&f)[NF][4]) const {
+    base.element(n0.b, n1.b, n2.b, n3.b, e, f);
+  }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+    const int k = i + j * (base.g.nx + 1);
+    T d0[NF];
+    base.get_u(n.b, d0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int idx = k + f * N;
+      const T Ad = base.masked(k, f) ? T(0) : v[f];
+      const T rs = n.r[f] - Ad;
+      const T dk = c1 * d0[f] + c2 * n.di[f] * rs;
+      const T y = d0[f] + dk;
+      reso[idx] = rs;
+      dnext[idx] = dk;
+      zo[idx] = y;
+      if (act) {
+        xo[idx] = n.x[f] + alpha * n.p[f];
+        ro[idx] = n.r[f];
+      }
+      if (last) {
+        red[0] += double(n.r[f]) * double(y);
+        red[1] += double(n.r[f]) * double(n.r[f]);
       }
     }
   }
@@ -2182,6 +2349,54 @@ CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, 
   return ca;
 }
 
+template <class Op>
+hipError_t launch_updcheb(hipStream_t s, const Op &op, const Grid &g, const March &m,
+                          const CgArgs &ca) {
+  const dim3 grid(march_blocks(m)), block(TPB);
+  switch (m.ch) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_updcheb<1, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_updcheb<2, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_updcheb<4, Op>), grid, block, 0, s, op, g, m, ca); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_updcheb<8, Op>), grid, block, 0, s, op, g, m, ca); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_updcheb(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                           int split, const T *ulin, const T *d, const uint8_t *qflag,
+                           const uint8_t *eact, const uint8_t *nflag, const T *x_in, T *x_out,
+                           const T *r_in, T *r_out, const T *p, const T *q, const T *Dinv,
+                           T *dnext, T *z_out, T *res_out, const CgArgs &ca, const ChebStep &s0,
+                           const ChebStep &s1) {
+  if (split == 1) {
+    using B = OpTangent<T, false, true, 1>;
+    OpUpdCheb<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), ulin},
+                    x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
+                    T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+    return launch_updcheb(s, op, g, m, ca);
+  }
+  using B = OpTangent<T, false, true, 0>;
+  OpUpdCheb<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), nullptr},
+                  x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
+                  T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+  return launch_updcheb(s, op, g, m, ca);
+}
+
+template <class T>
+hipError_t phase_updcheb(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                         const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                         const T *x_in, T *x_out, const T *r_in, T *r_out, const T *p,
+                         const T *q, const T *Dinv, T *dnext, T *z_out, T *res_out,
+                         const CgArgs &ca, const ChebStep &s0, const ChebStep &s1) {
+  using B = OpPhase<T, false, true>;
+  OpUpdCheb<B> op{B{g, c, coef, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0)}, x_in,
+                  r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
+                  T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+  return launch_updcheb(s, op, g, m, ca);
+}
+
 template <class T>
 hipError_t cheb_init(hipStream_t s, int n, const T *r, const T *Dinv, T *d0, T *z, T *res,
                      const CgArgs &ca, const ChebStep &cs) {
@@ -2483,6 +2698,17 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                          const uint8_t *, const T *, T *, const T *, T *,      \
                                          const T *, T *, const T *, const T *,                 \
                                          const CgArgs &, const ChebStep &);                    \
+  template hipError_t tangent_updcheb<T>(hipStream_t, const Grid &, const March &,             \
+                                         const ElasCoef &, int, const T *, const T *,          \
+                                         const uint8_t *, const uint8_t *, const uint8_t *,    \
+                                         const T *, T *, const T *, T *, const T *, const T *, \
+                                         const T *, T *, T *, T *, const CgArgs &,             \
+                                         const ChebStep &, const ChebStep &);                  \
+  template hipError_t phase_updcheb<T>(hipStream_t, const Grid &, const March &,               \
+                                       const PhaseCoef &, const T *, const uint8_t *,          \
+                                       const uint8_t *, const T *, T *, const T *, T *,        \
+                                       const T *, const T *, const T *, T *, T *, T *,         \
+                                       const CgArgs &, const ChebStep &, const ChebStep &);    \
   template hipError_t tangent_power_step<T>(hipStream_t, const Grid &, const March &,          \
                                             const ElasCoef &, int, const T *, const T *,       \
                                             const uint8_t *, const uint8_t *, const uint8_t *, \

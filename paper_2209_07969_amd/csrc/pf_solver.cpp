@@ -56,6 +56,7 @@ struct CgBuf {
   T *d = nullptr;      // d in this precision (operator data of the tangent)
   T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
   T *zc = nullptr, *rc = nullptr;   // second z and residual of the Chebyshev steps
+  T *dc = nullptr;                  // second Chebyshev step vector
   T *coef = nullptr;   // [4E] phase coefficient
 };
 
@@ -439,30 +440,30 @@ void cheb_steps(double lmax, int m, std::vector<ChebStep> *out) {
 // z = Chebyshev(r) (partials r.z, r.r from the last step)
 template <class T>
 pf_status enqueue_cheb(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca, int n,
-                       const std::vector<ChebStep> &cs, bool first_done, bool timed) {
+                       const std::vector<ChebStep> &cs, bool init, size_t kfirst, bool timed,
+                       const T *rcur) {
   CgBuf<T> &b = buf<T>(c);
-  T *D[2] = {b.R[1], b.W[1]};
+  T *D[2] = {b.W[1], b.dc};
   // z and the residual alternate between two buffers; the first step
   // starts from the buffer that makes the last one end in W[0]
   T *zb[2] = {b.W[0], b.zc}, *rb[2] = {b.S[1], b.rc};
   const int i0 = (int)((cs.size() - 1) & 1);
-  if (!first_done)
-    PF_HIP(c, cheb_init<T>(st, n, b.R[0], b.Dinv, D[0], zb[i0], rb[i0], ca, cs[0]));
-  for (size_t k = 1; k < cs.size(); ++k) {
+  if (init) PF_HIP(c, cheb_init<T>(st, n, rcur, b.Dinv, D[0], zb[i0], rb[i0], ca, cs[0]));
+  for (size_t k = kfirst; k < cs.size(); ++k) {
     const int in = i0 ^ (int)((k - 1) & 1), out = i0 ^ (int)(k & 1);
     // the steps leave their inputs intact: the timed sample repeats the first
-    const bool t = timed && k == 1;
+    const bool t = timed && k == kfirst;
     if (t) PF_HIP(c, hipEventRecord(c->ev[3], st));
     for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
       if (kind == K_ELASTIC) {
         PF_HIP(c, tangent_cheb_step<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
                                        c->tflag, c->eact, c->nflag, D[(k - 1) & 1], D[k & 1],
-                                       zb[in], zb[out], rb[in], rb[out], b.R[0], b.Dinv, ca,
+                                       zb[in], zb[out], rb[in], rb[out], rcur, b.Dinv, ca,
                                        cs[k]));
       } else {
         PF_HIP(c, phase_cheb_step<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
                                      D[(k - 1) & 1], D[k & 1], zb[in], zb[out], rb[in], rb[out],
-                                     b.R[0], b.Dinv, ca, cs[k]));
+                                     rcur, b.Dinv, ca, cs[k]));
       }
     }
     if (t) PF_HIP(c, hipEventRecord(c->ev[4], st));
@@ -475,6 +476,10 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
                          bool time_first, const std::vector<ChebStep> *cs) {
   CgBuf<T> &b = buf<T>(c);
   T *pold = b.P[0], *pnew = b.P[1];
+  // Jacobi-Chebyshev of degree >= 2: the update is fused with the first
+  // polynomial step and writes x and r to the other buffer of each pair, so
+  // iteration k (counted from an even start) reads X[k&1], R[k&1]
+  const bool fused = cs && cs->size() >= 2;
   for (int k = 0; k < iters; ++k) {
     // the apply kernel is idempotent (it rewrites p_new, q and its partials
     // from inputs it does not modify): the timed sample repeats it
@@ -490,18 +495,34 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
       }
     }
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
-    // Jacobi-Chebyshev: the update also takes the polynomial's first step
-    // (z and residual into the buffers the first Chebyshev step reads)
-    ChebFuse<T> cf{nullptr, nullptr, 0.0, 0};
-    T *zfirst = b.W[0];
-    if (cs) {
-      const bool odd = (((*cs).size() - 1) & 1) != 0;
-      zfirst = odd ? b.zc : b.W[0];
-      cf = ChebFuse<T>{b.R[1], odd ? b.rc : b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
+    if (fused) {
+      const int par = k & 1;
+      const int i0 = (int)((cs->size() - 1) & 1);
+      T *zb[2] = {b.W[0], b.zc}, *rb[2] = {b.S[1], b.rc};
+      for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
+        if (kind == K_ELASTIC) {
+          PF_HIP(c, tangent_updcheb<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d, c->tflag,
+                                       c->eact, c->nflag, b.X[par], b.X[par ^ 1], b.R[par],
+                                       b.R[par ^ 1], pnew, b.S[0], b.Dinv, b.dc, zb[i0 ^ 1],
+                                       rb[i0 ^ 1], ca, (*cs)[0], (*cs)[1]));
+        } else {
+          PF_HIP(c, phase_updcheb<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                     b.X[par], b.X[par ^ 1], b.R[par], b.R[par ^ 1], pnew, b.S[0],
+                                     b.Dinv, b.dc, zb[i0 ^ 1], rb[i0 ^ 1], ca, (*cs)[0],
+                                     (*cs)[1]));
+        }
+      }
+      if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
+      PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, false, 2, t && cs->size() > 2,
+                             b.R[par ^ 1]));
+    } else {
+      // Jacobi, or Chebyshev of degree 1: the update also takes the
+      // polynomial's only step (z and residual into W[0] and S[1])
+      ChebFuse<T> cf{nullptr, nullptr, 0.0, 0};
+      if (cs) cf = ChebFuse<T>{b.W[1], b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
+      PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca, cf));
+      if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
     }
-    PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], zfirst, pnew, b.S[0], b.Dinv, ca, cf));
-    if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
-    if (cs) PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, true, t && cs->size() > 1));
     std::swap(pold, pnew);
   }
   return PF_OK;
@@ -797,7 +818,7 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
   PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
-  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, false, false));
+  if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, true, 1, false, b.R[0]));
   int batch = std::max(4, c->opts.cg_check);
   batch += batch & 1;
   const int kid = (kind == K_ELASTIC) ? 0 : 1;
@@ -840,9 +861,13 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
       PF_HIP(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
       c->prof_launches[kid] += kTimedRepeat;
       c->prof_ms[kid] += a;
-      c->prof_launches[2] += 1;
-      c->prof_ms[2] += u;
-      if (cheb && cs.size() > 1 && kind == K_ELASTIC) {
+      // displacement solves only; the fused update + first Chebyshev step
+      // is repeated like the apply
+      if (kind == K_ELASTIC) {
+        c->prof_launches[2] += (cheb && cs.size() > 1) ? kTimedRepeat : 1;
+        c->prof_ms[2] += u;
+      }
+      if (cheb && cs.size() > 2 && kind == K_ELASTIC) {
         float q = 0.f;
         PF_HIP(c, hipEventElapsedTime(&q, c->ev[3], c->ev[4]));
         c->prof_launches[3] += kTimedRepeat;
@@ -853,7 +878,9 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
   }
   *iters = c->cgs2_h->b.iters;
   *status = c->cgs2_h->b.done;
-  *xout = b.X[0];
+  // the fused update alternates the x buffers: the last active iteration
+  // wrote X[iters & 1]
+  *xout = (cheb && cs.size() >= 2) ? b.X[*iters & 1] : b.X[0];
   return PF_OK;
 }
 
@@ -1330,7 +1357,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     A(&c->bd.R[k], n2); A(&c->bd.W[k], n2); A(&c->bd.S[k], n2); A(&c->bd.X[k], n2);
     A(&c->bd.P[k], n2);
   }
-  A(&c->bd.Dinv, n2); A(&c->bd.coef, E4); A(&c->bd.zc, n2); A(&c->bd.rc, n2);
+  A(&c->bd.Dinv, n2); A(&c->bd.coef, E4); A(&c->bd.zc, n2); A(&c->bd.rc, n2); A(&c->bd.dc, n2);
   if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bd.ulin, n2);
   c->bd.d = c->d;
   if (o.precision == PF_MIXED) {
@@ -1338,7 +1365,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
       A(&c->bf.R[k], n2); A(&c->bf.W[k], n2); A(&c->bf.S[k], n2); A(&c->bf.X[k], n2);
       A(&c->bf.P[k], n2);
     }
-    A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N); A(&c->bf.zc, n2); A(&c->bf.rc, n2);
+    A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N); A(&c->bf.zc, n2); A(&c->bf.rc, n2); A(&c->bf.dc, n2);
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
   A(&c->cgs, 2);

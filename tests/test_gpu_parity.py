@@ -112,12 +112,17 @@ def test_lshape_masked_history_fp64(gpu_lib, scheme):
     compare_history(gpu_lib, p, scheme, 0, 3, 1e-7)
 
 
+@pytest.mark.parametrize("rows", [0, 1])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_chebyshev_preconditioner_history(gpu_lib, precision):
-    """Jacobi-Chebyshev preconditioned solves reach the same fixed points."""
+def test_chebyshev_preconditioner_history(gpu_lib, precision, degree, rows):
+    """Jacobi-Chebyshev preconditioned solves reach the same fixed points:
+    degree 1 (update only), 2 (fused update is the last step), 3 and 4 (odd
+    and even buffer alternation), on both work decompositions."""
     p = W.tension_panel(n=16, l=0.1, du=1e-3, steps=6)
     orc = Oracle(p, 1)
-    ctx = gpu_lib.Context(p, scheme=1, precision=precision, precond=1, cheb_degree=3)
+    ctx = gpu_lib.Context(p, scheme=1, precision=precision, precond=1, cheb_degree=degree,
+                          march_rows=rows)
     for lam in p.loads:
         so = orc.load_step(float(lam))
         sg = ctx.load_step(float(lam))
@@ -128,6 +133,15 @@ def test_chebyshev_preconditioner_history(gpu_lib, precision):
             assert rel_l2(u, soa(orc.u)) <= (1e-7 if precision == 0 else 1e-6)
             assert np.abs(d - orc.d).max() <= 1e-5
     ctx.close()
+
+
+def test_chebyshev_spectral_masked(gpu_lib):
+    """Jacobi-Chebyshev on the spectral shear panel (mixed) and the masked
+    L-shape (FP64)."""
+    compare_history(gpu_lib, W.shear_panel(n=16, l=0.1, du=2e-3, steps=8), 3, 1, 8, 1e-6,
+                    precond=1, cheb_degree=3)
+    compare_history(gpu_lib, W.lshape_panel(n=32, steps=10, total=0.3), 1, 0, 3, 1e-7,
+                    precond=1, cheb_degree=5)
 
 
 def _ragged_panel():
