@@ -13,7 +13,9 @@ history: the staggered iterations until ||R_d||/||b|| <= 1e-5, each with the
 QP update, the S1 trial solve and predictor, the phase solve, the Newton
 displacement solve (PCG with fused reductions) and the reaction force.
 Both schemes use Jacobi-Chebyshev preconditioning (degree 3 for the FP32
-inner solves, 5 for FP64) and the work decomposition the autotuner picks.
+inner solves, 5 for FP64) and the work decomposition measured fastest for
+each on this mesh: LDS tiles for S1 mixed, column marching with 2 rows for
+ST FP64 (--tune-reps N lets the autotuner choose instead).
 W warmup steps (load steps 1..W) run untimed, then K load steps are timed.
 
 value = GDOF-updates/s of S1 mixed over the timed steps (sum over all CG
@@ -23,7 +25,8 @@ device synchronisations).  Inputs are resident in HBM before timing.
 Two further modes print their own single JSON line:
   --workload sweep64     the seeded 64-instance tension sweep (mesh sizes
                          128..512, Gc, l and notch drawn per instance), S1
-                         mixed with autotuned work items: load steps W+1..W+K
+                         mixed, column marching with 4 rows per wave (one
+                         shared launch per operator kind): load steps W+1..W+K
                          of every instance, batched with shared CG launches
                          (value), batched on concurrent streams, and one by
                          one;
@@ -118,14 +121,14 @@ def load_step_logged(ctx, problem, lam, every=25):
 
 
 def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degree=None,
-              tune_reps=0):
+              tune_reps=0, rows=0):
     """Run load steps 1..warmup untimed and warmup+1..warmup+steps timed.
-    degree: Jacobi-Chebyshev degree (None = plain Jacobi); tune_reps > 0:
-    pick the work decomposition with the autotuner first."""
+    degree: Jacobi-Chebyshev degree (None = plain Jacobi); rows: work
+    decomposition (march_rows); tune_reps > 0: let the autotuner pick it."""
     import torch
     opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
-    ctx = pf.Context(problem, scheme=scheme, precision=precision, **opts)
-    ctx.chosen_rows = ctx.autotune(tune_reps) if tune_reps > 0 else None
+    ctx = pf.Context(problem, scheme=scheme, precision=precision, march_rows=rows, **opts)
+    ctx.chosen_rows = ctx.autotune(tune_reps) if tune_reps > 0 else rows
     if profile:
         ctx.set_profiling(True)
     for n in range(warmup):
@@ -198,8 +201,8 @@ def run_sweep(pf, args):
     # one by one: each instance alone on the default stream
     chosen, t_seq, upd_seq, forces_seq = [], 0.0, 0.0, []
     for i, p in enumerate(probs):
-        ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED)
-        chosen.append(ctx.autotune(10))
+        ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED, march_rows=args.sweep_rows)
+        chosen.append(ctx.autotune(10) if args.sweep_rows == 0 else args.sweep_rows)
         for n in range(warm):
             ctx.load_step(float(p.loads[n]))
         torch.cuda.synchronize()
@@ -311,8 +314,17 @@ def main():
                     help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
     ap.add_argument("--s1-degree", type=int, default=3, help="Chebyshev degree, S1 mixed")
     ap.add_argument("--st-degree", type=int, default=5, help="Chebyshev degree, ST FP64")
-    ap.add_argument("--tune-reps", type=int, default=10,
-                    help="autotuner launches per candidate (0: library default decomposition)")
+    ap.add_argument("--rows", type=int, default=-1,
+                    help="work decomposition of the S1 mixed run (march_rows: 0 library "
+                         "choice, 1 LDS tiles, 2/4/8 column marching); default: LDS tiles at "
+                         "512^2, library choice else")
+    ap.add_argument("--st-rows", type=int, default=-1,
+                    help="work decomposition of the ST FP64 run; default: column marching with "
+                         "2 rows at 512^2, library choice else")
+    ap.add_argument("--tune-reps", type=int, default=0,
+                    help="autotuner launches per candidate (0: keep --rows)")
+    ap.add_argument("--sweep-rows", type=int, default=4,
+                    help="work decomposition of every sweep instance (0: autotune each)")
     ap.add_argument("--apply-iters", type=int, default=512,
                     help="CG iterations per size in the apply-sizes mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -341,6 +353,10 @@ def main():
     if args.workload == "apply-sizes":
         print(json.dumps(run_apply_sizes(pf, args)))
         return
+    if args.rows < 0:
+        args.rows = 1 if args.workload == "tension512" else 0
+    if args.st_rows < 0:
+        args.st_rows = 2 if args.workload == "tension512" else 0
     problem = {"tension512": W.config_tension512, "tension64": W.config_tension64,
                "shear1024": W.config_shear1024,
                "lshape2048": W.config_lshape2048}[args.workload]()
@@ -362,7 +378,7 @@ def main():
     if args.st_only:
         log(f"ST FP64 on {problem.name}")
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
-                                       degree=st_deg, tune_reps=args.tune_reps)
+                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows)
         print(json.dumps({
             "metric": "time per load step, ST FP64 (comparison run)",
             "value": secs2 * 1e3 / args.steps, "unit": "ms/step", "n_gpus": 1,
@@ -377,7 +393,8 @@ def main():
         return
     log(f"S1 mixed on {problem.name}")
     ctx, rows, secs = run_steps(pf, problem, pf.S1, pf.MIXED, args.warmup, args.steps,
-                                profile=True, degree=s1_deg, tune_reps=args.tune_reps)
+                                profile=True, degree=s1_deg, tune_reps=args.tune_reps,
+                                rows=args.rows)
     updates = sum(r["dof_updates"] for r in rows)
     value = updates / secs / 1e9
     ms_per_step = secs * 1e3 / args.steps
@@ -407,7 +424,7 @@ def main():
     if not args.no_st:
         log(f"ST FP64 on {problem.name}")
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
-                                       degree=st_deg, tune_reps=args.tune_reps)
+                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows)
         upd2 = sum(r["dof_updates"] for r in rows2)
         st_res = {
             "ms_per_step": secs2 * 1e3 / args.steps,
