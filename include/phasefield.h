@@ -105,6 +105,7 @@ typedef struct {
                         /* per iteration, FP32: two), 1 = one kernel per      */
                         /* iteration (Chronopoulos-Gear recurrences, one      */
                         /* reduction), 2 = two kernels (standard recurrences) */
+  double cheb_ratio;    /* Jacobi-Chebyshev interval [lmax/ratio, lmax]; 0 = 30 */
 } pf_solver_opts;
 
 typedef struct {
@@ -128,7 +129,7 @@ typedef struct {
 /* Fill *opts with defaults: ST, FP64, Jacobi (cheb_degree 3), tol_stag 1e-5, tol_pcg 1e-10,
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
- * march_rows 0, cg_kernels 0. */
+ * march_rows 0, cg_kernels 0, cheb_ratio 0 (30). */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

@@ -55,7 +55,8 @@ class SolverOpts(ctypes.Structure):
                 ("tol_newton", c_double), ("tol_inner", c_double), ("max_stag", c_int32),
                 ("max_newton", c_int32), ("max_cg", c_int32), ("cg_check", c_int32),
                 ("psi_crit", c_double), ("d_gate", c_double), ("trial_floor", c_double),
-                ("march_rows", c_int32), ("cg_kernels", c_int32)]
+                ("march_rows", c_int32), ("cg_kernels", c_int32),
+                ("cheb_ratio", c_double)]
 
 
 class StepStats(ctypes.Structure):

@@ -171,6 +171,16 @@ __device__ inline bool node_exists(const Grid &g, int i, int j) {
   return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
 }
 
+// Data an operator needs only at the nodes a work item stores: fetched with
+// the item's first loads (load_own) instead of after the element maths, so
+// no dependent memory round trip remains at the end of a kernel.
+struct OwnFlag { uint8_t nf; };
+__device__ inline OwnFlag load_flag(const uint8_t *nflag, const Grid &g, int i, int j) {
+  OwnFlag o{0};
+  if (nflag != nullptr && node_exists(g, i, j)) o.nf = nflag[i + j * (g.nx + 1)];
+  return o;
+}
+
 // --------------------------------------------------------- element maths
 
 // Elasticity, volumetric-deviatoric split.  sigma = A2 eps + (kap - A2/3) t I
@@ -478,6 +488,7 @@ template <int CH, class Op>
 struct Item {
   typename Op::Node R[CH + 2];
   typename Op::Elem El[CH + 1];
+  typename Op::Own O[CH];   // the lane's stored column, rows j0 .. j0+CH-1
 };
 
 template <int CH, class Op>
@@ -492,6 +503,8 @@ __device__ inline void item_load(const Op &op, const Grid &g, const March &ms, i
 #pragma unroll
   for (int r = 0; r < CH + 1; ++r)
     it.El[r] = (lane > 0) ? op.eload(c - 1, j0 - 1 + r) : typename Op::Elem{};
+#pragma unroll
+  for (int r = 0; r < CH; ++r) it.O[r] = op.load_own(c - 1, j0 + r);
 }
 
 template <int CH, class Op>
@@ -528,7 +541,7 @@ __device__ inline void item_compute(const Op &op, const Grid &g, const March &ms
       c3[k] = f[k][3];
       c2[k] = f[k][2];
     }
-    if (r >= 1 && own_col && je <= g.ny) op.store(n, je, out, bl, red);
+    if (r >= 1 && own_col && je <= g.ny) op.store(n, je, out, bl, it.O[r - 1], red);
     bl = tl;
     br = tr;
   }
@@ -573,6 +586,7 @@ template <class Op>
 struct TileRegs {
   typename Op::Node n[kTileLoads];
   typename Op::Elem e;
+  typename Op::Own o;   // the thread's owned node
 };
 
 template <class Op>
@@ -585,6 +599,8 @@ __device__ inline void tile_load(const Op &op, const March &ms, int tile, TileRe
     if (k < kTileN * kTileN) tr.n[r] = op.load(i0 + k % kTileN, j0 + k / kTileN);
   }
   tr.e = op.eload(i0 + threadIdx.x % kTileE, j0 + threadIdx.x / kTileE);
+  if (threadIdx.x < kTile * kTile)
+    tr.o = op.load_own(i0 + 1 + threadIdx.x % kTile, j0 + 1 + threadIdx.x / kTile);
 }
 
 template <class Op>
@@ -625,7 +641,7 @@ __device__ inline void tile_compute(const Op &op, const Grid &g, const March &ms
       for (int q = 0; q < NF; ++q)
         out[q] = sm.f[q][2][e] + sm.f[q][3][e + 1] + sm.f[q][1][e + kTileE] +
                  sm.f[q][0][e + kTileE + 1];
-      op.store(i, j, out, sm.node[(lj + 1) * kTileN + li + 1], red);
+      op.store(i, j, out, sm.node[(lj + 1) * kTileN + li + 1], tr.o, red);
     }
   }
   __syncthreads();   // the LDS is reused by the block's next tile
@@ -743,6 +759,11 @@ struct OpTangent {
   __device__ bool masked(int k, int q) const {
     return (nflag[k] & (q == 0 ? NF_UX : NF_UY)) != 0;
   }
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  static __device__ bool masked_own(const Own &o, int q) {
+    return (o.nf & (q == 0 ? NF_UX : NF_UY)) != 0;
+  }
   __device__ Elem eload(int ie, int je) const {
     Elem e{0, 0};
     if (elem_exists(g, ie, je, eact)) {
@@ -774,13 +795,13 @@ struct OpTangent {
       elastic_element<T, false>(ux, uy, dn, e.bits, c, f[0], f[1]);
     }
   }
-  __device__ void store(int i, int j, const T (&v)[2], const Node &n, double *red) const {
+  __device__ void store(int i, int j, const T (&v)[2], const Node &n, const Own &o,
+                        double *red) const {
     const int k = i + j * (g.nx + 1);
     T qx = v[0], qy = v[1];
     if (MASK) {
-      const uint8_t nf = nflag[k];
-      if (nf & NF_UX) qx = T(0);
-      if (nf & NF_UY) qy = T(0);
+      if (o.nf & NF_UX) qx = T(0);
+      if (o.nf & NF_UY) qy = T(0);
     }
     q[k] = qx;
     q[k + g.N] = qy;
@@ -821,6 +842,9 @@ struct OpPhase {
   __device__ void set_u(Node &n, const T (&u)[1]) const { n.p = u[0]; }
   __device__ void get_u(const Node &n, T (&u)[1]) const { u[0] = n.p; }
   __device__ bool masked(int k, int) const { return (nflag[k] & NF_D) != 0; }
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  static __device__ bool masked_own(const Own &o, int) { return (o.nf & NF_D) != 0; }
   __device__ Elem eload(int ie, int je) const {
     Elem e{};
     if (elem_exists(g, ie, je, eact)) {
@@ -844,10 +868,11 @@ struct OpPhase {
     const T cq[4] = {e.c[0], e.c[1], e.c[2], e.c[3]};
     phase_element<T>(p, cq, c, f[0]);
   }
-  __device__ void store(int i, int j, const T (&v)[1], const Node &n, double *red) const {
+  __device__ void store(int i, int j, const T (&v)[1], const Node &n, const Own &o,
+                        double *red) const {
     const int k = i + j * (g.nx + 1);
     T qv = v[0];
-    if (MASK && (nflag[k] & NF_D)) qv = T(0);
+    if (MASK && (o.nf & NF_D)) qv = T(0);
     q[k] = qv;
     if (FUSED) {
       pnew[k] = n.p;
@@ -897,14 +922,14 @@ struct OpForce {
     if (SPL == 1) spectral_element<double, true>(ux, uy, dn, ux, uy, c, f[0], f[1]);
     else elastic_element<double, true>(ux, uy, dn, 0u, c, f[0], f[1]);
   }
-  __device__ void store(int i, int j, const double (&v)[2], const Node &, double *red) const {
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  __device__ void store(int i, int j, const double (&v)[2], const Node &, const Own &o,
+                        double *red) const {
     const int k = i + j * (g.nx + 1);
     double rx = v[0], ry = v[1];
-    if (nflag != nullptr) {
-      const uint8_t nf = nflag[k];
-      if (nf & NF_UX) rx = 0.0;
-      if (nf & NF_UY) ry = 0.0;
-    }
+    if (o.nf & NF_UX) rx = 0.0;
+    if (o.nf & NF_UY) ry = 0.0;
     R[k] = sign * rx;
     R[k + g.N] = sign * ry;
     red[0] += rx * rx + ry * ry;
@@ -963,10 +988,13 @@ struct OpPhaseRes {
 #pragma unroll
     for (int a = 0; a < 4; ++a) f[0][a] -= f[1][a];
   }
-  __device__ void store(int i, int j, const double (&v)[2], const Node &, double *red) const {
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  __device__ void store(int i, int j, const double (&v)[2], const Node &, const Own &o,
+                        double *red) const {
     const int k = i + j * (g.nx + 1);
     double r = v[0], b = v[1];
-    if (nflag[k] & NF_D) { r = 0.0; b = 0.0; }
+    if (o.nf & NF_D) { r = 0.0; b = 0.0; }
     R[k] = sign * r;
     red[0] += r * r;
     red[1] += b * b;
@@ -1025,11 +1053,13 @@ struct OpTangentDiag {
       elastic_diag_element<T>(dn, e.bits, c, f[0], f[1]);
     }
   }
-  __device__ void store(int i, int j, const T (&v)[2], const Node &, double *) const {
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  __device__ void store(int i, int j, const T (&v)[2], const Node &, const Own &o,
+                        double *) const {
     const int k = i + j * (g.nx + 1);
-    const uint8_t nf = nflag[k];
-    Dinv[k] = ((nf & NF_UX) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
-    Dinv[k + g.N] = ((nf & NF_UY) || !(v[1] > T(0))) ? T(0) : T(1) / v[1];
+    Dinv[k] = ((o.nf & NF_UX) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+    Dinv[k + g.N] = ((o.nf & NF_UY) || !(v[1] > T(0))) ? T(0) : T(1) / v[1];
   }
 };
 
@@ -1066,9 +1096,12 @@ struct OpPhaseDiag {
     const T cq[4] = {e.c[0], e.c[1], e.c[2], e.c[3]};
     phase_diag_element<T>(cq, c, f[0]);
   }
-  __device__ void store(int i, int j, const T (&v)[1], const Node &, double *) const {
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  __device__ void store(int i, int j, const T (&v)[1], const Node &, const Own &o,
+                        double *) const {
     const int k = i + j * (g.nx + 1);
-    Dinv[k] = ((nflag[k] & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+    Dinv[k] = ((o.nf & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
   }
 };
 
@@ -1479,24 +1512,46 @@ struct OpCheb {
                           const Elem &e, T (&f)[NF][4]) const {
     base.element(n0, n1, n2, n3, e, f);
   }
-  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+  struct Own {
+    typename Base::Own b;
+    T res[NF], z[NF], di[NF], r[NF];
+  };
+  __device__ Own load_own(int i, int j) const {
+    Own o;
+    o.b = base.load_own(i, j);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) o.res[q] = o.z[q] = o.di[q] = o.r[q] = T(0);
+    if (node_exists(base.g, i, j)) {
+      const int k = i + j * (base.g.nx + 1);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const int idx = k + q * N;
+        o.res[q] = resi[idx];
+        o.z[q] = zi[idx];
+        o.di[q] = Dinv[idx];
+        if (last) o.r[q] = r[idx];
+      }
+    }
+    return o;
+  }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, const Own &o,
+                        double *red) const {
     const int k = i + j * (base.g.nx + 1);
     T dp[NF];
     base.get_u(n, dp);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       const int idx = k + q * N;
-      const T Ad = base.masked(k, q) ? T(0) : v[q];
-      const T rs = resi[idx] - Ad;
-      const T dk = c1 * dp[q] + c2 * Dinv[idx] * rs;
-      const T y = zi[idx] + dk;
+      const T Ad = Base::masked_own(o.b, q) ? T(0) : v[q];
+      const T rs = o.res[q] - Ad;
+      const T dk = c1 * dp[q] + c2 * o.di[q] * rs;
+      const T y = o.z[q] + dk;
       reso[idx] = rs;
       dnext[idx] = dk;
       zo[idx] = y;
       if (last) {
-        const T ri = r[idx];
-        red[0] += double(ri) * double(y);
-        red[1] += double(ri) * double(ri);
+        red[0] += double(o.r[q]) * double(y);
+        red[1] += double(o.r[q]) * double(o.r[q]);
       }
     }
   }
@@ -1571,14 +1626,17 @@ struct OpUpdCheb {
                           const Elem &e, T (&f)[NF][4]) const {
     base.element(n0.b, n1.b, n2.b, n3.b, e, f);
   }
-  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+  using Own = typename Base::Own;
+  __device__ Own load_own(int i, int j) const { return base.load_own(i, j); }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, const Own &o,
+                        double *red) const {
     const int k = i + j * (base.g.nx + 1);
     T d0[NF];
     base.get_u(n.b, d0);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int idx = k + f * N;
-      const T Ad = base.masked(k, f) ? T(0) : v[f];
+      const T Ad = Base::masked_own(o, f) ? T(0) : v[f];
       const T rs = n.r[f] - Ad;
       const T dk = c1 * d0[f] + c2 * n.di[f] * rs;
       const T y = d0[f] + dk;
@@ -1623,15 +1681,32 @@ struct OpPower {
                           const Elem &e, T (&f)[NF][4]) const {
     base.element(n0, n1, n2, n3, e, f);
   }
-  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, double *red) const {
+  struct Own {
+    typename Base::Own b;
+    T di[NF];
+  };
+  __device__ Own load_own(int i, int j) const {
+    Own o;
+    o.b = base.load_own(i, j);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) o.di[q] = T(0);
+    if (node_exists(base.g, i, j)) {
+      const int k = i + j * (base.g.nx + 1);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) o.di[q] = Dinv[k + q * N];
+    }
+    return o;
+  }
+  __device__ void store(int i, int j, const T (&v)[NF], const Node &n, const Own &o,
+                        double *red) const {
     const int k = i + j * (base.g.nx + 1);
     T vv[NF];
     base.get_u(n, vv);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       const int idx = k + q * N;
-      const T di = Dinv[idx];
-      const T Av = base.masked(k, q) ? T(0) : v[q];
+      const T di = o.di[q];
+      const T Av = Base::masked_own(o.b, q) ? T(0) : v[q];
       vnext[idx] = di * Av;
       red[0] += double(vv[q]) * double(Av);
       if (di > T(0)) red[1] += double(vv[q]) * double(vv[q]) / double(di);

@@ -422,8 +422,8 @@ pf_status estimate_lmax(pf_ctx *c, Kind kind, double *out) {
 }
 
 // Chebyshev coefficients for degree m on [lmax / ratio, lmax]
-void cheb_steps(double lmax, int m, std::vector<ChebStep> *out) {
-  const double hi = lmax, lo = lmax / kChebRatio;
+void cheb_steps(double lmax, int m, double ratio, std::vector<ChebStep> *out) {
+  const double hi = lmax, lo = lmax / ratio;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   out->clear();
   double rho = 1.0 / sigma;
@@ -813,7 +813,8 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
       PF_TRY(estimate_lmax<T>(c, kind, &est));
       lm = kChebSafety * est;
     }
-    cheb_steps(lm, std::max(1, c->opts.cheb_degree), &cs);
+    cheb_steps(lm, std::max(1, c->opts.cheb_degree),
+               c->opts.cheb_ratio > 0 ? c->opts.cheb_ratio : kChebRatio, &cs);
     ca.ext = 1;
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
@@ -1215,6 +1216,10 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   }
   if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) { *msg = "iteration limits"; return PF_E_INVALID_ARG; }
   if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
+  if (!(o->cheb_ratio >= 0) || (o->cheb_ratio > 0 && o->cheb_ratio <= 1)) {
+    *msg = "cheb_ratio must be 0 or > 1";
+    return PF_E_INVALID_ARG;
+  }
   if (o->cg_kernels < 0 || o->cg_kernels > 2) {
     *msg = "cg_kernels must be 0, 1 or 2";
     return PF_E_INVALID_ARG;
@@ -1342,6 +1347,10 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   c->pc = PhaseCoef{mt.Gc * mt.l, mt.Gc / mt.l, g.hx * g.hy / 4.0, 1.0 / g.hx, 1.0 / g.hy,
                     g.hy / 4.0, g.hx / 4.0};
   c->ms = march_shape(g, o.march_rows);
+  // the spectral tangent's 8-row marching item does not fit the register
+  // file (it spills); its default is at most 4 rows
+  if (o.march_rows == 0 && mat->split == PF_SPLIT_SPECTRAL && c->ms.ch == 8)
+    c->ms = march_shape(g, 4);
 
   pf_status s = PF_OK;
   auto A = [&](auto **p, size_t n) {

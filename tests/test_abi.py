@@ -62,6 +62,6 @@ def test_create_rejects_bad_arguments_without_device():
 def test_struct_layouts_match_header():
     import paper_2209_07969_amd as pf
     # 4 int32 + 4 double + 4 int32 + 3 double + 2 int32
-    assert ctypes.sizeof(pf.SolverOpts) == 4 * 4 + 4 * 8 + 4 * 4 + 3 * 8 + 2 * 4
+    assert ctypes.sizeof(pf.SolverOpts) == 4 * 4 + 4 * 8 + 4 * 4 + 3 * 8 + 2 * 4 + 8
     assert ctypes.sizeof(pf.MeshDesc) == 8 + 16 + 8
     assert ctypes.sizeof(pf.MaterialDesc) == 5 * 8 + 8
