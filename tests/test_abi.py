@@ -65,3 +65,34 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(pf.SolverOpts) == 4 * 4 + 4 * 8 + 4 * 4 + 3 * 8 + 2 * 4 + 8
     assert ctypes.sizeof(pf.MeshDesc) == 8 + 16 + 8
     assert ctypes.sizeof(pf.MaterialDesc) == 5 * 8 + 8
+
+
+def test_option_validation_without_device():
+    """Every out-of-range option is rejected by pf_create before any device
+    call (status 1 = PF_E_INVALID_ARG)."""
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    mesh = pf.MeshDesc(4, 4, 1.0, 1.0, None)
+    mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
+    cases = {"cheb_ratio": 0.5, "cg_kernels": 3, "march_rows": 3, "cheb_degree": 0,
+             "max_cg": 0, "max_stag": 0, "scheme": 7, "precision": 2, "precond": 5}
+    for name, value in cases.items():
+        o = pf.default_opts()
+        o.precond = 1          # Jacobi-Chebyshev, so that cheb_degree is checked
+        setattr(o, name, value)
+        h = ctypes.c_void_p()
+        st = lib.pf_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(o), None,
+                           ctypes.byref(h))
+        assert st == 1, (name, value, st)
+        assert not h.value
+
+
+def test_batch_and_allocator_argument_checks_without_device():
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    out = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.pf_batch_create(0, arr, 0, ctypes.byref(out)) == 1
+    assert lib.pf_batch_create(1, arr, 0, ctypes.byref(out)) == 1   # null member
+    assert lib.pf_batch_set_shared_launches(None, 1) == 1
+    assert lib.pf_set_allocator(None, pf.ALLOC_FN(), pf.RELEASE_FN(), None) == 1

@@ -36,15 +36,19 @@ def test_batch_matches_sequential(gpu_lib):
 
 
 def _mixed_members():
-    """Uneven mixed-precision members: two work-item heights, a spectral
-    member and a masked L-shape, so the shared launches hold several apply
-    groups and both operator kinds."""
+    """Uneven mixed-precision members: several work decompositions, a
+    spectral member, a masked L-shape and a Chebyshev-preconditioned member,
+    so the shared launches hold several apply groups and both operator
+    kinds while one member solves on its own stream."""
     return [
         (W.tension_panel(n=16, l=0.1, du=1e-3, steps=4, notch=0.5), 1, {}),
         (W.tension_panel(n=24, l=0.1, du=1e-3, steps=4, notch=0.375), 1, {"march_rows": 2}),
         (W.tension_panel(n=20, l=0.1, du=1e-3, steps=4, notch=0.45), 0, {"march_rows": 8}),
         (W.shear_panel(n=16, l=0.1, du=2e-3, steps=4), 3, {}),
         (W.lshape_panel(n=32, steps=4, total=0.12), 1, {}),
+        # Jacobi-Chebyshev member: its solves stay on its own stream
+        (W.tension_panel(n=18, l=0.1, du=1e-3, steps=4, notch=0.4), 1,
+         {"precond": 1, "cheb_degree": 3, "march_rows": 1}),
     ]
 
 
