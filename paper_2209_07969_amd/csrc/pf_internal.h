@@ -136,9 +136,14 @@ struct CgArgs {
 // One Jacobi-Chebyshev step (z = p(D^-1 A) D^-1 r by Chebyshev iteration on
 // A y = r from y = 0): d_0 = D^-1 r / theta; d_k = c1 d_{k-1} + c2 D^-1 res_k;
 // y_{k+1} = y_k + d_k; res_{k+1} = res_k - A d_k.
+// One step of the Jacobi-Chebyshev polynomial.  The coefficients live in
+// device memory (coef[0] = 1/theta, coef[2k-1], coef[2k] = c1, c2 of step
+// k >= 1), so captured CG batches stay valid when lambda_max is
+// re-estimated; `last` marks the step that writes the r.z, r.r partials.
+constexpr int kChebCoefs = 33;   // 1 + 2 x (16 - 1) + 2 spare
 struct ChebStep {
-  double inv_theta;
-  double c1, c2;
+  const double *coef;
+  int k;
   int last;
 };
 
@@ -210,7 +215,7 @@ template <class T>
 struct ChebFuse {
   T *d0;
   T *res;
-  double inv_theta;
+  const double *coef;   // coef[0] = 1/theta
   int last;
 };
 template <class T>

@@ -756,8 +756,8 @@ struct OpTangent {
     u[0] = n.px;
     u[1] = n.py;
   }
-  __device__ bool masked(int k, int q) const {
-    return (nflag[k] & (q == 0 ? NF_UX : NF_UY)) != 0;
+  __device__ bool masked(int k, int comp) const {
+    return (nflag[k] & (comp == 0 ? NF_UX : NF_UY)) != 0;
   }
   using Own = OwnFlag;
   __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
@@ -1351,7 +1351,7 @@ __device__ inline void cg_update_run(int n, T *__restrict__ x, T *__restrict__ r
   const bool fused = cf.d0 != nullptr;
   const bool ext = ca.ext != 0 && !fused;
   const bool parts = !ext && (!fused || cf.last);
-  const T it = T(cf.inv_theta);
+  const T it = fused ? T(cf.coef[0]) : T(0);
   // the first group's operands are in flight while the scalars are reduced
   T xv[kUpd], pv[kUpd], qv[kUpd], rv[kUpd], dv[kUpd];
   upd_load(n, i0, stride, x, p, q, r, Dinv, ext, xv, pv, qv, rv, dv);
@@ -1452,7 +1452,7 @@ __global__ void __launch_bounds__(TPB) k_cg_update_batch(const BatchUpdateEntry<
                                                          const int *bmap) {
   const BatchUpdateEntry<T> &e = tab[bmap[blockIdx.x]];
   const int bid = blockIdx.x - e.b0;
-  const ChebFuse<T> none{nullptr, nullptr, 0.0, 0};
+  const ChebFuse<T> none{nullptr, nullptr, nullptr, 0};
   cg_update_run<T>(e.n, e.x, e.r, e.z, e.p, e.q, e.Dinv, e.ca, none, bid, e.nb);
   // the thread that wrote this system's CG state also publishes it
   if (bid == 0 && threadIdx.x == 0) {
@@ -1474,7 +1474,7 @@ template <class T>
 __global__ void __launch_bounds__(TPB) k_cheb_init(int n, const T *r, const T *Dinv, T *d0, T *z,
                                                    T *res, CgArgs ca, ChebStep cs) {
   double v[2] = {0.0, 0.0};
-  const T it = T(cs.inv_theta);
+  const T it = T(cs.coef[0]);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const T ri = r[i];
     const T di = Dinv[i] * ri * it;
@@ -1502,7 +1502,8 @@ struct OpCheb {
   const T *r; const T *Dinv; T *dnext;
   const T *zi; const T *resi; T *zo; T *reso;
   int N;
-  T c1, c2;
+  const double *cf;   // device coefficients
+  int step;           // this is step `step` >= 1 of the polynomial
   int last;
   __device__ Node load(int i, int j) const { return base.load(i, j); }
   __device__ void fin(Node &n) const { base.fin(n); }
@@ -1537,6 +1538,7 @@ struct OpCheb {
   __device__ void store(int i, int j, const T (&v)[NF], const Node &n, const Own &o,
                         double *red) const {
     const int k = i + j * (base.g.nx + 1);
+    const T c1 = T(cf[2 * step - 1]), c2 = T(cf[2 * step]);
     T dp[NF];
     base.get_u(n, dp);
 #pragma unroll
@@ -1578,7 +1580,8 @@ struct OpUpdCheb {
   const T *x; const T *r; T *xo; T *ro; const T *p; const T *q; const T *Dinv;
   T *dnext; T *zo; T *reso;
   int N;
-  T alpha, inv_theta, c1, c2;
+  const double *cf;   // device coefficients: cf[0] = 1/theta, cf[1], cf[2] = step 1
+  T alpha;
   int act, last;
   __device__ Node load(int i, int j) const {
     Node n;
@@ -1604,7 +1607,7 @@ struct OpUpdCheb {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (act) n.r[f] = n.r[f] - alpha * n.q[f];
-      d0[f] = n.di[f] * n.r[f] * inv_theta;
+      d0[f] = n.di[f] * n.r[f] * T(cf[0]);
     }
     base.set_u(n.b, d0);
   }
@@ -1638,7 +1641,7 @@ struct OpUpdCheb {
       const int idx = k + f * N;
       const T Ad = Base::masked_own(o, f) ? T(0) : v[f];
       const T rs = n.r[f] - Ad;
-      const T dk = c1 * d0[f] + c2 * n.di[f] * rs;
+      const T dk = T(cf[1]) * d0[f] + T(cf[2]) * n.di[f] * rs;
       const T y = d0[f] + dk;
       reso[idx] = rs;
       dnext[idx] = dk;
@@ -2448,14 +2451,14 @@ hipError_t tangent_updcheb(hipStream_t s, const Grid &g, const March &m, const E
   if (split == 1) {
     using B = OpTangent<T, false, true, 1>;
     OpUpdCheb<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), ulin},
-                    x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
-                    T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+                    x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s1.coef,
+                    T(0), 0, s1.last};
     return launch_updcheb(s, op, g, m, ca);
   }
   using B = OpTangent<T, false, true, 0>;
   OpUpdCheb<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), nullptr},
-                  x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
-                  T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+                  x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s1.coef,
+                  T(0), 0, s1.last};
   return launch_updcheb(s, op, g, m, ca);
 }
 
@@ -2467,8 +2470,8 @@ hipError_t phase_updcheb(hipStream_t s, const Grid &g, const March &m, const Pha
                          const CgArgs &ca, const ChebStep &s0, const ChebStep &s1) {
   using B = OpPhase<T, false, true>;
   OpUpdCheb<B> op{B{g, c, coef, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0)}, x_in,
-                  r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, T(0),
-                  T(s0.inv_theta), T(s1.c1), T(s1.c2), 0, s1.last};
+                  r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s1.coef, T(0), 0,
+                  s1.last};
   return launch_updcheb(s, op, g, m, ca);
 }
 
@@ -2489,13 +2492,12 @@ hipError_t tangent_cheb_step(hipStream_t s, const Grid &g, const March &m, const
   if (split == 1) {
     using B = OpTangent<T, false, true, 1>;
     OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), ulin},
-                 r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2),
-                 cs.last};
+                 r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, cs.coef, cs.k, cs.last};
     return launch_march(s, op, g, m, ca.partB);
   }
   using B = OpTangent<T, false, true, 0>;
   OpCheb<B> op{B{g, c, d, qflag, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0), nullptr},
-               r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2), cs.last};
+               r, Dinv, dnext, z_in, res_in, z_out, res_out, g.N, cs.coef, cs.k, cs.last};
   return launch_march(s, op, g, m, ca.partB);
 }
 
@@ -2507,7 +2509,7 @@ hipError_t phase_cheb_step(hipStream_t s, const Grid &g, const March &m, const P
                            const ChebStep &cs) {
   using B = OpPhase<T, false, true>;
   OpCheb<B> op{B{g, c, coef, eact, nflag, dprev, nullptr, nullptr, nullptr, T(0)}, r, Dinv,
-               dnext, z_in, res_in, z_out, res_out, g.N, T(cs.c1), T(cs.c2), cs.last};
+               dnext, z_in, res_in, z_out, res_out, g.N, cs.coef, cs.k, cs.last};
   return launch_march(s, op, g, m, ca.partB);
 }
 

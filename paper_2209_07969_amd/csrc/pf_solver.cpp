@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <map>
 #include <memory>
@@ -57,6 +58,7 @@ struct CgBuf {
   T *ulin = nullptr;   // [2N] linearisation point of the spectral tangent
   T *zc = nullptr, *rc = nullptr;   // second z and residual of the Chebyshev steps
   T *dc = nullptr;                  // second Chebyshev step vector
+  T *pv[2] = {nullptr, nullptr};    // power-iteration vectors per operator kind
   T *coef = nullptr;   // [4E] phase coefficient
 };
 
@@ -117,8 +119,14 @@ struct pf_ctx {
   hipStream_t cap_stream = nullptr;
   bool use_graphs = true;
 
-  // Jacobi-Chebyshev: lambda_max(D^-1 A) estimates per [kind][fp32]
+  // Jacobi-Chebyshev: lambda_max(D^-1 A) per [kind][fp32], re-estimated
+  // for every solve from the previous power vector (0: no usable vector,
+  // the next estimate starts cold); the polynomial's coefficients in device
+  // memory (slot 2 kind + fp32) and a pinned mirror
   double lmax[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double pscale[2][2] = {{1.0, 1.0}, {1.0, 1.0}};
+  double *cheb_dev = nullptr;
+  double *cheb_h = nullptr;
 
   // shared CG launches of a batch (set only inside pf_batch_load_step)
   BatchSvc *svc = nullptr;
@@ -304,6 +312,8 @@ constexpr int kTimedRepeat = 4;
 // Jacobi-Chebyshev interval [lambda_max / kChebRatio, lambda_max] with
 // lambda_max = kChebSafety x the power-iteration estimate
 constexpr double kChebRatio = 30.0;
+constexpr int kPowerCold = 20;
+constexpr int kPowerWarm = 6;
 // FP64 iterative refinement of the phase solve (mixed precision): floor of
 // the attainable residual relative to ||b||, and the reduction per pass
 // below which the passes are taken to have stalled
@@ -392,47 +402,90 @@ pf_status cg_graph(pf_ctx *c, Kind kind, const Cg1Args &a, double tol, int niter
 
 // ---- two-kernel CG (standard recurrences), used for the FP32 inner solves.
 // Buffers: x = X[0], r = R[0], z = W[0], p_old/p_new = P[0]/P[1], q = S[0].
-// lambda_max of D^-1 A by 20 power-iteration steps on the current operator
-// (Rayleigh quotient in the D inner product), once per solve kind and
-// precision; b.Dinv must be set.  Buffers R[1]/W[1] serve as scratch.
+// lambda_max(D^-1 A) by power iteration (Rayleigh quotient in the D inner
+// product); b.Dinv must be set and W[1] serves as scratch.  The first
+// estimate runs kPowerCold steps from a fixed start, renormalising after
+// each.  Later ones continue from the previous vector for kPowerWarm steps,
+// so the estimate follows the operator as the damage grows; they keep the
+// previous normalisation (the operator changes little between solves, and
+// the Rayleigh quotient does not depend on the scale), so their launches
+// queue back to back and only the last step's sums are read.  A warm
+// estimate that comes out degenerate falls back to a cold one.  Both step
+// counts are even, so the latest vector ends in b.pv[kind].
+template <class T>
+pf_status power_step(pf_ctx *c, Kind kind, const T *v, T *vn, double scale) {
+  CgBuf<T> &b = buf<T>(c);
+  if (kind == K_ELASTIC) {
+    PF_HIP(c, tangent_power_step<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                    c->tflag, c->eact, c->nflag, v, vn, b.Dinv, scale, c->rs));
+  } else {
+    PF_HIP(c, phase_power_step<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, v,
+                                  vn, b.Dinv, scale, c->rs));
+  }
+  return PF_OK;
+}
+
 template <class T>
 pf_status estimate_lmax(pf_ctx *c, Kind kind, double *out) {
   CgBuf<T> &b = buf<T>(c);
   const int n = (kind == K_ELASTIC) ? 2 * c->g.N : c->g.N;
-  PF_HIP(c, power_start<T>(c->stream, n, b.Dinv, b.R[1]));
-  T *v = b.R[1], *vn = b.W[1];
-  double scale = 1.0, lam = 0.0;
-  for (int it = 0; it < 20; ++it) {
-    if (kind == K_ELASTIC) {
-      PF_HIP(c, tangent_power_step<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
-                                      c->tflag, c->eact, c->nflag, v, vn, b.Dinv, scale, c->rs));
-    } else {
-      PF_HIP(c, phase_power_step<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, v,
-                                    vn, b.Dinv, scale, c->rs));
+  const int fp32 = std::is_same<T, float>::value ? 1 : 0;
+  T *v = b.pv[kind], *vn = b.W[1];
+  if (c->lmax[kind][fp32] > 0.0) {
+    const double scale = c->pscale[kind][fp32];
+    for (int it = 0; it < kPowerWarm; ++it) {
+      PF_TRY(power_step<T>(c, kind, v, vn, scale));
+      std::swap(v, vn);
     }
     PF_TRY(read_scal(c));
     const double A = c->scal_h[SC_NORM_A], B = c->scal_h[SC_NORM_B];
-    if (!(B > 0.0) || !(A > 0.0)) break;
+    if (B > 0.0 && A > 0.0 && std::isfinite(A) && std::isfinite(B)) {
+      const double lam = A / B;
+      c->pscale[kind][fp32] = 1.0 / (lam * std::sqrt(B));
+      c->lmax[kind][fp32] = lam;
+      *out = lam;
+      return PF_OK;
+    }
+  }
+  PF_HIP(c, power_start<T>(c->stream, n, b.Dinv, b.pv[kind]));
+  v = b.pv[kind];
+  vn = b.W[1];
+  double scale = 1.0, lam = 0.0;
+  for (int it = 0; it < kPowerCold; ++it) {
+    PF_TRY(power_step<T>(c, kind, v, vn, scale));
+    PF_TRY(read_scal(c));
+    const double A = c->scal_h[SC_NORM_A], B = c->scal_h[SC_NORM_B];
+    if (!(B > 0.0) || !(A > 0.0) || !std::isfinite(A) || !std::isfinite(B)) {
+      // a degenerate operator (nothing free): no vector to continue from
+      c->lmax[kind][fp32] = 0.0;
+      *out = lam > 0.0 ? lam : 4.0;
+      return PF_OK;
+    }
     lam = A / B;
     scale = 1.0 / (lam * std::sqrt(B));
     std::swap(v, vn);
   }
-  *out = lam > 0.0 ? lam : 4.0;
+  c->pscale[kind][fp32] = scale;
+  c->lmax[kind][fp32] = lam;
+  *out = lam;
   return PF_OK;
 }
 
-// Chebyshev coefficients for degree m on [lmax / ratio, lmax]
-void cheb_steps(double lmax, int m, double ratio, std::vector<ChebStep> *out) {
+// Chebyshev coefficients for degree m on [lmax / ratio, lmax], written to
+// host[] (coef layout of ChebStep); the steps point at the device copy dev.
+void cheb_steps(double lmax, int m, double ratio, const double *dev, double *host,
+                std::vector<ChebStep> *out) {
   const double hi = lmax, lo = lmax / ratio;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   out->clear();
   double rho = 1.0 / sigma;
-  ChebStep s0{1.0 / theta, 0.0, 0.0, m == 1 ? 1 : 0};
-  out->push_back(s0);
+  host[0] = 1.0 / theta;
+  out->push_back(ChebStep{dev, 0, m == 1 ? 1 : 0});
   for (int k = 1; k < m; ++k) {
     const double rn = 1.0 / (2.0 * sigma - rho);
-    ChebStep sk{1.0 / theta, rn * rho, 2.0 * rn / delta, k == m - 1 ? 1 : 0};
-    out->push_back(sk);
+    host[2 * k - 1] = rn * rho;
+    host[2 * k] = 2.0 * rn / delta;
+    out->push_back(ChebStep{dev, k, k == m - 1 ? 1 : 0});
     rho = rn;
   }
 }
@@ -518,8 +571,8 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
     } else {
       // Jacobi, or Chebyshev of degree 1: the update also takes the
       // polynomial's only step (z and residual into W[0] and S[1])
-      ChebFuse<T> cf{nullptr, nullptr, 0.0, 0};
-      if (cs) cf = ChebFuse<T>{b.W[1], b.S[1], (*cs)[0].inv_theta, (*cs)[0].last};
+      ChebFuse<T> cf{nullptr, nullptr, nullptr, 0};
+      if (cs) cf = ChebFuse<T>{b.W[1], b.S[1], (*cs)[0].coef, (*cs)[0].last};
       PF_HIP(c, cg_update<T>(st, n, b.X[0], b.R[0], b.W[0], pnew, b.S[0], b.Dinv, ca, cf));
       if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
     }
@@ -807,14 +860,15 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
   const bool cheb = c->opts.precond == PF_PC_JACOBI_CHEBYSHEV;
   std::vector<ChebStep> cs;
   if (cheb) {
-    double &lm = c->lmax[kind][fp32];
-    if (lm == 0.0) {
-      double est = 0.0;
-      PF_TRY(estimate_lmax<T>(c, kind, &est));
-      lm = kChebSafety * est;
-    }
-    cheb_steps(lm, std::max(1, c->opts.cheb_degree),
-               c->opts.cheb_ratio > 0 ? c->opts.cheb_ratio : kChebRatio, &cs);
+    double est = 0.0;
+    PF_TRY(estimate_lmax<T>(c, kind, &est));
+    const int slot = 2 * (int)kind + fp32;
+    double *dev = c->cheb_dev + slot * kChebCoefs, *host = c->cheb_h + slot * kChebCoefs;
+    cheb_steps(kChebSafety * est, std::max(1, c->opts.cheb_degree),
+               c->opts.cheb_ratio > 0 ? c->opts.cheb_ratio : kChebRatio, dev, host, &cs);
+    // the previous solve of this kind has finished, so its copy has too
+    PF_HIP(c, hipMemcpyAsync(dev, host, kChebCoefs * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
     ca.ext = 1;
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
@@ -1367,6 +1421,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     A(&c->bd.P[k], n2);
   }
   A(&c->bd.Dinv, n2); A(&c->bd.coef, E4); A(&c->bd.zc, n2); A(&c->bd.rc, n2); A(&c->bd.dc, n2);
+  A(&c->bd.pv[0], n2); A(&c->bd.pv[1], n2);
   if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bd.ulin, n2);
   c->bd.d = c->d;
   if (o.precision == PF_MIXED) {
@@ -1375,8 +1430,10 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
       A(&c->bf.P[k], n2);
     }
     A(&c->bf.Dinv, n2); A(&c->bf.coef, E4); A(&c->bf.d, g.N); A(&c->bf.zc, n2); A(&c->bf.rc, n2); A(&c->bf.dc, n2);
+    A(&c->bf.pv[0], n2); A(&c->bf.pv[1], n2);
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
+  A(&c->cheb_dev, 4 * (size_t)kChebCoefs);
   A(&c->cgs, 2);
   A(&c->cgs2, 1);
   A(&c->cgpart, 6 * (size_t)kPMax);
@@ -1394,7 +1451,8 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     if (hipHostMalloc((void **)&c->cgs_h, 2 * sizeof(Cg1State)) != hipSuccess ||
         hipHostMalloc((void **)&c->cgs2_h, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess)
+        hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void **)&c->cheb_h, 4 * kChebCoefs * sizeof(double)) != hipSuccess)
       s = PF_E_OOM;
   }
   if (s == PF_OK) s = upload_constraints(c);
@@ -1423,6 +1481,7 @@ pf_status pf_destroy(pf_ctx *c) {
   if (c->cgs2_h) (void)hipHostFree(c->cgs2_h);
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
+  if (c->cheb_h) (void)hipHostFree(c->cheb_h);
   delete c;
   return PF_OK;
 }
