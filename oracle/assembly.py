@@ -77,8 +77,14 @@ def at2_coefficient(H, Gc, l):
     return Gc / l + 2.0 * H
 
 
-def trial_coefficient(c, cS, gate, theta):
-    """Mass coefficient of K_dd + K~ on gated points, floored at theta*c."""
-    ct = np.where(gate, np.maximum(c - cS, theta * c), c)
-    hits = int(np.count_nonzero(gate & (c - cS < theta * c)))
-    return ct, hits
+def trial_coefficient(c, cS, gate, theta, floor=True):
+    """Mass coefficient of K_dd + K~ (Section 3.4): c - c_S on gated points,
+    c elsewhere.  With floor, a gated coefficient below theta*c is raised to
+    theta*c; without, it is kept as it is (it may be negative, and K_dd + K~
+    indefinite).  hits counts the gated points below theta*c either way."""
+    below = gate & (c - cS < theta * c)
+    if floor:
+        ct = np.where(gate, np.maximum(c - cS, theta * c), c)
+    else:
+        ct = np.where(gate, c - cS, c)
+    return ct, int(np.count_nonzero(below))

@@ -19,6 +19,15 @@ One load step n at load factor lambda_n, from the committed state
    equation with that energy frozen (the AT2 equation is linear, so this
    is one solve).  ST skips the trial.  Then Newton for u at the new d, and
    recompute H and r.  The count N_stag includes the k = 0 u-solve.
+   Two literal readings of the trial are options of the problem:
+   * trial_operator = 1 keeps the mass coefficient c - c_S of K_dd + K~
+     unfloored, so the block may be indefinite (Section 3.4 prints no floor);
+     the direct solve gives its exact solution;
+   * trial_update = 1 takes d^{k+1} = d^k + Dd as the phase update and skips
+     the energy update and the corrected solve (the end of Section 3.5 notes
+     that AT2 with a history variable needs no energy update because its
+     equation is linear).  Ungated iterations take the standard solve, which
+     is the same update with K~ = 0.
 3. Commit u_n, d_n, H_n = max(H_{n-1}, Psi^+(u_n)) (the predicted energy is
    never stored) and the reaction force of the loaded Dirichlet group.
 """
@@ -166,11 +175,13 @@ class Oracle:
 
     def trial_increment(self, d, H, gate, psi_s):
         """First Newton iteration of the evolution equation with the augmented
-        block K_dd + K~ (eq_staggered_NR), K~ only on gated points, floored."""
+        block K_dd + K~ (eq_staggered_NR), K~ only on gated points; its mass
+        coefficient floored at theta c unless trial_operator = 1."""
         dq = self.mesh.interp(d)
         c = asm.at2_coefficient(H, self.Gc, self.l)
         cS = coupling_coefficient(dq, self.eta, psi_s)
-        ct, hits = asm.trial_coefficient(c, cS, gate, self.p.trial_floor)
+        literal = int(getattr(self.p, "trial_operator", 0)) == 1
+        ct, hits = asm.trial_coefficient(c, cS, gate, self.p.trial_floor, floor=not literal)
         A = asm.phase_matrix(self.mesh, ct, self.Gc, self.l)
         K, b = self.phase_system(H)
         Rd = K @ d - b
@@ -207,8 +218,10 @@ class Oracle:
         parts = self.energies(u, d)
         H = np.maximum(H_prev, parts["psi_plus"])
         r = self.stag_residual(d, H)
+        trial_only = int(getattr(p, "trial_update", 0)) == 1
         while r > p.tol_stag and st.n_stag < p.max_stag:
             H_hat = H
+            ng = 0
             if self.scheme != 0:
                 dq = self.mesh.interp(d)
                 psi = parts["psi_plus"]
@@ -220,10 +233,14 @@ class Oracle:
                     dd, hits = self.trial_increment(d, H, gate, psi_s)
                     st.n_trial += 1
                     st.floor_hits += hits
-                    ddq = self.mesh.interp(dd)
-                    psi_hat = predicted_energy(psi, psi_s, dq, self.eta, ddq, gate)
-                    H_hat = np.maximum(H, psi_hat)
-            d = self.solve_phase(H_hat, d)
+                    if trial_only:
+                        d = d + dd
+                    else:
+                        ddq = self.mesh.interp(dd)
+                        psi_hat = predicted_energy(psi, psi_s, dq, self.eta, ddq, gate)
+                        H_hat = np.maximum(H, psi_hat)
+            if not (trial_only and ng > 0):
+                d = self.solve_phase(H_hat, d)
             u, nit, ok = self.newton(u, d, R_ref)
             st.n_newton += nit
             st.converged &= ok

@@ -83,6 +83,8 @@ class Problem:
     psi_crit: float = -1.0             # < 0 means Gc / (c_w l) with c_w = 2
     d_gate: float = 0.95
     trial_floor: float = 0.1
+    trial_operator: int = 0            # 0: mass coefficient floored at theta c; 1: unfloored
+    trial_update: int = 0              # 0: trial -> predict -> correct; 1: d += trial increment
 
     @property
     def n_nodes(self) -> int:
