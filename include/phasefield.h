@@ -63,9 +63,27 @@ typedef enum { PF_SPLIT_VD = 0, PF_SPLIT_SPECTRAL = 1 } pf_split;
 typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
 
 /* Preconditioner of the linear solves: Jacobi, or Jacobi-Chebyshev (m
- * Chebyshev steps on D^-1 A over [lambda_max/30, lambda_max], lambda_max from
- * a power iteration once per context and solve kind, times 1.2). */
+ * Chebyshev steps on D^-1 A over [lambda_max/30, lambda_max], lambda_max times
+ * 1.2 from a power iteration that continues from the previous solve's vector
+ * for every solve). */
 typedef enum { PF_PC_JACOBI = 0, PF_PC_JACOBI_CHEBYSHEV = 1 } pf_precond;
+
+/* Trial block K_dd + K~ of S1/S2/S3 (Section 3.4).  FLOORED raises a gated
+ * mass coefficient c - c_S below theta*c (trial_floor) to theta*c, so the
+ * block stays SPD and is solved by PCG.  UNFLOORED keeps c - c_S as it is:
+ * the block may be indefinite and is solved by MINRES in FP64 with
+ * M = |diag| (tol_pcg on the M^-1 norm of the residual, at most max_cg
+ * iterations). */
+typedef enum { PF_TRIAL_FLOORED = 0, PF_TRIAL_UNFLOORED = 1 } pf_trial_operator;
+
+/* What the trial increment Dd feeds.  PREDICT_CORRECT: the predicted
+ * energy (Sections 3.3, 3.5), then the evolution solve with it frozen.
+ * TRIAL_ONLY: d^{k+1} = d^k + Dd directly, with no energy update and no
+ * corrected solve (the end of Section 3.5 notes that linear AT2 with a
+ * history variable needs no energy update); ungated iterations take the
+ * standard solve.  The trial-only increment is computed in FP64 in either
+ * precision. */
+typedef enum { PF_TRIAL_PREDICT_CORRECT = 0, PF_TRIAL_ONLY = 1 } pf_trial_update;
 
 typedef struct {
   int32_t nx, ny;              /* elements per direction, >= 1              */
@@ -106,6 +124,8 @@ typedef struct {
                         /* iteration (Chronopoulos-Gear recurrences, one      */
                         /* reduction), 2 = two kernels (standard recurrences) */
   double cheb_ratio;    /* Jacobi-Chebyshev interval [lmax/ratio, lmax]; 0 = 30 */
+  int32_t trial_operator; /* pf_trial_operator                                */
+  int32_t trial_update;   /* pf_trial_update                                  */
 } pf_solver_opts;
 
 typedef struct {
@@ -129,7 +149,8 @@ typedef struct {
 /* Fill *opts with defaults: ST, FP64, Jacobi (cheb_degree 3), tol_stag 1e-5, tol_pcg 1e-10,
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
- * march_rows 0, cg_kernels 0, cheb_ratio 0 (30). */
+ * march_rows 0, cg_kernels 0, cheb_ratio 0 (30), trial_operator FLOORED,
+ * trial_update PREDICT_CORRECT. */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

@@ -56,7 +56,8 @@ class SolverOpts(ctypes.Structure):
                 ("max_newton", c_int32), ("max_cg", c_int32), ("cg_check", c_int32),
                 ("psi_crit", c_double), ("d_gate", c_double), ("trial_floor", c_double),
                 ("march_rows", c_int32), ("cg_kernels", c_int32),
-                ("cheb_ratio", c_double)]
+                ("cheb_ratio", c_double), ("trial_operator", c_int32),
+                ("trial_update", c_int32)]
 
 
 class StepStats(ctypes.Structure):
@@ -190,7 +191,7 @@ class Context:
         o.scheme = int(scheme)
         o.precision = int(precision)
         for name in ("tol_stag", "tol_pcg", "tol_newton", "max_stag", "max_newton",
-                     "psi_crit", "d_gate", "trial_floor"):
+                     "psi_crit", "d_gate", "trial_floor", "trial_operator", "trial_update"):
             if hasattr(p, name):
                 setattr(o, name, getattr(p, name))
         for k, v in overrides.items():

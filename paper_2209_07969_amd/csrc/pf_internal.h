@@ -133,10 +133,10 @@ struct CgArgs {
   int npb;    // number of (r.z, r.r) partials the apply prologue reduces
 };
 
-// One Jacobi-Chebyshev step (z = p(D^-1 A) D^-1 r by Chebyshev iteration on
-// A y = r from y = 0): d_0 = D^-1 r / theta; d_k = c1 d_{k-1} + c2 D^-1 res_k;
-// y_{k+1} = y_k + d_k; res_{k+1} = res_k - A d_k.
-// One step of the Jacobi-Chebyshev polynomial.  The coefficients live in
+// One step of the Jacobi-Chebyshev polynomial (z = p(D^-1 A) D^-1 r by
+// Chebyshev iteration on A y = r from y = 0): d_0 = D^-1 r / theta;
+// d_k = c1 d_{k-1} + c2 D^-1 res_k; y_{k+1} = y_k + d_k;
+// res_{k+1} = res_k - A d_k.  The coefficients live in
 // device memory (coef[0] = 1/theta, coef[2k-1], coef[2k] = c1, c2 of step
 // k >= 1), so captured CG batches stay valid when lambda_max is
 // re-estimated; `last` marks the step that writes the r.z, r.r partials.
@@ -145,6 +145,49 @@ struct ChebStep {
   const double *coef;
   int k;
   int last;
+};
+
+// Preconditioned MINRES (Paige and Saunders) for the symmetric, possibly
+// indefinite phase trial block, FP64, M = |diag A| (SPD).  Lanczos step j
+// (1-based) applies A to v_j = y_{j-1} / beta_j, where y_{j-1} = M^-1 r_j and
+// beta_j^2 = r_j . y_{j-1}; the Givens rotation that advances x by step j
+// needs beta_{j+1}, so x and w of step j are updated in the apply of step
+// j + 1.  Two kernels per step, like the CG: the apply (prologue: reduce
+// beta_j, rotate for step j - 1, test convergence; q = A v_j, w and x of
+// step j - 1, partials of alpha_j = v_j . q) and the vector kernel
+// (r_{j+1} = q - alpha_j / beta_j r_j - beta_j / beta_{j-1} r_{j-1},
+// y_j = M^-1 r_{j+1}, partials of beta_{j+1}^2).  The apply writes half a,
+// the vector kernel half b, each reading the other's.
+struct MrHalf {
+  double beta, oldb, alfa;            // beta_j, beta_{j-1}, alpha_j
+  double cs, sn, dbar, epsln, phibar;  // rotation state
+  double beta1;                        // beta_1 = ||b||_{M^-1}
+  int done;    // 0 running, 1 converged, 2 breakdown, 3 iteration cap
+  int iters;   // steps whose x update has been applied
+  int first;   // set by the init kernel: the next apply is step 1
+  int pad;
+};
+struct MrState {
+  MrHalf a;
+  MrHalf b;
+};
+struct MrArgs {
+  MrState *st;
+  double *partA;   // alpha partials (apply blocks)
+  double *partB;   // beta^2 partials (init / vector kernel blocks)
+  int ga, gb;      // block counts of the apply and of the vector kernels
+  double tol;      // stop at phibar <= tol * beta_1
+  int maxit;
+};
+// Vectors of one MINRES solve (length N): x, w_j in w[j & 1], y_j in
+// y[j & 1], r_j in r[j & 1], q = A v_j, M^-1 = Dinv (0 on fixed nodes).
+struct MrVecs {
+  double *x;
+  double *w[2];
+  double *y[2];
+  double *r[2];
+  double *q;
+  const double *Dinv;
 };
 
 // Operator coefficients passed by value.
@@ -299,7 +342,17 @@ hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const Elas
                         const uint8_t *eact, const uint8_t *nflag, T *Dinv);
 template <class T>
 hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
-                      const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv);
+                      const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv,
+                      int absdiag = 0);
+
+// MINRES on the phase operator with coefficient coef (FP64; m a marching
+// shape, not tiles).  mr_init: r_1 = rhs, x = w = 0, y_0 = M^-1 rhs.
+hipError_t mr_init(hipStream_t s, int n, const double *rhs, const MrVecs &v, const MrArgs &a);
+hipError_t phase_mr_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const double *coef, const uint8_t *eact, const uint8_t *nflag,
+                          const MrVecs &v, const MrArgs &a, int j);
+hipError_t mr_update(hipStream_t s, int n, const MrVecs &v, const MrArgs &a, int j);
+int vec_block_count(int n);
 
 // Plain operator applies (no CG fusion, no masking) for the op entry points.
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
@@ -334,7 +387,7 @@ hipError_t qp_update(hipStream_t s, const Grid &g, const Mat &mt, const QpParams
 hipError_t tangent_flags(hipStream_t s, const Grid &g, const double *u, const uint8_t *eact,
                          uint8_t *qflag);
 template <class T>
-hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta,
+hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta, int floor,
                       const double *H, const double *psi_s, const uint8_t *qflag,
                       const double *d, const uint8_t *eact, T *coef, RedScratch rs);
 template <class T>

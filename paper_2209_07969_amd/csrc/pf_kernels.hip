@@ -1072,6 +1072,7 @@ struct OpPhaseDiag {
   struct Node { T dummy; };
   Grid g; PhaseCoef c;
   const T *coef; const uint8_t *eact; const uint8_t *nflag; T *Dinv;
+  int absdiag;   // 1: D = |diag| (SPD for an indefinite operator), 1 where it is 0
   __device__ Node load(int, int) const { return Node{T(0)}; }
   __device__ void fin(Node &) const {}
   __device__ Elem eload(int ie, int je) const {
@@ -1101,7 +1102,12 @@ struct OpPhaseDiag {
   __device__ void store(int i, int j, const T (&v)[1], const Node &, const Own &o,
                         double *) const {
     const int k = i + j * (g.nx + 1);
-    Dinv[k] = ((o.nf & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+    if (absdiag) {
+      const T a = v[0] < T(0) ? -v[0] : v[0];
+      Dinv[k] = (o.nf & NF_D) ? T(0) : (a > T(0) ? T(1) / a : T(1));
+    } else {
+      Dinv[k] = ((o.nf & NF_D) || !(v[0] > T(0))) ? T(0) : T(1) / v[0];
+    }
   }
 };
 
@@ -2100,7 +2106,7 @@ __global__ void __launch_bounds__(TPB) k_tangent_flags(Grid g, const double *u,
 // Mass coefficient of the augmented block K_dd + K~ (Section 3.4): on gated
 // points c - c_S floored at theta*c, c = Gc/l + 2H, c_S = 8(1-d)^2/g psi_S.
 template <class T>
-__global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta,
+__global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta, int floor,
                                                     const double *H, const double *psi_s,
                                                     const uint8_t *qflag, const double *d,
                                                     const uint8_t *eact, T *coef,
@@ -2130,7 +2136,7 @@ __global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta
       const double cS = 8.0 * om * om / (om * om + mt.eta) * psi_s[e + q * g.E]; \
       ct = c - cS;                                                               \
       if (ct < theta * c) {                                                      \
-        ct = theta * c;                                                          \
+        if (floor) ct = theta * c;                                               \
         hits += 1;                                                               \
       }                                                                          \
     }                                                                            \
@@ -2251,6 +2257,240 @@ __global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
   if (threadIdx.x == 0) {
     rs.scal[SC_SUM_X] = rs.partR[0];
     rs.scal[SC_SUM_Y] = rs.partR[kPMax];
+  }
+}
+
+// ------------------------------------------------------------- MINRES
+//
+// Preconditioned MINRES for the unfloored trial block of the evolution
+// equation, which is symmetric but may be indefinite (FP64).  Lanczos with
+// M = |diag A| builds v_j; a Givens QR of the tridiagonal matrix gives the
+// minimum-residual iterate x_j = x_{j-1} + phi_j w_j with
+// w_j = (v_j - eps_j w_{j-2} - delta_j w_{j-1}) / gamma_j.
+
+// Scalars of step j's apply, the same in every block.
+struct MrStep {
+  double s;       // 1 / beta_j  (v_j = s y_{j-1})
+  double sprev;   // 1 / beta_{j-1}
+  double oldeps, delta, igamma, phi;   // rotation of step j - 1
+  int upd;        // 1: update w and x of step j - 1
+  int done;       // -1 finished before this launch, else MrHalf::done
+};
+
+// Reduce beta_j, rotate for step j - 1 and test convergence; block 0
+// records the state in half a.
+__device__ inline MrStep mr_apply_prologue(const MrArgs &a, int bid) {
+  MrStep m{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
+  MrHalf h = a.st->b;
+  if (h.done != 0) {
+    m.done = -1;
+    return m;
+  }
+  double s2[1];
+  block_sum<1>(a.partB, a.gb, s2);
+  int done = 0;
+  if (!(s2[0] >= 0.0) || !isfinite(s2[0])) done = 2;   // M must be SPD
+  const double beta = done ? 0.0 : sqrt(s2[0]);
+  if (h.first) {
+    h.beta1 = beta;
+    h.phibar = beta;
+    h.cs = -1.0;
+    h.sn = 0.0;
+    h.dbar = 0.0;
+    h.epsln = 0.0;
+    if (done == 0 && beta == 0.0) done = 1;   // b = 0: x = 0
+  } else if (done == 0) {
+    const double oldeps = h.epsln;
+    const double delta = h.cs * h.dbar + h.sn * h.alfa;
+    const double gbar = h.sn * h.dbar - h.cs * h.alfa;
+    h.epsln = h.sn * beta;
+    h.dbar = -h.cs * beta;
+    const double gamma = sqrt(gbar * gbar + beta * beta);
+    if (!(gamma > 0.0) || !isfinite(gamma)) {
+      done = 2;   // singular tridiagonal: no minimum-residual step
+    } else {
+      h.cs = gbar / gamma;
+      h.sn = beta / gamma;
+      m.phi = h.cs * h.phibar;
+      h.phibar = h.sn * h.phibar;
+      m.oldeps = oldeps;
+      m.delta = delta;
+      m.igamma = 1.0 / gamma;
+      m.sprev = 1.0 / h.beta;
+      m.upd = 1;
+      h.iters += 1;
+      // beta = 0 ends the Lanczos process with sn = 0, phibar = 0
+      if (h.phibar <= a.tol * h.beta1) done = 1;
+      else if (h.iters >= a.maxit) done = 3;
+    }
+  }
+  h.oldb = h.first ? 0.0 : h.beta;
+  h.beta = beta;
+  h.first = 0;
+  h.done = done;
+  if (bid == 0 && threadIdx.x == 0) a.st->a = h;
+  m.s = beta > 0.0 ? 1.0 / beta : 0.0;
+  m.done = done;
+  return m;
+}
+
+// Apply of Lanczos step j on top of a phase operator whose input vector is
+// y_{j-1}: q = A v_j with v_j = y_{j-1} / beta_j; the stored nodes also take
+// w_{j-1} = (v_{j-1} - eps w_{j-3} - delta w_{j-2}) / gamma into wo (which
+// holds w_{j-3}) and x += phi w_{j-1}.  Partials: v_j . q.
+template <class Base>
+struct OpMrApply {
+  using T = typename Base::T;
+  using Elem = typename Base::Elem;
+  using Node = typename Base::Node;
+  static constexpr int NF = 1;
+  static constexpr int NR = 1;
+  Base base;
+  const T *yprev;   // y_{j-2}
+  T *wo;            // w_{j-3} in, w_{j-1} out
+  const T *wb;      // w_{j-2}
+  T *x; T *q;
+  T s, sprev, oldeps, delta, igamma, phi;
+  int upd;
+  __device__ Node load(int i, int j) const { return base.load(i, j); }
+  __device__ void fin(Node &n) const {
+    T u[1];
+    base.get_u(n, u);
+    u[0] *= s;
+    base.set_u(n, u);
+  }
+  __device__ Elem eload(int ie, int je) const { return base.eload(ie, je); }
+  static __device__ Node shfl_up(const Node &n) { return Base::shfl_up(n); }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          const Elem &e, T (&f)[1][4]) const {
+    base.element(n0, n1, n2, n3, e, f);
+  }
+  struct Own {
+    typename Base::Own b;
+    T yp, wa, wbv, xv;
+  };
+  __device__ Own load_own(int i, int j) const {
+    Own o;
+    o.b = base.load_own(i, j);
+    o.yp = o.wa = o.wbv = o.xv = T(0);
+    if (node_exists(base.g, i, j)) {
+      const int k = i + j * (base.g.nx + 1);
+      o.yp = yprev[k];
+      o.wa = wo[k];
+      o.wbv = wb[k];
+      o.xv = x[k];
+    }
+    return o;
+  }
+  __device__ void store(int i, int j, const T (&v)[1], const Node &n, const Own &o,
+                        double *red) const {
+    const int k = i + j * (base.g.nx + 1);
+    T vv[1];
+    base.get_u(n, vv);
+    const T qv = Base::masked_own(o.b, 0) ? T(0) : v[0];
+    q[k] = qv;
+    red[0] += double(vv[0]) * double(qv);
+    if (upd) {
+      const T wn = (o.yp * sprev - oldeps * o.wa - delta * o.wbv) * igamma;
+      wo[k] = wn;
+      x[k] = o.xv + phi * wn;
+    }
+  }
+};
+
+template <int CH, class Op>
+__global__ void __launch_bounds__(TPB) k_mr_apply(Op op, Grid g, March ms, MrArgs a, int n) {
+  const int bid = blockIdx.x, nb = gridDim.x;
+  const int lane = threadIdx.x & 63;
+  const int w0 = xcd_block(bid, nb) * WPB + (threadIdx.x >> 6);
+  const int nw = ms.nstrips * ms.nchunks;
+  // the first work item's loads are in flight during the prologue
+  Item<CH, Op> it;
+  if (w0 < nw) item_load<CH>(op, g, ms, w0, lane, it);
+  const MrStep m = mr_apply_prologue(a, bid);
+  if (m.done < 0 || m.done == 2) return;
+  if (m.done != 0) {
+    // converged or capped: only the last step's w and x update remains
+    if (m.upd) {
+      for (int k = bid * TPB + threadIdx.x; k < n; k += nb * TPB) {
+        const double wn = (op.yprev[k] * m.sprev - m.oldeps * op.wo[k] - m.delta * op.wb[k]) *
+                          m.igamma;
+        op.wo[k] = wn;
+        op.x[k] += m.phi * wn;
+      }
+    }
+    return;
+  }
+  op.s = m.s;
+  op.sprev = m.sprev;
+  op.oldeps = m.oldeps;
+  op.delta = m.delta;
+  op.igamma = m.igamma;
+  op.phi = m.phi;
+  op.upd = m.upd;
+  double red[1] = {0.0};
+  if (w0 < nw) item_compute<CH>(op, g, ms, w0, lane, it, red);
+  march_items<CH>(op, g, ms, w0 + nb * WPB, nb * WPB, red);
+  block_partial_at<1>(red, a.partA, bid);
+}
+
+__global__ void __launch_bounds__(TPB) k_mr_init(int n, const double *rhs, MrVecs v, MrArgs a) {
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double b = rhs[i];
+    v.r[0][i] = 0.0;
+    v.r[1][i] = b;
+    v.x[i] = 0.0;
+    v.w[0][i] = 0.0;
+    v.w[1][i] = 0.0;
+    const double y = v.Dinv[i] * b;
+    v.y[0][i] = y;
+    acc[0] += b * y;
+  }
+  block_partial<1>(acc, a.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    MrHalf h{};
+    h.first = 1;
+    a.st->a = h;
+    a.st->b = h;
+  }
+}
+
+// Vector kernel of step j: r_{j+1} (into the slot of r_{j-1}), y_j and the
+// partials of beta_{j+1}^2; block 0 publishes the state in half b.
+__global__ void __launch_bounds__(TPB) k_mr_update(int n, MrVecs v, MrArgs a, int j) {
+  MrHalf h = a.st->a;
+  if (h.done != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->b = h;
+    return;
+  }
+  double al[1];
+  block_sum<1>(a.partA, a.ga, al);
+  const double alfa = al[0];
+  if (!isfinite(alfa)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      h.done = 2;
+      a.st->b = h;
+    }
+    return;
+  }
+  const double c1 = alfa / h.beta;
+  const double c2 = h.oldb > 0.0 ? h.beta / h.oldb : 0.0;
+  const double *rj = v.r[j & 1];
+  double *rm = v.r[(j + 1) & 1];
+  double *y = v.y[j & 1];
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double rn = v.q[i] - c1 * rj[i] - c2 * rm[i];
+    rm[i] = rn;
+    const double yi = v.Dinv[i] * rn;
+    y[i] = yi;
+    acc[0] += rn * yi;
+  }
+  block_partial<1>(acc, a.partB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h.alfa = alfa;
+    a.st->b = h;
   }
 }
 
@@ -2599,9 +2839,42 @@ hipError_t tangent_diag(hipStream_t s, const Grid &g, const March &m, const Elas
 
 template <class T>
 hipError_t phase_diag(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
-                      const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv) {
-  OpPhaseDiag<T> op{g, c, coef, eact, nflag, Dinv};
+                      const T *coef, const uint8_t *eact, const uint8_t *nflag, T *Dinv,
+                      int absdiag) {
+  OpPhaseDiag<T> op{g, c, coef, eact, nflag, Dinv, absdiag};
   return launch_march(s, op, g, m, nullptr);
+}
+
+int vec_block_count(int n) { return vec_blocks(n); }
+
+hipError_t mr_init(hipStream_t s, int n, const double *rhs, const MrVecs &v, const MrArgs &a) {
+  if (a.gb != vec_blocks(n)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_init, dim3(a.gb), dim3(TPB), 0, s, n, rhs, v, a);
+  return hipGetLastError();
+}
+
+hipError_t phase_mr_apply(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const double *coef, const uint8_t *eact, const uint8_t *nflag,
+                          const MrVecs &v, const MrArgs &a, int j) {
+  if (j < 1 || a.ga != march_blocks(m)) return hipErrorInvalidValue;
+  using B = OpPhase<double, false, true>;
+  using Op = OpMrApply<B>;
+  Op op{B{g, c, coef, eact, nflag, v.y[(j - 1) & 1], nullptr, nullptr, nullptr, 0.0},
+        v.y[j & 1], v.w[(j - 1) & 1], v.w[j & 1], v.x, v.q, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
+  const dim3 grid(a.ga), block(TPB);
+  switch (m.ch) {
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mr_apply<2, Op>), grid, block, 0, s, op, g, m, a, g.N); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mr_apply<4, Op>), grid, block, 0, s, op, g, m, a, g.N); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mr_apply<8, Op>), grid, block, 0, s, op, g, m, a, g.N); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mr_update(hipStream_t s, int n, const MrVecs &v, const MrArgs &a, int j) {
+  if (j < 1 || a.gb != vec_blocks(n)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_update, dim3(a.gb), dim3(TPB), 0, s, n, v, a, j);
+  return hipGetLastError();
 }
 
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
@@ -2661,12 +2934,12 @@ hipError_t tangent_flags(hipStream_t s, const Grid &g, const double *u, const ui
 }
 
 template <class T>
-hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta,
+hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta, int floor,
                       const double *H, const double *psi_s, const uint8_t *qflag,
                       const double *d, const uint8_t *eact, T *coef, RedScratch rs) {
   const int blocks = (g.E + TPB - 1) / TPB;
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_coef<T>), dim3(blocks), dim3(TPB), 0, s, g, mt,
-                     theta, H, psi_s, qflag, d, eact, coef, rs);
+                     theta, floor, H, psi_s, qflag, d, eact, coef, rs);
   return hipGetLastError();
 }
 
@@ -2739,8 +3012,8 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                       const uint8_t *, const uint8_t *, const uint8_t *, T *); \
   template hipError_t phase_diag<T>(hipStream_t, const Grid &, const March &,                  \
                                     const PhaseCoef &, const T *, const uint8_t *,             \
-                                    const uint8_t *, T *);                                     \
-  template hipError_t trial_coef<T>(hipStream_t, const Grid &, const Mat &, double,            \
+                                    const uint8_t *, T *, int);                                \
+  template hipError_t trial_coef<T>(hipStream_t, const Grid &, const Mat &, double, int,       \
                                     const double *, const double *, const uint8_t *,           \
                                     const double *, const uint8_t *, T *, RedScratch);         \
   template hipError_t at2_coef<T>(hipStream_t, const Grid &, const Mat &, const double *,      \

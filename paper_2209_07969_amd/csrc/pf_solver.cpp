@@ -128,6 +128,10 @@ struct pf_ctx {
   double *cheb_dev = nullptr;
   double *cheb_h = nullptr;
 
+  // MINRES of the unfloored trial block: state and its pinned mirror
+  MrState *mrs = nullptr;
+  MrState *mrs_h = nullptr;
+
   // shared CG launches of a batch (set only inside pf_batch_load_step)
   BatchSvc *svc = nullptr;
   hipEvent_t ready_ev = nullptr;
@@ -1123,41 +1127,88 @@ pf_status phase_solve(pf_ctx *c, const double *Hs, pf_step_stats *st) {
   return phase_solve_impl<double>(c, Hs, st);
 }
 
-// Trial increment with the augmented block (Section 3.4) and the predictor
-// (Sections 3.3, 3.5); writes Hhat.
+// MINRES on the phase block held in bd.coef / bd.Dinv (M = |diag|) with
+// right-hand side c->Rd; the increment ends in bd.X[0].
+pf_status minres_phase(pf_ctx *c, double tol, int *iters, int *status, double **xout) {
+  CgBuf<double> &b = c->bd;
+  const int n = c->g.N;
+  // the kernels march in columns; LDS tiles fall back to 2-row marching
+  const March m = c->ms.ch == 1 ? march_shape(c->g, 2) : c->ms;
+  const MrVecs v{b.X[0], {b.W[0], b.W[1]}, {b.P[0], b.P[1]}, {b.R[0], b.R[1]}, b.S[0], b.Dinv};
+  const MrArgs a{c->mrs, c->rs.partR, c->rs.partR + 2 * kPMax, cg1_blocks(m),
+                 vec_block_count(n), tol, c->opts.max_cg};
+  PF_HIP(c, mr_init(c->stream, n, c->Rd, v, a));
+  const int batch = std::max(4, c->opts.cg_check);
+  for (int j = 1;;) {
+    for (int k = 0; k < batch; ++k, ++j) {
+      PF_HIP(c, phase_mr_apply(c->stream, c->g, m, c->pc, b.coef, c->eact, c->nflag, v, a, j));
+      PF_HIP(c, mr_update(c->stream, n, v, a, j));
+    }
+    PF_HIP(c, hipMemcpyAsync(c->mrs_h, c->mrs, sizeof(MrState), hipMemcpyDeviceToHost, c->stream));
+    PF_TRY(sync(c));
+    const MrHalf &h = c->mrs_h->b;
+    if (h.done != 0) {
+      *iters = h.iters;
+      *status = h.done;
+      *xout = b.X[0];
+      return PF_OK;
+    }
+  }
+}
+
+// Trial increment with the augmented block K_dd + K~ (Section 3.4), then
+// either the predictor (Sections 3.3, 3.5), which writes Hhat, or, for the
+// trial-only update, d += increment.  The floored block is SPD and solved by
+// PCG; the unfloored one may be indefinite and is solved by MINRES in FP64.
 template <class T>
 pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
   CgBuf<T> &b = buf<T>(c);
   const bool mixed = std::is_same<T, float>::value;
+  const bool literal = c->opts.trial_operator == PF_TRIAL_UNFLOORED;
   const int n = c->g.N;
   PF_TRY(zero_icount(c));
-  PF_HIP(c, trial_coef<T>(c->stream, c->g, c->mt, c->opts.trial_floor, c->H, c->psi_s, c->qflag,
-                          c->d, c->eact, b.coef, c->rs));
-  PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv));
+  PF_HIP(c, trial_coef<T>(c->stream, c->g, c->mt, c->opts.trial_floor, literal ? 0 : 1, c->H,
+                          c->psi_s, c->qflag, c->d, c->eact, b.coef, c->rs));
+  PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv,
+                          literal ? 1 : 0));
   double nR = 0.0, nb = 0.0;
   PF_TRY(phase_res(c, c->H, true, &nR, &nb));   // also reads icount (floor hits)
   st->floor_hits += (int64_t)c->icount_h[IC_FLOOR];
-  if (mixed) {
-    PF_HIP(c, convert<float, double>(c->stream, n, c->bf.R[0], c->Rd));
-  } else {
-    PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream));
-  }
   int iters = 0, status = 0;
   T *xs = nullptr;
-  PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status, &xs));
+  if constexpr (std::is_same<T, double>::value) {
+    if (literal) PF_TRY(minres_phase(c, c->opts.tol_pcg, &iters, &status, &xs));
+  }
+  if (!literal) {
+    if (mixed) {
+      PF_HIP(c, convert<float, double>(c->stream, n, c->bf.R[0], c->Rd));
+    } else {
+      PF_HIP(c, hipMemcpyAsync(c->bd.R[0], c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    PF_TRY(pcg<T>(c, K_PHASE, mixed ? c->opts.tol_inner : c->opts.tol_pcg, &iters, &status, &xs));
+  }
   st->n_cg_trial += iters;
   st->dof_updates += (double)iters * (double)c->n_free_d;
   if (status == 3) st->cg_not_converged += 1;
-  if (status == 2) return fail(c, PF_E_BREAKDOWN, "trial CG breakdown");
-  PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, xs, c->H, c->psi_s, c->qflag, c->eact,
-                         c->Hhat));
+  if (status == 2) return fail(c, PF_E_BREAKDOWN, literal ? "trial MINRES breakdown" : "trial CG breakdown");
+  if (c->opts.trial_update == PF_TRIAL_ONLY) {
+    PF_HIP(c, axpy_into<T>(c->stream, n, c->d, c->d, 1.0, xs));
+  } else {
+    PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, xs, c->H, c->psi_s, c->qflag, c->eact,
+                           c->Hhat));
+  }
   st->n_trial += 1;
   return PF_OK;
 }
 
+// The FP32 trial serves only the floored predictor; the trial-only update
+// is the phase update itself, and MINRES runs in FP64, so both take the
+// FP64 path in either precision.
 pf_status trial(pf_ctx *c, pf_step_stats *st) {
-  if (c->opts.precision == PF_MIXED) return trial_impl<float>(c, st);
+  if (c->opts.precision == PF_MIXED && c->opts.trial_operator == PF_TRIAL_FLOORED &&
+      c->opts.trial_update == PF_TRIAL_PREDICT_CORRECT)
+    return trial_impl<float>(c, st);
   return trial_impl<double>(c, st);
 }
 
@@ -1222,14 +1273,17 @@ pf_status open_step(pf_ctx *c, double lam) {
 
 pf_status iterate_once(pf_ctx *c) {
   const double *Hs = c->H;
+  bool updated = false;
   if (c->opts.scheme != PF_ST) {
     c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, c->gated_last);
     if (c->gated_last > 0) {
       PF_TRY(trial(c, &c->acc));
-      Hs = c->Hhat;
+      // trial-only: d already holds d + increment
+      if (c->opts.trial_update == PF_TRIAL_ONLY) updated = true;
+      else Hs = c->Hhat;
     }
   }
-  PF_TRY(phase_solve(c, Hs, &c->acc));
+  if (!updated) PF_TRY(phase_solve(c, Hs, &c->acc));
   bool ok = true;
   PF_TRY(newton(c, &c->acc, &ok));
   if (!ok) c->acc.converged = 0;
@@ -1272,6 +1326,11 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
   if (!(o->cheb_ratio >= 0) || (o->cheb_ratio > 0 && o->cheb_ratio <= 1)) {
     *msg = "cheb_ratio must be 0 or > 1";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->trial_operator < 0 || o->trial_operator > 1 || o->trial_update < 0 ||
+      o->trial_update > 1) {
+    *msg = "trial_operator and trial_update must be 0 or 1";
     return PF_E_INVALID_ARG;
   }
   if (o->cg_kernels < 0 || o->cg_kernels > 2) {
@@ -1434,6 +1493,7 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
   A(&c->cheb_dev, 4 * (size_t)kChebCoefs);
+  A(&c->mrs, 1);
   A(&c->cgs, 2);
   A(&c->cgs2, 1);
   A(&c->cgpart, 6 * (size_t)kPMax);
@@ -1452,7 +1512,8 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
         hipHostMalloc((void **)&c->cgs2_h, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess ||
-        hipHostMalloc((void **)&c->cheb_h, 4 * kChebCoefs * sizeof(double)) != hipSuccess)
+        hipHostMalloc((void **)&c->cheb_h, 4 * kChebCoefs * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->mrs_h, sizeof(MrState)) != hipSuccess)
       s = PF_E_OOM;
   }
   if (s == PF_OK) s = upload_constraints(c);
@@ -1482,6 +1543,7 @@ pf_status pf_destroy(pf_ctx *c) {
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   if (c->icount_h) (void)hipHostFree(c->icount_h);
   if (c->cheb_h) (void)hipHostFree(c->cheb_h);
+  if (c->mrs_h) (void)hipHostFree(c->mrs_h);
   delete c;
   return PF_OK;
 }

@@ -59,12 +59,44 @@ def test_create_rejects_bad_arguments_without_device():
     assert not h.value
 
 
+def c_layout(structs):
+    """sizeof and every field's offsetof, as the C compiler lays the header's
+    structs out (gcc on a program that includes the header)."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
+             "int main(void) {"]
+    for cname, fields in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines) + "\n")
+        subprocess.run([cc, "-std=c99", "-o", exe, src], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    res = {}
+    for line in out.splitlines():
+        cname, key, val = line.split()
+        res[(cname, key)] = int(val)
+    return res
+
+
 def test_struct_layouts_match_header():
+    """The ctypes mirrors have the C compiler's size and field offsets."""
     import paper_2209_07969_amd as pf
-    # 4 int32 + 4 double + 4 int32 + 3 double + 2 int32
-    assert ctypes.sizeof(pf.SolverOpts) == 4 * 4 + 4 * 8 + 4 * 4 + 3 * 8 + 2 * 4 + 8
-    assert ctypes.sizeof(pf.MeshDesc) == 8 + 16 + 8
-    assert ctypes.sizeof(pf.MaterialDesc) == 5 * 8 + 8
+    pairs = {"pf_solver_opts": pf.SolverOpts, "pf_mesh_desc": pf.MeshDesc,
+             "pf_material": pf.MaterialDesc, "pf_step_stats": pf.StepStats}
+    lay = c_layout({c: [f for f, _ in py._fields_] for c, py in pairs.items()})
+    for cname, py in pairs.items():
+        assert lay[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_option_validation_without_device():
@@ -75,7 +107,8 @@ def test_option_validation_without_device():
     mesh = pf.MeshDesc(4, 4, 1.0, 1.0, None)
     mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
     cases = {"cheb_ratio": 0.5, "cg_kernels": 3, "march_rows": 3, "cheb_degree": 0,
-             "max_cg": 0, "max_stag": 0, "scheme": 7, "precision": 2, "precond": 5}
+             "max_cg": 0, "max_stag": 0, "scheme": 7, "precision": 2, "precond": 5,
+             "trial_operator": 2, "trial_update": -1}
     for name, value in cases.items():
         o = pf.default_opts()
         o.precond = 1          # Jacobi-Chebyshev, so that cheb_degree is checked

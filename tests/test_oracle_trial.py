@@ -44,11 +44,15 @@ def bar_energies(p, lam):
     return psi_vol, psi_dev
 
 
-def scalar_map_history(p, scheme, floor, trial_only=True):
-    """(n_stag, d) per load step of the trial-only scheme on the bar."""
+def scalar_map_history(p, scheme, floor, trial_only=True, slopes=False):
+    """(n_stag, d) per load step of the trial-only scheme on the bar; with
+    slopes, also the factor by which the step's final d amplifies an error
+    of d: the product of |1 - c/a| (the map's derivative) over the trial
+    iterations since the last standard solve, which lands on 2H/c whatever
+    d was before it."""
     m = p.material
     psi_crit = m.Gc / (2 * m.l)
-    d, H_prev, out = 0.0, 0.0, []
+    d, H_prev, out, amp = 0.0, 0.0, [], 1.0
     for lam in p.loads:
         pv, pd = bar_energies(p, float(lam))
         psi = pv + pd
@@ -64,11 +68,13 @@ def scalar_map_history(p, scheme, floor, trial_only=True):
                 if floor:
                     a = max(a, p.trial_floor * c)
                 d = d - (c * d - 2 * H) / a
+                amp *= abs(1 - c / a)
             else:
                 d = 2 * H / c
+                amp = 1.0
             n += 1
             r = abs(c * d - 2 * H) / (2 * H)
-        out.append((n, d))
+        out.append((n, d, amp) if slopes else (n, d))
         H_prev = H
     return out
 
