@@ -32,7 +32,12 @@ Two further modes print their own single JSON line:
                          one;
   --workload apply-sizes the FP32 fused tangent apply and the CG vector
                          update at 512^2 .. 4096^2 (one displacement solve of
-                         a notched panel, CG capped), against the HBM peak.
+                         a notched panel, CG capped), against the HBM peak;
+  --workload trial-readings  ST and S1/S3 under the four readings of the
+                         trial solve (floored or unfloored block, predict ->
+                         correct or trial-only), FP64, over the whole load
+                         history of --trial-problem (64^2 by default):
+                         staggered counts, convergence and force curves.
 """
 from __future__ import annotations
 
@@ -301,6 +306,80 @@ def run_apply_sizes(pf, args):
     }
 
 
+def run_trial_readings(pf, args):
+    """The readings of the trial solve on one problem (FP64): the floored
+    block with predict -> correct (the default), the unfloored block by
+    MINRES, the trial-only update, both literal readings together, and ST
+    for reference.  Per step: staggered iterations, convergence, trial
+    solves and their iterations, floor candidates and the reaction force."""
+    import dataclasses
+    import workloads as W
+    base = {"tension64": W.config_tension64, "tension512": W.config_tension512}[
+        args.trial_problem]()
+    if args.max_stag > 0:
+        base = dataclasses.replace(base, max_stag=args.max_stag)
+    if args.trial_steps > 0:
+        base = dataclasses.replace(base, loads=base.loads[:args.trial_steps])
+    readings = [("ST", "st", 0, 0, 0)]
+    for scheme in (1, 3):
+        for name, key, op, upd in (("floored, predict-correct", "floored-pc", 0, 0),
+                                   ("unfloored (MINRES), predict-correct", "unfloored-pc", 1, 0),
+                                   ("floored, trial-only", "floored-only", 0, 1),
+                                   ("unfloored (MINRES), trial-only", "unfloored-only", 1, 1)):
+            readings.append((f"S{scheme} {name}", f"s{scheme}-{key}", scheme, op, upd))
+    if args.trial_reading != "all":
+        readings = [r for r in readings if r[1] == args.trial_reading]
+    out = []
+    ref_force = None
+    for label, _, scheme, op, upd in readings:
+        p = dataclasses.replace(base, trial_operator=op, trial_update=upd)
+        ctx = pf.Context(p, scheme=scheme, precision=pf.FP64)
+        torch_sync()
+        t0 = time.perf_counter()
+        rows = []
+        for lam in p.loads:
+            st = ctx.load_step(float(lam))
+            rows.append({"n_stag": st["n_stag"], "converged": st["converged"],
+                         "n_trial": st["n_trial"], "n_it_trial": st["n_cg_trial"],
+                         "floor_candidates": st["floor_hits"],
+                         "force": st["force"][p.load_comp]})
+            if st["n_stag"] >= 50:
+                log(f"    {label} step {len(rows)}: n_stag {st['n_stag']} "
+                    f"converged {st['converged']}")
+        torch_sync()
+        secs = time.perf_counter() - t0
+        ctx.close()
+        F = [r["force"] for r in rows]
+        if ref_force is None:
+            ref_force = F
+        peak = max(abs(f) for f in ref_force)
+        dev = max(abs(a - b) for a, b in zip(F, ref_force)) / peak
+        out.append({"reading": label, "seconds": secs,
+                    "n_stag_total": sum(r["n_stag"] for r in rows),
+                    "steps_not_converged": sum(1 for r in rows if not r["converged"]),
+                    "trial_iterations": sum(r["n_it_trial"] for r in rows),
+                    "force_dev_vs_st": dev, "steps": rows})
+        log(f"  {label}: {secs:.2f} s, N_stag {out[-1]['n_stag_total']}, "
+            f"not converged {out[-1]['steps_not_converged']}, force dev {dev:.3e}")
+    lit = ([r for r in out if r["reading"] == "S1 unfloored (MINRES), predict-correct"]
+           or out)[0]
+    return {
+        "metric": "staggered iterations per load history under the trial readings, 1 MI355X",
+        "value": lit["n_stag_total"], "unit": "staggered iterations", "n_gpus": 1,
+        "steps": len(base.loads), "warmup": 0, "ms_per_step": lit["seconds"] * 1e3 / len(base.loads),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"trial-readings: {base.name} ({base.nx}x{base.ny}, "
+                               f"{len(base.loads)} load steps), FP64, max_stag {base.max_stag}"},
+        "readings": out,
+    }
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,7 +387,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tension512",
                     choices=["tension512", "tension64", "shear1024", "lshape2048", "sweep64",
-                             "apply-sizes"])
+                             "apply-sizes", "trial-readings"])
+    ap.add_argument("--trial-problem", default="tension64", choices=["tension64", "tension512"],
+                    help="problem of the trial-readings mode (its whole load history)")
+    ap.add_argument("--trial-reading", default="all",
+                    choices=["all", "st"] + [f"s{k}-{r}" for k in (1, 3) for r in
+                                             ("floored-pc", "unfloored-pc", "floored-only",
+                                              "unfloored-only")],
+                    help="run only this reading in the trial-readings mode")
+    ap.add_argument("--trial-steps", type=int, default=0,
+                    help="first load steps of the trial-readings problem (0: all)")
+    ap.add_argument("--max-stag", type=int, default=0,
+                    help="staggered iteration cap of the trial-readings mode (0: the problem's)")
     ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
     ap.add_argument("--jacobi", action="store_true",
                     help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
@@ -352,6 +442,9 @@ def main():
         return
     if args.workload == "apply-sizes":
         print(json.dumps(run_apply_sizes(pf, args)))
+        return
+    if args.workload == "trial-readings":
+        print(json.dumps(run_trial_readings(pf, args)))
         return
     if args.rows < 0:
         args.rows = 1 if args.workload == "tension512" else 0
