@@ -138,3 +138,26 @@ def test_spectral_equals_vd_free_case_for_isotropic_tension():
 def test_degradation():
     assert C.degradation(0.0, 1e-6) == 1.0 + 1e-6
     assert C.degradation(1.0, 1e-6) == 1e-6
+
+
+@pytest.mark.parametrize("a,b", [(2e-3, 5e-4), (5e-4, 2e-3)])
+def test_spectral_scheme_parts_hand_values(a, b):
+    """Spectral split with a nonzero trace, principal strains (a, -b) rotated
+    by 20 degrees: Psi_vol = lam/2 <a - b>_+^2 (S1's part), Psi_dev =
+    mu <a>_+^2 (S2's part), Psi+ their sum (S3), Psi- = lam/2 <a - b>_-^2 +
+    mu b^2.  Lame constants from the textbook formulas, not the oracle's."""
+    lam = E * NU / ((1 + NU) * (1 - 2 * NU))
+    mu = E / (2 * (1 + NU))
+    th = np.deg2rad(20.0)
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    T = R @ np.diag([a, -b]) @ R.T
+    eps = np.array([[T[0, 0], T[1, 1], 2 * T[0, 1]]])
+    p = C.Constitutive(E, NU, 1).parts(eps)
+    t = a - b
+    vol = 0.5 * lam * max(t, 0.0) ** 2
+    dev = mu * a * a
+    assert np.isclose(p["psi_vol"][0], vol, rtol=1e-12, atol=1e-18)
+    assert np.isclose(p["psi_dev"][0], dev, rtol=1e-12)
+    assert np.isclose(p["psi_minus"][0], 0.5 * lam * min(t, 0.0) ** 2 + mu * b * b, rtol=1e-12)
+    for scheme, ref in ((1, vol), (2, dev), (3, vol + dev)):
+        assert np.isclose(C.scheme_part(p, scheme)[0], ref, rtol=1e-12, atol=1e-18)

@@ -172,3 +172,37 @@ def test_unfloored_coefficient_is_indefinite_where_floor_acts():
     f = o.d_free
     res = (A @ dd + (K @ o.d - b))[f]
     assert np.linalg.norm(res) <= 1e-8 * max(np.linalg.norm((K @ o.d - b)[f]), 1e-300)
+
+
+@pytest.mark.parametrize("theta", [0.1, 0.3])
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_floored_trial_increment_on_gated_bar(scheme, theta):
+    """The floor theta: at the bar's first gated step every point has
+    c - c_S < theta c for S2/S3, so the floored block acts on the uniform
+    increment as theta c M and the increment is -(c d - 2H) / (theta c),
+    with every gated point counted as floored."""
+    p = dataclasses.replace(W.homogeneous_bar(nx=3, ny=4, du=5e-3, steps=4), trial_floor=theta)
+    o = Oracle(p, scheme)
+    for lam in p.loads[:3]:
+        st = o.load_step(float(lam))
+        assert st.n_trial == 0
+    lam = float(p.loads[3])
+    u = o.u.copy()
+    u[o.u_fixed] = lam * o.u_unit[o.u_fixed]
+    u, _, ok = o.newton(u, o.d, 1.0)
+    assert ok
+    parts = o.energies(u, o.d)
+    H = np.maximum(o.H, parts["psi_plus"])
+    gate = np.ones_like(H, dtype=bool)
+    from oracle.constitutive import scheme_part
+    dd, hits = o.trial_increment(o.d, H, gate, scheme_part(parts, scheme))
+    m = p.material
+    pv, pd = bar_energies(p, lam)
+    Hs = pv + pd
+    c = m.Gc / m.l + 2 * Hs
+    d0 = float(o.d.mean())
+    om2 = (1 - d0) ** 2
+    cS = 8 * om2 / (om2 + m.eta) * {2: pd, 3: pv + pd}[scheme]
+    assert c - cS < theta * c                       # the floor acts everywhere
+    assert hits == gate.size
+    np.testing.assert_allclose(dd, -(c * d0 - 2 * Hs) / (theta * c), rtol=1e-9)
