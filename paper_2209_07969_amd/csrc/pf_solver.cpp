@@ -1166,6 +1166,8 @@ pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
   const bool mixed = std::is_same<T, float>::value;
   const bool literal = c->opts.trial_operator == PF_TRIAL_UNFLOORED;
   const int n = c->g.N;
+  // MINRES runs in FP64 only; trial() never sends the unfloored block here
+  if (mixed && literal) return fail(c, PF_E_STATE, "unfloored trial needs the FP64 path");
   PF_TRY(zero_icount(c));
   PF_HIP(c, trial_coef<T>(c->stream, c->g, c->mt, c->opts.trial_floor, literal ? 0 : 1, c->H,
                           c->psi_s, c->qflag, c->d, c->eact, b.coef, c->rs));
