@@ -51,13 +51,14 @@ def tangent_matrix(mesh, cons, u, d, eta):
     return _csr(rows, cols, Ke, 2 * mesh.n_nodes)
 
 
-def phase_matrix(mesh, coef, Gc, l):
-    """sum [coef_q N N^T + Gc l grad N . grad N^T] w detJ, coef per QP (Ea, 4)."""
+def phase_matrix(mesh, coef, Gc, l, lap=None):
+    """sum [coef_q N N^T + Gc l grad N . grad N^T] w detJ, coef per QP (Ea, 4);
+    lap replaces the Laplacian's factor Gc l where given (AT1: 2 Gc l / c_w)."""
     N = mesh.N                                                  # (4, 4) [q, a]
     mass = np.einsum("eq,qa,qb,eq->eab", coef, N, N, mesh.wdet)
-    lap = (np.einsum("eqa,eqb,eq->eab", mesh.dNdx, mesh.dNdx, mesh.wdet)
-           + np.einsum("eqa,eqb,eq->eab", mesh.dNdy, mesh.dNdy, mesh.wdet))
-    Ke = mass + Gc * l * lap
+    L = (np.einsum("eqa,eqb,eq->eab", mesh.dNdx, mesh.dNdx, mesh.wdet)
+         + np.einsum("eqa,eqb,eq->eab", mesh.dNdy, mesh.dNdy, mesh.wdet))
+    Ke = mass + (Gc * l if lap is None else lap) * L
     c = mesh.conn
     rows = np.repeat(c[:, :, None], 4, axis=2)
     cols = np.repeat(c[:, None, :], 4, axis=1)

@@ -28,6 +28,13 @@ One load step n at load factor lambda_n, from the committed state
      that AT2 with a history variable needs no energy update because its
      equation is linear).  Ungated iterations take the standard solve, which
      is the same update with K~ = 0.
+   phase_model = 1 swaps the evolution equation for AT1 with penalised
+   irreversibility (Section 2, eq_evolution_equation; oracle/at1.py): the
+   driving energy is Psi+ of the current displacement, the phase solve is a
+   semismooth Newton iteration on F_d, the trial block is its matrix plus K~
+   (the floor relative to its mass coefficient 2 Psi+ + gamma chi), and the
+   staggered residual is ||F_d|| / ||sum 2 Psi+ N||.  The committed maximum
+   of Psi+ is kept only as the gate's Psi_max, and d_{n-1} for the penalty.
 3. Commit u_n, d_n, H_n = max(H_{n-1}, Psi^+(u_n)) (the predicted energy is
    never stored) and the reaction force of the loaded Dirichlet group.
 """
@@ -40,6 +47,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from . import assembly as asm
+from . import at1
 from .constitutive import (Constitutive, coupling_coefficient, degradation,
                            predicted_energy, scheme_part)
 from .fem import Mesh
@@ -70,7 +78,13 @@ class Oracle:
         self.mesh = Mesh(p.nx, p.ny, p.lx, p.ly, p.elem_active)
         self.cons = Constitutive(m.E, m.nu, m.split)
         self.Gc, self.l, self.eta = m.Gc, m.l, m.eta
-        self.psi_crit = p.psi_crit if p.psi_crit >= 0 else m.Gc / (2.0 * m.l)
+        self.model = int(getattr(p, "phase_model", 0))
+        if self.model == 1:
+            self.gamma = at1.penalty_gamma(m.Gc, m.l, p.tol_ir)
+            crit = at1.psi_crit(m.Gc, m.l)
+        else:
+            crit = m.Gc / (2.0 * m.l)
+        self.psi_crit = p.psi_crit if p.psi_crit >= 0 else crit
         nn = self.mesh.n_nodes
         # constrained displacement DOFs and their unit values
         self.u_fixed = np.zeros(2 * nn, dtype=bool)
@@ -94,6 +108,7 @@ class Oracle:
         # state
         self.u = np.zeros(2 * nn)
         self.d = self.d_val.copy()
+        self.d_prev = self.d.copy()          # committed d (AT1 penalty)
         Ea = self.mesh.conn.shape[0]
         self.H = np.zeros((Ea, 4))
         self.step_index = 0
@@ -112,6 +127,7 @@ class Oracle:
         self.u[0::2] = u_soa[0]
         self.u[1::2] = u_soa[1]
         self.d = np.array(d, dtype=float)
+        self.d_prev = self.d.copy()
         self.H = np.asarray(H_planes)[:, self.mesh.elems].T.copy()
 
     # ---------------------------------------------------------- components
@@ -157,6 +173,11 @@ class Oracle:
         return K, b
 
     def stag_residual(self, d, H):
+        if self.model == 1:
+            R = at1.residual(self.mesh, H, d, self.d_prev, self.Gc, self.l, self.gamma)
+            nR = np.linalg.norm(R[self.d_free])
+            nb = at1.driving_scale(self.mesh, H, self.d_free)
+            return nR / nb if nb > 0 else nR
         K, b = self.phase_system(H)
         R = (K @ d - b)[self.d_free]
         nb = np.linalg.norm(b[self.d_free])
@@ -164,11 +185,17 @@ class Oracle:
         return nR / nb if nb > 0 else nR
 
     def solve_phase(self, H, d):
-        """Solve K_dd(H) d = b(H) with the Dirichlet values of d imposed."""
-        K, b = self.phase_system(H)
+        """Solve K_dd(H) d = b(H) with the Dirichlet values of d imposed
+        (AT1: F_d(d; H) = 0 by semismooth Newton, H being Psi+)."""
         f = self.d_free
         out = d.copy()
         out[~f] = self.d_val[~f]
+        if self.model == 1:
+            out, _, ok = at1.solve(self.mesh, H, out, self.d_prev, self.Gc, self.l, self.gamma, f)
+            if not ok:
+                raise RuntimeError("AT1 phase solve: active set did not settle")
+            return out
+        K, b = self.phase_system(H)
         rhs = b[f] - K[f][:, ~f] @ out[~f]
         out[f] = spla.spsolve(K[f][:, f].tocsc(), rhs)
         return out
@@ -178,13 +205,20 @@ class Oracle:
         block K_dd + K~ (eq_staggered_NR), K~ only on gated points; its mass
         coefficient floored at theta c unless trial_operator = 1."""
         dq = self.mesh.interp(d)
-        c = asm.at2_coefficient(H, self.Gc, self.l)
         cS = coupling_coefficient(dq, self.eta, psi_s)
         literal = int(getattr(self.p, "trial_operator", 0)) == 1
-        ct, hits = asm.trial_coefficient(c, cS, gate, self.p.trial_floor, floor=not literal)
-        A = asm.phase_matrix(self.mesh, ct, self.Gc, self.l)
-        K, b = self.phase_system(H)
-        Rd = K @ d - b
+        if self.model == 1:
+            chi = at1.active(self.mesh, d, self.d_prev)
+            c = at1.jacobian_coefficient(H, chi, self.gamma)
+            ct, hits = asm.trial_coefficient(c, cS, gate, self.p.trial_floor, floor=not literal)
+            A = at1.matrix(self.mesh, ct, self.Gc, self.l)
+            Rd = at1.residual(self.mesh, H, d, self.d_prev, self.Gc, self.l, self.gamma)
+        else:
+            c = asm.at2_coefficient(H, self.Gc, self.l)
+            ct, hits = asm.trial_coefficient(c, cS, gate, self.p.trial_floor, floor=not literal)
+            A = asm.phase_matrix(self.mesh, ct, self.Gc, self.l)
+            K, b = self.phase_system(H)
+            Rd = K @ d - b
         f = self.d_free
         dd = np.zeros_like(d)
         dd[f] = spla.spsolve(A[f][:, f].tocsc(), -Rd[f])
@@ -217,10 +251,11 @@ class Oracle:
         st.n_stag = 1
         parts = self.energies(u, d)
         H = np.maximum(H_prev, parts["psi_plus"])
-        r = self.stag_residual(d, H)
+        drive = parts["psi_plus"] if self.model == 1 else H
+        r = self.stag_residual(d, drive)
         trial_only = int(getattr(p, "trial_update", 0)) == 1
         while r > p.tol_stag and st.n_stag < p.max_stag:
-            H_hat = H
+            H_hat = drive
             ng = 0
             if self.scheme != 0:
                 dq = self.mesh.interp(d)
@@ -230,7 +265,7 @@ class Oracle:
                 st.gated_max = max(st.gated_max, ng)
                 if ng > 0:
                     psi_s = scheme_part(parts, self.scheme)
-                    dd, hits = self.trial_increment(d, H, gate, psi_s)
+                    dd, hits = self.trial_increment(d, drive, gate, psi_s)
                     st.n_trial += 1
                     st.floor_hits += hits
                     if trial_only:
@@ -238,7 +273,7 @@ class Oracle:
                     else:
                         ddq = self.mesh.interp(dd)
                         psi_hat = predicted_energy(psi, psi_s, dq, self.eta, ddq, gate)
-                        H_hat = np.maximum(H, psi_hat)
+                        H_hat = np.maximum(drive, psi_hat)
             if not (trial_only and ng > 0):
                 d = self.solve_phase(H_hat, d)
             u, nit, ok = self.newton(u, d, R_ref)
@@ -247,10 +282,12 @@ class Oracle:
             st.n_stag += 1
             parts = self.energies(u, d)
             H = np.maximum(H_prev, parts["psi_plus"])
-            r = self.stag_residual(d, H)
+            drive = parts["psi_plus"] if self.model == 1 else H
+            r = self.stag_residual(d, drive)
         st.r_stag = r
         st.converged &= bool(r <= p.tol_stag)
         self.u, self.d, self.H = u, d, H
+        self.d_prev = d.copy()
         self.step_index += 1
         fx, fy = self.reaction(u, d)
         st.force_xy = (fx, fy)

@@ -85,6 +85,8 @@ class Problem:
     trial_floor: float = 0.1
     trial_operator: int = 0            # 0: mass coefficient floored at theta c; 1: unfloored
     trial_update: int = 0              # 0: trial -> predict -> correct; 1: d += trial increment
+    phase_model: int = 0               # 0: AT2 with history field; 1: AT1 with penalty
+    tol_ir: float = 0.01               # irreversibility tolerance of the penalty (AT1)
 
     @property
     def n_nodes(self) -> int:
