@@ -175,6 +175,9 @@ class Context:
     """
 
     def __init__(self, problem, scheme=ST, precision=FP64, stream=None, **overrides):
+        if int(getattr(problem, "phase_model", 0)) != 0:
+            raise NotImplementedError("the HIP path implements AT2 with the history field "
+                                      "only (phase_model 0)")
         require_device()
         import torch
         self.lib = load_library()

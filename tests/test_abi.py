@@ -129,3 +129,14 @@ def test_batch_and_allocator_argument_checks_without_device():
     assert lib.pf_batch_create(1, arr, 0, ctypes.byref(out)) == 1   # null member
     assert lib.pf_batch_set_shared_launches(None, 1) == 1
     assert lib.pf_set_allocator(None, pf.ALLOC_FN(), pf.RELEASE_FN(), None) == 1
+
+
+def test_context_refuses_models_the_library_lacks():
+    """A problem asking for AT1 with the penalty (an oracle-only model) is
+    refused before any device call, rather than run silently as AT2."""
+    import dataclasses
+    import paper_2209_07969_amd as pf
+    import workloads as W
+    p = dataclasses.replace(W.homogeneous_bar(), phase_model=1)
+    with pytest.raises(NotImplementedError):
+        pf.Context(p)
