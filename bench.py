@@ -423,6 +423,9 @@ def main():
                     help="time only the ST FP64 run (long histories in separate jobs)")
     ap.add_argument("--full-history", action="store_true",
                     help="time the whole load history (warmup 0, all steps) for both schemes")
+    ap.add_argument("--at1", action="store_true",
+                    help="AT1 with penalised irreversibility instead of AT2 with the history "
+                         "field, for both schemes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -453,6 +456,9 @@ def main():
     problem = {"tension512": W.config_tension512, "tension64": W.config_tension64,
                "shear1024": W.config_shear1024,
                "lshape2048": W.config_lshape2048}[args.workload]()
+    if args.at1:
+        import dataclasses
+        problem = dataclasses.replace(problem, phase_model=1)
     if args.full_history:
         args.warmup, args.steps = 0, len(problem.loads)
     if args.copy_calibration:
@@ -556,6 +562,8 @@ def main():
             "precond": "jacobi" if s1_deg is None else f"jacobi-chebyshev degree {s1_deg}",
             "march_rows": rows_s1,
             "tol_stag": problem.tol_stag, "tol_pcg": problem.tol_pcg,
+            "phase_model": ("AT1 with penalised irreversibility" if args.at1
+                            else "AT2 with history field"),
         },
         "s1_mixed": {"n_stag": [r["n_stag"] for r in rows],
                      "time_ms": [round(r["time_ms"], 1) for r in rows]},

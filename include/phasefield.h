@@ -85,13 +85,25 @@ typedef enum { PF_TRIAL_FLOORED = 0, PF_TRIAL_UNFLOORED = 1 } pf_trial_operator;
  * precision. */
 typedef enum { PF_TRIAL_PREDICT_CORRECT = 0, PF_TRIAL_ONLY = 1 } pf_trial_update;
 
+/* Evolution equation (Section 2).  AT2_HISTORY: AT2 (w = d^2, c_w = 2) driven
+ * by the history field H = max(H, Psi+).  AT1_PENALTY: AT1 (w = d,
+ * c_w = 8/3) driven by Psi+ of the current displacement, with the penalty
+ * gamma <d - d_{n-1}>_-, gamma = 27 Gc / (64 l tol_ir^2), as the
+ * irreversibility constraint (eq_evolution_equation); its phase solve is a
+ * semismooth Newton iteration (FP64 in either precision) that ends when a
+ * step leaves the penalty's active points unchanged, and its staggered
+ * residual is ||F_d|| / ||sum 2 Psi+ N||.  H is still kept as the gate's
+ * Psi_max, and Psi_crit defaults to Gc / (c_w l). */
+typedef enum { PF_AT2_HISTORY = 0, PF_AT1_PENALTY = 1 } pf_phase_model;
+
 typedef struct {
   int32_t nx, ny;              /* elements per direction, >= 1              */
   double lx, ly;               /* domain size [mm], > 0                     */
   const uint8_t *elem_active;  /* nx*ny flags (1 = active) or NULL = all    */
 } pf_mesh_desc;
 
-/* Material (Section 2): g(d) = (1-d)^2 + eta, AT2 (w = d^2, c_w = 2). */
+/* Material (Section 2): g(d) = (1-d)^2 + eta; the crack model (AT2 or AT1)
+ * is pf_solver_opts::phase_model. */
 typedef struct {
   double E, nu;    /* Young's modulus [MPa], Poisson ratio                   */
   double Gc, l;    /* fracture toughness [N/mm], length scale [mm]           */
@@ -126,6 +138,8 @@ typedef struct {
   double cheb_ratio;    /* Jacobi-Chebyshev interval [lmax/ratio, lmax]; 0 = 30 */
   int32_t trial_operator; /* pf_trial_operator                                */
   int32_t trial_update;   /* pf_trial_update                                  */
+  double tol_ir;          /* AT1_PENALTY: irreversibility tolerance (0.01)    */
+  int32_t phase_model;    /* pf_phase_model                                   */
 } pf_solver_opts;
 
 typedef struct {
@@ -150,7 +164,7 @@ typedef struct {
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
  * march_rows 0, cg_kernels 0, cheb_ratio 0 (30), trial_operator FLOORED,
- * trial_update PREDICT_CORRECT. */
+ * trial_update PREDICT_CORRECT, tol_ir 0.01, phase_model AT2_HISTORY. */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

@@ -57,7 +57,7 @@ class SolverOpts(ctypes.Structure):
                 ("psi_crit", c_double), ("d_gate", c_double), ("trial_floor", c_double),
                 ("march_rows", c_int32), ("cg_kernels", c_int32),
                 ("cheb_ratio", c_double), ("trial_operator", c_int32),
-                ("trial_update", c_int32)]
+                ("trial_update", c_int32), ("tol_ir", c_double), ("phase_model", c_int32)]
 
 
 class StepStats(ctypes.Structure):
@@ -175,9 +175,6 @@ class Context:
     """
 
     def __init__(self, problem, scheme=ST, precision=FP64, stream=None, **overrides):
-        if int(getattr(problem, "phase_model", 0)) != 0:
-            raise NotImplementedError("the HIP path implements AT2 with the history field "
-                                      "only (phase_model 0)")
         require_device()
         import torch
         self.lib = load_library()
@@ -194,7 +191,8 @@ class Context:
         o.scheme = int(scheme)
         o.precision = int(precision)
         for name in ("tol_stag", "tol_pcg", "tol_newton", "max_stag", "max_newton",
-                     "psi_crit", "d_gate", "trial_floor", "trial_operator", "trial_update"):
+                     "psi_crit", "d_gate", "trial_floor", "trial_operator", "trial_update",
+                     "phase_model", "tol_ir"):
             if hasattr(p, name):
                 setattr(o, name, getattr(p, name))
         for k, v in overrides.items():

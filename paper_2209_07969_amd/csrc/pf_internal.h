@@ -83,7 +83,7 @@ enum ScalSlot {
   SC_SUM_X = 2,     // group reaction x
   SC_SUM_Y = 3,     // group reaction y
 };
-enum ICounter { IC_GATED = 0, IC_FLOOR = 1 };
+enum ICounter { IC_GATED = 0, IC_FLOOR = 1, IC_CHI = 2 };
 
 // Single-kernel CG (Chronopoulos-Gear recurrences): one kernel per iteration.
 // Kernel K_i reduces the partials of K_{i-1} (gamma = r.u, delta = w.u,
@@ -374,22 +374,38 @@ hipError_t internal_force(hipStream_t s, const Grid &g, const March &m, const El
 hipError_t phase_residual(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                           const double *H, const double *d, const uint8_t *eact,
                           const uint8_t *nflag, bool neg, double *R, RedScratch rs);
+// AT1 with the penalty: F_d(d; psi) (c.Gc_l = Gc/(c_w l), c.Gcl = 2 Gc l/c_w),
+// norms as phase_residual with b = sum 2 psi N.
+hipError_t phase_residual_at1(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                              const double *psi, const double *d, const double *dprev,
+                              double gamma, const uint8_t *eact, const uint8_t *nflag, bool neg,
+                              double *R, RedScratch rs);
+// AT1 Newton matrix coefficient 2 psi + gamma chi into coef; chi updated,
+// changed points counted in icount[IC_CHI]; at_kink: d_q = d_{n-1,q} counts
+// as active.
+hipError_t at1_coef(hipStream_t s, const Grid &g, double gamma, const double *psi,
+                    const double *d, const double *dprev, const uint8_t *eact, double *coef,
+                    uint8_t *chi, int at_kink, RedScratch rs);
 
 // Element-wise kernels.
 struct QpParams {
   int scheme;
   double psi_crit, d_gate;
 };
+// psi_out (may be null): Psi+ of the current displacement per point.
 hipError_t qp_update(hipStream_t s, const Grid &g, const Mat &mt, const QpParams &qp,
                      const double *u, const double *d, const uint8_t *eact,
                      const double *H_prev, double *H, double *psi_s, uint8_t *qflag,
-                     RedScratch rs);
+                     double *psi_out, RedScratch rs);
 hipError_t tangent_flags(hipStream_t s, const Grid &g, const double *u, const uint8_t *eact,
                          uint8_t *qflag);
 template <class T>
+// cbase (may be null, may alias coef): the block's own mass coefficient;
+// null means the AT2 coefficient Gc/l + 2H.
 hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta, int floor,
                       const double *H, const double *psi_s, const uint8_t *qflag,
-                      const double *d, const uint8_t *eact, T *coef, RedScratch rs);
+                      const double *d, const uint8_t *eact, const T *cbase, T *coef,
+                      RedScratch rs);
 template <class T>
 hipError_t at2_coef(hipStream_t s, const Grid &g, const Mat &mt, const double *H,
                     const uint8_t *eact, T *coef);

@@ -1001,6 +1001,88 @@ struct OpPhaseRes {
   }
 };
 
+// ---- AT1 residual with the penalty (Section 2, eq_evolution_equation;
+//      F_d of Section 3.2 with w = d): per quadrature point
+//      N [2 Psi+ d - 2 Psi+ + Gc/(c_w l) + gamma <d - d_{n-1}>_-]
+//      + (2 Gc l / c_w) grad N . grad d.  c.Gc_l holds Gc/(c_w l) and c.Gcl
+//      2 Gc l / c_w in an AT1 context.  [0] = F_d, [1] = sum 2 Psi+ N.
+struct OpPhaseResAT1 {
+  using T = double;
+  using Elem = ElemH;
+  static constexpr int NF = 2;
+  static constexpr int NR = 2;
+  struct Node { double d, dp; };
+  Grid g; PhaseCoef c;
+  const double *psi; const double *dd; const double *dprev; const uint8_t *eact;
+  const uint8_t *nflag;
+  double *R; double sign; double gamma;
+
+  __device__ Node load(int i, int j) const {
+    Node n{0.0, 0.0};
+    if (node_exists(g, i, j)) {
+      const int k = i + j * (g.nx + 1);
+      n.d = dd[k];
+      n.dp = dprev[k];
+    }
+    return n;
+  }
+  __device__ void fin(Node &) const {}
+  __device__ Elem eload(int ie, int je) const {
+    Elem e{};
+    if (elem_exists(g, ie, je, eact)) {
+      const int el = ie + je * g.nx;
+      e.H[0] = psi[el];
+      e.H[1] = psi[el + g.E];
+      e.H[2] = psi[el + 2 * g.E];
+      e.H[3] = psi[el + 3 * g.E];
+      e.active = 1;
+    }
+    return e;
+  }
+  static __device__ Node shfl_up(const Node &n) { return Node{lane_up(n.d), lane_up(n.dp)}; }
+  __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
+                          const Elem &e, double (&f)[2][4]) const {
+    if (!e.active) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { f[0][a] = 0; f[1][a] = 0; }
+      return;
+    }
+    const double *Pq = e.H;
+    const double cq[4] = {2.0 * Pq[0], 2.0 * Pq[1], 2.0 * Pq[2], 2.0 * Pq[3]};
+    const double p[4] = {n0.d, n1.d, n2.d, n3.d};
+    phase_element<double>(p, cq, c, f[0]);
+    // QP source Gc/(c_w l) + gamma min(d_q - d_{n-1,q}, 0) - 2 Psi+_q
+    const double pp[4] = {n0.dp, n1.dp, n2.dp, n3.dp};
+    double sq[4];
+    sq[0] = interp4<double, 0>(p[0], p[1], p[2], p[3]) - interp4<double, 0>(pp[0], pp[1], pp[2], pp[3]);
+    sq[1] = interp4<double, 1>(p[0], p[1], p[2], p[3]) - interp4<double, 1>(pp[0], pp[1], pp[2], pp[3]);
+    sq[2] = interp4<double, 2>(p[0], p[1], p[2], p[3]) - interp4<double, 2>(pp[0], pp[1], pp[2], pp[3]);
+    sq[3] = interp4<double, 3>(p[0], p[1], p[2], p[3]) - interp4<double, 3>(pp[0], pp[1], pp[2], pp[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      sq[q] = c.Gc_l + gamma * (sq[q] < 0.0 ? sq[q] : 0.0) - 2.0 * Pq[q];
+    const double w = c.wdet, w2 = 2.0 * c.wdet;
+#define PF_NA(a)                                                                              \
+  f[0][a] += w * (NW<0, a>::v * sq[0] + NW<1, a>::v * sq[1] + NW<2, a>::v * sq[2] +          \
+                  NW<3, a>::v * sq[3]);                                                       \
+  f[1][a] = w2 * (NW<0, a>::v * Pq[0] + NW<1, a>::v * Pq[1] + NW<2, a>::v * Pq[2] +          \
+                  NW<3, a>::v * Pq[3]);
+    PF_NA(0) PF_NA(1) PF_NA(2) PF_NA(3)
+#undef PF_NA
+  }
+  using Own = OwnFlag;
+  __device__ Own load_own(int i, int j) const { return load_flag(nflag, g, i, j); }
+  __device__ void store(int i, int j, const double (&v)[2], const Node &, const Own &o,
+                        double *red) const {
+    const int k = i + j * (g.nx + 1);
+    double r = v[0], b = v[1];
+    if (o.nf & NF_D) { r = 0.0; b = 0.0; }
+    R[k] = sign * r;
+    red[0] += r * r;
+    red[1] += b * b;
+  }
+};
+
 // ---- Jacobi diagonals (inverse, 0 on fixed DOFs)
 template <class TT, int SPL = 0>
 struct OpTangentDiag {
@@ -1993,7 +2075,7 @@ __global__ void __launch_bounds__(TPB) k_qp_update(Grid g, Mat mt, QpParams qp,
                                                    const double *u, const double *d,
                                                    const uint8_t *eact, const double *Hprev,
                                                    double *H, double *psi_s, uint8_t *qflag,
-                                                   RedScratch rs) {
+                                                   double *psi_out, RedScratch rs) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long ng = 0;
   if (e < g.E) {
@@ -2004,6 +2086,7 @@ __global__ void __launch_bounds__(TPB) k_qp_update(Grid g, Mat mt, QpParams qp,
       for (int q = 0; q < 4; ++q) {
         H[e + q * g.E] = Hprev[e + q * g.E];
         psi_s[e + q * g.E] = 0.0;
+        if (psi_out) psi_out[e + q * g.E] = 0.0;
       }
     } else {
       const int n0 = ie + je * (g.nx + 1);
@@ -2042,6 +2125,7 @@ __global__ void __launch_bounds__(TPB) k_qp_update(Grid g, Mat mt, QpParams qp,
       pdev = mt.mu * devdev;                                                             \
     }                                                                                    \
     const double pplus = pvol + pdev;                                                    \
+    if (psi_out) psi_out[e + q * g.E] = pplus;                                           \
     const double hp = Hprev[e + q * g.E];                                                \
     H[e + q * g.E] = pplus > hp ? pplus : hp;                                            \
     double ps = 0.0;                                                                     \
@@ -2109,7 +2193,7 @@ template <class T>
 __global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta, int floor,
                                                     const double *H, const double *psi_s,
                                                     const uint8_t *qflag, const double *d,
-                                                    const uint8_t *eact, T *coef,
+                                                    const uint8_t *eact, const T *cbase, T *coef,
                                                     RedScratch rs) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long hits = 0;
@@ -2128,7 +2212,8 @@ __global__ void __launch_bounds__(TPB) k_trial_coef(Grid g, Mat mt, double theta
     const double Gc_l = mt.Gc / mt.l;
 #define PF_QP(q)                                                                 \
   {                                                                              \
-    const double c = Gc_l + 2.0 * H[e + q * g.E];                                \
+    const double c = cbase ? double(cbase[e + q * g.E])                          \
+                           : Gc_l + 2.0 * H[e + q * g.E];                        \
     double ct = act ? c : 0.0;                                                   \
     if (act && ((fl >> (q + 4)) & 1u)) {                                         \
       const double dq = interp4<double, q>(dn[0], dn[1], dn[2], dn[3]);          \
@@ -2164,6 +2249,53 @@ __global__ void __launch_bounds__(TPB) k_at2_coef(Grid g, Mat mt, const double *
   const int e = i % g.E;
   const bool act = (eact == nullptr) || eact[e] != 0;
   coef[i] = act ? T(mt.Gc / mt.l + 2.0 * H[i]) : T(0);
+}
+
+// AT1 with the penalty: mass coefficient of the semismooth Newton matrix,
+// 2 Psi+_q + gamma chi_q with chi_q = [d_q < d_{n-1,q}] at the quadrature
+// point (Section 2, eq_evolution_equation).  With at_kink, points with
+// d_q = d_{n-1,q} count as active too (the other generalised derivative at
+// the kink).  chi is kept per point; the points whose chi changed since
+// the last call are counted (IC_CHI).
+template <class T>
+__global__ void __launch_bounds__(TPB) k_at1_coef(Grid g, double gamma, const double *psi,
+                                                  const double *d, const double *dprev,
+                                                  const uint8_t *eact, T *coef, uint8_t *chi,
+                                                  int at_kink, RedScratch rs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long nc = 0;
+  if (e < g.E) {
+    const int ie = e % g.nx, je = e / g.nx;
+    const bool act = (eact == nullptr) || eact[e] != 0;
+    const int n0 = ie + je * (g.nx + 1);
+    const int nn[4] = {n0, n0 + 1, n0 + 1 + (g.nx + 1), n0 + (g.nx + 1)};
+    double dn[4], pn[4];
+    for (int a = 0; a < 4; ++a) {
+      dn[a] = d[nn[a]];
+      pn[a] = dprev[nn[a]];
+    }
+#define PF_QP(q)                                                                 \
+  {                                                                              \
+    const int iq = e + q * g.E;                                                  \
+    const double dq = interp4<double, q>(dn[0], dn[1], dn[2], dn[3]);            \
+    const double pq = interp4<double, q>(pn[0], pn[1], pn[2], pn[3]);            \
+    const uint8_t x = (act && (dq < pq || (at_kink && dq == pq))) ? 1 : 0;      \
+    if (x != chi[iq]) nc += 1;                                                   \
+    chi[iq] = x;                                                                 \
+    coef[iq] = act ? T(2.0 * psi[iq] + (x ? gamma : 0.0)) : T(0);                \
+  }
+    PF_QP(0) PF_QP(1) PF_QP(2) PF_QP(3)
+#undef PF_QP
+  }
+  __shared__ unsigned long long shc[TPB / 64];
+  for (int off = 32; off > 0; off >>= 1) nc += __shfl_down(nc, off, 64);
+  if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = nc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += shc[w];
+    if (t) atomicAdd(rs.icount + IC_CHI, t);
+  }
 }
 
 // Fixed-stress predictor: on gated points with Dd_q > 0 the active energy is
@@ -2916,13 +3048,30 @@ hipError_t phase_residual(hipStream_t s, const Grid &g, const March &m, const Ph
   return launch_march_reduce<OpPhaseRes, 2>(s, op, g, m, rs, SC_NORM_A);
 }
 
+hipError_t phase_residual_at1(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                              const double *psi, const double *d, const double *dprev,
+                              double gamma, const uint8_t *eact, const uint8_t *nflag, bool neg,
+                              double *R, RedScratch rs) {
+  OpPhaseResAT1 op{g, c, psi, d, dprev, eact, nflag, R, neg ? -1.0 : 1.0, gamma};
+  return launch_march_reduce<OpPhaseResAT1, 2>(s, op, g, m, rs, SC_NORM_A);
+}
+
+hipError_t at1_coef(hipStream_t s, const Grid &g, double gamma, const double *psi,
+                    const double *d, const double *dprev, const uint8_t *eact, double *coef,
+                    uint8_t *chi, int at_kink, RedScratch rs) {
+  const int blocks = (g.E + TPB - 1) / TPB;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_at1_coef<double>), dim3(blocks), dim3(TPB), 0, s, g, gamma,
+                     psi, d, dprev, eact, coef, chi, at_kink, rs);
+  return hipGetLastError();
+}
+
 hipError_t qp_update(hipStream_t s, const Grid &g, const Mat &mt, const QpParams &qp,
                      const double *u, const double *d, const uint8_t *eact,
                      const double *H_prev, double *H, double *psi_s, uint8_t *qflag,
-                     RedScratch rs) {
+                     double *psi_out, RedScratch rs) {
   const int blocks = (g.E + TPB - 1) / TPB;
   hipLaunchKernelGGL(k_qp_update, dim3(blocks), dim3(TPB), 0, s, g, mt, qp, u, d, eact, H_prev,
-                     H, psi_s, qflag, rs);
+                     H, psi_s, qflag, psi_out, rs);
   return hipGetLastError();
 }
 
@@ -2936,10 +3085,11 @@ hipError_t tangent_flags(hipStream_t s, const Grid &g, const double *u, const ui
 template <class T>
 hipError_t trial_coef(hipStream_t s, const Grid &g, const Mat &mt, double theta, int floor,
                       const double *H, const double *psi_s, const uint8_t *qflag,
-                      const double *d, const uint8_t *eact, T *coef, RedScratch rs) {
+                      const double *d, const uint8_t *eact, const T *cbase, T *coef,
+                      RedScratch rs) {
   const int blocks = (g.E + TPB - 1) / TPB;
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_coef<T>), dim3(blocks), dim3(TPB), 0, s, g, mt,
-                     theta, floor, H, psi_s, qflag, d, eact, coef, rs);
+                     theta, floor, H, psi_s, qflag, d, eact, cbase, coef, rs);
   return hipGetLastError();
 }
 
@@ -3015,7 +3165,8 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                     const uint8_t *, T *, int);                                \
   template hipError_t trial_coef<T>(hipStream_t, const Grid &, const Mat &, double, int,       \
                                     const double *, const double *, const uint8_t *,           \
-                                    const double *, const uint8_t *, T *, RedScratch);         \
+                                    const double *, const uint8_t *, const T *, T *,           \
+                                    RedScratch);                                               \
   template hipError_t at2_coef<T>(hipStream_t, const Grid &, const Mat &, const double *,      \
                                   const uint8_t *, T *);                                       \
   template hipError_t predictor<T>(hipStream_t, const Grid &, const Mat &, const double *,     \

@@ -132,6 +132,14 @@ struct pf_ctx {
   MrState *mrs = nullptr;
   MrState *mrs_h = nullptr;
 
+  // AT1 with the penalty: Psi+ of the current displacement (the driving
+  // energy), the committed d, the penalty's active points, gamma
+  bool at1 = false;
+  double *psi_p = nullptr;
+  double *d_prev = nullptr;
+  uint8_t *chi = nullptr;
+  double gamma = 0.0;
+
   // shared CG launches of a batch (set only inside pf_batch_load_step)
   BatchSvc *svc = nullptr;
   hipEvent_t ready_ev = nullptr;
@@ -317,6 +325,8 @@ constexpr int kTimedRepeat = 4;
 // lambda_max = kChebSafety x the power-iteration estimate
 constexpr double kChebRatio = 30.0;
 constexpr int kPowerCold = 20;
+// AT1: c_w of w(d) = d
+constexpr double kAt1Cw = 8.0 / 3.0;
 constexpr int kPowerWarm = 6;
 // FP64 iterative refinement of the phase solve (mixed precision): floor of
 // the attainable residual relative to ||b||, and the reduction per pass
@@ -1081,6 +1091,63 @@ pf_status phase_res(pf_ctx *c, const double *Hs, bool neg, double *nR, double *n
   return PF_OK;
 }
 
+pf_status phase_res_at1(pf_ctx *c, const double *psi, bool neg, double *nR, double *nb) {
+  PF_HIP(c, phase_residual_at1(c->stream, c->g, c->ms, c->pc, psi, c->d, c->d_prev, c->gamma,
+                               c->eact, c->nflag, neg, c->Rd, c->rs));
+  PF_TRY(read_scal(c));
+  *nR = std::sqrt(c->scal_h[SC_NORM_A]);
+  *nb = std::sqrt(c->scal_h[SC_NORM_B]);
+  if (!is_finite(*nR) || !is_finite(*nb)) return fail(c, PF_E_NONFINITE, "phase residual is not finite");
+  return PF_OK;
+}
+
+// AT1 with the penalty: F_d(d; psi) = 0 by semismooth Newton in FP64.  Each
+// step solves J delta = -F_d with J's mass coefficient 2 psi + gamma chi for
+// the active points chi of the current d.  F_d is linear for a fixed active
+// set, so with exact solves the iteration could end when a step leaves chi
+// unchanged.  The CG solves are exact only to tol_pcg of the step's own
+// residual, and points that sit at the kink (d_q = d_{n-1,q} in the exact
+// solution) then keep flipping in and out of chi at that error level, so
+// the iteration ends on the residual instead: ||F_d|| within tol_pcg of the
+// solve's starting residual (or kRefineFloor of ||b||).  The first step takes points at the kink
+// (d_q = d_{n-1,q}, which is everywhere d has not moved since the last
+// commit) as active: the penalty's stiffness then bounds that step, where
+// the other choice would solve a nearly singular Laplacian wherever Psi+
+// vanishes and overshoot by orders of magnitude.
+constexpr int kAt1MaxNewton = 60;
+pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
+  CgBuf<double> &b = c->bd;
+  const int n = c->g.N;
+  double nR0 = 0.0;
+  for (int it = 0;; ++it) {
+    PF_TRY(zero_icount(c));
+    PF_HIP(c, at1_coef(c->stream, c->g, c->gamma, psi, c->d, c->d_prev, c->eact, b.coef, c->chi,
+                       it == 0 ? 1 : 0, c->rs));
+    double nR = 0.0, nb = 0.0;
+    PF_TRY(phase_res_at1(c, psi, true, &nR, &nb));   // also reads icount (chi changes)
+    if (it == 0) nR0 = nR;
+    const double target = std::max(c->opts.tol_pcg * nR0, kRefineFloor * nb);
+    if (it > 0 && nR <= target) break;
+    if (nR == 0.0) break;
+    if (it >= kAt1MaxNewton)
+      return fail(c, PF_E_NOT_CONVERGED, "AT1 phase solve: active set did not settle");
+    PF_HIP(c, phase_diag<double>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                 b.Dinv));
+    PF_HIP(c, hipMemcpyAsync(b.R[0], c->Rd, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    int iters = 0, status = 0;
+    double *xs = nullptr;
+    PF_TRY(pcg<double>(c, K_PHASE, c->opts.tol_pcg, &iters, &status, &xs));
+    st->n_cg_d += iters;
+    st->dof_updates += (double)iters * (double)c->n_free_d;
+    if (status == 3) st->cg_not_converged += 1;
+    if (status == 2) return fail(c, PF_E_BREAKDOWN, "AT1 phase CG breakdown");
+    PF_HIP(c, axpy_into<double>(c->stream, n, c->d, c->d, 1.0, xs));
+  }
+  st->n_dsolve += 1;
+  return PF_OK;
+}
+
 // Evolution solve K_dd(Hs) d = b(Hs): correction solves d += delta with
 // delta from PCG on the residual; FP64: one solve, mixed: refinement until
 // ||R_d|| <= tol_pcg ||R_d(start)||.
@@ -1123,6 +1190,7 @@ pf_status phase_solve_impl(pf_ctx *c, const double *Hs, pf_step_stats *st) {
 }
 
 pf_status phase_solve(pf_ctx *c, const double *Hs, pf_step_stats *st) {
+  if (c->at1) return phase_solve_at1(c, Hs, st);
   if (c->opts.precision == PF_MIXED) return phase_solve_impl<float>(c, Hs, st);
   return phase_solve_impl<double>(c, Hs, st);
 }
@@ -1166,15 +1234,30 @@ pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
   const bool mixed = std::is_same<T, float>::value;
   const bool literal = c->opts.trial_operator == PF_TRIAL_UNFLOORED;
   const int n = c->g.N;
-  // MINRES runs in FP64 only; trial() never sends the unfloored block here
-  if (mixed && literal) return fail(c, PF_E_STATE, "unfloored trial needs the FP64 path");
+  // MINRES and AT1 run in FP64 only; trial() never sends them here
+  if (mixed && (literal || c->at1)) return fail(c, PF_E_STATE, "this trial needs the FP64 path");
+  // AT2: the history field drives the evolution equation; AT1: Psi+ itself
+  const double *drive = c->at1 ? c->psi_p : c->H;
   PF_TRY(zero_icount(c));
+  const T *cbase = nullptr;
+  if constexpr (std::is_same<T, double>::value) {
+    if (c->at1) {
+      // the semismooth Newton matrix at d^k is the block's base
+      PF_HIP(c, at1_coef(c->stream, c->g, c->gamma, c->psi_p, c->d, c->d_prev, c->eact, b.coef,
+                         c->chi, 0, c->rs));
+      cbase = b.coef;
+    }
+  }
   PF_HIP(c, trial_coef<T>(c->stream, c->g, c->mt, c->opts.trial_floor, literal ? 0 : 1, c->H,
-                          c->psi_s, c->qflag, c->d, c->eact, b.coef, c->rs));
+                          c->psi_s, c->qflag, c->d, c->eact, cbase, b.coef, c->rs));
   PF_HIP(c, phase_diag<T>(c->stream, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag, b.Dinv,
                           literal ? 1 : 0));
   double nR = 0.0, nb = 0.0;
-  PF_TRY(phase_res(c, c->H, true, &nR, &nb));   // also reads icount (floor hits)
+  if (c->at1) {
+    PF_TRY(phase_res_at1(c, drive, true, &nR, &nb));   // also reads icount (floor hits)
+  } else {
+    PF_TRY(phase_res(c, c->H, true, &nR, &nb));
+  }
   st->floor_hits += (int64_t)c->icount_h[IC_FLOOR];
   int iters = 0, status = 0;
   T *xs = nullptr;
@@ -1197,8 +1280,8 @@ pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
   if (c->opts.trial_update == PF_TRIAL_ONLY) {
     PF_HIP(c, axpy_into<T>(c->stream, n, c->d, c->d, 1.0, xs));
   } else {
-    PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, xs, c->H, c->psi_s, c->qflag, c->eact,
-                           c->Hhat));
+    PF_HIP(c, predictor<T>(c->stream, c->g, c->mt, c->d, xs, drive, c->psi_s, c->qflag,
+                           c->eact, c->Hhat));
   }
   st->n_trial += 1;
   return PF_OK;
@@ -1209,7 +1292,7 @@ pf_status trial_impl(pf_ctx *c, pf_step_stats *st) {
 // FP64 path in either precision.
 pf_status trial(pf_ctx *c, pf_step_stats *st) {
   if (c->opts.precision == PF_MIXED && c->opts.trial_operator == PF_TRIAL_FLOORED &&
-      c->opts.trial_update == PF_TRIAL_PREDICT_CORRECT)
+      c->opts.trial_update == PF_TRIAL_PREDICT_CORRECT && !c->at1)
     return trial_impl<float>(c, st);
   return trial_impl<double>(c, st);
 }
@@ -1217,12 +1300,19 @@ pf_status trial(pf_ctx *c, pf_step_stats *st) {
 // QP update from the current (u, d) and the staggered residual.
 pf_status qp_and_residual(pf_ctx *c, double *r) {
   PF_TRY(zero_icount(c));
-  QpParams qp{c->opts.scheme, c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (2.0 * c->mt.l),
+  // Psi_crit = Gc / (c_w l): c_w = 2 (AT2), 8/3 (AT1)
+  const double cw = c->at1 ? kAt1Cw : 2.0;
+  QpParams qp{c->opts.scheme,
+              c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (cw * c->mt.l),
               c->opts.d_gate};
   PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, c->u, c->d, c->eact, c->H_prev, c->H, c->psi_s,
-                      c->qflag, c->rs));
+                      c->qflag, c->at1 ? c->psi_p : nullptr, c->rs));
   double nR = 0.0, nb = 0.0;
-  PF_TRY(phase_res(c, c->H, false, &nR, &nb));   // reads icount too
+  if (c->at1) {
+    PF_TRY(phase_res_at1(c, c->psi_p, false, &nR, &nb));   // reads icount too
+  } else {
+    PF_TRY(phase_res(c, c->H, false, &nR, &nb));
+  }
   c->gated_last = (int64_t)c->icount_h[IC_GATED];
   *r = (nb > 0.0) ? nR / nb : nR;
   return PF_OK;
@@ -1257,6 +1347,9 @@ pf_status open_step(pf_ctx *c, double lam) {
                            c->u));
   PF_HIP(c, lift_dirichlet(c->stream, c->g.N, c->nflag, NF_D | (NF_D << 4), c->g.N, c->d_fix, 1.0,
                            c->d));
+  if (c->at1)
+    PF_HIP(c, lift_dirichlet(c->stream, c->g.N, c->nflag, NF_D | (NF_D << 4), c->g.N, c->d_fix,
+                             1.0, c->d_prev));
   double R0 = 0.0;
   PF_TRY(residual_u(c, c->u, c->Ru, &R0));
   c->R_ref = R0 > 0.0 ? R0 : 1.0;
@@ -1274,7 +1367,7 @@ pf_status open_step(pf_ctx *c, double lam) {
 }
 
 pf_status iterate_once(pf_ctx *c) {
-  const double *Hs = c->H;
+  const double *Hs = c->at1 ? c->psi_p : c->H;
   bool updated = false;
   if (c->opts.scheme != PF_ST) {
     c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, c->gated_last);
@@ -1304,6 +1397,9 @@ void finish_stats(pf_ctx *c, pf_step_stats *st) {
 
 pf_status commit(pf_ctx *c) {
   std::swap(c->H_prev, c->H);
+  if (c->at1)
+    PF_HIP(c, hipMemcpyAsync(c->d_prev, c->d, c->g.N * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
   c->step_open = false;
   double f[2];
   PF_TRY(reaction(c, load_group_of(c), f));
@@ -1328,6 +1424,11 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
   if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
   if (!(o->cheb_ratio >= 0) || (o->cheb_ratio > 0 && o->cheb_ratio <= 1)) {
     *msg = "cheb_ratio must be 0 or > 1";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->phase_model < 0 || o->phase_model > 1 ||
+      (o->phase_model == PF_AT1_PENALTY && !(o->tol_ir > 0))) {
+    *msg = "phase_model must be 0 or 1, with tol_ir > 0 for AT1";
     return PF_E_INVALID_ARG;
   }
   if (o->trial_operator < 0 || o->trial_operator > 1 || o->trial_update < 0 ||
@@ -1411,6 +1512,7 @@ void pf_default_opts(pf_solver_opts *o) {
   o->psi_crit = -1.0;
   o->d_gate = 0.95;
   o->trial_floor = 0.1;
+  o->tol_ir = 0.01;
 }
 
 const char *pf_status_string(pf_status s) {
@@ -1461,6 +1563,13 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
                    g.hy / 4.0, g.hx / 4.0};
   c->pc = PhaseCoef{mt.Gc * mt.l, mt.Gc / mt.l, g.hx * g.hy / 4.0, 1.0 / g.hx, 1.0 / g.hy,
                     g.hy / 4.0, g.hx / 4.0};
+  c->at1 = o.phase_model == PF_AT1_PENALTY;
+  if (c->at1) {
+    // F_d with w = d: Laplacian factor 2 Gc l / c_w, source Gc / (c_w l)
+    c->pc.Gcl = 2.0 * mt.Gc * mt.l / kAt1Cw;
+    c->pc.Gc_l = mt.Gc / (kAt1Cw * mt.l);
+    c->gamma = 27.0 * mt.Gc / (64.0 * mt.l * o.tol_ir * o.tol_ir);
+  }
   c->ms = march_shape(g, o.march_rows);
   // the spectral tangent's 8-row marching item does not fit the register
   // file (it spills); its default is at most 4 rows
@@ -1496,6 +1605,11 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   }
   A(&c->cheb_dev, 4 * (size_t)kChebCoefs);
   A(&c->mrs, 1);
+  if (c->at1) {
+    A(&c->psi_p, E4);
+    A(&c->d_prev, g.N);
+    A(&c->chi, E4);
+  }
   A(&c->cgs, 2);
   A(&c->cgs2, 1);
   A(&c->cgpart, 6 * (size_t)kPMax);
@@ -1701,6 +1815,7 @@ pf_status pf_set_state(pf_ctx *c, const double *u, const double *d, const double
   PF_TRY(sync(c));
   if (u) PF_HIP(c, hipMemcpy(c->u, u, n2 * sizeof(double), hipMemcpyHostToDevice));
   if (d) PF_HIP(c, hipMemcpy(c->d, d, n * sizeof(double), hipMemcpyHostToDevice));
+  if (d && c->at1) PF_HIP(c, hipMemcpy(c->d_prev, d, n * sizeof(double), hipMemcpyHostToDevice));
   if (H) PF_HIP(c, hipMemcpy(c->H_prev, H, e4 * sizeof(double), hipMemcpyHostToDevice));
   return PF_OK;
 }
@@ -1924,7 +2039,8 @@ pf_status pf_op_qp_update(pf_ctx *c, int32_t scheme, const double *u, const doub
   PF_TRY(zero_icount(c));
   QpParams qp{scheme, c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (2.0 * c->mt.l),
               c->opts.d_gate};
-  PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, u, d, c->eact, H_prev, H, psi_s, flags, c->rs));
+  PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, u, d, c->eact, H_prev, H, psi_s, flags, nullptr,
+                      c->rs));
   if (n_gated) {
     PF_TRY(read_scal(c));
     *n_gated = (int64_t)c->icount_h[IC_GATED];

@@ -108,7 +108,7 @@ def test_option_validation_without_device():
     mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
     cases = {"cheb_ratio": 0.5, "cg_kernels": 3, "march_rows": 3, "cheb_degree": 0,
              "max_cg": 0, "max_stag": 0, "scheme": 7, "precision": 2, "precond": 5,
-             "trial_operator": 2, "trial_update": -1}
+             "trial_operator": 2, "trial_update": -1, "phase_model": 2}
     for name, value in cases.items():
         o = pf.default_opts()
         o.precond = 1          # Jacobi-Chebyshev, so that cheb_degree is checked
@@ -129,14 +129,3 @@ def test_batch_and_allocator_argument_checks_without_device():
     assert lib.pf_batch_create(1, arr, 0, ctypes.byref(out)) == 1   # null member
     assert lib.pf_batch_set_shared_launches(None, 1) == 1
     assert lib.pf_set_allocator(None, pf.ALLOC_FN(), pf.RELEASE_FN(), None) == 1
-
-
-def test_context_refuses_models_the_library_lacks():
-    """A problem asking for AT1 with the penalty (an oracle-only model) is
-    refused before any device call, rather than run silently as AT2."""
-    import dataclasses
-    import paper_2209_07969_amd as pf
-    import workloads as W
-    p = dataclasses.replace(W.homogeneous_bar(), phase_model=1)
-    with pytest.raises(NotImplementedError):
-        pf.Context(p)
