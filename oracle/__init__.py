@@ -1,4 +1,4 @@
-"""Plain FP64 CPU oracle for AT2 phase-field fracture with fixed-stress staggering.
+"""Plain FP64 CPU oracle for phase-field fracture with fixed-stress staggering.
 
 TEST INFRASTRUCTURE ONLY.  This package exists to check the HIP path.  Only the
 test suite, the smoke check and the CPU-baseline leg of the benchmark may import
@@ -18,10 +18,14 @@ phase-field model of brittle fracture based on the fixed-stress concept"):
   momentum balance and of the AT2 evolution equation (Section 3.2, weak
   forms; Section 3.4, augmented phase-field block).
 * ``staggered`` - the standard scheme (Section 3.1) and the S1/S2/S3 schemes
-  (Section 3.3-3.5), one load step at a time, with direct sparse solves.
+  (Section 3.3-3.5), one load step at a time, with direct sparse solves; the
+  literal readings of the trial solve (unfloored block, trial-only update).
+* ``at1`` - AT1 with penalised irreversibility (Section 2, the evolution
+  equation with the penalty; Section 3.2, F_d): residual, semismooth Newton
+  matrix and solve.
 
 Readings of passages that are silent or garbled are listed in the project's
 design notes and repeated where they are used.
 """
-from . import constitutive, fem, assembly, staggered  # noqa: F401
+from . import constitutive, fem, assembly, staggered, at1  # noqa: F401
 from .staggered import Oracle, StepStats  # noqa: F401
