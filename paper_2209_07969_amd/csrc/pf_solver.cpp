@@ -1109,7 +1109,12 @@ pf_status phase_res_at1(pf_ctx *c, const double *psi, bool neg, double *nR, doub
 // residual, and points that sit at the kink (d_q = d_{n-1,q} in the exact
 // solution) then keep flipping in and out of chi at that error level, so
 // the iteration ends on the residual instead: ||F_d|| within tol_pcg of the
-// solve's starting residual (or kRefineFloor of ||b||).  The first step takes points at the kink
+// solve's starting residual (or kRefineFloor of ||b||).  A solve that starts
+// from an already converged d (a later staggered iteration) can ask for less
+// than the rounding floor of F_d, whose terms are of order Gc/(c_w l) while
+// ||b|| and the start residual may be orders smaller; so once the active set
+// has stopped changing and a step no longer shrinks ||F_d|| by kRefineStall,
+// the residual is at that floor and the solve ends.  The first step takes points at the kink
 // (d_q = d_{n-1,q}, which is everywhere d has not moved since the last
 // commit) as active: the penalty's stiffness then bounds that step, where
 // the other choice would solve a nearly singular Laplacian wherever Psi+
@@ -1118,7 +1123,7 @@ constexpr int kAt1MaxNewton = 60;
 pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
   CgBuf<double> &b = c->bd;
   const int n = c->g.N;
-  double nR0 = 0.0;
+  double nR0 = 0.0, nR_prev = 0.0;
   for (int it = 0;; ++it) {
     PF_TRY(zero_icount(c));
     PF_HIP(c, at1_coef(c->stream, c->g, c->gamma, psi, c->d, c->d_prev, c->eact, b.coef, c->chi,
@@ -1128,6 +1133,7 @@ pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
     if (it == 0) nR0 = nR;
     const double target = std::max(c->opts.tol_pcg * nR0, kRefineFloor * nb);
     if (it > 0 && nR <= target) break;
+    if (it > 0 && c->icount_h[IC_CHI] == 0 && nR > kRefineStall * nR_prev) break;
     if (nR == 0.0) break;
     if (it >= kAt1MaxNewton)
       return fail(c, PF_E_NOT_CONVERGED, "AT1 phase solve: active set did not settle");
@@ -1143,6 +1149,7 @@ pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
     if (status == 3) st->cg_not_converged += 1;
     if (status == 2) return fail(c, PF_E_BREAKDOWN, "AT1 phase CG breakdown");
     PF_HIP(c, axpy_into<double>(c->stream, n, c->d, c->d, 1.0, xs));
+    nR_prev = nR;
   }
   st->n_dsolve += 1;
   return PF_OK;
