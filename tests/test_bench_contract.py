@@ -1,0 +1,47 @@
+"""The benchmark's host-side contract (no device): the one-GPU refusal, the
+counter-traffic lookup's guards, and the algorithmic byte counts the
+roofline divides by (each a count of the arrays the kernel must move)."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    line = json.loads(out.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_traffic_lookup_guards():
+    b = bench()
+    rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_tension512.json")))
+    # the committed record matches the current kernel source and its own kernel
+    assert b.measured_traffic(rec["kernel"]) == rec["traffic_bytes_per_launch"]
+    # another kernel's name never borrows it
+    assert b.measured_traffic("k_cg_updcheb<1, OpUpdCheb<OpTangent<float>>>") is None
+
+
+def test_algorithmic_bytes_per_node():
+    b = bench()
+    f32, flag = 4, 1
+    # apply: z, p_old, p_new, q (2 comps), d; node and element flags
+    assert b.fused_apply_bytes_per_node() == (4 * 2 + 1) * f32 + 2 * flag
+    # Chebyshev step: d_{k-1}, z, res, D^-1 in; d_k, z, res out (2 comps); d; flags
+    assert b.cheb_step_bytes_per_node() == (7 * 2 + 1) * f32 + 2 * flag
+    # update + first step: r, q, D^-1, x, p in; x, r, d_1, z, res out; d; flags
+    assert b.updcheb_bytes_per_node() == (10 * 2 + 1) * f32 + 2 * flag
+    # vector update: x, p, q, r, D^-1 in; x, r, z out, per DOF
+    assert b.update_bytes_per_node() == 2 * 8 * f32
