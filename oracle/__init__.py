@@ -23,9 +23,11 @@ phase-field model of brittle fracture based on the fixed-stress concept"):
 * ``at1`` - AT1 with penalised irreversibility (Section 2, the evolution
   equation with the penalty; Section 3.2, F_d): residual, semismooth Newton
   matrix and solve.
+* ``hex3d`` - the same model and staggered schemes on 3-D trilinear
+  hexahedra (2x2x2 Gauss) with the full 3-D volumetric-deviatoric split.
 
 Readings of passages that are silent or garbled are listed in the project's
 design notes and repeated where they are used.
 """
-from . import constitutive, fem, assembly, staggered, at1  # noqa: F401
+from . import constitutive, fem, assembly, staggered, at1, hex3d  # noqa: F401
 from .staggered import Oracle, StepStats  # noqa: F401

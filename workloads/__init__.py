@@ -237,6 +237,79 @@ def homogeneous_bar(nx=4, ny=4, lx=1.0, ly=1.0, E=2.1e5, nu=0.3, Gc=2.7, l=0.03,
 
 
 # --------------------------------------------------------------------------
+# Three dimensions (Q1 hexahedra): a slab extruded from a 2-D panel, and a
+# uniaxial bar
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Problem3D:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    ly: float
+    lz: float
+    material: Material
+    dir_u: List[DirichletU]            # comps 0, 1, 2 = x, y, z
+    dir_d_nodes: np.ndarray
+    dir_d_values: np.ndarray
+    loads: np.ndarray
+    load_group: int = 1
+    load_comp: int = 1
+    tol_stag: float = 1e-5
+    tol_pcg: float = 1e-10
+    tol_newton: float = 1e-9
+    max_stag: int = 500
+    max_newton: int = 25
+    psi_crit: float = -1.0
+    d_gate: float = 0.95
+    trial_floor: float = 0.1
+
+
+def slab_from_panel(p: Problem, nz: int = 1, lz: float = 0.1) -> Problem3D:
+    """The 2-D panel extruded over nz element layers of total thickness lz:
+    its Dirichlet data on every node layer, and u_z = 0 everywhere on both
+    faces z = 0 and z = lz (with nz = 1: on every node, i.e. plane strain)."""
+    P = (p.nx + 1) * (p.ny + 1)
+    layers = np.arange(nz + 1)
+    groups = []
+    for g in p.dir_u:
+        nodes = (g.nodes[None, :] + P * layers[:, None]).reshape(-1)
+        groups.append(DirichletU(nodes, np.tile(g.comps, nz + 1), np.tile(g.values, nz + 1)))
+    faces = np.concatenate([np.arange(P), np.arange(P) + nz * P])
+    groups.append(DirichletU(faces, np.full(faces.size, 2, np.int8), np.zeros(faces.size)))
+    dnodes = (p.dir_d_nodes[None, :] + P * layers[:, None]).reshape(-1)
+    return Problem3D(name=p.name + "_slab", nx=p.nx, ny=p.ny, nz=nz, lx=p.lx, ly=p.ly, lz=lz,
+                     material=p.material, dir_u=groups, dir_d_nodes=dnodes,
+                     dir_d_values=np.tile(p.dir_d_values, nz + 1), loads=p.loads.copy(),
+                     load_group=p.load_group, load_comp=p.load_comp, tol_stag=p.tol_stag,
+                     tol_pcg=p.tol_pcg, tol_newton=p.tol_newton, max_stag=p.max_stag,
+                     max_newton=p.max_newton, psi_crit=p.psi_crit, d_gate=p.d_gate,
+                     trial_floor=p.trial_floor)
+
+
+def uniaxial_bar3d(n=3, l=0.03, du=5e-3, steps=6, E=2.1e5, nu=0.3, Gc=2.7) -> Problem3D:
+    """Unit cube on rollers (u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
+    z = 0), top face y = 1 pulled by u_y = lambda: uniaxial stress."""
+    nx = ny = nz = n
+    P = (nx + 1) * (ny + 1)
+    k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    ids = (i + j * (nx + 1) + k * P).reshape(-1)
+    i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)
+    nodes = np.concatenate([ids[i == 0], ids[j == 0], ids[k == 0]])
+    comps = np.concatenate([np.zeros((i == 0).sum()), np.ones((j == 0).sum()),
+                            np.full((k == 0).sum(), 2)]).astype(np.int8)
+    fixed = DirichletU(nodes, comps, np.zeros(nodes.size))
+    top = ids[j == ny]
+    pull = DirichletU(top, np.ones(top.size, np.int8), np.ones(top.size))
+    return Problem3D(name="bar3d", nx=nx, ny=ny, nz=nz, lx=1.0, ly=1.0, lz=1.0,
+                     material=Material(E=E, nu=nu, Gc=Gc, l=l, eta=1e-6),
+                     dir_u=[fixed, pull], dir_d_nodes=np.zeros(0, np.int64),
+                     dir_d_values=np.zeros(0), loads=du * np.arange(1, steps + 1, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
 # Named configurations
 # --------------------------------------------------------------------------
 
