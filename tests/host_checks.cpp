@@ -1,0 +1,68 @@
+// Device-free paths of the C ABI, for a build of the library whose host code
+// carries AddressSanitizer / UndefinedBehaviorSanitizer: option validation,
+// status strings, argument checks on null handles.  Every call here returns
+// before any device work.  Exit status 0 when every call behaves as the
+// header documents.
+#include <cstdio>
+#include <cstring>
+
+#include "../include/phasefield.h"
+
+static int failures = 0;
+#define CHECK(cond)                                                        \
+  do {                                                                     \
+    if (!(cond)) {                                                         \
+      std::fprintf(stderr, "check failed: %s (line %d)\n", #cond, __LINE__); \
+      ++failures;                                                          \
+    }                                                                      \
+  } while (0)
+
+static pf_status create_with(void (*edit)(pf_solver_opts *)) {
+  pf_mesh_desc mesh{4, 4, 1.0, 1.0, nullptr};
+  pf_material mat{2.1e5, 0.3, 2.7, 0.03, 1e-6, 0};
+  pf_solver_opts o;
+  pf_default_opts(&o);
+  o.precond = 1;
+  edit(&o);
+  pf_ctx *ctx = nullptr;
+  pf_status s = pf_create(&mesh, &mat, &o, nullptr, &ctx);
+  CHECK(ctx == nullptr);
+  return s;
+}
+
+int main() {
+  pf_solver_opts o;
+  std::memset(&o, 0xab, sizeof(o));
+  pf_default_opts(&o);
+  CHECK(o.max_stag == 500 && o.trial_floor == 0.1 && o.tol_ir == 0.01 && o.phase_model == 0);
+  for (int s = PF_OK; s <= PF_E_NONFINITE; ++s) CHECK(pf_status_string((pf_status)s) != nullptr);
+
+  CHECK(create_with([](pf_solver_opts *p) { p->scheme = 7; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->precision = 2; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->cheb_degree = 0; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->cheb_ratio = 0.5; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->march_rows = 3; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->trial_floor = 0.0; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->trial_operator = 2; }) == PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->phase_model = 1; p->tol_ir = 0.0; }) ==
+        PF_E_INVALID_ARG);
+  CHECK(create_with([](pf_solver_opts *p) { p->max_cg = 0; }) == PF_E_INVALID_ARG);
+
+  pf_mesh_desc bad{0, 4, 1.0, 1.0, nullptr};
+  pf_material mat{2.1e5, 0.3, 2.7, 0.03, 1e-6, 0};
+  pf_default_opts(&o);
+  pf_ctx *ctx = nullptr;
+  CHECK(pf_create(&bad, &mat, &o, nullptr, &ctx) == PF_E_INVALID_ARG && ctx == nullptr);
+  CHECK(pf_create(nullptr, &mat, &o, nullptr, &ctx) == PF_E_INVALID_ARG);
+
+  CHECK(pf_load_step(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf_staggered_iterate(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf_commit_step(nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf_destroy(nullptr) == PF_E_INVALID_ARG || pf_destroy(nullptr) == PF_OK);
+  CHECK(pf_set_allocator(nullptr, nullptr, nullptr, nullptr) == PF_E_INVALID_ARG);
+  pf_batch *b = nullptr;
+  CHECK(pf_batch_create(0, nullptr, 1, &b) == PF_E_INVALID_ARG && b == nullptr);
+  CHECK(pf_batch_set_shared_launches(nullptr, 1) == PF_E_INVALID_ARG);
+  std::printf(failures ? "host checks: %d failures\n" : "host checks: ok\n", failures);
+  return failures ? 1 : 0;
+}
