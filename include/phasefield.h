@@ -90,10 +90,12 @@ typedef enum { PF_TRIAL_PREDICT_CORRECT = 0, PF_TRIAL_ONLY = 1 } pf_trial_update
  * c_w = 8/3) driven by Psi+ of the current displacement, with the penalty
  * gamma <d - d_{n-1}>_-, gamma = 27 Gc / (64 l tol_ir^2), as the
  * irreversibility constraint (eq_evolution_equation); its phase solve is a
- * semismooth Newton iteration (FP64 in either precision) that ends when a
- * step leaves the penalty's active points unchanged, and its staggered
- * residual is ||F_d|| / ||sum 2 Psi+ N||.  H is still kept as the gate's
- * Psi_max, and Psi_crit defaults to Gc / (c_w l). */
+ * semismooth Newton iteration (FP64 in either precision, at most 60 steps,
+ * PF_E_NOT_CONVERGED beyond) that ends when ||F_d|| is within tol_pcg of the
+ * solve's starting residual, or when the penalty's active points have
+ * stopped changing and a step no longer halves ||F_d|| (its rounding
+ * floor); its staggered residual is ||F_d|| / ||sum 2 Psi+ N||.  H is still
+ * kept as the gate's Psi_max, and Psi_crit defaults to Gc / (c_w l). */
 typedef enum { PF_AT2_HISTORY = 0, PF_AT1_PENALTY = 1 } pf_phase_model;
 
 typedef struct {
