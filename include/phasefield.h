@@ -223,6 +223,9 @@ pf_status pf_load_step(pf_ctx *ctx, double load_factor, pf_step_stats *stats);
  * pf_commit_step closes the step.  Errors: PF_E_STATE if load_factor
  * differs from the open step's. */
 pf_status pf_staggered_iterate(pf_ctx *ctx, double load_factor, pf_step_stats *stats);
+/* Commits the open step: H_n, d_{n-1} (AT1) and the reaction force of the
+ * load group (reported by the next pf_reaction_force).  Errors: PF_E_STATE
+ * when no step is open. */
 pf_status pf_commit_step(pf_ctx *ctx);
 
 /* Reaction force of a Dirichlet group: the sum over its entries of the
@@ -268,6 +271,9 @@ pf_status pf_batch_set_shared_launches(pf_batch *b, int32_t enable);
  * PF_E_NOT_CONVERGED if any member did not converge (all members are still
  * committed), or the first error of a member. */
 pf_status pf_batch_load_step(pf_batch *b, const double *load_factors, pf_step_stats *stats);
+/* Frees the batch and its shared-launch tables (its host threads live only
+ * inside each pf_batch_load_step call); the members stay valid and are
+ * destroyed by their owner afterwards.  NULL is accepted. */
 pf_status pf_batch_destroy(pf_batch *b);
 
 /* Autotuning of the operator kernels' work-item height (2, 4 or 8 node rows
@@ -292,6 +298,9 @@ pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
  * displacement solves, 3 = elasticity Chebyshev step.  Enabling resets the
  * counters. */
 pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
+/* Outputs (each may be NULL): timed launches, their summed milliseconds, and
+ * the nodes one launch covers.  Errors: PF_E_INVALID_ARG for a kernel id
+ * outside 0..3. */
 pf_status pf_kernel_time(pf_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms,
                          int64_t *nodes_per_launch);
 
