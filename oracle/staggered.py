@@ -203,7 +203,9 @@ class Oracle:
     def trial_increment(self, d, H, gate, psi_s):
         """First Newton iteration of the evolution equation with the augmented
         block K_dd + K~ (eq_staggered_NR), K~ only on gated points; its mass
-        coefficient floored at theta c unless trial_operator = 1."""
+        coefficient floored at theta c unless trial_operator = 1.  With AT1
+        (phase_model = 1) K_dd is the semismooth Newton matrix of F_d at d
+        and the right-hand side is -F_d(d); H is then Psi+."""
         dq = self.mesh.interp(d)
         cS = coupling_coefficient(dq, self.eta, psi_s)
         literal = int(getattr(self.p, "trial_operator", 0)) == 1
