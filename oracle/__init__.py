@@ -24,7 +24,8 @@ phase-field model of brittle fracture based on the fixed-stress concept"):
   equation with the penalty; Section 3.2, F_d): residual, semismooth Newton
   matrix and solve.
 * ``hex3d`` - the same model and staggered schemes on 3-D trilinear
-  hexahedra (2x2x2 Gauss) with the full 3-D volumetric-deviatoric split.
+  hexahedra (2x2x2 Gauss) with the full 3-D volumetric-deviatoric or
+  spectral split.
 
 Readings of passages that are silent or garbled are listed in the project's
 design notes and repeated where they are used.

@@ -3,8 +3,9 @@ Test infrastructure: only the tests, the smoke check and the benchmark's CPU
 baseline use it.
 
 The same model and staggered schemes as the 2-D oracle, in three
-dimensions: the volumetric-deviatoric split of Section 2 (eq_sigma) with the
-full 3-D strain, AT2 with the history field, the standard scheme
+dimensions: the volumetric-deviatoric split of Section 2 (eq_sigma) or the
+spectral split named there, both with the full 3-D strain (principal strains
+from a symmetric 3x3 eigendecomposition), AT2 with the history field, the standard scheme
 (Section 3.1) and the fixed-stress schemes S1/S2/S3 with the floored trial
 block, predictor and corrected solve (Sections 3.3-3.5).  The quadrature-
 point algebra of the predictor (coupling coefficient, half-step energy) does
@@ -131,6 +132,82 @@ class VD3D:
         return C
 
 
+def _tensor3(v):
+    """Engineering Voigt [xx, yy, zz, 2yz, 2xz, 2xy] -> symmetric 3x3 tensor."""
+    T = np.zeros(v.shape[:-1] + (3, 3))
+    T[..., 0, 0], T[..., 1, 1], T[..., 2, 2] = v[..., 0], v[..., 1], v[..., 2]
+    T[..., 1, 2] = T[..., 2, 1] = 0.5 * v[..., 3]
+    T[..., 0, 2] = T[..., 2, 0] = 0.5 * v[..., 4]
+    T[..., 0, 1] = T[..., 1, 0] = 0.5 * v[..., 5]
+    return T
+
+
+def _voigt_stress(S):
+    return np.stack([S[..., 0, 0], S[..., 1, 1], S[..., 2, 2], S[..., 1, 2], S[..., 0, 2],
+                     S[..., 0, 1]], axis=-1)
+
+
+class Spectral3D:
+    """Spectral split with the full 3-D strain (named in Section 2): Psi+ =
+    lam/2 <tr eps>_+^2 + mu sum <e_i>_+^2 over the principal strains e_i,
+    sigma = g [lam <t>_+ I + 2 mu eps+] + lam <t>_- I + 2 mu eps-.  A trace or
+    principal strain counts as positive only when strictly above zero."""
+
+    def __init__(self, E, nu):
+        self.lam, self.mu, self.K = lame(E, nu)
+
+    def parts(self, eps):
+        t = eps[..., 0] + eps[..., 1] + eps[..., 2]
+        w = np.linalg.eigvalsh(_tensor3(eps))
+        pv = 0.5 * self.lam * pos(t) ** 2
+        pd = self.mu * np.sum(pos(w) ** 2, axis=-1)
+        pm = 0.5 * self.lam * neg(t) ** 2 + self.mu * np.sum(neg(w) ** 2, axis=-1)
+        return {"t": t, "psi_vol": pv, "psi_dev": pd, "psi_plus": pv + pd, "psi_minus": pm}
+
+    def stress(self, eps, g):
+        t = eps[..., 0] + eps[..., 1] + eps[..., 2]
+        w, Q = np.linalg.eigh(_tensor3(eps))
+        ep = np.einsum("...ik,...k,...jk->...ij", Q, pos(w), Q)
+        en = np.einsum("...ik,...k,...jk->...ij", Q, neg(w), Q)
+        I = np.eye(3)
+        S = (g[..., None, None] * (self.lam * pos(t)[..., None, None] * I + 2 * self.mu * ep)
+             + self.lam * neg(t)[..., None, None] * I + 2 * self.mu * en)
+        return _voigt_stress(S)
+
+    @staticmethod
+    def _plus_map(w, Q, dE):
+        """Directional derivative of eps+ = sum <e_i>_+ n_i n_i along dE: in
+        the eigenbasis, entry (i, j) times (<e_i>_+ - <e_j>_+) / (e_i - e_j),
+        whose limit at e_i = e_j is H(e_i)."""
+        dEp = np.einsum("...ki,...kl,...lj->...ij", Q, dE, Q)
+        h = (w > 0.0).astype(float)
+        wi, wj = w[..., :, None], w[..., None, :]
+        diff = wi - wj
+        with np.errstate(divide="ignore", invalid="ignore"):
+            th = np.where(diff != 0.0, (pos(wi) - pos(wj)) / np.where(diff == 0.0, 1.0, diff),
+                          np.broadcast_to(h[..., :, None], diff.shape))
+        return np.einsum("...ik,...kl,...jl->...ij", Q, th * dEp, Q)
+
+    def tangent(self, eps, g):
+        t = eps[..., 0] + eps[..., 1] + eps[..., 2]
+        hp = (t > 0.0).astype(float)
+        w, Q = np.linalg.eigh(_tensor3(eps))
+        C = np.zeros(eps.shape[:-1] + (6, 6))
+        I = np.eye(3)
+        for col in range(6):
+            dv = np.zeros(eps.shape)
+            dv[..., col] = 1.0
+            dt = dv[..., 0] + dv[..., 1] + dv[..., 2]
+            dE = _tensor3(dv)
+            dEp = self._plus_map(w, Q, dE)
+            dS = (g[..., None, None] * (self.lam * (hp * dt)[..., None, None] * I
+                                        + 2 * self.mu * dEp)
+                  + self.lam * ((1 - hp) * dt)[..., None, None] * I
+                  + 2 * self.mu * (dE - dEp))
+            C[..., :, col] = _voigt_stress(dS)
+        return C
+
+
 def _csr(rows, cols, vals, n):
     return sp.csr_matrix((vals.reshape(-1), (rows.reshape(-1), cols.reshape(-1))), shape=(n, n))
 
@@ -191,7 +268,7 @@ class Oracle3D:
         self.p, self.scheme = p, int(scheme)
         m = p.material
         self.mesh = Mesh3D(p.nx, p.ny, p.nz, p.lx, p.ly, p.lz)
-        self.cons = VD3D(m.E, m.nu)
+        self.cons = VD3D(m.E, m.nu) if int(m.split) == 0 else Spectral3D(m.E, m.nu)
         self.Gc, self.l, self.eta = m.Gc, m.l, m.eta
         self.psi_crit = p.psi_crit if p.psi_crit >= 0 else m.Gc / (2.0 * m.l)
         nn = self.mesh.n_nodes

@@ -11,13 +11,20 @@
   eps (1 - 2 nu) is positive), so d = l E eps^2 / (Gc + l E eps^2) and the
   reaction force is g(d) E eps times the face area (textbook 3-D values,
   with E, not the plane-strain modulus).
+* Spectral split in 3-D: the shear panel (spectral split) extruded into a
+  slab matches the 2-D spectral oracle the same way (the out-of-plane
+  principal strain is zero); a diagonal strain with mixed signs gives the
+  energies and stresses by hand; rotating the strain rotates the stress and
+  leaves the energies unchanged (catches a wrong engineering-shear factor);
+  with every principal strain positive both splits give the undamaged
+  energy lam/2 t^2 + mu eps:eps; the tangent is the stress's derivative.
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import Oracle
-from oracle.hex3d import Oracle3D
+from oracle.hex3d import Oracle3D, Spectral3D, VD3D
 
 
 @pytest.mark.parametrize("nz", [1, 2])
@@ -69,3 +76,127 @@ def test_uniaxial_bar3d_closed_form(scheme):
             assert st.n_stag == 2
         else:
             assert st.n_stag <= 3
+
+
+def _assert_slab_matches(p2, scheme, nz, lz):
+    o2, o3 = Oracle(p2, scheme), Oracle3D(W.slab_from_panel(p2, nz=nz, lz=lz), scheme)
+    P = (p2.nx + 1) * (p2.ny + 1)
+    trials = 0
+    for lam in p2.loads:
+        s2, s3 = o2.load_step(float(lam)), o3.load_step(float(lam))
+        assert s2.converged and s3.converged
+        assert s2.n_stag == s3.n_stag, (scheme, lam, s2.n_stag, s3.n_stag)
+        trials += s3.n_trial
+        for k in range(nz + 1):
+            np.testing.assert_allclose(o3.d[k * P:(k + 1) * P], o2.d, rtol=1e-8, atol=1e-12)
+            uk = o3.u[3 * k * P:3 * (k + 1) * P]
+            np.testing.assert_allclose(uk[0::3], o2.u[0::2], rtol=1e-8, atol=1e-14)
+            np.testing.assert_allclose(uk[1::3], o2.u[1::2], rtol=1e-8, atol=1e-14)
+        assert np.abs(o3.u[2::3]).max() < 1e-14
+        assert np.isclose(s3.force, s2.force * lz, rtol=1e-8)
+    return trials
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+def test_spectral_slab_is_plane_strain(scheme):
+    # shear panel, spectral split; the second step runs gated trial solves (S1, S3)
+    p2 = W.shear_panel(n=8, l=0.2, du=4e-3, steps=2)
+    assert p2.material.split == W.SPLIT_SPECTRAL
+    trials = _assert_slab_matches(p2, scheme, nz=1, lz=0.1)
+    if scheme != 0:
+        assert trials > 0
+
+
+def test_spectral_slab_two_layers():
+    p2 = W.shear_panel(n=8, l=0.2, du=4e-3, steps=2)
+    assert _assert_slab_matches(p2, 1, nz=2, lz=0.1) > 0
+
+
+E, NU = 2.1e5, 0.3
+LAM = E * NU / ((1 + NU) * (1 - 2 * NU))
+MU = E / (2 * (1 + NU))
+
+
+def _rotation(a, b, c):
+    Rz = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]])
+    Ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(c), -np.sin(c)], [0, np.sin(c), np.cos(c)]])
+    return Rz @ Ry @ Rx
+
+
+def _voigt_strain(T):
+    return np.array([T[0, 0], T[1, 1], T[2, 2], 2 * T[1, 2], 2 * T[0, 2], 2 * T[0, 1]])
+
+
+def _stress_tensor(s):
+    return np.array([[s[0], s[5], s[4]], [s[5], s[1], s[3]], [s[4], s[3], s[2]]])
+
+
+def test_spectral3d_diagonal_hand_values():
+    c = Spectral3D(E, NU)
+    a, b, cz = 2e-3, -1e-3, 5e-4
+    t = a + b + cz
+    eps = np.array([[a, b, cz, 0.0, 0.0, 0.0]])
+    g = np.array([0.36])
+    P = c.parts(eps)
+    assert np.isclose(P["psi_vol"][0], 0.5 * LAM * t * t, rtol=1e-13)
+    assert np.isclose(P["psi_dev"][0], MU * (a * a + cz * cz), rtol=1e-13)
+    assert np.isclose(P["psi_minus"][0], MU * b * b, rtol=1e-13)
+    s = c.stress(eps, g)[0]
+    ref = [g[0] * (LAM * t + 2 * MU * a), g[0] * LAM * t + 2 * MU * b,
+           g[0] * (LAM * t + 2 * MU * cz), 0.0, 0.0, 0.0]
+    np.testing.assert_allclose(s, ref, rtol=1e-12, atol=1e-9)
+    # negative trace: the volumetric part goes undegraded
+    eps_c = np.array([[-a, b, -cz, 0.0, 0.0, 0.0]])
+    tc = -a + b - cz
+    sc = c.stress(eps_c, g)[0]
+    assert np.isclose(sc[0], LAM * tc + 2 * MU * (-a), rtol=1e-12)
+    assert np.isclose(c.parts(eps_c)["psi_plus"][0], 0.0)
+
+
+def test_spectral3d_rotation_covariance():
+    c = Spectral3D(E, NU)
+    D = np.diag([2e-3, -1e-3, 5e-4])
+    eps0 = _voigt_strain(D)[None]
+    g = np.array([0.5])
+    P0, S0 = c.parts(eps0), _stress_tensor(c.stress(eps0, g)[0])
+    for angles in [(0.3, 0.0, 0.0), (0.4, -0.7, 1.1), (2.0, 0.5, -0.9)]:
+        R = _rotation(*angles)
+        epsR = _voigt_strain(R @ D @ R.T)[None]
+        PR = c.parts(epsR)
+        for k in ("psi_vol", "psi_dev", "psi_minus"):
+            assert np.isclose(PR[k][0], P0[k][0], rtol=1e-12)
+        np.testing.assert_allclose(_stress_tensor(c.stress(epsR, g)[0]), R @ S0 @ R.T,
+                                   rtol=1e-10, atol=1e-7)
+
+
+def test_spectral_and_vd_agree_in_triaxial_tension():
+    rng = np.random.default_rng(11)
+    Q = _rotation(*rng.uniform(-np.pi, np.pi, 3))
+    D = np.diag([3e-3, 1e-3, 2e-4])
+    eps = _voigt_strain(Q @ D @ Q.T)[None]
+    g = np.array([0.25])
+    sp3, vd = Spectral3D(E, NU), VD3D(E, NU)
+    t = 4.2e-3
+    total = 0.5 * LAM * t * t + MU * np.sum(np.diag(D) ** 2)
+    for c in (sp3, vd):
+        P = c.parts(eps)
+        assert np.isclose(P["psi_plus"][0], total, rtol=1e-12)
+        assert P["psi_minus"][0] == pytest.approx(0.0, abs=1e-12 * total)
+    np.testing.assert_allclose(sp3.stress(eps, g), vd.stress(eps, g), rtol=1e-10, atol=1e-8)
+    np.testing.assert_allclose(sp3.tangent(eps, g), vd.tangent(eps, g), rtol=1e-10, atol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_spectral3d_tangent_is_stress_derivative(seed):
+    rng = np.random.default_rng(seed)
+    c = Spectral3D(E, NU)
+    eps = rng.normal(size=(6, 6)) * 1e-3
+    g = rng.uniform(0.05, 1.0, 6)
+    C = c.tangent(eps, g)
+    h = 1e-8
+    for k in range(6):
+        dv = np.zeros(6)
+        dv[k] = h
+        fd = (c.stress(eps + dv, g) - c.stress(eps - dv, g)) / (2 * h)
+        np.testing.assert_allclose(fd, C[:, :, k], rtol=0, atol=1e-8 * np.abs(C).max())
