@@ -171,8 +171,10 @@ void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t
  * (NULL = the null stream) on which every kernel of this context runs.  All
- * device memory is owned by the context.  Errors: PF_E_INVALID_ARG for bad
- * sizes or options, PF_E_OOM, PF_E_HIP. */
+ * device memory is owned by the context.  Size limit (32-bit kernel
+ * indices): 2 (nx+1)(ny+1) and 4 nx ny at most 2^31 - 2^16, i.e. up to
+ * about 23170 x 23170 elements.  Errors: PF_E_INVALID_ARG for bad sizes or
+ * options (checked before any device call), PF_E_OOM, PF_E_HIP. */
 pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat,
                     const pf_solver_opts *opts, void *hip_stream, pf_ctx **out);
 
@@ -252,12 +254,16 @@ pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
  * sweep of uneven instances).  Each member context should have its own HIP
  * stream (pf_create's hip_stream).  Two modes:
  *  - shared launches (default): one host thread per member runs its load
- *    step; its FP32 Jacobi CG solves (mixed precision) are queued, and once
- *    every member still inside its step is waiting, all queued systems are
- *    iterated together: per CG iteration one apply launch per (operator,
- *    split, work-item height) and one update launch, over a table of the
- *    systems, each keeping the blocks it would have on its own.  Other
- *    solves (FP64, Jacobi-Chebyshev) run on the member's stream.
+ *    step; its FP32 Jacobi CG solves (mixed precision) go to a service
+ *    thread that keeps one CG loop running over every queued system: per CG
+ *    iteration one apply launch per (operator, split, work-item height) and
+ *    one update launch, over a table of the systems, each keeping the
+ *    blocks it would have on its own.  Every few iterations (at the status
+ *    poll) finished systems return to their members and newly queued ones
+ *    join, so no member waits for another's solve to end.  Other solves
+ *    (FP64, Jacobi-Chebyshev) run on the member's stream.  The tables live
+ *    in memory of the batch's own (hipMalloc and hipHostMalloc), not in a
+ *    member's installed allocator.
  *  - concurrent streams: a pool of `workers` host threads (0 = 4) runs the
  *    members' steps, whose kernels overlap on the GPU.
  * Results are bit-identical to stepping the members one by one in either

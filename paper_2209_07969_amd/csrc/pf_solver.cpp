@@ -18,7 +18,6 @@
 #include <mutex>
 #include <thread>
 #include <tuple>
-#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -322,18 +321,22 @@ pf_status upload_constraints(pf_ctx *c) {
 enum Kind { K_ELASTIC = 0, K_PHASE = 1 };
 constexpr int kTimedRepeat = 4;
 // Jacobi-Chebyshev interval [lambda_max / kChebRatio, lambda_max] with
-// lambda_max = kChebSafety x the power-iteration estimate
+// lambda_max = kChebSafety x the power-iteration estimate; power-iteration
+// steps of a cold and of a warm estimate
 constexpr double kChebRatio = 30.0;
+constexpr double kChebSafety = 1.2;
 constexpr int kPowerCold = 20;
-// AT1: c_w of w(d) = d
-constexpr double kAt1Cw = 8.0 / 3.0;
 constexpr int kPowerWarm = 6;
 // FP64 iterative refinement of the phase solve (mixed precision): floor of
 // the attainable residual relative to ||b||, and the reduction per pass
 // below which the passes are taken to have stalled
 constexpr double kRefineFloor = 1e-13;
 constexpr double kRefineStall = 0.5;
-constexpr double kChebSafety = 1.2;
+// AT1: c_w of w(d) = d
+constexpr double kAt1Cw = 8.0 / 3.0;
+// largest 2N and 4E a context accepts: 32-bit indices with room for rounding
+// up to whole blocks
+constexpr long long kMaxIndexCount = (1LL << 31) - (1LL << 16);
 
 template <class T>
 CgBuf<T> &buf(pf_ctx *c);
@@ -1114,11 +1117,11 @@ pf_status phase_res_at1(pf_ctx *c, const double *psi, bool neg, double *nR, doub
 // than the rounding floor of F_d, whose terms are of order Gc/(c_w l) while
 // ||b|| and the start residual may be orders smaller; so once the active set
 // has stopped changing and a step no longer shrinks ||F_d|| by kRefineStall,
-// the residual is at that floor and the solve ends.  The first step takes points at the kink
-// (d_q = d_{n-1,q}, which is everywhere d has not moved since the last
-// commit) as active: the penalty's stiffness then bounds that step, where
-// the other choice would solve a nearly singular Laplacian wherever Psi+
-// vanishes and overshoot by orders of magnitude.
+// the residual is at that floor and the solve ends.  The first step takes
+// points at the kink (d_q = d_{n-1,q}, which is everywhere d has not moved
+// since the last commit) as active: the penalty's stiffness then bounds that
+// step, where the other choice would solve a nearly singular Laplacian
+// wherever Psi+ vanishes and overshoot by orders of magnitude.
 constexpr int kAt1MaxNewton = 60;
 pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
   CgBuf<double> &b = c->bd;
@@ -1369,7 +1372,6 @@ pf_status open_step(pf_ctx *c, double lam) {
   double r = 0.0;
   PF_TRY(qp_and_residual(c, &r));
   c->acc.r_stag = r;
-  c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, 0);
   return PF_OK;
 }
 
@@ -1416,9 +1418,18 @@ pf_status commit(pf_ctx *c) {
 }
 
 pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
-  if (o->scheme < 0 || o->scheme > 3) { *msg = "scheme"; return PF_E_INVALID_ARG; }
-  if (o->precision < 0 || o->precision > 1) { *msg = "precision"; return PF_E_INVALID_ARG; }
-  if (o->precond != PF_PC_JACOBI && o->precond != PF_PC_JACOBI_CHEBYSHEV) { *msg = "precond"; return PF_E_INVALID_ARG; }
+  if (o->scheme < 0 || o->scheme > 3) {
+    *msg = "scheme";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->precision < 0 || o->precision > 1) {
+    *msg = "precision";
+    return PF_E_INVALID_ARG;
+  }
+  if (o->precond != PF_PC_JACOBI && o->precond != PF_PC_JACOBI_CHEBYSHEV) {
+    *msg = "precond";
+    return PF_E_INVALID_ARG;
+  }
   if (o->precond == PF_PC_JACOBI_CHEBYSHEV && (o->cheb_degree < 1 || o->cheb_degree > 16)) {
     *msg = "cheb_degree must be in 1..16";
     return PF_E_INVALID_ARG;
@@ -1427,8 +1438,14 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
     *msg = "tolerances must be > 0";
     return PF_E_INVALID_ARG;
   }
-  if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) { *msg = "iteration limits"; return PF_E_INVALID_ARG; }
-  if (!(o->trial_floor > 0) || o->trial_floor > 1) { *msg = "trial_floor must be in (0,1]"; return PF_E_INVALID_ARG; }
+  if (o->max_stag < 1 || o->max_newton < 1 || o->max_cg < 1) {
+    *msg = "iteration limits";
+    return PF_E_INVALID_ARG;
+  }
+  if (!(o->trial_floor > 0) || o->trial_floor > 1) {
+    *msg = "trial_floor must be in (0,1]";
+    return PF_E_INVALID_ARG;
+  }
   if (!(o->cheb_ratio >= 0) || (o->cheb_ratio > 0 && o->cheb_ratio <= 1)) {
     *msg = "cheb_ratio must be 0 or > 1";
     return PF_E_INVALID_ARG;
@@ -1543,8 +1560,11 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   if (!mesh || !mat || !out) return PF_E_INVALID_ARG;
   *out = nullptr;
   if (mesh->nx < 1 || mesh->ny < 1 || !(mesh->lx > 0) || !(mesh->ly > 0)) return PF_E_INVALID_ARG;
-  const long long N = (long long)(mesh->nx + 1) * (mesh->ny + 1);
-  if (2 * N >= (1LL << 31)) return PF_E_INVALID_ARG;
+  // the kernels index displacement DOFs (2N) and quadrature points (4E) with
+  // 32-bit ints, and round those counts up to whole blocks
+  const long long N = ((long long)mesh->nx + 1) * ((long long)mesh->ny + 1);
+  const long long E = (long long)mesh->nx * mesh->ny;
+  if (2 * N > kMaxIndexCount || 4 * E > kMaxIndexCount) return PF_E_INVALID_ARG;
   if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0) || !(mat->l > 0) ||
       !(mat->eta >= 0) || (mat->split != PF_SPLIT_VD && mat->split != PF_SPLIT_SPECTRAL))
     return PF_E_INVALID_ARG;

@@ -59,6 +59,23 @@ def test_create_rejects_bad_arguments_without_device():
     assert not h.value
 
 
+def test_create_rejects_meshes_beyond_32bit_indices_without_device():
+    """The kernels index 2N displacement DOFs and 4E quadrature points with
+    32-bit ints; larger meshes are refused before any device call (4E is the
+    binding count on square meshes, 2N on thin strips, and nx + 1 must not
+    overflow when nx is the largest int32)."""
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
+    for nx, ny in [(23200, 23200), (1 << 15, 1 << 15), (1, 1 << 29), (1 << 29, 1),
+                   (2 ** 31 - 1, 1), (2 ** 31 - 1, 2 ** 31 - 1)]:
+        h = ctypes.c_void_p()
+        mesh = pf.MeshDesc(nx, ny, 1.0, 1.0, None)
+        assert lib.pf_create(ctypes.byref(mesh), ctypes.byref(mat), None, None,
+                             ctypes.byref(h)) == 1, (nx, ny)
+        assert not h.value
+
+
 def c_layout(structs):
     """sizeof and every field's offsetof, as the C compiler lays the header's
     structs out (gcc on a program that includes the header)."""
