@@ -152,10 +152,23 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(POINTER(ctype))
 
 
-def _dev_ptr(t):
+def _dev_arg(t, dtype, count, device, name):
+    """Pointer to tensor t after checking what the C ABI cannot: its dtype,
+    that it holds at least `count` elements (the kernels read or write that
+    many), that it is contiguous and resident on the context's device."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
-        raise ValueError("expected a contiguous device tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if t.numel() < count:
+        raise ValueError(f"{name}: needs {count} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.device.index != device:
+        raise ValueError(f"{name}: tensor is on device {t.device.index}, the context on {device}")
     return c_void_p(t.data_ptr())
 
 
@@ -208,6 +221,7 @@ class Context:
             raise PhaseFieldError(st, "pf_create failed: " +
                                   self.lib.pf_status_string(st).decode())
         self.h = h
+        self.device = torch.cuda.current_device()
         self.N = (p.nx + 1) * (p.ny + 1)
         self.E = p.nx * p.ny
         for gi, grp in enumerate(p.dir_u):
@@ -339,29 +353,48 @@ class Context:
         return n.value, ms.value, nodes.value
 
     # ------------------------------------------------- operator entries
+    # Device tensors in the layouts of include/phasefield.h: displacement
+    # fields [2N] (x plane, then y plane), nodal fields [N], quadrature-point
+    # fields [4E] (plane q holds point q of every element), flags [E] (uint8).
+    def _nodal(self, t, name, comps=1):
+        import torch
+        return _dev_arg(t, torch.float64, comps * self.N, self.device, name)
+
+    def _qp(self, t, name):
+        import torch
+        return _dev_arg(t, torch.float64, 4 * self.E, self.device, name)
+
+    def _flags(self, t, name):
+        import torch
+        return _dev_arg(t, torch.uint8, self.E, self.device, name)
+
     def op_internal_force(self, u, d, R):
-        self._check(self.lib.pf_op_internal_force(self.h, _dev_ptr(u), _dev_ptr(d), _dev_ptr(R)),
+        self._check(self.lib.pf_op_internal_force(self.h, self._nodal(u, "u", 2),
+                                                  self._nodal(d, "d"), self._nodal(R, "R", 2)),
                     "pf_op_internal_force")
 
     def op_tangent_apply(self, u, d, p, q):
-        self._check(self.lib.pf_op_tangent_apply(self.h, _dev_ptr(u), _dev_ptr(d), _dev_ptr(p),
-                                                 _dev_ptr(q)), "pf_op_tangent_apply")
+        self._check(self.lib.pf_op_tangent_apply(self.h, self._nodal(u, "u", 2), self._nodal(d, "d"),
+                                                 self._nodal(p, "p", 2), self._nodal(q, "q", 2)),
+                    "pf_op_tangent_apply")
 
     def op_phase_apply(self, coef, p, q):
-        self._check(self.lib.pf_op_phase_apply(self.h, _dev_ptr(coef), _dev_ptr(p), _dev_ptr(q)),
-                    "pf_op_phase_apply")
+        self._check(self.lib.pf_op_phase_apply(self.h, self._qp(coef, "coef"), self._nodal(p, "p"),
+                                               self._nodal(q, "q")), "pf_op_phase_apply")
 
     def op_qp_update(self, scheme, u, d, H_prev, H, psi_s, flags):
         n = c_int64()
-        self._check(self.lib.pf_op_qp_update(self.h, int(scheme), _dev_ptr(u), _dev_ptr(d),
-                                             _dev_ptr(H_prev), _dev_ptr(H), _dev_ptr(psi_s),
-                                             _dev_ptr(flags), ctypes.byref(n)),
+        self._check(self.lib.pf_op_qp_update(self.h, int(scheme), self._nodal(u, "u", 2),
+                                             self._nodal(d, "d"), self._qp(H_prev, "H_prev"),
+                                             self._qp(H, "H"), self._qp(psi_s, "psi_s"),
+                                             self._flags(flags, "flags"), ctypes.byref(n)),
                     "pf_op_qp_update")
         return n.value
 
     def op_predictor(self, d, dd, H, psi_s, flags, Hhat):
-        self._check(self.lib.pf_op_predictor(self.h, _dev_ptr(d), _dev_ptr(dd), _dev_ptr(H),
-                                             _dev_ptr(psi_s), _dev_ptr(flags), _dev_ptr(Hhat)),
+        self._check(self.lib.pf_op_predictor(self.h, self._nodal(d, "d"), self._nodal(dd, "dd"),
+                                             self._qp(H, "H"), self._qp(psi_s, "psi_s"),
+                                             self._flags(flags, "flags"), self._qp(Hhat, "Hhat")),
                     "pf_op_predictor")
 
 
@@ -385,6 +418,8 @@ class Batch:
             raise PhaseFieldError(st, "pf_batch_set_shared_launches failed")
 
     def load_step(self, load_factors, allow_not_converged=True):
+        if any(not getattr(c, "h", None) for c in self.members):
+            raise RuntimeError("a member context was closed before the batch")
         n = len(self.members)
         lam = np.ascontiguousarray(load_factors, dtype=np.float64)
         if lam.size != n:

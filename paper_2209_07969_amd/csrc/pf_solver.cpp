@@ -1307,14 +1307,18 @@ pf_status trial(pf_ctx *c, pf_step_stats *st) {
   return trial_impl<double>(c, st);
 }
 
+// Softening threshold of the gate: the option, or Psi_crit = Gc / (c_w l)
+// with c_w = 2 (AT2) or 8/3 (AT1).
+double psi_crit_of(const pf_ctx *c) {
+  if (c->opts.psi_crit >= 0) return c->opts.psi_crit;
+  const double cw = c->at1 ? kAt1Cw : 2.0;
+  return c->mt.Gc / (cw * c->mt.l);
+}
+
 // QP update from the current (u, d) and the staggered residual.
 pf_status qp_and_residual(pf_ctx *c, double *r) {
   PF_TRY(zero_icount(c));
-  // Psi_crit = Gc / (c_w l): c_w = 2 (AT2), 8/3 (AT1)
-  const double cw = c->at1 ? kAt1Cw : 2.0;
-  QpParams qp{c->opts.scheme,
-              c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (cw * c->mt.l),
-              c->opts.d_gate};
+  QpParams qp{c->opts.scheme, psi_crit_of(c), c->opts.d_gate};
   PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, c->u, c->d, c->eact, c->H_prev, c->H, c->psi_s,
                       c->qflag, c->at1 ? c->psi_p : nullptr, c->rs));
   double nR = 0.0, nb = 0.0;
@@ -2064,8 +2068,7 @@ pf_status pf_op_qp_update(pf_ctx *c, int32_t scheme, const double *u, const doub
   if (!c || !u || !d || !H_prev || !H || !psi_s || !flags) return PF_E_INVALID_ARG;
   if (scheme < 0 || scheme > 3) return fail(c, PF_E_INVALID_ARG, "scheme");
   PF_TRY(zero_icount(c));
-  QpParams qp{scheme, c->opts.psi_crit >= 0 ? c->opts.psi_crit : c->mt.Gc / (2.0 * c->mt.l),
-              c->opts.d_gate};
+  QpParams qp{scheme, psi_crit_of(c), c->opts.d_gate};
   PF_HIP(c, qp_update(c->stream, c->g, c->mt, qp, u, d, c->eact, H_prev, H, psi_s, flags, nullptr,
                       c->rs));
   if (n_gated) {
