@@ -160,7 +160,9 @@ def cpu_baseline(pf, problem):
     """Oracle (FP64, sparse direct solves) on a bounded sample: the k = 0
     displacement solve of load step 1 limited to one Newton iteration.  The
     GPU performs the same sample (FP64 ST, one Newton iteration) and its
-    DOF-update count converts the oracle's time into the metric's unit."""
+    DOF-update count converts the oracle's time into the metric's unit.
+    cores: the process's CPU time over the wall time of the sample (all
+    threads, so a multithreaded library call would show), rounded, at least 1."""
     import dataclasses
 
     import oracle
@@ -173,7 +175,7 @@ def cpu_baseline(pf, problem):
     import numpy as np
     orc = oracle.Oracle(p1, 0)
     lam = float(p1.loads[0])
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     u = orc.u.copy()
     u[orc.u_fixed] = lam * orc.u_unit[orc.u_fixed]
     R0 = np.linalg.norm(orc.residual_u(u, orc.d)[orc.u_free])
@@ -181,15 +183,16 @@ def cpu_baseline(pf, problem):
     parts = orc.energies(u, orc.d)
     H = np.maximum(orc.H, parts["psi_plus"])
     orc.stag_residual(orc.d, H)
-    t = time.perf_counter() - t0
-    cores = 1
+    t, cpu_s = time.perf_counter() - t0, time.process_time() - c0
+    cores = max(1, round(cpu_s / t))
     return {
         "value": gpu_updates / t / 1e9,
         "unit": "GDOF-updates/s (GPU-equivalent)",
         "cores": cores,
         "kind": "oracle",
         "sample": (f"{problem.name}: load step 1, k=0 displacement solve with one Newton "
-                   f"iteration (assembled CSR + SuperLU), {t:.1f} s on 1 host core; "
+                   f"iteration (assembled CSR + SuperLU), {t:.1f} s wall, {cpu_s:.1f} s CPU "
+                   f"({cores} host core{'s' if cores > 1 else ''}); "
                    f"rate = GPU CG DOF-updates for the same sample ({gpu_updates:.3e}) / "
                    f"oracle time"),
         "seconds": t,
