@@ -1,0 +1,78 @@
+/* phasefield3d.h - C ABI of the 3-D operators: trilinear hexahedra (Q1,
+ * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric split of
+ * Section 2 with the full 3-D strain and the AT2 phase operator.  They are
+ * the operators of the 2-D path (internal force, tangent apply, phase
+ * apply, quadrature-point update) on a mesh of hexahedra, as in the paper's
+ * one-element-thick slab (Section 4) or a full 3-D panel.
+ *
+ * Every entry point is stateless: it takes the mesh and material by value
+ * (read on the host), device pointers for the fields, and a hipStream_t
+ * (void *, NULL = the null stream) on which its one kernel is enqueued; it
+ * returns once the kernel is enqueued, without synchronising.  Fields are
+ * structure-of-arrays in device memory, all FP64 unless stated:
+ *   node (i, j, k) has id n = i + j (nx+1) + k (nx+1)(ny+1), N nodes;
+ *   element (ie, je, ke) has id e = ie + je nx + ke nx ny, E elements;
+ *   displacement-like fields [3N]: the x plane, then y, then z;
+ *   nodal scalars [N]; quadrature-point fields [8E], plane q holding point
+ *   q of every element (index e + q E).  Corner a of an element sits at
+ *   offsets (((a+1)>>1)&1, (a>>1)&1, a>>2) from its first node, and Gauss
+ *   point q at reference coordinates (2 di - 1, 2 dj - 1, 2 dk - 1)/sqrt 3
+ *   of corner q.
+ * The caller owns every buffer; outputs must not alias inputs.  No Dirichlet
+ * masking is applied.  Errors: PF_E_INVALID_ARG for a null pointer, a bad
+ * mesh (nx, ny, nz >= 1, lengths > 0, 3N and 8E at most 2^31 - 2^16), a bad
+ * material or a split other than PF_SPLIT_VD (the only split these kernels
+ * implement); PF_E_HIP if the launch fails.  Nothing is written on error.
+ */
+#ifndef PHASEFIELD3D_H
+#define PHASEFIELD3D_H
+
+#include "phasefield.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf3d_mesh {
+  int32_t nx, ny, nz;      /* elements per direction, >= 1 */
+  double lx, ly, lz;       /* box size [mm], > 0           */
+} pf3d_mesh;
+
+/* Internal force R = sum_e sum_q B^T sigma(eps(u), g(d_q)) w detJ with the
+ * split stress of Section 2 (eq_sigma), g(d) = (1-d)^2 + eta.
+ * u [3N], d [N] -> R [3N]. */
+pf_status pf3d_op_internal_force(const pf3d_mesh *mesh, const pf_material *mat,
+                                 const double *u, const double *d, double *R,
+                                 void *hip_stream);
+
+/* Tangent apply q = K_t(u; d) p of the split stress, its volumetric factor
+ * g K where tr eps(u) > 0 strictly, else K (eq_definition_+).
+ * u, p, q [3N]; d [N]. */
+pf_status pf3d_op_tangent_apply(const pf3d_mesh *mesh, const pf_material *mat,
+                                const double *u, const double *d, const double *p,
+                                double *q, void *hip_stream);
+
+/* Phase operator q = sum [coef_q N N^T + Gc l grad N . grad N^T] w detJ p
+ * with a per-point coefficient coef [8E] (K_dd uses Gc/l + 2H, the trial
+ * block of Section 3.4 a reduced one).  p, q [N]. */
+pf_status pf3d_op_phase_apply(const pf3d_mesh *mesh, const pf_material *mat,
+                              const double *coef, const double *p, double *q,
+                              void *hip_stream);
+
+/* Quadrature-point update (Sections 2, 3.5): from u [3N], d [N] and the
+ * committed history H_prev [8E], write H = max(H_prev, psi+) [8E], the
+ * scheme part psi_S [8E] (scheme 0 ST: 0; 1 S1: psi_vol = K/2 <tr eps>_+^2;
+ * 2 S2: psi_dev = mu eps_dev:eps_dev; 3 S3: psi+) and per element a flag
+ * word flags [E] (uint16): bit q = tr eps > 0 at point q, bit 8+q = the
+ * softening gate at point q (scheme != 0, psi+ > psi_crit, psi+ > H_prev
+ * and d_q < d_gate).  psi_crit < 0 means Gc / (2 l). */
+pf_status pf3d_op_qp_update(const pf3d_mesh *mesh, const pf_material *mat, int32_t scheme,
+                            double psi_crit, double d_gate, const double *u,
+                            const double *d, const double *H_prev, double *H,
+                            double *psi_s, uint16_t *flags, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHASEFIELD3D_H */

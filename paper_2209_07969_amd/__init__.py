@@ -6,7 +6,8 @@ if the library is missing or no HIP device is present.  PyTorch is used for
 the device, its current stream and device tensors passed to the operator
 entry points.
 
-The C ABI is declared in ``include/phasefield.h``.
+The C ABI is declared in ``include/phasefield.h`` (2-D solver and operators)
+and ``include/phasefield3d.h`` (3-D hexahedral operators).
 """
 from __future__ import annotations
 
@@ -33,6 +34,10 @@ EXPORTED = [
     "pf_batch_load_step", "pf_batch_destroy", "pf_autotune", "pf_set_allocator",
     "pf_batch_set_shared_launches",
 ]
+EXPORTED_3D = [
+    "pf3d_op_internal_force", "pf3d_op_tangent_apply", "pf3d_op_phase_apply",
+    "pf3d_op_qp_update",
+]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -42,6 +47,11 @@ RELEASE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
 class MeshDesc(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("lx", c_double), ("ly", c_double),
                 ("elem_active", c_void_p)]
+
+
+class Mesh3Desc(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("lx", c_double),
+                ("ly", c_double), ("lz", c_double)]
 
 
 class MaterialDesc(ctypes.Structure):
@@ -124,7 +134,12 @@ def load_library(path: str = LIB_PATH):
     lib.pf_set_allocator.argtypes = [P, ALLOC_FN, RELEASE_FN, P]
     lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_int64)]
-    for name in EXPORTED:
+    M3, MT = POINTER(Mesh3Desc), POINTER(MaterialDesc)
+    lib.pf3d_op_internal_force.argtypes = [M3, MT, P, P, P, P]
+    lib.pf3d_op_tangent_apply.argtypes = [M3, MT, P, P, P, P, P]
+    lib.pf3d_op_phase_apply.argtypes = [M3, MT, P, P, P, P]
+    lib.pf3d_op_qp_update.argtypes = [M3, MT, c_int32, c_double, c_double, P, P, P, P, P, P, P]
+    for name in EXPORTED + EXPORTED_3D:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
     _lib = lib
@@ -398,6 +413,71 @@ class Context:
                     "pf_op_predictor")
 
 
+class Hex3DOps:
+    """The 3-D operator entry points (include/phasefield3d.h) on the box mesh
+    of ``problem`` (any object with nx, ny, nz, lx, ly, lz and a material
+    with the split PF_SPLIT_VD).  Device tensors in the header's layouts:
+    displacement fields [3N] (x, y, z planes), nodal fields [N],
+    quadrature-point fields [8E] (plane q holds point q of every element),
+    flags [E] (int16 tensors holding the uint16 flag words).  Kernels go to
+    torch's current stream."""
+
+    def __init__(self, problem):
+        require_device()
+        import torch
+        self.lib = load_library()
+        p = problem
+        self.mesh = Mesh3Desc(int(p.nx), int(p.ny), int(p.nz), float(p.lx), float(p.ly),
+                              float(p.lz))
+        m = p.material
+        self.mat = MaterialDesc(m.E, m.nu, m.Gc, m.l, m.eta, int(m.split))
+        self.device = torch.cuda.current_device()
+        self.N = (p.nx + 1) * (p.ny + 1) * (p.nz + 1)
+        self.E = p.nx * p.ny * p.nz
+
+    def _arg(self, t, count, name, dtype=None):
+        import torch
+        return _dev_arg(t, torch.float64 if dtype is None else dtype, count, self.device, name)
+
+    def _stream(self):
+        import torch
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _check(self, st, what):
+        if st != 0:
+            raise PhaseFieldError(st, f"{what}: {self.lib.pf_status_string(st).decode()}")
+
+    def internal_force(self, u, d, R):
+        N = self.N
+        self._check(self.lib.pf3d_op_internal_force(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(u, 3 * N, "u"),
+            self._arg(d, N, "d"), self._arg(R, 3 * N, "R"), self._stream()),
+            "pf3d_op_internal_force")
+
+    def tangent_apply(self, u, d, p, q):
+        N = self.N
+        self._check(self.lib.pf3d_op_tangent_apply(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(u, 3 * N, "u"),
+            self._arg(d, N, "d"), self._arg(p, 3 * N, "p"), self._arg(q, 3 * N, "q"),
+            self._stream()), "pf3d_op_tangent_apply")
+
+    def phase_apply(self, coef, p, q):
+        self._check(self.lib.pf3d_op_phase_apply(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(coef, 8 * self.E, "coef"),
+            self._arg(p, self.N, "p"), self._arg(q, self.N, "q"), self._stream()),
+            "pf3d_op_phase_apply")
+
+    def qp_update(self, scheme, psi_crit, d_gate, u, d, H_prev, H, psi_s, flags):
+        import torch
+        N, E8 = self.N, 8 * self.E
+        self._check(self.lib.pf3d_op_qp_update(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), int(scheme), float(psi_crit),
+            float(d_gate), self._arg(u, 3 * N, "u"), self._arg(d, N, "d"),
+            self._arg(H_prev, E8, "H_prev"), self._arg(H, E8, "H"), self._arg(psi_s, E8, "psi_s"),
+            self._arg(flags, self.E, "flags", torch.int16), self._stream()),
+            "pf3d_op_qp_update")
+
+
 class Batch:
     """Several contexts advanced together (each should own a HIP stream, e.g.
     Context(..., stream=torch.cuda.Stream().cuda_stream)).  shared=True runs
@@ -442,5 +522,5 @@ class Batch:
             pass
 
 
-__all__ = ["Batch", "Context", "load_library", "require_device", "default_opts", "PhaseFieldError",
+__all__ = ["Batch", "Context", "Hex3DOps", "load_library", "require_device", "default_opts", "PhaseFieldError",
            "ST", "S1", "S2", "S3", "FP64", "MIXED", "EXPORTED"]

@@ -35,7 +35,8 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
     objs = []
-    for src, lang in (("pf_kernels.hip", "hip"), ("pf_solver.cpp", "hip")):
+    for src, lang in (("pf_kernels.hip", "hip"), ("pf_solver.cpp", "hip"),
+                      ("pf3d_kernels.hip", "hip")):
         obj = os.path.join(BUILD, src + ".o")
         _run([cc, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -1,0 +1,334 @@
+// Trilinear hexahedra (Q1, 2x2x2 Gauss) on a structured box: the per-node
+// and per-element arithmetic of the 3-D operators.  The device kernels in
+// pf3d_kernels.hip call these functions once per grid index; the functions
+// are __host__ __device__ so that a host build can replay a kernel's grid
+// index by index.
+//
+// Model (Section 2): volumetric-deviatoric split with the full 3-D strain,
+// sigma = g(d) [K <tr eps>_+ I + 2 mu eps_dev] + K <tr eps>_- I, AT2 phase
+// operator coef N N^T + Gc l grad N . grad N^T, history H = max(H_n, Psi+).
+//
+// Layout in device memory (structure of arrays):
+//   node (i, j, k) has id n = i + j (nx+1) + k (nx+1)(ny+1);
+//   element (ie, je, ke) has id e = ie + je nx + ke nx ny;
+//   displacement-like fields [3N]: the x plane, then y, then z;
+//   nodal scalars [N]; quadrature-point fields [8E]: plane q holds point q
+//   of every element (index e + q E); flags [E] (uint16).
+// Corner a of an element sits at offsets (di, dj, dk) = (((a+1)>>1)&1,
+// (a>>1)&1, a>>2), i.e. the bottom face counter-clockwise, then the top
+// face; Gauss point q sits at the reference coordinates (2 di - 1,
+// 2 dj - 1, 2 dk - 1) / sqrt(3) of corner q.
+#pragma once
+
+#include "../../include/phasefield3d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace pf3d {
+
+struct Grid3 {
+  int nx, ny, nz;
+  int N, E;             // nodes, elements
+  double hx, hy, hz;    // element edge lengths
+};
+
+struct Mat3 {
+  double lam, mu, K;    // Lame constants, bulk modulus K = lam + 2 mu / 3
+  double Gcl;           // Gc l, the phase operator's gradient factor
+  double eta;           // residual stiffness of g(d) = (1 - d)^2 + eta
+};
+
+struct Qp3 {
+  int scheme;           // 0 ST, 1 S1 (psi_vol), 2 S2 (psi_dev), 3 S3 (psi+)
+  double psi_crit;      // softening threshold of the gate
+  double d_gate;        // gate only where d_q < d_gate
+};
+
+constexpr int kTpb3 = 256;
+
+__host__ __device__ inline int corner_di(int a) { return ((a + 1) >> 1) & 1; }
+__host__ __device__ inline int corner_dj(int a) { return (a >> 1) & 1; }
+__host__ __device__ inline int corner_dk(int a) { return a >> 2; }
+
+// One-dimensional factor (1 + s_a s_q / sqrt 3) / 2 of the shape function
+// N_a at Gauss point q along one axis (s = +-1).
+__host__ __device__ inline double axis_factor(int oa, int oq) {
+  const double c = 0.28867513459481287;   // 1 / (2 sqrt 3)
+  return (oa == oq) ? 0.5 + c : 0.5 - c;
+}
+
+// N_a and grad N_a at Gauss point q of a box element with edges hx, hy, hz.
+struct ShapeAt {
+  double N, gx, gy, gz;
+};
+
+__host__ __device__ inline ShapeAt shape_at(const Grid3 &g, int a, int q) {
+  const double fx = axis_factor(corner_di(a), corner_di(q));
+  const double fy = axis_factor(corner_dj(a), corner_dj(q));
+  const double fz = axis_factor(corner_dk(a), corner_dk(q));
+  const double sx = corner_di(a) ? 1.0 : -1.0, sy = corner_dj(a) ? 1.0 : -1.0,
+               sz = corner_dk(a) ? 1.0 : -1.0;
+  return ShapeAt{fx * fy * fz, sx / g.hx * fy * fz, sy / g.hy * fx * fz, sz / g.hz * fx * fy};
+}
+
+__host__ __device__ inline int node_id(const Grid3 &g, int i, int j, int k) {
+  return i + j * (g.nx + 1) + k * (g.nx + 1) * (g.ny + 1);
+}
+
+// Node of corner b of the element whose first corner is node (ie, je, ke).
+__host__ __device__ inline int corner_node(const Grid3 &g, int ie, int je, int ke, int b) {
+  return node_id(g, ie + corner_di(b), je + corner_dj(b), ke + corner_dk(b));
+}
+
+__host__ __device__ inline double degrade(double d, double eta) {
+  return (1.0 - d) * (1.0 - d) + eta;
+}
+
+// Strain (engineering Voigt [xx, yy, zz, 2yz, 2xz, 2xy]) at Gauss point q
+// from the element's corner displacements u[b], u[8+b], u[16+b].
+__host__ __device__ inline void strain_at(const Grid3 &g, int q, const double *ue,
+                                          double eps[6]) {
+  for (int c = 0; c < 6; ++c) eps[c] = 0.0;
+  for (int b = 0; b < 8; ++b) {
+    const ShapeAt s = shape_at(g, b, q);
+    const double ux = ue[b], uy = ue[8 + b], uz = ue[16 + b];
+    eps[0] += s.gx * ux;
+    eps[1] += s.gy * uy;
+    eps[2] += s.gz * uz;
+    eps[3] += s.gz * uy + s.gy * uz;
+    eps[4] += s.gz * ux + s.gx * uz;
+    eps[5] += s.gy * ux + s.gx * uy;
+  }
+}
+
+// Split stress (Voigt [xx, yy, zz, yz, xz, xy]) at degradation gd; the
+// volumetric part is degraded only under expansion (tr eps > 0 strictly).
+__host__ __device__ inline void vd_stress(const Mat3 &m, const double eps[6], double gd,
+                                          double sig[6]) {
+  const double t = eps[0] + eps[1] + eps[2], m3 = t / 3.0;
+  const double vol = t > 0.0 ? gd * m.K * t : m.K * t;
+  for (int c = 0; c < 3; ++c) sig[c] = gd * 2.0 * m.mu * (eps[c] - m3) + vol;
+  for (int c = 3; c < 6; ++c) sig[c] = gd * m.mu * eps[c];
+}
+
+// Tangent of the split stress at the strain eps, applied to a strain
+// increment de: the volumetric factor is g K where tr eps > 0, else K.
+__host__ __device__ inline void vd_tangent_apply(const Mat3 &m, const double eps[6], double gd,
+                                                 const double de[6], double ds[6]) {
+  const double t = eps[0] + eps[1] + eps[2];
+  const double kf = t > 0.0 ? gd * m.K : m.K;
+  const double dt = de[0] + de[1] + de[2];
+  for (int c = 0; c < 3; ++c) ds[c] = gd * 2.0 * m.mu * (de[c] - dt / 3.0) + kf * dt;
+  for (int c = 3; c < 6; ++c) ds[c] = gd * m.mu * de[c];
+}
+
+// Energy parts: psi_vol = K/2 <t>_+^2, psi_dev = mu eps_dev : eps_dev.
+__host__ __device__ inline void vd_parts(const Mat3 &m, const double eps[6], double *t_out,
+                                         double *pvol, double *pdev) {
+  const double t = eps[0] + eps[1] + eps[2], m3 = t / 3.0;
+  double dd = 0.0;
+  for (int c = 0; c < 3; ++c) dd += (eps[c] - m3) * (eps[c] - m3);
+  for (int c = 3; c < 6; ++c) dd += 0.5 * eps[c] * eps[c];
+  const double tp = t > 0.0 ? t : 0.0;
+  *t_out = t;
+  *pvol = 0.5 * m.K * tp * tp;
+  *pdev = m.mu * dd;
+}
+
+// Load the 8 corner values of nodal planes (ncomp planes of N values) of
+// element (ie, je, ke) into out[c * 8 + b].
+__host__ __device__ inline void gather_corners(const Grid3 &g, int ie, int je, int ke,
+                                               const double *f, int ncomp, double *out) {
+  for (int b = 0; b < 8; ++b) {
+    const int nb = corner_node(g, ie, je, ke, b);
+    for (int c = 0; c < ncomp; ++c) out[c * 8 + b] = f[nb + c * g.N];
+  }
+}
+
+__host__ __device__ inline double interp_at(const Grid3 &g, int q, const double *fe) {
+  double s = 0.0;
+  for (int b = 0; b < 8; ++b) s += shape_at(g, b, q).N * fe[b];
+  return s;
+}
+
+// The elements that hold node n, each with the corner a that n is in it:
+// calls visit(ie, je, ke, a) for every such element inside the box.
+template <class F>
+__host__ __device__ inline void for_node_elements(const Grid3 &g, int n, F &&visit) {
+  const int P = (g.nx + 1) * (g.ny + 1);
+  const int k = n / P, r = n - k * P, j = r / (g.nx + 1), i = r - j * (g.nx + 1);
+  for (int a = 0; a < 8; ++a) {
+    const int ie = i - corner_di(a), je = j - corner_dj(a), ke = k - corner_dk(a);
+    if (ie < 0 || je < 0 || ke < 0 || ie >= g.nx || je >= g.ny || ke >= g.nz) continue;
+    visit(ie, je, ke, a);
+  }
+}
+
+// Internal force at node n: R_n = sum over its elements and their Gauss
+// points of B_a^T sigma(eps(u), g(d_q)) w, written to R[n], R[N+n], R[2N+n].
+__host__ __device__ inline void node_internal_force(const Grid3 &g, const Mat3 &m, int n,
+                                                    const double *u, const double *d,
+                                                    double *R) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    double ue[24], de[8];
+    gather_corners(g, ie, je, ke, u, 3, ue);
+    gather_corners(g, ie, je, ke, d, 1, de);
+    for (int q = 0; q < 8; ++q) {
+      double eps[6], sig[6];
+      strain_at(g, q, ue, eps);
+      vd_stress(m, eps, degrade(interp_at(g, q, de), m.eta), sig);
+      const ShapeAt s = shape_at(g, a, q);
+      fx += w * (s.gx * sig[0] + s.gz * sig[4] + s.gy * sig[5]);
+      fy += w * (s.gy * sig[1] + s.gz * sig[3] + s.gx * sig[5]);
+      fz += w * (s.gz * sig[2] + s.gy * sig[3] + s.gx * sig[4]);
+    }
+  });
+  R[n] = fx;
+  R[g.N + n] = fy;
+  R[2 * g.N + n] = fz;
+}
+
+// Tangent apply at node n: (K_t(u; d) p)_n with the tangent taken at u.
+__host__ __device__ inline void node_tangent_apply(const Grid3 &g, const Mat3 &m, int n,
+                                                   const double *u, const double *d,
+                                                   const double *p, double *out) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    double ue[24], pe[24], de[8];
+    gather_corners(g, ie, je, ke, u, 3, ue);
+    gather_corners(g, ie, je, ke, p, 3, pe);
+    gather_corners(g, ie, je, ke, d, 1, de);
+    for (int q = 0; q < 8; ++q) {
+      double eps[6], dep[6], ds[6];
+      strain_at(g, q, ue, eps);
+      strain_at(g, q, pe, dep);
+      vd_tangent_apply(m, eps, degrade(interp_at(g, q, de), m.eta), dep, ds);
+      const ShapeAt s = shape_at(g, a, q);
+      fx += w * (s.gx * ds[0] + s.gz * ds[4] + s.gy * ds[5]);
+      fy += w * (s.gy * ds[1] + s.gz * ds[3] + s.gx * ds[5]);
+      fz += w * (s.gz * ds[2] + s.gy * ds[3] + s.gx * ds[4]);
+    }
+  });
+  out[n] = fx;
+  out[g.N + n] = fy;
+  out[2 * g.N + n] = fz;
+}
+
+// Phase operator at node n: sum w [coef_q N_a (N . p) + Gc l grad N_a .
+// grad(N . p)] with the per-point coefficient coef[e + q E].
+__host__ __device__ inline void node_phase_apply(const Grid3 &g, const Mat3 &m, int n,
+                                                 const double *coef, const double *p,
+                                                 double *out) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double acc = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    const int e = ie + je * g.nx + ke * g.nx * g.ny;
+    double pe[8];
+    gather_corners(g, ie, je, ke, p, 1, pe);
+    for (int q = 0; q < 8; ++q) {
+      double pq = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+      for (int b = 0; b < 8; ++b) {
+        const ShapeAt s = shape_at(g, b, q);
+        pq += s.N * pe[b];
+        px += s.gx * pe[b];
+        py += s.gy * pe[b];
+        pz += s.gz * pe[b];
+      }
+      const ShapeAt s = shape_at(g, a, q);
+      acc += w * (coef[e + q * g.E] * s.N * pq + m.Gcl * (s.gx * px + s.gy * py + s.gz * pz));
+    }
+  });
+  out[n] = acc;
+}
+
+// Quadrature-point update of element e (Sections 2, 3.5): H = max(H_prev,
+// psi+), the scheme part psi_S, and flags bit q = tr eps > 0 at point q,
+// bit 8 + q = the softening gate at point q (a fixed-stress scheme, psi+
+// above psi_crit and above H_prev, d_q below d_gate).  Returns the number
+// of gated points.
+__host__ __device__ inline int elem_qp_update(const Grid3 &g, const Mat3 &m, const Qp3 &qp,
+                                              int e, const double *u, const double *d,
+                                              const double *Hprev, double *H, double *psi_s,
+                                              uint16_t *flags) {
+  const int ke = e / (g.nx * g.ny), r = e - ke * g.nx * g.ny, je = r / g.nx,
+            ie = r - je * g.nx;
+  double ue[24], de[8];
+  gather_corners(g, ie, je, ke, u, 3, ue);
+  gather_corners(g, ie, je, ke, d, 1, de);
+  unsigned fl = 0;
+  int ng = 0;
+  for (int q = 0; q < 8; ++q) {
+    double eps[6], t, pv, pd;
+    strain_at(g, q, ue, eps);
+    vd_parts(m, eps, &t, &pv, &pd);
+    const double pplus = pv + pd, hp = Hprev[e + q * g.E];
+    H[e + q * g.E] = pplus > hp ? pplus : hp;
+    double ps = 0.0;
+    if (qp.scheme == 1) ps = pv;
+    else if (qp.scheme == 2) ps = pd;
+    else if (qp.scheme == 3) ps = pplus;
+    psi_s[e + q * g.E] = ps;
+    if (t > 0.0) fl |= 1u << q;
+    const double dq = interp_at(g, q, de);
+    if (qp.scheme != 0 && pplus > qp.psi_crit && pplus > hp && dq < qp.d_gate) {
+      fl |= 1u << (q + 8);
+      ++ng;
+    }
+  }
+  flags[e] = uint16_t(fl);
+  return ng;
+}
+
+// Grid of a one-index-per-thread launch over count indices.
+__host__ __device__ inline int grid_index(int block, int thread) {
+  return block * kTpb3 + thread;
+}
+
+inline int grid_blocks(int count) { return (count + kTpb3 - 1) / kTpb3; }
+
+// ---- host side: mesh and material checks of the C ABI
+
+// largest 3N and 8E: 32-bit indices with room for rounding up to whole blocks
+constexpr long long kMaxIndexCount = (1LL << 31) - (1LL << 16);
+
+inline pf_status make_grid(const pf3d_mesh *mesh, Grid3 *g) {
+  if (!mesh || mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1 || !(mesh->lx > 0) ||
+      !(mesh->ly > 0) || !(mesh->lz > 0) || !std::isfinite(mesh->lx) ||
+      !std::isfinite(mesh->ly) || !std::isfinite(mesh->lz))
+    return PF_E_INVALID_ARG;
+  const long long N = ((long long)mesh->nx + 1) * ((long long)mesh->ny + 1) *
+                      ((long long)mesh->nz + 1);
+  const long long E = (long long)mesh->nx * mesh->ny * mesh->nz;
+  if (3 * N > kMaxIndexCount || 8 * E > kMaxIndexCount) return PF_E_INVALID_ARG;
+  *g = Grid3{mesh->nx, mesh->ny, mesh->nz, (int)N, (int)E, mesh->lx / mesh->nx,
+             mesh->ly / mesh->ny, mesh->lz / mesh->nz};
+  return PF_OK;
+}
+
+inline pf_status make_mat(const pf_material *mat, Mat3 *m) {
+  if (!mat || !(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0) ||
+      !(mat->l > 0) || !(mat->eta >= 0) || !std::isfinite(mat->E) || !std::isfinite(mat->Gc) ||
+      !std::isfinite(mat->l) || !std::isfinite(mat->eta) || mat->split != PF_SPLIT_VD)
+    return PF_E_INVALID_ARG;
+  const double mu = mat->E / (2.0 * (1.0 + mat->nu));
+  const double lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+  *m = Mat3{lam, mu, lam + 2.0 * mu / 3.0, mat->Gc * mat->l, mat->eta};
+  return PF_OK;
+}
+
+// Gate parameters; psi_crit < 0 means Gc / (c_w l) with c_w = 2 (AT2).
+inline pf_status make_qp(int scheme, double psi_crit, double d_gate, const pf_material *mat,
+                         Qp3 *qp) {
+  if (!mat || scheme < 0 || scheme > 3 || std::isnan(psi_crit) || std::isnan(d_gate))
+    return PF_E_INVALID_ARG;
+  *qp = Qp3{scheme, psi_crit >= 0 ? psi_crit : mat->Gc / (2.0 * mat->l), d_gate};
+  return PF_OK;
+}
+
+}  // namespace pf3d

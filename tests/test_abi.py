@@ -31,6 +31,17 @@ def test_library_exports_every_declared_symbol():
     assert set(pf.EXPORTED) == set(declared_functions())
 
 
+def test_library_exports_every_3d_symbol():
+    import paper_2209_07969_amd as pf
+    src = open(os.path.join(ROOT, "include", "phasefield3d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(pf3d_[a-z_0-9]+)\s*\(", src)))
+    assert names and set(pf.EXPORTED_3D) == set(names)
+    lib = pf.load_library()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
 def test_default_opts_and_status_strings():
     import paper_2209_07969_amd as pf
     o = pf.default_opts()

@@ -1,0 +1,112 @@
+"""3-D operator kernels on the GPU against the oracle's hexahedra, through
+the C ABI (include/phasefield3d.h): internal force, tangent apply, phase
+apply and the quadrature-point update, on meshes of one block, several
+blocks with a ragged tail, and one element.  The same per-index functions
+are checked on the host, grid by grid, by tests/test_hex3d_kernels_host.py.
+
+Opt-in (PF_GPU3D=1): these kernels have not yet been run on a GPU, so they
+are not part of the default GPU run until they have passed once there.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hex3d as H3
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("PF_GPU3D") != "1",
+                                 reason="3-D kernels not yet run on a GPU; set PF_GPU3D=1")]
+
+MESHES = [(3, 2, 2), (9, 7, 5), (17, 5, 3), (1, 1, 1)]
+
+
+class Box:
+    def __init__(self, nx, ny, nz):
+        import workloads as W
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.lx, self.ly, self.lz = 1.3, 0.7, 0.45
+        self.material = W.Material(E=2.1e5, nu=0.3, Gc=2.7, l=0.05, eta=1e-6, split=0)
+
+
+def soa(v):
+    return np.concatenate([v[0::3], v[1::3], v[2::3]])
+
+
+def dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def setup(gpu_lib, shape, seed):
+    b = Box(*shape)
+    ops = gpu_lib.Hex3DOps(b)
+    om = H3.Mesh3D(b.nx, b.ny, b.nz, b.lx, b.ly, b.lz)
+    return b, ops, om, np.random.default_rng(seed)
+
+
+@pytest.mark.parametrize("shape", MESHES)
+def test_internal_force_and_tangent_3d(gpu_lib, shape):
+    import torch
+    b, ops, om, rng = setup(gpu_lib, shape, sum(shape))
+    m = b.material
+    cons = H3.VD3D(m.E, m.nu)
+    N = om.n_nodes
+    u = rng.normal(size=3 * N) * 1e-3
+    d = rng.uniform(0, 1, size=N)
+    p = rng.normal(size=3 * N)
+    R_orc = soa(H3.internal_force(om, cons, u, d, m.eta))
+    q_orc = soa(H3.tangent_matrix(om, cons, u, d, m.eta) @ p)
+    R = torch.full((3 * N,), float("nan"), dtype=torch.float64, device="cuda")
+    q = torch.full_like(R, float("nan"))
+    ops.internal_force(dev(soa(u)), dev(d), R)
+    ops.tangent_apply(dev(soa(u)), dev(d), dev(soa(p)), q)
+    np.testing.assert_allclose(host(R), R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
+    np.testing.assert_allclose(host(q), q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
+
+
+@pytest.mark.parametrize("shape", MESHES)
+def test_phase_apply_3d(gpu_lib, shape):
+    import torch
+    b, ops, om, rng = setup(gpu_lib, shape, 7 + sum(shape))
+    N, E = om.n_nodes, om.conn.shape[0]
+    coef = rng.uniform(0.1, 50.0, size=(E, 8))
+    p = rng.normal(size=N)
+    q_orc = H3.phase_matrix(om, coef, b.material.Gc, b.material.l) @ p
+    q = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
+    ops.phase_apply(dev(coef.T.reshape(-1)), dev(p), q)
+    np.testing.assert_allclose(host(q), q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_qp_update_3d(gpu_lib, scheme):
+    import torch
+    b, ops, om, rng = setup(gpu_lib, (9, 7, 5), 100 + scheme)
+    m = b.material
+    cons = H3.VD3D(m.E, m.nu)
+    N, E = om.n_nodes, om.conn.shape[0]
+    u = rng.normal(size=3 * N) * 2e-3
+    d = rng.uniform(0, 1, size=N)
+    parts = cons.parts(om.strain(u))
+    psi = parts["psi_plus"]
+    Hprev = np.where(rng.uniform(size=psi.shape) < 0.5, psi * 0.5, psi * 1.5)
+    gate = ((psi > m.Gc / (2 * m.l)) & (psi > Hprev) & (om.interp(d) < 0.95) & (scheme != 0))
+    ps = {0: np.zeros_like(psi), 1: parts["psi_vol"], 2: parts["psi_dev"], 3: psi}[scheme]
+    H = torch.full((8 * E,), float("nan"), dtype=torch.float64, device="cuda")
+    PS = torch.full_like(H, float("nan"))
+    fl = torch.zeros(E, dtype=torch.int16, device="cuda")
+    ops.qp_update(scheme, -1.0, 0.95, dev(soa(u)), dev(d), dev(Hprev.T.reshape(-1)), H, PS, fl)
+    np.testing.assert_allclose(host(H).reshape(8, E).T, np.maximum(Hprev, psi), rtol=1e-12, atol=0)
+    np.testing.assert_allclose(host(PS).reshape(8, E).T, ps, rtol=1e-12,
+                               atol=1e-14 * max(ps.max(), 1))
+    flags = host(fl).view(np.uint16)
+    bits_t = np.stack([(flags >> q) & 1 for q in range(8)], axis=1).astype(bool)
+    bits_g = np.stack([(flags >> (q + 8)) & 1 for q in range(8)], axis=1).astype(bool)
+    np.testing.assert_array_equal(bits_t, parts["t"] > 0)
+    np.testing.assert_array_equal(bits_g, gate)
