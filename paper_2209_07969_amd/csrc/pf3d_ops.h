@@ -302,10 +302,13 @@ inline pf_status make_grid(const pf3d_mesh *mesh, Grid3 *g) {
       !(mesh->ly > 0) || !(mesh->lz > 0) || !std::isfinite(mesh->lx) ||
       !std::isfinite(mesh->ly) || !std::isfinite(mesh->lz))
     return PF_E_INVALID_ARG;
-  const long long N = ((long long)mesh->nx + 1) * ((long long)mesh->ny + 1) *
-                      ((long long)mesh->nz + 1);
-  const long long E = (long long)mesh->nx * mesh->ny * mesh->nz;
-  if (3 * N > kMaxIndexCount || 8 * E > kMaxIndexCount) return PF_E_INVALID_ARG;
+  // bound the partial product before the third factor so that nothing
+  // overflows 64 bits (each side is below 2^31)
+  const long long nxy = ((long long)mesh->nx + 1) * ((long long)mesh->ny + 1);
+  if (nxy > kMaxIndexCount / 3) return PF_E_INVALID_ARG;
+  const long long N = nxy * ((long long)mesh->nz + 1);
+  const long long E = (long long)mesh->nx * mesh->ny * mesh->nz;   // E < N
+  if (N > kMaxIndexCount / 3 || E > kMaxIndexCount / 8) return PF_E_INVALID_ARG;
   *g = Grid3{mesh->nx, mesh->ny, mesh->nz, (int)N, (int)E, mesh->lx / mesh->nx,
              mesh->ly / mesh->ny, mesh->lz / mesh->nz};
   return PF_OK;

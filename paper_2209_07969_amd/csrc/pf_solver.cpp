@@ -1566,9 +1566,10 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   if (mesh->nx < 1 || mesh->ny < 1 || !(mesh->lx > 0) || !(mesh->ly > 0)) return PF_E_INVALID_ARG;
   // the kernels index displacement DOFs (2N) and quadrature points (4E) with
   // 32-bit ints, and round those counts up to whole blocks
+  // (each side is below 2^31, so N < 2^62 fits; compare without multiplying)
   const long long N = ((long long)mesh->nx + 1) * ((long long)mesh->ny + 1);
   const long long E = (long long)mesh->nx * mesh->ny;
-  if (2 * N > kMaxIndexCount || 4 * E > kMaxIndexCount) return PF_E_INVALID_ARG;
+  if (N > kMaxIndexCount / 2 || E > kMaxIndexCount / 4) return PF_E_INVALID_ARG;
   if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0) || !(mat->l > 0) ||
       !(mat->eta >= 0) || (mat->split != PF_SPLIT_VD && mat->split != PF_SPLIT_SPECTRAL))
     return PF_E_INVALID_ARG;

@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "../include/phasefield.h"
+#include "../include/phasefield3d.h"
 
 static int failures = 0;
 #define CHECK(cond)                                                        \
@@ -54,6 +55,28 @@ int main() {
   pf_ctx *ctx = nullptr;
   CHECK(pf_create(&bad, &mat, &o, nullptr, &ctx) == PF_E_INVALID_ARG && ctx == nullptr);
   CHECK(pf_create(nullptr, &mat, &o, nullptr, &ctx) == PF_E_INVALID_ARG);
+  // meshes whose 2N or 4E overflow 32-bit kernel indices, and the largest nx
+  const int32_t big[][2] = {{23200, 23200}, {1, 1 << 29}, {2147483647, 1}, {2147483647, 2147483647}};
+  for (const auto &s : big) {
+    pf_mesh_desc m{s[0], s[1], 1.0, 1.0, nullptr};
+    CHECK(pf_create(&m, &mat, &o, nullptr, &ctx) == PF_E_INVALID_ARG && ctx == nullptr);
+  }
+
+  // 3-D operators: refused before any launch
+  double x[24] = {0};
+  uint16_t fl[1] = {0};
+  const pf3d_mesh m3{1, 1, 1, 1.0, 1.0, 1.0};
+  const pf3d_mesh m3bad[] = {{0, 1, 1, 1.0, 1.0, 1.0}, {1, 1, 1, 1.0, 0.0, 1.0},
+                             {1024, 1024, 1024, 1.0, 1.0, 1.0},
+                             {2147483647, 2147483647, 2147483647, 1.0, 1.0, 1.0}};
+  for (const auto &mb : m3bad)
+    CHECK(pf3d_op_internal_force(&mb, &mat, x, x, x, nullptr) == PF_E_INVALID_ARG);
+  pf_material spectral = mat;
+  spectral.split = PF_SPLIT_SPECTRAL;
+  CHECK(pf3d_op_tangent_apply(&m3, &spectral, x, x, x, x, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf3d_op_phase_apply(&m3, &mat, nullptr, x, x, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf3d_op_qp_update(&m3, &mat, 9, -1.0, 0.95, x, x, x, x, x, fl, nullptr) ==
+        PF_E_INVALID_ARG);
 
   CHECK(pf_load_step(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf_staggered_iterate(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);

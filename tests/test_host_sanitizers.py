@@ -1,7 +1,8 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
 (not GPU): a build whose host objects carry both sanitizers (device code is
 built as usual) runs tests/host_checks.cpp, the C ABI's device-free paths
-(option validation, status strings, null-handle argument checks).  The
+(option validation, status strings, null-handle argument checks, mesh size
+limits, the 3-D operators' argument checks).  The
 instrumented build takes a few minutes, so the test runs only with
 PF_SANITIZE=1 in the environment."""
 import os
@@ -28,7 +29,7 @@ def test_c_abi_host_paths_under_asan_ubsan():
              "-I" + os.path.join(ROOT, "include")] + san
     with tempfile.TemporaryDirectory() as d:
         objs = []
-        for src in ("pf_solver.cpp", "pf_kernels.hip"):
+        for src in ("pf_solver.cpp", "pf_kernels.hip", "pf3d_kernels.hip"):
             obj = os.path.join(d, src + ".o")
             subprocess.run([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj], check=True)
             objs.append(obj)
