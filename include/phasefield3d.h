@@ -2,8 +2,8 @@
  * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric split of
  * Section 2 with the full 3-D strain and the AT2 phase operator.  They are
  * the operators of the 2-D path (internal force, tangent apply, phase
- * apply, quadrature-point update) on a mesh of hexahedra, as in the paper's
- * one-element-thick slab (Section 4) or a full 3-D panel.
+ * apply, quadrature-point update, predictor) on a mesh of hexahedra, as in
+ * the paper's one-element-thick slab (Section 4) or a full 3-D panel.
  *
  * Every entry point is stateless: it takes the mesh and material by value
  * (read on the host), device pointers for the fields, and a hipStream_t
@@ -70,6 +70,14 @@ pf_status pf3d_op_qp_update(const pf3d_mesh *mesh, const pf_material *mat, int32
                             double psi_crit, double d_gate, const double *u,
                             const double *d, const double *H_prev, double *H,
                             double *psi_s, uint16_t *flags, void *hip_stream);
+
+/* Fixed-stress predictor (Section 3.3 half-step update, Section 3.5 gate and
+ * positive-increment rule): Hhat = max(H, H + ((1 + a Dd)^2 - 1) psi_S) at
+ * gated points with Dd_q > 0, else H; a = 2(1-d_q)/g(d_q).  d, dd [N];
+ * H, psi_s, Hhat [8E]; flags [E] as written by pf3d_op_qp_update. */
+pf_status pf3d_op_predictor(const pf3d_mesh *mesh, const pf_material *mat, const double *d,
+                            const double *dd, const double *H, const double *psi_s,
+                            const uint16_t *flags, double *Hhat, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,7 @@ EXPORTED = [
 ]
 EXPORTED_3D = [
     "pf3d_op_internal_force", "pf3d_op_tangent_apply", "pf3d_op_phase_apply",
-    "pf3d_op_qp_update",
+    "pf3d_op_qp_update", "pf3d_op_predictor",
 ]
 
 
@@ -139,6 +139,7 @@ def load_library(path: str = LIB_PATH):
     lib.pf3d_op_tangent_apply.argtypes = [M3, MT, P, P, P, P, P]
     lib.pf3d_op_phase_apply.argtypes = [M3, MT, P, P, P, P]
     lib.pf3d_op_qp_update.argtypes = [M3, MT, c_int32, c_double, c_double, P, P, P, P, P, P, P]
+    lib.pf3d_op_predictor.argtypes = [M3, MT, P, P, P, P, P, P, P]
     for name in EXPORTED + EXPORTED_3D:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
@@ -476,6 +477,15 @@ class Hex3DOps:
             self._arg(H_prev, E8, "H_prev"), self._arg(H, E8, "H"), self._arg(psi_s, E8, "psi_s"),
             self._arg(flags, self.E, "flags", torch.int16), self._stream()),
             "pf3d_op_qp_update")
+
+    def predictor(self, d, dd, H, psi_s, flags, Hhat):
+        import torch
+        N, E8 = self.N, 8 * self.E
+        self._check(self.lib.pf3d_op_predictor(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(d, N, "d"),
+            self._arg(dd, N, "dd"), self._arg(H, E8, "H"), self._arg(psi_s, E8, "psi_s"),
+            self._arg(flags, self.E, "flags", torch.int16), self._arg(Hhat, E8, "Hhat"),
+            self._stream()), "pf3d_op_predictor")
 
 
 class Batch:

@@ -43,6 +43,14 @@ __global__ void __launch_bounds__(kTpb3) k3_qp_update(Grid3 g, Mat3 m, Qp3 qp, c
   if (e < g.E) (void)elem_qp_update(g, m, qp, e, u, d, Hprev, H, psi_s, flags);
 }
 
+__global__ void __launch_bounds__(kTpb3) k3_predictor(Grid3 g, Mat3 m, const double *d,
+                                                      const double *dd, const double *H,
+                                                      const double *psi_s,
+                                                      const uint16_t *flags, double *Hhat) {
+  const int e = grid_index(blockIdx.x, threadIdx.x);
+  if (e < g.E) elem_predictor(g, m, e, d, dd, H, psi_s, flags, Hhat);
+}
+
 pf_status launched() {
   return hipGetLastError() == hipSuccess ? PF_OK : PF_E_HIP;
 }
@@ -100,6 +108,19 @@ pf_status pf3d_op_qp_update(const pf3d_mesh *mesh, const pf_material *mat, int32
   hipLaunchKernelGGL(k3_qp_update, dim3(grid_blocks(g.E)), dim3(kTpb3), 0,
                      static_cast<hipStream_t>(hip_stream), g, m, qp, u, d, H_prev, H, psi_s,
                      flags);
+  return launched();
+}
+
+pf_status pf3d_op_predictor(const pf3d_mesh *mesh, const pf_material *mat, const double *d,
+                            const double *dd, const double *H, const double *psi_s,
+                            const uint16_t *flags, double *Hhat, void *hip_stream) {
+  Grid3 g;
+  Mat3 m;
+  if (!d || !dd || !H || !psi_s || !flags || !Hhat || make_grid(mesh, &g) != PF_OK ||
+      make_mat(mat, &m) != PF_OK)
+    return PF_E_INVALID_ARG;
+  hipLaunchKernelGGL(k3_predictor, dim3(grid_blocks(g.E)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, m, d, dd, H, psi_s, flags, Hhat);
   return launched();
 }
 

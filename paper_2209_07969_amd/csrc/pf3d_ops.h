@@ -285,6 +285,40 @@ __host__ __device__ inline int elem_qp_update(const Grid3 &g, const Mat3 &m, con
   return ng;
 }
 
+// Fixed-stress predictor of element e (Sections 3.3, 3.5): at gated points
+// (flag bit 8 + q) with Dd_q > 0, Hhat = max(H, H + ((1 + a Dd_q)^2 - 1)
+// psi_S) with a = 2 (1 - d_q) / g(d_q), the factor that eq:epn1 and
+// e_dev_1/2 put on the scheme's strain invariant; elsewhere Hhat = H.  At a
+// gated point H = psi+, so this is the half-step active energy.
+__host__ __device__ inline void elem_predictor(const Grid3 &g, const Mat3 &m, int e,
+                                               const double *d, const double *dd,
+                                               const double *H, const double *psi_s,
+                                               const uint16_t *flags, double *Hhat) {
+  const unsigned fl = flags[e];
+  if ((fl >> 8) == 0) {
+    for (int q = 0; q < 8; ++q) Hhat[e + q * g.E] = H[e + q * g.E];
+    return;
+  }
+  const int ke = e / (g.nx * g.ny), r = e - ke * g.nx * g.ny, je = r / g.nx,
+            ie = r - je * g.nx;
+  double de[8], dde[8];
+  gather_corners(g, ie, je, ke, d, 1, de);
+  gather_corners(g, ie, je, ke, dd, 1, dde);
+  for (int q = 0; q < 8; ++q) {
+    const double h = H[e + q * g.E];
+    double out = h;
+    const double ddq = interp_at(g, q, dde);
+    if (((fl >> (q + 8)) & 1u) && ddq > 0.0) {
+      const double om = 1.0 - interp_at(g, q, de);
+      const double a = 2.0 * om / (om * om + m.eta);
+      const double sc = 1.0 + a * ddq;
+      const double ph = h + (sc * sc - 1.0) * psi_s[e + q * g.E];
+      out = ph > h ? ph : h;
+    }
+    Hhat[e + q * g.E] = out;
+  }
+}
+
 // Grid of a one-index-per-thread launch over count indices.
 __host__ __device__ inline int grid_index(int block, int thread) {
   return block * kTpb3 + thread;

@@ -64,4 +64,14 @@ int h3_qp_update(const pf3d_mesh *mesh, const pf_material *mat, int scheme, doub
   return PF_OK;
 }
 
+int h3_predictor(const pf3d_mesh *mesh, const pf_material *mat, const double *d,
+                 const double *dd, const double *H, const double *psi_s, const uint16_t *flags,
+                 double *Hhat) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  replay(g.E, [&](int e) { elem_predictor(g, m, e, d, dd, H, psi_s, flags, Hhat); });
+  return PF_OK;
+}
+
 }  // extern "C"

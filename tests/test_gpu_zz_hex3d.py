@@ -110,3 +110,10 @@ def test_qp_update_3d(gpu_lib, scheme):
     bits_g = np.stack([(flags >> (q + 8)) & 1 for q in range(8)], axis=1).astype(bool)
     np.testing.assert_array_equal(bits_t, parts["t"] > 0)
     np.testing.assert_array_equal(bits_g, gate)
+    from oracle.constitutive import predicted_energy
+    dd = rng.normal(size=N) * 0.05
+    Hh = torch.full_like(H, float("nan"))
+    ops.predictor(dev(d), dev(dd), H, PS, fl, Hh)
+    Hhat_orc = np.maximum(np.maximum(Hprev, psi),
+                          predicted_energy(psi, ps, om.interp(d), m.eta, om.interp(dd), gate))
+    np.testing.assert_allclose(host(Hh).reshape(8, E).T, Hhat_orc, rtol=1e-12, atol=0)

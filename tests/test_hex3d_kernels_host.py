@@ -23,6 +23,7 @@ import pytest
 
 import paper_2209_07969_amd as pf
 from oracle import hex3d as H3
+from oracle.constitutive import predicted_energy
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = "/opt/rocm/bin/hipcc"
@@ -51,7 +52,9 @@ def harness(tmp_path_factory):
     lib.h3_phase_apply.argtypes = [M3, MT, P, P, P]
     lib.h3_qp_update.argtypes = [M3, MT, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  P, P, P, P, P, P, ctypes.POINTER(ctypes.c_longlong)]
-    for f in ("h3_internal_force", "h3_tangent_apply", "h3_phase_apply", "h3_qp_update"):
+    lib.h3_predictor.argtypes = [M3, MT, P, P, P, P, P, P]
+    for f in ("h3_internal_force", "h3_tangent_apply", "h3_phase_apply", "h3_qp_update",
+              "h3_predictor"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -165,6 +168,20 @@ def test_qp_update(harness, shape, scheme):
     assert ng.value == int(gate.sum())
     if scheme != 0 and shape == (9, 7, 5):
         assert 0 < ng.value < gate.size
+    # predictor on the kernel's own H, psi_S and flags (checked above): a
+    # random increment with both signs, so the Dd > 0 rule is exercised
+    dd = rng.normal(size=N) * 0.05
+    Hh = out_f64(8 * E)
+    ddG = Guarded(dd)
+    assert harness.h3_predictor(mesh, mat, dG.ptr, ddG.ptr, Hout.ptr, PS.ptr, fl.ptr,
+                                Hh.ptr) == 0
+    assert np.all(np.isfinite(Hh.val)) and Hh.guards_intact()
+    H_orc = np.maximum(Hprev, psi)
+    Hhat_orc = np.maximum(H_orc, predicted_energy(psi, ps, dq, MAT["eta"], om.interp(dd), gate))
+    np.testing.assert_allclose(Hh.val.reshape(8, E).T, Hhat_orc, rtol=1e-12, atol=0)
+    if scheme != 0 and shape == (9, 7, 5):
+        moved = Hhat_orc > H_orc
+        assert 0 < moved.sum() < gate.sum()
 
 
 def test_checks_refuse_bad_arguments(harness):
