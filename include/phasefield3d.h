@@ -1,6 +1,7 @@
 /* phasefield3d.h - C ABI of the 3-D operators: trilinear hexahedra (Q1,
- * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric split of
- * Section 2 with the full 3-D strain and the AT2 phase operator.  They are
+ * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric or the
+ * spectral split of Section 2 with the full 3-D strain, and the AT2 phase
+ * operator.  They are
  * the operators of the 2-D path (internal force, tangent apply, phase
  * apply, quadrature-point update, predictor) on a mesh of hexahedra, as in
  * the paper's one-element-thick slab (Section 4) or a full 3-D panel.
@@ -20,9 +21,11 @@
  *   of corner q.
  * The caller owns every buffer; outputs must not alias inputs.  No Dirichlet
  * masking is applied.  Errors: PF_E_INVALID_ARG for a null pointer, a bad
- * mesh (nx, ny, nz >= 1, lengths > 0, 3N and 8E at most 2^31 - 2^16), a bad
- * material or a split other than PF_SPLIT_VD (the only split these kernels
- * implement); PF_E_HIP if the launch fails.  Nothing is written on error.
+ * mesh (nx, ny, nz >= 1, lengths > 0, 3N and 8E at most 2^31 - 2^16) or a
+ * bad material; PF_E_HIP if the launch fails.  Nothing is written on error.
+ * The spectral split takes the principal strains of the full 3x3 strain
+ * (cyclic Jacobi rotations); a principal strain counts as positive only
+ * when strictly above zero, as does the trace. */
  */
 #ifndef PHASEFIELD3D_H
 #define PHASEFIELD3D_H
@@ -39,14 +42,17 @@ typedef struct pf3d_mesh {
 } pf3d_mesh;
 
 /* Internal force R = sum_e sum_q B^T sigma(eps(u), g(d_q)) w detJ with the
- * split stress of Section 2 (eq_sigma), g(d) = (1-d)^2 + eta.
+ * split stress of Section 2 (eq_sigma; spectral: g [lam <t>_+ I + 2 mu
+ * eps+] + lam <t>_- I + 2 mu eps-), g(d) = (1-d)^2 + eta.
  * u [3N], d [N] -> R [3N]. */
 pf_status pf3d_op_internal_force(const pf3d_mesh *mesh, const pf_material *mat,
                                  const double *u, const double *d, double *R,
                                  void *hip_stream);
 
-/* Tangent apply q = K_t(u; d) p of the split stress, its volumetric factor
- * g K where tr eps(u) > 0 strictly, else K (eq_definition_+).
+/* Tangent apply q = K_t(u; d) p of the split stress at u (eq_definition_+):
+ * VD, volumetric factor g K where tr eps(u) > 0 strictly, else K; spectral,
+ * the derivative of eps+ with the divided differences (<e_i>_+ - <e_j>_+) /
+ * (e_i - e_j) between principal strains, H(e_i) where they coincide.
  * u, p, q [3N]; d [N]. */
 pf_status pf3d_op_tangent_apply(const pf3d_mesh *mesh, const pf_material *mat,
                                 const double *u, const double *d, const double *p,
@@ -61,8 +67,9 @@ pf_status pf3d_op_phase_apply(const pf3d_mesh *mesh, const pf_material *mat,
 
 /* Quadrature-point update (Sections 2, 3.5): from u [3N], d [N] and the
  * committed history H_prev [8E], write H = max(H_prev, psi+) [8E], the
- * scheme part psi_S [8E] (scheme 0 ST: 0; 1 S1: psi_vol = K/2 <tr eps>_+^2;
- * 2 S2: psi_dev = mu eps_dev:eps_dev; 3 S3: psi+) and per element a flag
+ * scheme part psi_S [8E] (scheme 0 ST: 0; 1 S1: psi_vol; 2 S2: psi_dev;
+ * 3 S3: psi+, with psi_vol = K/2 <tr eps>_+^2 and psi_dev = mu eps_dev:eps_dev
+ * for VD, lam/2 <tr eps>_+^2 and mu sum <e_i>_+^2 for the spectral split) and per element a flag
  * word flags [E] (uint16): bit q = tr eps > 0 at point q, bit 8+q = the
  * softening gate at point q (scheme != 0, psi+ > psi_crit, psi+ > H_prev
  * and d_q < d_gate).  psi_crit < 0 means Gc / (2 l). */

@@ -416,8 +416,8 @@ class Context:
 
 class Hex3DOps:
     """The 3-D operator entry points (include/phasefield3d.h) on the box mesh
-    of ``problem`` (any object with nx, ny, nz, lx, ly, lz and a material
-    with the split PF_SPLIT_VD).  Device tensors in the header's layouts:
+    of ``problem`` (any object with nx, ny, nz, lx, ly, lz and a material;
+    either split).  Device tensors in the header's layouts:
     displacement fields [3N] (x, y, z planes), nodal fields [N],
     quadrature-point fields [8E] (plane q holds point q of every element),
     flags [E] (int16 tensors holding the uint16 flag words).  Kernels go to

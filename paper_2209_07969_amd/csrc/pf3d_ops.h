@@ -4,9 +4,11 @@
 // are __host__ __device__ so that a host build can replay a kernel's grid
 // index by index.
 //
-// Model (Section 2): volumetric-deviatoric split with the full 3-D strain,
-// sigma = g(d) [K <tr eps>_+ I + 2 mu eps_dev] + K <tr eps>_- I, AT2 phase
-// operator coef N N^T + Gc l grad N . grad N^T, history H = max(H_n, Psi+).
+// Model (Section 2), with the full 3-D strain: the volumetric-deviatoric
+// split sigma = g(d) [K <tr eps>_+ I + 2 mu eps_dev] + K <tr eps>_- I, or the
+// spectral split sigma = g(d) [lam <tr eps>_+ I + 2 mu eps+] + lam <tr eps>_-
+// I + 2 mu eps- over the principal strains; AT2 phase operator coef N N^T +
+// Gc l grad N . grad N^T; history H = max(H_n, Psi+).
 //
 // Layout in device memory (structure of arrays):
 //   node (i, j, k) has id n = i + j (nx+1) + k (nx+1)(ny+1);
@@ -39,6 +41,7 @@ struct Mat3 {
   double lam, mu, K;    // Lame constants, bulk modulus K = lam + 2 mu / 3
   double Gcl;           // Gc l, the phase operator's gradient factor
   double eta;           // residual stiffness of g(d) = (1 - d)^2 + eta
+  int split;            // PF_SPLIT_VD or PF_SPLIT_SPECTRAL
 };
 
 struct Qp3 {
@@ -138,6 +141,152 @@ __host__ __device__ inline void vd_parts(const Mat3 &m, const double eps[6], dou
   *pdev = m.mu * dd;
 }
 
+// ---- spectral split
+
+// Symmetric 3x3 eigen-decomposition A = Q diag(w) Q^T by cyclic Jacobi
+// rotations: each rotation in the (p, r) plane annihilates A_pr, with the
+// tangent of the angle taken as the smaller root.  The sweeps stop once the
+// off-diagonal mass is below 1e-32 of the whole (quadratic convergence
+// reaches that in a few sweeps) and never exceed 16.  Exact zeros
+// off the diagonal are left alone, so a block-diagonal strain keeps its
+// block's eigenvalue exactly.  eps is an engineering Voigt strain.
+__host__ __device__ inline void sym3_eig(const double eps[6], double w[3], double Q[3][3]) {
+  double a[3][3] = {{eps[0], 0.5 * eps[5], 0.5 * eps[4]},
+                    {0.5 * eps[5], eps[1], 0.5 * eps[3]},
+                    {0.5 * eps[4], 0.5 * eps[3], eps[2]}};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Q[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off == 0.0 || off <= 1e-32 * (dia + 2.0 * off)) break;
+    for (int pr = 0; pr < 3; ++pr) {
+      const int p = pr == 2 ? 1 : 0, r = pr == 0 ? 1 : 2;
+      const double apr = a[p][r];
+      if (apr == 0.0) continue;
+      const double theta = (a[r][r] - a[p][p]) / (2.0 * apr);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      const int o = 3 - p - r;   // the third index
+      const double aop = a[o][p], aor = a[o][r];
+      a[p][p] -= t * apr;
+      a[r][r] += t * apr;
+      a[p][r] = a[r][p] = 0.0;
+      a[o][p] = a[p][o] = c * aop - s * aor;
+      a[o][r] = a[r][o] = s * aop + c * aor;
+      for (int k = 0; k < 3; ++k) {
+        const double qp = Q[k][p], qr = Q[k][r];
+        Q[k][p] = c * qp - s * qr;
+        Q[k][r] = s * qp + c * qr;
+      }
+    }
+  }
+  for (int i = 0; i < 3; ++i) w[i] = a[i][i];
+}
+
+__host__ __device__ inline double pos_part(double x) { return x > 0.0 ? x : 0.0; }
+
+// sum_k f_k Q[:,k] Q[:,k]^T as a Voigt stress-like vector [xx, yy, zz, yz, xz, xy].
+__host__ __device__ inline void spectral_sum(const double Q[3][3], const double f[3],
+                                             double out[6]) {
+  const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+  for (int c = 0; c < 6; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += f[k] * Q[I[c]][k] * Q[J[c]][k];
+    out[c] = s;
+  }
+}
+
+__host__ __device__ inline void spectral_stress(const Mat3 &m, const double eps[6], double gd,
+                                                double sig[6]) {
+  double w[3], Q[3][3];
+  sym3_eig(eps, w, Q);
+  const double t = eps[0] + eps[1] + eps[2];
+  const double fp[3] = {pos_part(w[0]), pos_part(w[1]), pos_part(w[2])};
+  const double fn[3] = {w[0] - fp[0], w[1] - fp[1], w[2] - fp[2]};
+  double ep[6], en[6];
+  spectral_sum(Q, fp, ep);
+  spectral_sum(Q, fn, en);
+  const double vol = t > 0.0 ? gd * m.lam * t : m.lam * t;
+  for (int c = 0; c < 6; ++c) sig[c] = gd * 2.0 * m.mu * ep[c] + 2.0 * m.mu * en[c];
+  for (int c = 0; c < 3; ++c) sig[c] += vol;
+}
+
+// Tangent of the spectral stress at eps applied to de: with dE the tensor
+// of de in the eigenbasis, deps+ = Q (theta o dE) Q^T with theta_ij =
+// (<e_i>_+ - <e_j>_+) / (e_i - e_j), or H(e_i) where e_i = e_j; then
+// dsigma = g [lam H(t) dt I + 2 mu deps+] + lam (1 - H(t)) dt I + 2 mu
+// (de - deps+).  H counts strictly positive values.
+__host__ __device__ inline void spectral_tangent_apply(const Mat3 &m, const double eps[6],
+                                                       double gd, const double de[6],
+                                                       double ds[6]) {
+  double w[3], Q[3][3];
+  sym3_eig(eps, w, Q);
+  const double D[3][3] = {{de[0], 0.5 * de[5], 0.5 * de[4]},
+                          {0.5 * de[5], de[1], 0.5 * de[3]},
+                          {0.5 * de[4], 0.5 * de[3], de[2]}};
+  // B = theta o (Q^T D Q)
+  double B[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) s += Q[k][i] * D[k][l] * Q[l][j];
+      const double diff = w[i] - w[j];
+      const double th = diff != 0.0 ? (pos_part(w[i]) - pos_part(w[j])) / diff
+                                    : (w[i] > 0.0 ? 1.0 : 0.0);
+      B[i][j] = th * s;
+    }
+  // deps+ = Q B Q^T, as a Voigt tensor [xx, yy, zz, yz, xz, xy]
+  const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+  double dp[6];
+  for (int c = 0; c < 6; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) s += Q[I[c]][k] * B[k][l] * Q[J[c]][l];
+    dp[c] = s;
+  }
+  const double t = eps[0] + eps[1] + eps[2], dt = de[0] + de[1] + de[2];
+  const double lv = t > 0.0 ? gd * m.lam * dt : m.lam * dt;
+  // the Voigt shear entries of de are engineering strains (twice the tensor)
+  const double dten[6] = {de[0], de[1], de[2], 0.5 * de[3], 0.5 * de[4], 0.5 * de[5]};
+  for (int c = 0; c < 6; ++c) ds[c] = gd * 2.0 * m.mu * dp[c] + 2.0 * m.mu * (dten[c] - dp[c]);
+  for (int c = 0; c < 3; ++c) ds[c] += lv;
+}
+
+// Energy parts of the spectral split: psi_vol = lam/2 <t>_+^2, psi_dev =
+// mu sum <e_i>_+^2.
+__host__ __device__ inline void spectral_parts(const Mat3 &m, const double eps[6],
+                                               double *t_out, double *pvol, double *pdev) {
+  double w[3], Q[3][3];
+  sym3_eig(eps, w, Q);
+  const double t = eps[0] + eps[1] + eps[2], tp = pos_part(t);
+  *t_out = t;
+  *pvol = 0.5 * m.lam * tp * tp;
+  *pdev = m.mu * (pos_part(w[0]) * pos_part(w[0]) + pos_part(w[1]) * pos_part(w[1]) +
+                  pos_part(w[2]) * pos_part(w[2]));
+}
+
+// The split's stress, tangent apply and energy parts.
+__host__ __device__ inline void split_stress(const Mat3 &m, const double eps[6], double gd,
+                                             double sig[6]) {
+  if (m.split == 1) spectral_stress(m, eps, gd, sig);
+  else vd_stress(m, eps, gd, sig);
+}
+
+__host__ __device__ inline void split_tangent_apply(const Mat3 &m, const double eps[6],
+                                                    double gd, const double de[6],
+                                                    double ds[6]) {
+  if (m.split == 1) spectral_tangent_apply(m, eps, gd, de, ds);
+  else vd_tangent_apply(m, eps, gd, de, ds);
+}
+
+__host__ __device__ inline void split_parts(const Mat3 &m, const double eps[6], double *t,
+                                            double *pvol, double *pdev) {
+  if (m.split == 1) spectral_parts(m, eps, t, pvol, pdev);
+  else vd_parts(m, eps, t, pvol, pdev);
+}
+
 // Load the 8 corner values of nodal planes (ncomp planes of N values) of
 // element (ie, je, ke) into out[c * 8 + b].
 __host__ __device__ inline void gather_corners(const Grid3 &g, int ie, int je, int ke,
@@ -181,7 +330,7 @@ __host__ __device__ inline void node_internal_force(const Grid3 &g, const Mat3 &
     for (int q = 0; q < 8; ++q) {
       double eps[6], sig[6];
       strain_at(g, q, ue, eps);
-      vd_stress(m, eps, degrade(interp_at(g, q, de), m.eta), sig);
+      split_stress(m, eps, degrade(interp_at(g, q, de), m.eta), sig);
       const ShapeAt s = shape_at(g, a, q);
       fx += w * (s.gx * sig[0] + s.gz * sig[4] + s.gy * sig[5]);
       fy += w * (s.gy * sig[1] + s.gz * sig[3] + s.gx * sig[5]);
@@ -208,7 +357,7 @@ __host__ __device__ inline void node_tangent_apply(const Grid3 &g, const Mat3 &m
       double eps[6], dep[6], ds[6];
       strain_at(g, q, ue, eps);
       strain_at(g, q, pe, dep);
-      vd_tangent_apply(m, eps, degrade(interp_at(g, q, de), m.eta), dep, ds);
+      split_tangent_apply(m, eps, degrade(interp_at(g, q, de), m.eta), dep, ds);
       const ShapeAt s = shape_at(g, a, q);
       fx += w * (s.gx * ds[0] + s.gz * ds[4] + s.gy * ds[5]);
       fy += w * (s.gy * ds[1] + s.gz * ds[3] + s.gx * ds[5]);
@@ -266,7 +415,7 @@ __host__ __device__ inline int elem_qp_update(const Grid3 &g, const Mat3 &m, con
   for (int q = 0; q < 8; ++q) {
     double eps[6], t, pv, pd;
     strain_at(g, q, ue, eps);
-    vd_parts(m, eps, &t, &pv, &pd);
+    split_parts(m, eps, &t, &pv, &pd);
     const double pplus = pv + pd, hp = Hprev[e + q * g.E];
     H[e + q * g.E] = pplus > hp ? pplus : hp;
     double ps = 0.0;
@@ -351,11 +500,12 @@ inline pf_status make_grid(const pf3d_mesh *mesh, Grid3 *g) {
 inline pf_status make_mat(const pf_material *mat, Mat3 *m) {
   if (!mat || !(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0) ||
       !(mat->l > 0) || !(mat->eta >= 0) || !std::isfinite(mat->E) || !std::isfinite(mat->Gc) ||
-      !std::isfinite(mat->l) || !std::isfinite(mat->eta) || mat->split != PF_SPLIT_VD)
+      !std::isfinite(mat->l) || !std::isfinite(mat->eta) ||
+      (mat->split != PF_SPLIT_VD && mat->split != PF_SPLIT_SPECTRAL))
     return PF_E_INVALID_ARG;
   const double mu = mat->E / (2.0 * (1.0 + mat->nu));
   const double lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
-  *m = Mat3{lam, mu, lam + 2.0 * mu / 3.0, mat->Gc * mat->l, mat->eta};
+  *m = Mat3{lam, mu, lam + 2.0 * mu / 3.0, mat->Gc * mat->l, mat->eta, mat->split};
   return PF_OK;
 }
 

@@ -71,9 +71,9 @@ int main() {
                              {2147483647, 2147483647, 2147483647, 1.0, 1.0, 1.0}};
   for (const auto &mb : m3bad)
     CHECK(pf3d_op_internal_force(&mb, &mat, x, x, x, nullptr) == PF_E_INVALID_ARG);
-  pf_material spectral = mat;
-  spectral.split = PF_SPLIT_SPECTRAL;
-  CHECK(pf3d_op_tangent_apply(&m3, &spectral, x, x, x, x, nullptr) == PF_E_INVALID_ARG);
+  pf_material no_split = mat;
+  no_split.split = 2;
+  CHECK(pf3d_op_tangent_apply(&m3, &no_split, x, x, x, x, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf3d_op_phase_apply(&m3, &mat, nullptr, x, x, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf3d_op_qp_update(&m3, &mat, 9, -1.0, 0.95, x, x, x, x, x, fl, nullptr) ==
         PF_E_INVALID_ARG);

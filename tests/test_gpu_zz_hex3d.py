@@ -22,11 +22,11 @@ MESHES = [(3, 2, 2), (9, 7, 5), (17, 5, 3), (1, 1, 1)]
 
 
 class Box:
-    def __init__(self, nx, ny, nz):
+    def __init__(self, nx, ny, nz, split=0):
         import workloads as W
         self.nx, self.ny, self.nz = nx, ny, nz
         self.lx, self.ly, self.lz = 1.3, 0.7, 0.45
-        self.material = W.Material(E=2.1e5, nu=0.3, Gc=2.7, l=0.05, eta=1e-6, split=0)
+        self.material = W.Material(E=2.1e5, nu=0.3, Gc=2.7, l=0.05, eta=1e-6, split=split)
 
 
 def soa(v):
@@ -44,19 +44,20 @@ def host(t):
     return t.cpu().numpy()
 
 
-def setup(gpu_lib, shape, seed):
-    b = Box(*shape)
+def setup(gpu_lib, shape, seed, split=0):
+    b = Box(*shape, split=split)
     ops = gpu_lib.Hex3DOps(b)
     om = H3.Mesh3D(b.nx, b.ny, b.nz, b.lx, b.ly, b.lz)
     return b, ops, om, np.random.default_rng(seed)
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("shape", MESHES)
-def test_internal_force_and_tangent_3d(gpu_lib, shape):
+def test_internal_force_and_tangent_3d(gpu_lib, shape, split):
     import torch
-    b, ops, om, rng = setup(gpu_lib, shape, sum(shape))
+    b, ops, om, rng = setup(gpu_lib, shape, sum(shape), split)
     m = b.material
-    cons = H3.VD3D(m.E, m.nu)
+    cons = (H3.VD3D if split == 0 else H3.Spectral3D)(m.E, m.nu)
     N = om.n_nodes
     u = rng.normal(size=3 * N) * 1e-3
     d = rng.uniform(0, 1, size=N)
@@ -84,12 +85,13 @@ def test_phase_apply_3d(gpu_lib, shape):
     np.testing.assert_allclose(host(q), q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("scheme", [0, 1, 2, 3])
-def test_qp_update_3d(gpu_lib, scheme):
+def test_qp_update_3d(gpu_lib, scheme, split):
     import torch
-    b, ops, om, rng = setup(gpu_lib, (9, 7, 5), 100 + scheme)
+    b, ops, om, rng = setup(gpu_lib, (9, 7, 5), 100 + scheme, split)
     m = b.material
-    cons = H3.VD3D(m.E, m.nu)
+    cons = (H3.VD3D if split == 0 else H3.Spectral3D)(m.E, m.nu)
     N, E = om.n_nodes, om.conn.shape[0]
     u = rng.normal(size=3 * N) * 2e-3
     d = rng.uniform(0, 1, size=N)

@@ -5,7 +5,8 @@ build of tests/hex3d_host_harness.cpp replays each launch's grid, block by
 block and thread by thread, through the same per-index functions and the C
 ABI's own mesh, material and gate checks.  This checks the indexing, the
 element and Gauss-point tables and the arithmetic of every kernel against
-the independently assembled oracle (oracle/hex3d.py) on meshes that span
+the independently assembled oracle (oracle/hex3d.py), with either split,
+on meshes that span
 one block, several blocks with a ragged tail, and a single element.  Every
 array sits between guard zones: inputs between NaNs (an out-of-bounds read
 turns an output non-finite), outputs between sentinels that must survive
@@ -87,10 +88,10 @@ def out_f64(n):
     return Guarded(n=n, guard=SENT, init=np.nan)
 
 
-def setup(nx, ny, nz, seed):
+def setup(nx, ny, nz, seed, split=0):
     lx, ly, lz = 1.3, 0.7, 0.45
     mesh = pf.Mesh3Desc(nx, ny, nz, lx, ly, lz)
-    mat = pf.MaterialDesc(MAT["E"], MAT["nu"], MAT["Gc"], MAT["l"], MAT["eta"], 0)
+    mat = pf.MaterialDesc(MAT["E"], MAT["nu"], MAT["Gc"], MAT["l"], MAT["eta"], split)
     om = H3.Mesh3D(nx, ny, nz, lx, ly, lz)
     rng = np.random.default_rng(seed)
     return mesh, mat, om, rng
@@ -100,10 +101,15 @@ def soa(v):
     return np.concatenate([v[0::3], v[1::3], v[2::3]])
 
 
+def oracle_split(split):
+    return (H3.VD3D if split == 0 else H3.Spectral3D)(MAT["E"], MAT["nu"])
+
+
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("shape", MESHES)
-def test_internal_force_and_tangent(harness, shape):
-    mesh, mat, om, rng = setup(*shape, seed=sum(shape))
-    cons = H3.VD3D(MAT["E"], MAT["nu"])
+def test_internal_force_and_tangent(harness, shape, split):
+    mesh, mat, om, rng = setup(*shape, seed=sum(shape), split=split)
+    cons = oracle_split(split)
     N = om.n_nodes
     u = rng.normal(size=3 * N) * 1e-3
     d = rng.uniform(0, 1, size=N)
@@ -133,11 +139,12 @@ def test_phase_apply(harness, shape):
     np.testing.assert_allclose(q.val, q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape", [(9, 7, 5), (2, 3, 1)])
-def test_qp_update(harness, shape, scheme):
-    mesh, mat, om, rng = setup(*shape, seed=100 + scheme)
-    cons = H3.VD3D(MAT["E"], MAT["nu"])
+def test_qp_update(harness, shape, scheme, split):
+    mesh, mat, om, rng = setup(*shape, seed=100 + scheme, split=split)
+    cons = oracle_split(split)
     N, E = om.n_nodes, om.conn.shape[0]
     u = rng.normal(size=3 * N) * 2e-3
     d = rng.uniform(0, 1, size=N)
@@ -187,7 +194,7 @@ def test_qp_update(harness, shape, scheme):
 def test_checks_refuse_bad_arguments(harness):
     lib = pf.load_library()
     mat = pf.MaterialDesc(MAT["E"], MAT["nu"], MAT["Gc"], MAT["l"], MAT["eta"], 0)
-    spectral = pf.MaterialDesc(MAT["E"], MAT["nu"], MAT["Gc"], MAT["l"], MAT["eta"], 1)
+    no_split = pf.MaterialDesc(MAT["E"], MAT["nu"], MAT["Gc"], MAT["l"], MAT["eta"], 2)
     x = Guarded(np.zeros(3 * 8))
     good = pf.Mesh3Desc(1, 1, 1, 1.0, 1.0, 1.0)
     null = ctypes.c_void_p()
@@ -200,7 +207,7 @@ def test_checks_refuse_bad_arguments(harness):
     for m in bad_meshes:
         assert lib.pf3d_op_internal_force(m, mat, x.ptr, x.ptr, x.ptr, s) == 1
         assert harness.h3_internal_force(m, mat, x.ptr, x.ptr, x.ptr) == 1
-    assert lib.pf3d_op_internal_force(good, spectral, x.ptr, x.ptr, x.ptr, s) == 1
+    assert lib.pf3d_op_internal_force(good, no_split, x.ptr, x.ptr, x.ptr, s) == 1
     assert lib.pf3d_op_internal_force(good, mat, null, x.ptr, x.ptr, s) == 1
     assert lib.pf3d_op_phase_apply(good, mat, x.ptr, x.ptr, null, s) == 1
     ng = ctypes.c_longlong()
@@ -211,3 +218,37 @@ def test_checks_refuse_bad_arguments(harness):
                                     x.ptr, x.ptr, ctypes.byref(ng)) == 1
     # nothing was written by a refused call
     assert np.all(x.val == 0.0) and x.guards_intact()
+
+
+def test_spectral_plane_fields(harness):
+    """Fields independent of z with u_z = 0 (the slab's kinematics): one
+    principal strain vanishes.  In exact arithmetic its z-shears cancel in
+    pairs of corners; both sides sum them in their own order and keep about
+    1e-18 of rounding, so that principal strain comes out near +-1e-33 with
+    an arbitrary sign, and the strict tie rule may classify it differently
+    on each side.  That choice only scales out-of-plane increments, so the
+    tangent is driven by a plane increment, as in the slab, where both sides
+    must agree."""
+    mesh, mat, om, rng = setup(9, 7, 3, seed=5, split=1)
+    cons = oracle_split(1)
+    N = om.n_nodes
+    P = (9 + 1) * (7 + 1)
+    uxy = rng.normal(size=(2, P)) * 1e-3
+    u = np.zeros(3 * N)
+    for k in range(4):
+        u[3 * (k * P + np.arange(P))] = uxy[0]
+        u[3 * (k * P + np.arange(P)) + 1] = uxy[1]
+    d = np.tile(rng.uniform(0, 1, size=P), 4)
+    pxy = rng.normal(size=(2, P))
+    p = np.zeros(3 * N)
+    for k in range(4):
+        p[3 * (k * P + np.arange(P))] = pxy[0]
+        p[3 * (k * P + np.arange(P)) + 1] = pxy[1]
+    R_orc = soa(H3.internal_force(om, cons, u, d, MAT["eta"]))
+    q_orc = soa(H3.tangent_matrix(om, cons, u, d, MAT["eta"]) @ p)
+    uG, dG, pG = Guarded(soa(u)), Guarded(d), Guarded(soa(p))
+    R, q = out_f64(3 * N), out_f64(3 * N)
+    assert harness.h3_internal_force(mesh, mat, uG.ptr, dG.ptr, R.ptr) == 0
+    assert harness.h3_tangent_apply(mesh, mat, uG.ptr, dG.ptr, pG.ptr, q.ptr) == 0
+    np.testing.assert_allclose(R.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
+    np.testing.assert_allclose(q.val, q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
