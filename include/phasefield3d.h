@@ -25,7 +25,7 @@
  * bad material; PF_E_HIP if the launch fails.  Nothing is written on error.
  * The spectral split takes the principal strains of the full 3x3 strain
  * (cyclic Jacobi rotations); a principal strain counts as positive only
- * when strictly above zero, as does the trace. */
+ * when strictly above zero, as does the trace.
  */
 #ifndef PHASEFIELD3D_H
 #define PHASEFIELD3D_H
