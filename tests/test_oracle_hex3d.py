@@ -200,3 +200,46 @@ def test_spectral3d_tangent_is_stress_derivative(seed):
         dv[k] = h
         fd = (c.stress(eps + dv, g) - c.stress(eps - dv, g)) / (2 * h)
         np.testing.assert_allclose(fd, C[:, :, k], rtol=0, atol=1e-8 * np.abs(C).max())
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+def test_uniaxial_bar3d_spectral_closed_form(scheme):
+    """Uniaxial stress with the spectral split: the principal strains are
+    eps (axial) and e_l twice (lateral, negative).  The lateral ones stay
+    undegraded, so sigma_l = g lam t + 2 mu e_l = 0 with t = eps + 2 e_l,
+    i.e. t = eps / (1 + g lam / mu); then Psi+ = lam/2 t^2 + mu eps^2 and
+    the axial stress is g (lam t + 2 mu eps).  Psi+ grows with d, so d is
+    the root of d = 2 l Psi+(d) / (Gc + 2 l Psi+(d)), which the staggered
+    schemes reach as their common fixed point.  Steps 1-4 reach d = 0.50,
+    beyond the stress peak (eps = 0.0127, d = 0.26); further on the
+    softening bar also has non-uniform equilibria, and S3 lands on one at
+    the next step, so the pin stops at step 4."""
+    import dataclasses
+
+    from scipy.optimize import brentq
+    p = W.uniaxial_bar3d(n=2, l=0.03, du=5e-3, steps=4)
+    m = dataclasses.replace(p.material, split=W.SPLIT_SPECTRAL)
+    p = dataclasses.replace(p, material=m, tol_stag=1e-11, max_stag=200)
+    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
+    mu = m.E / (2 * (1 + m.nu))
+    o = Oracle3D(p, scheme)
+    for lam_u in p.loads:
+        st = o.load_step(float(lam_u))
+        assert st.converged
+        eps = lam_u / p.ly
+
+        def parts(d):
+            g = (1 - d) ** 2 + m.eta
+            t = eps / (1 + g * lam / mu)
+            return g, t, 0.5 * lam * t * t + mu * eps * eps
+
+        d_ref = brentq(lambda d: d - 2 * m.l * parts(d)[2] / (m.Gc + 2 * m.l * parts(d)[2]),
+                       0.0, 1.0, xtol=1e-15)
+        g, t, _ = parts(d_ref)
+        np.testing.assert_allclose(o.d, d_ref, rtol=1e-8)
+        assert np.isclose(st.force, g * (lam * t + 2 * mu * eps) * p.lx * p.lz, rtol=1e-8)
+        # lateral contraction e_l = (t - eps) / 2 on the faces x = lx and z = lz
+        nodes = np.arange(o.mesh.n_nodes)
+        xface = nodes[(nodes % (p.nx + 1)) == p.nx]
+        np.testing.assert_allclose(o.u[3 * xface], 0.5 * (t - eps) * p.lx, rtol=1e-8)
+    assert 0.45 < d_ref < 0.55
