@@ -352,6 +352,28 @@ def batch_instances(count=64, seed=2209, steps=50, du=1.6e-4,
     return out
 
 
+def batch_instance_table(**kw):
+    """The drawn parameters of batch_instances(**kw), one dict per instance
+    (mesh size, Gc, l, notch length as snapped to the node grid, steps)."""
+    rows = []
+    for p in batch_instances(**kw):
+        notch_x = float(p.dir_d_nodes.max() % (p.nx + 1)) / p.nx
+        rows.append({"name": p.name, "n": p.nx, "Gc": p.material.Gc, "l": p.material.l,
+                     "notch_end": notch_x, "steps": int(p.loads.size),
+                     "du": float(p.loads[0])})
+    return rows
+
+
+def write_batch_instance_table(path, **kw):
+    """Record the sweep's instances as JSON (workloads/sweep64_instances.json
+    is this function's output for the defaults)."""
+    with open(path, "w") as f:
+        json.dump({"generator": "numpy.random.default_rng(2209), drawn per instance in the "
+                                "order n, Gc, l multiplier, notch length",
+                   "instances": batch_instance_table(**kw)}, f, indent=1)
+        f.write("\n")
+
+
 def problem_to_json(p: Problem) -> str:
     d = {
         "name": p.name, "nx": p.nx, "ny": p.ny, "lx": p.lx, "ly": p.ly,
