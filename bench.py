@@ -37,7 +37,12 @@ Two further modes print their own single JSON line:
                          trial solve (floored or unfloored block, predict ->
                          correct or trial-only), FP64, over the whole load
                          history of --trial-problem (64^2 by default):
-                         staggered counts, convergence and force curves.
+                         staggered counts, convergence and force curves;
+  --workload oracle-history  the CPU baseline over a whole load history: the
+                         oracle (FP64, direct solves) on the 64^2
+                         configuration for ST and S1, with the cap of
+                         --max-stag (no GPU needed), for comparison with the
+                         GPU times of trial-readings on the same history.
 """
 from __future__ import annotations
 
@@ -196,6 +201,42 @@ def cpu_baseline(pf, problem):
                    f"rate = GPU CG DOF-updates for the same sample ({gpu_updates:.3e}) / "
                    f"oracle time"),
         "seconds": t,
+    }
+
+
+def run_oracle_history(args):
+    """The oracle over the whole 64^2 load history, ST and S1, on one host
+    process: total time, staggered iterations per step, forces."""
+    import dataclasses
+
+    import oracle
+    import workloads as W
+    base = W.config_tension64()
+    if args.max_stag > 0:
+        base = dataclasses.replace(base, max_stag=args.max_stag)
+    out = []
+    for scheme in (0, 1):
+        orc = oracle.Oracle(base, scheme)
+        t0, c0 = time.perf_counter(), time.process_time()
+        rows = []
+        for lam in base.loads:
+            st = orc.load_step(float(lam))
+            rows.append({"n_stag": st.n_stag, "converged": bool(st.converged),
+                         "force": st.force})
+        secs, cpu_s = time.perf_counter() - t0, time.process_time() - c0
+        out.append({"scheme": ["ST", "S1"][scheme], "seconds": secs, "cpu_seconds": cpu_s,
+                    "cores": max(1, round(cpu_s / secs)),
+                    "n_stag_total": sum(r["n_stag"] for r in rows), "steps": rows})
+        log(f"  oracle {out[-1]['scheme']}: {secs:.1f} s, N_stag {out[-1]['n_stag_total']}")
+    return {
+        "metric": "oracle time per load history (CPU baseline), ST and S1 FP64",
+        "value": out[1]["seconds"], "unit": "s", "n_gpus": 0, "steps": len(base.loads),
+        "warmup": 0, "ms_per_step": out[1]["seconds"] * 1e3 / len(base.loads),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"oracle-history: {base.name} ({base.nx}x{base.ny}, "
+                               f"{len(base.loads)} load steps), max_stag {base.max_stag}"},
+        "cpu_baseline": {"kind": "oracle", "runs": out},
     }
 
 
@@ -390,7 +431,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tension512",
                     choices=["tension512", "tension64", "shear1024", "lshape2048", "sweep64",
-                             "apply-sizes", "trial-readings"])
+                             "apply-sizes", "trial-readings", "oracle-history"])
     ap.add_argument("--trial-problem", default="tension64", choices=["tension64", "tension512"],
                     help="problem of the trial-readings mode (its whole load history)")
     ap.add_argument("--trial-reading", default="all",
@@ -401,7 +442,8 @@ def main():
     ap.add_argument("--trial-steps", type=int, default=0,
                     help="first load steps of the trial-readings problem (0: all)")
     ap.add_argument("--max-stag", type=int, default=0,
-                    help="staggered iteration cap of the trial-readings mode (0: the problem's)")
+                    help="staggered iteration cap of the trial-readings and oracle-history "
+                         "modes (0: the problem's)")
     ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
     ap.add_argument("--jacobi", action="store_true",
                     help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
@@ -436,6 +478,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "oracle-history":
+        print(json.dumps(run_oracle_history(args)))
+        return
 
     import torch
 
