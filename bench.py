@@ -130,11 +130,26 @@ def load_step_logged(ctx, problem, lam, every=25):
     return st
 
 
+STEP_FIELDS = ("n_stag", "n_newton", "n_trial", "n_dsolve", "n_cg_u", "n_cg_d", "n_cg_trial",
+               "gated_max", "floor_hits", "r_stag", "force", "time_ms", "dof_updates",
+               "converged", "cg_not_converged")
+
+
+def step_record(label, step, timed, st):
+    """One JSON-lines record of a load step's statistics."""
+    rec = {"run": label, "step": step, "timed": timed}
+    for k in STEP_FIELDS:
+        v = st.get(k)
+        rec[k] = list(v) if isinstance(v, (tuple, list)) else v
+    return json.dumps(rec)
+
+
 def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degree=None,
-              tune_reps=0, rows=0):
+              tune_reps=0, rows=0, jsonl=None, label=""):
     """Run load steps 1..warmup untimed and warmup+1..warmup+steps timed.
     degree: Jacobi-Chebyshev degree (None = plain Jacobi); rows: work
-    decomposition (march_rows); tune_reps > 0: let the autotuner pick it."""
+    decomposition (march_rows); tune_reps > 0: let the autotuner pick it;
+    jsonl: an open file that receives one record per load step."""
     import torch
     opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
     ctx = pf.Context(problem, scheme=scheme, precision=precision, march_rows=rows, **opts)
@@ -143,6 +158,8 @@ def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degr
         ctx.set_profiling(True)
     for n in range(warmup):
         st = load_step_logged(ctx, problem, float(problem.loads[n]))
+        if jsonl:
+            jsonl.write(step_record(label, n + 1, False, st) + "\n")
         log(f"  warmup step {n+1}: n_stag={st['n_stag']} cg_u={st['n_cg_u']} "
             f"cg_d={st['n_cg_d']} cg_trial={st['n_cg_trial']} {st['time_ms']:.0f} ms")
     if profile:
@@ -153,6 +170,9 @@ def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degr
     for n in range(warmup, warmup + steps):
         st = load_step_logged(ctx, problem, float(problem.loads[n]))
         rows.append(st)
+        if jsonl:
+            jsonl.write(step_record(label, n + 1, True, st) + "\n")
+            jsonl.flush()
         log(f"  timed step {n+1}: n_stag={st['n_stag']} newton={st['n_newton']} "
             f"cg_u={st['n_cg_u']} cg_d={st['n_cg_d']} cg_trial={st['n_cg_trial']} "
             f"gated={st['gated_max']} F={st['force'][1]:.4f} {st['time_ms']:.0f} ms")
@@ -463,6 +483,9 @@ def main():
     ap.add_argument("--apply-iters", type=int, default=512,
                     help="CG iterations per size in the apply-sizes mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--stats-jsonl", default="",
+                    help="write one JSON line of statistics per load step of the S1 mixed and "
+                         "ST FP64 runs to this file")
     ap.add_argument("--no-st", action="store_true", help="skip the ST FP64 comparison run")
     ap.add_argument("--st-only", action="store_true",
                     help="time only the ST FP64 run (long histories in separate jobs)")
@@ -523,10 +546,12 @@ def main():
         raise SystemExit("warmup + steps exceeds the load history")
 
     s1_deg, st_deg = (None, None) if args.jacobi else (args.s1_degree, args.st_degree)
+    jsonl = open(args.stats_jsonl, "w") if args.stats_jsonl else None
     if args.st_only:
         log(f"ST FP64 on {problem.name}")
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
-                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows)
+                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows,
+                                       jsonl=jsonl, label="st_fp64")
         print(json.dumps({
             "metric": "time per load step, ST FP64 (comparison run)",
             "value": secs2 * 1e3 / args.steps, "unit": "ms/step", "n_gpus": 1,
@@ -538,11 +563,13 @@ def main():
             "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
             "march_rows": ctx2.chosen_rows, "dtype": "f64", "data": "synthetic"}))
         ctx2.close()
+        if jsonl:
+            jsonl.close()
         return
     log(f"S1 mixed on {problem.name}")
     ctx, rows, secs = run_steps(pf, problem, pf.S1, pf.MIXED, args.warmup, args.steps,
                                 profile=True, degree=s1_deg, tune_reps=args.tune_reps,
-                                rows=args.rows)
+                                rows=args.rows, jsonl=jsonl, label="s1_mixed")
     updates = sum(r["dof_updates"] for r in rows)
     value = updates / secs / 1e9
     ms_per_step = secs * 1e3 / args.steps
@@ -572,7 +599,8 @@ def main():
     if not args.no_st:
         log(f"ST FP64 on {problem.name}")
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
-                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows)
+                                       degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows,
+                                       jsonl=jsonl, label="st_fp64")
         upd2 = sum(r["dof_updates"] for r in rows2)
         st_res = {
             "ms_per_step": secs2 * 1e3 / args.steps,
@@ -634,6 +662,8 @@ def main():
     }
     if cpu is not None:
         cpu.pop("seconds", None)
+    if jsonl:
+        jsonl.close()
     print(json.dumps(out))
 
 

@@ -45,3 +45,17 @@ def test_algorithmic_bytes_per_node():
     assert b.updcheb_bytes_per_node() == (10 * 2 + 1) * f32 + 2 * flag
     # vector update: x, p, q, r, D^-1 in; x, r, z out, per DOF
     assert b.update_bytes_per_node() == 2 * 8 * f32
+
+
+def test_step_record_is_one_json_line():
+    b = bench()
+    st = {"n_stag": 5, "n_newton": 7, "n_trial": 2, "n_dsolve": 4, "n_cg_u": 900, "n_cg_d": 80,
+          "n_cg_trial": 40, "gated_max": 12, "floor_hits": 3, "r_stag": 8e-6,
+          "force": [0.0, 123.5], "time_ms": 42.0, "dof_updates": 1.5e6, "converged": 1,
+          "cg_not_converged": 0, "extra": "ignored"}
+    line = b.step_record("s1_mixed", 3, True, st)
+    assert "\n" not in line
+    rec = json.loads(line)
+    assert rec["run"] == "s1_mixed" and rec["step"] == 3 and rec["timed"] is True
+    assert rec["force"] == [0.0, 123.5] and rec["n_cg_trial"] == 40
+    assert set(rec) == {"run", "step", "timed", *b.STEP_FIELDS}
