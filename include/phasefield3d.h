@@ -2,9 +2,10 @@
  * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric or the
  * spectral split of Section 2 with the full 3-D strain, and the AT2 phase
  * operator.  They are
- * the operators of the 2-D path (internal force, tangent apply, phase
- * apply, quadrature-point update, predictor) on a mesh of hexahedra, as in
- * the paper's one-element-thick slab (Section 4) or a full 3-D panel.
+ * the element and node operators of the 2-D path (internal force, tangent
+ * apply and diagonal, phase apply, diagonal, right-hand side and mass
+ * coefficients, quadrature-point update, predictor) on a mesh of hexahedra,
+ * as in the paper's one-element-thick slab (Section 4) or a full 3-D panel.
  *
  * Every entry point is stateless: it takes the mesh and material by value
  * (read on the host), device pointers for the fields, and a hipStream_t
@@ -85,6 +86,33 @@ pf_status pf3d_op_qp_update(const pf3d_mesh *mesh, const pf_material *mat, int32
 pf_status pf3d_op_predictor(const pf3d_mesh *mesh, const pf_material *mat, const double *d,
                             const double *dd, const double *H, const double *psi_s,
                             const uint16_t *flags, double *Hhat, void *hip_stream);
+
+/* Diagonal of the tangent K_t(u; d) (the Jacobi preconditioner of the
+ * displacement solve).  u [3N], d [N] -> D [3N]. */
+pf_status pf3d_op_tangent_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                               const double *d, double *D, void *hip_stream);
+
+/* Diagonal of the phase operator with the per-point coefficient coef [8E]:
+ * D_n = sum [coef_q N_n^2 + Gc l |grad N_n|^2] w detJ.  -> D [N]. */
+pf_status pf3d_op_phase_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *coef,
+                             double *D, void *hip_stream);
+
+/* Right-hand side of the AT2 evolution equation (Section 2 with w = d^2):
+ * b = sum 2 H_q N w detJ.  H [8E] -> b [N]. */
+pf_status pf3d_op_phase_rhs(const pf3d_mesh *mesh, const double *H, double *b,
+                            void *hip_stream);
+
+/* Mass coefficient of the phase block at every point, coef [8E]: with
+ * trial = 0 the AT2 coefficient Gc/l + 2H; with trial = 1 that of the trial
+ * block K_dd + K~ (Section 3.4): at gated points (flags bit 8+q, from
+ * pf3d_op_qp_update) c - c_S with c_S = 8 (1-d_q)^2 / g(d_q) psi_S, and
+ * where that falls below theta c it is raised to theta c (floor = 1) or kept
+ * (floor = 0, the unfloored block, possibly indefinite).  psi_s, flags and
+ * d are read only with trial = 1 (may be NULL otherwise).  0 <= theta <= 1. */
+pf_status pf3d_op_phase_coef(const pf3d_mesh *mesh, const pf_material *mat, int32_t trial,
+                             double theta, int32_t floor, const double *H, const double *psi_s,
+                             const uint16_t *flags, const double *d, double *coef,
+                             void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,8 @@ EXPORTED = [
 ]
 EXPORTED_3D = [
     "pf3d_op_internal_force", "pf3d_op_tangent_apply", "pf3d_op_phase_apply",
-    "pf3d_op_qp_update", "pf3d_op_predictor",
+    "pf3d_op_qp_update", "pf3d_op_predictor", "pf3d_op_tangent_diag", "pf3d_op_phase_diag",
+    "pf3d_op_phase_rhs", "pf3d_op_phase_coef",
 ]
 
 
@@ -140,6 +141,10 @@ def load_library(path: str = LIB_PATH):
     lib.pf3d_op_phase_apply.argtypes = [M3, MT, P, P, P, P]
     lib.pf3d_op_qp_update.argtypes = [M3, MT, c_int32, c_double, c_double, P, P, P, P, P, P, P]
     lib.pf3d_op_predictor.argtypes = [M3, MT, P, P, P, P, P, P, P]
+    lib.pf3d_op_tangent_diag.argtypes = [M3, MT, P, P, P, P]
+    lib.pf3d_op_phase_diag.argtypes = [M3, MT, P, P, P]
+    lib.pf3d_op_phase_rhs.argtypes = [M3, P, P, P]
+    lib.pf3d_op_phase_coef.argtypes = [M3, MT, c_int32, c_double, c_int32, P, P, P, P, P, P]
     for name in EXPORTED + EXPORTED_3D:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
@@ -486,6 +491,39 @@ class Hex3DOps:
             self._arg(dd, N, "dd"), self._arg(H, E8, "H"), self._arg(psi_s, E8, "psi_s"),
             self._arg(flags, self.E, "flags", torch.int16), self._arg(Hhat, E8, "Hhat"),
             self._stream()), "pf3d_op_predictor")
+
+    def tangent_diag(self, u, d, D):
+        N = self.N
+        self._check(self.lib.pf3d_op_tangent_diag(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(u, 3 * N, "u"),
+            self._arg(d, N, "d"), self._arg(D, 3 * N, "D"), self._stream()),
+            "pf3d_op_tangent_diag")
+
+    def phase_diag(self, coef, D):
+        self._check(self.lib.pf3d_op_phase_diag(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), self._arg(coef, 8 * self.E, "coef"),
+            self._arg(D, self.N, "D"), self._stream()), "pf3d_op_phase_diag")
+
+    def phase_rhs(self, H, b):
+        self._check(self.lib.pf3d_op_phase_rhs(
+            ctypes.byref(self.mesh), self._arg(H, 8 * self.E, "H"), self._arg(b, self.N, "b"),
+            self._stream()), "pf3d_op_phase_rhs")
+
+    def phase_coef(self, H, coef, trial=None):
+        """AT2 coefficient, or with trial = (theta, floor, psi_s, flags, d)
+        the trial block's."""
+        import torch
+        E8 = 8 * self.E
+        if trial is None:
+            args = (0, 0.0, 0, None, None, None)
+        else:
+            theta, floor, psi_s, flags, d = trial
+            args = (1, float(theta), int(floor), self._arg(psi_s, E8, "psi_s"),
+                    self._arg(flags, self.E, "flags", torch.int16), self._arg(d, self.N, "d"))
+        self._check(self.lib.pf3d_op_phase_coef(
+            ctypes.byref(self.mesh), ctypes.byref(self.mat), args[0], args[1], args[2],
+            self._arg(H, E8, "H"), args[3], args[4], args[5], self._arg(coef, E8, "coef"),
+            self._stream()), "pf3d_op_phase_coef")
 
 
 class Batch:

@@ -51,6 +51,32 @@ __global__ void __launch_bounds__(kTpb3) k3_predictor(Grid3 g, Mat3 m, const dou
   if (e < g.E) elem_predictor(g, m, e, d, dd, H, psi_s, flags, Hhat);
 }
 
+__global__ void __launch_bounds__(kTpb3) k3_tangent_diag(Grid3 g, Mat3 m, const double *u,
+                                                         const double *d, double *D) {
+  const int n = grid_index(blockIdx.x, threadIdx.x);
+  if (n < g.N) node_tangent_diag(g, m, n, u, d, D);
+}
+
+__global__ void __launch_bounds__(kTpb3) k3_phase_diag(Grid3 g, Mat3 m, const double *coef,
+                                                       double *D) {
+  const int n = grid_index(blockIdx.x, threadIdx.x);
+  if (n < g.N) node_phase_diag(g, m, n, coef, D);
+}
+
+__global__ void __launch_bounds__(kTpb3) k3_phase_rhs(Grid3 g, const double *H, double *b) {
+  const int n = grid_index(blockIdx.x, threadIdx.x);
+  if (n < g.N) node_phase_rhs(g, n, H, b);
+}
+
+__global__ void __launch_bounds__(kTpb3) k3_phase_coef(Grid3 g, Mat3 m, int trial, double theta,
+                                                       int floor, const double *H,
+                                                       const double *psi_s,
+                                                       const uint16_t *flags, const double *d,
+                                                       double *coef) {
+  const int e = grid_index(blockIdx.x, threadIdx.x);
+  if (e < g.E) (void)elem_phase_coef(g, m, e, trial, theta, floor, H, psi_s, flags, d, coef);
+}
+
 pf_status launched() {
   return hipGetLastError() == hipSuccess ? PF_OK : PF_E_HIP;
 }
@@ -121,6 +147,53 @@ pf_status pf3d_op_predictor(const pf3d_mesh *mesh, const pf_material *mat, const
     return PF_E_INVALID_ARG;
   hipLaunchKernelGGL(k3_predictor, dim3(grid_blocks(g.E)), dim3(kTpb3), 0,
                      static_cast<hipStream_t>(hip_stream), g, m, d, dd, H, psi_s, flags, Hhat);
+  return launched();
+}
+
+pf_status pf3d_op_tangent_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                               const double *d, double *D, void *hip_stream) {
+  Grid3 g;
+  Mat3 m;
+  if (!u || !d || !D || make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK)
+    return PF_E_INVALID_ARG;
+  hipLaunchKernelGGL(k3_tangent_diag, dim3(grid_blocks(g.N)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, m, u, d, D);
+  return launched();
+}
+
+pf_status pf3d_op_phase_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *coef,
+                             double *D, void *hip_stream) {
+  Grid3 g;
+  Mat3 m;
+  if (!coef || !D || make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK)
+    return PF_E_INVALID_ARG;
+  hipLaunchKernelGGL(k3_phase_diag, dim3(grid_blocks(g.N)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, m, coef, D);
+  return launched();
+}
+
+pf_status pf3d_op_phase_rhs(const pf3d_mesh *mesh, const double *H, double *b,
+                            void *hip_stream) {
+  Grid3 g;
+  if (!H || !b || make_grid(mesh, &g) != PF_OK) return PF_E_INVALID_ARG;
+  hipLaunchKernelGGL(k3_phase_rhs, dim3(grid_blocks(g.N)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, H, b);
+  return launched();
+}
+
+pf_status pf3d_op_phase_coef(const pf3d_mesh *mesh, const pf_material *mat, int32_t trial,
+                             double theta, int32_t floor, const double *H, const double *psi_s,
+                             const uint16_t *flags, const double *d, double *coef,
+                             void *hip_stream) {
+  Grid3 g;
+  Mat3 m;
+  if (!H || !coef || (trial && (!psi_s || !flags || !d)) || trial < 0 || trial > 1 ||
+      floor < 0 || floor > 1 || !(theta >= 0.0 && theta <= 1.0) ||
+      make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK)
+    return PF_E_INVALID_ARG;
+  hipLaunchKernelGGL(k3_phase_coef, dim3(grid_blocks(g.E)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, m, trial, theta, floor, H, psi_s,
+                     flags, d, coef);
   return launched();
 }
 

@@ -42,6 +42,7 @@ struct Mat3 {
   double Gcl;           // Gc l, the phase operator's gradient factor
   double eta;           // residual stiffness of g(d) = (1 - d)^2 + eta
   int split;            // PF_SPLIT_VD or PF_SPLIT_SPECTRAL
+  double Gc_l;          // Gc / l, the AT2 mass coefficient's constant part
 };
 
 struct Qp3 {
@@ -396,6 +397,104 @@ __host__ __device__ inline void node_phase_apply(const Grid3 &g, const Mat3 &m, 
   out[n] = acc;
 }
 
+// Diagonal of the tangent at node n: for each component c, the sum over
+// its elements and points of w (B_a,c)^T C_t(eps(u)) B_a,c, i.e. the tangent
+// applied to the strain of a unit displacement of corner a along c.
+__host__ __device__ inline void node_tangent_diag(const Grid3 &g, const Mat3 &m, int n,
+                                                  const double *u, const double *d,
+                                                  double *D) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double dx = 0.0, dy = 0.0, dz = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    double ue[24], de[8];
+    gather_corners(g, ie, je, ke, u, 3, ue);
+    gather_corners(g, ie, je, ke, d, 1, de);
+    for (int q = 0; q < 8; ++q) {
+      double eps[6];
+      strain_at(g, q, ue, eps);
+      const double gd = degrade(interp_at(g, q, de), m.eta);
+      const ShapeAt s = shape_at(g, a, q);
+      const double bx[6] = {s.gx, 0.0, 0.0, 0.0, s.gz, s.gy};
+      const double by[6] = {0.0, s.gy, 0.0, s.gz, 0.0, s.gx};
+      const double bz[6] = {0.0, 0.0, s.gz, s.gy, s.gx, 0.0};
+      double ds[6];
+      split_tangent_apply(m, eps, gd, bx, ds);
+      dx += w * (s.gx * ds[0] + s.gz * ds[4] + s.gy * ds[5]);
+      split_tangent_apply(m, eps, gd, by, ds);
+      dy += w * (s.gy * ds[1] + s.gz * ds[3] + s.gx * ds[5]);
+      split_tangent_apply(m, eps, gd, bz, ds);
+      dz += w * (s.gz * ds[2] + s.gy * ds[3] + s.gx * ds[4]);
+    }
+  });
+  D[n] = dx;
+  D[g.N + n] = dy;
+  D[2 * g.N + n] = dz;
+}
+
+// Diagonal of the phase operator at node n: sum w [coef_q N_a^2 + Gc l
+// |grad N_a|^2].
+__host__ __device__ inline void node_phase_diag(const Grid3 &g, const Mat3 &m, int n,
+                                                const double *coef, double *D) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double acc = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    const int e = ie + je * g.nx + ke * g.nx * g.ny;
+    for (int q = 0; q < 8; ++q) {
+      const ShapeAt s = shape_at(g, a, q);
+      acc += w * (coef[e + q * g.E] * s.N * s.N +
+                  m.Gcl * (s.gx * s.gx + s.gy * s.gy + s.gz * s.gz));
+    }
+  });
+  D[n] = acc;
+}
+
+// AT2 right-hand side at node n: b_n = sum w 2 H_q N_a.
+__host__ __device__ inline void node_phase_rhs(const Grid3 &g, int n, const double *H,
+                                               double *b) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  double acc = 0.0;
+  for_node_elements(g, n, [&](int ie, int je, int ke, int a) {
+    const int e = ie + je * g.nx + ke * g.nx * g.ny;
+    for (int q = 0; q < 8; ++q) acc += w * 2.0 * H[e + q * g.E] * shape_at(g, a, q).N;
+  });
+  b[n] = acc;
+}
+
+// Mass coefficient of the phase block at the points of element e: the AT2
+// coefficient c = Gc/l + 2H (Section 2), or with trial = 1 that of the
+// trial block K_dd + K~ (Section 3.4): c - c_S at gated points, c_S = 8
+// (1 - d_q)^2 / g(d_q) psi_S, raised to theta c where it falls below
+// (floor = 1) or kept as it is (floor = 0).  Returns the gated points below
+// theta c.
+__host__ __device__ inline int elem_phase_coef(const Grid3 &g, const Mat3 &m, int e, int trial,
+                                               double theta, int floor, const double *H,
+                                               const double *psi_s, const uint16_t *flags,
+                                               const double *d, double *coef) {
+  const unsigned fl = trial ? flags[e] : 0u;
+  double de[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (fl >> 8) {
+    const int ke = e / (g.nx * g.ny), r = e - ke * g.nx * g.ny, je = r / g.nx,
+              ie = r - je * g.nx;
+    gather_corners(g, ie, je, ke, d, 1, de);
+  }
+  int below = 0;
+  for (int q = 0; q < 8; ++q) {
+    const double c = m.Gc_l + 2.0 * H[e + q * g.E];
+    double ct = c;
+    if ((fl >> (q + 8)) & 1u) {
+      const double om = 1.0 - interp_at(g, q, de);
+      const double cS = 8.0 * om * om / (om * om + m.eta) * psi_s[e + q * g.E];
+      ct = c - cS;
+      if (ct < theta * c) {
+        if (floor) ct = theta * c;
+        ++below;
+      }
+    }
+    coef[e + q * g.E] = ct;
+  }
+  return below;
+}
+
 // Quadrature-point update of element e (Sections 2, 3.5): H = max(H_prev,
 // psi+), the scheme part psi_S, and flags bit q = tr eps > 0 at point q,
 // bit 8 + q = the softening gate at point q (a fixed-stress scheme, psi+
@@ -505,7 +604,8 @@ inline pf_status make_mat(const pf_material *mat, Mat3 *m) {
     return PF_E_INVALID_ARG;
   const double mu = mat->E / (2.0 * (1.0 + mat->nu));
   const double lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
-  *m = Mat3{lam, mu, lam + 2.0 * mu / 3.0, mat->Gc * mat->l, mat->eta, mat->split};
+  *m = Mat3{lam,       mu,         lam + 2.0 * mu / 3.0, mat->Gc * mat->l,
+            mat->eta,  mat->split, mat->Gc / mat->l};
   return PF_OK;
 }
 

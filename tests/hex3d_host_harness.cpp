@@ -74,4 +74,43 @@ int h3_predictor(const pf3d_mesh *mesh, const pf_material *mat, const double *d,
   return PF_OK;
 }
 
+int h3_tangent_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                    const double *d, double *D) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  replay(g.N, [&](int n) { node_tangent_diag(g, m, n, u, d, D); });
+  return PF_OK;
+}
+
+int h3_phase_diag(const pf3d_mesh *mesh, const pf_material *mat, const double *coef,
+                  double *D) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  replay(g.N, [&](int n) { node_phase_diag(g, m, n, coef, D); });
+  return PF_OK;
+}
+
+int h3_phase_rhs(const pf3d_mesh *mesh, const double *H, double *b) {
+  Grid3 g;
+  if (make_grid(mesh, &g) != PF_OK) return PF_E_INVALID_ARG;
+  replay(g.N, [&](int n) { node_phase_rhs(g, n, H, b); });
+  return PF_OK;
+}
+
+int h3_phase_coef(const pf3d_mesh *mesh, const pf_material *mat, int trial, double theta,
+                  int floor, const double *H, const double *psi_s, const uint16_t *flags,
+                  const double *d, double *coef, long long *below) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  long long nb = 0;
+  replay(g.E, [&](int e) {
+    nb += elem_phase_coef(g, m, e, trial, theta, floor, H, psi_s, flags, d, coef);
+  });
+  *below = nb;
+  return PF_OK;
+}
+
 }  // extern "C"

@@ -119,3 +119,45 @@ def test_qp_update_3d(gpu_lib, scheme, split):
     Hhat_orc = np.maximum(np.maximum(Hprev, psi),
                           predicted_energy(psi, ps, om.interp(d), m.eta, om.interp(dd), gate))
     np.testing.assert_allclose(host(Hh).reshape(8, E).T, Hhat_orc, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_diagonals_rhs_and_coefficients_3d(gpu_lib, split):
+    import torch
+    from oracle.assembly import trial_coefficient
+    from oracle.constitutive import coupling_coefficient
+    b, ops, om, rng = setup(gpu_lib, (9, 7, 5), 31, split)
+    m = b.material
+    cons = (H3.VD3D if split == 0 else H3.Spectral3D)(m.E, m.nu)
+    N, E = om.n_nodes, om.conn.shape[0]
+    u = rng.normal(size=3 * N) * 5e-4
+    d = rng.uniform(0, 0.9, size=N)
+    coef = rng.uniform(0.1, 50.0, size=(E, 8))
+    Hq = rng.uniform(0.0, 30.0, size=(E, 8))
+    Dt = torch.full((3 * N,), float("nan"), dtype=torch.float64, device="cuda")
+    Dp = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
+    bb = torch.full_like(Dp, float("nan"))
+    ops.tangent_diag(dev(soa(u)), dev(d), Dt)
+    ops.phase_diag(dev(coef.T.reshape(-1)), Dp)
+    ops.phase_rhs(dev(Hq.T.reshape(-1)), bb)
+    np.testing.assert_allclose(host(Dt), soa(H3.tangent_matrix(om, cons, u, d, m.eta).diagonal()),
+                               rtol=1e-12)
+    np.testing.assert_allclose(host(Dp), H3.phase_matrix(om, coef, m.Gc, m.l).diagonal(),
+                               rtol=1e-12)
+    np.testing.assert_allclose(host(bb), H3.phase_rhs(om, Hq), rtol=1e-12)
+    # trial coefficient from the kernel's own QP update (S3, floored)
+    parts = cons.parts(om.strain(u))
+    psi = parts["psi_plus"]
+    Hprev = np.where(rng.uniform(size=psi.shape) < 0.5, psi * 0.5, psi * 1.5)
+    H = torch.full((8 * E,), float("nan"), dtype=torch.float64, device="cuda")
+    PS = torch.full_like(H, float("nan"))
+    fl = torch.zeros(E, dtype=torch.int16, device="cuda")
+    ops.qp_update(3, 0.0, 0.95, dev(soa(u)), dev(d), dev(Hprev.T.reshape(-1)), H, PS, fl)
+    co = torch.full_like(H, float("nan"))
+    ops.phase_coef(H, co, trial=(0.3, 1, PS, fl, dev(d)))
+    Hn = np.maximum(Hprev, psi)
+    gate = (psi > 0.0) & (psi > Hprev) & (om.interp(d) < 0.95)
+    c = m.Gc / m.l + 2.0 * Hn
+    ct, _ = trial_coefficient(c, coupling_coefficient(om.interp(d), m.eta, psi), gate, 0.3)
+    np.testing.assert_allclose(host(co).reshape(8, E).T, ct, rtol=1e-11,
+                               atol=1e-12 * np.abs(c).max())

@@ -24,7 +24,8 @@ import pytest
 
 import paper_2209_07969_amd as pf
 from oracle import hex3d as H3
-from oracle.constitutive import predicted_energy
+from oracle.assembly import trial_coefficient
+from oracle.constitutive import coupling_coefficient, predicted_energy
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = "/opt/rocm/bin/hipcc"
@@ -54,8 +55,14 @@ def harness(tmp_path_factory):
     lib.h3_qp_update.argtypes = [M3, MT, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  P, P, P, P, P, P, ctypes.POINTER(ctypes.c_longlong)]
     lib.h3_predictor.argtypes = [M3, MT, P, P, P, P, P, P]
+    lib.h3_tangent_diag.argtypes = [M3, MT, P, P, P]
+    lib.h3_phase_diag.argtypes = [M3, MT, P, P]
+    lib.h3_phase_rhs.argtypes = [M3, P, P]
+    lib.h3_phase_coef.argtypes = [M3, MT, ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P, P,
+                                  P, P, ctypes.POINTER(ctypes.c_longlong)]
     for f in ("h3_internal_force", "h3_tangent_apply", "h3_phase_apply", "h3_qp_update",
-              "h3_predictor"):
+              "h3_predictor", "h3_tangent_diag", "h3_phase_diag", "h3_phase_rhs",
+              "h3_phase_coef"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -252,3 +259,68 @@ def test_spectral_plane_fields(harness):
     assert harness.h3_tangent_apply(mesh, mat, uG.ptr, dG.ptr, pG.ptr, q.ptr) == 0
     np.testing.assert_allclose(R.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
     np.testing.assert_allclose(q.val, q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
+
+
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("shape", [(9, 7, 5), (1, 1, 1)])
+def test_diagonals_and_rhs(harness, shape, split):
+    mesh, mat, om, rng = setup(*shape, seed=31 + sum(shape), split=split)
+    cons = oracle_split(split)
+    N, E = om.n_nodes, om.conn.shape[0]
+    u = rng.normal(size=3 * N) * 1e-3
+    d = rng.uniform(0, 1, size=N)
+    coef = rng.uniform(0.1, 50.0, size=(E, 8))
+    Hq = rng.uniform(0.0, 30.0, size=(E, 8))
+    Dt_orc = soa(H3.tangent_matrix(om, cons, u, d, MAT["eta"]).diagonal())
+    Dp_orc = H3.phase_matrix(om, coef, MAT["Gc"], MAT["l"]).diagonal()
+    b_orc = H3.phase_rhs(om, Hq)
+    Dt, Dp, b = out_f64(3 * N), out_f64(N), out_f64(N)
+    assert harness.h3_tangent_diag(mesh, mat, Guarded(soa(u)).ptr, Guarded(d).ptr, Dt.ptr) == 0
+    assert harness.h3_phase_diag(mesh, mat, Guarded(coef.T.reshape(-1)).ptr, Dp.ptr) == 0
+    assert harness.h3_phase_rhs(mesh, Guarded(Hq.T.reshape(-1)).ptr, b.ptr) == 0
+    for arr in (Dt, Dp, b):
+        assert np.all(np.isfinite(arr.val)) and arr.guards_intact()
+    np.testing.assert_allclose(Dt.val, Dt_orc, rtol=1e-12)
+    np.testing.assert_allclose(Dp.val, Dp_orc, rtol=1e-12)
+    np.testing.assert_allclose(b.val, b_orc, rtol=1e-12)
+
+
+@pytest.mark.parametrize("floor", [1, 0])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+def test_phase_coefficients(harness, scheme, floor):
+    mesh, mat, om, rng = setup(9, 7, 5, seed=200 + scheme)
+    cons = oracle_split(0)
+    N, E = om.n_nodes, om.conn.shape[0]
+    # this scale puts some gated points below theta c and leaves others above
+    u = rng.normal(size=3 * N) * 5e-4
+    d = rng.uniform(0, 0.9, size=N)
+    parts = cons.parts(om.strain(u))
+    psi = parts["psi_plus"]
+    Hprev = np.where(rng.uniform(size=psi.shape) < 0.5, psi * 0.5, psi * 1.5)
+    uG, dG, HpG = Guarded(soa(u)), Guarded(d), Guarded(Hprev.T.reshape(-1))
+    Hout, PS = out_f64(8 * E), out_f64(8 * E)
+    fl = Guarded(n=E, dtype=np.uint16, guard=SENT16, init=0)
+    ng = ctypes.c_longlong()
+    assert harness.h3_qp_update(mesh, mat, scheme, 0.0, 0.95, uG.ptr, dG.ptr, HpG.ptr, Hout.ptr,
+                                PS.ptr, fl.ptr, ctypes.byref(ng)) == 0
+    H = np.maximum(Hprev, psi)
+    gate = (psi > 0.0) & (psi > Hprev) & (om.interp(d) < 0.95)
+    ps = {1: parts["psi_vol"], 2: parts["psi_dev"], 3: psi}[scheme]
+    c = MAT["Gc"] / MAT["l"] + 2.0 * H
+    cS = coupling_coefficient(om.interp(d), MAT["eta"], ps)
+    theta = 0.3
+    ct_orc, hits = trial_coefficient(c, cS, gate, theta, floor=bool(floor))
+    co, below = out_f64(8 * E), ctypes.c_longlong(-1)
+    assert harness.h3_phase_coef(mesh, mat, 1, theta, floor, Hout.ptr, PS.ptr, fl.ptr, dG.ptr,
+                                 co.ptr, ctypes.byref(below)) == 0
+    assert np.all(np.isfinite(co.val)) and co.guards_intact()
+    np.testing.assert_allclose(co.val.reshape(8, E).T, ct_orc, rtol=1e-12,
+                               atol=1e-12 * np.abs(c).max())
+    assert below.value == hits
+    assert 0 < hits < gate.sum()
+    # without the trial: the AT2 coefficient on every point
+    c0 = out_f64(8 * E)
+    assert harness.h3_phase_coef(mesh, mat, 0, theta, floor, Hout.ptr, PS.ptr, fl.ptr, dG.ptr,
+                                 c0.ptr, ctypes.byref(below)) == 0
+    np.testing.assert_allclose(c0.val.reshape(8, E).T, c, rtol=1e-14)
+    assert below.value == 0
