@@ -114,6 +114,55 @@ pf_status pf3d_op_phase_coef(const pf3d_mesh *mesh, const pf_material *mat, int3
                              const uint16_t *flags, const double *d, double *coef,
                              void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * 3-D load steps (Sections 3.1, 3.3-3.5 on hexahedra): the staggered loop of
+ * pf_load_step with these operators, in FP64 with Jacobi PCG for every
+ * linear solve, AT2 with the history field and, for S1/S2/S3, the floored
+ * trial block with predict -> correct.  pf3d_create takes pf_solver_opts
+ * (NULL: defaults) and refuses, with PF_E_INVALID_ARG, precision other than
+ * PF_FP64, precond other than PF_PC_JACOBI, phase_model AT1, the literal
+ * trial readings, and the 2-D checks' bad values.  The context owns its
+ * device memory (hipMalloc) and runs on hip_stream; calls on one context
+ * must not overlap.  Host arrays are copied before the call returns.
+ * Every reduction is summed per block by a fixed tree and over the blocks
+ * in order on the host, so results are deterministic.
+ * ------------------------------------------------------------------------- */
+typedef struct pf3d_ctx pf3d_ctx;
+
+pf_status pf3d_create(const pf3d_mesh *mesh, const pf_material *mat,
+                      const pf_solver_opts *opts, void *hip_stream, pf3d_ctx **out);
+
+/* Frees every buffer; NULL is accepted. */
+pf_status pf3d_destroy(pf3d_ctx *ctx);
+
+/* Displacement Dirichlet data of one group (0 <= group < 8): component
+ * comp[k] (0 = x, 1 = y, 2 = z) of node node[k] is load_factor *
+ * value_per_unit_load[k].  Replaces the group's previous data.  Group 1 is
+ * the loaded group whose reaction the step statistics carry (group 0 if
+ * group 1 is empty).  Errors: PF_E_INVALID_ARG for out-of-range nodes,
+ * components or groups, PF_E_NONFINITE for non-finite values. */
+pf_status pf3d_set_dirichlet_u(pf3d_ctx *ctx, int32_t group, int64_t n, const int64_t *node,
+                               const int8_t *comp, const double *value_per_unit_load);
+
+/* Phase-field Dirichlet data: node[k] keeps value[k] (imposed at once). */
+pf_status pf3d_set_dirichlet_d(pf3d_ctx *ctx, int64_t n, const int64_t *node,
+                               const double *value);
+
+/* One load step at load_factor, committed at the end (H_n = max(H_{n-1},
+ * Psi+(u_n))).  stats (may be NULL): counts as for pf_load_step, force[0]
+ * and force[1] the x and y reactions of the loaded group (all three from
+ * pf3d_reaction_force).  Returns PF_E_NOT_CONVERGED, not fatal, if the loop
+ * ended at max_stag or a Newton solve at max_newton. */
+pf_status pf3d_load_step(pf3d_ctx *ctx, double load_factor, pf_step_stats *stats);
+
+/* Reaction of a Dirichlet group at the committed state: the internal force
+ * summed over its entries per component, force[3] = (x, y, z). */
+pf_status pf3d_reaction_force(pf3d_ctx *ctx, int32_t group, double force[3]);
+
+/* Committed state to host arrays (each may be NULL): u [3N] (x, y, z
+ * planes), d [N], H [8E] (plane q = point q of every element). */
+pf_status pf3d_get_state(pf3d_ctx *ctx, double *u, double *d, double *H);
+
 #ifdef __cplusplus
 }
 #endif

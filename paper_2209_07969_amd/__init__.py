@@ -37,7 +37,9 @@ EXPORTED = [
 EXPORTED_3D = [
     "pf3d_op_internal_force", "pf3d_op_tangent_apply", "pf3d_op_phase_apply",
     "pf3d_op_qp_update", "pf3d_op_predictor", "pf3d_op_tangent_diag", "pf3d_op_phase_diag",
-    "pf3d_op_phase_rhs", "pf3d_op_phase_coef",
+    "pf3d_op_phase_rhs", "pf3d_op_phase_coef", "pf3d_create", "pf3d_destroy",
+    "pf3d_set_dirichlet_u", "pf3d_set_dirichlet_d", "pf3d_load_step", "pf3d_reaction_force",
+    "pf3d_get_state",
 ]
 
 
@@ -145,6 +147,14 @@ def load_library(path: str = LIB_PATH):
     lib.pf3d_op_phase_diag.argtypes = [M3, MT, P, P, P]
     lib.pf3d_op_phase_rhs.argtypes = [M3, P, P, P]
     lib.pf3d_op_phase_coef.argtypes = [M3, MT, c_int32, c_double, c_int32, P, P, P, P, P, P]
+    lib.pf3d_create.argtypes = [M3, MT, POINTER(SolverOpts), P, POINTER(P)]
+    lib.pf3d_destroy.argtypes = [P]
+    lib.pf3d_set_dirichlet_u.argtypes = [P, c_int32, c_int64, POINTER(c_int64), POINTER(c_int8),
+                                         dp]
+    lib.pf3d_set_dirichlet_d.argtypes = [P, c_int64, POINTER(c_int64), dp]
+    lib.pf3d_load_step.argtypes = [P, c_double, POINTER(StepStats)]
+    lib.pf3d_reaction_force.argtypes = [P, c_int32, dp]
+    lib.pf3d_get_state.argtypes = [P, dp, dp, dp]
     for name in EXPORTED + EXPORTED_3D:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
@@ -526,6 +536,87 @@ class Hex3DOps:
             self._stream()), "pf3d_op_phase_coef")
 
 
+class Hex3DContext:
+    """A 3-D load history on a box of trilinear hexahedra (pf3d_create):
+    ``problem`` has the attributes of ``workloads.Problem3D``.  FP64 with
+    Jacobi PCG, AT2 with the history field; ``scheme`` ST or S1/S2/S3 with
+    the floored trial block."""
+
+    def __init__(self, problem, scheme=ST, stream=None, **overrides):
+        require_device()
+        import torch
+        self.lib = load_library()
+        p = problem
+        self.p = p
+        mesh = Mesh3Desc(int(p.nx), int(p.ny), int(p.nz), float(p.lx), float(p.ly), float(p.lz))
+        m = p.material
+        mat = MaterialDesc(m.E, m.nu, m.Gc, m.l, m.eta, int(m.split))
+        o = default_opts()
+        o.scheme = int(scheme)
+        for name in ("tol_stag", "tol_pcg", "tol_newton", "max_stag", "max_newton",
+                     "psi_crit", "d_gate", "trial_floor"):
+            if hasattr(p, name):
+                setattr(o, name, getattr(p, name))
+        for k, v in overrides.items():
+            setattr(o, k, v)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = c_void_p()
+        st = self.lib.pf3d_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(o),
+                                  c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise PhaseFieldError(st, "pf3d_create failed: " +
+                                  self.lib.pf_status_string(st).decode())
+        self.h = h
+        self.N = (p.nx + 1) * (p.ny + 1) * (p.nz + 1)
+        self.E = p.nx * p.ny * p.nz
+        for gi, grp in enumerate(p.dir_u):
+            n = np.ascontiguousarray(grp.nodes, dtype=np.int64)
+            c = np.ascontiguousarray(grp.comps, dtype=np.int8)
+            v = np.ascontiguousarray(grp.values, dtype=np.float64)
+            self._check(self.lib.pf3d_set_dirichlet_u(self.h, gi, n.size, _ptr(n, c_int64),
+                                                      _ptr(c, c_int8), _ptr(v, c_double)),
+                        "pf3d_set_dirichlet_u")
+        n = np.ascontiguousarray(p.dir_d_nodes, dtype=np.int64)
+        v = np.ascontiguousarray(p.dir_d_values, dtype=np.float64)
+        self._check(self.lib.pf3d_set_dirichlet_d(self.h, n.size, _ptr(n, c_int64),
+                                                  _ptr(v, c_double)), "pf3d_set_dirichlet_d")
+
+    def _check(self, st, what):
+        if st != 0:
+            raise PhaseFieldError(st, f"{what}: {self.lib.pf_status_string(st).decode()}")
+
+    def load_step(self, lam, allow_not_converged=True):
+        st = StepStats()
+        s = self.lib.pf3d_load_step(self.h, float(lam), ctypes.byref(st))
+        if s != 0 and not (allow_not_converged and s == STATUS_NOT_CONVERGED):
+            self._check(s, "pf3d_load_step")
+        return st.as_dict()
+
+    def reaction_force(self, group=1):
+        f = np.zeros(3)
+        self._check(self.lib.pf3d_reaction_force(self.h, group, _ptr(f, c_double)),
+                    "pf3d_reaction_force")
+        return f
+
+    def get_state(self):
+        u, d, H = np.zeros(3 * self.N), np.zeros(self.N), np.zeros(8 * self.E)
+        self._check(self.lib.pf3d_get_state(self.h, _ptr(u, c_double), _ptr(d, c_double),
+                                            _ptr(H, c_double)), "pf3d_get_state")
+        return u.reshape(3, self.N), d, H.reshape(8, self.E)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pf3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Several contexts advanced together (each should own a HIP stream, e.g.
     Context(..., stream=torch.cuda.Stream().cuda_stream)).  shared=True runs
@@ -570,5 +661,5 @@ class Batch:
             pass
 
 
-__all__ = ["Batch", "Context", "Hex3DOps", "load_library", "require_device", "default_opts", "PhaseFieldError",
+__all__ = ["Batch", "Context", "Hex3DContext", "Hex3DOps", "load_library", "require_device", "default_opts", "PhaseFieldError",
            "ST", "S1", "S2", "S3", "FP64", "MIXED", "EXPORTED"]

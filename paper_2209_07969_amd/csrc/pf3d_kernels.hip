@@ -7,10 +7,14 @@
 
 #include "../../include/phasefield3d.h"
 #include "pf3d_ops.h"
+#include "pf3d_solver.h"
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <memory>
+#include <vector>
 
 using namespace pf3d;
 
@@ -81,7 +85,108 @@ pf_status launched() {
   return hipGetLastError() == hipSuccess ? PF_OK : PF_E_HIP;
 }
 
+// ---- the load step's device backend
+
+template <class F>
+__global__ void __launch_bounds__(kTpb3) k3_each(F f, int count) {
+  const int i = grid_index(blockIdx.x, threadIdx.x);
+  if (i < count) f(i);
+}
+
+// Per-block sum of f over the block's indices by a fixed binary tree in LDS
+// (the order the host replay reproduces); one partial per block.
+template <class F>
+__global__ void __launch_bounds__(kTpb3) k3_sum(F f, int count, double *part) {
+  __shared__ double v[kTpb3];
+  const int i = grid_index(blockIdx.x, threadIdx.x);
+  v[threadIdx.x] = i < count ? f(i) : 0.0;
+  __syncthreads();
+  for (int h = kTpb3 / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) v[threadIdx.x] += v[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Runs the solver's per-index functors as kernels on one stream.  Block
+// partials of a sum come back through a pinned buffer and are added on the
+// host in block order.  The first failing HIP call is kept in err; later
+// calls still run but the context reports PF_E_HIP.
+struct DeviceBackend {
+  hipStream_t s = nullptr;
+  double *part = nullptr, *part_h = nullptr;
+  int part_cap = 0;
+  hipError_t err = hipSuccess;
+
+  void note(hipError_t e) {
+    if (err == hipSuccess && e != hipSuccess) err = e;
+  }
+  bool reserve(int blocks) {
+    if (blocks <= part_cap) return true;
+    if (part) note(hipFree(part));
+    if (part_h) note(hipHostFree(part_h));
+    part = part_h = nullptr;
+    part_cap = 0;
+    if (hipMalloc((void **)&part, blocks * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&part_h, blocks * sizeof(double)) != hipSuccess) {
+      note(hipErrorOutOfMemory);
+      return false;
+    }
+    part_cap = blocks;
+    return true;
+  }
+  void *alloc(size_t bytes) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    note(hipMemsetAsync(p, 0, bytes, s));
+    return p;
+  }
+  void release(void *p) {
+    if (p) note(hipFree(p));
+  }
+  void upload(void *dst, const void *src, size_t n) {
+    note(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s));
+    note(hipStreamSynchronize(s));
+  }
+  void download(void *dst, const void *src, size_t n) {
+    note(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+    note(hipStreamSynchronize(s));
+  }
+  template <class F>
+  void each(int count, const F &f) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k3_each<F>, dim3(grid_blocks(count)), dim3(kTpb3), 0, s, f, count);
+    note(hipGetLastError());
+  }
+  template <class F>
+  double sum(int count, const F &f) {
+    const int nb = grid_blocks(count);
+    if (count <= 0 || !reserve(nb)) return 0.0;
+    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, s, f, count, part);
+    note(hipGetLastError());
+    note(hipMemcpyAsync(part_h, part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    note(hipStreamSynchronize(s));
+    if (err != hipSuccess) return 0.0;
+    double total = 0.0;
+    for (int b = 0; b < nb; ++b) total += part_h[b];
+    return total;
+  }
+  ~DeviceBackend() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (part) (void)hipFree(part);
+    if (part_h) (void)hipHostFree(part_h);
+  }
+};
+
 }  // namespace
+
+struct pf3d_ctx {
+  pf3d::Grid3 g{};
+  DeviceBackend be;
+  std::unique_ptr<pf3d::Solver3<DeviceBackend>> sol;
+  int load_group = 1;
+  int gsize[pf3d::kGroups3] = {};
+};
 
 extern "C" {
 
@@ -195,6 +300,106 @@ pf_status pf3d_op_phase_coef(const pf3d_mesh *mesh, const pf_material *mat, int3
                      static_cast<hipStream_t>(hip_stream), g, m, trial, theta, floor, H, psi_s,
                      flags, d, coef);
   return launched();
+}
+
+pf_status pf3d_create(const pf3d_mesh *mesh, const pf_material *mat,
+                      const pf_solver_opts *opts, void *hip_stream, pf3d_ctx **out) {
+  if (!out) return PF_E_INVALID_ARG;
+  *out = nullptr;
+  Grid3 g;
+  Mat3 m;
+  pf_solver_opts o;
+  if (opts) o = *opts;
+  else pf_default_opts(&o);
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK || check_opts3(&o) != PF_OK)
+    return PF_E_INVALID_ARG;
+  auto *c = new pf3d_ctx();
+  c->g = g;
+  c->be.s = static_cast<hipStream_t>(hip_stream);
+  c->sol.reset(new Solver3<DeviceBackend>(c->be, g, m, o));
+  const bool ok = c->sol->init() && c->be.reserve(grid_blocks(std::max(3 * g.N, 8 * g.E)));
+  if (!ok || c->be.err != hipSuccess) {
+    const pf_status s = c->be.err == hipErrorOutOfMemory || !ok ? PF_E_OOM : PF_E_HIP;
+    pf3d_destroy(c);
+    return s;
+  }
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf3d_destroy(pf3d_ctx *c) {
+  delete c;
+  return PF_OK;
+}
+
+pf_status pf3d_set_dirichlet_u(pf3d_ctx *c, int32_t group, int64_t n, const int64_t *node,
+                               const int8_t *comp, const double *value_per_unit_load) {
+  if (!c || group < 0 || group >= kGroups3 || n < 0 ||
+      (n > 0 && (!node || !comp || !value_per_unit_load)))
+    return PF_E_INVALID_ARG;
+  for (int64_t k = 0; k < n; ++k) {
+    if (node[k] < 0 || node[k] >= c->g.N || comp[k] < 0 || comp[k] > 2) return PF_E_INVALID_ARG;
+    if (!std::isfinite(value_per_unit_load[k])) return PF_E_NONFINITE;
+  }
+  if (!c->sol->set_dirichlet_u(group, n, node, comp, value_per_unit_load)) return PF_E_OOM;
+  c->gsize[group] = (int)n;
+  return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
+}
+
+pf_status pf3d_set_dirichlet_d(pf3d_ctx *c, int64_t n, const int64_t *node, const double *value) {
+  if (!c || n < 0 || (n > 0 && (!node || !value))) return PF_E_INVALID_ARG;
+  for (int64_t k = 0; k < n; ++k) {
+    if (node[k] < 0 || node[k] >= c->g.N) return PF_E_INVALID_ARG;
+    if (!std::isfinite(value[k])) return PF_E_NONFINITE;
+  }
+  if (!c->sol->set_dirichlet_d(n, node, value)) return PF_E_OOM;
+  return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
+}
+
+pf_status pf3d_load_step(pf3d_ctx *c, double load_factor, pf_step_stats *stats) {
+  if (!c) return PF_E_INVALID_ARG;
+  if (!std::isfinite(load_factor)) return PF_E_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  Counts3 st;
+  c->sol->load_step(load_factor, &st);
+  double f[3] = {0.0, 0.0, 0.0};
+  const int grp = c->gsize[1] > 0 ? 1 : 0;
+  c->sol->reaction(grp, f);
+  if (c->be.err != hipSuccess) return PF_E_HIP;
+  if (!std::isfinite(st.r_stag)) return PF_E_NONFINITE;
+  if (stats) {
+    *stats = pf_step_stats{};
+    stats->n_stag = st.n_stag;
+    stats->n_newton = st.n_newton;
+    stats->n_trial = st.n_trial;
+    stats->n_dsolve = st.n_dsolve;
+    stats->n_cg_u = st.n_cg_u;
+    stats->n_cg_d = st.n_cg_d;
+    stats->n_cg_trial = st.n_cg_trial;
+    stats->gated_max = st.gated_max;
+    stats->floor_hits = st.floor_hits;
+    stats->r_stag = st.r_stag;
+    stats->force[0] = f[0];
+    stats->force[1] = f[1];
+    stats->time_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->dof_updates = st.dof_updates;
+    stats->converged = st.converged ? 1 : 0;
+    stats->cg_not_converged = (int32_t)st.cg_not_converged;
+  }
+  return st.converged ? PF_OK : PF_E_NOT_CONVERGED;
+}
+
+pf_status pf3d_reaction_force(pf3d_ctx *c, int32_t group, double force[3]) {
+  if (!c || !force || group < 0 || group >= kGroups3) return PF_E_INVALID_ARG;
+  c->sol->reaction(group, force);
+  return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
+}
+
+pf_status pf3d_get_state(pf3d_ctx *c, double *u, double *d, double *H) {
+  if (!c) return PF_E_INVALID_ARG;
+  c->sol->get_state(u, d, H);
+  return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
 }
 
 }  // extern "C"

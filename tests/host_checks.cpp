@@ -77,6 +77,21 @@ int main() {
   CHECK(pf3d_op_phase_apply(&m3, &mat, nullptr, x, x, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf3d_op_qp_update(&m3, &mat, 9, -1.0, 0.95, x, x, x, x, x, fl, nullptr) ==
         PF_E_INVALID_ARG);
+  // 3-D load steps: options outside the path and null handles are refused
+  pf3d_ctx *c3 = nullptr;
+  pf_solver_opts o3;
+  pf_default_opts(&o3);
+  o3.precision = PF_MIXED;
+  CHECK(pf3d_create(&m3, &mat, &o3, nullptr, &c3) == PF_E_INVALID_ARG && c3 == nullptr);
+  pf_default_opts(&o3);
+  o3.phase_model = PF_AT1_PENALTY;
+  CHECK(pf3d_create(&m3, &mat, &o3, nullptr, &c3) == PF_E_INVALID_ARG && c3 == nullptr);
+  CHECK(pf3d_create(&m3bad[0], &mat, nullptr, nullptr, &c3) == PF_E_INVALID_ARG);
+  CHECK(pf3d_load_step(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf3d_reaction_force(nullptr, 1, x) == PF_E_INVALID_ARG);
+  CHECK(pf3d_get_state(nullptr, x, x, x) == PF_E_INVALID_ARG);
+  CHECK(pf3d_set_dirichlet_d(nullptr, 0, nullptr, nullptr) == PF_E_INVALID_ARG);
+  CHECK(pf3d_destroy(nullptr) == PF_OK);
 
   CHECK(pf_load_step(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf_staggered_iterate(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);

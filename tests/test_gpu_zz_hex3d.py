@@ -161,3 +161,44 @@ def test_diagonals_rhs_and_coefficients_3d(gpu_lib, split):
     ct, _ = trial_coefficient(c, coupling_coefficient(om.interp(d), m.eta, psi), gate, 0.3)
     np.testing.assert_allclose(host(co).reshape(8, E).T, ct, rtol=1e-11,
                                atol=1e-12 * np.abs(c).max())
+
+
+@pytest.mark.parametrize("case", ["cube_s1", "cube_unload_s1", "slab_st", "slab_s3", "slab2_s1",
+                                  "shear_s1"])
+def test_load_steps_3d(gpu_lib, case):
+    """pf3d_load_step against the 3-D oracle under the 2-D parity protocol."""
+    import dataclasses
+
+    import workloads as W
+    from oracle.hex3d import Oracle3D
+    if case == "cube_s1":
+        p, scheme = W.uniaxial_bar3d(n=2, l=0.03, du=5e-3, steps=4), 1
+    elif case == "cube_unload_s1":
+        p = W.uniaxial_bar3d(n=2, l=0.03, du=5e-3, steps=5)
+        p = dataclasses.replace(p, loads=np.array([5e-3, 1e-2, 1.4e-2, 7e-3, 1.2e-2, 1.5e-2]))
+        scheme = 1
+    elif case == "shear_s1":
+        p, scheme = W.slab_from_panel(W.shear_panel(n=8, l=0.2, du=4e-3, steps=2), 1, 0.1), 1
+    elif case == "slab2_s1":
+        p, scheme = W.slab_from_panel(W.tension_panel(n=12, l=0.2, du=2e-3, steps=2), 2, 0.1), 1
+    else:
+        p = W.slab_from_panel(W.tension_panel(n=8, l=0.2, du=2e-3, steps=2), 1, 0.1)
+        scheme = 0 if case == "slab_st" else 3
+    ctx = gpu_lib.Hex3DContext(p, scheme=scheme)
+    orc = Oracle3D(p, scheme)
+    forces, oforces = [], []
+    for lam in p.loads:
+        sg = ctx.load_step(float(lam))
+        so = orc.load_step(float(lam))
+        assert sg["converged"] and so.converged
+        assert abs(sg["n_stag"] - so.n_stag) <= 1
+        forces.append(ctx.reaction_force(p.load_group)[p.load_comp])
+        oforces.append(so.force)
+        if sg["n_stag"] == so.n_stag:
+            u, d, _ = ctx.get_state()
+            ou = np.stack([orc.u[0::3], orc.u[1::3], orc.u[2::3]])
+            assert np.linalg.norm(u - ou) <= 1e-7 * np.linalg.norm(ou)
+            assert np.abs(d - orc.d).max() <= 1e-5
+    ctx.close()
+    peak = max(abs(x) for x in oforces)
+    np.testing.assert_allclose(forces, oforces, rtol=0, atol=1e-7 * peak)
