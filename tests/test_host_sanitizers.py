@@ -1,10 +1,14 @@
-"""The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer.
+
+1. The library
 (not GPU): a build whose host objects carry both sanitizers (device code is
 built as usual) runs tests/host_checks.cpp, the C ABI's device-free paths
 (option validation, status strings, null-handle argument checks, mesh size
 limits, the 3-D operators' argument checks).  The
 instrumented build takes a few minutes, so the test runs only with
-PF_SANITIZE=1 in the environment."""
+PF_SANITIZE=1 in the environment.
+2. The 3-D kernels' host replay (every index the device grids compute),
+quick enough for every run."""
 import os
 import shutil
 import subprocess
@@ -46,3 +50,23 @@ def test_c_abi_host_paths_under_asan_ubsan():
         assert out.returncode == 0, out.stdout + out.stderr
         assert "runtime error" not in out.stderr and "AddressSanitizer" not in out.stderr
         assert "host checks: ok" in out.stdout
+
+
+def test_hex3d_replay_indices_under_asan_ubsan(tmp_path):
+    """Every 3-D kernel's grid, replayed on the host with each array in a
+    heap buffer of exactly its size, under AddressSanitizer: an index the
+    device grid would compute outside a buffer is reported here, before any
+    device run (tests/hex3d_asan_main.cpp).  Host-only build, a few seconds,
+    so it is part of the default run."""
+    if not os.path.exists(HIPCC):
+        pytest.skip("ROCm compiler not found")
+    exe = str(tmp_path / "hex3d_asan")
+    subprocess.run([HIPCC, "-x", "hip", "--offload-arch=gfx950", "--offload-host-only", "-O1",
+                    "-g", "-std=c++17", "-Xarch_host", "-fsanitize=address,undefined",
+                    "-Xarch_host", "-fno-omit-frame-pointer", "-I" + os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "hex3d_asan_main.cpp"), "-o", exe], check=True)
+    env = dict(os.environ, UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "AddressSanitizer" not in out.stderr and "runtime error" not in out.stderr
+    assert "hex3d asan: ok" in out.stdout
