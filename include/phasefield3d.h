@@ -1,16 +1,17 @@
-/* phasefield3d.h - C ABI of the 3-D operators: trilinear hexahedra (Q1,
- * 2x2x2 Gauss) on a structured box, the volumetric-deviatoric or the
- * spectral split of Section 2 with the full 3-D strain, and the AT2 phase
- * operator.  They are
- * the element and node operators of the 2-D path (internal force, tangent
- * apply and diagonal, phase apply, diagonal, right-hand side and mass
- * coefficients, quadrature-point update, predictor) on a mesh of hexahedra,
+/* phasefield3d.h - C ABI of the 3-D path: trilinear hexahedra (Q1, 2x2x2
+ * Gauss) on a structured box, the volumetric-deviatoric or the spectral
+ * split of Section 2 with the full 3-D strain, and the AT2 phase operator,
  * as in the paper's one-element-thick slab (Section 4) or a full 3-D panel.
+ * Two parts: the element and node operators of the 2-D path (internal
+ * force, tangent apply and diagonal, phase apply, diagonal, right-hand side
+ * and mass coefficients, quadrature-point update, predictor), and below
+ * them a load step built on those operators (pf3d_create ... pf3d_load_step).
  *
- * Every entry point is stateless: it takes the mesh and material by value
- * (read on the host), device pointers for the fields, and a hipStream_t
- * (void *, NULL = the null stream) on which its one kernel is enqueued; it
- * returns once the kernel is enqueued, without synchronising.  Fields are
+ * The operator entry points (pf3d_op_*) are stateless: each takes the mesh
+ * and material by value (read on the host), device pointers for the
+ * fields, and a hipStream_t (void *, NULL = the null stream) on which its
+ * one kernel is enqueued; it returns once the kernel is enqueued, without
+ * synchronising.  Fields are
  * structure-of-arrays in device memory, all FP64 unless stated:
  *   node (i, j, k) has id n = i + j (nx+1) + k (nx+1)(ny+1), N nodes;
  *   element (ie, je, ke) has id e = ie + je nx + ke nx ny, E elements;
