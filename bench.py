@@ -38,6 +38,11 @@ Two further modes print their own single JSON line:
                          correct or trial-only), FP64, over the whole load
                          history of --trial-problem (64^2 by default):
                          staggered counts, convergence and force curves;
+  --workload slab3d      the 3-D load step (pf3d_load_step, FP64, Jacobi PCG)
+                         on the 64^2 tension panel extruded into a slab of
+                         two element layers, S1 and ST over --steps load
+                         steps after --warmup: time per step, GDOF-updates/s
+                         and staggered counts;
   --workload oracle-history  the CPU baseline over a whole load history: the
                          oracle (FP64, direct solves) on the 64^2
                          configuration for ST and S1, with the cap of
@@ -260,6 +265,46 @@ def run_oracle_history(args):
     }
 
 
+def run_slab3d(pf, args):
+    """S1 and ST through the 3-D load step on the extruded 64^2 panel."""
+    import torch
+
+    import workloads as W
+    p = W.slab_from_panel(W.config_tension64(), nz=2, lz=2.0 / 64)
+    if args.warmup + args.steps > len(p.loads):
+        raise SystemExit("warmup + steps exceeds the load history")
+    runs = {}
+    for name, scheme in (("S1", pf.S1), ("ST", pf.ST)):
+        ctx = pf.Hex3DContext(p, scheme=scheme)
+        for n in range(args.warmup):
+            ctx.load_step(float(p.loads[n]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = [ctx.load_step(float(p.loads[n]))
+                for n in range(args.warmup, args.warmup + args.steps)]
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ctx.close()
+        runs[name] = {"seconds": secs, "ms_per_step": secs * 1e3 / args.steps,
+                      "gdof_updates_per_s": sum(r["dof_updates"] for r in rows) / secs / 1e9,
+                      "n_stag": [r["n_stag"] for r in rows],
+                      "force_y": [r["force"][1] for r in rows]}
+        log(f"  3-D {name}: {secs:.2f} s, N_stag {runs[name]['n_stag']}")
+    s1 = runs["S1"]
+    return {
+        "metric": "time per load step, 3-D slab, S1 vs ST FP64, 1 MI355X",
+        "value": s1["gdof_updates_per_s"], "unit": "GDOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": s1["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"slab3d: {p.nx}x{p.ny}x{p.nz} hexahedra (the {p.nx}^2 notched "
+                               f"tension panel extruded, u_z = 0 on both faces), load steps "
+                               f"{args.warmup + 1}..{args.warmup + args.steps}"},
+        "s1_fp64": s1, "st_fp64": runs["ST"],
+        "speedup_s1_vs_st": runs["ST"]["seconds"] / s1["seconds"],
+    }
+
+
 def run_sweep(pf, args):
     """Batched vs one-by-one throughput of the 64-instance sweep."""
     import torch
@@ -451,7 +496,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tension512",
                     choices=["tension512", "tension64", "shear1024", "lshape2048", "sweep64",
-                             "apply-sizes", "trial-readings", "oracle-history"])
+                             "apply-sizes", "trial-readings", "oracle-history", "slab3d"])
     ap.add_argument("--trial-problem", default="tension64", choices=["tension64", "tension512"],
                     help="problem of the trial-readings mode (its whole load history)")
     ap.add_argument("--trial-reading", default="all",
@@ -520,6 +565,9 @@ def main():
         return
     if args.workload == "trial-readings":
         print(json.dumps(run_trial_readings(pf, args)))
+        return
+    if args.workload == "slab3d":
+        print(json.dumps(run_slab3d(pf, args)))
         return
     if args.rows < 0:
         args.rows = 1 if args.workload == "tension512" else 0
