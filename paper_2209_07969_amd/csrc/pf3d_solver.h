@@ -17,8 +17,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstring>
-#include <string>
 #include <vector>
 
 namespace pf3d {
