@@ -164,6 +164,12 @@ pf_status pf3d_reaction_force(pf3d_ctx *ctx, int32_t group, double force[3]);
  * planes), d [N], H [8E] (plane q = point q of every element). */
 pf_status pf3d_get_state(pf3d_ctx *ctx, double *u, double *d, double *H);
 
+/* Committed state from host arrays in the same layouts (each may be NULL,
+ * keeping that field): checkpoint and resume.  The phase field's Dirichlet
+ * values are imposed on d.  Errors: PF_E_NONFINITE for NaN/Inf (nothing is
+ * written then). */
+pf_status pf3d_set_state(pf3d_ctx *ctx, const double *u, const double *d, const double *H);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,7 +39,7 @@ EXPORTED_3D = [
     "pf3d_op_qp_update", "pf3d_op_predictor", "pf3d_op_tangent_diag", "pf3d_op_phase_diag",
     "pf3d_op_phase_rhs", "pf3d_op_phase_coef", "pf3d_create", "pf3d_destroy",
     "pf3d_set_dirichlet_u", "pf3d_set_dirichlet_d", "pf3d_load_step", "pf3d_reaction_force",
-    "pf3d_get_state",
+    "pf3d_get_state", "pf3d_set_state",
 ]
 
 
@@ -155,6 +155,7 @@ def load_library(path: str = LIB_PATH):
     lib.pf3d_load_step.argtypes = [P, c_double, POINTER(StepStats)]
     lib.pf3d_reaction_force.argtypes = [P, c_int32, dp]
     lib.pf3d_get_state.argtypes = [P, dp, dp, dp]
+    lib.pf3d_set_state.argtypes = [P, dp, dp, dp]
     for name in EXPORTED + EXPORTED_3D:
         if name != "pf_default_opts" and name not in ("pf_status_string", "pf_last_error"):
             getattr(lib, name).restype = c_int32
@@ -604,6 +605,19 @@ class Hex3DContext:
         self._check(self.lib.pf3d_get_state(self.h, _ptr(u, c_double), _ptr(d, c_double),
                                             _ptr(H, c_double)), "pf3d_get_state")
         return u.reshape(3, self.N), d, H.reshape(8, self.E)
+
+    def set_state(self, u=None, d=None, H=None):
+        def arr(x, n):
+            if x is None:
+                return None, None
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+            if a.size != n:
+                raise ValueError("state array has the wrong size")
+            return a, _ptr(a, c_double)
+        ua, up = arr(u, 3 * self.N)
+        da, dpp = arr(d, self.N)
+        Ha, Hp = arr(H, 8 * self.E)
+        self._check(self.lib.pf3d_set_state(self.h, up, dpp, Hp), "pf3d_set_state")
 
     def close(self):
         if getattr(self, "h", None):

@@ -396,6 +396,22 @@ pf_status pf3d_reaction_force(pf3d_ctx *c, int32_t group, double force[3]) {
   return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
 }
 
+pf_status pf3d_set_state(pf3d_ctx *c, const double *u, const double *d, const double *H) {
+  if (!c) return PF_E_INVALID_ARG;
+  const size_t n3 = 3 * (size_t)c->g.N, n = c->g.N, e8 = 8 * (size_t)c->g.E;
+  if (u)
+    for (size_t k = 0; k < n3; ++k)
+      if (!std::isfinite(u[k])) return PF_E_NONFINITE;
+  if (d)
+    for (size_t k = 0; k < n; ++k)
+      if (!std::isfinite(d[k])) return PF_E_NONFINITE;
+  if (H)
+    for (size_t k = 0; k < e8; ++k)
+      if (!std::isfinite(H[k])) return PF_E_NONFINITE;
+  c->sol->set_state(u, d, H);
+  return c->be.err == hipSuccess ? PF_OK : PF_E_HIP;
+}
+
 pf_status pf3d_get_state(pf3d_ctx *c, double *u, double *d, double *H) {
   if (!c) return PF_E_INVALID_ARG;
   c->sol->get_state(u, d, H);

@@ -256,6 +256,17 @@ class Solver3 {
       f[c] = gn_[grp] ? be_.sum(gn_[grp], FGroupSum{Rt_, gdof_[grp], gcomp_dev_[grp], c}) : 0.0;
   }
 
+  // Committed state from host arrays (each may be null); the phase field's
+  // Dirichlet values are imposed on the new d.
+  void set_state(const double *u, const double *d, const double *H) {
+    if (u) be_.upload(u_, u, 3 * (size_t)g_.N * sizeof(double));
+    if (d) {
+      be_.upload(d_, d, (size_t)g_.N * sizeof(double));
+      be_.each(g_.N, FSetFixed{fd_, dval_, 1.0, d_});
+    }
+    if (H) be_.upload(Hc_, H, 8 * (size_t)g_.E * sizeof(double));
+  }
+
   void get_state(double *u, double *d, double *H) {
     if (u) be_.download(u, u_, 3 * (size_t)g_.N * sizeof(double));
     if (d) be_.download(d, d_, (size_t)g_.N * sizeof(double));

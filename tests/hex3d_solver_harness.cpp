@@ -101,6 +101,10 @@ void h3s_get_state(void *h, double *u, double *d, double *H) {
   static_cast<HostCtx *>(h)->sol->get_state(u, d, H);
 }
 
+void h3s_set_state(void *h, const double *u, const double *d, const double *H) {
+  static_cast<HostCtx *>(h)->sol->set_state(u, d, H);
+}
+
 void h3s_destroy(void *h) { delete static_cast<HostCtx *>(h); }
 
 }  // extern "C"

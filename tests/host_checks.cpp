@@ -90,6 +90,7 @@ int main() {
   CHECK(pf3d_load_step(nullptr, 1.0, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf3d_reaction_force(nullptr, 1, x) == PF_E_INVALID_ARG);
   CHECK(pf3d_get_state(nullptr, x, x, x) == PF_E_INVALID_ARG);
+  CHECK(pf3d_set_state(nullptr, x, x, x) == PF_E_INVALID_ARG);
   CHECK(pf3d_set_dirichlet_d(nullptr, 0, nullptr, nullptr) == PF_E_INVALID_ARG);
   CHECK(pf3d_destroy(nullptr) == PF_OK);
 

@@ -203,3 +203,20 @@ def test_load_steps_3d(gpu_lib, case):
     ctx.close()
     peak = max(abs(x) for x in oforces)
     np.testing.assert_allclose(forces, oforces, rtol=0, atol=1e-7 * peak)
+
+
+def test_checkpoint_and_resume_3d(gpu_lib):
+    """A state saved after step 2 and resumed in a fresh context reproduces
+    step 3 of the uninterrupted run bit for bit (deterministic reductions)."""
+    import workloads as W
+    p = W.slab_from_panel(W.tension_panel(n=8, l=0.2, du=2e-3, steps=3), 1, 0.1)
+    a, b = gpu_lib.Hex3DContext(p, scheme=1), gpu_lib.Hex3DContext(p, scheme=1)
+    for lam in p.loads[:2]:
+        a.load_step(float(lam))
+    b.set_state(*a.get_state())
+    sa, sb = a.load_step(float(p.loads[2])), b.load_step(float(p.loads[2]))
+    assert sa["n_stag"] == sb["n_stag"] and sa["force"] == sb["force"] and sa["n_trial"] > 0
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
