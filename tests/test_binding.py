@@ -43,3 +43,19 @@ def test_batch_refuses_a_closed_member():
     with pytest.raises(RuntimeError, match="closed"):
         b.load_step([1.0, 1.0])
     b.close()
+
+
+def test_every_entry_fails_loudly_without_a_device():
+    """The product path has no CPU fallback: without a HIP device every
+    class that would run kernels raises before touching the library's
+    compute entry points (not GPU; skipped where a device is visible)."""
+    if torch.cuda.is_available():
+        import pytest as _pytest
+        _pytest.skip("a HIP device is visible")
+    import workloads as W
+    p2 = W.tension_panel(n=4, steps=1)
+    p3 = W.uniaxial_bar3d(n=1, steps=1)
+    for make in (lambda: pf.Context(p2), lambda: pf.Hex3DOps(p3),
+                 lambda: pf.Hex3DContext(p3)):
+        with pytest.raises(RuntimeError, match="no HIP device"):
+            make()
