@@ -43,6 +43,10 @@ Two further modes print their own single JSON line:
                          two element layers, S1 and ST over --steps load
                          steps after --warmup: time per step, GDOF-updates/s
                          and staggered counts;
+  --workload apply3d     the 3-D operators (node-gather kernels, FP64) on
+                         cubes of 32^3..96^3 elements: time per launch and
+                         algorithmic GB/s of the internal force, tangent
+                         apply and phase apply;
   --workload oracle-history  the CPU baseline over a whole load history: the
                          oracle (FP64, direct solves) on the 64^2
                          configuration for ST and S1, with the cap of
@@ -262,6 +266,68 @@ def run_oracle_history(args):
         "config": {"workload": f"oracle-history: {base.name} ({base.nx}x{base.ny}, "
                                f"{len(base.loads)} load steps), max_stag {base.max_stag}"},
         "cpu_baseline": {"kind": "oracle", "runs": out},
+    }
+
+
+# Algorithmic bytes per node of the 3-D operators (FP64): internal force
+# reads u (3 comps) and d, writes R (3); tangent apply reads u, d and p (3),
+# writes q (3); phase apply reads the 8 point coefficients of one element
+# per node, p and writes q.
+BYTES_3D = {"internal_force": (3 + 1 + 3) * 8, "tangent_apply": (3 + 1 + 3 + 3) * 8,
+            "phase_apply": (8 + 1 + 1) * 8}
+
+
+def run_apply3d(pf, args):
+    """Time per launch of the 3-D operators over cube sizes."""
+    import types
+
+    import torch
+
+    import workloads as W
+    out = []
+    for n in (32, 64, 96):
+        box = types.SimpleNamespace(nx=n, ny=n, nz=n, lx=1.0, ly=1.0, lz=1.0,
+                                    material=W.Material())
+        ops = pf.Hex3DOps(box)
+        N, E = ops.N, ops.E
+        g = torch.Generator(device="cuda").manual_seed(n)
+        u = torch.rand(3 * N, dtype=torch.float64, device="cuda", generator=g) * 1e-3
+        d = torch.rand(N, dtype=torch.float64, device="cuda", generator=g)
+        pvec = torch.rand(3 * N, dtype=torch.float64, device="cuda", generator=g)
+        coef = torch.rand(8 * E, dtype=torch.float64, device="cuda", generator=g) + 1.0
+        q3 = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        q1 = torch.empty(N, dtype=torch.float64, device="cuda")
+        calls = {"internal_force": lambda: ops.internal_force(u, d, q3),
+                 "tangent_apply": lambda: ops.tangent_apply(u, d, pvec, q3),
+                 "phase_apply": lambda: ops.phase_apply(coef, d, q1)}
+        for name, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            gbs = BYTES_3D[name] * N / (us * 1e-6) / 1e9
+            out.append({"mesh": f"{n}^3", "kernel": name, "nodes": N, "us": us, "GBs": gbs,
+                        "frac_hbm": gbs / HBM_PEAK_GBS})
+            log(f"  {n}^3 {name}: {us:.1f} us, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS * 100:.1f} %)")
+    big = [r for r in out if r["mesh"] == "96^3" and r["kernel"] == "tangent_apply"][0]
+    return {
+        "metric": "3-D tangent apply GB/s vs mesh size, 1 MI355X", "value": big["GBs"],
+        "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": big["us"] / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "apply3d: unit cubes of 32^3, 64^3 and 96^3 trilinear "
+                               "hexahedra, random fields, VD split"},
+        "roofline": {"bound": "alu", "achieved": big["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": big["frac_hbm"], "traffic": None,
+                     "note": "node-gather kernels re-evaluate each element per node; the "
+                             "fraction is of the HBM peak they cannot reach"},
+        "sizes": out,
     }
 
 
@@ -496,7 +562,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tension512",
                     choices=["tension512", "tension64", "shear1024", "lshape2048", "sweep64",
-                             "apply-sizes", "trial-readings", "oracle-history", "slab3d"])
+                             "apply-sizes", "trial-readings", "oracle-history", "slab3d",
+                             "apply3d"])
     ap.add_argument("--trial-problem", default="tension64", choices=["tension64", "tension512"],
                     help="problem of the trial-readings mode (its whole load history)")
     ap.add_argument("--trial-reading", default="all",
@@ -568,6 +635,9 @@ def main():
         return
     if args.workload == "slab3d":
         print(json.dumps(run_slab3d(pf, args)))
+        return
+    if args.workload == "apply3d":
+        print(json.dumps(run_apply3d(pf, args)))
         return
     if args.rows < 0:
         args.rows = 1 if args.workload == "tension512" else 0
