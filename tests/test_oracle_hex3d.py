@@ -243,3 +243,81 @@ def test_uniaxial_bar3d_spectral_closed_form(scheme):
         xface = nodes[(nodes % (p.nx + 1)) == p.nx]
         np.testing.assert_allclose(o.u[3 * xface], 0.5 * (t - eps) * p.lx, rtol=1e-8)
     assert 0.45 < d_ref < 0.55
+
+
+def _linear_field(mesh, A, b=None):
+    """Nodal values of u(x) = A x (+ b) on the box mesh (interleaved dofs)."""
+    P = (mesh.nx + 1) * (mesh.ny + 1)
+    n = np.arange(mesh.n_nodes)
+    k, r = n // P, n % P
+    j, i = r // (mesh.nx + 1), r % (mesh.nx + 1)
+    X = np.stack([i * mesh.lx / mesh.nx, j * mesh.ly / mesh.ny, k * mesh.lz / mesh.nz], axis=1)
+    if A.ndim == 1:          # scalar field a . x + b
+        return X @ A + (b or 0.0), X
+    u = X @ A.T
+    return u.reshape(-1), X
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_patch_test_3d(split):
+    """Trilinear hexahedra reproduce a linear displacement exactly: the
+    strain at every point is sym(A), with engineering shears 2 eps_ij
+    (this pins all six rows of B, the shear rows included, which the slab
+    and the uniaxial cube leave untested); with uniform d the stress is
+    uniform, so the internal force vanishes at interior nodes, and the
+    stored energy integrates to volume x Psi(eps)."""
+    from oracle.hex3d import Mesh3D, Spectral3D, VD3D, internal_force
+    m = Mesh3D(3, 4, 2, 1.3, 0.7, 0.45)
+    A = np.array([[1.0, 0.4, -0.3], [0.2, -0.6, 0.5], [-0.1, 0.7, 0.8]]) * 1e-3
+    u, _ = _linear_field(m, A)
+    S = 0.5 * (A + A.T)
+    eps_ref = np.array([S[0, 0], S[1, 1], S[2, 2], 2 * S[1, 2], 2 * S[0, 2], 2 * S[0, 1]])
+    eps = m.strain(u)
+    np.testing.assert_allclose(eps, np.broadcast_to(eps_ref, eps.shape), rtol=0, atol=1e-15)
+    cons = (VD3D if split == 0 else Spectral3D)(2.1e5, 0.3)
+    d = np.full(m.n_nodes, 0.3)
+    R = internal_force(m, cons, u, d, 1e-6).reshape(-1, 3)
+    P = (m.nx + 1) * (m.ny + 1)
+    n = np.arange(m.n_nodes)
+    k, r = n // P, n % P
+    j, i = r // (m.nx + 1), r % (m.nx + 1)
+    interior = (i > 0) & (i < m.nx) & (j > 0) & (j < m.ny) & (k > 0) & (k < m.nz)
+    assert interior.any()
+    scale = np.abs(R).max()
+    assert np.abs(R[interior]).max() <= 1e-12 * scale
+    parts = cons.parts(eps)
+    g = (1 - 0.3) ** 2 + 1e-6
+    energy = np.sum(m.wdet * (g * parts["psi_plus"] + parts["psi_minus"]))
+    ref = cons.parts(eps_ref[None])
+    vol = m.lx * m.ly * m.lz
+    assert np.isclose(energy, vol * (g * ref["psi_plus"][0] + ref["psi_minus"][0]), rtol=1e-12)
+
+
+def test_phase_operator_3d_integrals():
+    """The 3-D phase operator against integrals a linear field fixes: the
+    mass part with coefficient c sums to c x volume; the gradient part
+    annihilates constants, has zero interior rows on a linear d, and gives
+    d^T L d = Gc l |grad d|^2 x volume (exact for a linear d), which pins
+    the z-derivatives the slab's z-uniform fields never exercise."""
+    from oracle.hex3d import Mesh3D, phase_matrix
+    m = Mesh3D(3, 2, 4, 1.3, 0.7, 0.45)
+    E = m.conn.shape[0]
+    vol = m.lx * m.ly * m.lz
+    c = 7.5
+    M = phase_matrix(m, np.full((E, 8), c), 0.0, 1.0)          # mass only (Gc l = 0)
+    one = np.ones(m.n_nodes)
+    assert np.isclose(one @ (M @ one), c * vol, rtol=1e-13)
+    Gc, l = 2.7, 0.05
+    L = phase_matrix(m, np.zeros((E, 8)), Gc, l)               # gradient part only
+    assert np.abs(L @ one).max() <= 1e-12 * Gc * l
+    a = np.array([0.3, -1.1, 2.0])
+    d, X = _linear_field(m, a, 0.25)
+    Ld = L @ d
+    P = (m.nx + 1) * (m.ny + 1)
+    n = np.arange(m.n_nodes)
+    k, r = n // P, n % P
+    j, i = r // (m.nx + 1), r % (m.nx + 1)
+    interior = (i > 0) & (i < m.nx) & (j > 0) & (j < m.ny) & (k > 0) & (k < m.nz)
+    assert interior.any()
+    assert np.abs(Ld[interior]).max() <= 1e-12 * np.abs(Ld).max()
+    assert np.isclose(d @ Ld, Gc * l * (a @ a) * vol, rtol=1e-12)
