@@ -321,3 +321,24 @@ def test_phase_operator_3d_integrals():
     assert interior.any()
     assert np.abs(Ld[interior]).max() <= 1e-12 * np.abs(Ld).max()
     assert np.isclose(d @ Ld, Gc * l * (a @ a) * vol, rtol=1e-12)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_tangent_matrix_3d_is_force_jacobian(split):
+    """The assembled 3-D tangent equals the central-difference Jacobian of
+    the assembled internal force along random directions (both splits; the
+    VD point tangent has no other pin of its own)."""
+    from oracle.hex3d import Mesh3D, Spectral3D, VD3D, internal_force, tangent_matrix
+    m = Mesh3D(2, 3, 2, 1.3, 0.7, 0.45)
+    cons = (VD3D if split == 0 else Spectral3D)(2.1e5, 0.3)
+    rng = np.random.default_rng(17 + split)
+    u = rng.normal(size=3 * m.n_nodes) * 1e-3
+    d = rng.uniform(0, 0.9, size=m.n_nodes)
+    K = tangent_matrix(m, cons, u, d, 1e-6)
+    assert abs(K - K.T).max() <= 1e-12 * abs(K).max()
+    h = 1e-9
+    for _ in range(3):
+        p = rng.normal(size=u.size)
+        fd = (internal_force(m, cons, u + h * p, d, 1e-6)
+              - internal_force(m, cons, u - h * p, d, 1e-6)) / (2 * h)
+        np.testing.assert_allclose(fd, K @ p, rtol=0, atol=1e-6 * np.abs(K @ p).max())
