@@ -108,6 +108,15 @@ __global__ void __launch_bounds__(kTpb3) k3_sum(F f, int count, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// The block partials added in block order, left at slot (one thread: the
+// order of the host's sum).
+__global__ void k3_finish(const double *part, int nb, double *slot) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[b];
+  *slot = t;
+}
+
 // Runs the solver's per-index functors as kernels on one stream.  Block
 // partials of a sum come back through a pinned buffer and are added on the
 // host in block order.  The first failing HIP call is kept in err; later
@@ -156,6 +165,21 @@ struct DeviceBackend {
   void each(int count, const F &f) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k3_each<F>, dim3(grid_blocks(count)), dim3(kTpb3), 0, s, f, count);
+    note(hipGetLastError());
+  }
+  bool ok() const { return err == hipSuccess; }
+  template <class F>
+  void sum_into(int count, const F &f, double *slot) {
+    const int nb = grid_blocks(count);
+    if (count <= 0) {
+      hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, s, part, 0, slot);
+      note(hipGetLastError());
+      return;
+    }
+    if (!reserve(nb)) return;
+    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, s, f, count, part);
+    note(hipGetLastError());
+    hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, s, part, nb, slot);
     note(hipGetLastError());
   }
   template <class F>

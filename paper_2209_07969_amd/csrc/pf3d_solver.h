@@ -8,6 +8,8 @@
 //                       block of kTpb3 indices by a fixed binary tree and then
 //                       over the blocks in order, so that every backend gives
 //                       the same bits;
+//   B::sum_into(count, f, slot)  the same sum, left in device memory at slot
+//                       (no host synchronisation);
 //   B::alloc/release/upload/download for the buffers.
 // The device backend (pf3d_kernels.hip) launches one kernel per call; a host
 // backend that replays the same grid serves the tests.
@@ -143,6 +145,83 @@ struct FGroupSum {
 
 constexpr int kGroups3 = 8;
 
+// Iterations enqueued between two polls of the CG state.
+constexpr int kCgBatch3 = 16;
+
+// Scalars of one CG solve, kept in device memory between its launches.
+// done: 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 at max_cg,
+// 4 zero right-hand side.
+struct CgState3 {
+  double bb, rz, pq, rr, rz_new, alpha, beta, tol2;
+  int iters, maxit, done, pad;
+};
+
+struct FCgStart {
+  CgState3 *s; double tol; int maxit;
+  __host__ __device__ void operator()(int) const {
+    s->tol2 = tol * tol * s->bb;
+    s->iters = 0;
+    s->maxit = maxit;
+    s->done = s->bb == 0.0 ? 4 : 0;
+  }
+};
+// q = 0 on fixed entries; returns p . q
+struct FMaskDot {
+  double *q; const double *p; const uint8_t *fixed;
+  __host__ __device__ double operator()(int i) const {
+    if (fixed[i]) {
+      q[i] = 0.0;
+      return 0.0;
+    }
+    return p[i] * q[i];
+  }
+};
+struct FCgAlpha {
+  CgState3 *s;
+  __host__ __device__ void operator()(int) const {
+    if (s->done) return;
+    if (!(s->pq > 0.0)) {
+      s->done = 2;
+      return;
+    }
+    s->alpha = s->rz / s->pq;
+  }
+};
+// x += alpha p, r -= alpha q on free entries while the solve runs
+struct FCgXR {
+  const CgState3 *s; double *x, *r; const double *p, *q; const uint8_t *fixed;
+  __host__ __device__ void operator()(int i) const {
+    if (s->done || fixed[i]) return;
+    x[i] += s->alpha * p[i];
+    r[i] -= s->alpha * q[i];
+  }
+};
+// counts the iteration, tests ||r||^2 <= tol^2 ||b||^2 and max_cg, forms beta
+struct FCgBeta {
+  CgState3 *s;
+  __host__ __device__ void operator()(int) const {
+    if (s->done) return;
+    s->iters += 1;
+    if (s->rr <= s->tol2) {
+      s->done = 1;
+      return;
+    }
+    if (s->iters >= s->maxit) {
+      s->done = 3;
+      return;
+    }
+    s->beta = s->rz_new / s->rz;
+    s->rz = s->rz_new;
+  }
+};
+struct FCgP {
+  const CgState3 *s; double *p; const double *z; const uint8_t *fixed;
+  __host__ __device__ void operator()(int i) const {
+    if (s->done) return;
+    p[i] = fixed[i] ? 0.0 : z[i] + s->beta * p[i];
+  }
+};
+
 // The options the 3-D load step takes: FP64 with Jacobi PCG, AT2 with the
 // history field, the floored trial block with predict -> correct; the
 // tolerances and limits as for the 2-D path.
@@ -190,7 +269,7 @@ class Solver3 {
     for (double **p : {&Hc_, &H_, &Hhat_, &psi_, &coef_, &ctr_})
       if (!(*p = alloc<double>(E8))) return false;
     if (!(flags_ = alloc<uint16_t>(g_.E)) || !(fu_ = alloc<uint8_t>(N3)) ||
-        !(fd_ = alloc<uint8_t>(N)))
+        !(fd_ = alloc<uint8_t>(N)) || !(cs_ = alloc<CgState3>(1)))
       return false;
     host_fu_.assign(N3, 0);
     host_fd_.assign(N, 0);
@@ -335,38 +414,39 @@ class Solver3 {
   }
 
   // Jacobi PCG on the free entries: x = A^-1 rhs to ||r|| <= tol ||rhs||,
-  // with A applied by apply(p, q) and the inverse diagonal in Dinv_.
+  // with A applied by apply(p, q) and the inverse diagonal in Dinv_.  The
+  // scalars stay in device memory (CgState3); batches of kCgBatch3
+  // iterations are enqueued between polls of the state, and the launches of
+  // a batch after the solve has ended change nothing.
   template <class Apply>
   int pcg(int n, const double *rhs, const uint8_t *fixed, double tol, Apply &&apply,
           Counts3 *st) {
     be_.each(n, FFill{0.0, x_});
     be_.each(n, FAxpy{rhs, rhs, 0.0, fixed, r_});            // r = rhs on free entries
-    const double nb = std::sqrt(be_.sum(n, FDot{r_, r_, fixed}));
-    if (nb == 0.0) return 0;
+    be_.sum_into(n, FDot{r_, r_, fixed}, &cs_->bb);
     be_.each(n, FMul{Dinv_, r_, z_});
     be_.each(n, FAxpy{z_, z_, 0.0, fixed, p_});
-    double rz = be_.sum(n, FDot{r_, z_, fixed});
-    int it = 0;
-    for (; it < o_.max_cg; ++it) {
-      apply(p_, q_);
-      be_.each(n, FAxpy{q_, q_, 0.0, fixed, q_});
-      const double pq = be_.sum(n, FDot{p_, q_, fixed});
-      if (!(pq > 0.0)) break;
-      const double alpha = rz / pq;
-      be_.each(n, FAxpy{x_, p_, alpha, fixed, x_});
-      be_.each(n, FAxpy{r_, q_, -alpha, fixed, r_});
-      const double rr = be_.sum(n, FDot{r_, r_, fixed});
-      if (std::sqrt(rr) <= tol * nb) {
-        ++it;
-        break;
+    be_.sum_into(n, FDot{r_, z_, fixed}, &cs_->rz);
+    be_.each(1, FCgStart{cs_, tol, o_.max_cg});
+    CgState3 h{};
+    be_.download(&h, cs_, sizeof h);
+    while (!h.done) {
+      for (int k = 0; k < kCgBatch3; ++k) {
+        apply(p_, q_);
+        be_.sum_into(n, FMaskDot{q_, p_, fixed}, &cs_->pq);
+        be_.each(1, FCgAlpha{cs_});
+        be_.each(n, FCgXR{cs_, x_, r_, p_, q_, fixed});
+        be_.sum_into(n, FDot{r_, r_, fixed}, &cs_->rr);
+        be_.each(n, FMul{Dinv_, r_, z_});
+        be_.sum_into(n, FDot{r_, z_, fixed}, &cs_->rz_new);
+        be_.each(1, FCgBeta{cs_});
+        be_.each(n, FCgP{cs_, p_, z_, fixed});
       }
-      be_.each(n, FMul{Dinv_, r_, z_});
-      const double rz_new = be_.sum(n, FDot{r_, z_, fixed});
-      be_.each(n, FAxpy{z_, p_, rz_new / rz, fixed, p_});
-      rz = rz_new;
+      be_.download(&h, cs_, sizeof h);
+      if (!be_.ok()) break;
     }
-    if (it >= o_.max_cg) st->cg_not_converged += 1;
-    return it;
+    if (h.done == 3) st->cg_not_converged += 1;
+    return h.iters;
   }
 
   // Newton for u at fixed d (Section 3.1), line search of at most 5
@@ -478,6 +558,7 @@ class Solver3 {
          *ctr_ = nullptr;
   uint16_t *flags_ = nullptr;
   uint8_t *fu_ = nullptr, *fd_ = nullptr;
+  CgState3 *cs_ = nullptr;
   std::vector<uint8_t> host_fu_, host_fd_;
   std::vector<double> host_unit_, host_dval_;
   std::vector<int64_t> gnode_[kGroups3];

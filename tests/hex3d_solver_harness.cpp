@@ -31,6 +31,11 @@ struct HostBackend {
         if (i < count) f(i);
       }
   }
+  bool ok() const { return true; }
+  template <class F>
+  void sum_into(int count, const F &f, double *slot) {
+    *slot = sum(count, f);
+  }
   template <class F>
   double sum(int count, const F &f) {
     double total = 0.0;
