@@ -214,6 +214,14 @@ struct FCgBeta {
     s->rz = s->rz_new;
   }
 };
+// an operator apply that returns at once when the solve has ended
+template <class F>
+struct FWhileRunning {
+  const CgState3 *s; F f;
+  __host__ __device__ void operator()(int i) const {
+    if (!s->done) f(i);
+  }
+};
 struct FCgP {
   const CgState3 *s; double *p; const double *z; const uint8_t *fixed;
   __host__ __device__ void operator()(int i) const {
@@ -464,7 +472,7 @@ class Solver3 {
       be_.each(N3, FInvDiag{D_, fu_, Dinv_});
       const double *u = u_;
       const int cg = pcg(N3, R_, fu_, o_.tol_pcg, [&](const double *p, double *q) {
-        be_.each(g_.N, FTangent{g_, m_, u, d_, p, q});
+        be_.each(g_.N, FWhileRunning<FTangent>{cs_, FTangent{g_, m_, u, d_, p, q}});
       }, st);
       st->n_cg_u += cg;
       st->dof_updates += double(cg) * double(nfree_u_);
@@ -515,7 +523,7 @@ class Solver3 {
     be_.each(N, FPhaseDiag{g_, m_, coef_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
     const int cg = pcg(N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
-      be_.each(N, FPhase{g_, m_, coef_, p, q});
+      be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, coef_, p, q}});
     }, st);
     st->n_cg_d += cg;
     st->dof_updates += double(cg) * double(nfree_d_);
@@ -535,7 +543,7 @@ class Solver3 {
     be_.each(N, FPhaseDiag{g_, m_, ctr_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
     const int cg = pcg(N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
-      be_.each(N, FPhase{g_, m_, ctr_, p, q});
+      be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, ctr_, p, q}});
     }, st);
     st->n_cg_trial += cg;
     st->dof_updates += double(cg) * double(nfree_d_);
