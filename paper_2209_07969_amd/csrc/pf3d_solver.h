@@ -187,13 +187,25 @@ struct FCgAlpha {
     s->alpha = s->rz / s->pq;
   }
 };
-// x += alpha p, r -= alpha q on free entries while the solve runs
-struct FCgXR {
+// x += alpha p, r -= alpha q on free entries while the solve runs;
+// returns r_i^2 of the updated r (0 on fixed entries)
+struct FCgXRNorm {
   const CgState3 *s; double *x, *r; const double *p, *q; const uint8_t *fixed;
-  __host__ __device__ void operator()(int i) const {
-    if (s->done || fixed[i]) return;
-    x[i] += s->alpha * p[i];
-    r[i] -= s->alpha * q[i];
+  __host__ __device__ double operator()(int i) const {
+    if (fixed[i]) return 0.0;
+    if (!s->done) {
+      x[i] += s->alpha * p[i];
+      r[i] -= s->alpha * q[i];
+    }
+    return r[i] * r[i];
+  }
+};
+// z = D^-1 r; returns r_i z_i (0 on fixed entries)
+struct FPrecDot {
+  const double *Dinv, *r; double *z; const uint8_t *fixed;
+  __host__ __device__ double operator()(int i) const {
+    z[i] = Dinv[i] * r[i];
+    return fixed[i] ? 0.0 : r[i] * z[i];
   }
 };
 // counts the iteration, tests ||r||^2 <= tol^2 ||b||^2 and max_cg, forms beta
@@ -443,10 +455,8 @@ class Solver3 {
         apply(p_, q_);
         be_.sum_into(n, FMaskDot{q_, p_, fixed}, &cs_->pq);
         be_.each(1, FCgAlpha{cs_});
-        be_.each(n, FCgXR{cs_, x_, r_, p_, q_, fixed});
-        be_.sum_into(n, FDot{r_, r_, fixed}, &cs_->rr);
-        be_.each(n, FMul{Dinv_, r_, z_});
-        be_.sum_into(n, FDot{r_, z_, fixed}, &cs_->rz_new);
+        be_.sum_into(n, FCgXRNorm{cs_, x_, r_, p_, q_, fixed}, &cs_->rr);
+        be_.sum_into(n, FPrecDot{Dinv_, r_, z_, fixed}, &cs_->rz_new);
         be_.each(1, FCgBeta{cs_});
         be_.each(n, FCgP{cs_, p_, z_, fixed});
       }
