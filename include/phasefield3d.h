@@ -153,7 +153,9 @@ pf_status pf3d_set_dirichlet_d(pf3d_ctx *ctx, int64_t n, const int64_t *node,
  * Psi+(u_n))).  stats (may be NULL): counts as for pf_load_step, force[0]
  * and force[1] the x and y reactions of the loaded group (all three from
  * pf3d_reaction_force).  Returns PF_E_NOT_CONVERGED, not fatal, if the loop
- * ended at max_stag or a Newton solve at max_newton. */
+ * ended at max_stag or a Newton solve at max_newton (the step is committed
+ * either way); PF_E_NONFINITE if the staggered residual is not finite;
+ * PF_E_HIP on a device error (the state is then undefined). */
 pf_status pf3d_load_step(pf3d_ctx *ctx, double load_factor, pf_step_stats *stats);
 
 /* Reaction of a Dirichlet group at the committed state: the internal force
