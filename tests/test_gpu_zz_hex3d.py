@@ -165,7 +165,7 @@ def test_diagonals_rhs_and_coefficients_3d(gpu_lib, split):
 
 
 @pytest.mark.parametrize("case", ["cube_s1", "cube_unload_s1", "slab_st", "slab_s3", "slab2_s1",
-                                  "shear_s1"])
+                                  "shear_s1", "tilted_st", "tilted_s1"])
 def test_load_steps_3d(gpu_lib, case):
     """pf3d_load_step against the 3-D oracle under the 2-D parity protocol."""
     import dataclasses
@@ -180,6 +180,8 @@ def test_load_steps_3d(gpu_lib, case):
         scheme = 1
     elif case == "shear_s1":
         p, scheme = W.slab_from_panel(W.shear_panel(n=8, l=0.2, du=4e-3, steps=2), 1, 0.1), 1
+    elif case in ("tilted_st", "tilted_s1"):
+        p, scheme = W.tilted_notched_box3d(), (0 if case == "tilted_st" else 1)
     elif case == "slab2_s1":
         p, scheme = W.slab_from_panel(W.tension_panel(n=12, l=0.2, du=2e-3, steps=2), 2, 0.1), 1
     else:

@@ -206,3 +206,18 @@ def test_checkpoint_and_resume_is_exact(solver):
     finally:
         solver.h3s_destroy(a)
         solver.h3s_destroy(b)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_tilted_notched_box(solver, scheme):
+    p = W.tilted_notched_box3d()
+    trials = compare_history(solver, p, scheme, min_trials=1 if scheme else 0)
+    orc = Oracle3D(p, scheme)
+    for lam in p.loads:
+        orc.load_step(float(lam))
+    P = (p.nx + 1) * (p.ny + 1)
+    # the fields really vary through the thickness
+    d_front, d_back = orc.d[:P], orc.d[p.nz * P:]
+    assert np.abs(d_back - d_front).max() > 0.1
+    if scheme:
+        assert trials > 0

@@ -309,6 +309,30 @@ def uniaxial_bar3d(n=3, l=0.03, du=5e-3, steps=6, E=2.1e5, nu=0.3, Gc=2.7) -> Pr
                      dir_d_values=np.zeros(0), loads=du * np.arange(1, steps + 1, dtype=np.float64))
 
 
+def tilted_notched_box3d(n=4, nz=2, du=3e-3, steps=2, l=0.25) -> Problem3D:
+    """A notched box (n x n x nz elements, 1 x 1 x 0.5): bottom face fixed,
+    top face pulled by u_y = lambda (0.5 + z/lz), i.e. more at the back than
+    at the front, a half-width notch (d = 1) on the mid plane y = 0.5, the
+    remaining faces free.  Its fields vary through the thickness, unlike
+    those of the extruded slab (uniform in z) and the cube (homogeneous)."""
+    lx = ly = 1.0
+    lz = 0.5
+    P = (n + 1) * (n + 1)
+    k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    ids = (i + j * (n + 1) + k * P).reshape(-1)
+    i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)
+    bot = ids[j == 0]
+    fixed = DirichletU(np.repeat(bot, 3), np.tile(np.array([0, 1, 2], np.int8), bot.size),
+                       np.zeros(3 * bot.size))
+    top = j == n
+    pull = DirichletU(ids[top], np.ones(top.sum(), np.int8), 0.5 + k[top] / nz)
+    notch = ids[(j == n // 2) & (i <= n // 2)]
+    return Problem3D(name="tilted_box", nx=n, ny=n, nz=nz, lx=lx, ly=ly, lz=lz,
+                     material=Material(l=l), dir_u=[fixed, pull],
+                     dir_d_nodes=notch.astype(np.int64), dir_d_values=np.ones(notch.size),
+                     loads=du * np.arange(1, steps + 1, dtype=np.float64))
+
+
 # --------------------------------------------------------------------------
 # Named configurations
 # --------------------------------------------------------------------------
