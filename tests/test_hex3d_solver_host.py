@@ -11,7 +11,8 @@ max |d - d_oracle| <= 1e-5 and the reaction within 1e-7 of its peak, on
 the uniaxial cube (both splits, with its closed form through the oracle's
 own pins), the notched tension panel extruded into a slab (one and two
 element layers, the latter over several ragged blocks) for ST, S1 and S3,
-and the spectral shear slab.  The device build is compared by
+the spectral shear slab, and a notched box whose damage varies through the
+thickness.  The device build is compared by
 tests/test_gpu_zz_hex3d.py.
 """
 import ctypes
