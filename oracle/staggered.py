@@ -65,6 +65,10 @@ class StepStats:
     force: float = 0.0
     force_xy: tuple = (0.0, 0.0)
     time_s: float = 0.0
+    # size of the last staggered iteration (reporting only): ||u^k - u^{k-1}||
+    # / ||u^k|| and max |d^k - d^{k-1}|; both 0 when the step took k = 0 only
+    last_du: float = 0.0
+    last_dd: float = 0.0
 
 
 class Oracle:
@@ -257,6 +261,7 @@ class Oracle:
         r = self.stag_residual(d, drive)
         trial_only = int(getattr(p, "trial_update", 0)) == 1
         while r > p.tol_stag and st.n_stag < p.max_stag:
+            u_before, d_before = u.copy(), d.copy()
             H_hat = drive
             ng = 0
             if self.scheme != 0:
@@ -286,6 +291,9 @@ class Oracle:
             H = np.maximum(H_prev, parts["psi_plus"])
             drive = parts["psi_plus"] if self.model == 1 else H
             r = self.stag_residual(d, drive)
+            nu_ = np.linalg.norm(u)
+            st.last_du = float(np.linalg.norm(u - u_before) / (nu_ if nu_ > 0 else 1.0))
+            st.last_dd = float(np.abs(d - d_before).max()) if d.size else 0.0
         st.r_stag = r
         st.converged &= bool(r <= p.tol_stag)
         self.u, self.d, self.H = u, d, H
