@@ -92,3 +92,48 @@ def test_autotune_keeps_parity(gpu_lib):
         assert abs(sg["n_stag"] - so.n_stag) <= 1
         assert abs(sg["force"][1] - so.force) <= 1e-4 * abs(so.force)
     ctx.close()
+
+
+def _oracle_batch_members():
+    """Eight uneven mixed-precision members of a tension sweep (meshes 12^2
+    to 24^2, two regularisation lengths, four notch lengths, S1/S2/S3 and one
+    ST member): each is compared with its own oracle run."""
+    spec = [(16, 0.1, 0.5, 1), (24, 0.1, 0.375, 1), (20, 0.08, 0.45, 2), (12, 0.12, 0.5, 3),
+            (18, 0.1, 0.4, 1), (22, 0.09, 0.3, 0), (14, 0.1, 0.6, 1), (16, 0.08, 0.35, 3)]
+    return [(W.tension_panel(n=n, l=l, du=1e-3, steps=5, notch=a), s) for n, l, a, s in spec]
+
+
+@pytest.mark.parametrize("shared", [True, False])
+def test_batch_members_match_oracle(gpu_lib, shared):
+    """Every member of an 8-instance mixed batch (shared CG launches or
+    concurrent streams) against its own FP64 oracle history, step by step
+    under the parity protocol."""
+    import torch
+    from _parity import check_step, soa
+    mem = _oracle_batch_members()
+    streams = [torch.cuda.Stream() for _ in mem]
+    ctxs = [gpu_lib.Context(p, scheme=s, precision=1, stream=st.cuda_stream)
+            for (p, s), st in zip(mem, streams)]
+    orcs = [Oracle(p, s) for p, s in mem]
+    B = gpu_lib.Batch(ctxs, workers=4, shared=shared)
+    n_steps = 5
+    F = [([], []) for _ in mem]
+    n_full = [0] * len(mem)
+    for k in range(n_steps):
+        sb = B.load_step([float(p.loads[k]) for p, _ in mem])
+        for i, ((p, s), orc, ctx) in enumerate(zip(mem, orcs, ctxs)):
+            so = orc.load_step(float(p.loads[k]))
+            u, d, _ = ctx.get_state()
+            n_full[i] += check_step(f"member {i} (n={p.nx}, scheme {s}) step {k + 1}",
+                                    so.n_stag, so.last_du, so.last_dd, soa(orc.u), orc.d,
+                                    sb[i]["n_stag"], u, d, 1e-6)
+            F[i][0].append(so.force)
+            F[i][1].append(sb[i]["force"][1])
+    B.close()
+    for i, (fo, fg) in enumerate(F):
+        fo, fg = np.array(fo), np.array(fg)
+        err = np.abs(fg - fo).max() / np.abs(fo).max()
+        assert err <= 1e-4, (i, err)
+        assert n_full[i] >= n_steps - 1, (i, n_full[i])
+    for c in ctxs:
+        c.close()

@@ -156,3 +156,32 @@ def test_fullsize_lshape2048_s1_mixed(gpu_lib):
     st, u, d, H, Hp = run_gpu(gpu_lib, p, 1, 1, 2)
     assert st["converged"] == 1
     check_state(p, st, u, d, H, Hp, np.random.default_rng(2048), n_samples=100)
+
+
+def test_post_nucleation_tension256_s1_mixed(gpu_lib):
+    """A converged state after the crack has nucleated and run: the 256^2
+    tension panel with l = 2h (the benchmark panel's l/h), S1 mixed with the
+    benchmark's launch configuration, stepped until the reaction has fallen
+    below 0.9 of its peak; that step's state is checked like the full-size
+    states above."""
+    n = 256
+    p = W.tension_panel(n=n, l=2.0 / n, du=4e-4, steps=24, name="tension256")
+    ctx = gpu_lib.Context(p, scheme=1, precision=1, precond=1, cheb_degree=3, march_rows=1)
+    peak = 0.0
+    found = None
+    for k in range(p.loads.size):
+        H_prev = ctx.get_state()[2].copy()
+        st = ctx.load_step(float(p.loads[k]))
+        F = st["force"][1]
+        print(f"  step {k + 1}: n_stag={st['n_stag']} converged={st['converged']} F={F:.4f}",
+              flush=True)
+        if st["converged"] and F < 0.9 * peak:
+            found = (st, H_prev)
+            break
+        peak = max(peak, F)
+    assert found is not None, "no converged post-peak step"
+    st, H_prev = found
+    u, d, H = ctx.get_state()
+    ctx.close()
+    assert d.max() > 0.95
+    check_state(p, st, u, d, H, H_prev, np.random.default_rng(256))
