@@ -16,7 +16,15 @@ Both schemes use Jacobi-Chebyshev preconditioning (degree 3 for the FP32
 inner solves, 5 for FP64) and the work decomposition measured fastest for
 each on this mesh: LDS tiles for S1 mixed, column marching with 2 rows for
 ST FP64 (--tune-reps N lets the autotuner choose instead).
-W warmup steps (load steps 1..W) run untimed, then K load steps are timed.
+The timed window ends in load step 91, the step in which the crack runs
+through the ligament (the longest steps of the history, where the schemes
+differ most): load steps 1..91-K-W run first with S1 mixed, untimed, and
+both schemes start from that committed state; W warmup steps follow
+untimed, then K load steps are timed (--window-end moves the window,
+--full-history times all 100 steps from the initial state).  Each scheme
+stops a step at max_stag = 500 staggered iterations; the line lists the
+steps that ended there and gives the speedup over the whole window and over
+the steps both schemes converged.
 
 value = GDOF-updates/s of S1 mixed over the timed steps (sum over all CG
 solves of free DOFs x iterations, divided by the wall time between two
@@ -69,6 +77,9 @@ KIND = {"tension512": "notched tension panel", "tension64": "notched tension pan
         "shear1024": "notched shear panel (spectral split)",
         "lshape2048": "L-shaped panel (masked quadrant)"}
 HBM_PEAK_GBS = 8000.0
+# The load step of the 512^2 tension history in which the crack runs through
+# the ligament (both schemes; the longest steps of the history).
+NUCLEATION_STEP_512 = 91
 
 
 def log(*a):
@@ -99,6 +110,14 @@ def updcheb_bytes_per_node():
     return (2 * 5 + 1 + 2 * 5) * 4 + 1 + 1
 
 
+def updcheb2_bytes_per_node(last=True):
+    """Algorithmic bytes per node of the FP32 CG update fused with the first
+    two Chebyshev steps on the tangent (k_cg_updcheb2<OpTangent<float>>, LDS
+    tiles): read r, q, D^-1, x, p (2 comps each), d, node flag, element flag;
+    write x, r, z (2 comps each) and, when more steps follow, d_2 and res_2."""
+    return (2 * 5 + 1 + 2 * (3 if last else 5)) * 4 + 1 + 1
+
+
 def update_bytes_per_node():
     """Algorithmic bytes per node of the FP32 CG vector update (k_cg_update):
     per DOF read x, p, q, r, D^-1 and write x, r, z, two DOFs per node."""
@@ -107,19 +126,21 @@ def update_bytes_per_node():
 
 def measured_traffic(kname):
     """Per-launch HBM bytes of the dominant kernel from the committed counter
-    runs (profiles/hbm_traffic_tension512.json), or None when the kernel
-    source has changed since the counters were taken or the counters were
-    taken on another kernel."""
+    runs (profiles/hbm_traffic_tension512.json) and a note naming that
+    source, or (None, None) when the kernel source has changed since the
+    counters were taken or they were taken on another kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_tension512.json")
     src = os.path.join(ROOT, "paper_2209_07969_amd", "csrc", "pf_kernels.hip")
     if not os.path.exists(path):
-        return None
+        return None, None
     rec = json.load(open(path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("kernel_source_sha256") != sha or rec.get("kernel") != kname:
-        return None
-    return rec["traffic_bytes_per_launch"]
+        return None, None
+    return rec["traffic_bytes_per_launch"], (
+        f"profiles/hbm_traffic_tension512.json: rocprofv3 FETCH_SIZE and WRITE_SIZE runs of "
+        f"this kernel, taken on pf_kernels.hip sha256 {sha[:16]} (the source built here)")
 
 
 def load_step_logged(ctx, problem, lam, every=25):
@@ -140,8 +161,8 @@ def load_step_logged(ctx, problem, lam, every=25):
 
 
 STEP_FIELDS = ("n_stag", "n_newton", "n_trial", "n_dsolve", "n_cg_u", "n_cg_d", "n_cg_trial",
-               "gated_max", "floor_hits", "r_stag", "force", "time_ms", "dof_updates",
-               "converged", "cg_not_converged")
+               "gated_max", "floor_hits", "r_stag", "force", "time_ms", "time_u_ms",
+               "time_d_ms", "dof_updates", "converged", "cg_not_converged")
 
 
 def step_record(label, step, timed, st):
@@ -154,18 +175,22 @@ def step_record(label, step, timed, st):
 
 
 def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degree=None,
-              tune_reps=0, rows=0, jsonl=None, label=""):
-    """Run load steps 1..warmup untimed and warmup+1..warmup+steps timed.
-    degree: Jacobi-Chebyshev degree (None = plain Jacobi); rows: work
-    decomposition (march_rows); tune_reps > 0: let the autotuner pick it;
-    jsonl: an open file that receives one record per load step."""
+              tune_reps=0, rows=0, jsonl=None, label="", start=0, state=None):
+    """Run load steps start+1..start+warmup untimed and the next `steps`
+    timed.  state: (u, d, H) committed after load step `start` (None: the
+    initial state, start = 0).  degree: Jacobi-Chebyshev degree (None = plain
+    Jacobi); rows: work decomposition (march_rows); tune_reps > 0: let the
+    autotuner pick it; jsonl: an open file that receives one record per load
+    step."""
     import torch
     opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
     ctx = pf.Context(problem, scheme=scheme, precision=precision, march_rows=rows, **opts)
+    if state is not None:
+        ctx.set_state(*state)
     ctx.chosen_rows = ctx.autotune(tune_reps) if tune_reps > 0 else rows
     if profile:
         ctx.set_profiling(True)
-    for n in range(warmup):
+    for n in range(start, start + warmup):
         st = load_step_logged(ctx, problem, float(problem.loads[n]))
         if jsonl:
             jsonl.write(step_record(label, n + 1, False, st) + "\n")
@@ -176,39 +201,99 @@ def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degr
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rows = []
-    for n in range(warmup, warmup + steps):
+    for n in range(start + warmup, start + warmup + steps):
         st = load_step_logged(ctx, problem, float(problem.loads[n]))
+        st["step"] = n + 1
         rows.append(st)
         if jsonl:
             jsonl.write(step_record(label, n + 1, True, st) + "\n")
             jsonl.flush()
-        log(f"  timed step {n+1}: n_stag={st['n_stag']} newton={st['n_newton']} "
-            f"cg_u={st['n_cg_u']} cg_d={st['n_cg_d']} cg_trial={st['n_cg_trial']} "
-            f"gated={st['gated_max']} F={st['force'][1]:.4f} {st['time_ms']:.0f} ms")
+        log(f"  timed step {n+1}: n_stag={st['n_stag']} conv={st['converged']} "
+            f"newton={st['n_newton']} cg_u={st['n_cg_u']} cg_d={st['n_cg_d']} "
+            f"cg_trial={st['n_cg_trial']} gated={st['gated_max']} F={st['force'][1]:.4f} "
+            f"{st['time_ms']:.0f} ms (u {st['time_u_ms']:.0f}, d {st['time_d_ms']:.0f})")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return ctx, rows, t1 - t0
 
 
+def prefix_state(pf, problem, n_steps, degree, rows):
+    """The committed state after load steps 1..n_steps of S1 mixed: the
+    common starting point of both timed runs (input preparation, untimed)."""
+    if n_steps <= 0:
+        return None
+    opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
+    ctx = pf.Context(problem, scheme=pf.S1, precision=pf.MIXED, march_rows=rows, **opts)
+    t0 = time.perf_counter()
+    for n in range(n_steps):
+        st = ctx.load_step(float(problem.loads[n]))
+        if (n + 1) % 10 == 0 or n + 1 == n_steps:
+            log(f"  prefix step {n + 1}: n_stag={st['n_stag']} F={st['force'][1]:.4f} "
+                f"({time.perf_counter() - t0:.1f} s)")
+    state = ctx.get_state()
+    ctx.close()
+    return state
+
+
+def step_table(rows):
+    """Per-step record of a timed run for the JSON line."""
+    return [{"step": r["step"], "n_stag": r["n_stag"], "converged": int(r["converged"]),
+             "n_newton": r["n_newton"], "n_cg_u": r["n_cg_u"], "n_cg_d": r["n_cg_d"],
+             "n_cg_trial": r["n_cg_trial"], "time_ms": round(r["time_ms"], 1),
+             "time_u_ms": round(r["time_u_ms"], 1), "time_d_ms": round(r["time_d_ms"], 1)}
+            for r in rows]
+
+
+def copy_bandwidth():
+    """Measured device-to-device copy rate (GB/s, bytes read + written) of a
+    1 GiB buffer, the box's practical HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    n = 256 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * 4 * n / sec / 1e9
+
+
 def cpu_baseline(pf, problem):
-    """Oracle (FP64, sparse direct solves) on a bounded sample: the k = 0
-    displacement solve of load step 1 limited to one Newton iteration.  The
-    GPU performs the same sample (FP64 ST, one Newton iteration) and its
-    DOF-update count converts the oracle's time into the metric's unit.
-    cores: the process's CPU time over the wall time of the sample (all
-    threads, so a multithreaded library call would show), rounded, at least 1."""
+    """The oracle (FP64, assembled CSR + SuperLU), untuned, on a bounded
+    sample of the workload: the k = 0 displacement solve of load step 1
+    limited to one Newton iteration (assemble R_u and K_t, one sparse direct
+    solve, the line-search residual), then the QP update and the staggered
+    residual.  value: its wall time in seconds.  The GPU runs the same sample
+    (ST FP64, one Newton iteration: pf_staggered_iterate opening step 1) in a
+    second fresh context after a first one has warmed the library up; its
+    time is reported beside the oracle's.  cores: the process's CPU time over
+    the oracle's wall time (all threads, so a multithreaded library call
+    would show), rounded, at least 1."""
     import dataclasses
 
-    import oracle
-    p1 = dataclasses.replace(problem)
-    p1.max_newton = 1
-    ctx = pf.Context(p1, scheme=pf.ST, precision=pf.FP64, max_newton=1)
-    st = ctx.staggered_iterate(float(p1.loads[0]))
-    gpu_updates = st["dof_updates"]
-    ctx.close()
     import numpy as np
-    orc = oracle.Oracle(p1, 0)
+    import torch
+
+    import oracle
+    p1 = dataclasses.replace(problem, max_newton=1)
     lam = float(p1.loads[0])
+    for rep in range(2):
+        ctx = pf.Context(p1, scheme=pf.ST, precision=pf.FP64, max_newton=1)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        ctx.staggered_iterate(lam)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - tg
+        ctx.close()
+    orc = oracle.Oracle(p1, 0)
     t0, c0 = time.perf_counter(), time.process_time()
     u = orc.u.copy()
     u[orc.u_fixed] = lam * orc.u_unit[orc.u_fixed]
@@ -220,16 +305,18 @@ def cpu_baseline(pf, problem):
     t, cpu_s = time.perf_counter() - t0, time.process_time() - c0
     cores = max(1, round(cpu_s / t))
     return {
-        "value": gpu_updates / t / 1e9,
-        "unit": "GDOF-updates/s (GPU-equivalent)",
+        "value": t,
+        "unit": "s per sample (one Newton iteration of the k = 0 displacement solve of load "
+                "step 1, QP update and staggered residual)",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{problem.name}: load step 1, k=0 displacement solve with one Newton "
-                   f"iteration (assembled CSR + SuperLU), {t:.1f} s wall, {cpu_s:.1f} s CPU "
-                   f"({cores} host core{'s' if cores > 1 else ''}); "
-                   f"rate = GPU CG DOF-updates for the same sample ({gpu_updates:.3e}) / "
-                   f"oracle time"),
-        "seconds": t,
+        "sample": (f"{problem.name} ({2 * (problem.nx + 1) * (problem.ny + 1)} displacement "
+                   f"DOF): load step 1, k = 0 displacement solve with one Newton iteration "
+                   f"(assembled CSR + SuperLU), {t:.1f} s wall, {cpu_s:.1f} s CPU "
+                   f"({cores} host core{'s' if cores > 1 else ''}); the GPU's ST FP64 run of "
+                   f"the same sample took {t_gpu * 1e3:.1f} ms"),
+        "gpu_same_sample_s": t_gpu,
+        "oracle_over_gpu": t / t_gpu,
     }
 
 
@@ -372,30 +459,47 @@ def run_slab3d(pf, args):
 
 
 def run_sweep(pf, args):
-    """Batched vs one-by-one throughput of the 64-instance sweep."""
+    """Batched vs one-by-one throughput of the 64-instance sweep.  Modes
+    (--sweep-modes): shared CG launches, concurrent streams, one by one;
+    value is the first listed mode's GDOF-updates/s.  Each mode runs load
+    steps 1..W untimed, then W+1..W+K timed, of every instance."""
     import torch
 
     import workloads as W
     probs = W.batch_instances()
     steps, warm = args.steps, args.warmup
-    # one by one: each instance alone on the default stream
-    chosen, t_seq, upd_seq, forces_seq = [], 0.0, 0.0, []
-    for i, p in enumerate(probs):
-        ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED, march_rows=args.sweep_rows)
-        chosen.append(ctx.autotune(10) if args.sweep_rows == 0 else args.sweep_rows)
-        for n in range(warm):
-            ctx.load_step(float(p.loads[n]))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rows = [ctx.load_step(float(p.loads[n])) for n in range(warm, warm + steps)]
-        torch.cuda.synchronize()
-        t_seq += time.perf_counter() - t0
-        upd_seq += sum(r["dof_updates"] for r in rows)
-        forces_seq.append([r["force"] for r in rows])
-        ctx.close()
-        if (i + 1) % 16 == 0:
-            log(f"  one by one: {i + 1}/64 instances, {t_seq:.1f} s timed")
-    # batched, both modes: members on their own streams, same work-item heights
+    if warm + steps > min(len(p.loads) for p in probs):
+        raise SystemExit("warmup + steps exceeds the instances' load history")
+    modes = [m.strip() for m in args.sweep_modes.split(",") if m.strip()]
+    if not modes or any(m not in ("shared", "streams", "one") for m in modes):
+        raise SystemExit("--sweep-modes: a comma list of shared, streams, one")
+    chosen = [args.sweep_rows] * len(probs)
+    if args.sweep_rows == 0:
+        for i, p in enumerate(probs):
+            ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED, march_rows=0)
+            chosen[i] = ctx.autotune(10)
+            ctx.close()
+    res = {}
+
+    def one_by_one():
+        t, upd, forces, rows_all = 0.0, 0.0, [], []
+        for i, p in enumerate(probs):
+            ctx = pf.Context(p, scheme=pf.S1, precision=pf.MIXED, march_rows=chosen[i])
+            for n in range(warm):
+                ctx.load_step(float(p.loads[n]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rows = [ctx.load_step(float(p.loads[n])) for n in range(warm, warm + steps)]
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            upd += sum(r["dof_updates"] for r in rows)
+            forces.append([r["force"] for r in rows])
+            rows_all.append(rows)
+            ctx.close()
+            if (i + 1) % 16 == 0:
+                log(f"  one by one: {i + 1}/64 instances, {t:.1f} s timed")
+        return t, upd, forces, rows_all
+
     def batched(shared):
         streams = [torch.cuda.Stream() for _ in probs]
         ctxs = [pf.Context(p, scheme=pf.S1, precision=pf.MIXED, stream=st.cuda_stream,
@@ -405,40 +509,56 @@ def run_sweep(pf, args):
             B.load_step([float(p.loads[n]) for p in probs])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rows = [B.load_step([float(p.loads[n]) for p in probs])
-                for n in range(warm, warm + steps)]
+        rows = []
+        for n in range(warm, warm + steps):
+            rows.append(B.load_step([float(p.loads[n]) for p in probs]))
+            if (n + 1) % 5 == 0:
+                log(f"  {'shared launches' if shared else 'concurrent streams'}: load step "
+                    f"{n + 1}, {time.perf_counter() - t0:.1f} s, max N_stag "
+                    f"{max(r['n_stag'] for r in rows[-1])}")
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         B.close()
         for c in ctxs:
             c.close()
         upd = sum(r["dof_updates"] for rr in rows for r in rr)
-        same = all(rows[k][i]["force"] == forces_seq[i][k]
-                   for i in range(len(probs)) for k in range(steps))
-        log(f"  batched ({'shared launches' if shared else 'concurrent streams'}): {t:.2f} s, "
-            f"identical to one by one: {same}")
-        return t, upd, same
-    t_str, upd_str, same_str = batched(False)
-    t_bat, upd_bat, same = batched(True)
+        forces = [[rows[k][i]["force"] for k in range(steps)] for i in range(len(probs))]
+        rows_t = [[rows[k][i] for k in range(steps)] for i in range(len(probs))]
+        return t, upd, forces, rows_t
+
+    for m in modes:
+        if m == "one":
+            res[m] = one_by_one()
+        else:
+            res[m] = batched(m == "shared")
+        log(f"  {m}: {res[m][0]:.2f} s, {res[m][1] / res[m][0] / 1e9:.1f} GDOF-updates/s")
+    ref = res[modes[0]]
+    same = {m: res[m][2] == ref[2] for m in modes[1:]}
+    rows_ref = ref[3]
+    n_stag = [sum(r["n_stag"] for r in rr) for rr in rows_ref]
+    capped = sum(1 for rr in rows_ref for r in rr if not r["converged"])
     sizes = [p.nx for p in probs]
-    value = upd_bat / t_bat / 1e9
-    return {
+    names = {"shared": "shared_launches", "streams": "concurrent_streams", "one": "one_by_one"}
+    out = {
         "metric": "GDOF-updates/s, 64-instance S1 mixed sweep, batched vs one by one, 1 MI355X",
-        "value": value, "unit": "GDOF-updates/s", "n_gpus": 1, "steps": steps,
-        "warmup": warm, "ms_per_step": t_bat * 1e3 / steps, "higher_is_better": True,
+        "value": ref[1] / ref[0] / 1e9, "unit": "GDOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": ref[0] * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": (f"sweep64: 64 seeded notched tension instances, meshes "
                                 f"{min(sizes)}^2..{max(sizes)}^2 (sum {sum(s * s for s in sizes)} "
                                 f"elements), load steps {warm + 1}..{warm + steps} of 50"),
                    "scheme": "S1", "precision": "mixed", "workers": args.workers,
-                   "march_rows": sorted(set(chosen))},
-        "one_by_one": {"value": upd_seq / t_seq / 1e9, "seconds": t_seq},
-        "concurrent_streams": {"value": upd_str / t_str / 1e9, "seconds": t_str,
-                               "identical_forces": same_str},
-        "batched_seconds": t_bat,
-        "speedup_batched_vs_one_by_one": t_seq / t_bat,
-        "identical_forces": same,
+                   "march_rows": sorted(set(chosen)), "mode": names[modes[0]]},
+        "staggered_iterations_per_instance": n_stag,
+        "steps_at_max_stag": capped,
     }
+    for m in modes:
+        t, upd = res[m][0], res[m][1]
+        out[names[m]] = {"value": upd / t / 1e9, "seconds": t,
+                         "identical_forces_to_first_mode": same.get(m, True)}
+    if "one" in res and modes[0] != "one":
+        out["speedup_vs_one_by_one"] = res["one"][0] / ref[0]
+    return out
 
 
 def run_apply_sizes(pf, args):
@@ -577,6 +697,12 @@ def main():
                     help="staggered iteration cap of the trial-readings and oracle-history "
                          "modes (0: the problem's)")
     ap.add_argument("--workers", type=int, default=16, help="host workers of the sweep batch")
+    ap.add_argument("--sweep-modes", default="shared,streams,one",
+                    help="sweep64: comma list of modes to run (shared launches, concurrent "
+                         "streams, one by one); value is the first mode's throughput")
+    ap.add_argument("--schemes", default="",
+                    help="comma list of further fixed-stress schemes (S2, S3) run in mixed "
+                         "precision on the same window as S1 mixed, reported beside it")
     ap.add_argument("--jacobi", action="store_true",
                     help="plain Jacobi instead of Jacobi-Chebyshev for both schemes")
     ap.add_argument("--s1-degree", type=int, default=3, help="Chebyshev degree, S1 mixed")
@@ -603,6 +729,11 @@ def main():
                     help="time only the ST FP64 run (long histories in separate jobs)")
     ap.add_argument("--full-history", action="store_true",
                     help="time the whole load history (warmup 0, all steps) for both schemes")
+    ap.add_argument("--window-end", type=int, default=-1,
+                    help="last timed load step: load steps 1..end-steps-warmup run first "
+                         "(S1 mixed, untimed) and both schemes start from that state; default "
+                         "91 on tension512 (the step in which the crack runs through the "
+                         "ligament), else warmup + steps from the initial state")
     ap.add_argument("--at1", action="store_true",
                     help="AT1 with penalised irreversibility instead of AT2 with the history "
                          "field, for both schemes")
@@ -651,6 +782,14 @@ def main():
         problem = dataclasses.replace(problem, phase_model=1)
     if args.full_history:
         args.warmup, args.steps = 0, len(problem.loads)
+        args.window_end = len(problem.loads)
+    if args.window_end < 0:
+        args.window_end = (NUCLEATION_STEP_512 if args.workload == "tension512"
+                           else args.warmup + args.steps)
+    start = args.window_end - args.steps - args.warmup
+    if start < 0 or args.window_end > len(problem.loads):
+        raise SystemExit("the window (warmup + steps ending at --window-end) does not fit the "
+                         "load history")
     if args.copy_calibration:
         # plain elementwise kernels of known size for counter scaling: a fill
         # (256 MiB written) and a scale-copy (256 MiB read + 256 MiB written)
@@ -660,34 +799,35 @@ def main():
             torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    if args.warmup + args.steps > len(problem.loads):
-        raise SystemExit("warmup + steps exceeds the load history")
-
     s1_deg, st_deg = (None, None) if args.jacobi else (args.s1_degree, args.st_degree)
     jsonl = open(args.stats_jsonl, "w") if args.stats_jsonl else None
     if args.st_only:
         log(f"ST FP64 on {problem.name}")
+        state = prefix_state(pf, problem, start, s1_deg, args.rows)
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
                                        degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows,
-                                       jsonl=jsonl, label="st_fp64")
+                                       jsonl=jsonl, label="st_fp64", start=start, state=state)
         print(json.dumps({
             "metric": "time per load step, ST FP64 (comparison run)",
             "value": secs2 * 1e3 / args.steps, "unit": "ms/step", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs2 * 1e3 / args.steps,
             "higher_is_better": False, "seconds": secs2,
             "gdof_updates_per_s": sum(r["dof_updates"] for r in rows2) / secs2 / 1e9,
-            "n_stag": [r["n_stag"] for r in rows2],
-            "time_ms": [round(r["time_ms"], 1) for r in rows2],
+            "max_stag": problem.max_stag, "steps_table": step_table(rows2),
             "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
             "march_rows": ctx2.chosen_rows, "dtype": "f64", "data": "synthetic"}))
         ctx2.close()
         if jsonl:
             jsonl.close()
         return
+    log(f"{problem.name}: load steps 1..{start} (S1 mixed, untimed) give both runs their "
+        f"starting state")
+    state = prefix_state(pf, problem, start, s1_deg, args.rows)
     log(f"S1 mixed on {problem.name}")
     ctx, rows, secs = run_steps(pf, problem, pf.S1, pf.MIXED, args.warmup, args.steps,
                                 profile=True, degree=s1_deg, tune_reps=args.tune_reps,
-                                rows=args.rows, jsonl=jsonl, label="s1_mixed")
+                                rows=args.rows, jsonl=jsonl, label="s1_mixed", start=start,
+                                state=state)
     updates = sum(r["dof_updates"] for r in rows)
     value = updates / secs / 1e9
     ms_per_step = secs * 1e3 / args.steps
@@ -701,40 +841,77 @@ def main():
     cands = [(ma / max(la, 1), la, ma / max(la, 1), fused_apply_bytes_per_node(),
               f"k_cg_apply<{rows_s1}, OpTangent<float>> (fused CG direction update + "
               f"tangent apply)")]
+    two = rows_s1 == 1 and s1_deg is not None and s1_deg >= 3   # tiles: two steps fused
     if s1_deg and s1_deg >= 2 and lf:
-        cands.append((mf / lf, lf, mf / lf, updcheb_bytes_per_node(),
-                      f"k_cg_updcheb<{rows_s1}, OpUpdCheb<OpTangent<float>>> (CG update fused "
-                      f"with the first Chebyshev step)"))
-    if s1_deg and s1_deg >= 3 and lc:
-        cands.append(((s1_deg - 2) * mc / lc, lc, mc / lc, cheb_step_bytes_per_node(),
+        if two:
+            cands.append((mf / lf, lf, mf / lf, updcheb2_bytes_per_node(s1_deg == 3),
+                          "k_cg_updcheb2<OpTangent<float>> (CG update fused with the first two "
+                          "Chebyshev steps)"))
+        else:
+            cands.append((mf / lf, lf, mf / lf, updcheb_bytes_per_node(),
+                          f"k_cg_updcheb<{rows_s1}, OpUpdCheb<OpTangent<float>>> (CG update "
+                          f"fused with the first Chebyshev step)"))
+    further = (s1_deg - 3) if two else ((s1_deg - 2) if s1_deg else 0)
+    if further > 0 and lc:
+        cands.append((further * mc / lc, lc, mc / lc, cheb_step_bytes_per_node(),
                       f"k_march<{rows_s1}, OpCheb<OpTangent<float>>> (Jacobi-Chebyshev step)"))
     _, launches, avg_ms, bpn, kname = max(cands, key=lambda c: c[0])
     alg_bytes = bpn * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     ctx.close()
 
+    extra = {}
+    for name in [x.strip().upper() for x in args.schemes.split(",") if x.strip()]:
+        if name not in ("S2", "S3"):
+            raise SystemExit(f"--schemes: unknown scheme {name}")
+        log(f"{name} mixed on {problem.name}")
+        ctx3, rows3, secs3 = run_steps(pf, problem, {"S2": pf.S2, "S3": pf.S3}[name], pf.MIXED,
+                                       args.warmup, args.steps, degree=s1_deg,
+                                       tune_reps=args.tune_reps, rows=args.rows, jsonl=jsonl,
+                                       label=f"{name.lower()}_mixed", start=start, state=state)
+        extra[f"{name.lower()}_mixed"] = {
+            "seconds": secs3, "ms_per_step": secs3 * 1e3 / args.steps,
+            "gdof_updates_per_s": sum(r["dof_updates"] for r in rows3) / secs3 / 1e9,
+            "steps": step_table(rows3)}
+        ctx3.close()
+
     st_res = None
     if not args.no_st:
         log(f"ST FP64 on {problem.name}")
         ctx2, rows2, secs2 = run_steps(pf, problem, pf.ST, pf.FP64, args.warmup, args.steps,
                                        degree=st_deg, tune_reps=args.tune_reps, rows=args.st_rows,
-                                       jsonl=jsonl, label="st_fp64")
+                                       jsonl=jsonl, label="st_fp64", start=start, state=state)
         upd2 = sum(r["dof_updates"] for r in rows2)
         st_res = {
+            "seconds": secs2,
             "ms_per_step": secs2 * 1e3 / args.steps,
             "gdof_updates_per_s": upd2 / secs2 / 1e9,
-            "n_stag": [r["n_stag"] for r in rows2],
-            "time_ms": [round(r["time_ms"], 1) for r in rows2],
             "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
             "march_rows": ctx2.chosen_rows,
+            "steps": step_table(rows2),
         }
         ctx2.close()
+
+    # speedup over the whole window and over the steps both runs converged
+    conv = None
+    if st_res:
+        both = [(a, b) for a, b in zip(rows, rows2) if a["converged"] and b["converged"]]
+        t_s1 = sum(a["time_ms"] for a, _ in both)
+        t_st = sum(b["time_ms"] for _, b in both)
+        conv = {"steps": [a["step"] for a, _ in both],
+                "s1_mixed_ms": t_s1, "st_fp64_ms": t_st,
+                "speedup": (t_st / t_s1) if t_s1 > 0 else None}
+    capped = {"s1_mixed": [r["step"] for r in rows if not r["converged"]],
+              "st_fp64": [r["step"] for r in rows2 if not r["converged"]] if st_res else None}
+    copy_gbs = copy_bandwidth()
+    log(f"device copy (1 GiB): {copy_gbs:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline sample")
         cpu = cpu_baseline(pf, problem)
 
+    traffic, traffic_src = measured_traffic(kname)
     out = {
         "metric": METRIC,
         "value": value,
@@ -750,9 +927,15 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{problem.name}: {problem.nx}x{problem.ny} Q1 {KIND[args.workload]}, "
-                         f"l={problem.material.l} mm, load steps {args.warmup + 1}.."
-                         f"{args.warmup + args.steps} of {len(problem.loads)} x "
-                         f"{problem.loads[0]:.2g} mm"),
+                         f"l={problem.material.l} mm, load steps {start + args.warmup + 1}.."
+                         f"{start + args.warmup + args.steps} of {len(problem.loads)} x "
+                         f"{problem.loads[0]:.2g} mm"
+                         + (f" (both runs from the S1 mixed state after step {start}, then "
+                            f"{args.warmup} untimed steps)" if start > 0 else "")
+                         + (" ending in the step where the crack runs through the ligament"
+                            if args.workload == "tension512"
+                            and args.window_end == NUCLEATION_STEP_512 else "")),
+            "max_stag": problem.max_stag,
             "scheme": "S1", "precision": "mixed (FP32 inner CG, FP64 outer)",
             "precond": "jacobi" if s1_deg is None else f"jacobi-chebyshev degree {s1_deg}",
             "march_rows": rows_s1,
@@ -760,10 +943,12 @@ def main():
             "phase_model": ("AT1 with penalised irreversibility" if args.at1
                             else "AT2 with history field"),
         },
-        "s1_mixed": {"n_stag": [r["n_stag"] for r in rows],
-                     "time_ms": [round(r["time_ms"], 1) for r in rows]},
+        "s1_mixed": {"seconds": secs, "steps": step_table(rows)},
         "st_fp64": st_res,
         "speedup_s1_mixed_vs_st_fp64": (st_res["ms_per_step"] / ms_per_step) if st_res else None,
+        "speedup_converged_steps": conv,
+        **extra,
+        "steps_at_max_stag": capped,
         "roofline": {
             "kernel": kname,
             "bound": "hbm",
@@ -771,15 +956,16 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kname),
+            "traffic": traffic,
+            "traffic_source": traffic_src,
             "avg_launch_us": avg_ms * 1e3,
             "sampled_launches": launches,
             "bytes_per_launch": alg_bytes,
+            "copy_GBs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "cpu_baseline": cpu,
     }
-    if cpu is not None:
-        cpu.pop("seconds", None)
     if jsonl:
         jsonl.close()
     print(json.dumps(out))

@@ -123,7 +123,10 @@ typedef struct {
   double tol_stag;      /* staggered tolerance on ||R_d||/||b|| (Section 3.1) */
   double tol_pcg;       /* relative tolerance of each linear correction solve */
   double tol_newton;    /* Newton: ||R_u|| <= tol_newton * ||R_u(lifted)||    */
-  double tol_inner;     /* PF_MIXED: relative tolerance of FP32 inner CG      */
+  double tol_inner;     /* PF_MIXED: tightest relative tolerance of an FP32   */
+                        /* inner CG.  A displacement solve asks for          */
+                        /* min(0.1, max(tol_inner, 0.1 tol/||R_u||)), tol    */
+                        /* being the Newton target (inexact Newton)          */
   int32_t max_stag;     /* max u-solves per load step (k = 0 included)        */
   int32_t max_newton;   /* max Newton iterations per u-solve                  */
   int32_t max_cg;       /* max CG iterations per linear solve                 */
@@ -160,6 +163,11 @@ typedef struct {
   double dof_updates;   /* sum over CG solves of free DOFs x iterations       */
   int32_t converged;    /* 1 if r_stag <= tol_stag and Newton converged       */
   int32_t cg_not_converged; /* linear solves that hit max_cg                  */
+  double time_u_ms;     /* host wall time of the displacement solves (Newton, */
+                        /* k = 0 included)                                    */
+  double time_d_ms;     /* host wall time of the phase part of k >= 1: trial, */
+                        /* predictor and evolution solve (the paper's split   */
+                        /* of wall time into d- and u-solves, Section 4.4)    */
 } pf_step_stats;
 
 /* Fill *opts with defaults: ST, FP64, Jacobi (cheb_degree 3), tol_stag 1e-5, tol_pcg 1e-10,
@@ -296,9 +304,10 @@ pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
  * Single-kernel CG solves time that kernel (a whole iteration); two-kernel
  * CG solves time the fused operator apply and their vector update.  The
  * update is one launch between the events, except with Jacobi-Chebyshev of
- * degree >= 2, where it is fused with the first polynomial step into a
- * repeatable operator kernel timed like the apply.  The next polynomial
- * step of the displacement solves (degree >= 3, repeatable) is timed too.
+ * degree >= 2, where it is fused with the first polynomial step (with the
+ * first two steps on LDS tiles, degree >= 3) into a repeatable operator
+ * kernel timed like the apply.  The next separate polynomial step of the
+ * displacement solves (repeatable) is timed too.
  * kernel: 0 = elasticity CG kernel, 1 = phase CG kernel, 2 = vector update
  * (fused with the first Chebyshev step where it applies) of the
  * displacement solves, 3 = elasticity Chebyshev step.  Enabling resets the

@@ -79,7 +79,8 @@ class StepStats(ctypes.Structure):
                 ("n_cg_trial", c_int64), ("gated_max", c_int64), ("floor_hits", c_int64),
                 ("r_stag", c_double), ("force", c_double * 2), ("time_ms", c_double),
                 ("dof_updates", c_double), ("converged", c_int32),
-                ("cg_not_converged", c_int32)]
+                ("cg_not_converged", c_int32), ("time_u_ms", c_double),
+                ("time_d_ms", c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

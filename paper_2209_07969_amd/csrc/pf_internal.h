@@ -310,6 +310,23 @@ hipError_t phase_updcheb(hipStream_t s, const Grid &g, const March &m, const Pha
                          const T *x_in, T *x_out, const T *r_in, T *r_out, const T *p,
                          const T *q, const T *Dinv, T *dnext, T *z_out, T *res_out,
                          const CgArgs &ca, const ChebStep &s0, const ChebStep &s1);
+// The same update fused with the first two Chebyshev steps (LDS tiles only,
+// m.ch == 1; degree >= 3): writes x_out, r_out, z_out and, unless s2 is the
+// last step, d2 into dnext and res2 into res_out; s2 is step 2 of the
+// polynomial.
+template <class T>
+hipError_t tangent_updcheb2(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *x_in, T *x_out,
+                            const T *r_in, T *r_out, const T *p, const T *q, const T *Dinv,
+                            T *dnext, T *z_out, T *res_out, const CgArgs &ca,
+                            const ChebStep &s2);
+template <class T>
+hipError_t phase_updcheb2(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                          const T *x_in, T *x_out, const T *r_in, T *r_out, const T *p,
+                          const T *q, const T *Dinv, T *dnext, T *z_out, T *res_out,
+                          const CgArgs &ca, const ChebStep &s2);
 // Power iteration step for lambda_max(D^-1 A): vnext = D^-1 A (scale v);
 // scal[SC_NORM_A] = v'Av and scal[SC_NORM_B] = v'Dv (of the scaled v).
 template <class T>

@@ -39,6 +39,7 @@ constexpr double GA = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
 constexpr double GB = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
 constexpr int WPB = 4;                            // waves per block (march)
 constexpr int TPB = 256;
+static_assert(kPMax % TPB == 0, "block_sum reads kPMax / TPB partials per thread");
 
 // ------------------------------------------------------- lane shifts
 
@@ -104,11 +105,11 @@ __device__ inline void block_partial_at(double (&v)[NV], double *part, int bid) 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += sh[k][w];
+#pragma unroll
+      for (int w = 0; w < TPB / 64; ++w) s += sh[k][w];
       part[k * kPMax + bid] = s;
     }
   }
@@ -119,24 +120,40 @@ __device__ inline void block_partial(double (&v)[NV], double *part) {
   block_partial_at<NV>(v, part, blockIdx.x);
 }
 
-// Fixed-order sum of np partials written by an earlier kernel, returned in
-// every thread of the block (bit-identical in every block).
+// Fixed-order sum of np <= kPMax partials written by an earlier kernel,
+// returned in every thread of the block (bit-identical in every block).
+// Thread t adds partials t, t + TPB, t + 2 TPB, ... in that order.  Every
+// load is issued before the first add, so the prologue of a kernel costs one
+// memory round trip instead of one per partial a thread reads (a loop that
+// adds as it loads waits for each load in turn).  Absent partials add 0.
 template <int NV>
 __device__ inline void block_sum(const double *part, int np, double (&out)[NV]) {
+  constexpr int R = kPMax / TPB;
   __shared__ double sh[NV][TPB / 64];
+  double v[NV][R];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int b = threadIdx.x + r * TPB;
+      v[k][r] = b < np ? part[k * kPMax + b] : 0.0;
+    }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < np; b += blockDim.x) s += part[k * kPMax + b];
+    // the sum starts from the first value itself (an add of 0.0 there would
+    // be placed with its load and wait for it)
+    double s = v[k][0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) s += v[k][r];
     s = wave_sum_last(s);
     if ((threadIdx.x & 63) == 63) sh[k][threadIdx.x >> 6] = s;
   }
   __syncthreads();
-  const int nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[k][w];
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w) s += sh[k][w];
     out[k] = s;
   }
   __syncthreads();
@@ -1402,6 +1419,266 @@ __device__ inline void cg_updcheb_run(Op op, const Grid &g, const March &ms, con
 template <int CH, class Op>
 __global__ void __launch_bounds__(TPB) k_cg_updcheb(Op op, Grid g, March ms, CgArgs ca) {
   cg_updcheb_run<CH>(op, g, ms, ca, blockIdx.x, gridDim.x);
+}
+
+// ---- CG update fused with the first two Jacobi-Chebyshev steps (LDS tiles)
+//
+// The block of a tile of kTile x kTile owned nodes stages the (kTile+4)^2
+// nodes around it, a ring of two.  Pass 1: every staged node takes
+// r_new = r - alpha q (while the CG is active) and d0 = D^-1 r_new / theta;
+// the (kTile+3)^2 elements among them apply the operator to d0, and the
+// (kTile+2)^2 nodes of the tile and its first ring form res1 = r_new - A d0,
+// d1 = c1 d0 + c2 D^-1 res1 and z1 = d0 + d1.  Pass 2: the (kTile+1)^2
+// elements touching the tile apply the operator to d1, and the owned nodes
+// form res2 = res1 - A d1, d2 = c3 d1 + c4 D^-1 res2 and z2 = z1 + d2.
+// Owned nodes write x + alpha p and r_new to the other buffer of each pair,
+// z2 and, when more steps follow, d2 and res2; when the polynomial ends
+// here they write the partials of r.z and r.r instead.  Node for node this
+// is the arithmetic of the fused update and one further Chebyshev step
+// (OpUpdCheb, OpCheb), without the second launch and without writing and
+// re-reading d1, z1 and res1.  Both neighbouring tiles compute the first
+// ring.  Nothing it reads is written, so a launch may be repeated.
+constexpr int kU2N = kTile + 4;   // staged nodes per side
+constexpr int kU2E = kTile + 3;   // pass-1 elements per side
+constexpr int kU2M = kTile + 2;   // pass-1 nodes per side (tile and first ring)
+
+template <class Base>
+struct UpdCheb2 {
+  using T = typename Base::T;
+  Base base;
+  const T *x; const T *r; T *xo; T *ro; const T *p; const T *q; const T *Dinv;
+  T *dnext; T *zo; T *reso;
+  int N;
+  const double *cf;   // cf[0] = 1/theta; cf[1], cf[2]: step 1; cf[3], cf[4]: step 2
+  int last;           // step 2 is the polynomial's last
+};
+
+template <class Base>
+struct UpdCheb2Lds {
+  using T = typename Base::T;
+  static constexpr int NF = Base::NF;
+  typename Base::Node a[kU2N * kU2N];   // operator input d0, staged nodes
+  typename Base::Node b[kU2M * kU2M];   // operator input d1, tile and first ring
+  typename Base::Own own[kU2N * kU2N];
+  typename Base::Elem el[kU2E * kU2E];
+  T rn[NF][kU2N * kU2N];                // r_new
+  T di[NF][kU2N * kU2N];                // D^-1
+  T rs1[NF][kU2M * kU2M];
+  T z1[NF][kU2M * kU2M];
+  T f[NF][4][kU2E * kU2E];              // element corner values, both passes
+};
+
+template <class Base>
+struct UpdCheb2Regs {
+  using T = typename Base::T;
+  static constexpr int NF = Base::NF;
+  static constexpr int NSL = (kU2N * kU2N + TPB - 1) / TPB;
+  static constexpr int NEL = (kU2E * kU2E + TPB - 1) / TPB;
+  typename Base::Node n[NSL];
+  typename Base::Own o[NSL];
+  T r[NSL][NF], q[NSL][NF], di[NSL][NF];
+  typename Base::Elem e[NEL];
+  T x[NF], p[NF];   // the thread's owned node
+};
+
+template <class Base>
+__device__ inline void updcheb2_load(const UpdCheb2<Base> &op, const Grid &g, const March &ms,
+                                     int tile, UpdCheb2Regs<Base> &tr) {
+  using T = typename Base::T;
+  constexpr int NF = Base::NF;
+  const int i0 = (tile % ms.nstrips) * kTile - 2, j0 = (tile / ms.nstrips) * kTile - 2;
+#pragma unroll
+  for (int r = 0; r < UpdCheb2Regs<Base>::NSL; ++r) {
+    const int k = threadIdx.x + r * TPB;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) tr.r[r][f] = tr.q[r][f] = tr.di[r][f] = T(0);
+    if (k < kU2N * kU2N) {
+      const int i = i0 + k % kU2N, j = j0 + k / kU2N;
+      tr.n[r] = op.base.load_aux(i, j);
+      tr.o[r] = op.base.load_own(i, j);
+      if (node_exists(g, i, j)) {
+        const int idx = i + j * (g.nx + 1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          tr.r[r][f] = op.r[idx + f * op.N];
+          tr.q[r][f] = op.q[idx + f * op.N];
+          tr.di[r][f] = op.Dinv[idx + f * op.N];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
+    const int e = threadIdx.x + r * TPB;
+    if (e < kU2E * kU2E) tr.e[r] = op.base.eload(i0 + e % kU2E, j0 + e / kU2E);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) tr.x[f] = tr.p[f] = T(0);
+  if (threadIdx.x < kTile * kTile) {
+    const int i = i0 + 2 + threadIdx.x % kTile, j = j0 + 2 + threadIdx.x / kTile;
+    if (node_exists(g, i, j)) {
+      const int idx = i + j * (g.nx + 1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        tr.x[f] = op.x[idx + f * op.N];
+        tr.p[f] = op.p[idx + f * op.N];
+      }
+    }
+  }
+}
+
+template <class Base>
+__device__ inline void updcheb2_compute(const UpdCheb2<Base> &op, const Grid &g, const March &ms,
+                                        int tile, const UpdCheb2Regs<Base> &tr,
+                                        UpdCheb2Lds<Base> &sm, bool act, typename Base::T alpha,
+                                        double (&red)[2]) {
+  using T = typename Base::T;
+  constexpr int NF = Base::NF;
+  const Base &B = op.base;
+  const T c0 = T(op.cf[0]), c1 = T(op.cf[1]), c2 = T(op.cf[2]), c3 = T(op.cf[3]),
+          c4 = T(op.cf[4]);
+  // stage: r_new and d0 on every staged node
+#pragma unroll
+  for (int r = 0; r < UpdCheb2Regs<Base>::NSL; ++r) {
+    const int k = threadIdx.x + r * TPB;
+    if (k < kU2N * kU2N) {
+      T d0[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        T rn = tr.r[r][f];
+        if (act) rn = rn - alpha * tr.q[r][f];
+        sm.rn[f][k] = rn;
+        sm.di[f][k] = tr.di[r][f];
+        d0[f] = tr.di[r][f] * rn * c0;
+      }
+      typename Base::Node n = tr.n[r];
+      B.set_u(n, d0);
+      sm.a[k] = n;
+      sm.own[k] = tr.o[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
+    const int e = threadIdx.x + r * TPB;
+    if (e < kU2E * kU2E) sm.el[e] = tr.e[r];
+  }
+  __syncthreads();
+  // pass 1: A d0 on the (kTile+3)^2 elements of the staged nodes
+#pragma unroll
+  for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
+    const int e = threadIdx.x + r * TPB;
+    if (e < kU2E * kU2E) {
+      const int b = (e / kU2E) * kU2N + e % kU2E;
+      T fe[NF][4];
+      B.element(sm.a[b], sm.a[b + 1], sm.a[b + kU2N + 1], sm.a[b + kU2N], sm.el[e], fe);
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sm.f[f][c][e] = fe[f][c];
+    }
+  }
+  __syncthreads();
+  // pass 1 nodes: staged node (a, b), 1 <= a, b <= kTile + 2, is corner 2 of
+  // element (a-1, b-1), 3 of (a, b-1), 1 of (a-1, b) and 0 of (a, b)
+  for (int m = threadIdx.x; m < kU2M * kU2M; m += TPB) {
+    const int a = 1 + m % kU2M, b = 1 + m / kU2M;
+    const int k = b * kU2N + a, e = (b - 1) * kU2E + (a - 1);
+    T d0[NF], d1[NF];
+    B.get_u(sm.a[k], d0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T Ad = sm.f[f][2][e] + sm.f[f][3][e + 1] + sm.f[f][1][e + kU2E] + sm.f[f][0][e + kU2E + 1];
+      if (Base::masked_own(sm.own[k], f)) Ad = T(0);
+      const T rs = sm.rn[f][k] - Ad;
+      const T dk = c1 * d0[f] + c2 * sm.di[f][k] * rs;
+      sm.rs1[f][m] = rs;
+      sm.z1[f][m] = d0[f] + dk;
+      d1[f] = dk;
+    }
+    typename Base::Node n = sm.a[k];
+    B.set_u(n, d1);
+    sm.b[m] = n;
+  }
+  __syncthreads();
+  // pass 2: A d1 on the (kTile+1)^2 elements touching the tile; element
+  // (a, b), 1 <= a, b <= kTile + 1, has corner 0 at pass-1 node (a, b)
+  {
+    static_assert(kTileE * kTileE == TPB, "one pass-2 element per thread");
+    const int a = 1 + threadIdx.x % kTileE, b = 1 + threadIdx.x / kTileE;
+    const int m0 = (b - 1) * kU2M + (a - 1);
+    T fe[NF][4];
+    B.element(sm.b[m0], sm.b[m0 + 1], sm.b[m0 + kU2M + 1], sm.b[m0 + kU2M],
+              sm.el[b * kU2E + a], fe);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm.f[f][c][threadIdx.x] = fe[f][c];
+  }
+  __syncthreads();
+  // owned nodes: staged node (2 + li, 2 + lj)
+  if (threadIdx.x < kTile * kTile) {
+    const int li = threadIdx.x % kTile, lj = threadIdx.x / kTile;
+    const int i = (tile % ms.nstrips) * kTile + li, j = (tile / ms.nstrips) * kTile + lj;
+    if (i <= g.nx && j <= g.ny) {
+      const int e = lj * kTileE + li;
+      const int m = (lj + 1) * kU2M + (li + 1), k = (lj + 2) * kU2N + (li + 2);
+      const int gk = i + j * (g.nx + 1);
+      T d1[NF];
+      B.get_u(sm.b[m], d1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        T Ad = sm.f[f][2][e] + sm.f[f][3][e + 1] + sm.f[f][1][e + kTileE] +
+               sm.f[f][0][e + kTileE + 1];
+        if (Base::masked_own(sm.own[k], f)) Ad = T(0);
+        const T rs = sm.rs1[f][m] - Ad;
+        const T dk = c3 * d1[f] + c4 * sm.di[f][k] * rs;
+        const T z = sm.z1[f][m] + dk;
+        const T rn = sm.rn[f][k];
+        const int idx = gk + f * op.N;
+        op.zo[idx] = z;
+        if (op.last) {
+          red[0] += double(rn) * double(z);
+          red[1] += double(rn) * double(rn);
+        } else {
+          op.dnext[idx] = dk;
+          op.reso[idx] = rs;
+        }
+        if (act) {
+          op.xo[idx] = tr.x[f] + alpha * tr.p[f];
+          op.ro[idx] = rn;
+        }
+      }
+    }
+  }
+  __syncthreads();   // the LDS is reused by the block's next tile
+}
+
+template <class Base>
+__global__ void __launch_bounds__(TPB) k_cg_updcheb2(UpdCheb2<Base> op, Grid g, March ms,
+                                                     CgArgs ca) {
+  using T = typename Base::T;
+  __shared__ UpdCheb2Lds<Base> sm;
+  const int bid = blockIdx.x, nb = gridDim.x;
+  const int nt = ms.nstrips * ms.nchunks;
+  double red[2] = {0.0, 0.0};
+  double alpha = 0.0;
+  int t = xcd_block(bid, nb);
+  // the first tile's loads are in flight during the prologue's reduction
+  UpdCheb2Regs<Base> tr;
+  if (t < nt) updcheb2_load(op, g, ms, t, tr);
+  const bool act = cg_update_prologue(ca, &alpha, bid);
+  for (; t < nt; t += nb) {
+    updcheb2_compute(op, g, ms, t, tr, sm, act, T(alpha), red);
+    if (t + nb < nt) updcheb2_load(op, g, ms, t + nb, tr);
+  }
+  if (op.last) block_partial_at<2>(red, ca.partB, bid);
+  if (act && bid == 0 && threadIdx.x == 0) {
+    ca.st->b.rz_prev = ca.st->a.rz;
+    ca.st->b.rr0 = ca.st->a.rr0;
+    ca.st->b.done = 0;
+    ca.st->b.iters = ca.st->a.iters + 1;
+    ca.st->b.first = 0;
+  }
 }
 
 // Elements per thread whose operands are loaded before the scalars.
@@ -2847,6 +3124,48 @@ hipError_t phase_updcheb(hipStream_t s, const Grid &g, const March &m, const Pha
   return launch_updcheb(s, op, g, m, ca);
 }
 
+template <class Base>
+hipError_t launch_updcheb2(hipStream_t s, const UpdCheb2<Base> &op, const Grid &g,
+                           const March &m, const CgArgs &ca) {
+  if (m.ch != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_updcheb2<Base>), dim3(march_blocks(m)), dim3(TPB), 0, s,
+                     op, g, m, ca);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t tangent_updcheb2(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                            int split, const T *ulin, const T *d, const uint8_t *qflag,
+                            const uint8_t *eact, const uint8_t *nflag, const T *x_in, T *x_out,
+                            const T *r_in, T *r_out, const T *p, const T *q, const T *Dinv,
+                            T *dnext, T *z_out, T *res_out, const CgArgs &ca,
+                            const ChebStep &s2) {
+  if (split == 1) {
+    using B = OpTangent<T, false, true, 1>;
+    UpdCheb2<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), ulin},
+                   x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s2.coef,
+                   s2.last};
+    return launch_updcheb2(s, op, g, m, ca);
+  }
+  using B = OpTangent<T, false, true, 0>;
+  UpdCheb2<B> op{B{g, c, d, qflag, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0), nullptr},
+                 x_in, r_in, x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s2.coef,
+                 s2.last};
+  return launch_updcheb2(s, op, g, m, ca);
+}
+
+template <class T>
+hipError_t phase_updcheb2(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
+                          const T *coef, const uint8_t *eact, const uint8_t *nflag,
+                          const T *x_in, T *x_out, const T *r_in, T *r_out, const T *p,
+                          const T *q, const T *Dinv, T *dnext, T *z_out, T *res_out,
+                          const CgArgs &ca, const ChebStep &s2) {
+  using B = OpPhase<T, false, true>;
+  UpdCheb2<B> op{B{g, c, coef, eact, nflag, nullptr, nullptr, nullptr, nullptr, T(0)}, x_in, r_in,
+                 x_out, r_out, p, q, Dinv, dnext, z_out, res_out, g.N, s2.coef, s2.last};
+  return launch_updcheb2(s, op, g, m, ca);
+}
+
 template <class T>
 hipError_t cheb_init(hipStream_t s, int n, const T *r, const T *Dinv, T *d0, T *z, T *res,
                      const CgArgs &ca, const ChebStep &cs) {
@@ -3210,6 +3529,17 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                        const uint8_t *, const T *, T *, const T *, T *,        \
                                        const T *, const T *, const T *, T *, T *, T *,         \
                                        const CgArgs &, const ChebStep &, const ChebStep &);    \
+  template hipError_t tangent_updcheb2<T>(hipStream_t, const Grid &, const March &,            \
+                                          const ElasCoef &, int, const T *, const T *,         \
+                                          const uint8_t *, const uint8_t *, const uint8_t *,   \
+                                          const T *, T *, const T *, T *, const T *,           \
+                                          const T *, const T *, T *, T *, T *,                 \
+                                          const CgArgs &, const ChebStep &);                   \
+  template hipError_t phase_updcheb2<T>(hipStream_t, const Grid &, const March &,              \
+                                        const PhaseCoef &, const T *, const uint8_t *,         \
+                                        const uint8_t *, const T *, T *, const T *, T *,       \
+                                        const T *, const T *, const T *, T *, T *, T *,        \
+                                        const CgArgs &, const ChebStep &);                     \
   template hipError_t tangent_power_step<T>(hipStream_t, const Grid &, const March &,          \
                                             const ElasCoef &, int, const T *, const T *,       \
                                             const uint8_t *, const uint8_t *, const uint8_t *, \

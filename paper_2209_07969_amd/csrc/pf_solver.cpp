@@ -565,7 +565,29 @@ pf_status enqueue_iters2(pf_ctx *c, hipStream_t st, Kind kind, const CgArgs &ca,
       }
     }
     if (t) PF_HIP(c, hipEventRecord(c->ev[1], st));
-    if (fused) {
+    if (fused && cs->size() >= 3 && c->ms.ch == 1) {
+      // LDS tiles: the update and the first two polynomial steps are one
+      // kernel; step 2's z, residual and direction land where step 2 of the
+      // separate kernels puts them (zb[i0], rb[i0], W[1])
+      const int par = k & 1;
+      const int i0 = (int)((cs->size() - 1) & 1);
+      T *zb[2] = {b.W[0], b.zc}, *rb[2] = {b.S[1], b.rc};
+      for (int rep = 0; rep < (t ? kTimedRepeat : 1); ++rep) {
+        if (kind == K_ELASTIC) {
+          PF_HIP(c, tangent_updcheb2<T>(st, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                        c->tflag, c->eact, c->nflag, b.X[par], b.X[par ^ 1],
+                                        b.R[par], b.R[par ^ 1], pnew, b.S[0], b.Dinv, b.W[1],
+                                        zb[i0], rb[i0], ca, (*cs)[2]));
+        } else {
+          PF_HIP(c, phase_updcheb2<T>(st, c->g, c->ms, c->pc, b.coef, c->eact, c->nflag,
+                                      b.X[par], b.X[par ^ 1], b.R[par], b.R[par ^ 1], pnew,
+                                      b.S[0], b.Dinv, b.W[1], zb[i0], rb[i0], ca, (*cs)[2]));
+        }
+      }
+      if (t) PF_HIP(c, hipEventRecord(c->ev[2], st));
+      PF_TRY(enqueue_cheb<T>(c, st, kind, ca, n, *cs, false, 3, t && cs->size() > 3,
+                             b.R[par ^ 1]));
+    } else if (fused) {
       const int par = k & 1;
       const int i0 = (int)((cs->size() - 1) & 1);
       T *zb[2] = {b.W[0], b.zc}, *rb[2] = {b.S[1], b.rc};
@@ -939,7 +961,10 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
         c->prof_launches[2] += (cheb && cs.size() > 1) ? kTimedRepeat : 1;
         c->prof_ms[2] += u;
       }
-      if (cheb && cs.size() > 2 && kind == K_ELASTIC) {
+      // the first separate polynomial step (timed by enqueue_cheb) is step 3
+      // where the update kernel takes two steps (LDS tiles), else step 2
+      const size_t first_sep = (cheb && cs.size() >= 3 && c->ms.ch == 1) ? 3 : 2;
+      if (cheb && cs.size() > first_sep && kind == K_ELASTIC) {
         float q = 0.f;
         PF_HIP(c, hipEventElapsedTime(&q, c->ev[3], c->ev[4]));
         c->prof_launches[3] += kTimedRepeat;
@@ -1020,6 +1045,24 @@ pf_status residual_u(pf_ctx *c, const double *u, double *R, double *norm) {
   return PF_OK;
 }
 
+// Inexact Newton for the mixed path: an FP32 inner solve only has to bring
+// the FP64 residual ||R|| down to the Newton target tol, so it is asked for a
+// relative reduction of kForcing * tol / ||R||, no tighter than tol_inner
+// (what FP32 CG resolves) and no looser than kForcingMax.  A step that
+// starts near the target then costs a short solve instead of a full one.
+// With the split's piecewise-linear stress a Newton step inside one active
+// set is exact up to the linear solve, so the step lands about a factor
+// kForcing below the target: a margin for the FP32 solve's rounding, and
+// room for the staggered iteration, which carries the displacement's
+// remaining error into the next phase solve (a missed target costs one
+// more short step).
+constexpr double kForcing = 0.1;
+constexpr double kForcingMax = 0.1;
+
+inline double inner_tolerance(double tol_inner, double target, double nr) {
+  return std::min(kForcingMax, std::max(tol_inner, kForcing * target / nr));
+}
+
 template <class T>
 pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
   *ok = true;
@@ -1027,7 +1070,6 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
   PF_TRY(residual_u(c, c->u, c->Ru, &nr));
   const double tol = c->opts.tol_newton * c->R_ref;
   const bool mixed = std::is_same<T, float>::value;
-  const double tol_lin = mixed ? c->opts.tol_inner : c->opts.tol_pcg;
   int it = 0;
   CgBuf<T> &b = buf<T>(c);
   const int n2 = 2 * c->g.N;
@@ -1053,6 +1095,8 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
                               c->eact, c->nflag, b.Dinv));
     int iters = 0, status = 0;
     T *xs = nullptr;
+    const double tol_lin =
+        mixed ? inner_tolerance(c->opts.tol_inner, tol, nr) : c->opts.tol_pcg;
     PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status, &xs));
     st->n_cg_u += iters;
     st->dof_updates += (double)iters * (double)c->n_free_u;
@@ -1116,8 +1160,11 @@ pf_status phase_res_at1(pf_ctx *c, const double *psi, bool neg, double *nR, doub
 // from an already converged d (a later staggered iteration) can ask for less
 // than the rounding floor of F_d, whose terms are of order Gc/(c_w l) while
 // ||b|| and the start residual may be orders smaller; so once the active set
-// has stopped changing and a step no longer shrinks ||F_d|| by kRefineStall,
-// the residual is at that floor and the solve ends.  The first step takes
+// has stopped changing and a step whose CG solve converged no longer shrinks
+// ||F_d|| by kRefineStall, the residual is at that floor and the solve ends
+// (with an unchanged active set F_d is linear, and a converged solve would
+// otherwise cut it by about tol_pcg).  A CG solve that stopped at max_cg
+// proves nothing about the floor, so after one the loop goes on.  The first step takes
 // points at the kink (d_q = d_{n-1,q}, which is everywhere d has not moved
 // since the last commit) as active: the penalty's stiffness then bounds that
 // step, where the other choice would solve a nearly singular Laplacian
@@ -1127,6 +1174,7 @@ pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
   CgBuf<double> &b = c->bd;
   const int n = c->g.N;
   double nR0 = 0.0, nR_prev = 0.0;
+  int last_status = 0;
   for (int it = 0;; ++it) {
     PF_TRY(zero_icount(c));
     PF_HIP(c, at1_coef(c->stream, c->g, c->gamma, psi, c->d, c->d_prev, c->eact, b.coef, c->chi,
@@ -1136,7 +1184,8 @@ pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
     if (it == 0) nR0 = nR;
     const double target = std::max(c->opts.tol_pcg * nR0, kRefineFloor * nb);
     if (it > 0 && nR <= target) break;
-    if (it > 0 && c->icount_h[IC_CHI] == 0 && nR > kRefineStall * nR_prev) break;
+    if (it > 0 && c->icount_h[IC_CHI] == 0 && last_status == 1 && nR > kRefineStall * nR_prev)
+      break;
     if (nR == 0.0) break;
     if (it >= kAt1MaxNewton)
       return fail(c, PF_E_NOT_CONVERGED, "AT1 phase solve: active set did not settle");
@@ -1147,6 +1196,7 @@ pf_status phase_solve_at1(pf_ctx *c, const double *psi, pf_step_stats *st) {
     int iters = 0, status = 0;
     double *xs = nullptr;
     PF_TRY(pcg<double>(c, K_PHASE, c->opts.tol_pcg, &iters, &status, &xs));
+    last_status = status;
     st->n_cg_d += iters;
     st->dof_updates += (double)iters * (double)c->n_free_d;
     if (status == 3) st->cg_not_converged += 1;
@@ -1370,7 +1420,10 @@ pf_status open_step(pf_ctx *c, double lam) {
   c->step_open = true;
   c->step_load = lam;
   bool ok = true;
-  PF_TRY(newton(c, &c->acc, &ok));
+  const auto t_u = std::chrono::steady_clock::now();
+  PF_TRY(newton(c, &c->acc, &ok));   // ends on a synchronising residual read
+  c->acc.time_u_ms +=
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_u).count();
   c->acc.n_stag = 1;
   if (!ok) c->acc.converged = 0;
   double r = 0.0;
@@ -1382,6 +1435,9 @@ pf_status open_step(pf_ctx *c, double lam) {
 pf_status iterate_once(pf_ctx *c) {
   const double *Hs = c->at1 ? c->psi_p : c->H;
   bool updated = false;
+  // wall time of the phase part (trial, predictor, evolution solve) and of
+  // the displacement solve, split at a stream synchronisation
+  const auto t_d = std::chrono::steady_clock::now();
   if (c->opts.scheme != PF_ST) {
     c->acc.gated_max = std::max<int64_t>(c->acc.gated_max, c->gated_last);
     if (c->gated_last > 0) {
@@ -1392,8 +1448,13 @@ pf_status iterate_once(pf_ctx *c) {
     }
   }
   if (!updated) PF_TRY(phase_solve(c, Hs, &c->acc));
+  PF_TRY(sync(c));
+  const auto t_u = std::chrono::steady_clock::now();
   bool ok = true;
-  PF_TRY(newton(c, &c->acc, &ok));
+  PF_TRY(newton(c, &c->acc, &ok));   // ends on a synchronising residual read
+  const auto t_e = std::chrono::steady_clock::now();
+  c->acc.time_d_ms += std::chrono::duration<double, std::milli>(t_u - t_d).count();
+  c->acc.time_u_ms += std::chrono::duration<double, std::milli>(t_e - t_u).count();
   if (!ok) c->acc.converged = 0;
   c->acc.n_stag += 1;
   double r = 0.0;

@@ -27,11 +27,20 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_lookup_guards():
     b = bench()
+    import hashlib
     rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_tension512.json")))
-    # the committed record matches the current kernel source and its own kernel
-    assert b.measured_traffic(rec["kernel"]) == rec["traffic_bytes_per_launch"]
+    src_path = os.path.join(ROOT, "paper_2209_07969_amd", "csrc", "pf_kernels.hip")
+    sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
+    traffic, src = b.measured_traffic(rec["kernel"])
+    if rec["kernel_source_sha256"] == sha:
+        # counters taken on this very source: reported, with their origin
+        assert traffic == rec["traffic_bytes_per_launch"]
+        assert "hbm_traffic_tension512.json" in src and sha[:16] in src
+    else:
+        # the kernels changed since the counters were taken: nothing reported
+        assert (traffic, src) == (None, None)
     # another kernel's name never borrows it
-    assert b.measured_traffic("k_cg_updcheb<1, OpUpdCheb<OpTangent<float>>>") is None
+    assert b.measured_traffic("k_cg_updcheb<1, OpUpdCheb<OpTangent<float>>>") == (None, None)
 
 
 def test_algorithmic_bytes_per_node():
@@ -43,6 +52,9 @@ def test_algorithmic_bytes_per_node():
     assert b.cheb_step_bytes_per_node() == (7 * 2 + 1) * f32 + 2 * flag
     # update + first step: r, q, D^-1, x, p in; x, r, d_1, z, res out; d; flags
     assert b.updcheb_bytes_per_node() == (10 * 2 + 1) * f32 + 2 * flag
+    # update + two steps: r, q, D^-1, x, p in; x, r, z out (d_2, res_2 when more follow)
+    assert b.updcheb2_bytes_per_node(True) == (8 * 2 + 1) * f32 + 2 * flag
+    assert b.updcheb2_bytes_per_node(False) == (10 * 2 + 1) * f32 + 2 * flag
     # vector update: x, p, q, r, D^-1 in; x, r, z out, per DOF
     assert b.update_bytes_per_node() == 2 * 8 * f32
 
@@ -51,7 +63,8 @@ def test_step_record_is_one_json_line():
     b = bench()
     st = {"n_stag": 5, "n_newton": 7, "n_trial": 2, "n_dsolve": 4, "n_cg_u": 900, "n_cg_d": 80,
           "n_cg_trial": 40, "gated_max": 12, "floor_hits": 3, "r_stag": 8e-6,
-          "force": [0.0, 123.5], "time_ms": 42.0, "dof_updates": 1.5e6, "converged": 1,
+          "force": [0.0, 123.5], "time_ms": 42.0, "time_u_ms": 30.0, "time_d_ms": 9.0,
+          "dof_updates": 1.5e6, "converged": 1,
           "cg_not_converged": 0, "extra": "ignored"}
     line = b.step_record("s1_mixed", 3, True, st)
     assert "\n" not in line

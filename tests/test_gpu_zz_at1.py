@@ -9,6 +9,11 @@ the bar's scalar equation and the oracle.
   other parity tests (counts within +-1, u to 1e-7 / 1e-6, d to 1e-5, force
   curve to 1e-4 of its peak), FP64 for ST, S1 and S3, mixed for S1, and S1
   on LDS tiles.
+* The 64^2 tension panel at l = 2h (the length-scale ratio of the 512^2
+  configuration), load steps 1-2: the regime in which a later staggered
+  iteration's phase solve starts from a converged d and can only stop at
+  the rounding floor of F_d (tests/test_at1_stop_rule.py emulates it on the
+  CPU); ST and S1 against the oracle under the same protocol.
 """
 import dataclasses
 
@@ -51,3 +56,11 @@ def test_at1_panel_history(gpu_lib, scheme, precision, rows):
     p = dataclasses.replace(W.tension_panel(n=16, l=0.1, du=1e-3, steps=8), phase_model=1)
     compare_history(gpu_lib, p, scheme, precision, 8, 1e-7 if precision == 0 else 1e-6,
                     march_rows=rows)
+
+
+@pytest.mark.parametrize("scheme,precision", [(0, 0), (1, 0), (1, 1)])
+def test_at1_l2h_panel_first_steps(gpu_lib, scheme, precision):
+    n = 64
+    p = dataclasses.replace(W.tension_panel(n=n, l=2.0 / n, du=6e-5, steps=2),
+                            phase_model=1)
+    compare_history(gpu_lib, p, scheme, precision, 2, 1e-7 if precision == 0 else 1e-6)
