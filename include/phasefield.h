@@ -357,6 +357,35 @@ pf_status pf_op_predictor(pf_ctx *ctx, const double *d, const double *dd,
                           const double *H, const double *psi_s,
                           const uint8_t *flags, double *Hhat);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.
+ *
+ * pf_tangent_apply_noalloc: q = K_t(u; d) p as pf_op_tangent_apply computes
+ * it (same kernels, the work decomposition of a context with default
+ * options), without a context and without allocating: no hipMalloc, hipFree
+ * or allocating library call.  The per-element indicator bytes (tr eps > 0
+ * at each quadrature point) go to a static device array of the library,
+ * PF_NOALLOC_MAX_ELEMENTS bytes on each device it runs on, held until the
+ * process ends and shared by every call on that device; each call rewrites
+ * the nx*ny bytes it uses.  Calls that overlap on one device (different
+ * streams) therefore race; calls on one stream do not.
+ *   mesh: nx, ny, lx, ly as for pf_create, but elem_active is NULL or a
+ *         DEVICE pointer to nx*ny flags (nothing is copied);
+ *   mat:  E, nu, eta and split are used;
+ *   u, p, q [2N], d [N]: device pointers on the current device (N =
+ *         (nx+1)(ny+1)); q is overwritten;
+ *   hip_stream: the stream the kernels run on (NULL = the null stream).
+ * Stream-ordered, does not synchronise.  Errors: PF_E_INVALID_ARG for a
+ * null pointer, a bad mesh or material, or nx*ny > PF_NOALLOC_MAX_ELEMENTS
+ * (checked before any device call); PF_E_HIP if the scratch address cannot
+ * be found or a launch fails.
+ * ------------------------------------------------------------------------- */
+#define PF_NOALLOC_MAX_ELEMENTS (16 * 1024 * 1024)
+pf_status pf_tangent_apply_noalloc(const pf_mesh_desc *mesh, const pf_material *mat,
+                                   const double *u, const double *d, const double *p,
+                                   double *q, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTED = [
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
     "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create",
     "pf_batch_load_step", "pf_batch_destroy", "pf_autotune", "pf_set_allocator",
-    "pf_batch_set_shared_launches",
+    "pf_batch_set_shared_launches", "pf_tangent_apply_noalloc",
 ]
 EXPORTED_3D = [
     "pf3d_op_internal_force", "pf3d_op_tangent_apply", "pf3d_op_phase_apply",
@@ -138,6 +138,8 @@ def load_library(path: str = LIB_PATH):
     lib.pf_set_allocator.argtypes = [P, ALLOC_FN, RELEASE_FN, P]
     lib.pf_kernel_time.argtypes = [P, c_int32, POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_int64)]
+    lib.pf_tangent_apply_noalloc.argtypes = [POINTER(MeshDesc), POINTER(MaterialDesc), P, P, P,
+                                             P, P]
     M3, MT = POINTER(Mesh3Desc), POINTER(MaterialDesc)
     lib.pf3d_op_internal_force.argtypes = [M3, MT, P, P, P, P]
     lib.pf3d_op_tangent_apply.argtypes = [M3, MT, P, P, P, P, P]
@@ -429,6 +431,37 @@ class Context:
                                              self._qp(H, "H"), self._qp(psi_s, "psi_s"),
                                              self._flags(flags, "flags"), self._qp(Hhat, "Hhat")),
                     "pf_op_predictor")
+
+
+NOALLOC_MAX_ELEMENTS = 16 * 1024 * 1024
+
+
+def tangent_apply_noalloc(problem, u, d, p, q, elem_active=None, stream=None):
+    """pf_tangent_apply_noalloc: q = K_t(u; d) p without a context and
+    without device allocation.  problem: nx, ny, lx, ly and material as for
+    Context; u, p, q [2N] and d [N] float64 device tensors on the current
+    device; elem_active: None or a uint8 device tensor [nx*ny]; stream: a
+    hipStream_t handle (None = torch's current stream)."""
+    import torch
+    require_device()
+    lib = load_library()
+    dev = torch.cuda.current_device()
+    N = (problem.nx + 1) * (problem.ny + 1)
+    mask = None if elem_active is None else _dev_arg(elem_active, torch.uint8,
+                                                      problem.nx * problem.ny, dev,
+                                                      "elem_active").value
+    mesh = MeshDesc(int(problem.nx), int(problem.ny), float(problem.lx), float(problem.ly), mask)
+    m = problem.material
+    mat = MaterialDesc(m.E, m.nu, m.Gc, m.l, m.eta, int(m.split))
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = lib.pf_tangent_apply_noalloc(
+        ctypes.byref(mesh), ctypes.byref(mat), _dev_arg(u, torch.float64, 2 * N, dev, "u"),
+        _dev_arg(d, torch.float64, N, dev, "d"), _dev_arg(p, torch.float64, 2 * N, dev, "p"),
+        _dev_arg(q, torch.float64, 2 * N, dev, "q"), c_void_p(stream))
+    if st != 0:
+        raise PhaseFieldError(st, "pf_tangent_apply_noalloc: " +
+                              lib.pf_status_string(st).decode())
 
 
 class Hex3DOps:

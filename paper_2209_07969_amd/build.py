@@ -36,7 +36,7 @@ def build(verbose: bool = True) -> str:
     cc = hipcc()
     objs = []
     for src, lang in (("pf_kernels.hip", "hip"), ("pf_solver.cpp", "hip"),
-                      ("pf3d_kernels.hip", "hip")):
+                      ("pf3d_kernels.hip", "hip"), ("pf_noalloc.hip", "hip")):
         obj = os.path.join(BUILD, src + ".o")
         _run([cc, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

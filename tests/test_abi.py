@@ -157,3 +157,27 @@ def test_batch_and_allocator_argument_checks_without_device():
     assert lib.pf_batch_create(1, arr, 0, ctypes.byref(out)) == 1   # null member
     assert lib.pf_batch_set_shared_launches(None, 1) == 1
     assert lib.pf_set_allocator(None, pf.ALLOC_FN(), pf.RELEASE_FN(), None) == 1
+
+
+def test_noalloc_tangent_apply_refusals_without_device():
+    """pf_tangent_apply_noalloc checks its arguments before any device call:
+    null pointers, a bad mesh or material, and meshes whose element count
+    exceeds the static scratch array (one byte per element).  The pointer
+    passed is never dereferenced: every call here is refused first."""
+    import paper_2209_07969_amd as pf
+    lib = pf.load_library()
+    mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
+    fake = ctypes.c_void_p(256)
+    f = lib.pf_tangent_apply_noalloc
+    for nx, ny in [(4097, 4096), (2 ** 31 - 1, 2), (1 << 24, 2), (1, (1 << 24) + 1)]:
+        mesh = pf.MeshDesc(nx, ny, 1.0, 1.0, None)
+        assert nx * ny > pf.NOALLOC_MAX_ELEMENTS
+        assert f(ctypes.byref(mesh), ctypes.byref(mat), fake, fake, fake, fake, None) == 1
+    mesh = pf.MeshDesc(0, 4, 1.0, 1.0, None)
+    assert f(ctypes.byref(mesh), ctypes.byref(mat), fake, fake, fake, fake, None) == 1
+    mesh = pf.MeshDesc(4, 4, 1.0, 1.0, None)
+    assert f(ctypes.byref(mesh), ctypes.byref(mat), None, fake, fake, fake, None) == 1
+    assert f(ctypes.byref(mesh), ctypes.byref(mat), fake, fake, fake, None, None) == 1
+    bad = pf.MaterialDesc(2.1e5, 0.5, 2.7, 0.03, 1e-6, 0)
+    assert f(ctypes.byref(mesh), ctypes.byref(bad), fake, fake, fake, fake, None) == 1
+    assert f(None, ctypes.byref(mat), fake, fake, fake, fake, None) == 1
