@@ -712,6 +712,16 @@ struct ElemNone { uint8_t active; };
 
 // ---- elasticity tangent (optionally fused with the CG direction update
 //      p = z + beta p_old; the fused op also accumulates p.q)
+//
+// Node record: the input vector (px, py) and the damage d, plus only what
+// the variant reads besides: the old direction ox, oy (fused CG apply) and
+// the linearisation point lx, ly (spectral split).  The records are staged
+// in LDS, so unused fields would cost LDS and occupancy.
+template <class T, bool FUSED, int SPL> struct TanNode { T px, py, d; };
+template <class T> struct TanNode<T, true, 0> { T px, py, d, ox, oy; };
+template <class T> struct TanNode<T, false, 1> { T px, py, d, lx, ly; };
+template <class T> struct TanNode<T, true, 1> { T px, py, d, ox, oy, lx, ly; };
+
 template <class TT, bool FUSED, bool MASK, int SPL = 0>
 struct OpTangent {
   using T = TT;
@@ -720,7 +730,7 @@ struct OpTangent {
   static constexpr int NR = FUSED ? 1 : 0;
   // raw: px, py = z; ox, oy = p_old (fused only); fin: p = z + beta p_old;
   // lx, ly = linearisation point (spectral split only)
-  struct Node { T px, py, d, ox, oy, lx, ly; };
+  using Node = TanNode<T, FUSED, SPL>;
   Grid g; ElasCoef c;
   const T *d; const uint8_t *qflag; const uint8_t *eact; const uint8_t *nflag;
   const T *z; const T *pold; T *pnew; T *q;
@@ -728,16 +738,16 @@ struct OpTangent {
   const T *ulin;
 
   __device__ Node load(int i, int j) const {
-    Node n{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Node n{};
     if (node_exists(g, i, j)) {
       const int k = i + j * (g.nx + 1);
       n.px = z[k];
       n.py = z[k + g.N];
-      if (FUSED) {
+      if constexpr (FUSED) {
         n.ox = pold[k];
         n.oy = pold[k + g.N];
       }
-      if (SPL == 1) {
+      if constexpr (SPL == 1) {
         n.lx = ulin[k];
         n.ly = ulin[k + g.N];
       }
@@ -746,7 +756,7 @@ struct OpTangent {
     return n;
   }
   __device__ void fin(Node &n) const {
-    if (FUSED) {
+    if constexpr (FUSED) {
       n.px += beta * n.ox;
       n.py += beta * n.oy;
     }
@@ -754,11 +764,11 @@ struct OpTangent {
   // operator data only (no CG vectors): d and, for the spectral split, the
   // linearisation point
   __device__ Node load_aux(int i, int j) const {
-    Node n{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Node n{};
     if (node_exists(g, i, j)) {
       const int k = i + j * (g.nx + 1);
       n.d = d[k];
-      if (SPL == 1) {
+      if constexpr (SPL == 1) {
         n.lx = ulin[k];
         n.ly = ulin[k + g.N];
       }
@@ -790,9 +800,15 @@ struct OpTangent {
     return e;
   }
   static __device__ Node shfl_up(const Node &n) {
-    return Node{lane_up(n.px), lane_up(n.py), lane_up(n.d), T(0),
-                T(0), SPL == 1 ? lane_up(n.lx) : T(0),
-                SPL == 1 ? lane_up(n.ly) : T(0)};
+    Node m{};   // the old direction is not passed on: fin has been applied
+    m.px = lane_up(n.px);
+    m.py = lane_up(n.py);
+    m.d = lane_up(n.d);
+    if constexpr (SPL == 1) {
+      m.lx = lane_up(n.lx);
+      m.ly = lane_up(n.ly);
+    }
+    return m;
   }
   __device__ void element(const Node &n0, const Node &n1, const Node &n2, const Node &n3,
                           const Elem &e, T (&f)[2][4]) const {
@@ -804,7 +820,7 @@ struct OpTangent {
     const T ux[4] = {n0.px, n1.px, n2.px, n3.px};
     const T uy[4] = {n0.py, n1.py, n2.py, n3.py};
     const T dn[4] = {n0.d, n1.d, n2.d, n3.d};
-    if (SPL == 1) {
+    if constexpr (SPL == 1) {
       const T lx[4] = {n0.lx, n1.lx, n2.lx, n3.lx};
       const T ly[4] = {n0.ly, n1.ly, n2.ly, n3.ly};
       spectral_element<T, false>(ux, uy, dn, lx, ly, c, f[0], f[1]);
@@ -1653,9 +1669,18 @@ __device__ inline void updcheb2_compute(const UpdCheb2<Base> &op, const Grid &g,
   __syncthreads();   // the LDS is reused by the block's next tile
 }
 
+// FP32 with compact node records (VD tangent, phase operator): ask for five
+// blocks per CU, so that one launch at 512^2 (1225 tiles) holds every tile
+// at once; the others take what their registers allow.
 template <class Base>
-__global__ void __launch_bounds__(TPB) k_cg_updcheb2(UpdCheb2<Base> op, Grid g, March ms,
-                                                     CgArgs ca) {
+constexpr int updcheb2_min_blocks() {
+  using T = typename Base::T;
+  return (sizeof(T) == 4 && sizeof(typename Base::Node) <= 3 * sizeof(T)) ? 5 : 1;
+}
+
+template <class Base>
+__global__ void __launch_bounds__(TPB, updcheb2_min_blocks<Base>())
+    k_cg_updcheb2(UpdCheb2<Base> op, Grid g, March ms, CgArgs ca) {
   using T = typename Base::T;
   __shared__ UpdCheb2Lds<Base> sm;
   const int bid = blockIdx.x, nb = gridDim.x;
