@@ -510,12 +510,23 @@ def run_sweep(pf, args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rows = []
+        jl = open(args.stats_jsonl, "a") if args.stats_jsonl else None
         for n in range(warm, warm + steps):
             rows.append(B.load_step([float(p.loads[n]) for p in probs]))
+            if jl:
+                jl.write(json.dumps({
+                    "mode": "shared" if shared else "streams", "step": n + 1,
+                    "seconds": time.perf_counter() - t0,
+                    "n_stag": [r["n_stag"] for r in rows[-1]],
+                    "converged": [int(r["converged"]) for r in rows[-1]],
+                    "dof_updates": sum(r["dof_updates"] for r in rows[-1])}) + "\n")
+                jl.flush()
             if (n + 1) % 5 == 0:
                 log(f"  {'shared launches' if shared else 'concurrent streams'}: load step "
                     f"{n + 1}, {time.perf_counter() - t0:.1f} s, max N_stag "
                     f"{max(r['n_stag'] for r in rows[-1])}")
+        if jl:
+            jl.close()
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         B.close()
@@ -838,8 +849,11 @@ def main():
     la, ma, nodes = ctx.kernel_time(0)
     lf, mf, _ = ctx.kernel_time(2)
     lc, mc, _ = ctx.kernel_time(3)
+    # template argument of the kernel names: the work-item height, which the
+    # library picks from the mesh size when rows is 0 (column marching)
+    ch = "CH" if rows_s1 == 0 else rows_s1
     cands = [(ma / max(la, 1), la, ma / max(la, 1), fused_apply_bytes_per_node(),
-              f"k_cg_apply<{rows_s1}, OpTangent<float>> (fused CG direction update + "
+              f"k_cg_apply<{ch}, OpTangent<float>> (fused CG direction update + "
               f"tangent apply)")]
     two = rows_s1 == 1 and s1_deg is not None and s1_deg >= 3   # tiles: two steps fused
     if s1_deg and s1_deg >= 2 and lf:
@@ -849,12 +863,12 @@ def main():
                           "Chebyshev steps)"))
         else:
             cands.append((mf / lf, lf, mf / lf, updcheb_bytes_per_node(),
-                          f"k_cg_updcheb<{rows_s1}, OpUpdCheb<OpTangent<float>>> (CG update "
+                          f"k_cg_updcheb<{ch}, OpUpdCheb<OpTangent<float>>> (CG update "
                           f"fused with the first Chebyshev step)"))
     further = (s1_deg - 3) if two else ((s1_deg - 2) if s1_deg else 0)
     if further > 0 and lc:
         cands.append((further * mc / lc, lc, mc / lc, cheb_step_bytes_per_node(),
-                      f"k_march<{rows_s1}, OpCheb<OpTangent<float>>> (Jacobi-Chebyshev step)"))
+                      f"k_march<{ch}, OpCheb<OpTangent<float>>> (Jacobi-Chebyshev step)"))
     _, launches, avg_ms, bpn, kname = max(cands, key=lambda c: c[0])
     alg_bytes = bpn * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
