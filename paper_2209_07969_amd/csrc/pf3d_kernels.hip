@@ -26,11 +26,19 @@ __global__ void __launch_bounds__(kTpb3) k3_internal_force(Grid3 g, Mat3 m, cons
   if (n < g.N) node_internal_force(g, m, n, u, d, R);
 }
 
-__global__ void __launch_bounds__(kTpb3) k3_tangent_apply(Grid3 g, Mat3 m, const double *u,
+struct T3DevSync {
+  __device__ void operator()() const { __syncthreads(); }
+};
+
+// Element-once tangent apply (t3_tangent_block); a non-null done that is
+// set skips the launch (a CG solve that has already ended).
+__global__ void __launch_bounds__(kTpb3) k3_tangent_tiled(Grid3 g, Mat3 m, const double *u,
                                                           const double *d, const double *p,
-                                                          double *q) {
-  const int n = grid_index(blockIdx.x, threadIdx.x);
-  if (n < g.N) node_tangent_apply(g, m, n, u, d, p, q);
+                                                          double *q, const int *done) {
+  if (done != nullptr && *done) return;
+  __shared__ T3Lds sm;
+  double out[1][24], carry[1][3];
+  t3_tangent_block<1>(g, m, u, d, p, q, blockIdx.x, threadIdx.x, sm, out, carry, T3DevSync{});
 }
 
 __global__ void __launch_bounds__(kTpb3) k3_phase_apply(Grid3 g, Mat3 m, const double *coef,
@@ -167,6 +175,13 @@ struct DeviceBackend {
     hipLaunchKernelGGL(k3_each<F>, dim3(grid_blocks(count)), dim3(kTpb3), 0, s, f, count);
     note(hipGetLastError());
   }
+  // q = K_t(u; d) p by the element-once kernel; skipped while *done is set
+  void tangent_apply(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
+                     const double *p, double *q, const int *done) {
+    hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0, s, g, m, u, d, p, q,
+                       done);
+    note(hipGetLastError());
+  }
   bool ok() const { return err == hipSuccess; }
   template <class F>
   void sum_into(int count, const F &f, double *slot) {
@@ -233,8 +248,8 @@ pf_status pf3d_op_tangent_apply(const pf3d_mesh *mesh, const pf_material *mat,
   Mat3 m;
   if (!u || !d || !p || !q || make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK)
     return PF_E_INVALID_ARG;
-  hipLaunchKernelGGL(k3_tangent_apply, dim3(grid_blocks(g.N)), dim3(kTpb3), 0,
-                     static_cast<hipStream_t>(hip_stream), g, m, u, d, p, q);
+  hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0,
+                     static_cast<hipStream_t>(hip_stream), g, m, u, d, p, q, nullptr);
   return launched();
 }
 

@@ -567,6 +567,179 @@ __host__ __device__ inline void elem_predictor(const Grid3 &g, const Mat3 &m, in
   }
 }
 
+// ---- element-once tangent apply: tiles of node columns marching in z
+//
+// The node-gather apply above evaluates every element once for each of its
+// eight nodes.  Here a block owns a tile of kT3 x kT3 node columns and a
+// chunk of kT3Z node planes, and marches through the element layers that
+// touch its planes.  For each layer ke it stages node plane ke + 1 in LDS
+// (plane ke was staged for the layer before; the first layer stages both),
+// and its kTpb3 threads take the (kT3 + 1)^2 elements of the layer that touch
+// the tile, each computing its element's eight corner contributions once.
+// An owned node of plane ke then adds the four contributions from the layer
+// below (carried in its thread) and the four from this layer, in a fixed
+// order; the top plane of the mesh has only the layer below.  Every output is
+// written by one thread: deterministic, no atomics.  The phases are
+// functions of one thread index, so a host build can replay a block by
+// running each phase for all threads between the block's barriers.
+constexpr int kT3 = 15;         // owned node columns per tile side
+constexpr int kT3E = kT3 + 1;   // element columns per tile side
+constexpr int kT3N = kT3 + 2;   // staged node columns per side
+constexpr int kT3Z = 8;         // node planes per block
+static_assert(kT3E * kT3E == kTpb3, "one element column per thread");
+
+struct T3Node {
+  double ux, uy, uz, px, py, pz, d;
+};
+struct T3Lds {
+  T3Node plane[2][kT3N * kT3N];   // two node planes, slot k & 1
+  double f[4][3][kTpb3];          // four corners of each element of the layer
+};
+
+__host__ __device__ inline int t3_tiles_x(const Grid3 &g) { return (g.nx + kT3) / kT3; }
+__host__ __device__ inline int t3_tiles_y(const Grid3 &g) { return (g.ny + kT3) / kT3; }
+__host__ __device__ inline int t3_chunks_z(const Grid3 &g) { return (g.nz + kT3Z) / kT3Z; }
+inline int t3_blocks(const Grid3 &g) { return t3_tiles_x(g) * t3_tiles_y(g) * t3_chunks_z(g); }
+
+// Tangent apply of one element: out[3a + c] = sum_q w (B_a^T C_t(eps_q(u),
+// g(d_q)) eps_q(p))_c, the element's share of node_tangent_apply at corner a.
+__host__ __device__ inline void elem_tangent_apply(const Grid3 &g, const Mat3 &m,
+                                                   const double *ue, const double *pe,
+                                                   const double *de, double out[24]) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  for (int x = 0; x < 24; ++x) out[x] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    double eps[6], dep[6], ds[6];
+    strain_at(g, q, ue, eps);
+    strain_at(g, q, pe, dep);
+    split_tangent_apply(m, eps, degrade(interp_at(g, q, de), m.eta), dep, ds);
+    for (int a = 0; a < 8; ++a) {
+      const ShapeAt s = shape_at(g, a, q);
+      out[3 * a + 0] += w * (s.gx * ds[0] + s.gz * ds[4] + s.gy * ds[5]);
+      out[3 * a + 1] += w * (s.gy * ds[1] + s.gz * ds[3] + s.gx * ds[5]);
+      out[3 * a + 2] += w * (s.gz * ds[2] + s.gy * ds[3] + s.gx * ds[4]);
+    }
+  }
+}
+
+// Thread t stages its entries of node plane k (columns i0 - 1 .. i0 + kT3,
+// j0 - 1 .. j0 + kT3) into slot s; nodes outside the box are zero.
+__host__ __device__ inline void t3_stage(const Grid3 &g, const double *u, const double *d,
+                                         const double *p, int i0, int j0, int k, int s, int t,
+                                         T3Lds &sm) {
+  for (int c = t; c < kT3N * kT3N; c += kTpb3) {
+    const int i = i0 - 1 + c % kT3N, j = j0 - 1 + c / kT3N;
+    T3Node n{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz) {
+      const int id = node_id(g, i, j, k);
+      n = T3Node{u[id], u[id + g.N], u[id + 2 * g.N], p[id], p[id + g.N], p[id + 2 * g.N], d[id]};
+    }
+    sm.plane[s][c] = n;
+  }
+}
+
+// Thread t computes element t of layer ke (zero outside the box).
+__host__ __device__ inline void t3_element(const Grid3 &g, const Mat3 &m, int i0, int j0, int ke,
+                                           int t, const T3Lds &sm, double out[24]) {
+  const int el = t % kT3E, ej = t / kT3E;
+  const int ie = i0 - 1 + el, je = j0 - 1 + ej;
+  if (ie < 0 || ie >= g.nx || je < 0 || je >= g.ny || ke < 0 || ke >= g.nz) {
+    for (int x = 0; x < 24; ++x) out[x] = 0.0;
+    return;
+  }
+  double ue[24], pe[24], de[8];
+  for (int b = 0; b < 8; ++b) {
+    const T3Node &n = sm.plane[(ke + corner_dk(b)) & 1]
+                              [(ej + corner_dj(b)) * kT3N + el + corner_di(b)];
+    ue[b] = n.ux; ue[8 + b] = n.uy; ue[16 + b] = n.uz;
+    pe[b] = n.px; pe[8 + b] = n.py; pe[16 + b] = n.pz;
+    de[b] = n.d;
+  }
+  elem_tangent_apply(g, m, ue, pe, de, out);
+}
+
+// Thread t stores the corners of plane ke (h = 0: corners 0-3) or of plane
+// ke + 1 (h = 1: corners 4-7) of its element.
+__host__ __device__ inline void t3_put(const double out[24], int h, int t, T3Lds &sm) {
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) sm.f[a][c][t] = out[3 * (4 * h + a) + c];
+}
+
+// Owned node column t (< kT3^2): the four stored corner values at its node,
+// corner 2 of element (li, lj), 3 of (li+1, lj), 1 of (li, lj+1) and 0 of
+// (li+1, lj+1) (corners 6, 7, 5, 4 for the upper half).
+__host__ __device__ inline void t3_gather(const T3Lds &sm, int t, double s[3]) {
+  const int li = t % kT3, lj = t / kT3, e = lj * kT3E + li;
+  for (int c = 0; c < 3; ++c)
+    s[c] = sm.f[2][c][e] + sm.f[3][c][e + 1] + sm.f[1][c][e + kT3E] + sm.f[0][c][e + kT3E + 1];
+}
+
+// One block of the element-once apply, played by NT threads t0 .. t0+NT-1
+// (the device runs one per thread, NT = 1; a host replay runs the block's
+// kTpb3 threads in one call).  sync() is the block's barrier.
+template <int NT, class Sync>
+__host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, const double *u,
+                                                 const double *d, const double *p, double *q,
+                                                 int blk, int t0, T3Lds &sm,
+                                                 double (&out)[NT][24], double (&carry)[NT][3],
+                                                 const Sync &sync) {
+  const int nxt = t3_tiles_x(g), nyt = t3_tiles_y(g);
+  const int i0 = (blk % nxt) * kT3, j0 = ((blk / nxt) % nyt) * kT3;
+  const int k0 = (blk / (nxt * nyt)) * kT3Z;
+  const int k1 = (k0 + kT3Z < g.nz + 1) ? k0 + kT3Z : g.nz + 1;   // owned planes [k0, k1)
+  const int kb = k0 > 0 ? k0 - 1 : 0;                              // element layers [kb, kl]
+  const int kl = (k1 - 1 < g.nz - 1) ? k1 - 1 : g.nz - 1;
+  for (int r = 0; r < NT; ++r)
+    for (int c = 0; c < 3; ++c) carry[r][c] = 0.0;
+  for (int ke = kb; ke <= kl; ++ke) {
+    if (ke == kb)
+      for (int r = 0; r < NT; ++r) t3_stage(g, u, d, p, i0, j0, ke, ke & 1, t0 + r, sm);
+    for (int r = 0; r < NT; ++r) t3_stage(g, u, d, p, i0, j0, ke + 1, (ke + 1) & 1, t0 + r, sm);
+    sync();
+    for (int r = 0; r < NT; ++r) {
+      t3_element(g, m, i0, j0, ke, t0 + r, sm, out[r]);
+      t3_put(out[r], 0, t0 + r, sm);
+    }
+    sync();
+    if (ke >= k0)
+      for (int r = 0; r < NT; ++r) {
+        const int t = t0 + r, i = i0 + t % kT3, j = j0 + t / kT3;
+        if (t < kT3 * kT3 && i <= g.nx && j <= g.ny) {
+          double s[3];
+          t3_gather(sm, t, s);
+          const int id = node_id(g, i, j, ke);
+          for (int c = 0; c < 3; ++c) q[id + c * g.N] = carry[r][c] + s[c];
+        }
+      }
+    sync();
+    for (int r = 0; r < NT; ++r) t3_put(out[r], 1, t0 + r, sm);
+    sync();
+    for (int r = 0; r < NT; ++r)
+      if (t0 + r < kT3 * kT3) t3_gather(sm, t0 + r, carry[r]);
+  }
+  // the top plane of the box has the layer below only
+  if (g.nz >= k0 && g.nz < k1)
+    for (int r = 0; r < NT; ++r) {
+      const int t = t0 + r, i = i0 + t % kT3, j = j0 + t / kT3;
+      if (t < kT3 * kT3 && i <= g.nx && j <= g.ny) {
+        const int id = node_id(g, i, j, g.nz);
+        for (int c = 0; c < 3; ++c) q[id + c * g.N] = carry[r][c];
+      }
+    }
+}
+
+// Host replay of the element-once apply over its whole grid (tests only).
+struct T3HostSync {
+  void operator()() const {}
+};
+inline void t3_tangent_host(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
+                            const double *p, double *q) {
+  static T3Lds sm;
+  static double out[kTpb3][24], carry[kTpb3][3];
+  for (int b = 0; b < t3_blocks(g); ++b)
+    t3_tangent_block<kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
+}
+
 // Grid of a one-index-per-thread launch over count indices.
 __host__ __device__ inline int grid_index(int block, int thread) {
   return block * kTpb3 + thread;

@@ -29,10 +29,6 @@ struct FForce {
   Grid3 g; Mat3 m; const double *u, *d; double *R;
   __host__ __device__ void operator()(int n) const { node_internal_force(g, m, n, u, d, R); }
 };
-struct FTangent {
-  Grid3 g; Mat3 m; const double *u, *d, *p; double *q;
-  __host__ __device__ void operator()(int n) const { node_tangent_apply(g, m, n, u, d, p, q); }
-};
 struct FTangentDiag {
   Grid3 g; Mat3 m; const double *u, *d; double *D;
   __host__ __device__ void operator()(int n) const { node_tangent_diag(g, m, n, u, d, D); }
@@ -482,7 +478,7 @@ class Solver3 {
       be_.each(N3, FInvDiag{D_, fu_, Dinv_});
       const double *u = u_;
       const int cg = pcg(N3, R_, fu_, o_.tol_pcg, [&](const double *p, double *q) {
-        be_.each(g_.N, FWhileRunning<FTangent>{cs_, FTangent{g_, m_, u, d_, p, q}});
+        be_.tangent_apply(g_, m_, u, d_, p, q, &cs_->done);
       }, st);
       st->n_cg_u += cg;
       st->dof_updates += double(cg) * double(nfree_u_);

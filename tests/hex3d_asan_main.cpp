@@ -7,6 +7,7 @@
 #include "hex3d_host_harness.cpp"
 #include "hex3d_solver_harness.cpp"
 
+#include <cmath>
 #include <cstdio>
 #include <vector>
 
@@ -35,6 +36,19 @@ void run_ops(const pf3d_mesh &mesh, const pf_material &mat) {
   long long ng = 0, below = 0;
   h3_internal_force(&mesh, &mat, u.data(), d.data(), R.data());
   h3_tangent_apply(&mesh, &mat, u.data(), d.data(), p.data(), q.data());
+  // the element-once grid against the node gather: the same per-element
+  // arithmetic summed in another order
+  std::vector<double> qg(3 * N);
+  h3_tangent_apply_gather(&mesh, &mat, u.data(), d.data(), p.data(), qg.data());
+  double dmax = 0.0, qmax = 0.0;
+  for (size_t i = 0; i < 3 * N; ++i) {
+    dmax = std::fmax(dmax, std::fabs(q[i] - qg[i]));
+    qmax = std::fmax(qmax, std::fabs(qg[i]));
+  }
+  if (!(dmax <= 1e-12 * qmax)) {
+    std::printf("tiled tangent apply differs from the gather: %g of %g\n", dmax, qmax);
+    std::exit(1);
+  }
   h3_tangent_diag(&mesh, &mat, u.data(), d.data(), Dt.data());
   h3_phase_apply(&mesh, &mat, coef.data(), d.data(), qd.data());
   h3_phase_diag(&mesh, &mat, coef.data(), Dp.data());
@@ -119,8 +133,10 @@ void run_steps(const pf3d_mesh &mesh, const pf_material &mat, int scheme) {
 }  // namespace
 
 int main() {
+  // the last spans two tiles of node columns in x and y and two chunks of
+  // node planes in z of the element-once apply
   const pf3d_mesh meshes[] = {{1, 1, 1, 1.0, 1.0, 1.0}, {5, 4, 3, 1.3, 0.7, 0.45},
-                              {9, 7, 5, 1.3, 0.7, 0.45}};
+                              {9, 7, 5, 1.3, 0.7, 0.45}, {17, 16, 9, 1.1, 0.9, 0.6}};
   for (int split = 0; split < 2; ++split) {
     const pf_material mat{2.1e5, 0.3, 2.7, 0.2, 1e-6, split};
     for (const auto &m : meshes) run_ops(m, mat);

@@ -36,6 +36,15 @@ int h3_tangent_apply(const pf3d_mesh *mesh, const pf_material *mat, const double
   Grid3 g;
   Mat3 m;
   if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  t3_tangent_host(g, m, u, d, p, q);   // the element-once kernel's grid
+  return PF_OK;
+}
+
+int h3_tangent_apply_gather(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                            const double *d, const double *p, double *q) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
   replay(g.N, [&](int n) { node_tangent_apply(g, m, n, u, d, p, q); });
   return PF_OK;
 }

@@ -31,6 +31,11 @@ struct HostBackend {
         if (i < count) f(i);
       }
   }
+  // the element-once tangent apply, replayed block by block
+  void tangent_apply(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
+                     const double *p, double *q, const int *done) {
+    if (!*done) t3_tangent_host(g, m, u, d, p, q);
+  }
   bool ok() const { return true; }
   template <class F>
   void sum_into(int count, const F &f, double *slot) {

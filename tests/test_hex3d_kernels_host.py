@@ -33,7 +33,9 @@ GUARD = 64
 SENT = 1.2345e300
 SENT16 = 0xBEEF
 
-MESHES = [(3, 2, 2), (9, 7, 5), (17, 5, 3), (1, 1, 1)]
+# (4, 16, 9) spans two tiles of node columns in y and two chunks of node
+# planes in z of the element-once tangent apply; (17, 5, 3) two tiles in x
+MESHES = [(3, 2, 2), (9, 7, 5), (17, 5, 3), (1, 1, 1), (4, 16, 9)]
 MAT = dict(E=2.1e5, nu=0.3, Gc=2.7, l=0.05, eta=1e-6)
 
 
