@@ -1494,7 +1494,6 @@ struct UpdCheb2Regs {
   typename Base::Own o[NSL];
   T r[NSL][NF], q[NSL][NF], di[NSL][NF];
   typename Base::Elem e[NEL];
-  T x[NF], p[NF];   // the thread's owned node
 };
 
 template <class Base>
@@ -1527,19 +1526,6 @@ __device__ inline void updcheb2_load(const UpdCheb2<Base> &op, const Grid &g, co
   for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
     const int e = threadIdx.x + r * TPB;
     if (e < kU2E * kU2E) tr.e[r] = op.base.eload(i0 + e % kU2E, j0 + e / kU2E);
-  }
-#pragma unroll
-  for (int f = 0; f < NF; ++f) tr.x[f] = tr.p[f] = T(0);
-  if (threadIdx.x < kTile * kTile) {
-    const int i = i0 + 2 + threadIdx.x % kTile, j = j0 + 2 + threadIdx.x / kTile;
-    if (node_exists(g, i, j)) {
-      const int idx = i + j * (g.nx + 1);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        tr.x[f] = op.x[idx + f * op.N];
-        tr.p[f] = op.p[idx + f * op.N];
-      }
-    }
   }
 }
 
@@ -1616,6 +1602,24 @@ __device__ inline void updcheb2_compute(const UpdCheb2<Base> &op, const Grid &g,
     sm.b[m] = n;
   }
   __syncthreads();
+  // x and p of the owned node are needed only at the end: their loads are
+  // issued here, in flight during pass 2, instead of with the staged loads
+  // (where they would hold registers through pass 1)
+  T xv[NF], pv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) xv[f] = pv[f] = T(0);
+  if (act && threadIdx.x < kTile * kTile) {
+    const int i = (tile % ms.nstrips) * kTile + threadIdx.x % kTile;
+    const int j = (tile / ms.nstrips) * kTile + threadIdx.x / kTile;
+    if (i <= g.nx && j <= g.ny) {
+      const int idx = i + j * (g.nx + 1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        xv[f] = op.x[idx + f * op.N];
+        pv[f] = op.p[idx + f * op.N];
+      }
+    }
+  }
   // pass 2: A d1 on the (kTile+1)^2 elements touching the tile; element
   // (a, b), 1 <= a, b <= kTile + 1, has corner 0 at pass-1 node (a, b)
   {
@@ -1660,7 +1664,7 @@ __device__ inline void updcheb2_compute(const UpdCheb2<Base> &op, const Grid &g,
           op.reso[idx] = rs;
         }
         if (act) {
-          op.xo[idx] = tr.x[f] + alpha * tr.p[f];
+          op.xo[idx] = xv[f] + alpha * pv[f];
           op.ro[idx] = rn;
         }
       }
