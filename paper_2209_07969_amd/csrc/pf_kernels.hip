@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
+#include <utility>
 
 namespace pf {
 namespace {
@@ -39,7 +41,7 @@ constexpr double GA = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
 constexpr double GB = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
 constexpr int WPB = 4;                            // waves per block (march)
 constexpr int TPB = 256;
-static_assert(kPMax % TPB == 0, "block_sum reads kPMax / TPB partials per thread");
+static_assert(kPMax % (2 * TPB) == 0, "block_sum reads pairs of partials, kPMax / (2 TPB) per thread");
 
 // ------------------------------------------------------- lane shifts
 
@@ -61,6 +63,13 @@ __device__ inline double lane_up(double x) {
   const int hi = lane_up_bits(static_cast<int>(b >> 32));
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               static_cast<unsigned int>(lo));
+}
+
+// Load at a 32-bit byte offset from a uniform base: the scalar-base form of
+// the global load, with no 64-bit address arithmetic per lane.
+template <class T>
+__device__ inline T ldo(const T *base, unsigned byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
 // ------------------------------------------------------------ reductions
@@ -122,39 +131,63 @@ __device__ inline void block_partial(double (&v)[NV], double *part) {
 
 // Fixed-order sum of np <= kPMax partials written by an earlier kernel,
 // returned in every thread of the block (bit-identical in every block).
-// Thread t adds partials t, t + TPB, t + 2 TPB, ... in that order.  Every
-// load is issued before the first add, so the prologue of a kernel costs one
-// memory round trip instead of one per partial a thread reads (a loop that
-// adds as it loads waits for each load in turn).  Absent partials add 0.
-template <int NV>
-__device__ inline void block_sum(const double *part, int np, double (&out)[NV]) {
-  constexpr int R = kPMax / TPB;
-  __shared__ double sh[NV][TPB / 64];
-  double v[NV][R];
+// Thread t reads the pair of partials (2t, 2t+1) + 2 TPB r for the rounds
+// r < nr = ceil(np / (2 TPB)), one 16-byte load each, and adds them in round
+// order; in the last round the partials at np or beyond count 0.  The round
+// count is a template argument (block_sum dispatches on nr, which is
+// uniform), so every load is issued before the first add, the prologue of a
+// kernel costs one memory round trip, and only the last round is masked.
+// The pointer is 16-byte aligned (buffers are 256-byte aligned and every
+// partial array starts at an even index).
+template <int NV, int NR>
+__device__ inline void block_sum_rounds(const double *part, int np, double (&s)[NV]) {
+  const unsigned off = 16u * threadIdx.x;   // byte offset of the thread's pair in round 0
+  double2 v[NV][NR];
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int b = threadIdx.x + r * TPB;
-      v[k][r] = b < np ? part[k * kPMax + b] : 0.0;
-    }
+    for (int r = 0; r < NR; ++r)
+      v[k][r] = ldo(reinterpret_cast<const double2 *>(part + k * kPMax + r * 2 * TPB), off);
+  const int b = 2 * static_cast<int>(threadIdx.x) + (NR - 1) * 2 * TPB;   // last round's pair
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    // the sum starts from the first value itself (an add of 0.0 there would
-    // be placed with its load and wait for it)
-    double s = v[k][0];
+    v[k][NR - 1].x = b < np ? v[k][NR - 1].x : 0.0;
+    v[k][NR - 1].y = b + 1 < np ? v[k][NR - 1].y : 0.0;
+    // the first pair starts the sum (an add of 0.0 there would be placed
+    // with its load and wait for it)
+    double t = v[k][0].x + v[k][0].y;
 #pragma unroll
-    for (int r = 1; r < R; ++r) s += v[k][r];
-    s = wave_sum_last(s);
-    if ((threadIdx.x & 63) == 63) sh[k][threadIdx.x >> 6] = s;
+    for (int r = 1; r < NR; ++r) t = t + v[k][r].x + v[k][r].y;
+    s[k] = t;
+  }
+}
+
+template <int NV>
+__device__ inline void block_sum(const double *part, int np, double (&out)[NV]) {
+  static_assert(kPMax == 8 * TPB, "block_sum dispatches on up to four rounds of pairs");
+  __shared__ double sh[NV][TPB / 64];
+  double s[NV];
+  switch ((np + 2 * TPB - 1) / (2 * TPB)) {
+    case 1: block_sum_rounds<NV, 1>(part, np, s); break;
+    case 2: block_sum_rounds<NV, 2>(part, np, s); break;
+    case 3: block_sum_rounds<NV, 3>(part, np, s); break;
+    case 4: block_sum_rounds<NV, 4>(part, np, s); break;
+    default:
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double w = wave_sum_last(s[k]);
+    if ((threadIdx.x & 63) == 63) sh[k][threadIdx.x >> 6] = w;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
+    double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < TPB / 64; ++w) s += sh[k][w];
-    out[k] = s;
+    for (int w = 0; w < TPB / 64; ++w) t += sh[k][w];
+    out[k] = t;
   }
   __syncthreads();
 }
@@ -187,6 +220,26 @@ __device__ inline bool elem_exists(const Grid &g, int ie, int je, const uint8_t 
 __device__ inline bool node_exists(const Grid &g, int i, int j) {
   return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
 }
+
+// Unchecked loads for work items that lie inside the mesh (ldo, above):
+// every array an op reads this way is split into planes of at most N
+// values, so the offsets fit in 32 bits while N * 8 bytes does.
+__device__ inline bool offsets32(const Grid &g) { return g.N < (1 << 29); }
+
+// True when the box of nodes [i0, i0 + n) x [j0, j0 + n) and the elements
+// between them lie inside the mesh and the 32-bit offsets apply.
+__device__ inline bool box_inside(const Grid &g, int i0, int j0, int n) {
+  return offsets32(g) && i0 >= 0 && j0 >= 0 && i0 + n - 1 <= g.nx && j0 + n - 1 <= g.ny;
+}
+
+// Ops with unchecked loads (load_fast, load_aux_fast, eload_fast,
+// load_own_fast, by node and element index) take that path in the LDS-tile
+// kernels for tiles inside the mesh.
+template <class Op, class = void>
+struct HasFast : std::false_type {};
+template <class Op>
+struct HasFast<Op, std::void_t<decltype(std::declval<const Op &>().load_fast(0u))>>
+    : std::true_type {};
 
 // Data an operator needs only at the nodes a work item stores: fetched with
 // the item's first loads (load_own) instead of after the element maths, so
@@ -610,6 +663,23 @@ template <class Op>
 __device__ inline void tile_load(const Op &op, const March &ms, int tile, TileRegs<Op> &tr) {
   static_assert(kTileE * kTileE == TPB, "one element per thread");
   const int i0 = (tile % ms.nstrips) * kTile - 1, j0 = (tile / ms.nstrips) * kTile - 1;
+  if constexpr (HasFast<Op>::value) {
+    const Grid &g = op.g;
+    if (box_inside(g, i0, j0, kTileN)) {
+      const unsigned row = unsigned(g.nx) + 1u, base = unsigned(j0) * row + unsigned(i0);
+#pragma unroll
+      for (int r = 0; r < kTileLoads; ++r) {
+        const unsigned k = threadIdx.x + r * TPB;
+        if (k < kTileN * kTileN) tr.n[r] = op.load_fast(base + (k / kTileN) * row + k % kTileN);
+      }
+      tr.e = op.eload_fast(unsigned(j0) * unsigned(g.nx) + unsigned(i0) +
+                           (threadIdx.x / kTileE) * unsigned(g.nx) + threadIdx.x % kTileE);
+      if (threadIdx.x < kTile * kTile)
+        tr.o = op.load_own_fast(base + row + 1u + (threadIdx.x / kTile) * row +
+                                threadIdx.x % kTile);
+      return;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < kTileLoads; ++r) {
     const int k = threadIdx.x + r * TPB;
@@ -775,6 +845,42 @@ struct OpTangent {
     }
     return n;
   }
+  __device__ Node load_fast(unsigned k) const {
+    Node n;
+    const unsigned o = k * unsigned(sizeof(T));
+    n.px = ldo(z, o);
+    n.py = ldo(z + g.N, o);
+    if constexpr (FUSED) {
+      n.ox = ldo(pold, o);
+      n.oy = ldo(pold + g.N, o);
+    }
+    if constexpr (SPL == 1) {
+      n.lx = ldo(ulin, o);
+      n.ly = ldo(ulin + g.N, o);
+    }
+    n.d = ldo(d, o);
+    return n;
+  }
+  __device__ Node load_aux_fast(unsigned k) const {
+    Node n{};
+    const unsigned o = k * unsigned(sizeof(T));
+    n.d = ldo(d, o);
+    if constexpr (SPL == 1) {
+      n.lx = ldo(ulin, o);
+      n.ly = ldo(ulin + g.N, o);
+    }
+    return n;
+  }
+  // both bytes are loaded before either is used (no dependent round trip)
+  __device__ Elem eload_fast(unsigned e) const {
+    Elem el;
+    el.bits = ldo(qflag, e);
+    el.active = eact == nullptr ? uint8_t(1) : ldo(eact, e);   // nonzero = active
+    return el;
+  }
+  __device__ OwnFlag load_own_fast(unsigned k) const {
+    return OwnFlag{nflag == nullptr ? uint8_t(0) : ldo(nflag, k)};
+  }
   __device__ void set_u(Node &n, const T (&u)[2]) const {
     n.px = u[0];
     n.py = u[1];
@@ -872,6 +978,24 @@ struct OpPhase {
     if (FUSED) n.p += beta * n.o;
   }
   __device__ Node load_aux(int, int) const { return Node{T(0), T(0)}; }
+  __device__ Node load_fast(unsigned k) const {
+    const unsigned o = k * unsigned(sizeof(T));
+    Node n{ldo(z, o), T(0)};
+    if (FUSED) n.o = ldo(pold, o);
+    return n;
+  }
+  __device__ Node load_aux_fast(unsigned) const { return Node{T(0), T(0)}; }
+  __device__ Elem eload_fast(unsigned e) const {
+    Elem el;
+    const unsigned o = e * unsigned(sizeof(T));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) el.c[q] = ldo(coef + q * g.E, o);
+    el.active = eact == nullptr ? uint8_t(1) : ldo(eact, e);   // nonzero = active
+    return el;
+  }
+  __device__ OwnFlag load_own_fast(unsigned k) const {
+    return OwnFlag{nflag == nullptr ? uint8_t(0) : ldo(nflag, k)};
+  }
   __device__ void set_u(Node &n, const T (&u)[1]) const { n.p = u[0]; }
   __device__ void get_u(const Node &n, T (&u)[1]) const { u[0] = n.p; }
   __device__ bool masked(int k, int) const { return (nflag[k] & NF_D) != 0; }
@@ -1502,9 +1626,43 @@ __device__ inline void updcheb2_load(const UpdCheb2<Base> &op, const Grid &g, co
   using T = typename Base::T;
   constexpr int NF = Base::NF;
   const int i0 = (tile % ms.nstrips) * kTile - 2, j0 = (tile / ms.nstrips) * kTile - 2;
+  if constexpr (HasFast<Base>::value) {
+    if (box_inside(g, i0, j0, kU2N)) {
+      const unsigned row = unsigned(g.nx) + 1u, base = unsigned(j0) * row + unsigned(i0);
+#pragma unroll
+      for (int r = 0; r < UpdCheb2Regs<Base>::NSL; ++r) {
+        const unsigned k = threadIdx.x + r * TPB;
+        if (k < kU2N * kU2N) {
+          const unsigned idx = base + (k / kU2N) * row + k % kU2N;
+          const unsigned o = idx * unsigned(sizeof(T));
+          tr.n[r] = op.base.load_aux_fast(idx);
+          tr.o[r] = op.base.load_own_fast(idx);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            tr.r[r][f] = ldo(op.r + f * op.N, o);
+            tr.q[r][f] = ldo(op.q + f * op.N, o);
+            tr.di[r][f] = ldo(op.Dinv + f * op.N, o);
+          }
+        }
+      }
+      const unsigned ebase = unsigned(j0) * unsigned(g.nx) + unsigned(i0);
+#pragma unroll
+      for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
+        const unsigned e = threadIdx.x + r * TPB;
+        if (e < kU2E * kU2E)
+          tr.e[r] = op.base.eload_fast(ebase + (e / kU2E) * unsigned(g.nx) + e % kU2E);
+      }
+      return;
+    }
+  }
+  // the thread index is opaque here, so that the compiler does not hoist
+  // this path's per-thread address arithmetic out of the kernel's tile loop
+  // (where it would hold registers through the computation of every tile)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
 #pragma unroll
   for (int r = 0; r < UpdCheb2Regs<Base>::NSL; ++r) {
-    const int k = threadIdx.x + r * TPB;
+    const int k = tid + r * TPB;
 #pragma unroll
     for (int f = 0; f < NF; ++f) tr.r[r][f] = tr.q[r][f] = tr.di[r][f] = T(0);
     if (k < kU2N * kU2N) {
@@ -1524,7 +1682,7 @@ __device__ inline void updcheb2_load(const UpdCheb2<Base> &op, const Grid &g, co
   }
 #pragma unroll
   for (int r = 0; r < UpdCheb2Regs<Base>::NEL; ++r) {
-    const int e = threadIdx.x + r * TPB;
+    const int e = tid + r * TPB;
     if (e < kU2E * kU2E) tr.e[r] = op.base.eload(i0 + e % kU2E, j0 + e / kU2E);
   }
 }
@@ -1691,14 +1849,16 @@ __global__ void __launch_bounds__(TPB, updcheb2_min_blocks<Base>())
   const int nt = ms.nstrips * ms.nchunks;
   double red[2] = {0.0, 0.0};
   double alpha = 0.0;
-  int t = xcd_block(bid, nb);
-  // the first tile's loads are in flight during the prologue's reduction
+  const int t0 = xcd_block(bid, nb);
+  // the first tile's loads are in flight during the prologue's reduction;
+  // a later tile of the block is loaded after the previous one is done (a
+  // prefetch would hold its registers through the whole computation)
   UpdCheb2Regs<Base> tr;
-  if (t < nt) updcheb2_load(op, g, ms, t, tr);
+  if (t0 < nt) updcheb2_load(op, g, ms, t0, tr);
   const bool act = cg_update_prologue(ca, &alpha, bid);
-  for (; t < nt; t += nb) {
+  for (int t = t0; t < nt; t += nb) {
+    if (t != t0) updcheb2_load(op, g, ms, t, tr);
     updcheb2_compute(op, g, ms, t, tr, sm, act, T(alpha), red);
-    if (t + nb < nt) updcheb2_load(op, g, ms, t + nb, tr);
   }
   if (op.last) block_partial_at<2>(red, ca.partB, bid);
   if (act && bid == 0 && threadIdx.x == 0) {
