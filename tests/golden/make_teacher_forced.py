@@ -7,14 +7,15 @@ steps were chosen from the oracle's own history of each panel:
 
 * ``tension64_<scheme>.npz`` - the 64^2 notched tension panel (20 steps of
   3e-4 mm, l = 0.03 mm), schemes ST, S1 and S3, FP64 oracle, load steps
-  1-19.  Step 10 is the last step before the crack runs, step 11 is the
-  nucleation step (the largest staggered count of the first crack, where the
-  fixed-stress schemes gain most: Section 4.1), step 19 is the step in which
-  the ligament breaks.  Stored: the per-step record of every step (staggered
+  1-20 (the whole load history of the panel).  Step 10 is the last step
+  before the crack runs, step 11 is the nucleation step (the largest
+  staggered count of the first crack, where the fixed-stress schemes gain
+  most: Section 4.1), step 19 is the step in which the ligament breaks.
+  Stored: the per-step record of every step (staggered
   count, reaction, residual, converged flag, size of the last staggered
-  iteration) and the committed u and d after steps 9, 10, 11, 18 and 19,
-  with H after steps 9, 10 and 18 (the inputs of the forced steps 10, 11
-  and 19).
+  iteration) and the committed u and d after steps 9, 10, 11, 18, 19 and
+  20, with H after steps 9, 10 and 18 (the inputs of the forced steps 10,
+  11 and 19).
 * ``shear32_<scheme>.npz`` - a 32^2 shear panel with the spectral split
   (l = 0.06 mm, 3e-3 mm per step), schemes ST and S1: the committed state
   before and after the first step past the peak of the reaction curve
@@ -43,8 +44,8 @@ from oracle import Oracle  # noqa: E402
 OUT = os.path.join(HERE, "teacher_forced")
 SCHEMES = {"ST": 0, "S1": 1, "S2": 2, "S3": 3}
 
-TENSION_STEPS = 19
-TENSION_KEEP = (9, 10, 11, 18, 19)     # committed u, d after these steps
+TENSION_STEPS = 20
+TENSION_KEEP = (9, 10, 11, 18, 19, 20)  # committed u, d after these steps
 TENSION_KEEP_H = (9, 10, 18)           # H after these (inputs of 10, 11, 19)
 SHEAR_MAX_STEPS = 14
 
