@@ -297,10 +297,11 @@ pf_status pf_batch_destroy(pf_batch *b);
 pf_status pf_autotune(pf_ctx *ctx, int32_t reps, int32_t *chosen);
 
 /* Kernel timing for measurement.  When enabled, the CG drivers time a sample
- * of the CG kernel launches with HIP events on the context's stream: per
- * enqueued batch, the first iteration's operator kernel (idempotent: it only
- * reads buffers it does not write) is launched four times back to back
- * between one event pair.  Launch counts and elapsed times accumulate.
+ * of the CG kernel launches with HIP events on the context's stream: in one
+ * enqueued CG batch of every eight of the displacement solves and of the
+ * phase solves (counted from enabling, the first included), the first
+ * iteration's operator kernel (idempotent: it only reads buffers it does not
+ * write) is launched four times back to back between one event pair.  Launch counts and elapsed times accumulate.
  * Single-kernel CG solves time that kernel (a whole iteration); two-kernel
  * CG solves time the fused operator apply and their vector update.  The
  * update is one launch between the events, except with Jacobi-Chebyshev of

@@ -38,10 +38,10 @@ struct alignas(128) CgHalfA {
 struct alignas(128) CgHalfB {
   double rz_prev; // r.z of the previous iteration (for beta)
   double rr0;
+  double tol2;    // squared relative tolerance of the solve (set by the init)
   int done;
   int iters;
   int first;      // 1 before the first direction
-  int pad;
 };
 struct CgState {
   CgHalfA a;

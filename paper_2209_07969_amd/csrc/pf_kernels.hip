@@ -1418,6 +1418,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ca.st->b.rz_prev = 0.0;
     ca.st->b.rr0 = 0.0;
+    ca.st->b.tol2 = ca.tol2;
     ca.st->b.done = 0;
     ca.st->b.iters = 0;
     ca.st->b.first = 1;
@@ -1435,7 +1436,7 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta, int bid)
   const double rr0 = first ? rr : ca.st->b.rr0;
   if (!done) {
     if (!(rr == rr) || !(rz == rz)) done = 2;
-    else if (rr <= ca.tol2 * rr0) done = 1;
+    else if (rr <= ca.st->b.tol2 * rr0) done = 1;
     else if (iters >= ca.maxit) done = 3;
   }
   if (bid == 0 && threadIdx.x == 0) {
