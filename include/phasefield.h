@@ -272,15 +272,19 @@ pf_status pf_free_dofs(pf_ctx *ctx, int64_t *n_free_u, int64_t *n_free_d);
  *    (FP64, Jacobi-Chebyshev) run on the member's stream.  The tables live
  *    in memory of the batch's own (hipMalloc and hipHostMalloc), not in a
  *    member's installed allocator.
- *  - concurrent streams: a pool of `workers` host threads (0 = 4) runs the
- *    members' steps, whose kernels overlap on the GPU.
+ *  - concurrent streams: a pool of host threads (4 unless
+ *    pf_batch_set_workers says otherwise) runs the members' steps, whose
+ *    kernels overlap on the GPU.
  * Results are bit-identical to stepping the members one by one in either
  * mode.  The batch borrows its members: destroy it first.
  * ------------------------------------------------------------------------- */
 typedef struct pf_batch pf_batch;
-pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out);
+/* n >= 1 distinct, non-NULL members.  Errors: PF_E_INVALID_ARG. */
+pf_status pf_batch_create(int32_t n, pf_ctx *const *members, pf_batch **out);
 /* enable = 1: shared launches (default); 0: concurrent streams. */
 pf_status pf_batch_set_shared_launches(pf_batch *b, int32_t enable);
+/* Host threads of the concurrent-stream mode (>= 1; default 4). */
+pf_status pf_batch_set_workers(pf_batch *b, int32_t workers);
 /* load_factors[n], stats[n] (may be NULL).  Returns PF_OK, or
  * PF_E_NOT_CONVERGED if any member did not converge (all members are still
  * committed), or the first error of a member. */

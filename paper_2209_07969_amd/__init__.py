@@ -30,7 +30,7 @@ EXPORTED = [
     "pf_load_step", "pf_staggered_iterate", "pf_commit_step", "pf_reaction_force",
     "pf_get_state", "pf_set_state", "pf_status_string", "pf_last_error", "pf_free_dofs",
     "pf_op_internal_force", "pf_op_tangent_apply", "pf_op_phase_apply", "pf_op_qp_update",
-    "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create",
+    "pf_op_predictor", "pf_set_profiling", "pf_kernel_time", "pf_batch_create", "pf_batch_set_workers",
     "pf_batch_load_step", "pf_batch_destroy", "pf_autotune", "pf_set_allocator",
     "pf_batch_set_shared_launches", "pf_tangent_apply_noalloc",
 ]
@@ -130,7 +130,8 @@ def load_library(path: str = LIB_PATH):
     lib.pf_op_qp_update.argtypes = [P, c_int32, P, P, P, P, P, P, POINTER(c_int64)]
     lib.pf_op_predictor.argtypes = [P, P, P, P, P, P, P]
     lib.pf_set_profiling.argtypes = [P, c_int32]
-    lib.pf_batch_create.argtypes = [c_int32, POINTER(P), c_int32, POINTER(P)]
+    lib.pf_batch_create.argtypes = [c_int32, POINTER(P), POINTER(P)]
+    lib.pf_batch_set_workers.argtypes = [P, c_int32]
     lib.pf_batch_load_step.argtypes = [P, POINTER(c_double), POINTER(StepStats)]
     lib.pf_batch_destroy.argtypes = [P]
     lib.pf_batch_set_shared_launches.argtypes = [P, c_int32]
@@ -676,10 +677,13 @@ class Batch:
         self.members = list(contexts)
         arr = (c_void_p * len(self.members))(*[c.h for c in self.members])
         h = c_void_p()
-        st = self.lib.pf_batch_create(len(self.members), arr, int(workers), ctypes.byref(h))
+        st = self.lib.pf_batch_create(len(self.members), arr, ctypes.byref(h))
         if st != 0:
             raise PhaseFieldError(st, "pf_batch_create failed")
         self.h = h
+        st = self.lib.pf_batch_set_workers(h, int(workers))
+        if st != 0:
+            raise PhaseFieldError(st, "pf_batch_set_workers failed")
         st = self.lib.pf_batch_set_shared_launches(h, 1 if shared else 0)
         if st != 0:
             raise PhaseFieldError(st, "pf_batch_set_shared_launches failed")

@@ -1953,8 +1953,8 @@ struct pf_batch {
   std::unique_ptr<BatchSvc> svc;
 };
 
-pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf_batch **out) {
-  if (!out || n < 1 || !members || workers < 0) return PF_E_INVALID_ARG;
+pf_status pf_batch_create(int32_t n, pf_ctx *const *members, pf_batch **out) {
+  if (!out || n < 1 || !members) return PF_E_INVALID_ARG;
   *out = nullptr;
   std::vector<pf_ctx *> m(members, members + n);
   for (int i = 0; i < n; ++i) {
@@ -1964,8 +1964,14 @@ pf_status pf_batch_create(int32_t n, pf_ctx *const *members, int32_t workers, pf
   }
   pf_batch *b = new pf_batch();
   b->members = std::move(m);
-  b->workers = workers > 0 ? workers : 4;
+  b->workers = 4;
   *out = b;
+  return PF_OK;
+}
+
+pf_status pf_batch_set_workers(pf_batch *b, int32_t workers) {
+  if (!b || workers < 1) return PF_E_INVALID_ARG;
+  b->workers = workers;
   return PF_OK;
 }
 

@@ -100,7 +100,8 @@ int main() {
   CHECK(pf_destroy(nullptr) == PF_E_INVALID_ARG || pf_destroy(nullptr) == PF_OK);
   CHECK(pf_set_allocator(nullptr, nullptr, nullptr, nullptr) == PF_E_INVALID_ARG);
   pf_batch *b = nullptr;
-  CHECK(pf_batch_create(0, nullptr, 1, &b) == PF_E_INVALID_ARG && b == nullptr);
+  CHECK(pf_batch_create(0, nullptr, &b) == PF_E_INVALID_ARG && b == nullptr);
+  CHECK(pf_batch_set_workers(nullptr, 4) == PF_E_INVALID_ARG);
   CHECK(pf_batch_set_shared_launches(nullptr, 1) == PF_E_INVALID_ARG);
   std::printf(failures ? "host checks: %d failures\n" : "host checks: ok\n", failures);
   return failures ? 1 : 0;

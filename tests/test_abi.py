@@ -153,9 +153,10 @@ def test_batch_and_allocator_argument_checks_without_device():
     lib = pf.load_library()
     out = ctypes.c_void_p()
     arr = (ctypes.c_void_p * 1)(None)
-    assert lib.pf_batch_create(0, arr, 0, ctypes.byref(out)) == 1
-    assert lib.pf_batch_create(1, arr, 0, ctypes.byref(out)) == 1   # null member
+    assert lib.pf_batch_create(0, arr, ctypes.byref(out)) == 1
+    assert lib.pf_batch_create(1, arr, ctypes.byref(out)) == 1   # null member
     assert lib.pf_batch_set_shared_launches(None, 1) == 1
+    assert lib.pf_batch_set_workers(None, 4) == 1
     assert lib.pf_set_allocator(None, pf.ALLOC_FN(), pf.RELEASE_FN(), None) == 1
 
 
