@@ -89,8 +89,9 @@ def run(case):
 
 def main(argv):
     os.makedirs(OUT, exist_ok=True)
-    cases = argv or ["tension128_ST", "tension128_S1", "shear128_ST", "shear128_S1",
-                     "lshape256_ST", "lshape256_S1"]
+    cases = argv or ["tension128_ST", "tension128_S1", "tension128_S3", "shear128_ST",
+                     "shear128_S1", "shear128_S2", "shear128_S3", "lshape256_ST",
+                     "lshape256_S1", "lshape256_S2"]
     for c in cases:
         run(c)
 

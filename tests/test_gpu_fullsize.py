@@ -185,3 +185,31 @@ def test_post_nucleation_tension256_s1_mixed(gpu_lib):
     ctx.close()
     assert d.max() > 0.95
     check_state(p, st, u, d, H, H_prev, np.random.default_rng(256))
+
+
+def test_post_nucleation_tension512_s1_mixed(gpu_lib):
+    """The 512^2 configuration in the benchmark's launch configuration (S1
+    mixed, LDS tiles, Jacobi-Chebyshev of degree 3) through its crack run:
+    load steps 1-93, where the crack crosses the ligament in steps 91-93
+    (steps 91 and 92 stop at the 500-iteration cap), then step 94, whose
+    converged state is checked like the states above.  About two minutes on
+    one GPU."""
+    p = W.config_tension512()
+    ctx = gpu_lib.Context(p, scheme=1, precision=1, precond=1, cheb_degree=3, march_rows=1)
+    peak = 0.0
+    for k in range(93):
+        st = ctx.load_step(float(p.loads[k]))
+        peak = max(peak, st["force"][1])
+        if st["n_stag"] > 20:
+            print(f"  step {k + 1}: n_stag={st['n_stag']} converged={st['converged']} "
+                  f"F={st['force'][1]:.4f}", flush=True)
+    H_prev = ctx.get_state()[2].copy()
+    st = ctx.load_step(float(p.loads[93]))
+    print(f"  step 94: n_stag={st['n_stag']} converged={st['converged']} "
+          f"F={st['force'][1]:.4f} (peak {peak:.4f})", flush=True)
+    u, d, H = ctx.get_state()
+    ctx.close()
+    assert st["converged"] == 1
+    assert st["force"][1] < 0.9 * peak        # past the peak: the crack has run
+    assert d.max() > 0.95
+    check_state(p, st, u, d, H, H_prev, np.random.default_rng(94), n_samples=100)

@@ -17,8 +17,8 @@ the GPU from the zero state, with no state injected, and compares:
 The panels: the 64^2 notched tension panel over its 20 steps (ST, S1, S3;
 the crack nucleates at step 11 and breaks the ligament by step 19), and
 reduced versions of the three larger configurations with their l/h ratio:
-the 128^2 tension panel, the 128^2 spectral shear panel and the 256^2 masked
-L-shaped panel (ST and S1).
+the 128^2 tension panel (ST, S1, S3), the 128^2 spectral shear panel (ST,
+S1, S2, S3) and the 256^2 masked L-shaped panel (ST, S1, S2).
 """
 import dataclasses
 import os
@@ -104,9 +104,15 @@ def test_tension64_whole_history_benchmark_launch(gpu_lib):
              march_rows=1)
 
 
+# each configuration's schemes (the tension panel: ST and S1/S3; the spectral
+# shear panel: S1/S2/S3 against ST; the L-shape: S1 and S2 against ST), in
+# FP64 and mixed precision
 REDUCED = [("tension128", "ST", 0), ("tension128", "S1", 0), ("tension128", "S1", 1),
+           ("tension128", "S3", 1),
            ("shear128", "ST", 0), ("shear128", "S1", 0), ("shear128", "S1", 1),
-           ("lshape256", "ST", 0), ("lshape256", "S1", 0), ("lshape256", "S1", 1)]
+           ("shear128", "S2", 0), ("shear128", "S2", 1), ("shear128", "S3", 1),
+           ("lshape256", "ST", 0), ("lshape256", "S1", 0), ("lshape256", "S1", 1),
+           ("lshape256", "S2", 0), ("lshape256", "S2", 1)]
 
 
 @pytest.mark.parametrize("kind,scheme,precision", REDUCED)
