@@ -266,7 +266,7 @@ def copy_bandwidth():
     return 2 * 4 * n / sec / 1e9
 
 
-def cpu_baseline(pf, problem):
+def cpu_baseline(pf, problem, st_steps=None):
     """The oracle (FP64, assembled CSR + SuperLU), untuned, on a bounded
     sample of the workload: the k = 0 displacement solve of load step 1
     limited to one Newton iteration (assemble R_u and K_t, one sparse direct
@@ -276,7 +276,11 @@ def cpu_baseline(pf, problem):
     second fresh context after a first one has warmed the library up; its
     time is reported beside the oracle's.  cores: the process's CPU time over
     the oracle's wall time (all threads, so a multithreaded library call
-    would show), rounded, at least 1."""
+    would show), rounded, at least 1.  After the sample, one phase solve
+    (assembled K_dd(H), SuperLU) is timed on its own; with st_steps (the ST
+    FP64 run's per-step records) the line adds an estimate of the oracle's
+    time for that run's window: Newton iterations x the sample time plus
+    staggered iterations x the phase-solve time."""
     import dataclasses
 
     import numpy as np
@@ -304,6 +308,16 @@ def cpu_baseline(pf, problem):
     orc.stag_residual(orc.d, H)
     t, cpu_s = time.perf_counter() - t0, time.process_time() - c0
     cores = max(1, round(cpu_s / t))
+    tp = time.perf_counter()
+    orc.solve_phase(H, orc.d)
+    t_phase = time.perf_counter() - tp
+    est = None
+    if st_steps:
+        est = {"seconds": sum(r["n_newton"] * t + r["n_stag"] * t_phase for r in st_steps),
+               "gpu_st_fp64_seconds": sum(r["time_ms"] for r in st_steps) / 1e3,
+               "steps": [r["step"] for r in st_steps],
+               "method": ("extrapolated: the ST FP64 run's Newton iterations x the sample time "
+                          "plus its staggered iterations x the phase-solve time")}
     return {
         "value": t,
         "unit": "s per sample (one Newton iteration of the k = 0 displacement solve of load "
@@ -317,6 +331,8 @@ def cpu_baseline(pf, problem):
                    f"the same sample took {t_gpu * 1e3:.1f} ms"),
         "gpu_same_sample_s": t_gpu,
         "oracle_over_gpu": t / t_gpu,
+        "phase_solve_s": t_phase,
+        "window_estimate": est,
     }
 
 
@@ -923,7 +939,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline sample")
-        cpu = cpu_baseline(pf, problem)
+        cpu = cpu_baseline(pf, problem, rows2 if st_res else None)
 
     traffic, traffic_src = measured_traffic(kname)
     out = {
