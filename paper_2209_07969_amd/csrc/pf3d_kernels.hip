@@ -116,6 +116,44 @@ __global__ void __launch_bounds__(kTpb3) k3_sum(F f, int count, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// Both sums of a Sum2 functor, by the same tree; partials a, b of block k
+// at part[2k], part[2k + 1].
+template <class F>
+__global__ void __launch_bounds__(kTpb3) k3_sum2(F f, int count, double *part) {
+  __shared__ double va[kTpb3], vb[kTpb3];
+  const int i = grid_index(blockIdx.x, threadIdx.x);
+  Sum2 x{0.0, 0.0};
+  if (i < count) x = f(i);
+  va[threadIdx.x] = x.a;
+  vb[threadIdx.x] = x.b;
+  __syncthreads();
+  for (int h = kTpb3 / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      va[threadIdx.x] += va[threadIdx.x + h];
+      vb[threadIdx.x] += vb[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = va[0];
+    part[2 * blockIdx.x + 1] = vb[0];
+  }
+}
+
+// The two sums in block order, left at sa and sb, then post(0) (one thread).
+template <class P>
+__global__ void k3_finish2(const double *part, int nb, double *sa, double *sb, P post) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  *sa = a;
+  *sb = b;
+  post(0);
+}
+
 // The block partials added in block order, left at slot (one thread: the
 // order of the host's sum).
 __global__ void k3_finish(const double *part, int nb, double *slot) {
@@ -133,7 +171,18 @@ struct DeviceBackend {
   hipStream_t s = nullptr;
   double *part = nullptr, *part_h = nullptr;
   int part_cap = 0;
+  int part_gen = 0;   // bumped whenever part is reallocated (recorded graphs hold it)
   hipError_t err = hipSuccess;
+  struct Graph {
+    int key, gen;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t cap = nullptr;   // recording stream (created on first use)
+  bool capturing = false;
+  // the stream launches go to: the recording stream while a batch is
+  // recorded, else the context's stream
+  hipStream_t st() const { return capturing ? cap : s; }
 
   void note(hipError_t e) {
     if (err == hipSuccess && e != hipSuccess) err = e;
@@ -150,7 +199,57 @@ struct DeviceBackend {
       return false;
     }
     part_cap = blocks;
+    ++part_gen;
     return true;
+  }
+  // A CG batch recorded under key, replayed while the partials buffer it
+  // reduces into is the same one.
+  bool replay(int key) {
+    for (const Graph &g : graphs)
+      if (g.key == key && g.gen == part_gen) {
+        note(hipGraphLaunch(g.exec, s));
+        return true;
+      }
+    return false;
+  }
+  // The batch is recorded on a stream of the backend's own and replayed on
+  // the context's stream (which may be the null stream).
+  bool capture_begin(int blocks) {
+    if (err != hipSuccess || !reserve(blocks)) return false;
+    if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+      cap = nullptr;
+      (void)hipGetLastError();
+      return false;
+    }
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    capturing = true;
+    return true;
+  }
+  // Ends the recording, keeps the graph under key (replacing an older one)
+  // and launches it once.
+  void capture_end(int key) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    capturing = false;
+    note(e);
+    if (e != hipSuccess) return;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    note(e);
+    if (e != hipSuccess) return;
+    for (size_t k = 0; k < graphs.size();)
+      if (graphs[k].key == key) {
+        (void)hipGraphExecDestroy(graphs[k].exec);
+        graphs.erase(graphs.begin() + k);
+      } else {
+        ++k;
+      }
+    graphs.push_back({key, part_gen, ex});
+    note(hipGraphLaunch(ex, s));
   }
   void *alloc(size_t bytes) {
     void *p = nullptr;
@@ -172,13 +271,13 @@ struct DeviceBackend {
   template <class F>
   void each(int count, const F &f) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k3_each<F>, dim3(grid_blocks(count)), dim3(kTpb3), 0, s, f, count);
+    hipLaunchKernelGGL(k3_each<F>, dim3(grid_blocks(count)), dim3(kTpb3), 0, st(), f, count);
     note(hipGetLastError());
   }
   // q = K_t(u; d) p by the element-once kernel; skipped while *done is set
   void tangent_apply(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
                      const double *p, double *q, const int *done) {
-    hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0, s, g, m, u, d, p, q,
+    hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0, st(), g, m, u, d, p, q,
                        done);
     note(hipGetLastError());
   }
@@ -187,21 +286,32 @@ struct DeviceBackend {
   void sum_into(int count, const F &f, double *slot) {
     const int nb = grid_blocks(count);
     if (count <= 0) {
-      hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, s, part, 0, slot);
+      hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, st(), part, 0, slot);
       note(hipGetLastError());
       return;
     }
     if (!reserve(nb)) return;
-    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, s, f, count, part);
+    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, st(), f, count, part);
     note(hipGetLastError());
-    hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, s, part, nb, slot);
+    hipLaunchKernelGGL(k3_finish, dim3(1), dim3(1), 0, st(), part, nb, slot);
+    note(hipGetLastError());
+  }
+  template <class F, class P>
+  void sum2_into(int count, const F &f, double *sa, double *sb, const P &post) {
+    const int nb = count > 0 ? grid_blocks(count) : 0;
+    if (nb > 0) {
+      if (!reserve(2 * nb)) return;
+      hipLaunchKernelGGL(k3_sum2<F>, dim3(nb), dim3(kTpb3), 0, st(), f, count, part);
+      note(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k3_finish2<P>, dim3(1), dim3(1), 0, st(), part, nb, sa, sb, post);
     note(hipGetLastError());
   }
   template <class F>
   double sum(int count, const F &f) {
     const int nb = grid_blocks(count);
     if (count <= 0 || !reserve(nb)) return 0.0;
-    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, s, f, count, part);
+    hipLaunchKernelGGL(k3_sum<F>, dim3(nb), dim3(kTpb3), 0, st(), f, count, part);
     note(hipGetLastError());
     note(hipMemcpyAsync(part_h, part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
     note(hipStreamSynchronize(s));
@@ -211,7 +321,9 @@ struct DeviceBackend {
     return total;
   }
   ~DeviceBackend() {
-    if (s) (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    for (const Graph &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap) (void)hipStreamDestroy(cap);
     if (part) (void)hipFree(part);
     if (part_h) (void)hipHostFree(part_h);
   }
@@ -356,7 +468,8 @@ pf_status pf3d_create(const pf3d_mesh *mesh, const pf_material *mat,
   c->g = g;
   c->be.s = static_cast<hipStream_t>(hip_stream);
   c->sol.reset(new Solver3<DeviceBackend>(c->be, g, m, o));
-  const bool ok = c->sol->init() && c->be.reserve(grid_blocks(std::max(3 * g.N, 8 * g.E)));
+  const bool ok = c->sol->init() &&
+                  c->be.reserve(std::max(2 * grid_blocks(3 * g.N), grid_blocks(8 * g.E)));
   if (!ok || c->be.err != hipSuccess) {
     const pf_status s = c->be.err == hipErrorOutOfMemory || !ok ? PF_E_OOM : PF_E_HIP;
     pf3d_destroy(c);

@@ -10,6 +10,15 @@
 //                       the same bits;
 //   B::sum_into(count, f, slot)  the same sum, left in device memory at slot
 //                       (no host synchronisation);
+//   B::sum2_into(count, f, slot_a, slot_b, post)  the two sums of a functor
+//                       returning Sum2, in the same order, left at the two
+//                       slots, after which post(0) runs once (one thread);
+//   B::replay(key), B::capture_begin(blocks), B::capture_end(key)  an
+//                       optional record-and-replay of a CG batch: replay
+//                       launches the batch recorded under key if it is still
+//                       valid; capture_begin (which first reserves `blocks`
+//                       reduction partials) starts recording, or returns
+//                       false, and the batch then runs as it is enqueued;
 //   B::alloc/release/upload/download for the buffers.
 // The device backend (pf3d_kernels.hip) launches one kernel per call; a host
 // backend that replays the same grid serves the tests.
@@ -148,7 +157,7 @@ constexpr int kCgBatch3 = 16;
 // done: 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 at max_cg,
 // 4 zero right-hand side.
 struct CgState3 {
-  double bb, rz, pq, rr, rz_new, alpha, beta, tol2;
+  double bb, rz, pq, rr, rz_new, beta, tol2;
   int iters, maxit, done, pad;
 };
 
@@ -172,7 +181,31 @@ struct FMaskDot {
     return p[i] * q[i];
   }
 };
-struct FCgAlpha {
+// Two sums of one pass (see B::sum2_into).
+struct Sum2 {
+  double a, b;
+};
+// One pass of the CG update: with alpha = rz / pq, x += alpha p and
+// r -= alpha q on free entries while the solve runs and p.q > 0; then
+// z = D^-1 r.  Returns (r_i^2, r_i z_i), (0, 0) on fixed entries.  Every
+// thread forms the same alpha from the same two scalars.
+struct FCgUpdate {
+  const CgState3 *s; double *x, *r, *z; const double *p, *q, *Dinv; const uint8_t *fixed;
+  __host__ __device__ Sum2 operator()(int i) const {
+    if (!fixed[i] && !s->done && s->pq > 0.0) {
+      const double alpha = s->rz / s->pq;
+      x[i] += alpha * p[i];
+      r[i] -= alpha * q[i];
+    }
+    const double zi = Dinv[i] * r[i];
+    z[i] = zi;
+    if (fixed[i]) return Sum2{0.0, 0.0};
+    return Sum2{r[i] * r[i], r[i] * zi};
+  }
+};
+// After the update's sums: a breakdown (p.q <= 0) ends the solve; else
+// counts the iteration, tests ||r||^2 <= tol^2 ||b||^2 and max_cg, forms beta
+struct FCgBeta {
   CgState3 *s;
   __host__ __device__ void operator()(int) const {
     if (s->done) return;
@@ -180,35 +213,6 @@ struct FCgAlpha {
       s->done = 2;
       return;
     }
-    s->alpha = s->rz / s->pq;
-  }
-};
-// x += alpha p, r -= alpha q on free entries while the solve runs;
-// returns r_i^2 of the updated r (0 on fixed entries)
-struct FCgXRNorm {
-  const CgState3 *s; double *x, *r; const double *p, *q; const uint8_t *fixed;
-  __host__ __device__ double operator()(int i) const {
-    if (fixed[i]) return 0.0;
-    if (!s->done) {
-      x[i] += s->alpha * p[i];
-      r[i] -= s->alpha * q[i];
-    }
-    return r[i] * r[i];
-  }
-};
-// z = D^-1 r; returns r_i z_i (0 on fixed entries)
-struct FPrecDot {
-  const double *Dinv, *r; double *z; const uint8_t *fixed;
-  __host__ __device__ double operator()(int i) const {
-    z[i] = Dinv[i] * r[i];
-    return fixed[i] ? 0.0 : r[i] * z[i];
-  }
-};
-// counts the iteration, tests ||r||^2 <= tol^2 ||b||^2 and max_cg, forms beta
-struct FCgBeta {
-  CgState3 *s;
-  __host__ __device__ void operator()(int) const {
-    if (s->done) return;
     s->iters += 1;
     if (s->rr <= s->tol2) {
       s->done = 1;
@@ -434,8 +438,10 @@ class Solver3 {
   // scalars stay in device memory (CgState3); batches of kCgBatch3
   // iterations are enqueued between polls of the state, and the launches of
   // a batch after the solve has ended change nothing.
+  // key names the call site (its buffers and operator), under which the
+  // backend may keep the batch as a replayable graph.
   template <class Apply>
-  int pcg(int n, const double *rhs, const uint8_t *fixed, double tol, Apply &&apply,
+  int pcg(int key, int n, const double *rhs, const uint8_t *fixed, double tol, Apply &&apply,
           Counts3 *st) {
     be_.each(n, FFill{0.0, x_});
     be_.each(n, FAxpy{rhs, rhs, 0.0, fixed, r_});            // r = rhs on free entries
@@ -447,14 +453,18 @@ class Solver3 {
     CgState3 h{};
     be_.download(&h, cs_, sizeof h);
     while (!h.done) {
-      for (int k = 0; k < kCgBatch3; ++k) {
-        apply(p_, q_);
-        be_.sum_into(n, FMaskDot{q_, p_, fixed}, &cs_->pq);
-        be_.each(1, FCgAlpha{cs_});
-        be_.sum_into(n, FCgXRNorm{cs_, x_, r_, p_, q_, fixed}, &cs_->rr);
-        be_.sum_into(n, FPrecDot{Dinv_, r_, z_, fixed}, &cs_->rz_new);
-        be_.each(1, FCgBeta{cs_});
-        be_.each(n, FCgP{cs_, p_, z_, fixed});
+      if (!be_.replay(key)) {
+        // every launch of a batch reads and writes the same buffers, so the
+        // backend can record the batch once and replay it
+        const bool rec = be_.capture_begin(2 * grid_blocks(n));
+        for (int k = 0; k < kCgBatch3; ++k) {
+          apply(p_, q_);
+          be_.sum_into(n, FMaskDot{q_, p_, fixed}, &cs_->pq);
+          be_.sum2_into(n, FCgUpdate{cs_, x_, r_, z_, p_, q_, Dinv_, fixed}, &cs_->rr,
+                        &cs_->rz_new, FCgBeta{cs_});
+          be_.each(n, FCgP{cs_, p_, z_, fixed});
+        }
+        if (rec) be_.capture_end(key);
       }
       be_.download(&h, cs_, sizeof h);
       if (!be_.ok()) break;
@@ -477,7 +487,10 @@ class Solver3 {
       be_.each(g_.N, FTangentDiag{g_, m_, u_, d_, D_});
       be_.each(N3, FInvDiag{D_, fu_, Dinv_});
       const double *u = u_;
-      const int cg = pcg(N3, R_, fu_, o_.tol_pcg, [&](const double *p, double *q) {
+      // the line search swaps u_ and ut_, so the batch's graph depends on
+      // which of the two buffers holds the Newton point
+      const int cg = pcg(u_ < ut_ ? 0 : 3, N3, R_, fu_, o_.tol_pcg,
+                         [&](const double *p, double *q) {
         be_.tangent_apply(g_, m_, u, d_, p, q, &cs_->done);
       }, st);
       st->n_cg_u += cg;
@@ -528,7 +541,7 @@ class Solver3 {
     phase_residual(Hs, &nR, &nb);
     be_.each(N, FPhaseDiag{g_, m_, coef_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
-    const int cg = pcg(N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
+    const int cg = pcg(1, N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
       be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, coef_, p, q}});
     }, st);
     st->n_cg_d += cg;
@@ -548,7 +561,7 @@ class Solver3 {
         g_.E, FFloorHits{g_, m_, o_.trial_floor, H_, psi_, flags_, d_, ctr_});
     be_.each(N, FPhaseDiag{g_, m_, ctr_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
-    const int cg = pcg(N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
+    const int cg = pcg(2, N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
       be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, ctr_, p, q}});
     }, st);
     st->n_cg_trial += cg;

@@ -37,9 +37,37 @@ struct HostBackend {
     if (!*done) t3_tangent_host(g, m, u, d, p, q);
   }
   bool ok() const { return true; }
+  // no recording on the host: a batch runs as it is enqueued
+  bool replay(int) { return false; }
+  bool capture_begin(int) { return false; }
+  void capture_end(int) {}
   template <class F>
   void sum_into(int count, const F &f, double *slot) {
     *slot = sum(count, f);
+  }
+  template <class F, class P>
+  void sum2_into(int count, const F &f, double *sa, double *sb, const P &post) {
+    double ta = 0.0, tb = 0.0;
+    double va[kTpb3], vb[kTpb3];
+    for (int b = 0; b < grid_blocks(count); ++b) {
+      for (int t = 0; t < kTpb3; ++t) {
+        const int i = grid_index(b, t);
+        Sum2 x{0.0, 0.0};
+        if (i < count) x = f(i);
+        va[t] = x.a;
+        vb[t] = x.b;
+      }
+      for (int h = kTpb3 / 2; h > 0; h >>= 1)
+        for (int t = 0; t < h; ++t) {
+          va[t] += va[t + h];
+          vb[t] += vb[t + h];
+        }
+      ta += va[0];
+      tb += vb[0];
+    }
+    *sa = ta;
+    *sb = tb;
+    post(0);
   }
   template <class F>
   double sum(int count, const F &f) {
