@@ -246,7 +246,7 @@ def step_table(rows):
 
 def copy_bandwidth():
     """Measured device-to-device copy rate (GB/s, bytes read + written) of a
-    1 GiB buffer, the box's practical HBM ceiling beside the 8 TB/s peak."""
+    1 GiB buffer: the GPU's practical HBM ceiling beside the 8 TB/s peak."""
     import torch
     n = 256 * 1024 * 1024
     src = torch.ones(n, dtype=torch.float32, device="cuda")
