@@ -92,7 +92,8 @@ struct pf_ctx {
   CgBuf<float> bf;
   Cg1State *cgs = nullptr;     // [2]
   CgState *cgs2 = nullptr;      // two-kernel CG state
-  CgState *cgs2_h = nullptr;
+  CgState *cgs2_h = nullptr;    // [2]: the polls of two batches in flight
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double *cgpart = nullptr;     // [2][3][kPMax]
   RedScratch rs{};
   // pinned host mirrors
@@ -946,16 +947,48 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
       c->graphs.push_back({kind, fp32, ngraph, variant, tol, ex});
     }
   }
-  for (;;) {
-    const bool tb = timed && (c->prof_tick[kid]++ % kProfEvery) == 0;
+  // A batch, then a copy of the CG state to one of two host slots and an
+  // event after it.  While the residual's decay between polls says that the
+  // solve needs well over another batch, the next batch and its poll are
+  // enqueued before the host waits for the current one, so the GPU does not
+  // idle through the round trip.  A batch enqueued after convergence exits
+  // in its kernels' prologues, as the rest of a batch does.
+  auto enqueue_batch = [&](bool tb, int slot) -> pf_status {
     if (tb) PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, 2, true, cheb ? &cs : nullptr));
     if (ex) {
       PF_HIP(c, hipGraphLaunch(ex, c->stream));
     } else {
       PF_TRY(enqueue_iters2<T>(c, c->stream, kind, ca, n, ngraph, false, cheb ? &cs : nullptr));
     }
-    PF_HIP(c, hipMemcpyAsync(c->cgs2_h, c->cgs2, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-    PF_TRY(sync(c));
+    PF_HIP(c, hipMemcpyAsync(c->cgs2_h + slot, c->cgs2, sizeof(CgState), hipMemcpyDeviceToHost,
+                             c->stream));
+    PF_HIP(c, hipEventRecord(c->poll_ev[slot], c->stream));
+    return PF_OK;
+  };
+  const double tol2 = tol * tol;
+  int slot = 0;
+  bool ahead = false;               // the batch of `slot` is already enqueued
+  double rr_last = -1.0, rr0 = 0.0; // r.r, the initial r.r and the iteration count
+  int it_last = 0;                  // at the previous poll
+  double log_rate = 0.0;            // log of the per-iteration decay of r.r (< 0)
+  const int per_batch = ngraph + (timed ? 2 : 0);
+  for (;;) {
+    bool tb = false;
+    if (!ahead) {
+      tb = timed && (c->prof_tick[kid]++ % kProfEvery) == 0;
+      PF_TRY(enqueue_batch(tb, slot));
+    }
+    bool next_ahead = false;
+    // the batch of `slot` runs iterations it_last .. it_last + per_batch;
+    // one enqueued ahead would run the next per_batch
+    const double target = tol2 * rr0;
+    if (!tb && rr_last > target && target > 0.0 && log_rate < 0.0 &&
+        std::log(target / rr_last) / log_rate > 2.5 * per_batch) {
+      PF_TRY(enqueue_batch(false, slot ^ 1));
+      next_ahead = true;
+    }
+    PF_HIP(c, hipEventSynchronize(c->poll_ev[slot]));
+    const CgState &h = c->cgs2_h[slot];
     if (tb) {
       float a = 0.f, u = 0.f;
       PF_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
@@ -978,10 +1011,20 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
         c->prof_ms[3] += q;
       }
     }
-    if (c->cgs2_h->b.done != 0) break;
+    // a batch enqueued ahead finishes in stream order: it writes the other
+    // slot and no buffer the caller reads
+    if (h.b.done != 0) break;
+    if (rr_last > 0.0 && h.a.rr > 0.0 && h.a.iters > it_last)
+      log_rate = std::log(h.a.rr / rr_last) / double(h.a.iters - it_last);
+    rr_last = h.a.rr;
+    rr0 = h.a.rr0;
+    it_last = h.a.iters;
+    if (next_ahead) slot ^= 1;
+    ahead = next_ahead;
   }
-  *iters = c->cgs2_h->b.iters;
-  *status = c->cgs2_h->b.done;
+  const CgState &fin = c->cgs2_h[slot];
+  *iters = fin.b.iters;
+  *status = fin.b.done;
   // the fused update alternates the x buffers: the last active iteration
   // wrote X[iters & 1]
   *xout = (cheb && cs.size() >= 2) ? b.X[*iters & 1] : b.X[0];
@@ -1726,7 +1769,9 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
   }
   if (s == PF_OK) {
     if (hipHostMalloc((void **)&c->cgs_h, 2 * sizeof(Cg1State)) != hipSuccess ||
-        hipHostMalloc((void **)&c->cgs2_h, sizeof(CgState)) != hipSuccess ||
+        hipHostMalloc((void **)&c->cgs2_h, 2 * sizeof(CgState)) != hipSuccess ||
+        hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void **)&c->cheb_h, 4 * kChebCoefs * sizeof(double)) != hipSuccess ||
@@ -1753,6 +1798,8 @@ pf_status pf_destroy(pf_ctx *c) {
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
+  for (auto &e : c->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->cgs_h) (void)hipHostFree(c->cgs_h);
