@@ -73,6 +73,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time per load history and GDOF-updates/s, S1 mixed vs std FP64, 1 MI355X"
+GUESS_VECTORS = 0   # --guess-vectors: starting guesses of the displacement solves (timed runs)
 KIND = {"tension512": "notched tension panel", "tension64": "notched tension panel",
         "shear1024": "notched shear panel (spectral split)",
         "lshape2048": "L-shaped panel (masked quadrant)"}
@@ -184,6 +185,8 @@ def run_steps(pf, problem, scheme, precision, warmup, steps, profile=False, degr
     step."""
     import torch
     opts = {} if degree is None else {"precond": 1, "cheb_degree": degree}
+    if GUESS_VECTORS:
+        opts["guess_vectors"] = GUESS_VECTORS
     ctx = pf.Context(problem, scheme=scheme, precision=precision, march_rows=rows, **opts)
     if state is not None:
         ctx.set_state(*state)
@@ -764,10 +767,15 @@ def main():
     ap.add_argument("--at1", action="store_true",
                     help="AT1 with penalised irreversibility instead of AT2 with the history "
                          "field, for both schemes")
+    ap.add_argument("--guess-vectors", type=int, default=0,
+                    help="start the displacement solves of the timed runs from the projection "
+                         "onto this many earlier solutions (0..4; 0 = from zero)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
 
+    global GUESS_VECTORS
+    GUESS_VECTORS = args.guess_vectors
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -842,7 +850,8 @@ def main():
             "gdof_updates_per_s": sum(r["dof_updates"] for r in rows2) / secs2 / 1e9,
             "max_stag": problem.max_stag, "steps_table": step_table(rows2),
             "precond": "jacobi" if st_deg is None else f"jacobi-chebyshev degree {st_deg}",
-            "march_rows": ctx2.chosen_rows, "dtype": "f64", "data": "synthetic"}))
+            "march_rows": ctx2.chosen_rows, "guess_vectors": GUESS_VECTORS, "dtype": "f64",
+            "data": "synthetic"}))
         ctx2.close()
         if jsonl:
             jsonl.close()
@@ -972,6 +981,7 @@ def main():
             "tol_stag": problem.tol_stag, "tol_pcg": problem.tol_pcg,
             "phase_model": ("AT1 with penalised irreversibility" if args.at1
                             else "AT2 with history field"),
+            "guess_vectors": GUESS_VECTORS,
         },
         "s1_mixed": {"seconds": secs, "steps": step_table(rows)},
         "st_fp64": st_res,

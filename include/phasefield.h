@@ -145,6 +145,11 @@ typedef struct {
   int32_t trial_update;   /* pf_trial_update                                  */
   double tol_ir;          /* AT1_PENALTY: irreversibility tolerance (0.01)    */
   int32_t phase_model;    /* pf_phase_model                                   */
+  int32_t guess_vectors;  /* 0..4: displacement CG solves whose relative      */
+                          /* tolerance is below 1e-3 start from the Galerkin  */
+                          /* projection of their right-hand side onto the     */
+                          /* last guess_vectors such solutions (two-kernel CG */
+                          /* on the context's stream only; 0 = off)           */
 } pf_solver_opts;
 
 typedef struct {
@@ -174,7 +179,8 @@ typedef struct {
  * tol_newton 1e-9, tol_inner 1e-5, max_stag 500, max_newton 25,
  * max_cg 200000, cg_check 32, psi_crit -1, d_gate 0.95, trial_floor 0.1,
  * march_rows 0, cg_kernels 0, cheb_ratio 0 (30), trial_operator FLOORED,
- * trial_update PREDICT_CORRECT, tol_ir 0.01, phase_model AT2_HISTORY. */
+ * trial_update PREDICT_CORRECT, tol_ir 0.01, phase_model AT2_HISTORY,
+ * guess_vectors 0. */
 void pf_default_opts(pf_solver_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t

@@ -70,7 +70,8 @@ class SolverOpts(ctypes.Structure):
                 ("psi_crit", c_double), ("d_gate", c_double), ("trial_floor", c_double),
                 ("march_rows", c_int32), ("cg_kernels", c_int32),
                 ("cheb_ratio", c_double), ("trial_operator", c_int32),
-                ("trial_update", c_int32), ("tol_ir", c_double), ("phase_model", c_int32)]
+                ("trial_update", c_int32), ("tol_ir", c_double), ("phase_model", c_int32),
+                ("guess_vectors", c_int32)]
 
 
 class StepStats(ctypes.Structure):

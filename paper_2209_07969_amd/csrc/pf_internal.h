@@ -39,6 +39,7 @@ struct alignas(128) CgHalfB {
   double rz_prev; // r.z of the previous iteration (for beta)
   double rr0;
   double tol2;    // squared relative tolerance of the solve (set by the init)
+  double rr_abs;  // > 0: converged at r.r <= rr_abs instead (a warm start)
   int done;
   int iters;
   int first;      // 1 before the first direction
@@ -131,6 +132,24 @@ struct CgArgs {
               // also writes the (r.z, r.r) partials; the vector kernels then
               // update only x and r
   int npb;    // number of (r.z, r.r) partials the apply prologue reduces
+  int warm;   // 1: x holds a starting guess and r its residual (the init keeps x)
+  double rr_abs;  // > 0: absolute convergence target for r.r (a warm start)
+};
+
+// Starting guess of a displacement solve from earlier solutions (the
+// Galerkin projection of the right-hand side onto their span, with the
+// current operator): up to kGuessMax stored solutions v_j and w_j = K v_j.
+constexpr int kGuessMax = 4;
+// v_j . w_k (j <= k), v_j . b, b . b
+constexpr int kGuessDots = kGuessMax * (kGuessMax + 1) / 2 + kGuessMax + 1;
+template <class T>
+struct GuessArgs {
+  const T *v[kGuessMax];
+  const T *w[kGuessMax];
+  int m, n;
+};
+struct GuessCoef {
+  double c[kGuessMax];
 };
 
 // One step of the Jacobi-Chebyshev polynomial (z = p(D^-1 A) D^-1 r by
@@ -370,6 +389,20 @@ hipError_t phase_mr_apply(hipStream_t s, const Grid &g, const March &m, const Ph
                           const MrVecs &v, const MrArgs &a, int j);
 hipError_t mr_update(hipStream_t s, int n, const MrVecs &v, const MrArgs &a, int j);
 int vec_block_count(int n);
+
+// q = K_t p in the CG's precision, zero on fixed displacement entries.
+template <class T>
+hipError_t tangent_apply_masked(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                                int split, const T *ulin, const T *d, const uint8_t *qflag,
+                                const uint8_t *eact, const uint8_t *nflag, const T *p, T *q);
+// The kGuessDots sums of a starting guess (b = the right-hand side), block
+// partials then finalised into out[0 .. kGuessDots).
+template <class T>
+hipError_t guess_dots(hipStream_t s, const GuessArgs<T> &a, const T *b, double *part,
+                      double *out);
+// x = sum_j c_j v_j and r = b - sum_j c_j w_j, in place of b.
+template <class T>
+hipError_t guess_combine(hipStream_t s, const GuessArgs<T> &a, const GuessCoef &c, T *x, T *rb);
 
 // Plain operator applies (no CG fusion, no masking) for the op entry points.
 hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,

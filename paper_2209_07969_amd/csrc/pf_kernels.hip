@@ -1404,7 +1404,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
                                                  const T *Dinv, CgArgs ca) {
   double v[2] = {0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    x[i] = T(0);
+    if (!ca.warm) x[i] = T(0);
     pold[i] = T(0);
     if (!ca.ext) {
       const T ri = r[i];
@@ -1419,6 +1419,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int n, T *x, T *r, T *z, T *pol
     ca.st->b.rz_prev = 0.0;
     ca.st->b.rr0 = 0.0;
     ca.st->b.tol2 = ca.tol2;
+    ca.st->b.rr_abs = ca.rr_abs;
     ca.st->b.done = 0;
     ca.st->b.iters = 0;
     ca.st->b.first = 1;
@@ -1436,7 +1437,7 @@ __device__ inline int cg_apply_prologue(const CgArgs &ca, double *beta, int bid)
   const double rr0 = first ? rr : ca.st->b.rr0;
   if (!done) {
     if (!(rr == rr) || !(rz == rz)) done = 2;
-    else if (rr <= ca.st->b.tol2 * rr0) done = 1;
+    else if (rr <= (ca.st->b.rr_abs > 0.0 ? ca.st->b.rr_abs : ca.st->b.tol2 * rr0)) done = 1;
     else if (iters >= ca.maxit) done = 3;
   }
   if (bid == 0 && threadIdx.x == 0) {
@@ -2859,6 +2860,62 @@ __global__ void __launch_bounds__(TPB) k_group_sum(int n, const int64_t *dof,
   }
 }
 
+// ---- starting guess of a displacement solve from earlier solutions
+
+// Per thread over a grid stride: v_j . w_k (j <= k), v_j . b and b . b in
+// FP64, then block partials (unused pairs add 0).
+template <class T>
+__global__ void __launch_bounds__(TPB) k_guess_dots(GuessArgs<T> a, const T *b, double *part) {
+  double acc[kGuessDots];
+#pragma unroll
+  for (int k = 0; k < kGuessDots; ++k) acc[k] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+    double v[kGuessMax], w[kGuessMax];
+#pragma unroll
+    for (int j = 0; j < kGuessMax; ++j) {
+      v[j] = j < a.m ? double(a.v[j][i]) : 0.0;
+      w[j] = j < a.m ? double(a.w[j][i]) : 0.0;
+    }
+    const double bi = double(b[i]);
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < kGuessMax; ++j)
+#pragma unroll
+      for (int l = j; l < kGuessMax; ++l) acc[k++] += v[j] * w[l];
+#pragma unroll
+    for (int j = 0; j < kGuessMax; ++j) acc[k++] += v[j] * bi;
+    acc[k] += bi * bi;
+  }
+  block_partial<kGuessDots>(acc, part);
+}
+
+// One block: each of nv partial arrays (stride kPMax) summed in the fixed
+// order of block_sum, to out[k].
+__global__ void __launch_bounds__(TPB) k_finalize_each(const double *part, int np, int nv,
+                                                       double *out) {
+  for (int k = 0; k < nv; ++k) {
+    double s[1];
+    block_sum<1>(part + k * kPMax, np, s);
+    if (threadIdx.x == 0) out[k] = s[0];
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_guess_combine(GuessArgs<T> a, GuessCoef c, T *x,
+                                                       T *rb) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+    double xi = 0.0, ri = double(rb[i]);
+#pragma unroll
+    for (int j = 0; j < kGuessMax; ++j)
+      if (j < a.m) {
+        xi += c.c[j] * double(a.v[j][i]);
+        ri -= c.c[j] * double(a.w[j][i]);
+      }
+    x[i] = T(xi);
+    rb[i] = T(ri);
+  }
+}
+
 // ------------------------------------------------------------- MINRES
 //
 // Preconditioned MINRES for the unfloored trial block of the evolution
@@ -3263,6 +3320,8 @@ CgArgs cg_args(const Grid &, const March &m, int n, CgState *st, RedScratch rs, 
   ca.maxit = maxit;
   ca.ext = 0;
   ca.npb = ca.gb;
+  ca.warm = 0;
+  ca.rr_abs = 0.0;
   return ca;
 }
 
@@ -3532,6 +3591,38 @@ hipError_t tangent_apply_plain(hipStream_t s, const Grid &g, const March &m, con
   return launch_march(s, op, g, m, nullptr);
 }
 
+template <class T>
+hipError_t tangent_apply_masked(hipStream_t s, const Grid &g, const March &m, const ElasCoef &c,
+                                int split, const T *ulin, const T *d, const uint8_t *qflag,
+                                const uint8_t *eact, const uint8_t *nflag, const T *p, T *q) {
+  if (split == 1) {
+    OpTangent<T, false, true, 1> op{g, c, d, qflag, eact, nflag, p, nullptr, nullptr, q, T(0),
+                                    ulin};
+    return launch_march(s, op, g, m, nullptr);
+  }
+  OpTangent<T, false, true, 0> op{g, c, d, qflag, eact, nflag, p, nullptr, nullptr, q, T(0),
+                                  nullptr};
+  return launch_march(s, op, g, m, nullptr);
+}
+
+template <class T>
+hipError_t guess_dots(hipStream_t s, const GuessArgs<T> &a, const T *b, double *part,
+                      double *out) {
+  const int nb = vec_blocks(a.n);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_guess_dots<T>), dim3(nb), dim3(TPB), 0, s, a, b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize_each, dim3(1), dim3(TPB), 0, s, part, nb, kGuessDots, out);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t guess_combine(hipStream_t s, const GuessArgs<T> &a, const GuessCoef &c, T *x, T *rb) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_guess_combine<T>), dim3(vec_blocks(a.n)), dim3(TPB), 0, s,
+                     a, c, x, rb);
+  return hipGetLastError();
+}
+
 hipError_t phase_apply_plain(hipStream_t s, const Grid &g, const March &m, const PhaseCoef &c,
                              const double *coef, const uint8_t *eact, const double *p,
                              double *q) {
@@ -3685,6 +3776,14 @@ hipError_t fill_zero_bytes(hipStream_t s, void *p, size_t bytes) {
                                    const T *);                                                 \
   template hipError_t cg_init<T>(hipStream_t, int, T *, T *, T *, T *, const T *,             \
                                  const CgArgs &);                                              \
+  template hipError_t tangent_apply_masked<T>(hipStream_t, const Grid &, const March &,        \
+                                              const ElasCoef &, int, const T *, const T *,     \
+                                              const uint8_t *, const uint8_t *,                \
+                                              const uint8_t *, const T *, T *);                \
+  template hipError_t guess_dots<T>(hipStream_t, const GuessArgs<T> &, const T *, double *,    \
+                                    double *);                                                 \
+  template hipError_t guess_combine<T>(hipStream_t, const GuessArgs<T> &, const GuessCoef &,   \
+                                       T *, T *);                                              \
   template hipError_t cg_update<T>(hipStream_t, int, T *, T *, T *, const T *, const T *,      \
                                    const T *, const CgArgs &, const ChebFuse<T> &);            \
   template hipError_t tangent_cg_apply<T>(hipStream_t, const Grid &, const March &,            \

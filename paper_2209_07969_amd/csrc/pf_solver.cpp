@@ -59,6 +59,8 @@ struct CgBuf {
   T *dc = nullptr;                  // second Chebyshev step vector
   T *pv[2] = {nullptr, nullptr};    // power-iteration vectors per operator kind
   T *coef = nullptr;   // [4E] phase coefficient
+  T *gv[kGuessMax] = {};   // [2N] stored displacement solutions (starting guesses)
+  T *gw[kGuessMax] = {};   // [2N] K v_j with the current operator
 };
 
 struct BatchSvc;
@@ -93,6 +95,10 @@ struct pf_ctx {
   Cg1State *cgs = nullptr;     // [2]
   CgState *cgs2 = nullptr;      // two-kernel CG state
   CgState *cgs2_h = nullptr;    // [2]: the polls of two batches in flight
+  int guess_m = 0, guess_next = 0;   // stored solutions, ring position
+  double *guess_part = nullptr;      // [kGuessDots * kPMax] block partials
+  double *guess_out = nullptr;       // [kGuessDots] finalised sums
+  double *guess_h = nullptr;         // host copy
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double *cgpart = nullptr;     // [2][3][kPMax]
   RedScratch rs{};
@@ -321,6 +327,12 @@ pf_status upload_constraints(pf_ctx *c) {
 // ------------------------------------------------------------------ PCG
 
 enum Kind { K_ELASTIC = 0, K_PHASE = 1 };
+// A two-kernel CG solve from a starting guess: x already holds it and the
+// right-hand side buffer its residual; the solve ends at r.r <= rr_abs.
+struct CgStart {
+  int warm = 0;
+  double rr_abs = 0.0;
+};
 constexpr int kTimedRepeat = 4;
 // With timing on, one enqueued CG batch in kProfEvery of each kind (the
 // first included) carries the timed launches, so the sample adds little to
@@ -893,7 +905,8 @@ pf_status shared_pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, 
 }
 
 template <class T>
-pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
+pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout,
+               const CgStart &start = CgStart{}) {
   if constexpr (std::is_same<T, float>::value) {
     if (c->svc && c->opts.precond == PF_PC_JACOBI && !c->profiling)
       return shared_pcg(c, kind, tol, iters, status, xout);
@@ -917,6 +930,8 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
     ca.ext = 1;
     ca.npb = cs.size() > 1 ? cg1_blocks(c->ms) : ca.gb;
   }
+  ca.warm = start.warm;
+  ca.rr_abs = start.rr_abs;
   PF_HIP(c, cg_init<T>(c->stream, n, b.X[0], b.R[0], b.W[0], b.P[0], b.Dinv, ca));
   if (cheb) PF_TRY(enqueue_cheb<T>(c, c->stream, kind, ca, n, cs, true, 1, false, b.R[0]));
   int batch = std::max(4, c->opts.cg_check);
@@ -1037,12 +1052,13 @@ pf_status pcg2(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xo
 // graph) between polls of the device-side status; kernels after convergence
 // exit in their prologue.  *xout points to the solution buffer.
 template <class T>
-pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout) {
+pf_status pcg(pf_ctx *c, Kind kind, double tol, int *iters, int *status, T **xout,
+              const CgStart &start = CgStart{}) {
   // the single-kernel formulation marches columns; LDS tiles use two kernels
   const bool two = c->opts.cg_kernels == 2 || c->ms.ch == 1 ||
                    (c->opts.cg_kernels == 0 && std::is_same<T, float>::value);
   if (two || c->opts.precond == PF_PC_JACOBI_CHEBYSHEV)
-    return pcg2<T>(c, kind, tol, iters, status, xout);
+    return pcg2<T>(c, kind, tol, iters, status, xout, start);
   CgBuf<T> &b = buf<T>(c);
   Cg1Args a;
   a.st = c->cgs;
@@ -1114,6 +1130,121 @@ inline double inner_tolerance(double tol_inner, double target, double nr) {
   return std::min(kForcingMax, std::max(tol_inner, kForcing * target / nr));
 }
 
+// ---- starting guesses of the displacement solves
+//
+// Consecutive displacement solves of a load history have nearly the same
+// operator, and their solutions (the response to a load increment, to the
+// change of d in one staggered iteration) point in nearly the same
+// directions.  A solve whose relative tolerance is below kGuessTol starts
+// from x0 = V c, the Galerkin projection of its right-hand side b onto the
+// span of the last stored solutions V with the current operator K:
+// (V' K V) c = V' b, the x0 of least energy error in that span.  Its
+// residual b - K V c replaces b, and the solve ends at the same absolute
+// target, tol ||b||, as a solve from zero.
+constexpr double kGuessTol = 1e-3;
+
+template <class T>
+bool guess_applies(const pf_ctx *c, double tol) {
+  if (c->opts.guess_vectors <= 0 || tol >= kGuessTol) return false;
+  if (c->opts.precond == PF_PC_JACOBI_CHEBYSHEV) return true;
+  const bool two = c->opts.cg_kernels == 2 || c->ms.ch == 1 ||
+                   (c->opts.cg_kernels == 0 && std::is_same<T, float>::value);
+  // FP32 Jacobi solves of a batch member go to the shared launches
+  const bool shared = std::is_same<T, float>::value && c->svc && !c->profiling;
+  return two && !shared;
+}
+
+// Solve G c = g for a symmetric positive semidefinite m x m Gram matrix:
+// symmetric Gaussian elimination on the unit-diagonal scaling, where a
+// direction whose pivot falls below kGuessPivot (a stored solution nearly in
+// the span of the ones before it) is left out (c_j = 0).
+constexpr double kGuessPivot = 1e-10;
+void guess_solve(int m, const double *G, const double *g, double *cout) {
+  double sc[kGuessMax], A[kGuessMax][kGuessMax], y[kGuessMax];
+  bool use[kGuessMax];
+  for (int i = 0; i < m; ++i) {
+    use[i] = G[i * m + i] > 0.0 && std::isfinite(G[i * m + i]);
+    sc[i] = use[i] ? 1.0 / std::sqrt(G[i * m + i]) : 0.0;
+  }
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i][j] = sc[i] * sc[j] * G[i * m + j];
+    y[i] = sc[i] * g[i];
+  }
+  for (int k = 0; k < m; ++k) {
+    if (!use[k] || !(A[k][k] > kGuessPivot)) {
+      use[k] = false;
+      continue;
+    }
+    for (int i = k + 1; i < m; ++i) {
+      if (!use[i]) continue;
+      const double f = A[i][k] / A[k][k];
+      for (int j = k; j < m; ++j) A[i][j] -= f * A[k][j];
+      y[i] -= f * y[k];
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    double v = 0.0;
+    if (use[k]) {
+      v = y[k];
+      for (int j = k + 1; j < m; ++j) v -= A[k][j] * y[j];
+      v /= A[k][k];
+    }
+    y[k] = v;   // the scaled solution, back-substituted in place
+  }
+  for (int i = 0; i < m; ++i) cout[i] = std::isfinite(y[i]) ? sc[i] * y[i] : 0.0;
+}
+
+// x0 into X[0] and its residual into R[0] (which holds b); *start tells
+// the CG about it.
+template <class T>
+pf_status guess_start(pf_ctx *c, double tol, CgStart *start) {
+  CgBuf<T> &b = buf<T>(c);
+  const int m = c->guess_m;
+  GuessArgs<T> a{};
+  a.m = m;
+  a.n = 2 * c->g.N;
+  for (int j = 0; j < m; ++j) {
+    PF_HIP(c, tangent_apply_masked<T>(c->stream, c->g, c->ms, c->ec, c->mt.split, b.ulin, b.d,
+                                      c->tflag, c->eact, c->nflag, b.gv[j], b.gw[j]));
+    a.v[j] = b.gv[j];
+    a.w[j] = b.gw[j];
+  }
+  PF_HIP(c, guess_dots<T>(c->stream, a, b.R[0], c->guess_part, c->guess_out));
+  PF_HIP(c, hipMemcpyAsync(c->guess_h, c->guess_out, kGuessDots * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  PF_TRY(sync(c));
+  // the sums come in the order v_j . w_k (j <= k, row by row of the
+  // kGuessMax x kGuessMax triangle), v_j . b, b . b
+  double G[kGuessMax * kGuessMax], gb[kGuessMax];
+  int k = 0;
+  for (int j = 0; j < kGuessMax; ++j)
+    for (int l = j; l < kGuessMax; ++l, ++k)
+      if (j < m && l < m) G[j * m + l] = G[l * m + j] = c->guess_h[k];
+  for (int j = 0; j < kGuessMax; ++j, ++k)
+    if (j < m) gb[j] = c->guess_h[k];
+  const double bb = c->guess_h[k];
+  if (!(bb > 0.0) || !std::isfinite(bb)) return PF_OK;   // nothing to solve: start from 0
+  GuessCoef cf{};
+  guess_solve(m, G, gb, cf.c);
+  PF_HIP(c, guess_combine<T>(c->stream, a, cf, b.X[0], b.R[0]));
+  start->warm = 1;
+  start->rr_abs = tol * tol * bb;
+  return PF_OK;
+}
+
+// Keep the solution of a solve that took the guess path (the ring's oldest
+// entry is replaced once it is full).
+template <class T>
+pf_status guess_store(pf_ctx *c, const T *x) {
+  CgBuf<T> &b = buf<T>(c);
+  const int cap = c->opts.guess_vectors;
+  PF_HIP(c, hipMemcpyAsync(b.gv[c->guess_next], x, 2 * (size_t)c->g.N * sizeof(T),
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->guess_next = (c->guess_next + 1) % cap;
+  if (c->guess_m < cap) ++c->guess_m;
+  return PF_OK;
+}
+
 template <class T>
 pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
   *ok = true;
@@ -1148,7 +1279,11 @@ pf_status newton_impl(pf_ctx *c, pf_step_stats *st, bool *ok) {
     T *xs = nullptr;
     const double tol_lin =
         mixed ? inner_tolerance(c->opts.tol_inner, tol, nr) : c->opts.tol_pcg;
-    PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status, &xs));
+    const bool guess = guess_applies<T>(c, tol_lin);
+    CgStart start;
+    if (guess && c->guess_m > 0) PF_TRY(guess_start<T>(c, tol_lin, &start));
+    PF_TRY(pcg<T>(c, K_ELASTIC, tol_lin, &iters, &status, &xs, start));
+    if (guess && status != 2) PF_TRY(guess_store<T>(c, xs));
     st->n_cg_u += iters;
     st->dof_updates += (double)iters * (double)c->n_free_u;
     if (status == 3) st->cg_not_converged += 1;
@@ -1576,6 +1711,10 @@ pf_status check_opts(const pf_solver_opts *o, std::string *msg) {
     *msg = "trial_operator and trial_update must be 0 or 1";
     return PF_E_INVALID_ARG;
   }
+  if (o->guess_vectors < 0 || o->guess_vectors > kGuessMax) {
+    *msg = "guess_vectors must be in 0..4";
+    return PF_E_INVALID_ARG;
+  }
   if (o->cg_kernels < 0 || o->cg_kernels > 2) {
     *msg = "cg_kernels must be 0, 1 or 2";
     return PF_E_INVALID_ARG;
@@ -1747,6 +1886,17 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
     A(&c->bf.pv[0], n2); A(&c->bf.pv[1], n2);
     if (mat->split == PF_SPLIT_SPECTRAL) A(&c->bf.ulin, n2);
   }
+  if (o.guess_vectors > 0) {
+    for (int j = 0; j < o.guess_vectors; ++j) {
+      if (o.precision == PF_MIXED) {
+        A(&c->bf.gv[j], n2); A(&c->bf.gw[j], n2);
+      } else {
+        A(&c->bd.gv[j], n2); A(&c->bd.gw[j], n2);
+      }
+    }
+    A(&c->guess_part, kGuessDots * (size_t)kPMax);
+    A(&c->guess_out, kGuessDots);
+  }
   A(&c->cheb_dev, 4 * (size_t)kChebCoefs);
   A(&c->mrs, 1);
   if (c->at1) {
@@ -1775,7 +1925,8 @@ pf_status pf_create(const pf_mesh_desc *mesh, const pf_material *mat, const pf_s
         hipHostMalloc((void **)&c->scal_h, kScal * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->icount_h, kICounters * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void **)&c->cheb_h, 4 * kChebCoefs * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->mrs_h, sizeof(MrState)) != hipSuccess)
+        hipHostMalloc((void **)&c->mrs_h, sizeof(MrState)) != hipSuccess ||
+        hipHostMalloc((void **)&c->guess_h, kGuessDots * sizeof(double)) != hipSuccess)
       s = PF_E_OOM;
   }
   if (s == PF_OK) s = upload_constraints(c);
@@ -1808,6 +1959,7 @@ pf_status pf_destroy(pf_ctx *c) {
   if (c->icount_h) (void)hipHostFree(c->icount_h);
   if (c->cheb_h) (void)hipHostFree(c->cheb_h);
   if (c->mrs_h) (void)hipHostFree(c->mrs_h);
+  if (c->guess_h) (void)hipHostFree(c->guess_h);
   delete c;
   return PF_OK;
 }

@@ -136,7 +136,7 @@ def test_option_validation_without_device():
     mat = pf.MaterialDesc(2.1e5, 0.3, 2.7, 0.03, 1e-6, 0)
     cases = {"cheb_ratio": 0.5, "cg_kernels": 3, "march_rows": 3, "cheb_degree": 0,
              "max_cg": 0, "max_stag": 0, "scheme": 7, "precision": 2, "precond": 5,
-             "trial_operator": 2, "trial_update": -1, "phase_model": 2}
+             "trial_operator": 2, "trial_update": -1, "phase_model": 2, "guess_vectors": 5}
     for name, value in cases.items():
         o = pf.default_opts()
         o.precond = 1          # Jacobi-Chebyshev, so that cheb_degree is checked

@@ -59,10 +59,12 @@ def free_run(pf, p, scheme, precision, z, stored, **opts):
     F_scale = np.abs(z["force"]).max()
     ctx = pf.Context(p, scheme=scheme, precision=precision, **opts)
     worst_F = 0.0
+    stats = []
     try:
         for n in range(1, n_steps + 1):
             k = n - 1
             sg = ctx.load_step(float(p.loads[k]))
+            stats.append(sg)
             n_o, n_g = int(z["n_stag"][k]), int(sg["n_stag"])
             F_g = float(sg["force"][p.load_comp])
             eF = abs(F_g - float(z["force"][k])) / F_scale
@@ -84,6 +86,7 @@ def free_run(pf, p, scheme, precision, z, stored, **opts):
     finally:
         ctx.close()
     print(f"  largest force error over the history {worst_F:.1e}", flush=True)
+    return stats
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -121,3 +124,27 @@ def test_reduced_configuration_history(gpu_lib, kind, scheme, precision):
     assert int(z["scheme"]) == SCHEME[scheme]
     p = reduced_problem(kind, int(z["max_stag"]))
     free_run(gpu_lib, p, SCHEME[scheme], precision, z, [int(s) for s in z["stored_steps"]])
+
+
+@pytest.mark.parametrize("scheme,precision,opts", [
+    ("S1", 1, {"precond": 1, "cheb_degree": 3, "march_rows": 1}),
+    ("ST", 0, {"precond": 1, "cheb_degree": 5, "march_rows": 2}),
+    ("S3", 1, {})])
+def test_tension64_whole_history_with_starting_guesses(gpu_lib, scheme, precision, opts):
+    """Displacement solves started from the projection onto the last four
+    solutions (guess_vectors = 4) give the same history as the oracle, under
+    the same protocol, with fewer displacement CG iterations than the same
+    run from zero."""
+    z = _load("teacher_forced", f"tension64_{scheme}")
+    stored = sorted(int(k[2:]) for k in z.files if k.startswith("u_"))
+    p = W.config_tension64()
+    with_guess = free_run(gpu_lib, p, SCHEME[scheme], precision, z, stored, guess_vectors=4,
+                          **opts)
+    ctx = gpu_lib.Context(p, scheme=SCHEME[scheme], precision=precision, **opts)
+    plain = [ctx.load_step(float(lam)) for lam in p.loads[:len(with_guess)]]
+    ctx.close()
+    cg_guess = sum(st["n_cg_u"] for st in with_guess)
+    cg_plain = sum(st["n_cg_u"] for st in plain)
+    print(f"  displacement CG iterations: {cg_guess} with starting guesses, {cg_plain} from zero",
+          flush=True)
+    assert cg_guess < cg_plain
