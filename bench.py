@@ -13,9 +13,11 @@ history: the staggered iterations until ||R_d||/||b|| <= 1e-5, each with the
 QP update, the S1 trial solve and predictor, the phase solve, the Newton
 displacement solve (PCG with fused reductions) and the reaction force.
 Both schemes use Jacobi-Chebyshev preconditioning (degree 3 for the FP32
-inner solves, 5 for FP64) and the work decomposition measured fastest for
-each on this mesh: LDS tiles for S1 mixed, column marching with 2 rows for
-ST FP64 (--tune-reps N lets the autotuner choose instead).
+inner solves, 5 for FP64), start their displacement solves from the
+projection onto the last four solutions (--guess-vectors), and use the work
+decomposition measured fastest for each on this mesh: LDS tiles for S1
+mixed, column marching with 2 rows for ST FP64 (--tune-reps N lets the
+autotuner choose instead).
 The timed window ends in load step 91, the step in which the crack runs
 through the ligament (the longest steps of the history, where the schemes
 differ most): load steps 1..91-K-W run first with S1 mixed, untimed, and
@@ -767,9 +769,10 @@ def main():
     ap.add_argument("--at1", action="store_true",
                     help="AT1 with penalised irreversibility instead of AT2 with the history "
                          "field, for both schemes")
-    ap.add_argument("--guess-vectors", type=int, default=0,
-                    help="start the displacement solves of the timed runs from the projection "
-                         "onto this many earlier solutions (0..4; 0 = from zero)")
+    ap.add_argument("--guess-vectors", type=int, default=4,
+                    help="start the displacement solves of the timed runs (both schemes) from "
+                         "the projection onto this many earlier solutions (0..4; 0 = from "
+                         "zero)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
