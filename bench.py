@@ -488,6 +488,13 @@ def run_sweep(pf, args):
 
     import workloads as W
     probs = W.batch_instances()
+    # --sweep-part K/M: the instances i with i % M == K (a long history split
+    # over several jobs)
+    part_k, part_m = (int(v) for v in args.sweep_part.split("/"))
+    if not (part_m >= 1 and 0 <= part_k < part_m):
+        raise SystemExit("--sweep-part: K/M with 0 <= K < M")
+    index = [i for i in range(len(probs)) if i % part_m == part_k]
+    probs = [probs[i] for i in index]
     steps, warm = args.steps, args.warmup
     if warm + steps > min(len(p.loads) for p in probs):
         raise SystemExit("warmup + steps exceeds the instances' load history")
@@ -518,7 +525,7 @@ def run_sweep(pf, args):
             rows_all.append(rows)
             ctx.close()
             if (i + 1) % 16 == 0:
-                log(f"  one by one: {i + 1}/64 instances, {t:.1f} s timed")
+                log(f"  one by one: {i + 1}/{len(probs)} instances, {t:.1f} s timed")
         return t, upd, forces, rows_all
 
     def batched(shared):
@@ -537,7 +544,8 @@ def run_sweep(pf, args):
             if jl:
                 jl.write(json.dumps({
                     "mode": "shared" if shared else "streams", "step": n + 1,
-                    "seconds": time.perf_counter() - t0,
+                    "seconds": time.perf_counter() - t0, "instances": index,
+                    "force": [r["force"] for r in rows[-1]],
                     "n_stag": [r["n_stag"] for r in rows[-1]],
                     "converged": [int(r["converged"]) for r in rows[-1]],
                     "dof_updates": sum(r["dof_updates"] for r in rows[-1])}) + "\n")
@@ -576,7 +584,8 @@ def run_sweep(pf, args):
         "value": ref[1] / ref[0] / 1e9, "unit": "GDOF-updates/s", "n_gpus": 1, "steps": steps,
         "warmup": warm, "ms_per_step": ref[0] * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": (f"sweep64: 64 seeded notched tension instances, meshes "
+        "config": {"workload": (f"sweep64: {len(probs)} of the 64 seeded notched tension "
+                                f"instances (index % {part_m} == {part_k}), meshes "
                                 f"{min(sizes)}^2..{max(sizes)}^2 (sum {sum(s * s for s in sizes)} "
                                 f"elements), load steps {warm + 1}..{warm + steps} of 50"),
                    "scheme": "S1", "precision": "mixed", "workers": args.workers,
@@ -748,6 +757,8 @@ def main():
                          "2 rows at 512^2, library choice else")
     ap.add_argument("--tune-reps", type=int, default=0,
                     help="autotuner launches per candidate (0: keep --rows)")
+    ap.add_argument("--sweep-part", default="0/1",
+                    help="sweep64: K/M runs the instances whose index is K modulo M")
     ap.add_argument("--sweep-rows", type=int, default=4,
                     help="work decomposition of every sweep instance (0: autotune each)")
     ap.add_argument("--apply-iters", type=int, default=512,
