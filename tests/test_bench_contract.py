@@ -72,3 +72,17 @@ def test_step_record_is_one_json_line():
     assert rec["run"] == "s1_mixed" and rec["step"] == 3 and rec["timed"] is True
     assert rec["force"] == [0.0, 123.5] and rec["n_cg_trial"] == 40
     assert set(rec) == {"run", "step", "timed", *b.STEP_FIELDS}
+
+
+def test_sweep_part_is_validated_before_any_device_work():
+    """--sweep-part K/M must name a residue class of the 64 instances; a bad
+    one ends the run before a context is created (pf is never touched)."""
+    import types
+
+    import pytest
+    b = bench()
+    for bad in ("2/2", "-1/2", "0/0"):
+        args = types.SimpleNamespace(sweep_part=bad, steps=1, warmup=1, sweep_modes="shared",
+                                     sweep_rows=4, workers=1, stats_jsonl="")
+        with pytest.raises(SystemExit):
+            b.run_sweep(None, args)
