@@ -31,14 +31,28 @@ struct T3DevSync {
 };
 
 // Element-once tangent apply (t3_tangent_block); a non-null done that is
-// set skips the launch (a CG solve that has already ended).
-__global__ void __launch_bounds__(kTpb3) k3_tangent_tiled(Grid3 g, Mat3 m, const double *u,
-                                                          const double *d, const double *p,
-                                                          double *q, const int *done) {
+// set skips the launch (a CG solve that has already ended).  SPL = m.split:
+// the VD instance, free of the spectral split's registers, asks for two
+// blocks per CU.
+template <int SPL>
+__global__ void __launch_bounds__(kTpb3, SPL == 0 ? 2 : 1)
+    k3_tangent_tiled(Grid3 g, Mat3 m, const double *u, const double *d, const double *p,
+                     double *q, const int *done) {
   if (done != nullptr && *done) return;
   __shared__ T3Lds sm;
   double out[1][24], carry[1][3];
-  t3_tangent_block<1>(g, m, u, d, p, q, blockIdx.x, threadIdx.x, sm, out, carry, T3DevSync{});
+  t3_tangent_block<SPL, 1>(g, m, u, d, p, q, blockIdx.x, threadIdx.x, sm, out, carry,
+                           T3DevSync{});
+}
+
+void launch_tangent_tiled(hipStream_t s, const Grid3 &g, const Mat3 &m, const double *u,
+                          const double *d, const double *p, double *q, const int *done) {
+  if (m.split == 1)
+    hipLaunchKernelGGL(k3_tangent_tiled<1>, dim3(t3_blocks(g)), dim3(kTpb3), 0, s, g, m, u, d,
+                       p, q, done);
+  else
+    hipLaunchKernelGGL(k3_tangent_tiled<0>, dim3(t3_blocks(g)), dim3(kTpb3), 0, s, g, m, u, d,
+                       p, q, done);
 }
 
 __global__ void __launch_bounds__(kTpb3) k3_phase_apply(Grid3 g, Mat3 m, const double *coef,
@@ -277,8 +291,7 @@ struct DeviceBackend {
   // q = K_t(u; d) p by the element-once kernel; skipped while *done is set
   void tangent_apply(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
                      const double *p, double *q, const int *done) {
-    hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0, st(), g, m, u, d, p, q,
-                       done);
+    launch_tangent_tiled(st(), g, m, u, d, p, q, done);
     note(hipGetLastError());
   }
   bool ok() const { return err == hipSuccess; }
@@ -360,8 +373,7 @@ pf_status pf3d_op_tangent_apply(const pf3d_mesh *mesh, const pf_material *mat,
   Mat3 m;
   if (!u || !d || !p || !q || make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK)
     return PF_E_INVALID_ARG;
-  hipLaunchKernelGGL(k3_tangent_tiled, dim3(t3_blocks(g)), dim3(kTpb3), 0,
-                     static_cast<hipStream_t>(hip_stream), g, m, u, d, p, q, nullptr);
+  launch_tangent_tiled(static_cast<hipStream_t>(hip_stream), g, m, u, d, p, q, nullptr);
   return launched();
 }
 

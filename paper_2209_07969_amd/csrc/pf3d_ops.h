@@ -119,14 +119,17 @@ __host__ __device__ inline void vd_stress(const Mat3 &m, const double eps[6], do
 }
 
 // Tangent of the split stress at the strain eps, applied to a strain
-// increment de: the volumetric factor is g K where tr eps > 0, else K.
-__host__ __device__ inline void vd_tangent_apply(const Mat3 &m, const double eps[6], double gd,
-                                                 const double de[6], double ds[6]) {
-  const double t = eps[0] + eps[1] + eps[2];
-  const double kf = t > 0.0 ? gd * m.K : m.K;
+// increment de: the volumetric factor is g K where tr eps > 0 (act), else K.
+__host__ __device__ inline void vd_tangent_apply_act(const Mat3 &m, bool act, double gd,
+                                                     const double de[6], double ds[6]) {
+  const double kf = act ? gd * m.K : m.K;
   const double dt = de[0] + de[1] + de[2];
   for (int c = 0; c < 3; ++c) ds[c] = gd * 2.0 * m.mu * (de[c] - dt / 3.0) + kf * dt;
   for (int c = 3; c < 6; ++c) ds[c] = gd * m.mu * de[c];
+}
+__host__ __device__ inline void vd_tangent_apply(const Mat3 &m, const double eps[6], double gd,
+                                                 const double de[6], double ds[6]) {
+  vd_tangent_apply_act(m, eps[0] + eps[1] + eps[2] > 0.0, gd, de, ds);
 }
 
 // Energy parts: psi_vol = K/2 <t>_+^2, psi_dev = mu eps_dev : eps_dev.
@@ -603,16 +606,35 @@ inline int t3_blocks(const Grid3 &g) { return t3_tiles_x(g) * t3_tiles_y(g) * t3
 
 // Tangent apply of one element: out[3a + c] = sum_q w (B_a^T C_t(eps_q(u),
 // g(d_q)) eps_q(p))_c, the element's share of node_tangent_apply at corner a.
+// SPL is the split (0 volumetric-deviatoric, 1 spectral).  The VD tangent
+// depends on u only through the sign of tr eps_q(u), so those eight signs
+// are taken first and u is not held through the main loop (the same
+// operations in the same order as the spectral form, so the same result).
+template <int SPL>
 __host__ __device__ inline void elem_tangent_apply(const Grid3 &g, const Mat3 &m,
                                                    const double *ue, const double *pe,
                                                    const double *de, double out[24]) {
   const double w = g.hx * g.hy * g.hz / 8.0;
   for (int x = 0; x < 24; ++x) out[x] = 0.0;
+  unsigned act = 0;
+  if constexpr (SPL == 0) {
+    for (int q = 0; q < 8; ++q) {
+      double eps[6];
+      strain_at(g, q, ue, eps);
+      if (eps[0] + eps[1] + eps[2] > 0.0) act |= 1u << q;
+    }
+  }
   for (int q = 0; q < 8; ++q) {
-    double eps[6], dep[6], ds[6];
-    strain_at(g, q, ue, eps);
+    double dep[6], ds[6];
     strain_at(g, q, pe, dep);
-    split_tangent_apply(m, eps, degrade(interp_at(g, q, de), m.eta), dep, ds);
+    const double gd = degrade(interp_at(g, q, de), m.eta);
+    if constexpr (SPL == 0) {
+      vd_tangent_apply_act(m, ((act >> q) & 1u) != 0u, gd, dep, ds);
+    } else {
+      double eps[6];
+      strain_at(g, q, ue, eps);
+      spectral_tangent_apply(m, eps, gd, dep, ds);
+    }
     for (int a = 0; a < 8; ++a) {
       const ShapeAt s = shape_at(g, a, q);
       out[3 * a + 0] += w * (s.gx * ds[0] + s.gz * ds[4] + s.gy * ds[5]);
@@ -639,6 +661,7 @@ __host__ __device__ inline void t3_stage(const Grid3 &g, const double *u, const 
 }
 
 // Thread t computes element t of layer ke (zero outside the box).
+template <int SPL>
 __host__ __device__ inline void t3_element(const Grid3 &g, const Mat3 &m, int i0, int j0, int ke,
                                            int t, const T3Lds &sm, double out[24]) {
   const int el = t % kT3E, ej = t / kT3E;
@@ -655,7 +678,7 @@ __host__ __device__ inline void t3_element(const Grid3 &g, const Mat3 &m, int i0
     pe[b] = n.px; pe[8 + b] = n.py; pe[16 + b] = n.pz;
     de[b] = n.d;
   }
-  elem_tangent_apply(g, m, ue, pe, de, out);
+  elem_tangent_apply<SPL>(g, m, ue, pe, de, out);
 }
 
 // Thread t stores the corners of plane ke (h = 0: corners 0-3) or of plane
@@ -676,8 +699,8 @@ __host__ __device__ inline void t3_gather(const T3Lds &sm, int t, double s[3]) {
 
 // One block of the element-once apply, played by NT threads t0 .. t0+NT-1
 // (the device runs one per thread, NT = 1; a host replay runs the block's
-// kTpb3 threads in one call).  sync() is the block's barrier.
-template <int NT, class Sync>
+// kTpb3 threads in one call).  sync() is the block's barrier; SPL = m.split.
+template <int SPL, int NT, class Sync>
 __host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, const double *u,
                                                  const double *d, const double *p, double *q,
                                                  int blk, int t0, T3Lds &sm,
@@ -697,7 +720,7 @@ __host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, 
     for (int r = 0; r < NT; ++r) t3_stage(g, u, d, p, i0, j0, ke + 1, (ke + 1) & 1, t0 + r, sm);
     sync();
     for (int r = 0; r < NT; ++r) {
-      t3_element(g, m, i0, j0, ke, t0 + r, sm, out[r]);
+      t3_element<SPL>(g, m, i0, j0, ke, t0 + r, sm, out[r]);
       t3_put(out[r], 0, t0 + r, sm);
     }
     sync();
@@ -736,8 +759,12 @@ inline void t3_tangent_host(const Grid3 &g, const Mat3 &m, const double *u, cons
                             const double *p, double *q) {
   static T3Lds sm;
   static double out[kTpb3][24], carry[kTpb3][3];
-  for (int b = 0; b < t3_blocks(g); ++b)
-    t3_tangent_block<kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
+  for (int b = 0; b < t3_blocks(g); ++b) {
+    if (m.split == 1)
+      t3_tangent_block<1, kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
+    else
+      t3_tangent_block<0, kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
+  }
 }
 
 // Grid of a one-index-per-thread launch over count indices.
