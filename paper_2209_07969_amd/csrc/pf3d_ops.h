@@ -570,10 +570,11 @@ __host__ __device__ inline void elem_predictor(const Grid3 &g, const Mat3 &m, in
   }
 }
 
-// ---- element-once tangent apply: tiles of node columns marching in z
+// ---- element-once operators: tiles of node columns marching in z
 //
-// The node-gather apply above evaluates every element once for each of its
-// eight nodes.  Here a block owns a tile of kT3 x kT3 node columns and a
+// The node-gather operators above evaluate every element once for each of
+// its eight nodes.  For the internal force and the tangent apply, whose
+// element is costly, a block instead owns a tile of kT3 x kT3 node columns and a
 // chunk of kT3Z node planes, and marches through the element layers that
 // touch its planes.  For each layer ke it stages node plane ke + 1 in LDS
 // (plane ke was staged for the layer before; the first layer stages both),
@@ -585,18 +586,23 @@ __host__ __device__ inline void elem_predictor(const Grid3 &g, const Mat3 &m, in
 // written by one thread: deterministic, no atomics.  The phases are
 // functions of one thread index, so a host build can replay a block by
 // running each phase for all threads between the block's barriers.
+//
+// An element operator Op provides the staged node record Op::Node (value-
+// initialised to zero outside the box), its output components Op::NC,
+//   Node stage(const Grid3 &, int node) const
+//   void element(const Grid3 &, const Mat3 &, int e, const Node *c[8],
+//                double out[8 * NC]) const     (out[NC * a + comp])
+// and the output array q (component c of node n at q[n + c N]).
 constexpr int kT3 = 15;         // owned node columns per tile side
 constexpr int kT3E = kT3 + 1;   // element columns per tile side
 constexpr int kT3N = kT3 + 2;   // staged node columns per side
 constexpr int kT3Z = 8;         // node planes per block
 static_assert(kT3E * kT3E == kTpb3, "one element column per thread");
 
-struct T3Node {
-  double ux, uy, uz, px, py, pz, d;
-};
-struct T3Lds {
-  T3Node plane[2][kT3N * kT3N];   // two node planes, slot k & 1
-  double f[4][3][kTpb3];          // four corners of each element of the layer
+template <class Node, int NC>
+struct T3LdsT {
+  Node plane[2][kT3N * kT3N];   // two node planes, slot k & 1
+  double f[4][NC][kTpb3];       // four corners of each element of the layer
 };
 
 __host__ __device__ inline int t3_tiles_x(const Grid3 &g) { return (g.nx + kT3) / kT3; }
@@ -644,68 +650,134 @@ __host__ __device__ inline void elem_tangent_apply(const Grid3 &g, const Mat3 &m
   }
 }
 
+// Internal force of one element: out[3a + c] = sum_q w (B_a^T sigma(eps_q(u),
+// g(d_q)))_c, the element's share of node_internal_force at corner a.
+template <int SPL>
+__host__ __device__ inline void elem_internal_force(const Grid3 &g, const Mat3 &m,
+                                                    const double *ue, const double *de,
+                                                    double out[24]) {
+  const double w = g.hx * g.hy * g.hz / 8.0;
+  for (int x = 0; x < 24; ++x) out[x] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    double eps[6], sig[6];
+    strain_at(g, q, ue, eps);
+    const double gd = degrade(interp_at(g, q, de), m.eta);
+    if constexpr (SPL == 0) vd_stress(m, eps, gd, sig);
+    else spectral_stress(m, eps, gd, sig);
+    for (int a = 0; a < 8; ++a) {
+      const ShapeAt s = shape_at(g, a, q);
+      out[3 * a + 0] += w * (s.gx * sig[0] + s.gz * sig[4] + s.gy * sig[5]);
+      out[3 * a + 1] += w * (s.gy * sig[1] + s.gz * sig[3] + s.gx * sig[5]);
+      out[3 * a + 2] += w * (s.gz * sig[2] + s.gy * sig[3] + s.gx * sig[4]);
+    }
+  }
+}
+
+// The element operators of the tiled kernels.
+struct T3Node {
+  double ux, uy, uz, px, py, pz, d;
+};
+template <int SPL>
+struct T3TangentOp {
+  using Node = T3Node;
+  static constexpr int NC = 3;
+  const double *u, *d, *p;
+  double *q;
+  __host__ __device__ Node stage(const Grid3 &g, int id) const {
+    return Node{u[id], u[id + g.N], u[id + 2 * g.N], p[id], p[id + g.N], p[id + 2 * g.N], d[id]};
+  }
+  __host__ __device__ void element(const Grid3 &g, const Mat3 &m, int, const Node *const c[8],
+                                   double out[24]) const {
+    double ue[24], pe[24], de[8];
+    for (int b = 0; b < 8; ++b) {
+      ue[b] = c[b]->ux; ue[8 + b] = c[b]->uy; ue[16 + b] = c[b]->uz;
+      pe[b] = c[b]->px; pe[8 + b] = c[b]->py; pe[16 + b] = c[b]->pz;
+      de[b] = c[b]->d;
+    }
+    elem_tangent_apply<SPL>(g, m, ue, pe, de, out);
+  }
+};
+struct T3UdNode {
+  double ux, uy, uz, d;
+};
+template <int SPL>
+struct T3ForceOp {
+  using Node = T3UdNode;
+  static constexpr int NC = 3;
+  const double *u, *d;
+  double *q;
+  __host__ __device__ Node stage(const Grid3 &g, int id) const {
+    return Node{u[id], u[id + g.N], u[id + 2 * g.N], d[id]};
+  }
+  __host__ __device__ void element(const Grid3 &g, const Mat3 &m, int, const Node *const c[8],
+                                   double out[24]) const {
+    double ue[24], de[8];
+    for (int b = 0; b < 8; ++b) {
+      ue[b] = c[b]->ux; ue[8 + b] = c[b]->uy; ue[16 + b] = c[b]->uz;
+      de[b] = c[b]->d;
+    }
+    elem_internal_force<SPL>(g, m, ue, de, out);
+  }
+};
 // Thread t stages its entries of node plane k (columns i0 - 1 .. i0 + kT3,
 // j0 - 1 .. j0 + kT3) into slot s; nodes outside the box are zero.
-__host__ __device__ inline void t3_stage(const Grid3 &g, const double *u, const double *d,
-                                         const double *p, int i0, int j0, int k, int s, int t,
-                                         T3Lds &sm) {
+template <class Op>
+__host__ __device__ inline void t3_stage(const Op &op, const Grid3 &g, int i0, int j0, int k,
+                                         int s, int t, T3LdsT<typename Op::Node, Op::NC> &sm) {
   for (int c = t; c < kT3N * kT3N; c += kTpb3) {
     const int i = i0 - 1 + c % kT3N, j = j0 - 1 + c / kT3N;
-    T3Node n{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz) {
-      const int id = node_id(g, i, j, k);
-      n = T3Node{u[id], u[id + g.N], u[id + 2 * g.N], p[id], p[id + g.N], p[id + 2 * g.N], d[id]};
-    }
+    typename Op::Node n{};
+    if (i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz)
+      n = op.stage(g, node_id(g, i, j, k));
     sm.plane[s][c] = n;
   }
 }
 
 // Thread t computes element t of layer ke (zero outside the box).
-template <int SPL>
-__host__ __device__ inline void t3_element(const Grid3 &g, const Mat3 &m, int i0, int j0, int ke,
-                                           int t, const T3Lds &sm, double out[24]) {
+template <class Op>
+__host__ __device__ inline void t3_element(const Op &op, const Grid3 &g, const Mat3 &m, int i0,
+                                           int j0, int ke, int t,
+                                           const T3LdsT<typename Op::Node, Op::NC> &sm,
+                                           double out[8 * Op::NC]) {
   const int el = t % kT3E, ej = t / kT3E;
   const int ie = i0 - 1 + el, je = j0 - 1 + ej;
   if (ie < 0 || ie >= g.nx || je < 0 || je >= g.ny || ke < 0 || ke >= g.nz) {
-    for (int x = 0; x < 24; ++x) out[x] = 0.0;
+    for (int x = 0; x < 8 * Op::NC; ++x) out[x] = 0.0;
     return;
   }
-  double ue[24], pe[24], de[8];
-  for (int b = 0; b < 8; ++b) {
-    const T3Node &n = sm.plane[(ke + corner_dk(b)) & 1]
-                              [(ej + corner_dj(b)) * kT3N + el + corner_di(b)];
-    ue[b] = n.ux; ue[8 + b] = n.uy; ue[16 + b] = n.uz;
-    pe[b] = n.px; pe[8 + b] = n.py; pe[16 + b] = n.pz;
-    de[b] = n.d;
-  }
-  elem_tangent_apply<SPL>(g, m, ue, pe, de, out);
+  const typename Op::Node *c[8];
+  for (int b = 0; b < 8; ++b)
+    c[b] = &sm.plane[(ke + corner_dk(b)) & 1][(ej + corner_dj(b)) * kT3N + el + corner_di(b)];
+  op.element(g, m, ie + je * g.nx + ke * g.nx * g.ny, c, out);
 }
 
 // Thread t stores the corners of plane ke (h = 0: corners 0-3) or of plane
 // ke + 1 (h = 1: corners 4-7) of its element.
-__host__ __device__ inline void t3_put(const double out[24], int h, int t, T3Lds &sm) {
+template <int NC, class Node>
+__host__ __device__ inline void t3_put(const double *out, int h, int t, T3LdsT<Node, NC> &sm) {
   for (int a = 0; a < 4; ++a)
-    for (int c = 0; c < 3; ++c) sm.f[a][c][t] = out[3 * (4 * h + a) + c];
+    for (int c = 0; c < NC; ++c) sm.f[a][c][t] = out[NC * (4 * h + a) + c];
 }
 
 // Owned node column t (< kT3^2): the four stored corner values at its node,
 // corner 2 of element (li, lj), 3 of (li+1, lj), 1 of (li, lj+1) and 0 of
 // (li+1, lj+1) (corners 6, 7, 5, 4 for the upper half).
-__host__ __device__ inline void t3_gather(const T3Lds &sm, int t, double s[3]) {
+template <int NC, class Node>
+__host__ __device__ inline void t3_gather(const T3LdsT<Node, NC> &sm, int t, double *s) {
   const int li = t % kT3, lj = t / kT3, e = lj * kT3E + li;
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NC; ++c)
     s[c] = sm.f[2][c][e] + sm.f[3][c][e + 1] + sm.f[1][c][e + kT3E] + sm.f[0][c][e + kT3E + 1];
 }
 
-// One block of the element-once apply, played by NT threads t0 .. t0+NT-1
+// One block of an element-once operator, played by NT threads t0 .. t0+NT-1
 // (the device runs one per thread, NT = 1; a host replay runs the block's
-// kTpb3 threads in one call).  sync() is the block's barrier; SPL = m.split.
-template <int SPL, int NT, class Sync>
-__host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, const double *u,
-                                                 const double *d, const double *p, double *q,
-                                                 int blk, int t0, T3Lds &sm,
-                                                 double (&out)[NT][24], double (&carry)[NT][3],
-                                                 const Sync &sync) {
+// kTpb3 threads in one call).  sync() is the block's barrier.
+template <class Op, int NT, class Sync>
+__host__ __device__ inline void t3_block(const Op &op, const Grid3 &g, const Mat3 &m, int blk,
+                                         int t0, T3LdsT<typename Op::Node, Op::NC> &sm,
+                                         double (&out)[NT][8 * Op::NC],
+                                         double (&carry)[NT][Op::NC], const Sync &sync) {
+  constexpr int NC = Op::NC;
   const int nxt = t3_tiles_x(g), nyt = t3_tiles_y(g);
   const int i0 = (blk % nxt) * kT3, j0 = ((blk / nxt) % nyt) * kT3;
   const int k0 = (blk / (nxt * nyt)) * kT3Z;
@@ -713,32 +785,32 @@ __host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, 
   const int kb = k0 > 0 ? k0 - 1 : 0;                              // element layers [kb, kl]
   const int kl = (k1 - 1 < g.nz - 1) ? k1 - 1 : g.nz - 1;
   for (int r = 0; r < NT; ++r)
-    for (int c = 0; c < 3; ++c) carry[r][c] = 0.0;
+    for (int c = 0; c < NC; ++c) carry[r][c] = 0.0;
   for (int ke = kb; ke <= kl; ++ke) {
     if (ke == kb)
-      for (int r = 0; r < NT; ++r) t3_stage(g, u, d, p, i0, j0, ke, ke & 1, t0 + r, sm);
-    for (int r = 0; r < NT; ++r) t3_stage(g, u, d, p, i0, j0, ke + 1, (ke + 1) & 1, t0 + r, sm);
+      for (int r = 0; r < NT; ++r) t3_stage(op, g, i0, j0, ke, ke & 1, t0 + r, sm);
+    for (int r = 0; r < NT; ++r) t3_stage(op, g, i0, j0, ke + 1, (ke + 1) & 1, t0 + r, sm);
     sync();
     for (int r = 0; r < NT; ++r) {
-      t3_element<SPL>(g, m, i0, j0, ke, t0 + r, sm, out[r]);
-      t3_put(out[r], 0, t0 + r, sm);
+      t3_element(op, g, m, i0, j0, ke, t0 + r, sm, out[r]);
+      t3_put<NC>(out[r], 0, t0 + r, sm);
     }
     sync();
     if (ke >= k0)
       for (int r = 0; r < NT; ++r) {
         const int t = t0 + r, i = i0 + t % kT3, j = j0 + t / kT3;
         if (t < kT3 * kT3 && i <= g.nx && j <= g.ny) {
-          double s[3];
-          t3_gather(sm, t, s);
+          double s[NC];
+          t3_gather<NC>(sm, t, s);
           const int id = node_id(g, i, j, ke);
-          for (int c = 0; c < 3; ++c) q[id + c * g.N] = carry[r][c] + s[c];
+          for (int c = 0; c < NC; ++c) op.q[id + c * g.N] = carry[r][c] + s[c];
         }
       }
     sync();
-    for (int r = 0; r < NT; ++r) t3_put(out[r], 1, t0 + r, sm);
+    for (int r = 0; r < NT; ++r) t3_put<NC>(out[r], 1, t0 + r, sm);
     sync();
     for (int r = 0; r < NT; ++r)
-      if (t0 + r < kT3 * kT3) t3_gather(sm, t0 + r, carry[r]);
+      if (t0 + r < kT3 * kT3) t3_gather<NC>(sm, t0 + r, carry[r]);
   }
   // the top plane of the box has the layer below only
   if (g.nz >= k0 && g.nz < k1)
@@ -746,25 +818,38 @@ __host__ __device__ inline void t3_tangent_block(const Grid3 &g, const Mat3 &m, 
       const int t = t0 + r, i = i0 + t % kT3, j = j0 + t / kT3;
       if (t < kT3 * kT3 && i <= g.nx && j <= g.ny) {
         const int id = node_id(g, i, j, g.nz);
-        for (int c = 0; c < 3; ++c) q[id + c * g.N] = carry[r][c];
+        for (int c = 0; c < NC; ++c) op.q[id + c * g.N] = carry[r][c];
       }
     }
 }
 
-// Host replay of the element-once apply over its whole grid (tests only).
+// Host replay of an element-once operator over its whole grid (tests only).
 struct T3HostSync {
   void operator()() const {}
 };
+template <class Op>
+inline void t3_host(const Op &op, const Grid3 &g, const Mat3 &m) {
+  static T3LdsT<typename Op::Node, Op::NC> sm;
+  static double out[kTpb3][8 * Op::NC], carry[kTpb3][Op::NC];
+  for (int b = 0; b < t3_blocks(g); ++b)
+    t3_block<Op, kTpb3>(op, g, m, b, 0, sm, out, carry, T3HostSync{});
+}
 inline void t3_tangent_host(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
                             const double *p, double *q) {
-  static T3Lds sm;
-  static double out[kTpb3][24], carry[kTpb3][3];
-  for (int b = 0; b < t3_blocks(g); ++b) {
-    if (m.split == 1)
-      t3_tangent_block<1, kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
-    else
-      t3_tangent_block<0, kTpb3>(g, m, u, d, p, q, b, 0, sm, out, carry, T3HostSync{});
-  }
+  if (m.split == 1) t3_host(T3TangentOp<1>{u, d, p, q}, g, m);
+  else t3_host(T3TangentOp<0>{u, d, p, q}, g, m);
+}
+// The tiled internal force pays only once the tiles fill the GPU: on fewer
+// blocks the node gather, one thread per node, is faster (45 tiles at 32^3:
+// 69 us tiled against 45 us gathered; 225 tiles at 64^3: 74 us against
+// 164 us).
+constexpr int kT3ForceMinBlocks = 128;
+inline bool t3_force_tiled(const Grid3 &g) { return t3_blocks(g) >= kT3ForceMinBlocks; }
+
+inline void t3_force_host(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
+                          double *R) {
+  if (m.split == 1) t3_host(T3ForceOp<1>{u, d, R}, g, m);
+  else t3_host(T3ForceOp<0>{u, d, R}, g, m);
 }
 
 // Grid of a one-index-per-thread launch over count indices.

@@ -34,17 +34,9 @@ namespace pf3d {
 
 // ---- per-index functors
 
-struct FForce {
-  Grid3 g; Mat3 m; const double *u, *d; double *R;
-  __host__ __device__ void operator()(int n) const { node_internal_force(g, m, n, u, d, R); }
-};
 struct FTangentDiag {
   Grid3 g; Mat3 m; const double *u, *d; double *D;
   __host__ __device__ void operator()(int n) const { node_tangent_diag(g, m, n, u, d, D); }
-};
-struct FPhase {
-  Grid3 g; Mat3 m; const double *coef, *p; double *q;
-  __host__ __device__ void operator()(int n) const { node_phase_apply(g, m, n, coef, p, q); }
 };
 struct FPhaseDiag {
   Grid3 g; Mat3 m; const double *coef; double *D;
@@ -226,14 +218,6 @@ struct FCgBeta {
     s->rz = s->rz_new;
   }
 };
-// an operator apply that returns at once when the solve has ended
-template <class F>
-struct FWhileRunning {
-  const CgState3 *s; F f;
-  __host__ __device__ void operator()(int i) const {
-    if (!s->done) f(i);
-  }
-};
 struct FCgP {
   const CgState3 *s; double *p; const double *z; const uint8_t *fixed;
   __host__ __device__ void operator()(int i) const {
@@ -350,7 +334,7 @@ class Solver3 {
 
   // Reaction of group grp: the internal force summed over its entries.
   void reaction(int grp, double f[3]) {
-    be_.each(g_.N, FForce{g_, m_, u_, d_, Rt_});
+    be_.internal_force(g_, m_, u_, d_, Rt_);
     for (int c = 0; c < 3; ++c)
       f[c] = gn_[grp] ? be_.sum(gn_[grp], FGroupSum{Rt_, gdof_[grp], gcomp_dev_[grp], c}) : 0.0;
   }
@@ -428,7 +412,7 @@ class Solver3 {
   // R = internal force at (u, d_), zero on fixed DOFs; returns ||R||.
   double residual_u(const double *u, double *R) {
     const int N3 = 3 * g_.N;
-    be_.each(g_.N, FForce{g_, m_, u, d_, R});
+    be_.internal_force(g_, m_, u, d_, R);
     be_.each(N3, FAxpy{R, R, 0.0, fu_, R});
     return std::sqrt(be_.sum(N3, FDot{R, R, fu_}));
   }
@@ -518,7 +502,7 @@ class Solver3 {
     const int N = g_.N;
     be_.each(g_.E, FPhaseCoef{g_, m_, 0, 0.0, Hs, nullptr, nullptr, nullptr, coef_});
     be_.each(N, FPhaseRhs{g_, Hs, b_});
-    be_.each(N, FPhase{g_, m_, coef_, d_, Rd_});
+    be_.phase_apply(g_, m_, coef_, d_, Rd_, nullptr);
     be_.each(N, FAxpy{Rd_, b_, -1.0, fd_, Rd_});
     *nR = std::sqrt(be_.sum(N, FDot{Rd_, Rd_, fd_}));
     *nb = std::sqrt(be_.sum(N, FDot{b_, b_, fd_}));
@@ -542,7 +526,7 @@ class Solver3 {
     be_.each(N, FPhaseDiag{g_, m_, coef_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
     const int cg = pcg(1, N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
-      be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, coef_, p, q}});
+      be_.phase_apply(g_, m_, coef_, p, q, &cs_->done);
     }, st);
     st->n_cg_d += cg;
     st->dof_updates += double(cg) * double(nfree_d_);
@@ -562,7 +546,7 @@ class Solver3 {
     be_.each(N, FPhaseDiag{g_, m_, ctr_, D_});
     be_.each(N, FInvDiag{D_, fd_, Dinv_});
     const int cg = pcg(2, N, Rd_, fd_, o_.tol_pcg, [&](const double *p, double *q) {
-      be_.each(N, FWhileRunning<FPhase>{cs_, FPhase{g_, m_, ctr_, p, q}});
+      be_.phase_apply(g_, m_, ctr_, p, q, &cs_->done);
     }, st);
     st->n_cg_trial += cg;
     st->dof_updates += double(cg) * double(nfree_d_);

@@ -36,21 +36,29 @@ void run_ops(const pf3d_mesh &mesh, const pf_material &mat) {
   long long ng = 0, below = 0;
   h3_internal_force(&mesh, &mat, u.data(), d.data(), R.data());
   h3_tangent_apply(&mesh, &mat, u.data(), d.data(), p.data(), q.data());
-  // the element-once grid against the node gather: the same per-element
+  h3_phase_apply(&mesh, &mat, coef.data(), d.data(), qd.data());
+  // the element-once grids against the node gathers: the same per-element
   // arithmetic summed in another order
-  std::vector<double> qg(3 * N);
+  std::vector<double> Rg(3 * N), qg(3 * N);
+  // (the ABI's force takes the gather on small meshes: compare the tiles)
+  h3_internal_force_tiled(&mesh, &mat, u.data(), d.data(), R.data());
+  h3_internal_force_gather(&mesh, &mat, u.data(), d.data(), Rg.data());
   h3_tangent_apply_gather(&mesh, &mat, u.data(), d.data(), p.data(), qg.data());
-  double dmax = 0.0, qmax = 0.0;
-  for (size_t i = 0; i < 3 * N; ++i) {
-    dmax = std::fmax(dmax, std::fabs(q[i] - qg[i]));
-    qmax = std::fmax(qmax, std::fabs(qg[i]));
-  }
-  if (!(dmax <= 1e-12 * qmax)) {
-    std::printf("tiled tangent apply differs from the gather: %g of %g\n", dmax, qmax);
-    std::exit(1);
+  const std::vector<double> *pairs[2][2] = {{&R, &Rg}, {&q, &qg}};
+  const char *names[2] = {"internal force", "tangent apply"};
+  for (int k = 0; k < 2; ++k) {
+    const std::vector<double> &a = *pairs[k][0], &b = *pairs[k][1];
+    double dmax = 0.0, bmax = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+      dmax = std::fmax(dmax, std::fabs(a[i] - b[i]));
+      bmax = std::fmax(bmax, std::fabs(b[i]));
+    }
+    if (!(dmax <= 1e-12 * bmax)) {
+      std::printf("tiled %s differs from the gather: %g of %g\n", names[k], dmax, bmax);
+      std::exit(1);
+    }
   }
   h3_tangent_diag(&mesh, &mat, u.data(), d.data(), Dt.data());
-  h3_phase_apply(&mesh, &mat, coef.data(), d.data(), qd.data());
   h3_phase_diag(&mesh, &mat, coef.data(), Dp.data());
   h3_phase_rhs(&mesh, Hprev.data(), b.data());
   for (int scheme = 0; scheme < 4; ++scheme) {

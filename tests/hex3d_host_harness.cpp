@@ -27,6 +27,26 @@ int h3_internal_force(const pf3d_mesh *mesh, const pf_material *mat, const doubl
   Grid3 g;
   Mat3 m;
   if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  // the launch the C ABI makes: element-once tiles where they fill the GPU
+  if (t3_force_tiled(g)) t3_force_host(g, m, u, d, R);
+  else replay(g.N, [&](int n) { node_internal_force(g, m, n, u, d, R); });
+  return PF_OK;
+}
+
+int h3_internal_force_tiled(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                            const double *d, double *R) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
+  t3_force_host(g, m, u, d, R);   // the element-once grid at any size
+  return PF_OK;
+}
+
+int h3_internal_force_gather(const pf3d_mesh *mesh, const pf_material *mat, const double *u,
+                             const double *d, double *R) {
+  Grid3 g;
+  Mat3 m;
+  if (make_grid(mesh, &g) != PF_OK || make_mat(mat, &m) != PF_OK) return PF_E_INVALID_ARG;
   replay(g.N, [&](int n) { node_internal_force(g, m, n, u, d, R); });
   return PF_OK;
 }

@@ -31,10 +31,20 @@ struct HostBackend {
         if (i < count) f(i);
       }
   }
-  // the element-once tangent apply, replayed block by block
+  // the operators of the device's kernels, replayed block by block
   void tangent_apply(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
                      const double *p, double *q, const int *done) {
     if (!*done) t3_tangent_host(g, m, u, d, p, q);
+  }
+  void internal_force(const Grid3 &g, const Mat3 &m, const double *u, const double *d,
+                      double *R) {
+    if (t3_force_tiled(g)) t3_force_host(g, m, u, d, R);
+    else each(g.N, [&](int n) { node_internal_force(g, m, n, u, d, R); });
+  }
+  void phase_apply(const Grid3 &g, const Mat3 &m, const double *coef, const double *p,
+                   double *q, const int *done) {
+    if (done == nullptr || !*done)
+      each(g.N, [&](int n) { node_phase_apply(g, m, n, coef, p, q); });
   }
   bool ok() const { return true; }
   // no recording on the host: a batch runs as it is enqueued

@@ -73,6 +73,24 @@ def test_internal_force_and_tangent_3d(gpu_lib, shape, split):
     np.testing.assert_allclose(host(q), q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
 
 
+@pytest.mark.parametrize("split", [0, 1])
+def test_internal_force_3d_element_once_tiles(gpu_lib, split):
+    """A mesh whose tiles fill the GPU (16 x 2 x 1020 elements: 2 x 1 tiles
+    of node columns, 128 chunks of planes, ragged in x and z), where the
+    internal force runs element-once instead of as a node gather."""
+    import torch
+    b, ops, om, rng = setup(gpu_lib, (16, 2, 1020), 1038 + split, split)
+    m = b.material
+    cons = (H3.VD3D if split == 0 else H3.Spectral3D)(m.E, m.nu)
+    N = om.n_nodes
+    u = rng.normal(size=3 * N) * 1e-3
+    d = rng.uniform(0, 1, size=N)
+    R_orc = soa(H3.internal_force(om, cons, u, d, m.eta))
+    R = torch.full((3 * N,), float("nan"), dtype=torch.float64, device="cuda")
+    ops.internal_force(dev(soa(u)), dev(d), R)
+    np.testing.assert_allclose(host(R), R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
+
+
 @pytest.mark.parametrize("shape", MESHES)
 def test_phase_apply_3d(gpu_lib, shape):
     import torch

@@ -52,6 +52,7 @@ def harness(tmp_path_factory):
     P = ctypes.c_void_p
     M3, MT = ctypes.POINTER(pf.Mesh3Desc), ctypes.POINTER(pf.MaterialDesc)
     lib.h3_internal_force.argtypes = [M3, MT, P, P, P]
+    lib.h3_internal_force_tiled.argtypes = [M3, MT, P, P, P]
     lib.h3_tangent_apply.argtypes = [M3, MT, P, P, P, P]
     lib.h3_phase_apply.argtypes = [M3, MT, P, P, P]
     lib.h3_qp_update.argtypes = [M3, MT, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -62,7 +63,8 @@ def harness(tmp_path_factory):
     lib.h3_phase_rhs.argtypes = [M3, P, P]
     lib.h3_phase_coef.argtypes = [M3, MT, ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P, P,
                                   P, P, ctypes.POINTER(ctypes.c_longlong)]
-    for f in ("h3_internal_force", "h3_tangent_apply", "h3_phase_apply", "h3_qp_update",
+    for f in ("h3_internal_force", "h3_internal_force_tiled", "h3_tangent_apply",
+              "h3_phase_apply", "h3_qp_update",
               "h3_predictor", "h3_tangent_diag", "h3_phase_diag", "h3_phase_rhs",
               "h3_phase_coef"):
         getattr(lib, f).restype = ctypes.c_int
@@ -133,6 +135,12 @@ def test_internal_force_and_tangent(harness, shape, split):
         assert np.all(np.isfinite(arr.val)) and arr.guards_intact()
     np.testing.assert_allclose(R.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
     np.testing.assert_allclose(q.val, q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
+    # the element-once internal force (the ABI's choice once the tiles fill
+    # the GPU, larger meshes than these) on the same inputs
+    Rt = out_f64(3 * N)
+    assert harness.h3_internal_force_tiled(mesh, mat, uG.ptr, dG.ptr, Rt.ptr) == 0
+    assert np.all(np.isfinite(Rt.val)) and Rt.guards_intact()
+    np.testing.assert_allclose(Rt.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
 
 
 @pytest.mark.parametrize("shape", MESHES)
@@ -261,6 +269,12 @@ def test_spectral_plane_fields(harness):
     assert harness.h3_tangent_apply(mesh, mat, uG.ptr, dG.ptr, pG.ptr, q.ptr) == 0
     np.testing.assert_allclose(R.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
     np.testing.assert_allclose(q.val, q_orc, rtol=0, atol=1e-12 * np.abs(q_orc).max())
+    # the element-once internal force (the ABI's choice once the tiles fill
+    # the GPU, larger meshes than these) on the same inputs
+    Rt = out_f64(3 * N)
+    assert harness.h3_internal_force_tiled(mesh, mat, uG.ptr, dG.ptr, Rt.ptr) == 0
+    assert np.all(np.isfinite(Rt.val)) and Rt.guards_intact()
+    np.testing.assert_allclose(Rt.val, R_orc, rtol=0, atol=1e-12 * np.abs(R_orc).max())
 
 
 @pytest.mark.parametrize("split", [0, 1])
